@@ -1,0 +1,251 @@
+/*
+ * pmchwt.h -- C ABI of the MI355X (gfx950) library for the Calderon-preconditioned
+ * PMCHWT boundary element method of Kleanthous, Betcke, Hewett,
+ * Escapil-Inchauspe, Jerez-Hanckes and Baran, "Accelerated Calderon
+ * preconditioning for Maxwell transmission problems".
+ *
+ * The library assembles the Galerkin matrices of the electric (S) and magnetic
+ * (C) boundary integral operators (Section 2) on Rao-Wilton-Glisson functions
+ * of the primal mesh and on Buffa-Christiansen functions of the barycentric
+ * mesh (Section 3.2), builds the multi-particle PMCHWT operator A and one of
+ * the preconditioners I, A, D, D^i, D^e, S^i, S^e (Section 3.1), optionally
+ * restricted to near-field interactions (the cutoff chi of Section 3.3), and
+ * solves  M_P^-1 P M_A^-1 A x = M_P^-1 P M_A^-1 b  with restarted GMRES
+ * (Section 3.2, Section 4).  Every step runs in HIP kernels on one GPU; the
+ * host only builds mesh topology and index tables.
+ *
+ * Conventions
+ *  - All functions return 0 (PMCHWT_OK) or a negative pmchwt_status; the
+ *    message of the last failure is returned by pmchwt_last_error(ctx).
+ *  - Input arrays are host memory owned by the caller and copied during the
+ *    call.  Output arrays are caller-allocated host memory of the stated
+ *    size.  All device memory is allocated and owned by the context and freed
+ *    by pmchwt_destroy.
+ *  - A context is not thread safe; use one per host thread.
+ *  - Meshes: vertices double[nv*3] (x,y,z), triangles int32[nt*3] indexing
+ *    them, counter-clockwise seen from the exterior medium (the normal n_m of
+ *    Section 2 points outwards), closed, 2-manifold, no degenerate triangles.
+ *  - Edges of a scatterer are numbered in lexicographic order of their
+ *    (lower vertex, higher vertex) index pair.  T+ of an edge is the triangle
+ *    that traverses it from its lower to its higher vertex.  RWG functions are
+ *    in unit-flux form, (x - p+)/(2 A+) on T+ and -(x - p-)/(2 A-) on T-
+ *    (the paper fixes no normalisation; physical outputs do not depend on it).
+ *    BC function e is the Buffa-Christiansen function attached to edge e,
+ *    oriented from its lower to its higher vertex.
+ *  - Unknowns are scatterer-major: scatterer m holds [x_D (E_m); x_N (E_m)],
+ *    the RWG coefficients of the scaled traces u^s_m = [gamma_D E^s;
+ *    k_e gamma_N E^s] of Section 2 (mu = 1).
+ *  - Complex numbers cross the ABI interleaved as pmchwt_complex.
+ *  - Wavenumbers: k_m = k_e sqrt(eps_m) (principal root), mu = 1.
+ */
+#ifndef PMCHWT_H
+#define PMCHWT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmchwt_ctx pmchwt_ctx;
+
+typedef struct {
+  double re, im;
+} pmchwt_complex;
+
+typedef enum {
+  PMCHWT_OK = 0,
+  PMCHWT_ERR_INVALID_ARG = -1,   /* bad pointer, size, option or index */
+  PMCHWT_ERR_INVALID_MESH = -2,  /* open, non-manifold, mis-oriented or degenerate mesh */
+  PMCHWT_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
+  PMCHWT_ERR_DEVICE = -4,        /* a HIP or rocSOLVER call failed */
+  PMCHWT_ERR_NOT_CONVERGED = -5, /* GMRES hit max_iter; outputs hold the last iterate */
+  PMCHWT_ERR_OVER_BUDGET = -6,   /* request larger than the server's HBM budget */
+  PMCHWT_ERR_CANCELLED = -7,     /* server request cancelled */
+  PMCHWT_ERR_STATE = -8          /* call out of order (e.g. solve before assemble) */
+} pmchwt_status;
+
+/* Preconditioning operator P (Section 3.1; cost per iteration in Table 1). */
+typedef enum {
+  PMCHWT_P_I = 0,     /* no preconditioner: GMRES on A itself                     */
+  PMCHWT_P_A = 1,     /* P = A (classical Calderon)                               */
+  PMCHWT_P_D = 2,     /* block diagonal of A: A^e_m + A^i_m per scatterer          */
+  PMCHWT_P_D_INT = 3, /* A^i_m per scatterer                                      */
+  PMCHWT_P_D_EXT = 4, /* A^e_m per scatterer                                      */
+  PMCHWT_P_S_INT = 5, /* [[0, S^i_m/k_m], [-k_m S^i_m, 0]] per scatterer           */
+  PMCHWT_P_S_EXT = 6  /* [[0, S^e_m/k_e], [-k_e S^e_m, 0]] per scatterer           */
+} pmchwt_precond;
+
+typedef enum { PMCHWT_FP64 = 0, PMCHWT_MIXED = 1 } pmchwt_precision;
+typedef enum { PMCHWT_OP_S = 0, PMCHWT_OP_C = 1 } pmchwt_opkind;
+typedef enum { PMCHWT_EXT = 0, PMCHWT_INT = 1 } pmchwt_medium;
+typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
+
+/* Quadrature and compression parameters of one operator family (the
+ * bi-parametric parameters (chi, q) of Section 3.3).
+ *   q_near, q_medium, q_far : orders 1..4 of the symmetric triangle rules
+ *       (1, 3, 4, 6 points per triangle) for disjoint pairs with relative
+ *       distance |c1 - c2| / max(diam) < 2, in [2, 4), >= 4.
+ *   n_singular : Gauss-Legendre points per coordinate of the Sauter-Schwab
+ *       rules for identical / shared-edge / shared-vertex pairs
+ *       (paper's q_singular = 6 <-> 4, q_singular = 1 <-> 1), 1..8.
+ *   chi : near-field cutoff, absolute length; an entry (i, j) of P is kept iff
+ *       the bounding boxes of the supports of functions i and j are at most
+ *       chi apart; chi < 0 means infinity.  Ignored for A (always dense).
+ *   precision : PMCHWT_FP64, or PMCHWT_MIXED = disjoint pairs and operator
+ *       storage in FP32, singular pairs in FP64.                              */
+typedef struct {
+  int32_t q_near, q_medium, q_far;
+  int32_t n_singular;
+  double chi;
+  int32_t precision;
+} pmchwt_assembly_opts;
+
+/* Restarted GMRES (Section 4: tol 1e-5, restart 200).
+ *   tol      : relative residual of the preconditioned system
+ *   restart  : rho, Krylov vectors per cycle (1..1024)
+ *   max_iter : total iteration cap
+ *   ir_max   : outer iterative-refinement steps with an FP64 residual
+ *              b - A x (0 = none)                                          */
+typedef struct {
+  double tol;
+  int32_t restart;
+  int32_t max_iter;
+  int32_t ir_max;
+} pmchwt_solver_opts;
+
+typedef struct {
+  int32_t iterations;        /* total GMRES iterations R over all refinement steps     */
+  int32_t converged;         /* 1 if every right-hand side met tol                      */
+  int64_t matvecs;           /* boundary-operator applications, Table 1's unit          */
+  double rel_residual;       /* worst final preconditioned relative residual            */
+  int32_t ir_steps;          /* refinement steps performed                              */
+  int32_t restarts;          /* completed GMRES cycles                                  */
+  double ms_solve;           /* device time of the solve phase                          */
+} pmchwt_solve_stats;
+
+/* Per-phase device timings (HIP events on the context's stream) and the
+ * algorithmic work of the last assemble / solve, for roofline reporting.     */
+typedef struct {
+  double ms_assemble_A;      /* regular + singular + scatter kernels of A               */
+  double ms_assemble_regular;/* regular-pair kernel alone (sum over its launches)       */
+  double ms_assemble_singular;
+  double ms_assemble_P;      /* near-field BC kernel                                    */
+  double ms_mass;            /* mass and Gram matrices and their inverses               */
+  int64_t regular_pairs;     /* ordered disjoint triangle pairs integrated, per k       */
+  int64_t regular_point_pairs;
+  int64_t singular_pairs;
+  int64_t singular_point_pairs;
+  int64_t bary_pairs;        /* barycentric triangle pairs integrated for P             */
+  int64_t nnz_P;             /* stored entries per BC operator                          */
+  int32_t regular_launches;
+  int32_t n_wavenumbers;     /* wavenumbers per regular pair in the A kernels           */
+  double ms_matvec_total;    /* dense operator application kernels during the solve     */
+  int64_t matvec_launches;
+  int64_t matvec_bytes;      /* algorithmic operator bytes read by those launches       */
+} pmchwt_profile;
+
+/* Version string of the library. */
+const char *pmchwt_version(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run all work on, or NULL for a stream owned by the context.               */
+int pmchwt_create(pmchwt_ctx **out, int device, void *hip_stream);
+
+/* Add scatterer Gamma_m with relative permittivity eps_r (mu_r = 1).
+ * Validates the mesh (closed, consistently oriented, no zero-area
+ * triangle); on failure returns PMCHWT_ERR_INVALID_MESH.                    */
+int pmchwt_add_scatterer(pmchwt_ctx *ctx, const double *verts, int32_t nv, const int32_t *tris,
+                         int32_t nt, pmchwt_complex eps_r, int32_t *scatterer_id_out);
+
+/* Exterior wavenumber k_e > 0 (Section 2). */
+int pmchwt_set_wavenumber(pmchwt_ctx *ctx, double k_ext);
+
+/* Number of scatterers, edges E_m of scatterer m, total unknowns 2 sum E_m. */
+int pmchwt_sizes(const pmchwt_ctx *ctx, int32_t *n_scatterers, int64_t *n_unknowns);
+int pmchwt_num_edges(const pmchwt_ctx *ctx, int32_t m, int32_t *E_out);
+
+/* Assemble A (RWG x RWG: S^e, C^e on all scatterers at k_e, S^i_m, C^i_m at
+ * k_m), the BC operators the chosen preconditioner needs (near-field cutoff
+ * P->chi), the mixed mass matrices M_A = <bc_j, rwg_i> (Section 3.2) and
+ * their inverses, and the RWG Gram matrices used by the right-hand side.
+ * Re-assembling replaces all previous operators.                              */
+int pmchwt_assemble(pmchwt_ctx *ctx, const pmchwt_assembly_opts *A, const pmchwt_assembly_opts *P,
+                    pmchwt_precond kind);
+
+/* Copy one assembled Galerkin block to host.  op: S or C; medium: EXT (k_e)
+ * or INT (k_m, only m == l); space: RWG (operators of A) or BC (operators of
+ * P, zero outside the near field; only operators the preconditioner uses).
+ * Block (m, l) has rows = functions of scatterer m, columns = of scatterer l;
+ * out is row-major E_m x E_l with leading dimension ld >= E_l.              */
+int pmchwt_get_block(pmchwt_ctx *ctx, pmchwt_opkind op, pmchwt_medium medium, pmchwt_space space,
+                     int32_t m, int32_t l, pmchwt_complex *out, int64_t ld);
+
+/* Same operators, n individual entries (rows[i], cols[i]) of block (m, l).  */
+int pmchwt_get_entries(pmchwt_ctx *ctx, pmchwt_opkind op, pmchwt_medium medium, pmchwt_space space,
+                       int32_t m, int32_t l, int64_t n, const int32_t *rows, const int32_t *cols,
+                       pmchwt_complex *out);
+
+/* Mixed mass matrix M_A of scatterer m, row-major E_m x E_m (rows RWG i,
+ * columns BC j), real.                                                        */
+int pmchwt_get_mass(pmchwt_ctx *ctx, int32_t m, double *out);
+
+/* Galerkin right-hand side b_i = <(I/2 - D^i) u^inc, rwg_i> (Section 3.2) for
+ * nrhs plane waves E^inc = p exp(i k_e d.x): dirs double[nrhs*3] unit, pols
+ * pmchwt_complex[nrhs*3] with p.d = 0.  b_out[nrhs * N], N = unknowns.
+ * The incident traces enter the identity term exactly and D^i through their
+ * L2 projection onto RWG.                                                     */
+int pmchwt_rhs(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols, int32_t nrhs,
+               pmchwt_complex *b_out);
+
+/* y = Op x for nrhs vectors of length N.  which = 0: A, 1: the preconditioned
+ * product M_P^-1 P M_A^-1 A (A alone for P = I).                              */
+int pmchwt_apply(pmchwt_ctx *ctx, int32_t which, const pmchwt_complex *x, int32_t nrhs,
+                 pmchwt_complex *y);
+
+/* Solve for the scattered traces of nrhs incident plane waves (see
+ * pmchwt_rhs) with GMRES on the preconditioned system.  currents_out[nrhs*N].
+ * Returns PMCHWT_ERR_NOT_CONVERGED (outputs still written) if max_iter is
+ * reached before tol.  stats may be NULL.                                     */
+int pmchwt_solve(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols, int32_t nrhs,
+                 const pmchwt_solver_opts *opts, pmchwt_complex *currents_out,
+                 pmchwt_solve_stats *stats);
+
+/* Far-field pattern F with E^s ~ exp(i k_e r)/r F(xhat) (Stratton-Chu,
+ * Section 2) at nobs unit directions obs double[nobs*3], for nrhs current
+ * vectors: F_out[nrhs * nobs * 3].                                            */
+int pmchwt_far_field(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs,
+                     const double *obs, int32_t nobs, pmchwt_complex *F_out);
+
+/* Extinction (optical theorem, (4 pi / k_e) Im(p* . F(d))) and scattering
+ * (integral of |F|^2 over the sphere, 64 Gauss-Legendre nodes in cos(theta)
+ * x 128 uniform nodes in phi) cross sections for nrhs solutions.            */
+int pmchwt_cross_sections(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs,
+                          const double *dirs, const pmchwt_complex *pols, double *sigma_ext,
+                          double *sigma_sca);
+
+/* Host-only view of the Buffa-Christiansen construction (Section 3.2; no GPU
+ * and no context needed).  For a mesh (same conventions as
+ * pmchwt_add_scatterer) every BC function e restricted to a barycentric
+ * child c = 6 t + j of its support is an RT0 field  alpha x - w.  Writes
+ * `count` records: ids[2q] = e, ids[2q+1] = c, vals[4q..4q+3] =
+ * (alpha, wx, wy, wz).  Pass ids = vals = NULL to query count first; on the
+ * second call *count must hold the capacity.                                */
+int pmchwt_bc_fields(const double *verts, int32_t nv, const int32_t *tris, int32_t nt, int64_t *count,
+                     int32_t *ids, double *vals);
+
+/* Timings and work counters of the last assemble and solve. */
+int pmchwt_get_profile(const pmchwt_ctx *ctx, pmchwt_profile *out);
+
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char *pmchwt_last_error(const pmchwt_ctx *ctx);
+
+/* Free every device and host resource of ctx.  NULL is allowed. */
+void pmchwt_destroy(pmchwt_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMCHWT_H */

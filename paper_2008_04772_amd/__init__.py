@@ -1,0 +1,355 @@
+"""Python binding of libpmchwt.so, the MI355X (gfx950) PMCHWT library.
+
+Argument marshalling only: numpy arrays are passed as plain host pointers to
+the C ABI declared in include/pmchwt.h, whose entry points carry the same
+names.  Every computation runs in the library's HIP kernels.  Importing this
+module fails loudly when the shared library has not been built; there is no
+fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmchwt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libpmchwt.so is not built; run `python -m paper_2008_04772_amd.build` "
+        "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_OUT_OF_MEMORY, ERR_DEVICE = -1, -2, -3, -4
+ERR_NOT_CONVERGED, ERR_OVER_BUDGET, ERR_CANCELLED, ERR_STATE = -5, -6, -7, -8
+
+PRECOND = {"I": 0, "A": 1, "D": 2, "D_INT": 3, "D_EXT": 4, "S_INT": 5, "S_EXT": 6}
+FP64, MIXED = 0, 1
+OP_S, OP_C = 0, 1
+EXT, INT = 0, 1
+RWG, BC = 0, 1
+
+
+class pmchwt_complex(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class pmchwt_assembly_opts(ctypes.Structure):
+    _fields_ = [("q_near", ctypes.c_int32), ("q_medium", ctypes.c_int32), ("q_far", ctypes.c_int32),
+                ("n_singular", ctypes.c_int32), ("chi", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class pmchwt_solver_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("ir_max", ctypes.c_int32)]
+
+
+class pmchwt_solve_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("matvecs", ctypes.c_int64),
+                ("rel_residual", ctypes.c_double), ("ir_steps", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("ms_solve", ctypes.c_double)]
+
+
+class pmchwt_profile(ctypes.Structure):
+    _fields_ = [("ms_assemble_A", ctypes.c_double), ("ms_assemble_regular", ctypes.c_double),
+                ("ms_assemble_singular", ctypes.c_double), ("ms_assemble_P", ctypes.c_double),
+                ("ms_mass", ctypes.c_double), ("regular_pairs", ctypes.c_int64),
+                ("regular_point_pairs", ctypes.c_int64), ("singular_pairs", ctypes.c_int64),
+                ("singular_point_pairs", ctypes.c_int64), ("bary_pairs", ctypes.c_int64),
+                ("nnz_P", ctypes.c_int64), ("regular_launches", ctypes.c_int32),
+                ("n_wavenumbers", ctypes.c_int32), ("ms_matvec_total", ctypes.c_double),
+                ("matvec_launches", ctypes.c_int64), ("matvec_bytes", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pc = ctypes.POINTER(pmchwt_complex)
+
+_SIGS = {
+    "pmchwt_version": ([], ctypes.c_char_p),
+    "pmchwt_create": ([ctypes.POINTER(_P), ctypes.c_int, _P], ctypes.c_int),
+    "pmchwt_add_scatterer": ([_P, _pd, ctypes.c_int32, _pi32, ctypes.c_int32, pmchwt_complex, _pi32], ctypes.c_int),
+    "pmchwt_set_wavenumber": ([_P, ctypes.c_double], ctypes.c_int),
+    "pmchwt_sizes": ([_P, _pi32, _pi64], ctypes.c_int),
+    "pmchwt_num_edges": ([_P, ctypes.c_int32, _pi32], ctypes.c_int),
+    "pmchwt_assemble": ([_P, ctypes.POINTER(pmchwt_assembly_opts), ctypes.POINTER(pmchwt_assembly_opts),
+                         ctypes.c_int], ctypes.c_int),
+    "pmchwt_get_block": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, _pc,
+                          ctypes.c_int64], ctypes.c_int),
+    "pmchwt_get_entries": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int64, _pi32, _pi32, _pc], ctypes.c_int),
+    "pmchwt_get_mass": ([_P, ctypes.c_int32, _pd], ctypes.c_int),
+    "pmchwt_rhs": ([_P, _pd, _pc, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_apply": ([_P, ctypes.c_int32, _pc, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_solve": ([_P, _pd, _pc, ctypes.c_int32, ctypes.POINTER(pmchwt_solver_opts), _pc,
+                      ctypes.POINTER(pmchwt_solve_stats)], ctypes.c_int),
+    "pmchwt_far_field": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_cross_sections": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, _pd], ctypes.c_int),
+    "pmchwt_bc_fields": ([_pd, ctypes.c_int32, _pi32, ctypes.c_int32, _pi64, _pi32, _pd], ctypes.c_int),
+    "pmchwt_get_profile": ([_P, ctypes.POINTER(pmchwt_profile)], ctypes.c_int),
+    "pmchwt_last_error": ([_P], ctypes.c_char_p),
+    "pmchwt_destroy": ([_P], None),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class PmchwtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pmchwt error {code}: {msg}")
+        self.code = code
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _check(ctx, rc, allow=()):
+    if rc != OK and rc not in allow:
+        msg = _lib.pmchwt_last_error(ctx) if ctx else b""
+        raise PmchwtError(rc, (msg or b"").decode())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# Entry points, same names as the C ABI
+# ---------------------------------------------------------------------------
+
+def pmchwt_version():
+    return _lib.pmchwt_version().decode()
+
+
+def pmchwt_create(device=0, stream=None):
+    h = _P()
+    rc = _lib.pmchwt_create(ctypes.byref(h), int(device), _P(stream) if stream else None)
+    if rc != OK:
+        raise PmchwtError(rc, "pmchwt_create failed")
+    return h
+
+
+def pmchwt_destroy(ctx):
+    _lib.pmchwt_destroy(ctx)
+
+
+def pmchwt_add_scatterer(ctx, verts, tris, eps_r):
+    v = _f64(verts)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    sid = ctypes.c_int32(-1)
+    eps = complex(eps_r)
+    _check(ctx, _lib.pmchwt_add_scatterer(ctx, _ptr(v, _pd), len(v), _ptr(t, _pi32), len(t),
+                                          pmchwt_complex(eps.real, eps.imag), ctypes.byref(sid)))
+    return sid.value
+
+
+def pmchwt_set_wavenumber(ctx, k_ext):
+    _check(ctx, _lib.pmchwt_set_wavenumber(ctx, float(k_ext)))
+
+
+def pmchwt_sizes(ctx):
+    ns, nu = ctypes.c_int32(), ctypes.c_int64()
+    _check(ctx, _lib.pmchwt_sizes(ctx, ctypes.byref(ns), ctypes.byref(nu)))
+    return ns.value, nu.value
+
+
+def pmchwt_num_edges(ctx, m):
+    E = ctypes.c_int32()
+    _check(ctx, _lib.pmchwt_num_edges(ctx, int(m), ctypes.byref(E)))
+    return E.value
+
+
+def assembly_opts(q=(4, 3, 2), n_singular=4, chi=-1.0, precision=FP64):
+    return pmchwt_assembly_opts(int(q[0]), int(q[1]), int(q[2]), int(n_singular),
+                                float(chi) if chi is not None and np.isfinite(chi) else -1.0, int(precision))
+
+
+def pmchwt_assemble(ctx, optsA, optsP, precond="S_INT"):
+    kind = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    _check(ctx, _lib.pmchwt_assemble(ctx, ctypes.byref(optsA), ctypes.byref(optsP), kind))
+
+
+def pmchwt_get_block(ctx, op, medium, space, m, l):
+    Em, El = pmchwt_num_edges(ctx, m), pmchwt_num_edges(ctx, l)
+    out = np.zeros((Em, El), dtype=np.complex128)
+    _check(ctx, _lib.pmchwt_get_block(ctx, op, medium, space, m, l, _ptr(out, _pc), El))
+    return out
+
+
+def pmchwt_get_entries(ctx, op, medium, space, m, l, rows, cols):
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    out = np.zeros(len(r), dtype=np.complex128)
+    _check(ctx, _lib.pmchwt_get_entries(ctx, op, medium, space, m, l, len(r), _ptr(r, _pi32), _ptr(c, _pi32),
+                                        _ptr(out, _pc)))
+    return out
+
+
+def pmchwt_get_mass(ctx, m):
+    E = pmchwt_num_edges(ctx, m)
+    out = np.zeros((E, E))
+    _check(ctx, _lib.pmchwt_get_mass(ctx, m, _ptr(out, _pd)))
+    return out
+
+
+def _waves(dirs, pols):
+    d = _f64(dirs).reshape(-1, 3)
+    p = _c128(pols).reshape(-1, 3)
+    if len(d) != len(p):
+        raise ValueError("dirs and pols differ in length")
+    return d, p
+
+
+def pmchwt_rhs(ctx, dirs, pols):
+    d, p = _waves(dirs, pols)
+    _, N = pmchwt_sizes(ctx)
+    out = np.zeros((len(d), N), dtype=np.complex128)
+    _check(ctx, _lib.pmchwt_rhs(ctx, _ptr(d, _pd), _ptr(p, _pc), len(d), _ptr(out, _pc)))
+    return out
+
+
+def pmchwt_apply(ctx, which, x):
+    x = _c128(np.atleast_2d(x))
+    y = np.zeros_like(x)
+    _check(ctx, _lib.pmchwt_apply(ctx, int(which), _ptr(x, _pc), x.shape[0], _ptr(y, _pc)))
+    return y
+
+
+def solver_opts(tol=1e-6, restart=200, max_iter=2000, ir_max=0):
+    return pmchwt_solver_opts(float(tol), int(restart), int(max_iter), int(ir_max))
+
+
+def pmchwt_solve(ctx, dirs, pols, opts, allow_not_converged=False):
+    d, p = _waves(dirs, pols)
+    _, N = pmchwt_sizes(ctx)
+    out = np.zeros((len(d), N), dtype=np.complex128)
+    st = pmchwt_solve_stats()
+    allow = (ERR_NOT_CONVERGED,) if allow_not_converged else ()
+    _check(ctx, _lib.pmchwt_solve(ctx, _ptr(d, _pd), _ptr(p, _pc), len(d), ctypes.byref(opts), _ptr(out, _pc),
+                                  ctypes.byref(st)), allow)
+    return out, st
+
+
+def pmchwt_far_field(ctx, currents, obs):
+    x = _c128(np.atleast_2d(currents))
+    o = _f64(obs).reshape(-1, 3)
+    F = np.zeros((x.shape[0], len(o), 3), dtype=np.complex128)
+    _check(ctx, _lib.pmchwt_far_field(ctx, _ptr(x, _pc), x.shape[0], _ptr(o, _pd), len(o), _ptr(F, _pc)))
+    return F
+
+
+def pmchwt_cross_sections(ctx, currents, dirs, pols):
+    x = _c128(np.atleast_2d(currents))
+    d, p = _waves(dirs, pols)
+    se = np.zeros(x.shape[0])
+    ss = np.zeros(x.shape[0])
+    _check(ctx, _lib.pmchwt_cross_sections(ctx, _ptr(x, _pc), x.shape[0], _ptr(d, _pd), _ptr(p, _pc),
+                                           _ptr(se, _pd), _ptr(ss, _pd)))
+    return se, ss
+
+
+def pmchwt_bc_fields(verts, tris):
+    """Host-only: (edge ids, child ids, alpha, w) of every BC restriction."""
+    v = _f64(verts)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    n = ctypes.c_int64(0)
+    rc = _lib.pmchwt_bc_fields(_ptr(v, _pd), len(v), _ptr(t, _pi32), len(t), ctypes.byref(n), None, None)
+    if rc != OK:
+        raise PmchwtError(rc, "pmchwt_bc_fields failed")
+    ids = np.zeros((n.value, 2), dtype=np.int32)
+    vals = np.zeros((n.value, 4))
+    rc = _lib.pmchwt_bc_fields(_ptr(v, _pd), len(v), _ptr(t, _pi32), len(t), ctypes.byref(n), _ptr(ids, _pi32),
+                               _ptr(vals, _pd))
+    if rc != OK:
+        raise PmchwtError(rc, "pmchwt_bc_fields failed")
+    return ids[:, 0], ids[:, 1], vals[:, 0], vals[:, 1:]
+
+
+def pmchwt_get_profile(ctx):
+    p = pmchwt_profile()
+    _check(ctx, _lib.pmchwt_get_profile(ctx, ctypes.byref(p)))
+    return {f: getattr(p, f) for f, _ in pmchwt_profile._fields_}
+
+
+class Context:
+    """Owns one pmchwt context; methods forward to the entry points above."""
+
+    def __init__(self, device=0, stream=None):
+        self.h = pmchwt_create(device, stream)
+
+    def close(self):
+        if self.h:
+            pmchwt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_scatterer(self, verts, tris, eps_r):
+        return pmchwt_add_scatterer(self.h, verts, tris, eps_r)
+
+    def set_wavenumber(self, k):
+        pmchwt_set_wavenumber(self.h, k)
+
+    def sizes(self):
+        return pmchwt_sizes(self.h)
+
+    def num_edges(self, m):
+        return pmchwt_num_edges(self.h, m)
+
+    def assemble(self, optsA, optsP, precond="S_INT"):
+        pmchwt_assemble(self.h, optsA, optsP, precond)
+
+    def get_block(self, op, medium, space, m=0, l=0):
+        return pmchwt_get_block(self.h, op, medium, space, m, l)
+
+    def get_entries(self, op, medium, space, m, l, rows, cols):
+        return pmchwt_get_entries(self.h, op, medium, space, m, l, rows, cols)
+
+    def get_mass(self, m=0):
+        return pmchwt_get_mass(self.h, m)
+
+    def rhs(self, dirs, pols):
+        return pmchwt_rhs(self.h, dirs, pols)
+
+    def apply(self, which, x):
+        return pmchwt_apply(self.h, which, x)
+
+    def solve(self, dirs, pols, opts, allow_not_converged=False):
+        return pmchwt_solve(self.h, dirs, pols, opts, allow_not_converged)
+
+    def far_field(self, currents, obs):
+        return pmchwt_far_field(self.h, currents, obs)
+
+    def cross_sections(self, currents, dirs, pols):
+        return pmchwt_cross_sections(self.h, currents, dirs, pols)
+
+    def profile(self):
+        return pmchwt_get_profile(self.h)

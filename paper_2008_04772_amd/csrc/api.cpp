@@ -1,0 +1,1776 @@
+// C ABI of the PMCHWT library (include/pmchwt.h).
+//
+// Host side: mesh topology and dual-cell tables (geometry.cpp), pair lists,
+// quadrature tables, the near-field pattern, and the GMRES control flow
+// (Hessenberg matrix and Givens rotations of each right-hand side, a few
+// hundred scalars).  Device side: every integral, operator application,
+// orthogonalisation and vector update (kernels.hip), and the one-off dense LU
+// factorisations of the mass and Gram matrices (rocSOLVER).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pmchwt.h"
+#include "geometry.hpp"
+#include "kernels.hpp"
+
+using namespace pmchwt;
+using cd = std::complex<double>;
+
+namespace {
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct Scat {
+  Topo topo;
+  DualCells dual;
+  bool dual_built = false;
+  cd eps, k;
+  int edge_off = 0, tri_off = 0, vert_off = 0, cell_off = 0, child_off = 0, bvert_off = 0;
+};
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) throw Fail{PMCHWT_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+}  // namespace
+
+struct pmchwt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  double k_ext = 0.0;
+  std::vector<Scat> sc;
+  int F_tot = 0, E_tot = 0, nv_tot = 0;
+  bool geo_uploaded = false;
+  // union geometry (SoA)
+  DBuf tv, tcen, tdiam2, tarea, tvid, t2e, tsgn, tscat, edge_off, k_int;
+  // A
+  bool have_A = false;
+  int precA = PMCHWT_FP64;
+  DBuf Se, Ce;
+  std::vector<DBuf> Si, Ci;
+  DBuf Si_ptr, Ci_ptr, ld_int;
+  pmchwt_assembly_opts optA{}, optP{};
+  // P (near-field BC operators, CSR over union edge indices)
+  int precond = -1;
+  bool P_int = false, P_ext = false, P_C = false, P_cross = false;
+  int64_t nnzP = 0;
+  DBuf p_rowptr, p_col, PSi, PCi, PSe, PCe;
+  std::vector<int64_t> h_rowptr;
+  std::vector<int32_t> h_col;
+  // mass / Gram
+  std::vector<DBuf> MA, Minv, MinvT, Glu, Gpiv;
+  // work vectors
+  DBuf work;
+  size_t work_bytes = 0;
+  pmchwt_profile prof{};
+
+  ~pmchwt_ctx() {
+    if (blas) rocblas_destroy_handle(blas);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+template <typename T>
+DBuf dalloc(size_t n) {
+  DBuf b;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&b.p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{PMCHWT_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+  }
+  b.bytes = n * sizeof(T);
+  return b;
+}
+
+template <typename T>
+DBuf upload(pmchwt_ctx* c, const std::vector<T>& v) {
+  DBuf b = dalloc<T>(v.size());
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return b;
+}
+
+int fail(pmchwt_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <typename F>
+int guarded(pmchwt_ctx* c, F&& f) {
+  if (!c) return PMCHWT_ERR_INVALID_ARG;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    int rc = f();
+    if (rc == PMCHWT_OK) c->err.clear();
+    return rc;
+  } catch (const Fail& e) {
+    c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return PMCHWT_ERR_OUT_OF_MEMORY;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature tables (host copies; the kernels read them from constant memory
+// or from device tables).
+// ---------------------------------------------------------------------------
+void triangle_rules(double l[14][3], double w[14]) {
+  int k = 0;
+  auto orbit = [&](double beta, double wt) {
+    const double a = 1.0 - 2.0 * beta;
+    const double pts[3][3] = {{a, beta, beta}, {beta, a, beta}, {beta, beta, a}};
+    for (int i = 0; i < 3; ++i) {
+      for (int d = 0; d < 3; ++d) l[k][d] = pts[i][d];
+      w[k++] = wt;
+    }
+  };
+  // degree 1: centroid
+  l[k][0] = l[k][1] = l[k][2] = 1.0 / 3.0;
+  w[k++] = 1.0;
+  // degree 2: orbit (2/3, 1/6, 1/6)
+  orbit(1.0 / 6.0, 1.0 / 3.0);
+  // degree 3: centroid with weight -27/48 and orbit (3/5, 1/5, 1/5) with 25/48
+  l[k][0] = l[k][1] = l[k][2] = 1.0 / 3.0;
+  w[k++] = -27.0 / 48.0;
+  orbit(0.2, 25.0 / 48.0);
+  // degree 4: Dunavant's two-orbit six-point rule
+  orbit(0.44594849091596488632, 0.22338158967801146570);
+  orbit(0.091576213509770743460, 0.10995174365532186764);
+}
+
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double z1 = z;
+      z = z1 - p1 / pp;
+      if (std::fabs(z - z1) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// Sauter-Schwab rules on That x That, That = {0 <= x2 <= x1 <= 1}
+// (Sauter & Schwab, Boundary Element Methods, Sec. 5.2.1): identical panels
+// 6 regions with Jacobian xi^3 eta1^2 eta2, common edge (x2 = 0 shared) 5
+// regions (xi^3 eta1^2, then xi^3 eta1^2 eta2), common vertex (origin) 2
+// regions with xi^3 eta2.  Records (x1, x2, y1, y2, w).
+void sauter_schwab(int kind, int n, std::vector<double>& out) {
+  std::vector<double> g, gw;
+  gauss_legendre01(n, g, gw);
+  out.clear();
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < n; ++c)
+        for (int d = 0; d < n; ++d) {
+          const double xi = g[a], e1 = g[b], e2 = g[c], e3 = g[d];
+          const double wt = gw[a] * gw[b] * gw[c] * gw[d];
+          auto put = [&](double x1, double x2, double y1, double y2, double jac) {
+            out.push_back(x1);
+            out.push_back(x2);
+            out.push_back(y1);
+            out.push_back(y2);
+            out.push_back(wt * jac);
+          };
+          if (kind == 3) {
+            const double j = xi * xi * xi * e1 * e1 * e2;
+            put(xi, xi * (1 - e1 + e1 * e2), xi * (1 - e1 * e2 * e3), xi * (1 - e1), j);
+            put(xi * (1 - e1 * e2 * e3), xi * (1 - e1), xi, xi * (1 - e1 + e1 * e2), j);
+            put(xi, xi * e1 * (1 - e2 + e2 * e3), xi * (1 - e1 * e2), xi * e1 * (1 - e2), j);
+            put(xi * (1 - e1 * e2), xi * e1 * (1 - e2), xi, xi * e1 * (1 - e2 + e2 * e3), j);
+            put(xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3), xi, xi * e1 * (1 - e2), j);
+            put(xi, xi * e1 * (1 - e2), xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3), j);
+          } else if (kind == 2) {
+            const double j1 = xi * xi * xi * e1 * e1, j2 = j1 * e2;
+            put(xi, xi * e1 * e3, xi * (1 - e1 * e2), xi * e1 * (1 - e2), j1);
+            put(xi, xi * e1, xi * (1 - e1 * e2 * e3), xi * e1 * e2 * (1 - e3), j2);
+            put(xi * (1 - e1 * e2), xi * e1 * (1 - e2), xi, xi * e1 * e2 * e3, j2);
+            put(xi * (1 - e1 * e2 * e3), xi * e1 * e2 * (1 - e3), xi, xi * e1, j2);
+            put(xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3), xi, xi * e1 * e2, j2);
+          } else {
+            const double j = xi * xi * xi * e2;
+            put(xi, xi * e1, xi * e2, xi * e2 * e3, j);
+            put(xi * e2, xi * e2 * e3, xi, xi * e1, j);
+          }
+        }
+}
+
+struct SSTables {
+  DBuf tab[4];
+  int npts[4] = {0, 0, 0, 0};
+  int n = -1;
+};
+
+void build_ss(pmchwt_ctx* c, int n, SSTables& t) {
+  for (int kind = 1; kind <= 3; ++kind) {
+    std::vector<double> v;
+    sauter_schwab(kind, n, v);
+    t.npts[kind] = int(v.size() / 5);
+    t.tab[kind] = upload(c, v);
+  }
+  t.n = n;
+}
+
+void check_opts(const pmchwt_assembly_opts* o, const char* which) {
+  if (!o) throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + " options are NULL"};
+  auto okq = [](int q) { return q >= 1 && q <= 4; };
+  if (!okq(o->q_near) || !okq(o->q_medium) || !okq(o->q_far))
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": quadrature orders must be 1..4"};
+  if (o->n_singular < 1 || o->n_singular > 8)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": n_singular must be 1..8"};
+  if (o->precision != PMCHWT_FP64 && o->precision != PMCHWT_MIXED)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": unknown precision"};
+}
+
+// ---------------------------------------------------------------------------
+// Union geometry upload
+// ---------------------------------------------------------------------------
+void upload_geometry(pmchwt_ctx* c) {
+  if (c->geo_uploaded) return;
+  const int F = c->F_tot;
+  std::vector<double> tv(9 * size_t(F)), tcen(3 * size_t(F)), tdiam2(F), tarea(F);
+  std::vector<int32_t> tvid(3 * size_t(F)), t2e(3 * size_t(F)), tscat(F), eoff, kint_dummy;
+  std::vector<int8_t> tsgn(3 * size_t(F));
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const Topo& T = s.topo;
+    for (int f = 0; f < T.F; ++f) {
+      const int g = s.tri_off + f;
+      double P[3][3];
+      for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) {
+          P[k][d] = T.v[3 * size_t(T.t[3 * f + k]) + d];
+          tv[size_t(3 * k + d) * F + g] = P[k][d];
+        }
+      for (int d = 0; d < 3; ++d) tcen[size_t(d) * F + g] = (P[0][d] + P[1][d] + P[2][d]) / 3.0;
+      double dm = 0.0;
+      const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+      for (auto& q : pr) {
+        const double ex = P[q[0]][0] - P[q[1]][0], ey = P[q[0]][1] - P[q[1]][1], ez = P[q[0]][2] - P[q[1]][2];
+        const double e2 = ex * ex + ey * ey + ez * ez;
+        dm = std::max(dm, e2);
+      }
+      tdiam2[g] = dm;
+      tarea[g] = T.area[f];
+      for (int a = 0; a < 3; ++a) {
+        tvid[size_t(a) * F + g] = s.vert_off + T.t[3 * f + a];
+        t2e[size_t(a) * F + g] = s.edge_off + T.t2e[3 * f + a];
+        tsgn[size_t(a) * F + g] = T.sgn[3 * f + a];
+      }
+      tscat[g] = int32_t(m);
+    }
+    eoff.push_back(s.edge_off);
+  }
+  c->tv = upload(c, tv);
+  c->tcen = upload(c, tcen);
+  c->tdiam2 = upload(c, tdiam2);
+  c->tarea = upload(c, tarea);
+  c->tvid = upload(c, tvid);
+  c->t2e = upload(c, t2e);
+  c->tsgn = upload(c, tsgn);
+  c->tscat = upload(c, tscat);
+  c->edge_off = upload(c, eoff);
+  c->geo_uploaded = true;
+}
+
+void upload_k(pmchwt_ctx* c) {
+  std::vector<double> k;
+  for (auto& s : c->sc) {
+    s.k = c->k_ext * std::sqrt(s.eps);
+    k.push_back(s.k.real());
+    k.push_back(s.k.imag());
+  }
+  c->k_int = upload(c, k);
+}
+
+template <typename M>
+AsmParams<M> asm_params(pmchwt_ctx* c) {
+  AsmParams<M> p{};
+  p.F = c->F_tot;
+  p.tv = c->tv.as<double>();
+  p.tcen = c->tcen.as<double>();
+  p.tdiam2 = c->tdiam2.as<double>();
+  p.tarea = c->tarea.as<double>();
+  p.tvid = c->tvid.as<int32_t>();
+  p.t2e = c->t2e.as<int32_t>();
+  p.tsgn = c->tsgn.as<int8_t>();
+  p.tscat = c->tscat.as<int32_t>();
+  p.edge_off = c->edge_off.as<int32_t>();
+  p.k_int = c->k_int.as<double>();
+  p.k_ext = c->k_ext;
+  p.Se = c->Se.as<M>();
+  p.Ce = c->Ce.as<M>();
+  p.ld_ext = c->E_tot;
+  p.Si = c->Si_ptr.as<M*>();
+  p.Ci = c->Ci_ptr.as<M*>();
+  p.ld_int = c->ld_int.as<int64_t>();
+  return p;
+}
+
+struct EvTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit EvTimer(hipStream_t st) : s(st) {
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, s));
+  }
+  double stop() {
+    HIPCHK(hipEventRecord(b, s));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+  ~EvTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Assembly of A
+// ---------------------------------------------------------------------------
+template <typename M>
+void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
+  const int64_t E = c->E_tot;
+  c->Se = dalloc<M>(size_t(2 * E * E));
+  c->Ce = dalloc<M>(size_t(2 * E * E));
+  std::vector<M*> sp, cp;
+  std::vector<int64_t> lds;
+  c->Si.clear();
+  c->Ci.clear();
+  for (auto& s : c->sc) {
+    const int64_t Em = s.topo.E;
+    c->Si.push_back(dalloc<M>(size_t(2 * Em * Em)));
+    c->Ci.push_back(dalloc<M>(size_t(2 * Em * Em)));
+    sp.push_back(c->Si.back().as<M>());
+    cp.push_back(c->Ci.back().as<M>());
+    lds.push_back(Em);
+  }
+  c->Si_ptr = upload(c, sp);
+  c->Ci_ptr = upload(c, cp);
+  c->ld_int = upload(c, lds);
+  auto zero = [&](DBuf& b) {
+    if (sizeof(M) == 8)
+      launch_zero(reinterpret_cast<double*>(b.p), int64_t(b.bytes / 8), c->stream);
+    else
+      launch_zero_f(reinterpret_cast<float*>(b.p), int64_t(b.bytes / 4), c->stream);
+  };
+  zero(c->Se);
+  zero(c->Ce);
+  for (auto& b : c->Si) zero(b);
+  for (auto& b : c->Ci) zero(b);
+
+  AsmParams<M> p = asm_params<M>(c);
+  p.q_near = o.q_near;
+  p.q_medium = o.q_medium;
+  p.q_far = o.q_far;
+
+  // singular pair list: ordered pairs sharing at least one vertex
+  std::vector<std::vector<int32_t>> v2t(c->nv_tot);
+  for (auto& s : c->sc)
+    for (int f = 0; f < s.topo.F; ++f)
+      for (int a = 0; a < 3; ++a) v2t[s.vert_off + s.topo.t[3 * f + a]].push_back(s.tri_off + f);
+  std::vector<int32_t> pairs;
+  int64_t npts_sing = 0;
+  SSTables ss;
+  build_ss(c, o.n_singular, ss);
+  for (auto& s : c->sc)
+    for (int f = 0; f < s.topo.F; ++f) {
+      const int g = s.tri_off + f;
+      std::vector<int32_t> nb;
+      for (int a = 0; a < 3; ++a)
+        for (int t : v2t[s.vert_off + s.topo.t[3 * f + a]]) nb.push_back(t);
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      for (int t : nb) {
+        pairs.push_back(g);
+        pairs.push_back(t);
+        int shared = 0;
+        const int t_loc = t - s.tri_off;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) shared += (s.topo.t[3 * f + a] == s.topo.t[3 * t_loc + b]);
+        npts_sing += ss.npts[shared];
+      }
+    }
+  DBuf dpairs = upload(c, pairs);
+  SingParams sp_{};
+  sp_.npairs = int64_t(pairs.size() / 2);
+  sp_.pairs = dpairs.as<int32_t>();
+  for (int k = 1; k <= 3; ++k) {
+    sp_.tab[k] = ss.tab[k].as<double>();
+    sp_.npts[k] = ss.npts[k];
+  }
+  EvTimer all(c->stream);
+  {
+    EvTimer t(c->stream);
+    if (sizeof(M) == 8)
+      launch_regular<double, M>(p, 0, c->F_tot, c->stream);
+    else
+      launch_regular<float, M>(p, 0, c->F_tot, c->stream);
+    HIPCHK(hipGetLastError());
+    c->prof.ms_assemble_regular = t.stop();
+  }
+  {
+    EvTimer t(c->stream);
+    launch_singular<M>(p, sp_, c->stream);
+    HIPCHK(hipGetLastError());
+    c->prof.ms_assemble_singular = t.stop();
+  }
+  c->prof.ms_assemble_A = all.stop();
+  c->prof.regular_launches = (c->F_tot + 65534) / 65535;
+  // work counters: disjoint ordered pairs by class (host count, same rule as the kernel)
+  int64_t reg_pairs = 0, reg_pts = 0;
+  {
+    const int F = c->F_tot;
+    std::vector<double> cen(3 * size_t(F)), dm(F);
+    std::vector<std::array<int32_t, 3>> vid(F);
+    std::vector<int32_t> scat(F);
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      for (int f = 0; f < s.topo.F; ++f) {
+        const int g = s.tri_off + f;
+        double P[3][3];
+        for (int k = 0; k < 3; ++k)
+          for (int d = 0; d < 3; ++d) P[k][d] = s.topo.v[3 * size_t(s.topo.t[3 * f + k]) + d];
+        for (int d = 0; d < 3; ++d) cen[3 * size_t(g) + d] = (P[0][d] + P[1][d] + P[2][d]) / 3.0;
+        double mm = 0;
+        const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+        for (auto& q : pr) {
+          const double ex = P[q[0]][0] - P[q[1]][0], ey = P[q[0]][1] - P[q[1]][1], ez = P[q[0]][2] - P[q[1]][2];
+          mm = std::max(mm, ex * ex + ey * ey + ez * ez);
+        }
+        dm[g] = mm;
+        for (int a = 0; a < 3; ++a) vid[g][a] = s.vert_off + s.topo.t[3 * f + a];
+      }
+    }
+    const int np[5] = {0, 1, 3, 4, 6};
+    const int qs[3] = {o.q_near, o.q_medium, o.q_far};
+    // sample-free exact count over all pairs (host, O(F^2) integer/compare work)
+    for (int a = 0; a < F; ++a)
+      for (int b = a + 1; b < F; ++b) {
+        bool sh = false;
+        for (int i = 0; i < 3 && !sh; ++i)
+          for (int j = 0; j < 3; ++j) sh |= (vid[a][i] == vid[b][j]);
+        if (sh) continue;
+        const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1], dz = cen[3 * a + 2] - cen[3 * b + 2];
+        const double d2 = dx * dx + dy * dy + dz * dz, m2 = std::max(dm[a], dm[b]);
+        const int cls = d2 < 4.0 * m2 ? 0 : (d2 < 16.0 * m2 ? 1 : 2);
+        reg_pairs += 2;
+        reg_pts += 2 * int64_t(np[qs[cls]]) * np[qs[cls]];
+      }
+  }
+  c->prof.regular_pairs = reg_pairs;
+  c->prof.regular_point_pairs = reg_pts;
+  c->prof.singular_pairs = sp_.npairs;
+  c->prof.singular_point_pairs = npts_sing;
+  c->prof.n_wavenumbers = 2;
+}
+
+// ---------------------------------------------------------------------------
+// Dual cells and near-field BC operators of P
+// ---------------------------------------------------------------------------
+struct CellDev {
+  DBuf cell_ptr, ring, child_v, child_vid, child_cen, child_diam2, child_area, coef_ptr, coef, cell_scat;
+  DBuf child_cell, child_pos, child_parent, inc_ptr, inc_edges, edge_scat, edge_off;
+  int nchild = 0, ncell = 0;
+  CellParams params() const {
+    CellParams p{};
+    p.cell_ptr = cell_ptr.as<int32_t>();
+    p.ring = ring.as<int32_t>();
+    p.child_v = child_v.as<double>();
+    p.child_vid = child_vid.as<int32_t>();
+    p.child_cen = child_cen.as<double>();
+    p.child_diam2 = child_diam2.as<double>();
+    p.child_area = child_area.as<double>();
+    p.coef_ptr = coef_ptr.as<int64_t>();
+    p.coef = coef.as<double>();
+    p.cell_scat = cell_scat.as<int32_t>();
+    return p;
+  }
+};
+
+void build_duals(pmchwt_ctx* c) {
+  int cell_off = 0, child_off = 0, bvert_off = 0;
+  for (auto& s : c->sc) {
+    if (!s.dual_built) {
+      std::string err;
+      if (!build_dual(s.topo, s.dual, err)) throw Fail{PMCHWT_ERR_INVALID_MESH, err};
+      if (s.dual.max_valence > 16) throw Fail{PMCHWT_ERR_INVALID_MESH, "vertex valence above 16"};
+      s.dual_built = true;
+    }
+    s.cell_off = cell_off;
+    s.child_off = child_off;
+    s.bvert_off = bvert_off;
+    cell_off += s.topo.nv;
+    child_off += 6 * s.topo.F;
+    bvert_off += s.dual.nbv;
+  }
+}
+
+void upload_cells(pmchwt_ctx* c, CellDev& d) {
+  std::vector<int32_t> cell_ptr{0}, ring, child_vid, cell_scat, child_cell, child_pos, child_parent, inc_ptr{0},
+      inc_edges, edge_scat;
+  std::vector<double> child_v, child_cen, child_diam2, child_area, coef;
+  std::vector<int64_t> coef_ptr{0};
+  std::vector<int32_t> eoff;
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const DualCells& D = s.dual;
+    const Topo& T = s.topo;
+    eoff.push_back(s.edge_off);
+    for (int e = 0; e < T.E; ++e) edge_scat.push_back(int32_t(m));
+    for (int ch = 0; ch < 6 * T.F; ++ch) {
+      double P[3][3];
+      for (int k = 0; k < 3; ++k) {
+        const int id = D.child_vid[3 * size_t(ch) + k];
+        child_vid.push_back(s.bvert_off + id);
+        for (int dd = 0; dd < 3; ++dd) {
+          P[k][dd] = D.bv[3 * size_t(id) + dd];
+          child_v.push_back(P[k][dd]);
+        }
+      }
+      for (int dd = 0; dd < 3; ++dd) child_cen.push_back((P[0][dd] + P[1][dd] + P[2][dd]) / 3.0);
+      double mm = 0;
+      const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+      for (auto& q : pr) {
+        const double ex = P[q[0]][0] - P[q[1]][0], ey = P[q[0]][1] - P[q[1]][1], ez = P[q[0]][2] - P[q[1]][2];
+        mm = std::max(mm, ex * ex + ey * ey + ez * ez);
+      }
+      child_diam2.push_back(mm);
+      const double u[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+      const double w[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+      const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      child_area.push_back(0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]));
+      child_parent.push_back(s.tri_off + ch / 6);
+    }
+    child_cell.resize(child_cell.size() + 6 * size_t(T.F));
+    child_pos.resize(child_pos.size() + 6 * size_t(T.F));
+    for (int v = 0; v < T.nv; ++v) {
+      const int n2 = D.cell_ptr[v + 1] - D.cell_ptr[v];
+      for (int i = 0; i < n2; ++i) {
+        const int ch = D.ring[D.cell_ptr[v] + i];
+        ring.push_back(s.child_off + ch);
+        child_cell[s.child_off + ch] = s.cell_off + v;
+        child_pos[s.child_off + ch] = i;
+      }
+      cell_ptr.push_back(cell_ptr.back() + n2);
+      for (int q = D.inc_ptr[v]; q < D.inc_ptr[v + 1]; ++q) inc_edges.push_back(s.edge_off + D.inc_edges[q]);
+      inc_ptr.push_back(int32_t(inc_edges.size()));
+      const int64_t recs = D.coef_ptr[v + 1] - D.coef_ptr[v];
+      for (int64_t r = 0; r < 4 * recs; ++r) coef.push_back(D.coef[4 * size_t(D.coef_ptr[v]) + r]);
+      coef_ptr.push_back(coef_ptr.back() + recs);
+      cell_scat.push_back(int32_t(m));
+    }
+  }
+  d.ncell = int(cell_scat.size());
+  d.nchild = int(child_area.size());
+  d.cell_ptr = upload(c, cell_ptr);
+  d.ring = upload(c, ring);
+  d.child_v = upload(c, child_v);
+  d.child_vid = upload(c, child_vid);
+  d.child_cen = upload(c, child_cen);
+  d.child_diam2 = upload(c, child_diam2);
+  d.child_area = upload(c, child_area);
+  d.coef_ptr = upload(c, coef_ptr);
+  d.coef = upload(c, coef);
+  d.cell_scat = upload(c, cell_scat);
+  d.child_cell = upload(c, child_cell);
+  d.child_pos = upload(c, child_pos);
+  d.child_parent = upload(c, child_parent);
+  d.inc_ptr = upload(c, inc_ptr);
+  d.inc_edges = upload(c, inc_edges);
+  d.edge_scat = upload(c, edge_scat);
+  d.edge_off = upload(c, eoff);
+}
+
+// Kept entries of P: (i, j) with dist(bbox_i, bbox_j) <= chi (chi < 0: all),
+// restricted to diagonal scatterer blocks unless `cross`.
+void build_pattern(pmchwt_ctx* c, double chi, bool cross, std::vector<int64_t>& rowptr, std::vector<int32_t>& col) {
+  const int E = c->E_tot;
+  std::vector<double> lo(3 * size_t(E)), hi(3 * size_t(E));
+  std::vector<int32_t> scat(E);
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    for (int e = 0; e < s.topo.E; ++e) {
+      for (int d = 0; d < 3; ++d) {
+        lo[3 * size_t(s.edge_off + e) + d] = s.dual.bbox[6 * size_t(e) + d];
+        hi[3 * size_t(s.edge_off + e) + d] = s.dual.bbox[6 * size_t(e) + 3 + d];
+      }
+      scat[s.edge_off + e] = int32_t(m);
+    }
+  }
+  rowptr.assign(1, 0);
+  col.clear();
+  auto keep = [&](int i, int j) {
+    if (!cross && scat[i] != scat[j]) return false;
+    if (chi < 0) return true;
+    double g2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double g = std::max(0.0, std::max(lo[3 * size_t(j) + d] - hi[3 * size_t(i) + d],
+                                              lo[3 * size_t(i) + d] - hi[3 * size_t(j) + d]));
+      g2 = g2 + g * g;
+    }
+    return std::sqrt(g2) <= chi;
+  };
+  if (chi < 0) {
+    for (int i = 0; i < E; ++i) {
+      for (int j = 0; j < E; ++j)
+        if (keep(i, j)) col.push_back(j);
+      rowptr.push_back(int64_t(col.size()));
+    }
+    return;
+  }
+  // uniform grid on box centres; cell size >= chi + largest box extent
+  double ext = 0.0, gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {-1e300, -1e300, -1e300};
+  for (int e = 0; e < E; ++e)
+    for (int d = 0; d < 3; ++d) {
+      ext = std::max(ext, hi[3 * size_t(e) + d] - lo[3 * size_t(e) + d]);
+      const double ce = 0.5 * (lo[3 * size_t(e) + d] + hi[3 * size_t(e) + d]);
+      gmin[d] = std::min(gmin[d], ce);
+      gmax[d] = std::max(gmax[d], ce);
+    }
+  const double h = chi + ext + 1e-12;
+  int dims[3];
+  for (int d = 0; d < 3; ++d) dims[d] = std::max(1, std::min(1024, int((gmax[d] - gmin[d]) / h) + 1));
+  auto cell_of = [&](int e, int* ijk) {
+    for (int d = 0; d < 3; ++d) {
+      const double ce = 0.5 * (lo[3 * size_t(e) + d] + hi[3 * size_t(e) + d]);
+      ijk[d] = std::min(dims[d] - 1, std::max(0, int((ce - gmin[d]) / h)));
+    }
+  };
+  std::unordered_map<int64_t, std::vector<int32_t>> grid;
+  for (int e = 0; e < E; ++e) {
+    int ijk[3];
+    cell_of(e, ijk);
+    grid[(int64_t(ijk[0]) * dims[1] + ijk[1]) * dims[2] + ijk[2]].push_back(e);
+  }
+  std::vector<int32_t> row;
+  for (int i = 0; i < E; ++i) {
+    int ijk[3];
+    cell_of(i, ijk);
+    row.clear();
+    for (int a = -1; a <= 1; ++a)
+      for (int b = -1; b <= 1; ++b)
+        for (int q = -1; q <= 1; ++q) {
+          const int x = ijk[0] + a, y = ijk[1] + b, z = ijk[2] + q;
+          if (x < 0 || y < 0 || z < 0 || x >= dims[0] || y >= dims[1] || z >= dims[2]) continue;
+          auto it = grid.find((int64_t(x) * dims[1] + y) * dims[2] + z);
+          if (it == grid.end()) continue;
+          for (int j : it->second)
+            if (keep(i, j)) row.push_back(j);
+        }
+    std::sort(row.begin(), row.end());
+    col.insert(col.end(), row.begin(), row.end());
+    rowptr.push_back(int64_t(col.size()));
+  }
+}
+
+void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, CellDev& cells) {
+  c->PSi.release();
+  c->PCi.release();
+  c->PSe.release();
+  c->PCe.release();
+  c->precond = kind;
+  c->P_int = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_INT || kind == PMCHWT_P_S_INT);
+  c->P_ext = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_EXT || kind == PMCHWT_P_S_EXT);
+  c->P_C = !(kind == PMCHWT_P_S_INT || kind == PMCHWT_P_S_EXT);
+  c->P_cross = (kind == PMCHWT_P_A && c->sc.size() > 1);
+  c->nnzP = 0;
+  c->prof.ms_assemble_P = 0;
+  c->prof.bary_pairs = 0;
+  if (kind == PMCHWT_P_I) return;
+  build_pattern(c, o.chi, c->P_cross, c->h_rowptr, c->h_col);
+  c->nnzP = int64_t(c->h_col.size());
+  c->p_rowptr = upload(c, c->h_rowptr);
+  c->p_col = upload(c, c->h_col);
+  // per union edge: its two end cells and its slot in each
+  const int E = c->E_tot;
+  std::vector<int32_t> ecell(2 * size_t(E)), eslot(2 * size_t(E)), cell_n;
+  std::vector<int32_t> cell_first_child;
+  for (auto& s : c->sc) {
+    const DualCells& D = s.dual;
+    for (int v = 0; v < s.topo.nv; ++v) {
+      cell_n.push_back((D.cell_ptr[v + 1] - D.cell_ptr[v]) / 2);
+      for (int q = D.inc_ptr[v]; q < D.inc_ptr[v + 1]; ++q) {
+        const int e = s.edge_off + D.inc_edges[q];
+        const int end = (s.topo.edges[2 * size_t(D.inc_edges[q])] == v) ? 0 : 1;
+        ecell[2 * size_t(e) + end] = s.cell_off + v;
+        eslot[2 * size_t(e) + end] = q - D.inc_ptr[v];
+      }
+    }
+  }
+  std::unordered_map<int64_t, int64_t> pair_index;
+  std::vector<int32_t> cpairs;
+  std::vector<int64_t> slot_off{0}, slot_pos;
+  const int64_t ncell = int64_t(cell_n.size());
+  for (int i = 0; i < E; ++i)
+    for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) {
+      const int j = c->h_col[p];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          const int cv = ecell[2 * size_t(i) + a], cw = ecell[2 * size_t(j) + b];
+          const int64_t key = int64_t(cv) * ncell + cw;
+          auto it = pair_index.find(key);
+          int64_t idx;
+          if (it == pair_index.end()) {
+            idx = int64_t(cpairs.size() / 2);
+            pair_index.emplace(key, idx);
+            cpairs.push_back(cv);
+            cpairs.push_back(cw);
+            const int64_t ns = int64_t(cell_n[cv]) * cell_n[cw];
+            slot_off.push_back(slot_off.back() + ns);
+            slot_pos.resize(slot_pos.size() + ns, -1);
+          } else {
+            idx = it->second;
+          }
+          slot_pos[slot_off[idx] + int64_t(eslot[2 * size_t(i) + a]) * cell_n[cw] + eslot[2 * size_t(j) + b]] = p;
+        }
+    }
+  int64_t bary_pairs = 0;
+  for (size_t q = 0; q < cpairs.size(); q += 2) bary_pairs += int64_t(4) * cell_n[cpairs[q]] * cell_n[cpairs[q + 1]];
+  c->prof.bary_pairs = bary_pairs;
+  DBuf d_cp = upload(c, cpairs), d_so = upload(c, slot_off), d_sp = upload(c, slot_pos);
+  auto vals = [&](DBuf& b) {
+    b = dalloc<double>(2 * size_t(c->nnzP));
+    launch_zero(b.as<double>(), 2 * c->nnzP, c->stream);
+  };
+  if (c->P_int) {
+    vals(c->PSi);
+    if (c->P_C) vals(c->PCi);
+  }
+  if (c->P_ext) {
+    vals(c->PSe);
+    if (c->P_C) vals(c->PCe);
+  }
+  SSTables ss;
+  build_ss(c, o.n_singular, ss);
+  BCJob j{};
+  j.npairs = int64_t(cpairs.size() / 2);
+  j.cpairs = d_cp.as<int32_t>();
+  j.slot_off = d_so.as<int64_t>();
+  j.slot_pos = d_sp.as<int64_t>();
+  j.want_int = c->P_int;
+  j.want_ext = c->P_ext;
+  j.want_C = c->P_C;
+  j.k_int = c->k_int.as<double>();
+  j.k_ext = c->k_ext;
+  j.q_near = o.q_near;
+  j.q_medium = o.q_medium;
+  j.q_far = o.q_far;
+  j.n_sing = o.n_singular;
+  for (int k = 1; k <= 3; ++k) {
+    j.tab[k] = ss.tab[k].as<double>();
+    j.npts[k] = ss.npts[k];
+  }
+  j.out_Si = c->PSi.as<double>();
+  j.out_Ci = c->PCi.as<double>();
+  j.out_Se = c->PSe.as<double>();
+  j.out_Ce = c->PCe.as<double>();
+  EvTimer t(c->stream);
+  if (j.npairs > 0) launch_bc_nearfield(asm_params<double>(c), cells.params(), j, c->stream);
+  HIPCHK(hipGetLastError());
+  c->prof.ms_assemble_P = t.stop();
+  c->prof.nnz_P = c->nnzP;
+}
+
+void rocsolver_check(rocblas_status s, const char* what) {
+  if (s != rocblas_status_success) throw Fail{PMCHWT_ERR_DEVICE, std::string(what) + " failed"};
+}
+
+void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
+  EvTimer t(c->stream);
+  c->MA.clear();
+  c->Minv.clear();
+  c->MinvT.clear();
+  c->Glu.clear();
+  c->Gpiv.clear();
+  std::vector<int64_t> off, ld;
+  int64_t tot = 0;
+  for (auto& s : c->sc) {
+    off.push_back(tot);
+    ld.push_back(s.topo.E);
+    tot += int64_t(s.topo.E) * s.topo.E;
+  }
+  DBuf d_off = upload(c, off), d_ld = upload(c, ld);
+  DBuf mass = dalloc<double>(size_t(tot)), gram = dalloc<double>(size_t(tot));
+  launch_zero(mass.as<double>(), tot, c->stream);
+  launch_zero(gram.as<double>(), tot, c->stream);
+  MassJob mj{};
+  mj.nchild = cells.nchild;
+  mj.child_cell = cells.child_cell.as<int32_t>();
+  mj.child_pos = cells.child_pos.as<int32_t>();
+  mj.child_parent = cells.child_parent.as<int32_t>();
+  mj.inc_ptr = cells.inc_ptr.as<int32_t>();
+  mj.inc_edges = cells.inc_edges.as<int32_t>();
+  mj.edge_scat = cells.edge_scat.as<int32_t>();
+  mj.edge_off = cells.edge_off.as<int32_t>();
+  mj.mat_off = d_off.as<int64_t>();
+  mj.ld = d_ld.as<int64_t>();
+  mj.out = mass.as<double>();
+  AsmParams<double> g = asm_params<double>(c);
+  launch_mass(g, cells.params(), mj, c->stream);
+  mj.out = gram.as<double>();
+  launch_gram(g, mj, c->stream);
+  HIPCHK(hipGetLastError());
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const int n = c->sc[m].topo.E;
+    const size_t nn = size_t(n) * n;
+    DBuf MA = dalloc<double>(nn), Mi = dalloc<double>(nn), MiT = dalloc<double>(nn), G = dalloc<double>(nn);
+    HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(G.p, gram.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    DBuf piv = dalloc<rocblas_int>(size_t(n)), info = dalloc<rocblas_int>(1), gpiv = dalloc<rocblas_int>(size_t(n));
+    // row-major M_A is column-major M_A^T; inverting it in place yields the
+    // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
+    rocsolver_check(rocsolver_dgetrf(c->blas, n, n, Mi.as<double>(), n, piv.as<rocblas_int>(), info.as<rocblas_int>()),
+                    "rocsolver_dgetrf(mass)");
+    rocsolver_check(rocsolver_dgetri(c->blas, n, Mi.as<double>(), n, piv.as<rocblas_int>(), info.as<rocblas_int>()),
+                    "rocsolver_dgetri(mass)");
+    rocblas_int hinfo = 0;
+    HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hinfo != 0) throw Fail{PMCHWT_ERR_DEVICE, "mixed mass matrix is singular"};
+    launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
+    rocsolver_check(rocsolver_dgetrf(c->blas, n, n, G.as<double>(), n, gpiv.as<rocblas_int>(), info.as<rocblas_int>()),
+                    "rocsolver_dgetrf(gram)");
+    HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hinfo != 0) throw Fail{PMCHWT_ERR_DEVICE, "RWG Gram matrix is singular"};
+    c->MA.push_back(std::move(MA));
+    c->Minv.push_back(std::move(Mi));
+    c->MinvT.push_back(std::move(MiT));
+    c->Glu.push_back(std::move(G));
+    c->Gpiv.push_back(std::move(gpiv));
+  }
+  c->prof.ms_mass = t.stop();
+}
+
+// ---------------------------------------------------------------------------
+// Operator application.  Internal vectors: [rhs][D (E_tot) ; N (E_tot)] complex128.
+// ---------------------------------------------------------------------------
+int64_t vlen(const pmchwt_ctx* c) { return 2 * int64_t(c->E_tot); }
+
+double* need_work(pmchwt_ctx* c, size_t doubles) {
+  if (c->work_bytes < doubles * 8) {
+    c->work = dalloc<double>(doubles);
+    c->work_bytes = doubles * 8;
+  }
+  return c->work.as<double>();
+}
+
+int64_t A_matvecs(const pmchwt_ctx* c) {
+  const int64_t M = int64_t(c->sc.size());
+  return 4 * M * M + 4 * M;
+}
+
+int64_t P_matvecs(const pmchwt_ctx* c) {
+  const int64_t M = int64_t(c->sc.size());
+  switch (c->precond) {
+    case PMCHWT_P_A: return 4 * M * M + 4 * M;
+    case PMCHWT_P_D: return 8 * M;
+    case PMCHWT_P_D_INT:
+    case PMCHWT_P_D_EXT: return 4 * M;
+    case PMCHWT_P_S_INT:
+    case PMCHWT_P_S_EXT: return 2 * M;
+    default: return 0;
+  }
+}
+
+// y = A x (y overwritten)
+void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  launch_zero(y, 2 * vs * nrhs, c->stream);
+  EvTimer t(c->stream);
+  if (c->precA == PMCHWT_FP64) {
+    launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), E, int(E), int(E), c->k_ext, 0.0, x,
+                               x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), s.topo.E, s.topo.E, s.topo.E,
+                                 s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
+                                 vs, c->stream);
+    }
+  } else {
+    launch_gemv_pmchwt<float>(c->Se.as<float>(), c->Ce.as<float>(), E, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
+                              y, y + 2 * E, nrhs, vs, c->stream);
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), s.topo.E, s.topo.E, s.topo.E,
+                                s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
+                                vs, c->stream);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  c->prof.ms_matvec_total += t.stop();
+  c->prof.matvec_launches += 1 + int64_t(c->sc.size());
+  int64_t bytes = 2 * E * E;
+  for (auto& s : c->sc) bytes += 2 * int64_t(s.topo.E) * s.topo.E;
+  c->prof.matvec_bytes += bytes * (c->precA == PMCHWT_FP64 ? 16 : 8);
+}
+
+// z = M_P^-1 P M_A^-1 y  (z overwritten; tmp: 2 vectors of scratch)
+void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double* t2, int nrhs) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  if (c->precond == PMCHWT_P_I) {
+    HIPCHK(hipMemcpyAsync(z, y, size_t(2 * vs * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
+    return;
+  }
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const int64_t o = s.edge_off;
+    for (int comp = 0; comp < 2; ++comp)
+      launch_gemv_real(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * (comp * E + o),
+                       t1 + 2 * (comp * E + o), nrhs, vs, c->stream);
+  }
+  launch_zero(t2, 2 * vs * nrhs, c->stream);
+  const int64_t* rp = c->p_rowptr.as<int64_t>();
+  const int32_t* cl = c->p_col.as<int32_t>();
+  if (c->P_int) {
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_spmv_pmchwt<double>(rp + o, cl, c->PSi.as<double>(), c->P_C ? c->PCi.as<double>() : nullptr, s.topo.E,
+                                 s.k.real(), s.k.imag(), t1, t1 + 2 * E, t2 + 2 * o, t2 + 2 * (E + o), nrhs, vs,
+                                 c->stream);
+    }
+  }
+  if (c->P_ext)
+    launch_spmv_pmchwt<double>(rp, cl, c->PSe.as<double>(), c->P_C ? c->PCe.as<double>() : nullptr, int(E), c->k_ext,
+                               0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, nrhs, vs, c->stream);
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const int64_t o = s.edge_off;
+    for (int comp = 0; comp < 2; ++comp)
+      launch_gemv_real(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * (comp * E + o),
+                       z + 2 * (comp * E + o), nrhs, vs, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// API layout (scatterer-major [D_m ; N_m]) <-> internal layout ([D ; N] over the union)
+void to_internal(const pmchwt_ctx* c, const pmchwt_complex* in, int nrhs, std::vector<double>& out) {
+  const int64_t E = c->E_tot, N = 2 * E;
+  out.assign(size_t(2 * N * nrhs), 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    for (auto& s : c->sc)
+      for (int e = 0; e < s.topo.E; ++e)
+        for (int comp = 0; comp < 2; ++comp) {
+          const pmchwt_complex v = in[r * N + 2 * int64_t(s.edge_off) + comp * s.topo.E + e];
+          const int64_t k = r * N + comp * E + s.edge_off + e;
+          out[2 * k] = v.re;
+          out[2 * k + 1] = v.im;
+        }
+}
+
+void to_api(const pmchwt_ctx* c, const std::vector<double>& in, int nrhs, pmchwt_complex* out) {
+  const int64_t E = c->E_tot, N = 2 * E;
+  for (int r = 0; r < nrhs; ++r)
+    for (auto& s : c->sc)
+      for (int e = 0; e < s.topo.E; ++e)
+        for (int comp = 0; comp < 2; ++comp) {
+          const int64_t k = r * N + comp * E + s.edge_off + e;
+          out[r * N + 2 * int64_t(s.edge_off) + comp * s.topo.E + e] = {in[2 * k], in[2 * k + 1]};
+        }
+}
+
+// Galerkin right-hand side into device buffer b (internal layout)
+void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  std::vector<double> hp(6 * size_t(nrhs));
+  for (int r = 0; r < nrhs; ++r)
+    for (int d = 0; d < 3; ++d) {
+      hp[6 * r + 2 * d] = pols[3 * r + d].re;
+      hp[6 * r + 2 * d + 1] = pols[3 * r + d].im;
+    }
+  std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
+  DBuf dd = upload(c, hd), dp = upload(c, hp);
+  DBuf g = dalloc<double>(size_t(2 * vs * nrhs)), h = dalloc<double>(size_t(2 * vs * nrhs)),
+       cinc = dalloc<double>(size_t(2 * vs * nrhs)), t = dalloc<double>(size_t(2 * vs * nrhs));
+  launch_zero(g.as<double>(), 2 * vs * nrhs, c->stream);
+  launch_zero(h.as<double>(), 2 * vs * nrhs, c->stream);
+  RhsJob j{};
+  j.F = c->F_tot;
+  j.nrhs = nrhs;
+  j.dirs = dd.as<double>();
+  j.pols = dp.as<double>();
+  j.k_ext = c->k_ext;
+  j.E_tot = E;
+  j.g = g.as<double>();
+  j.h = h.as<double>();
+  launch_rhs(asm_params<double>(c), j, c->stream);
+  HIPCHK(hipGetLastError());
+  // c_inc = G^-1 h per scatterer (LU from rocSOLVER), both components
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const int n = s.topo.E;
+    const int nvec = 2 * nrhs;  // (r, comp)
+    DBuf B = dalloc<double>(size_t(n) * 2 * nvec);
+    // vectors (r, comp) start at h + 2*(r*vs + comp*E + off): stride between
+    // consecutive comp is E, between r is vs = 2E, so nvec vectors with stride E
+    launch_pack_cols(h.as<double>() + 2 * int64_t(s.edge_off), E, n, nvec, B.as<double>(), c->stream);
+    rocsolver_check(rocsolver_dgetrs(c->blas, rocblas_operation_none, n, 2 * nvec, c->Glu[m].as<double>(), n,
+                                     c->Gpiv[m].as<rocblas_int>(), B.as<double>(), n),
+                    "rocsolver_dgetrs(gram)");
+    launch_unpack_cols(B.as<double>(), n, nvec, cinc.as<double>() + 2 * int64_t(s.edge_off), E, c->stream);
+  }
+  // b = g/2 - A^i c_inc
+  launch_zero(t.as<double>(), 2 * vs * nrhs, c->stream);
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const int64_t o = s.edge_off;
+    const double* x = cinc.as<double>();
+    double* y = t.as<double>();
+    if (c->precA == PMCHWT_FP64)
+      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), s.topo.E, s.topo.E, s.topo.E,
+                                 s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
+                                 vs, c->stream);
+    else
+      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, s.k.real(),
+                                s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs,
+                                c->stream);
+  }
+  HIPCHK(hipMemcpyAsync(b, g.p, size_t(2 * vs * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
+  launch_axpby(b, t.as<double>(), vs, int(vs), nrhs, 0.5, -1.0, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// Batched restarted GMRES on  Op = Ptilde A  (Ptilde = I for P = I),
+// classical Gram-Schmidt with one re-orthogonalisation pass (CGS2).
+// Reading: the paper does not state the orthogonalisation; CGS2 has the
+// stability of modified Gram-Schmidt and maps onto two batched products.
+// A true residual is recomputed at the end of every full cycle (the
+// floor(R/rho) term of Table 1).
+// ---------------------------------------------------------------------------
+struct GmresOut {
+  std::vector<int> iters, restarts;
+  std::vector<double> relres;
+  std::vector<int> converged;
+};
+
+void op_apply(pmchwt_ctx* c, const double* x, double* y, double* s1, double* s2, double* s3, int nrhs) {
+  if (c->precond == PMCHWT_P_I) {
+    apply_A(c, x, y, nrhs);
+    return;
+  }
+  apply_A(c, x, s1, nrhs);
+  apply_Ptilde(c, s1, y, s2, s3, nrhs);
+}
+
+GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol, int rho, int max_iter) {
+  const int64_t vs = vlen(c);
+  const int n = int(vs);
+  const int64_t vecd = 2 * vs;  // doubles per vector
+  // workspace: V (rho+1) x nrhs vectors, w, r, 3 scratch
+  const size_t need = size_t(rho + 1 + 5) * nrhs * vecd + 4 * size_t(rho + 2) * nrhs + 16 * size_t(nrhs);
+  double* W = need_work(c, need);
+  double* V = W;
+  double* w = V + size_t(rho + 1) * nrhs * vecd;
+  double* r = w + nrhs * vecd;
+  double* s1 = r + nrhs * vecd;
+  double* s2 = s1 + nrhs * vecd;
+  double* s3 = s2 + nrhs * vecd;
+  double* dh = s3 + nrhs * vecd;            // nrhs x (rho+2) complex
+  double* dn = dh + 2 * size_t(rho + 2) * nrhs;
+  DBuf dact = dalloc<int32_t>(nrhs);
+  const int64_t vstep = int64_t(nrhs) * vs;  // complex offset between basis vectors
+  GmresOut out;
+  out.iters.assign(nrhs, 0);
+  out.restarts.assign(nrhs, 0);
+  out.relres.assign(nrhs, 1.0);
+  out.converged.assign(nrhs, 0);
+  launch_zero(x, vecd * nrhs, c->stream);
+  HIPCHK(hipMemcpyAsync(r, bt, size_t(vecd * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
+  std::vector<double> bnorm(nrhs), beta(nrhs), hn(nrhs);
+  launch_norms(bt, vs, n, nrhs, dn, c->stream);
+  HIPCHK(hipMemcpyAsync(bnorm.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  beta = bnorm;
+  std::vector<int32_t> active(nrhs);
+  for (int q = 0; q < nrhs; ++q) {
+    if (bnorm[q] == 0.0) {
+      out.converged[q] = 1;
+      out.relres[q] = 0.0;
+    }
+  }
+  std::vector<cd> H(size_t(rho + 1) * rho * nrhs), cs(size_t(rho) * nrhs), sn(size_t(rho) * nrhs),
+      g(size_t(rho + 1) * nrhs);
+  std::vector<double> hbuf(2 * size_t(rho + 2) * nrhs);
+  std::vector<double> scale(nrhs);
+  DBuf dscale = dalloc<double>(nrhs);
+  DBuf dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
+  auto Hm = [&](int q, int i, int j) -> cd& { return H[(size_t(q) * (rho + 1) + i) * rho + j]; };
+  int total = 0;
+  while (true) {
+    bool any = false;
+    for (int q = 0; q < nrhs; ++q) {
+      active[q] = !out.converged[q];
+      any |= bool(active[q]);
+    }
+    if (!any || total >= max_iter) break;
+    HIPCHK(hipMemcpyAsync(dact.p, active.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+    for (int q = 0; q < nrhs; ++q) scale[q] = active[q] ? 1.0 / beta[q] : 0.0;
+    HIPCHK(hipMemcpyAsync(dscale.p, scale.data(), 8 * nrhs, hipMemcpyHostToDevice, c->stream));
+    launch_scale_copy(r, vs, V, vs, n, nrhs, dscale.as<double>(), c->stream);
+    std::fill(H.begin(), H.end(), cd(0));
+    std::fill(g.begin(), g.end(), cd(0));
+    for (int q = 0; q < nrhs; ++q) g[size_t(q) * (rho + 1)] = beta[q];
+    std::vector<int> jend(nrhs, 0);
+    std::vector<int> done_cycle(nrhs, 0);
+    int j = 0;
+    for (; j < rho && total < max_iter; ++j) {
+      op_apply(c, V + size_t(j) * nrhs * vecd, w, s1, s2, s3, nrhs);
+      // CGS2
+      std::vector<double> hsum(2 * size_t(j + 1) * nrhs, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
+        launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
+        HIPCHK(hipMemcpyAsync(hbuf.data(), dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += hbuf[k];
+      }
+      launch_norms(w, vs, n, nrhs, dn, c->stream);
+      HIPCHK(hipMemcpyAsync(hn.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int q = 0; q < nrhs; ++q) scale[q] = (active[q] && hn[q] > 0) ? 1.0 / hn[q] : 0.0;
+      HIPCHK(hipMemcpyAsync(dscale.p, scale.data(), 8 * nrhs, hipMemcpyHostToDevice, c->stream));
+      launch_scale_copy(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, dscale.as<double>(), c->stream);
+      ++total;
+      bool all_done = true;
+      for (int q = 0; q < nrhs; ++q) {
+        if (!active[q]) continue;
+        out.iters[q] += 1;
+        for (int i = 0; i <= j; ++i) Hm(q, i, j) = cd(hsum[2 * (size_t(q) * (j + 1) + i)], hsum[2 * (size_t(q) * (j + 1) + i) + 1]);
+        Hm(q, j + 1, j) = hn[q];
+        for (int i = 0; i < j; ++i) {
+          const cd a = Hm(q, i, j), b = Hm(q, i + 1, j);
+          const cd c_ = cs[size_t(q) * rho + i], s_ = sn[size_t(q) * rho + i];
+          Hm(q, i, j) = c_ * a + s_ * b;
+          Hm(q, i + 1, j) = -std::conj(s_) * a + std::conj(c_) * b;
+        }
+        const cd a = Hm(q, j, j), b = Hm(q, j + 1, j);
+        const double den = std::sqrt(std::norm(a) + std::norm(b));
+        const cd c_ = den > 0 ? std::conj(a) / den : cd(1), s_ = den > 0 ? std::conj(b) / den : cd(0);
+        cs[size_t(q) * rho + j] = c_;
+        sn[size_t(q) * rho + j] = s_;
+        Hm(q, j, j) = den;
+        Hm(q, j + 1, j) = 0;
+        cd& gj = g[size_t(q) * (rho + 1) + j];
+        g[size_t(q) * (rho + 1) + j + 1] = -std::conj(s_) * gj;
+        gj = c_ * gj;
+        const double res = std::abs(g[size_t(q) * (rho + 1) + j + 1]) / bnorm[q];
+        out.relres[q] = res;
+        jend[q] = j + 1;
+        // converged inside the cycle (a convergence exactly at the cycle end
+        // still goes through the cycle-end residual, as Table 1 counts it)
+        if (res <= tol && j + 1 < rho) {
+          done_cycle[q] = 1;
+          active[q] = 0;
+        } else {
+          all_done = false;
+        }
+      }
+      HIPCHK(hipMemcpyAsync(dact.p, active.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+      if (all_done) {
+        ++j;
+        break;
+      }
+    }
+    // x += V y for every right-hand side that iterated in this cycle
+    std::vector<double> ybuf(2 * size_t(rho + 1) * nrhs, 0.0);
+    std::vector<int32_t> upd(nrhs, 0);
+    int maxj = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      const int m = jend[q];
+      if (m == 0) continue;
+      upd[q] = 1;
+      maxj = std::max(maxj, m);
+      std::vector<cd> y(m);
+      for (int i = m - 1; i >= 0; --i) {
+        cd s = g[size_t(q) * (rho + 1) + i];
+        for (int k = i + 1; k < m; ++k) s -= Hm(q, i, k) * y[k];
+        y[i] = s / Hm(q, i, i);
+      }
+      for (int i = 0; i < m; ++i) {
+        ybuf[2 * (size_t(q) * (rho + 1) + i)] = y[i].real();
+        ybuf[2 * (size_t(q) * (rho + 1) + i) + 1] = y[i].imag();
+      }
+    }
+    if (maxj > 0) {
+      HIPCHK(hipMemcpyAsync(dy.p, ybuf.data(), ybuf.size() * 8, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(dact.p, upd.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+      launch_update(V, vstep, maxj, x, vs, n, dact.as<int32_t>(), nrhs, vs, dy.as<double>(), rho + 1, 1.0, c->stream);
+    }
+    for (int q = 0; q < nrhs; ++q)
+      if (done_cycle[q]) out.converged[q] = 1;
+    bool pending = false;
+    for (int q = 0; q < nrhs; ++q) pending |= (!out.converged[q] && jend[q] > 0);
+    if (!pending) break;
+    // end of a full cycle: true residual r = bt - Op x
+    op_apply(c, x, r, s1, s2, s3, nrhs);
+    launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
+    launch_norms(r, vs, n, nrhs, dn, c->stream);
+    HIPCHK(hipMemcpyAsync(beta.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int q = 0; q < nrhs; ++q) {
+      if (out.converged[q] || jend[q] == 0) continue;
+      out.restarts[q] += 1;
+      out.relres[q] = beta[q] / bnorm[q];
+      if (beta[q] / bnorm[q] <= tol) out.converged[q] = 1;
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pmchwt_version(void) { return "pmchwt-mi355x 0.1 (gfx950)"; }
+
+int pmchwt_create(pmchwt_ctx** out, int device, void* hip_stream) {
+  if (!out) return PMCHWT_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return PMCHWT_ERR_DEVICE;
+  if (device < 0 || device >= ndev) return PMCHWT_ERR_INVALID_ARG;
+  auto* c = new (std::nothrow) pmchwt_ctx();
+  if (!c) return PMCHWT_ERR_OUT_OF_MEMORY;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return PMCHWT_ERR_DEVICE;
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return PMCHWT_ERR_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    delete c;
+    return PMCHWT_ERR_DEVICE;
+  }
+  rocblas_set_stream(c->blas, c->stream);
+  double l[14][3], w[14];
+  triangle_rules(l, w);
+  if (upload_rules(&l[0][0], w, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete c;
+    return PMCHWT_ERR_DEVICE;
+  }
+  *out = c;
+  return PMCHWT_OK;
+}
+
+int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                         pmchwt_complex eps_r, int32_t* id) {
+  return guarded(c, [&]() -> int {
+    if (!verts || !tris || nv <= 0 || nt <= 0) return fail(c, PMCHWT_ERR_INVALID_ARG, "null or empty mesh");
+    Scat s;
+    std::string err;
+    if (!build_topology(verts, nv, tris, nt, s.topo, err)) return fail(c, PMCHWT_ERR_INVALID_MESH, err);
+    s.eps = cd(eps_r.re, eps_r.im);
+    s.edge_off = c->E_tot;
+    s.tri_off = c->F_tot;
+    s.vert_off = c->nv_tot;
+    c->E_tot += s.topo.E;
+    c->F_tot += s.topo.F;
+    c->nv_tot += s.topo.nv;
+    c->sc.push_back(std::move(s));
+    c->geo_uploaded = false;
+    c->have_A = false;
+    if (id) *id = int32_t(c->sc.size() - 1);
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_set_wavenumber(pmchwt_ctx* c, double k) {
+  return guarded(c, [&]() -> int {
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(c, PMCHWT_ERR_INVALID_ARG, "k_ext must be positive");
+    c->k_ext = k;
+    c->have_A = false;
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_sizes(const pmchwt_ctx* c, int32_t* ns, int64_t* nu) {
+  if (!c) return PMCHWT_ERR_INVALID_ARG;
+  if (ns) *ns = int32_t(c->sc.size());
+  if (nu) *nu = 2 * int64_t(c->E_tot);
+  return PMCHWT_OK;
+}
+
+int pmchwt_num_edges(const pmchwt_ctx* c, int32_t m, int32_t* E) {
+  if (!c || !E || m < 0 || m >= int32_t(c->sc.size())) return PMCHWT_ERR_INVALID_ARG;
+  *E = c->sc[m].topo.E;
+  return PMCHWT_OK;
+}
+
+int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_assembly_opts* P,
+                    pmchwt_precond kind) {
+  return guarded(c, [&]() -> int {
+    if (c->sc.empty()) return fail(c, PMCHWT_ERR_STATE, "no scatterer added");
+    if (!(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "wavenumber not set");
+    check_opts(A, "A");
+    check_opts(P, "P");
+    if (int(kind) < 0 || int(kind) > 6) return fail(c, PMCHWT_ERR_INVALID_ARG, "unknown preconditioner");
+    c->have_A = false;
+    c->prof = pmchwt_profile{};
+    build_duals(c);
+    upload_geometry(c);
+    upload_k(c);
+    c->optA = *A;
+    c->optP = *P;
+    c->precA = A->precision;
+    if (A->precision == PMCHWT_FP64)
+      assemble_A_impl<double>(c, *A);
+    else
+      assemble_A_impl<float>(c, *A);
+    CellDev cells;
+    upload_cells(c, cells);
+    assemble_P_impl(c, *P, int(kind), cells);
+    assemble_mass_impl(c, cells);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_A = true;
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_get_block(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchwt_space sp, int32_t m, int32_t l,
+                     pmchwt_complex* out, int64_t ld) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    const int M = int(c->sc.size());
+    if (!out || m < 0 || l < 0 || m >= M || l >= M) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad block index");
+    if (med == PMCHWT_INT && m != l) return fail(c, PMCHWT_ERR_INVALID_ARG, "interior operators are block diagonal");
+    const Scat& sm = c->sc[m];
+    const Scat& sl = c->sc[l];
+    const int Em = sm.topo.E, El = sl.topo.E;
+    if (ld < El) return fail(c, PMCHWT_ERR_INVALID_ARG, "ld too small");
+    if (sp == PMCHWT_RWG) {
+      const DBuf* src;
+      int64_t sld, r0, c0;
+      if (med == PMCHWT_EXT) {
+        src = op == PMCHWT_OP_S ? &c->Se : &c->Ce;
+        sld = c->E_tot;
+        r0 = sm.edge_off;
+        c0 = sl.edge_off;
+      } else {
+        src = op == PMCHWT_OP_S ? &c->Si[m] : &c->Ci[m];
+        sld = Em;
+        r0 = 0;
+        c0 = 0;
+      }
+      const size_t es = c->precA == PMCHWT_FP64 ? 16 : 8;
+      std::vector<char> buf(size_t(Em) * El * es);
+      HIPCHK(hipMemcpy2DAsync(buf.data(), El * es, static_cast<char*>(src->p) + (r0 * sld + c0) * es, sld * es, El * es,
+                              Em, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int i = 0; i < Em; ++i)
+        for (int j = 0; j < El; ++j) {
+          if (es == 16) {
+            const double* p = reinterpret_cast<const double*>(buf.data()) + 2 * (size_t(i) * El + j);
+            out[i * ld + j] = {p[0], p[1]};
+          } else {
+            const float* p = reinterpret_cast<const float*>(buf.data()) + 2 * (size_t(i) * El + j);
+            out[i * ld + j] = {p[0], p[1]};
+          }
+        }
+      return PMCHWT_OK;
+    }
+    const DBuf* v = nullptr;
+    if (med == PMCHWT_INT) v = op == PMCHWT_OP_S ? &c->PSi : &c->PCi;
+    else v = op == PMCHWT_OP_S ? &c->PSe : &c->PCe;
+    if (!v->p) return fail(c, PMCHWT_ERR_STATE, "this BC operator is not part of the preconditioner");
+    std::vector<double> vals(2 * size_t(c->nnzP));
+    HIPCHK(hipMemcpyAsync(vals.data(), v->p, vals.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < Em; ++i) {
+      for (int j = 0; j < El; ++j) out[i * ld + j] = {0, 0};
+      const int gi = sm.edge_off + i;
+      for (int64_t p = c->h_rowptr[gi]; p < c->h_rowptr[gi + 1]; ++p) {
+        const int gj = c->h_col[p];
+        if (gj >= sl.edge_off && gj < sl.edge_off + El) out[i * ld + (gj - sl.edge_off)] = {vals[2 * p], vals[2 * p + 1]};
+      }
+    }
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_get_entries(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchwt_space sp, int32_t m, int32_t l,
+                       int64_t n, const int32_t* rows, const int32_t* cols, pmchwt_complex* out) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    const int M = int(c->sc.size());
+    if (n < 0 || (n > 0 && (!rows || !cols || !out)) || m < 0 || l < 0 || m >= M || l >= M)
+      return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    if (med == PMCHWT_INT && m != l) return fail(c, PMCHWT_ERR_INVALID_ARG, "interior operators are block diagonal");
+    const Scat& sm = c->sc[m];
+    const Scat& sl = c->sc[l];
+    for (int64_t q = 0; q < n; ++q)
+      if (rows[q] < 0 || rows[q] >= sm.topo.E || cols[q] < 0 || cols[q] >= sl.topo.E)
+        return fail(c, PMCHWT_ERR_INVALID_ARG, "entry index out of range");
+    if (sp == PMCHWT_RWG) {
+      const size_t es = c->precA == PMCHWT_FP64 ? 16 : 8;
+      const DBuf* src = med == PMCHWT_EXT ? (op == PMCHWT_OP_S ? &c->Se : &c->Ce) : (op == PMCHWT_OP_S ? &c->Si[m] : &c->Ci[m]);
+      const int64_t sld = med == PMCHWT_EXT ? c->E_tot : sm.topo.E;
+      const int64_t r0 = med == PMCHWT_EXT ? sm.edge_off : 0, c0 = med == PMCHWT_EXT ? sl.edge_off : 0;
+      for (int64_t q = 0; q < n; ++q) {
+        char buf[16];
+        HIPCHK(hipMemcpyAsync(buf, static_cast<char*>(src->p) + ((r0 + rows[q]) * sld + c0 + cols[q]) * es, es,
+                              hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (es == 16) {
+          double d[2];
+          std::memcpy(d, buf, 16);
+          out[q] = {d[0], d[1]};
+        } else {
+          float f[2];
+          std::memcpy(f, buf, 8);
+          out[q] = {f[0], f[1]};
+        }
+      }
+      return PMCHWT_OK;
+    }
+    const DBuf* v = med == PMCHWT_INT ? (op == PMCHWT_OP_S ? &c->PSi : &c->PCi) : (op == PMCHWT_OP_S ? &c->PSe : &c->PCe);
+    if (!v->p) return fail(c, PMCHWT_ERR_STATE, "this BC operator is not part of the preconditioner");
+    for (int64_t q = 0; q < n; ++q) {
+      const int gi = sm.edge_off + rows[q], gj = sl.edge_off + cols[q];
+      auto b = c->h_col.begin() + c->h_rowptr[gi], e = c->h_col.begin() + c->h_rowptr[gi + 1];
+      auto it = std::lower_bound(b, e, gj);
+      if (it == e || *it != gj) {
+        out[q] = {0, 0};
+        continue;
+      }
+      const int64_t p = it - c->h_col.begin();
+      double d[2];
+      HIPCHK(hipMemcpyAsync(d, v->as<double>() + 2 * p, 16, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      out[q] = {d[0], d[1]};
+    }
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_get_mass(pmchwt_ctx* c, int32_t m, double* out) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (!out || m < 0 || m >= int32_t(c->sc.size())) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    const size_t n = size_t(c->sc[m].topo.E);
+    HIPCHK(hipMemcpyAsync(out, c->MA[m].p, n * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs, pmchwt_complex* b_out) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (nrhs <= 0 || !dirs || !pols || !b_out) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    const int64_t vs = vlen(c);
+    DBuf b = dalloc<double>(size_t(2 * vs * nrhs));
+    build_rhs(c, dirs, pols, nrhs, b.as<double>());
+    std::vector<double> h(size_t(2 * vs * nrhs));
+    HIPCHK(hipMemcpy(h.data(), b.p, h.size() * 8, hipMemcpyDeviceToHost));
+    to_api(c, h, nrhs, b_out);
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t nrhs, pmchwt_complex* y) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (nrhs <= 0 || !x || !y || (which != 0 && which != 1)) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    const int64_t vs = vlen(c);
+    std::vector<double> h;
+    to_internal(c, x, nrhs, h);
+    DBuf dx = upload(c, h), dy = dalloc<double>(h.size()), s1 = dalloc<double>(h.size()), s2 = dalloc<double>(h.size()),
+         s3 = dalloc<double>(h.size());
+    if (which == 0)
+      apply_A(c, dx.as<double>(), dy.as<double>(), nrhs);
+    else
+      op_apply(c, dx.as<double>(), dy.as<double>(), s1.as<double>(), s2.as<double>(), s3.as<double>(), nrhs);
+    HIPCHK(hipMemcpyAsync(h.data(), dy.p, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    to_api(c, h, nrhs, y);
+    (void)vs;
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs,
+                 const pmchwt_solver_opts* o, pmchwt_complex* cur, pmchwt_solve_stats* st) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (nrhs <= 0 || !dirs || !pols || !cur || !o) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    if (!(o->tol > 0) || o->restart < 1 || o->restart > 1024 || o->max_iter < 1 || o->ir_max < 0)
+      return fail(c, PMCHWT_ERR_INVALID_ARG, "bad solver options");
+    const int64_t vs = vlen(c);
+    const size_t nd = size_t(2 * vs * nrhs);
+    DBuf b = dalloc<double>(nd), bt = dalloc<double>(nd), x = dalloc<double>(nd), s1 = dalloc<double>(nd),
+         s2 = dalloc<double>(nd), d = dalloc<double>(nd), r = dalloc<double>(nd);
+    EvTimer tm(c->stream);
+    c->prof.ms_matvec_total = 0;
+    c->prof.matvec_launches = 0;
+    c->prof.matvec_bytes = 0;
+    build_rhs(c, dirs, pols, nrhs, b.as<double>());
+    // bt = Ptilde b
+    apply_Ptilde(c, b.as<double>(), bt.as<double>(), s1.as<double>(), s2.as<double>(), nrhs);
+    GmresOut g = gmres(c, bt.as<double>(), x.as<double>(), nrhs, o->tol, o->restart, o->max_iter);
+    int64_t mv_max = 0;
+    int it_max = 0, restarts = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      const int64_t mv = (A_matvecs(c) + P_matvecs(c)) * (g.iters[q] + g.restarts[q]) + P_matvecs(c);
+      mv_max = std::max(mv_max, mv);
+      it_max = std::max(it_max, g.iters[q]);
+      restarts = std::max(restarts, g.restarts[q]);
+    }
+    // iterative refinement: r = b - A x in FP64 accumulation, correction solve
+    int ir = 0;
+    for (; ir < o->ir_max; ++ir) {
+      apply_A(c, x.as<double>(), r.as<double>(), nrhs);
+      launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
+      apply_Ptilde(c, r.as<double>(), s1.as<double>(), s2.as<double>(), d.as<double>(), nrhs);
+      std::vector<double> nr(nrhs), nb(nrhs);
+      DBuf dn = dalloc<double>(2 * nrhs);
+      launch_norms(s1.as<double>(), vs, int(vs), nrhs, dn.as<double>(), c->stream);
+      launch_norms(bt.as<double>(), vs, int(vs), nrhs, dn.as<double>() + nrhs, c->stream);
+      HIPCHK(hipMemcpyAsync(nr.data(), dn.p, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(nb.data(), dn.as<double>() + nrhs, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      bool ok = true;
+      for (int q = 0; q < nrhs; ++q) ok &= (nr[q] <= o->tol * nb[q]);
+      mv_max += A_matvecs(c) + P_matvecs(c);
+      if (ok) break;
+      HIPCHK(hipMemcpyAsync(r.p, s1.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
+      GmresOut g2 = gmres(c, r.as<double>(), d.as<double>(), nrhs, o->tol, o->restart, o->max_iter);
+      launch_axpby(x.as<double>(), d.as<double>(), vs, int(vs), nrhs, 1.0, 1.0, c->stream);
+      int mi = 0;
+      for (int q = 0; q < nrhs; ++q) {
+        mi = std::max(mi, g2.iters[q]);
+        mv_max += (A_matvecs(c) + P_matvecs(c)) * (g2.iters[q] + g2.restarts[q]);
+        g.converged[q] = g2.converged[q];
+        g.relres[q] = g2.relres[q];
+      }
+      it_max += mi;
+    }
+    const double ms = tm.stop();
+    std::vector<double> h(nd);
+    HIPCHK(hipMemcpyAsync(h.data(), x.p, nd * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    to_api(c, h, nrhs, cur);
+    bool conv = true;
+    double worst = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      conv &= bool(g.converged[q]);
+      worst = std::max(worst, g.relres[q]);
+    }
+    if (st) {
+      st->iterations = it_max;
+      st->converged = conv;
+      st->matvecs = mv_max;
+      st->rel_residual = worst;
+      st->ir_steps = ir;
+      st->restarts = restarts;
+      st->ms_solve = ms;
+    }
+    if (!conv) return fail(c, PMCHWT_ERR_NOT_CONVERGED, "GMRES reached max_iter");
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* obs, int32_t nobs,
+                     pmchwt_complex* F) {
+  return guarded(c, [&]() -> int {
+    if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
+    if (nrhs <= 0 || nobs <= 0 || !cur || !obs || !F) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    upload_geometry(c);
+    std::vector<double> h;
+    to_internal(c, cur, nrhs, h);
+    DBuf dx = upload(c, h);
+    std::vector<double> ho(obs, obs + 3 * size_t(nobs));
+    DBuf dobs = upload(c, ho), dF = dalloc<double>(6 * size_t(nobs) * nrhs);
+    launch_far_field(asm_params<double>(c), dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs,
+                     dF.as<double>(), c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hf(6 * size_t(nobs) * nrhs);
+    HIPCHK(hipMemcpyAsync(hf.data(), dF.p, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < hf.size() / 2; ++k) F[k] = {hf[2 * k], hf[2 * k + 1]};
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* dirs,
+                          const pmchwt_complex* pols, double* sext, double* ssca) {
+  return guarded(c, [&]() -> int {
+    if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
+    if (nrhs <= 0 || !cur || !dirs || !pols || !sext || !ssca) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    upload_geometry(c);
+    const int nth = 64, nph = 128, nobs = nth * nph;
+    std::vector<double> ct, wt;
+    gauss_legendre01(nth, ct, wt);
+    std::vector<double> obs(3 * size_t(nobs)), w(nobs);
+    for (int a = 0; a < nth; ++a)
+      for (int b = 0; b < nph; ++b) {
+        const double cz = 2.0 * ct[a] - 1.0, sz = std::sqrt(std::max(0.0, 1.0 - cz * cz));
+        const double ph = 2.0 * M_PI * b / nph;
+        const int o = a * nph + b;
+        obs[3 * o] = sz * std::cos(ph);
+        obs[3 * o + 1] = sz * std::sin(ph);
+        obs[3 * o + 2] = cz;
+        w[o] = 2.0 * wt[a] * (2.0 * M_PI / nph);
+      }
+    std::vector<double> h;
+    to_internal(c, cur, nrhs, h);
+    DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc<double>(6 * size_t(nobs) * nrhs),
+         dsig = dalloc<double>(nrhs);
+    AsmParams<double> g = asm_params<double>(c);
+    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs, dF.as<double>(), c->stream);
+    launch_sigma_sca(dF.as<double>(), nobs, nrhs, dw.as<double>(), dsig.as<double>(), c->stream);
+    std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
+    DBuf dd = upload(c, hd), dFd = dalloc<double>(6 * size_t(nrhs) * nrhs);
+    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dd.as<double>(), nrhs, dFd.as<double>(), c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> fd(6 * size_t(nrhs) * nrhs);
+    HIPCHK(hipMemcpyAsync(ssca, dsig.p, 8 * size_t(nrhs), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(fd.data(), dFd.p, fd.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int r = 0; r < nrhs; ++r) {
+      // (4 pi / k) Im(conj(p) . F(d))
+      double im = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double fr = fd[6 * (size_t(r) * nrhs + r) + 2 * d], fi = fd[6 * (size_t(r) * nrhs + r) + 2 * d + 1];
+        const double pr = pols[3 * r + d].re, pi = pols[3 * r + d].im;
+        im += pr * fi - pi * fr;
+      }
+      sext[r] = 4.0 * M_PI / c->k_ext * im;
+    }
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_bc_fields(const double* verts, int32_t nv, const int32_t* tris, int32_t nt, int64_t* count, int32_t* ids,
+                     double* vals) {
+  if (!verts || !tris || !count || nv <= 0 || nt <= 0) return PMCHWT_ERR_INVALID_ARG;
+  Topo T;
+  DualCells D;
+  std::string err;
+  if (!build_topology(verts, nv, tris, nt, T, err)) return PMCHWT_ERR_INVALID_MESH;
+  if (!build_dual(T, D, err)) return PMCHWT_ERR_INVALID_MESH;
+  int64_t n = 0;
+  for (int v = 0; v < T.nv; ++v) n += int64_t(D.inc_ptr[v + 1] - D.inc_ptr[v]) * (D.cell_ptr[v + 1] - D.cell_ptr[v]);
+  if (!ids || !vals) {
+    *count = n;
+    return PMCHWT_OK;
+  }
+  if (*count < n) return PMCHWT_ERR_INVALID_ARG;
+  int64_t q = 0;
+  for (int v = 0; v < T.nv; ++v) {
+    const int n2 = D.cell_ptr[v + 1] - D.cell_ptr[v];
+    for (int s = 0; s < n2 / 2; ++s)
+      for (int u = 0; u < n2; ++u) {
+        const size_t rec = size_t(D.coef_ptr[v]) + size_t(s) * n2 + u;
+        ids[2 * q] = D.inc_edges[D.inc_ptr[v] + s];
+        ids[2 * q + 1] = D.ring[D.cell_ptr[v] + u];
+        for (int k = 0; k < 4; ++k) vals[4 * q + k] = D.coef[4 * rec + k];
+        ++q;
+      }
+  }
+  *count = q;
+  return PMCHWT_OK;
+}
+
+int pmchwt_get_profile(const pmchwt_ctx* c, pmchwt_profile* out) {
+  if (!c || !out) return PMCHWT_ERR_INVALID_ARG;
+  *out = c->prof;
+  return PMCHWT_OK;
+}
+
+const char* pmchwt_last_error(const pmchwt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void pmchwt_destroy(pmchwt_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+}  // extern "C"

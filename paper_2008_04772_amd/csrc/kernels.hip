@@ -1,0 +1,6 @@
+// Single translation unit for all device code of the PMCHWT library (the
+// quadrature tables in constant memory are shared by the assembly, barycentric
+// and far-field kernels).
+#include "assembly.inl"
+#include "bc.inl"
+#include "linalg.inl"

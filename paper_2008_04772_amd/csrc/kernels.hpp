@@ -1,0 +1,153 @@
+// Kernel parameter blocks and host launch wrappers of the PMCHWT library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmchwt {
+
+// Primal triangles of all scatterers (union numbering), SoA.
+template <typename M>
+struct AsmParams {
+  int F;                       // triangles
+  const double* tv;            // 9*F: vertex k, component d at (3k+d)*F + t
+  const double* tcen;          // 3*F centroids ((P0+P1)+P2)/3
+  const double* tdiam2;        // F: max squared edge length
+  const double* tarea;         // F
+  const int32_t* tvid;         // 3*F vertex ids (global)
+  const int32_t* t2e;          // 3*F union edge index of local basis a
+  const int8_t* tsgn;          // 3*F sign of local basis a
+  const int32_t* tscat;        // F scatterer id
+  const int32_t* edge_off;     // per scatterer: first union edge
+  const double* k_int;         // per scatterer: interior wavenumber (re, im)
+  double k_ext;
+  int q_near, q_medium, q_far; // rule orders 1..4
+  M* Se;                       // exterior operators, E_tot x E_tot
+  M* Ce;
+  int64_t ld_ext;
+  M** Si;                      // per scatterer interior operators, E_m x E_m
+  M** Ci;
+  const int64_t* ld_int;
+};
+
+// Sauter-Schwab tables per relation kind (1 vertex, 2 edge, 3 identical):
+// records (x1, x2, y1, y2, w) on That x That.
+struct SingParams {
+  int64_t npairs;
+  const int32_t* pairs;        // 2*npairs (t1, t2), ordered
+  const double* tab[4];
+  int npts[4];
+};
+
+// Dual cells (barycentric rings) of all scatterers.
+struct CellParams {
+  const int32_t* cell_ptr;     // ncell+1 into ring
+  const int32_t* ring;         // global child ids
+  const double* child_v;       // 9 per child (AoS)
+  const int32_t* child_vid;    // 3 per child, barycentric vertex ids (globally offset)
+  const double* child_cen;     // 3 per child
+  const double* child_diam2;   // 1 per child
+  const double* child_area;    // 1 per child
+  const int64_t* coef_ptr;     // ncell+1 (in 4-double records)
+  const double* coef;          // (alpha, wx, wy, wz) per (cell, slot, ring position)
+  const int32_t* cell_scat;    // scatterer of each cell
+};
+
+// Near-field BC operator job: one wavefront per cell pair.
+struct BCJob {
+  int64_t npairs;
+  const int32_t* cpairs;       // 2*npairs (cell v, cell w)
+  const int64_t* slot_off;     // npairs+1: offsets into slot_pos
+  const int64_t* slot_pos;     // N_v x N_w CSR positions, -1 = dropped by the near-field cutoff
+  int want_int, want_ext, want_C;
+  const double* k_int;         // per scatterer (re, im)
+  double k_ext;
+  int q_near, q_medium, q_far, n_sing;
+  const double* tab[4];
+  int npts[4];
+  double* out_Si;              // CSR values (re, im) interleaved, FP64
+  double* out_Ci;
+  double* out_Se;
+  double* out_Ce;
+};
+
+// Mass / Gram / right-hand-side / far-field parameter blocks.
+struct MassJob {
+  int nchild;
+  const int32_t* child_cell;   // cell of each child
+  const int32_t* child_pos;    // ring position
+  const int32_t* child_parent; // global primal triangle
+  const int32_t* inc_ptr;      // per cell: offset into inc_edges
+  const int32_t* inc_edges;    // union edge ids
+  const int32_t* edge_scat;    // scatterer of each union edge
+  const int32_t* edge_off;     // per scatterer
+  const int64_t* mat_off;      // per scatterer offset (elements) into mass storage
+  const int64_t* ld;           // per scatterer E_m
+  double* out;                 // dense FP64 matrices, row-major
+};
+
+struct RhsJob {
+  int F, nrhs;
+  const double* dirs;          // 3*nrhs
+  const double* pols;          // 6*nrhs (re,im per component)
+  double k_ext;
+  int64_t E_tot;
+  double* g;                   // [nrhs][2][E_tot] complex: identity-term projections
+  double* h;                   // [nrhs][2][E_tot] complex: L2 projections
+};
+
+hipError_t upload_rules(const double* l, const double* w, hipStream_t s);
+
+template <typename R, typename M>
+void launch_regular(const AsmParams<M>& p, int t1_begin, int t1_end, hipStream_t st);
+template <typename M>
+void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st);
+
+void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, const BCJob& j, hipStream_t st);
+void launch_mass(const AsmParams<double>& geo, const CellParams& c, const MassJob& j, hipStream_t st);
+void launch_gram(const AsmParams<double>& geo, const MassJob& j, hipStream_t st);
+void launch_rhs(const AsmParams<double>& geo, const RhsJob& j, hipStream_t st);
+
+// Linear algebra -------------------------------------------------------------
+// Dense PMCHWT block application on a vector batch:
+//   yD += C xD + (1/k) S xN ;  yN += -k S xD + C xN
+// S, C row-major rows x cols, complex interleaved, element M.  Vectors are
+// complex128; vector r of the batch starts at r*vstride.
+template <typename M>
+void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
+                        const double* xD, const double* xN, double* yD, double* yN, int nrhs,
+                        int64_t vstride, hipStream_t st);
+// Same with a CSR pattern (rowptr, col) and value arrays S, C (either may be
+// null: treated as zero).
+template <typename M>
+void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows,
+                        double kr, double ki, const double* xD, const double* xN, double* yD, double* yN,
+                        int nrhs, int64_t vstride, hipStream_t st);
+// y = alpha * Mreal x (dense real row-major, rows x cols), complex vectors
+void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
+                      double* y, int nrhs, int64_t vstride, hipStream_t st);
+void launch_transpose(const double* in, double* out, int n, hipStream_t st);
+
+// GMRES helpers on batches of complex128 vectors of length n.
+void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
+                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st);
+void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
+                   const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride,
+                   double sign, hipStream_t st);
+void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st);
+void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
+                       const double* scale, hipStream_t st);
+void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,
+                  hipStream_t st);
+void launch_zero(double* p, int64_t n, hipStream_t st);
+void launch_zero_f(float* p, int64_t n, hipStream_t st);
+void launch_pack_cols(const double* src, int64_t sstride, int E, int nvec, double* dst, hipStream_t st);
+void launch_unpack_cols(const double* src, int E, int nvec, double* dst, int64_t dstride, hipStream_t st);
+
+// Far field: per-triangle RT0 coefficients of the currents, then the pattern.
+void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
+                      const double* obs, int nobs, double* F_out, hipStream_t st);
+void launch_sigma_sca(const double* F, int nobs, int nrhs, const double* w, double* out, hipStream_t st);
+
+}  // namespace pmchwt

@@ -1,0 +1,430 @@
+// Operator application and Krylov kernels (Section 3.2 product operator,
+// GMRES of Section 4).
+//
+// Dense operators are HBM-bound at a few right-hand sides: each wavefront
+// streams rows of S and C once for all vectors of the batch and accumulates in
+// FP64 (also for FP32 storage).  Krylov vectors are complex128.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pmchwt {
+
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+template <typename M>
+struct Pair2 {
+  M re, im;
+};
+
+// ---------------------------------------------------------------------------
+// yD += C xD + (1/k) S xN ; yN += -k S xD + C xN, one wavefront per row.
+// ---------------------------------------------------------------------------
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, const M* __restrict__ C,
+                                                     int64_t ld, int rows, int cols, double kr, double ki,
+                                                     const double* __restrict__ xD,
+                                                     const double* __restrict__ xN, double* yD, double* yN,
+                                                     int64_t vstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= rows) return;
+  double a[NR][8];
+  for (int r = 0; r < NR; ++r)
+    for (int q = 0; q < 8; ++q) a[r][q] = 0.0;
+  const Pair2<M>* Sr = reinterpret_cast<const Pair2<M>*>(S + 2 * int64_t(row) * ld);
+  const Pair2<M>* Cr = reinterpret_cast<const Pair2<M>*>(C + 2 * int64_t(row) * ld);
+  for (int j = lane; j < cols; j += 64) {
+    const Pair2<M> s = Sr[j], c = Cr[j];
+    const double sr = double(s.re), si = double(s.im), cr = double(c.re), ci = double(c.im);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* pd = xD + 2 * (int64_t(r) * vstride + j);
+      const double* pn = xN + 2 * (int64_t(r) * vstride + j);
+      const double dr = pd[0], di = pd[1], nr = pn[0], ni = pn[1];
+      a[r][0] += cr * dr - ci * di;  // C xD
+      a[r][1] += cr * di + ci * dr;
+      a[r][2] += sr * nr - si * ni;  // S xN
+      a[r][3] += sr * ni + si * nr;
+      a[r][4] += sr * dr - si * di;  // S xD
+      a[r][5] += sr * di + si * dr;
+      a[r][6] += cr * nr - ci * ni;  // C xN
+      a[r][7] += cr * ni + ci * nr;
+    }
+  }
+  for (int r = 0; r < NR; ++r)
+    for (int q = 0; q < 8; ++q) a[r][q] = wsum(a[r][q]);
+  if (lane == 0) {
+    const double k2 = kr * kr + ki * ki;
+    const double ikr = kr / k2, iki = -ki / k2;  // 1/k
+    for (int r = 0; r < NR; ++r) {
+      double* yd = yD + 2 * (int64_t(r) * vstride + row);
+      double* yn = yN + 2 * (int64_t(r) * vstride + row);
+      // S xN / k
+      const double t_re = a[r][2] * ikr - a[r][3] * iki, t_im = a[r][2] * iki + a[r][3] * ikr;
+      // -k S xD
+      const double u_re = -(kr * a[r][4] - ki * a[r][5]), u_im = -(kr * a[r][5] + ki * a[r][4]);
+      yd[0] += a[r][0] + t_re;
+      yd[1] += a[r][1] + t_im;
+      yn[0] += u_re + a[r][6];
+      yn[1] += u_im + a[r][7];
+    }
+  }
+}
+
+template <typename M>
+void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
+                        const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
+                        hipStream_t st) {
+  const dim3 grid((rows + 3) / 4), block(256);
+  int r0 = 0;
+  while (r0 < nrhs) {
+    const int left = nrhs - r0;
+    const double* xd = xD + 2 * int64_t(r0) * vstride;
+    const double* xn = xN + 2 * int64_t(r0) * vstride;
+    double* yd = yD + 2 * int64_t(r0) * vstride;
+    double* yn = yN + 2 * int64_t(r0) * vstride;
+    if (left >= 4) {
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 4>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
+                         vstride);
+      r0 += 4;
+    } else if (left >= 2) {
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 2>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
+                         vstride);
+      r0 += 2;
+    } else {
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 1>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
+                         vstride);
+      r0 += 1;
+    }
+  }
+}
+template void launch_gemv_pmchwt<double>(const double*, const double*, int64_t, int, int, double, double,
+                                         const double*, const double*, double*, double*, int, int64_t,
+                                         hipStream_t);
+template void launch_gemv_pmchwt<float>(const float*, const float*, int64_t, int, int, double, double,
+                                        const double*, const double*, double*, double*, int, int64_t,
+                                        hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Same block structure on a CSR pattern; S or C may be null.
+// ---------------------------------------------------------------------------
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col, const M* __restrict__ S,
+                                                     const M* __restrict__ C, int rows, double kr, double ki,
+                                                     const double* __restrict__ xD,
+                                                     const double* __restrict__ xN, double* yD, double* yN,
+                                                     int64_t vstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= rows) return;
+  double a[NR][8];
+  for (int r = 0; r < NR; ++r)
+    for (int q = 0; q < 8; ++q) a[r][q] = 0.0;
+  for (int64_t p = rowptr[row] + lane; p < rowptr[row + 1]; p += 64) {
+    const int j = col[p];
+    double sr = 0, si = 0, cr = 0, ci = 0;
+    if (S) {
+      sr = double(S[2 * p]);
+      si = double(S[2 * p + 1]);
+    }
+    if (C) {
+      cr = double(C[2 * p]);
+      ci = double(C[2 * p + 1]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* pd = xD + 2 * (int64_t(r) * vstride + j);
+      const double* pn = xN + 2 * (int64_t(r) * vstride + j);
+      const double dr = pd[0], di = pd[1], nr = pn[0], ni = pn[1];
+      a[r][0] += cr * dr - ci * di;
+      a[r][1] += cr * di + ci * dr;
+      a[r][2] += sr * nr - si * ni;
+      a[r][3] += sr * ni + si * nr;
+      a[r][4] += sr * dr - si * di;
+      a[r][5] += sr * di + si * dr;
+      a[r][6] += cr * nr - ci * ni;
+      a[r][7] += cr * ni + ci * nr;
+    }
+  }
+  for (int r = 0; r < NR; ++r)
+    for (int q = 0; q < 8; ++q) a[r][q] = wsum(a[r][q]);
+  if (lane == 0) {
+    const double k2 = kr * kr + ki * ki;
+    const double ikr = kr / k2, iki = -ki / k2;
+    for (int r = 0; r < NR; ++r) {
+      double* yd = yD + 2 * (int64_t(r) * vstride + row);
+      double* yn = yN + 2 * (int64_t(r) * vstride + row);
+      const double t_re = a[r][2] * ikr - a[r][3] * iki, t_im = a[r][2] * iki + a[r][3] * ikr;
+      const double u_re = -(kr * a[r][4] - ki * a[r][5]), u_im = -(kr * a[r][5] + ki * a[r][4]);
+      yd[0] += a[r][0] + t_re;
+      yd[1] += a[r][1] + t_im;
+      yn[0] += u_re + a[r][6];
+      yn[1] += u_im + a[r][7];
+    }
+  }
+}
+
+template <typename M>
+void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows, double kr,
+                        double ki, const double* xD, const double* xN, double* yD, double* yN, int nrhs,
+                        int64_t vstride, hipStream_t st) {
+  const dim3 grid((rows + 3) / 4), block(256);
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0;
+    const double* xd = xD + 2 * int64_t(r0) * vstride;
+    const double* xn = xN + 2 * int64_t(r0) * vstride;
+    double* yd = yD + 2 * int64_t(r0) * vstride;
+    double* yn = yN + 2 * int64_t(r0) * vstride;
+    if (left >= 4) {
+      hipLaunchKernelGGL((k_spmv_pmchwt<M, 4>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
+                         yn, vstride);
+      r0 += 4;
+    } else {
+      hipLaunchKernelGGL((k_spmv_pmchwt<M, 1>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
+                         yn, vstride);
+      r0 += 1;
+    }
+  }
+}
+template void launch_spmv_pmchwt<double>(const int64_t*, const int32_t*, const double*, const double*, int,
+                                         double, double, const double*, const double*, double*, double*, int,
+                                         int64_t, hipStream_t);
+template void launch_spmv_pmchwt<float>(const int64_t*, const int32_t*, const float*, const float*, int, double,
+                                        double, const double*, const double*, double*, double*, int, int64_t,
+                                        hipStream_t);
+
+// ---------------------------------------------------------------------------
+// y = alpha * M x, M real dense row-major; complex vectors (overwrites y).
+// ---------------------------------------------------------------------------
+template <int NR>
+__global__ __launch_bounds__(256) void k_gemv_real(const double* __restrict__ Mat, int64_t ld, int rows, int cols,
+                                                   double alpha, const double* __restrict__ x, double* y,
+                                                   int64_t vstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= rows) return;
+  double a[NR][2];
+  for (int r = 0; r < NR; ++r) a[r][0] = a[r][1] = 0.0;
+  const double* mr = Mat + int64_t(row) * ld;
+  for (int j = lane; j < cols; j += 64) {
+    const double m = mr[j];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* px = x + 2 * (int64_t(r) * vstride + j);
+      a[r][0] += m * px[0];
+      a[r][1] += m * px[1];
+    }
+  }
+  for (int r = 0; r < NR; ++r) {
+    a[r][0] = wsum(a[r][0]);
+    a[r][1] = wsum(a[r][1]);
+  }
+  if (lane == 0)
+    for (int r = 0; r < NR; ++r) {
+      double* py = y + 2 * (int64_t(r) * vstride + row);
+      py[0] = alpha * a[r][0];
+      py[1] = alpha * a[r][1];
+    }
+}
+
+void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+                      int nrhs, int64_t vstride, hipStream_t st) {
+  const dim3 grid((rows + 3) / 4), block(256);
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0;
+    const double* xx = x + 2 * int64_t(r0) * vstride;
+    double* yy = y + 2 * int64_t(r0) * vstride;
+    if (left >= 8) {
+      hipLaunchKernelGGL((k_gemv_real<8>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride);
+      r0 += 8;
+    } else if (left >= 2) {
+      hipLaunchKernelGGL((k_gemv_real<2>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride);
+      r0 += 2;
+    } else {
+      hipLaunchKernelGGL((k_gemv_real<1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride);
+      r0 += 1;
+    }
+  }
+}
+
+__global__ void k_transpose(const double* in, double* out, int n) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = by + k, j = bx + threadIdx.x;
+    if (i < n && j < n) tile[k][threadIdx.x] = in[int64_t(i) * n + j];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = bx + k, j = by + threadIdx.x;
+    if (i < n && j < n) out[int64_t(i) * n + j] = tile[threadIdx.x][k];
+  }
+}
+
+void launch_transpose(const double* in, double* out, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, in, out, n);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov helpers.  Vector i of right-hand side r: V + 2*(i*vstep + r*rstride_v).
+// ---------------------------------------------------------------------------
+__global__ void k_dots(const double* V, int64_t vstep, const double* w, int64_t wstride, int n,
+                       const int32_t* active, int64_t rstride_v, double* out, int nvec) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  if (!active[r]) return;
+  const double* v = V + 2 * (int64_t(i) * vstep + int64_t(r) * rstride_v);
+  const double* ww = w + 2 * int64_t(r) * wstride;
+  double re = 0, im = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double vr = v[2 * k], vi = v[2 * k + 1], xr = ww[2 * k], xi = ww[2 * k + 1];
+    re += vr * xr + vi * xi;  // conj(v) w
+    im += vr * xi - vi * xr;
+  }
+  __shared__ double sr[256], si[256];
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * (int64_t(r) * nvec + i)] = sr[0];
+    out[2 * (int64_t(r) * nvec + i) + 1] = si[0];
+  }
+}
+
+void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
+                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots, dim3(nvec, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v, out,
+                     nvec);
+}
+
+// w^r[k] += sign * sum_i V_i^r[k] h[r][i]
+__global__ void k_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
+                         const int32_t* active, int64_t rstride_v, const double* h, int64_t hstride, double sign) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= n || !active[r]) return;
+  double re = 0, im = 0;
+  for (int i = 0; i < nvec; ++i) {
+    const double* v = V + 2 * (int64_t(i) * vstep + int64_t(r) * rstride_v + k);
+    const double hr = h[2 * (int64_t(r) * hstride + i)], hi = h[2 * (int64_t(r) * hstride + i) + 1];
+    re += v[0] * hr - v[1] * hi;
+    im += v[0] * hi + v[1] * hr;
+  }
+  double* ww = w + 2 * (int64_t(r) * wstride + k);
+  ww[0] += sign * re;
+  ww[1] += sign * im;
+}
+
+void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
+                   const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride, double sign,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
+                     rstride_v, h, hstride, sign);
+}
+
+__global__ void k_norms(const double* w, int64_t wstride, int n, double* out) {
+  const int r = blockIdx.x;
+  const double* ww = w + 2 * int64_t(r) * wstride;
+  double s = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) s += ww[2 * k] * ww[2 * k] + ww[2 * k + 1] * ww[2 * k + 1];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = sqrt(red[0]);
+}
+
+void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norms, dim3(nrhs), dim3(256), 0, st, w, wstride, n, out);
+}
+
+__global__ void k_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n,
+                             const double* scale) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= n) return;
+  const double s = scale[r];
+  v[2 * (int64_t(r) * vstride + k)] = s * w[2 * (int64_t(r) * wstride + k)];
+  v[2 * (int64_t(r) * vstride + k) + 1] = s * w[2 * (int64_t(r) * wstride + k) + 1];
+}
+
+void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
+                       const double* scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, w, wstride, v, vstride, n, scale);
+}
+
+// y = a y + b x  (complex vectors, real scalars)
+__global__ void k_axpby(double* y, const double* x, int64_t stride, int n, double a, double b) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= 2 * int64_t(n)) return;
+  const int64_t o = 2 * int64_t(r) * stride + k;
+  y[o] = a * y[o] + b * x[o];
+}
+
+void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(unsigned((2 * int64_t(n) + 255) / 256), nrhs), dim3(256), 0, st, y, x, stride, n,
+                     a, b);
+}
+
+template <typename T>
+__global__ void k_zero(T* p, int64_t n) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x)
+    p[k] = T(0);
+}
+
+void launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_zero<double>, dim3(unsigned(blocks)), dim3(256), 0, st, p, n);
+}
+
+void launch_zero_f(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_zero<float>, dim3(unsigned(blocks)), dim3(256), 0, st, p, n);
+}
+
+// complex vectors (nvec, each E long, stride sstride complex) <-> real
+// column-major matrix E x 2 nvec (re, im columns), for LAPACK-style solves.
+__global__ void k_pack(const double* src, int64_t sstride, int E, int nvec, double* dst) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= int64_t(E) * nvec) return;
+  const int q = int(k / E), e = int(k % E);
+  dst[int64_t(2 * q) * E + e] = src[2 * (int64_t(q) * sstride + e)];
+  dst[int64_t(2 * q + 1) * E + e] = src[2 * (int64_t(q) * sstride + e) + 1];
+}
+
+__global__ void k_unpack(const double* src, int E, int nvec, double* dst, int64_t dstride) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= int64_t(E) * nvec) return;
+  const int q = int(k / E), e = int(k % E);
+  dst[2 * (int64_t(q) * dstride + e)] = src[int64_t(2 * q) * E + e];
+  dst[2 * (int64_t(q) * dstride + e) + 1] = src[int64_t(2 * q + 1) * E + e];
+}
+
+void launch_pack_cols(const double* src, int64_t sstride, int E, int nvec, double* dst, hipStream_t st) {
+  const int64_t n = int64_t(E) * nvec;
+  hipLaunchKernelGGL(k_pack, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, src, sstride, E, nvec, dst);
+}
+
+void launch_unpack_cols(const double* src, int E, int nvec, double* dst, int64_t dstride, hipStream_t st) {
+  const int64_t n = int64_t(E) * nvec;
+  hipLaunchKernelGGL(k_unpack, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, src, E, nvec, dst, dstride);
+}
+
+}  // namespace pmchwt

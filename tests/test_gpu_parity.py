@@ -1,0 +1,111 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical inputs.
+
+Tolerances (stated per operator): FP64 Galerkin blocks 1e-10 relative
+(Frobenius and max-entry), FP32-regular / FP64-singular blocks 1e-4, FP64
+solves at tol 1e-11 to 1e-8, cross sections 1e-6 (the oracle's
+and the library's far-field rules are identical).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import note, rel_fro, rel_max, make_ctx
+from oracle import operators as ops
+from oracle import pmchwt as opm
+from oracle.mesh import Topology, Barycentric
+
+pytestmark = pytest.mark.gpu
+
+EPS = 3.17 + 0.01j
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2008_04772_amd as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def sphere1():
+    return synth.icosphere(1)
+
+
+@pytest.fixture(scope="module")
+def oracle_sphere1(sphere1):
+    pr = opm.Problem([sphere1], EPS, 1.3, precond="D", qP=(4, 3, 2), nP=4)
+    pr.assemble_A()
+    pr.assemble_P()
+    pr.assemble_mass()
+    return pr
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-4)])
+def test_A_blocks(P, sphere1, oracle_sphere1, precision, tol):
+    note(f"A blocks: icosphere(1), k=1.3, precision={precision}")
+    ctx = make_ctx(P, [sphere1], EPS, 1.3, precond="D", precision=precision)
+    pr = oracle_sphere1
+    for op, med, ref in ((P.OP_S, P.EXT, pr.Se), (P.OP_C, P.EXT, pr.Ce),
+                         (P.OP_S, P.INT, pr.Si[0]), (P.OP_C, P.INT, pr.Ci[0])):
+        got = ctx.get_block(op, med, P.RWG, 0, 0)
+        note(f"  op={op} med={med} fro={rel_fro(got, ref):.2e} max={rel_max(got, ref):.2e}")
+        assert rel_fro(got, ref) < tol and rel_max(got, ref) < tol
+
+
+def test_P_blocks_full_and_mass(P, sphere1, oracle_sphere1):
+    note("P (=D) BC blocks and mixed mass: icosphere(1), q=(4,3,2), n=4")
+    ctx = make_ctx(P, [sphere1], EPS, 1.3, precond="D")
+    pr = oracle_sphere1
+    for op, med, key in ((P.OP_S, P.INT, ("int", 0, "S")), (P.OP_C, P.INT, ("int", 0, "C")),
+                         (P.OP_S, P.EXT, ("ext", 0, "S")), (P.OP_C, P.EXT, ("ext", 0, "C"))):
+        got = ctx.get_block(op, med, P.BC, 0, 0)
+        ref = pr.PBC[key]
+        note(f"  {key} fro={rel_fro(got, ref):.2e} max={rel_max(got, ref):.2e}")
+        assert rel_fro(got, ref) < 1e-10 and rel_max(got, ref) < 1e-10
+    M = ctx.get_mass(0)
+    note(f"  mass fro={rel_fro(M, pr.MA[0]):.2e}")
+    assert rel_fro(M, pr.MA[0]) < 1e-12
+
+
+@pytest.mark.parametrize("chi", [0.3, 0.0])
+def test_P_nearfield_cutoff(P, sphere1, chi):
+    note(f"near-field S^i on BC: icosphere(1), chi={chi}, q=(1,1,1), n=1")
+    ctx = make_ctx(P, [sphere1], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=chi, precond="S_INT")
+    B = Barycentric(Topology(*sphere1))
+    lo, hi = ops.bc_bboxes(B)
+    mask = ops.nearfield_mask(lo, hi, chi)
+    ref = ops.assemble_bc(B, 2.0 * np.sqrt(EPS), (1, 1, 1), 1, ("S",))["S"] * mask
+    got = ctx.get_block(P.OP_S, P.INT, P.BC, 0, 0)
+    assert np.array_equal(got != 0, mask)
+    note(f"  fro={rel_fro(got, ref):.2e} nnz={mask.sum()}")
+    assert rel_fro(got, ref) < 1e-10
+
+
+def test_rhs_apply_solve_cross_sections(P, sphere1, oracle_sphere1):
+    note("rhs / apply / solve / cross sections: icosphere(1), P = D")
+    pr = oracle_sphere1
+    ctx = make_ctx(P, [sphere1], EPS, 1.3, precond="D")
+    dirs, pols = synth.plane_wave_set(2, seed=7)
+    b_ref = pr.rhs(dirs, pols)
+    b = ctx.rhs(dirs, pols)
+    note(f"  rhs fro={rel_fro(b, b_ref):.2e}")
+    assert rel_fro(b, b_ref) < 1e-11
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, pr.N)) + 1j * rng.normal(size=(2, pr.N))
+    y = ctx.apply(0, x)
+    assert rel_fro(y, x @ pr.A.T) < 1e-11
+    Pt = pr.precond_matrix()
+    y = ctx.apply(1, x)
+    note(f"  apply Ptilde A fro={rel_fro(y, x @ (Pt @ pr.A).T):.2e}")
+    assert rel_fro(y, x @ (Pt @ pr.A).T) < 1e-10
+    xs, st = ctx.solve(dirs, pols, P.solver_opts(tol=1e-12, restart=200, max_iter=500))
+    x_ref = pr.solve_direct(b_ref)
+    note(f"  solve iters={st.iterations} matvecs={st.matvecs} err={rel_fro(xs, x_ref):.2e}")
+    assert rel_fro(xs, x_ref) < 1e-9
+    se, ss = ctx.cross_sections(xs, dirs, pols)
+    se_ref, ss_ref = pr.cross_sections(x_ref, dirs, pols)
+    note(f"  sigma_ext {se} vs {se_ref}; sigma_sca {ss} vs {ss_ref}")
+    assert np.allclose(se, se_ref, rtol=1e-8) and np.allclose(ss, ss_ref, rtol=1e-8)
+    obs = synth.plane_wave_set(3, seed=9)[0]
+    F = ctx.far_field(xs, obs)
+    assert rel_fro(F, pr.far_field(x_ref, obs)) < 1e-9
