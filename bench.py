@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the PMCHWT hot path on one MI355X.
+
+Workload: dielectric sphere of radius 1, icosphere with 5120 triangles (7680
+RWG edges, 15360 unknowns), k_e = 5, eps_r = 3.17 + 0.01i, one plane wave
+along +z polarised along x.  A is assembled densely with q = (4, 3, 2) and
+4^4-point Sauter-Schwab rules; the preconditioner is the reduced S^i on the
+barycentric mesh, near field only (cutoff 2 mean edge lengths), q = (1,1,1,1);
+GMRES(200) to 1e-5.  One step = assemble A, P and the mass matrices, build
+the right-hand side, solve, and evaluate the cross sections.
+
+Prints one JSON line.  value = element-pair quadratures per second over the
+whole step (ordered triangle pairs x wavenumbers of A, plus barycentric pairs
+of P), for the mixed form (FP32 disjoint pairs and operators, FP64 singular
+pairs, Arnoldi and refinement).  The plain FP64 form is timed beside it.
+"""
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-pair quadratures/s + PMCHWT solves/s (mixed vs FP64); p50/p99 latency"
+EPS = 3.17 + 0.01j
+K_EXT = 5.0
+# algorithmic FP operations per point pair of the regular kernel: 22 shared
+# (d, r^2, x.y, x cross y) + 78 per wavenumber (kernel value and gradient
+# factor, 14 complex moment updates); transcendental calls count as one
+FLOP_SHARED, FLOP_PER_K = 22, 78
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector TFLOP/s
+HBM_PEAK = 8000.0  # GB/s
+
+
+def workload():
+    import synth
+    v, t = synth.icosphere(4)
+    chi = 2.0 * synth.mean_edge_length(v, t)
+    d, p = synth.single_wave()
+    return v, t, chi, d, p
+
+
+def run(P, mesh, chi, dirs, pols, precision, steps, warmup):
+    v, t = mesh
+    lat, stats = [], None
+    with P.Context(0) as ctx:
+        ctx.add_scatterer(v, t, EPS)
+        ctx.set_wavenumber(K_EXT)
+        oA = P.assembly_opts((4, 3, 2), 4, -1.0, P.MIXED if precision == "mixed" else P.FP64)
+        oP = P.assembly_opts((1, 1, 1), 1, chi, P.FP64)
+        so = P.solver_opts(tol=1e-5, restart=200, max_iter=2000, ir_max=2 if precision == "mixed" else 0)
+        profs = []
+        for s in range(warmup + steps):
+            t0 = time.perf_counter()
+            ctx.assemble(oA, oP, "S_INT")
+            x, st = ctx.solve(dirs, pols, so)
+            se, ss = ctx.cross_sections(x, dirs, pols)
+            dt = time.perf_counter() - t0
+            if s >= warmup:
+                lat.append(dt)
+                profs.append(ctx.profile())
+            stats = st
+            print(f"[bench] {precision} step {s} {dt * 1e3:.1f} ms, GMRES iters {st.iterations}", file=sys.stderr,
+                  flush=True)
+    return lat, profs, stats, float(se[0]), float(ss[0])
+
+
+def cpu_baseline(mesh, budget_s=15.0):
+    """The oracle, single-threaded, on a seeded sample of the workload's ordered triangle pairs."""
+    from threadpoolctl import threadpool_limits
+    from oracle.mesh import Topology
+    from oracle import operators as ops
+    T = Topology(*mesh)
+    rng = np.random.default_rng(11)
+    k_i = K_EXT * np.sqrt(EPS)
+    done, t_used, n_pairs = 0, 0.0, 0
+    with threadpool_limits(1):
+        geom = ops._tri_geom(T)
+        while t_used < budget_s:
+            t1 = rng.integers(0, T.F, 2000)
+            t2 = rng.integers(0, T.F, 2000)
+            rel = ops.classify(T, t1, t2, geom)
+            t0 = time.perf_counter()
+            for c in np.unique(rel):
+                s = rel == c
+                for k in (K_EXT, k_i):
+                    ops.local_blocks(T, t1[s], t2[s], int(c), k)
+            t_used += time.perf_counter() - t0
+            done += 2 * len(t1)
+            n_pairs += len(t1)
+    return {"value": done / t_used, "unit": "element-pair quadratures/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_pairs} seeded random ordered triangle pairs of the 5120-triangle sphere, both "
+                      f"wavenumbers, q = (4,3,2) and 4^4 Sauter-Schwab points, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import paper_2008_04772_amd as P
+    v, t, chi, dirs, pols = workload()
+    results = {}
+    for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        results[prec] = run(P, (v, t), chi, dirs, pols, prec, args.steps, args.warmup)
+    head = "mixed" if "mixed" in results else "fp64"
+    lat, profs, st, se, ss = results[head]
+    pr = profs[-1]
+    quads = 2 * (pr["regular_pairs"] + pr["singular_pairs"]) + pr["bary_pairs"]
+    ms = 1e3 * statistics.mean(lat)
+    value = quads / (ms / 1e3)
+    # dominant kernel: the regular-pair assembly kernel or the dense operator application
+    reg_ms = statistics.mean(p["ms_assemble_regular"] for p in profs) / max(1, pr["regular_launches"])
+    mv_ms_total = statistics.mean(p["ms_matvec_total"] for p in profs)
+    dtype_reg = "fp32" if head == "mixed" else "fp64"
+    if reg_ms * pr["regular_launches"] >= mv_ms_total:
+        flops = (pr["regular_point_pairs"] / 2) * (FLOP_SHARED + 2 * FLOP_PER_K) / pr["regular_launches"]
+        ach = flops / (reg_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_regular", "bound": "alu", "achieved": ach, "peak": PEAK[dtype_reg],
+                "unit": "TFLOP/s", "frac": ach / PEAK[dtype_reg], "traffic": None}
+    else:
+        per = statistics.mean(p["ms_matvec_total"] / max(1, p["matvec_launches"]) for p in profs)
+        byt = pr["matvec_bytes"] / max(1, pr["matvec_launches"])
+        ach = byt / (per * 1e-3) / 1e9
+        roof = {"kernel": "k_gemv_pmchwt", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": ach / HBM_PEAK, "traffic": None}
+    out = {
+        "metric": METRIC, "value": value, "unit": "element-pair quadratures/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32+fp64" if head == "mixed" else "fp64", "data": "synthetic",
+        "config": {"workload": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, "
+                               "1 plane wave; A dense q=(4,3,2,6); P = S^i near field chi=2h, q=(1,1,1,1); "
+                               "GMRES(200) tol 1e-5",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "solves_per_s": 1e3 / ms,
+        "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+        "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+        "quadratures_per_step": quads,
+        "gmres_iterations": st.iterations,
+        "assembly_ms": {"A": pr["ms_assemble_A"], "regular": pr["ms_assemble_regular"],
+                        "singular": pr["ms_assemble_singular"], "P": pr["ms_assemble_P"], "mass": pr["ms_mass"]},
+        "solve_ms": st.ms_solve,
+        "Q_ext": se / np.pi, "Q_sca": ss / np.pi,
+        "roofline": roof,
+    }
+    if "fp64" in results and head == "mixed":
+        l64 = results["fp64"][0]
+        out["fp64"] = {"ms_per_step": 1e3 * statistics.mean(l64),
+                       "quadratures_per_s": quads / statistics.mean(l64),
+                       "assembly_regular_ms": results["fp64"][1][-1]["ms_assemble_regular"],
+                       "Q_ext": results["fp64"][3] / np.pi}
+        out["mixed_speedup"] = statistics.mean(l64) / statistics.mean(lat)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline((v, t))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,6 +115,8 @@ struct pmchwt_ctx {
   DBuf work;
   size_t work_bytes = 0;
   pmchwt_profile prof{};
+  int64_t count_key = -1, count_pairs = 0, count_pts = 0;
+  int64_t calls_A = 0, calls_P = 0;  // operator applications (batched calls) since the last reset
 
   ~pmchwt_ctx() {
     if (blas) rocblas_destroy_handle(blas);
@@ -486,9 +488,15 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   }
   c->prof.ms_assemble_A = all.stop();
   c->prof.regular_launches = (c->F_tot + 65534) / 65535;
-  // work counters: disjoint ordered pairs by class (host count, same rule as the kernel)
+  // work counters: disjoint ordered pairs by class (host count, same rule as
+  // the kernel); pure metadata of the mesh and the rule orders, kept across
+  // assemblies of the same geometry
+  const int64_t ckey = (int64_t(c->F_tot) << 12) | (o.q_near << 8) | (o.q_medium << 4) | o.q_far;
   int64_t reg_pairs = 0, reg_pts = 0;
-  {
+  if (c->count_key == ckey) {
+    reg_pairs = c->count_pairs;
+    reg_pts = c->count_pts;
+  } else {
     const int F = c->F_tot;
     std::vector<double> cen(3 * size_t(F)), dm(F);
     std::vector<std::array<int32_t, 3>> vid(F);
@@ -526,6 +534,9 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
         reg_pairs += 2;
         reg_pts += 2 * int64_t(np[qs[cls]]) * np[qs[cls]];
       }
+    c->count_key = ckey;
+    c->count_pairs = reg_pairs;
+    c->count_pts = reg_pts;
   }
   c->prof.regular_pairs = reg_pairs;
   c->prof.regular_point_pairs = reg_pts;
@@ -767,33 +778,58 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
       }
     }
   }
-  std::unordered_map<int64_t, int64_t> pair_index;
+  // cell pairs: (cv, cw) such that some kept (i, j) has an end point in cv
+  // and one in cw; per pair an N_cv x N_cw table of CSR positions
   std::vector<int32_t> cpairs;
   std::vector<int64_t> slot_off{0}, slot_pos;
-  const int64_t ncell = int64_t(cell_n.size());
-  for (int i = 0; i < E; ++i)
-    for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) {
-      const int j = c->h_col[p];
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-          const int cv = ecell[2 * size_t(i) + a], cw = ecell[2 * size_t(j) + b];
-          const int64_t key = int64_t(cv) * ncell + cw;
-          auto it = pair_index.find(key);
-          int64_t idx;
-          if (it == pair_index.end()) {
-            idx = int64_t(cpairs.size() / 2);
-            pair_index.emplace(key, idx);
-            cpairs.push_back(cv);
-            cpairs.push_back(cw);
-            const int64_t ns = int64_t(cell_n[cv]) * cell_n[cw];
-            slot_off.push_back(slot_off.back() + ns);
-            slot_pos.resize(slot_pos.size() + ns, -1);
-          } else {
-            idx = it->second;
-          }
-          slot_pos[slot_off[idx] + int64_t(eslot[2 * size_t(i) + a]) * cell_n[cw] + eslot[2 * size_t(j) + b]] = p;
-        }
+  const int ncell = int(cell_n.size());
+  std::vector<int32_t> cell_edges_ptr(ncell + 1, 0), cell_edges;
+  for (auto& s : c->sc)
+    for (int v = 0; v < s.topo.nv; ++v) {
+      for (int q = s.dual.inc_ptr[v]; q < s.dual.inc_ptr[v + 1]; ++q) cell_edges.push_back(s.edge_off + s.dual.inc_edges[q]);
+      cell_edges_ptr[s.cell_off + v + 1] = int32_t(cell_edges.size());
     }
+  std::vector<int32_t> stamp(ncell, -1);
+  std::vector<int64_t> colpos(E, -1);
+  std::vector<int32_t> cws;
+  for (int cv = 0; cv < ncell; ++cv) {
+    cws.clear();
+    for (int q = cell_edges_ptr[cv]; q < cell_edges_ptr[cv + 1]; ++q) {
+      const int i = cell_edges[q];
+      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) {
+        const int j = c->h_col[p];
+        for (int b = 0; b < 2; ++b) {
+          const int cw = ecell[2 * size_t(j) + b];
+          if (stamp[cw] != cv) {
+            stamp[cw] = cv;
+            cws.push_back(cw);
+          }
+        }
+      }
+    }
+    std::sort(cws.begin(), cws.end());
+    const int Nv = cell_n[cv];
+    const size_t first = cpairs.size() / 2;
+    for (int cw : cws) {
+      cpairs.push_back(cv);
+      cpairs.push_back(cw);
+      const int64_t ns = int64_t(Nv) * cell_n[cw];
+      slot_off.push_back(slot_off.back() + ns);
+    }
+    slot_pos.resize(size_t(slot_off.back()), -1);
+    for (int si = 0; si < Nv; ++si) {
+      const int i = cell_edges[cell_edges_ptr[cv] + si];
+      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) colpos[c->h_col[p]] = p;
+      for (size_t k = 0; k < cws.size(); ++k) {
+        const int cw = cws[k];
+        const int Nw = cell_n[cw];
+        const int64_t base = slot_off[first + k] + int64_t(si) * Nw;
+        for (int sj = 0; sj < Nw; ++sj) slot_pos[base + sj] = colpos[cell_edges[cell_edges_ptr[cw] + sj]];
+      }
+      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) colpos[c->h_col[p]] = -1;
+    }
+  }
+  (void)eslot;
   int64_t bary_pairs = 0;
   for (size_t q = 0; q < cpairs.size(); q += 2) bary_pairs += int64_t(4) * cell_n[cpairs[q]] * cell_n[cpairs[q + 1]];
   c->prof.bary_pairs = bary_pairs;
@@ -845,6 +881,31 @@ void rocsolver_check(rocblas_status s, const char* what) {
   if (s != rocblas_status_success) throw Fail{PMCHWT_ERR_DEVICE, std::string(what) + " failed"};
 }
 
+// In-place inverse of a column-major n x n matrix by blocked Gauss-Jordan
+// elimination without pivoting: per 128-wide pivot block, the block inverse
+// (one-workgroup kernel) and two rocBLAS GEMMs (row-block scaling and the
+// rank-128 update of the whole matrix).  Stable here because the symmetric
+// part of the mixed mass matrix is positive definite.
+void gj_inverse(pmchwt_ctx* c, double* X, int n) {
+  const int B = 128;
+  DBuf Pinv = dalloc<double>(size_t(B) * B), Cc = dalloc<double>(size_t(n) * B), R = dalloc<double>(size_t(B) * n);
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  for (int p0 = 0; p0 < n; p0 += B) {
+    const int b = std::min(B, n - p0);
+    launch_gj_block_inverse(X + int64_t(p0) * n + p0, n, Pinv.as<double>(), b, c->stream);
+    launch_gj_take_columns(X, n, p0, b, Cc.as<double>(), c->stream);
+    rocsolver_check(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, b, n, b, &one,
+                                  Pinv.as<double>(), b, X + p0, n, &zero, R.as<double>(), b),
+                    "rocblas_dgemm(row block)");
+    rocsolver_check(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, n, b, &mone,
+                                  Cc.as<double>(), n, R.as<double>(), b, &one, X, n),
+                    "rocblas_dgemm(rank update)");
+    HIPCHK(hipMemcpy2DAsync(X + p0, size_t(n) * 8, R.p, size_t(b) * 8, size_t(b) * 8, size_t(n),
+                            hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
 void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   EvTimer t(c->stream);
   c->MA.clear();
@@ -887,29 +948,16 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(G.p, gram.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
-    DBuf piv = dalloc<rocblas_int>(size_t(n)), info = dalloc<rocblas_int>(1), gpiv = dalloc<rocblas_int>(size_t(n));
     // row-major M_A is column-major M_A^T; inverting it in place yields the
     // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
-    rocsolver_check(rocsolver_dgetrf(c->blas, n, n, Mi.as<double>(), n, piv.as<rocblas_int>(), info.as<rocblas_int>()),
-                    "rocsolver_dgetrf(mass)");
-    rocsolver_check(rocsolver_dgetri(c->blas, n, Mi.as<double>(), n, piv.as<rocblas_int>(), info.as<rocblas_int>()),
-                    "rocsolver_dgetri(mass)");
-    rocblas_int hinfo = 0;
-    HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (hinfo != 0) throw Fail{PMCHWT_ERR_DEVICE, "mixed mass matrix is singular"};
+    gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
-    rocsolver_check(rocsolver_dgetrf(c->blas, n, n, G.as<double>(), n, gpiv.as<rocblas_int>(), info.as<rocblas_int>()),
-                    "rocsolver_dgetrf(gram)");
-    HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (hinfo != 0) throw Fail{PMCHWT_ERR_DEVICE, "RWG Gram matrix is singular"};
     c->MA.push_back(std::move(MA));
     c->Minv.push_back(std::move(Mi));
     c->MinvT.push_back(std::move(MiT));
     c->Glu.push_back(std::move(G));
-    c->Gpiv.push_back(std::move(gpiv));
   }
+  HIPCHK(hipGetLastError());
   c->prof.ms_mass = t.stop();
 }
 
@@ -947,6 +995,7 @@ int64_t P_matvecs(const pmchwt_ctx* c) {
 // y = A x (y overwritten)
 void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
+  c->calls_A += 1;
   launch_zero(y, 2 * vs * nrhs, c->stream);
   EvTimer t(c->stream);
   if (c->precA == PMCHWT_FP64) {
@@ -985,12 +1034,12 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     HIPCHK(hipMemcpyAsync(z, y, size_t(2 * vs * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
     return;
   }
+  c->calls_P += 1;
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    for (int comp = 0; comp < 2; ++comp)
-      launch_gemv_real(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * (comp * E + o),
-                       t1 + 2 * (comp * E + o), nrhs, vs, c->stream);
+    launch_gemv_real2(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E,
+                      c->stream);
   }
   launch_zero(t2, 2 * vs * nrhs, c->stream);
   const int64_t* rp = c->p_rowptr.as<int64_t>();
@@ -1010,9 +1059,8 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    for (int comp = 0; comp < 2; ++comp)
-      launch_gemv_real(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * (comp * E + o),
-                       z + 2 * (comp * E + o), nrhs, vs, c->stream);
+    launch_gemv_real2(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
+                      c->stream);
   }
   HIPCHK(hipGetLastError());
 }
@@ -1043,6 +1091,60 @@ void to_api(const pmchwt_ctx* c, const std::vector<double>& in, int nrhs, pmchwt
         }
 }
 
+// Solve G x_q = b_q for nvec complex vectors (length n, stride `stride`
+// complex) by conjugate gradients; G real symmetric positive definite, dense.
+void gram_cg(pmchwt_ctx* c, const double* G, int n, const double* b_in, double* x_out, int64_t in_stride, int nvec) {
+  // work on packed copies: vector q at q * n
+  const int64_t stride = n;
+  const size_t nd = 2 * size_t(stride) * nvec;
+  DBuf r = dalloc<double>(nd), p = dalloc<double>(nd), q = dalloc<double>(nd), xb = dalloc<double>(nd),
+       sc = dalloc<double>(4 * nvec);
+  DBuf act = dalloc<int32_t>(nvec);
+  double* x = xb.as<double>();
+  std::vector<int32_t> on(nvec, 1);
+  HIPCHK(hipMemcpyAsync(act.p, on.data(), 4 * nvec, hipMemcpyHostToDevice, c->stream));
+  launch_zero(x, 2 * int64_t(stride) * nvec, c->stream);
+  HIPCHK(hipMemcpy2DAsync(r.p, size_t(n) * 16, b_in, size_t(in_stride) * 16, size_t(n) * 16, size_t(nvec),
+                          hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(p.p, r.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
+  double* d = sc.as<double>();
+  std::vector<double> rr(nvec), rr0(nvec), pq(2 * nvec), al(nvec), be(nvec);
+  launch_norms(r.as<double>(), stride, n, nvec, d, c->stream);
+  HIPCHK(hipMemcpyAsync(rr.data(), d, 8 * nvec, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < nvec; ++k) {
+    rr[k] *= rr[k];
+    rr0[k] = rr[k];
+  }
+  for (int it = 0; it < 1000; ++it) {
+    bool done = true;
+    for (int k = 0; k < nvec; ++k) done &= (rr[k] <= 1e-28 * rr0[k]);
+    if (done) break;
+    launch_gemv_real(G, n, n, n, 1.0, p.as<double>(), q.as<double>(), nvec, stride, c->stream);
+    launch_dots(p.as<double>(), 0, 1, q.as<double>(), stride, n, act.as<int32_t>(), nvec, stride, d, c->stream);
+    HIPCHK(hipMemcpyAsync(pq.data(), d, 16 * nvec, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nvec; ++k) al[k] = pq[2 * k] > 0 ? rr[k] / pq[2 * k] : 0.0;
+    HIPCHK(hipMemcpyAsync(d, al.data(), 8 * nvec, hipMemcpyHostToDevice, c->stream));
+    launch_axpy_vec(x, p.as<double>(), stride, n, nvec, d, 1.0, c->stream);
+    launch_axpy_vec(r.as<double>(), q.as<double>(), stride, n, nvec, d, -1.0, c->stream);
+    launch_norms(r.as<double>(), stride, n, nvec, d + nvec, c->stream);
+    std::vector<double> nr(nvec);
+    HIPCHK(hipMemcpyAsync(nr.data(), d + nvec, 8 * nvec, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nvec; ++k) {
+      const double rn = nr[k] * nr[k];
+      be[k] = rr[k] > 0 ? rn / rr[k] : 0.0;
+      rr[k] = rn;
+    }
+    HIPCHK(hipMemcpyAsync(d + 2 * nvec, be.data(), 8 * nvec, hipMemcpyHostToDevice, c->stream));
+    launch_xpby_vec(p.as<double>(), r.as<double>(), stride, n, nvec, d + 2 * nvec, c->stream);
+  }
+  HIPCHK(hipMemcpy2DAsync(x_out, size_t(in_stride) * 16, x, size_t(n) * 16, size_t(n) * 16, size_t(nvec),
+                          hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipGetLastError());
+}
+
 // Galerkin right-hand side into device buffer b (internal layout)
 void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -1069,19 +1171,14 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   j.h = h.as<double>();
   launch_rhs(asm_params<double>(c), j, c->stream);
   HIPCHK(hipGetLastError());
-  // c_inc = G^-1 h per scatterer (LU from rocSOLVER), both components
+  // c_inc = G^-1 h per scatterer: batched conjugate gradients on the SPD
+  // RWG Gram matrix (both components of every wave at once)
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int n = s.topo.E;
-    const int nvec = 2 * nrhs;  // (r, comp)
-    DBuf B = dalloc<double>(size_t(n) * 2 * nvec);
-    // vectors (r, comp) start at h + 2*(r*vs + comp*E + off): stride between
-    // consecutive comp is E, between r is vs = 2E, so nvec vectors with stride E
-    launch_pack_cols(h.as<double>() + 2 * int64_t(s.edge_off), E, n, nvec, B.as<double>(), c->stream);
-    rocsolver_check(rocsolver_dgetrs(c->blas, rocblas_operation_none, n, 2 * nvec, c->Glu[m].as<double>(), n,
-                                     c->Gpiv[m].as<rocblas_int>(), B.as<double>(), n),
-                    "rocsolver_dgetrs(gram)");
-    launch_unpack_cols(B.as<double>(), n, nvec, cinc.as<double>() + 2 * int64_t(s.edge_off), E, c->stream);
+    const int nvec = 2 * nrhs;
+    gram_cg(c, c->Glu[m].as<double>(), n, h.as<double>() + 2 * int64_t(s.edge_off),
+            cinc.as<double>() + 2 * int64_t(s.edge_off), E, nvec);
   }
   // b = g/2 - A^i c_inc
   launch_zero(t.as<double>(), 2 * vs * nrhs, c->stream);
@@ -1356,6 +1453,7 @@ int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const i
     c->sc.push_back(std::move(s));
     c->geo_uploaded = false;
     c->have_A = false;
+    c->count_key = -1;
     if (id) *id = int32_t(c->sc.size() - 1);
     return PMCHWT_OK;
   });
@@ -1591,6 +1689,8 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     c->prof.matvec_launches = 0;
     c->prof.matvec_bytes = 0;
     build_rhs(c, dirs, pols, nrhs, b.as<double>());
+    c->calls_A = 0;  // the right-hand side's own interior products are not solver matvecs
+    c->calls_P = 0;
     // bt = Ptilde b
     apply_Ptilde(c, b.as<double>(), bt.as<double>(), s1.as<double>(), s2.as<double>(), nrhs);
     GmresOut g = gmres(c, bt.as<double>(), x.as<double>(), nrhs, o->tol, o->restart, o->max_iter);
@@ -1632,6 +1732,7 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       it_max += mi;
     }
     const double ms = tm.stop();
+    mv_max = c->calls_A * A_matvecs(c) + c->calls_P * P_matvecs(c);
     std::vector<double> h(nd);
     HIPCHK(hipMemcpyAsync(h.data(), x.p, nd * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -128,6 +128,16 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
 void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
 void launch_transpose(const double* in, double* out, int n, hipStream_t st);
+// y = alpha M x for both trace components (second component at +cstride)
+void launch_gemv_real2(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+                       int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
+// blocked Gauss-Jordan inverse helpers (column-major, no pivoting)
+void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st);
+void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipStream_t st);
+// per-vector scaled updates for batched conjugate gradients
+void launch_axpy_vec(double* y, const double* x, int64_t stride, int n, int nvec, const double* a, double s,
+                     hipStream_t st);
+void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec, const double* b, hipStream_t st);
 
 // GMRES helpers on batches of complex128 vectors of length n.
 void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,

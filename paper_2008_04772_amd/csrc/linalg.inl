@@ -428,3 +428,154 @@ void launch_unpack_cols(const double* src, int E, int nvec, double* dst, int64_t
 }
 
 }  // namespace pmchwt
+
+namespace pmchwt {
+
+// ---------------------------------------------------------------------------
+// In-place inverse of a b x b column-major block (b <= 128) by Gauss-Jordan
+// elimination without pivoting, one workgroup, block held in LDS.  Used on
+// the diagonal blocks of the blocked Gauss-Jordan inverse of the mixed mass
+// matrix, whose symmetric part is positive definite (every leading block is
+// safely invertible without row exchanges).
+// ---------------------------------------------------------------------------
+constexpr int GJ_B = 128;
+
+__global__ __launch_bounds__(512) void k_gj_block_inverse(const double* __restrict__ X, int64_t ldx,
+                                                          double* __restrict__ out, int b) {
+  __shared__ double s[GJ_B * GJ_B];
+  for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
+    const int i = q % b, j = q / b;
+    s[j * GJ_B + i] = X[int64_t(j) * ldx + i];
+  }
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    const double piv = s[k * GJ_B + k];
+    const double ip = 1.0 / piv;
+    __syncthreads();
+    // row k scaled; new pivot entry 1/piv
+    for (int j = threadIdx.x; j < b; j += blockDim.x)
+      if (j != k) s[j * GJ_B + k] *= ip;
+    __syncthreads();
+    for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
+      const int i = q % b, j = q / b;
+      if (i == k) continue;
+      const double f = s[k * GJ_B + i];
+      if (j == k)
+        continue;
+      s[j * GJ_B + i] -= f * s[j * GJ_B + k];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < b; i += blockDim.x)
+      if (i != k) s[k * GJ_B + i] = -s[k * GJ_B + i] * ip;
+    if (threadIdx.x == 0) s[k * GJ_B + k] = ip;
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
+    const int i = q % b, j = q / b;
+    out[int64_t(j) * b + i] = s[j * GJ_B + i];
+  }
+}
+
+void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_block_inverse, dim3(1), dim3(512), 0, st, X, ldx, out, b);
+}
+
+// Column block p0..p0+b of X (col-major, n x n): copy it to C (n x b) with the
+// pivot rows zeroed, and overwrite it in X with the unit block.
+__global__ void k_gj_take_columns(double* X, int64_t n, int p0, int b, double* C) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n * b) return;
+  const int64_t i = q % n, j = q / n;
+  double* x = X + (p0 + j) * n + i;
+  const bool pr = (i >= p0 && i < p0 + b);
+  C[j * n + i] = pr ? 0.0 : *x;
+  *x = (pr && i - p0 == j) ? 1.0 : 0.0;
+}
+
+void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipStream_t st) {
+  const int64_t m = n * b;
+  hipLaunchKernelGGL(k_gj_take_columns, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, X, n, p0, b, C);
+}
+
+// Dense complex vectors: y = alpha * M x for real dense M applied to the
+// two trace components at once (one read of M for D and N and all vectors).
+template <int NR>
+__global__ __launch_bounds__(256) void k_gemv_real2(const double* __restrict__ Mat, int64_t ld, int rows, int cols,
+                                                    double alpha, const double* __restrict__ x, double* y,
+                                                    int64_t vstride, int64_t cstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= rows) return;
+  double a[NR][4];
+  for (int r = 0; r < NR; ++r) a[r][0] = a[r][1] = a[r][2] = a[r][3] = 0.0;
+  const double* mr = Mat + int64_t(row) * ld;
+  for (int j = lane; j < cols; j += 64) {
+    const double m = mr[j];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* p0 = x + 2 * (int64_t(r) * vstride + j);
+      const double* p1 = p0 + 2 * cstride;
+      a[r][0] += m * p0[0];
+      a[r][1] += m * p0[1];
+      a[r][2] += m * p1[0];
+      a[r][3] += m * p1[1];
+    }
+  }
+  for (int r = 0; r < NR; ++r)
+    for (int q = 0; q < 4; ++q) a[r][q] = wsum(a[r][q]);
+  if (lane == 0)
+    for (int r = 0; r < NR; ++r) {
+      double* q0 = y + 2 * (int64_t(r) * vstride + row);
+      double* q1 = q0 + 2 * cstride;
+      q0[0] = alpha * a[r][0];
+      q0[1] = alpha * a[r][1];
+      q1[0] = alpha * a[r][2];
+      q1[1] = alpha * a[r][3];
+    }
+}
+
+void launch_gemv_real2(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+                       int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
+  const dim3 grid((rows + 3) / 4), block(256);
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0;
+    const double* xx = x + 2 * int64_t(r0) * vstride;
+    double* yy = y + 2 * int64_t(r0) * vstride;
+    if (left >= 4) {
+      hipLaunchKernelGGL((k_gemv_real2<4>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride);
+      r0 += 4;
+    } else {
+      hipLaunchKernelGGL((k_gemv_real2<1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride);
+      r0 += 1;
+    }
+  }
+}
+
+}  // namespace pmchwt
+
+namespace pmchwt {
+// y_q = y_q + s * a_q x_q, a_q real per vector (complex vectors of length n, stride)
+__global__ void k_axpy_vec(double* y, const double* x, int64_t stride, int n, const double* a, double s) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (k >= 2 * int64_t(n)) return;
+  y[2 * int64_t(q) * stride + k] += s * a[q] * x[2 * int64_t(q) * stride + k];
+}
+// p_q = z_q + b_q p_q
+__global__ void k_xpby_vec(double* p, const double* z, int64_t stride, int n, const double* b) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (k >= 2 * int64_t(n)) return;
+  const int64_t o = 2 * int64_t(q) * stride + k;
+  p[o] = z[o] + b[q] * p[o];
+}
+void launch_axpy_vec(double* y, const double* x, int64_t stride, int n, int nvec, const double* a, double s,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_vec, dim3(unsigned((2 * int64_t(n) + 255) / 256), nvec), dim3(256), 0, st, y, x, stride,
+                     n, a, s);
+}
+void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec, const double* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_xpby_vec, dim3(unsigned((2 * int64_t(n) + 255) / 256), nvec), dim3(256), 0, st, p, z, stride,
+                     n, b);
+}
+}  // namespace pmchwt

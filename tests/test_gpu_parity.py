@@ -76,9 +76,11 @@ def test_P_nearfield_cutoff(P, sphere1, chi):
     mask = ops.nearfield_mask(lo, hi, chi)
     ref = ops.assemble_bc(B, 2.0 * np.sqrt(EPS), (1, 1, 1), 1, ("S",))["S"] * mask
     got = ctx.get_block(P.OP_S, P.INT, P.BC, 0, 0)
-    assert np.array_equal(got != 0, mask)
-    note(f"  fro={rel_fro(got, ref):.2e} nnz={mask.sum()}")
-    assert rel_fro(got, ref) < 1e-10
+    # entries beyond the cutoff are exactly zero; kept ones match the oracle
+    # (some kept entries vanish by symmetry, so they are not tested for != 0)
+    assert np.all(got[~mask] == 0)
+    note(f"  fro={rel_fro(got, ref):.2e} max={rel_max(got, ref):.2e} nnz={mask.sum()}")
+    assert rel_fro(got, ref) < 1e-10 and rel_max(got, ref) < 1e-10
 
 
 def test_rhs_apply_solve_cross_sections(P, sphere1, oracle_sphere1):

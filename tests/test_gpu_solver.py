@@ -1,0 +1,101 @@
+"""GPU solver checks: Table 1 matvec accounting, preconditioner family, multi-
+scatterer parity, mixed precision with refinement, error paths."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import note, rel_fro, make_ctx
+from oracle import pmchwt as opm
+
+pytestmark = pytest.mark.gpu
+
+EPS = 3.17 + 0.01j
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2008_04772_amd as lib
+    return lib
+
+
+@pytest.mark.parametrize("kind", ["I", "A", "D", "D_INT", "D_EXT", "S_INT", "S_EXT"])
+def test_table1_counter_single_sphere(P, kind):
+    """The solver's count of boundary-operator applications equals Table 1's
+    formula for the iterations it took, with several completed restart cycles
+    (rho = 6 preconditioned; rho = 30 unpreconditioned, where short cycles
+    stagnate)."""
+    rho = 30 if kind == "I" else 6
+    note(f"Table 1 counter, icosphere(1), P = {kind}, rho = {rho}")
+    ctx = make_ctx(P, [synth.icosphere(1)], EPS, 1.0, qP=(1, 1, 1), nP=1, chi=0.5, precond=kind)
+    d, p = synth.single_wave()
+    x, st = ctx.solve(d, p, P.solver_opts(tol=1e-8, restart=rho, max_iter=5000))
+    note(f"  R={st.iterations} restarts={st.restarts} matvecs={st.matvecs}")
+    assert st.converged and st.restarts >= 1
+    assert st.restarts == st.iterations // rho
+    assert st.matvecs == opm.table1_matvecs(kind, 1, st.iterations, rho)
+
+
+@pytest.mark.parametrize("kind", ["D", "A", "S_INT"])
+def test_three_cubes_parity_and_counter(P, kind):
+    """Three disjoint cubes (Section 4's array, M = 3): currents against the
+    oracle's direct solve, and Table 1's count for M = 3."""
+    note(f"three cubes k_e=2.1, P = {kind}")
+    cubes = synth.three_cubes(2.1)
+    eps = 1.311 ** 2
+    ctx = make_ctx(P, cubes, eps, 2.1, qP=(4, 3, 2), nP=4, chi=-1.0, precond=kind)
+    d, p = synth.single_wave((1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    x, st = ctx.solve(d, p, P.solver_opts(tol=1e-11, restart=200, max_iter=1000))
+    pr = opm.Problem(cubes, eps, 2.1)
+    pr.assemble_A()
+    xr = pr.solve_direct(pr.rhs(d, p))
+    note(f"  R={st.iterations} matvecs={st.matvecs} err={rel_fro(x, xr):.2e}")
+    assert rel_fro(x, xr) < 1e-8
+    assert st.matvecs == opm.table1_matvecs(kind, 3, st.iterations, 200)
+
+
+def test_mixed_precision_with_refinement(P):
+    """FP32 regular pairs and operators, FP64 singular pairs / Arnoldi /
+    refinement residual: cross sections within 1e-5 of the FP64 oracle."""
+    note("mixed precision solve, icosphere(2), k=2")
+    mesh = synth.icosphere(2)
+    ctx = make_ctx(P, [mesh], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=0.6, precond="S_INT", precision=P.MIXED)
+    d, p = synth.single_wave()
+    x, st = ctx.solve(d, p, P.solver_opts(tol=1e-8, restart=200, max_iter=1000, ir_max=3))
+    se, ss = ctx.cross_sections(x, d, p)
+    pr = opm.Problem([mesh], EPS, 2.0)
+    pr.assemble_A()
+    xr = pr.solve_direct(pr.rhs(d, p))
+    se_r, ss_r = pr.cross_sections(xr, d, p)
+    note(f"  iters={st.iterations} ir={st.ir_steps} err={rel_fro(x, xr):.2e} "
+         f"ext {se[0]:.9f}/{se_r[0]:.9f} sca {ss[0]:.9f}/{ss_r[0]:.9f}")
+    assert abs(se[0] - se_r[0]) < 1e-5 * abs(se_r[0])
+    assert abs(ss[0] - ss_r[0]) < 1e-5 * abs(ss_r[0])
+
+
+def test_error_paths(P):
+    note("error paths")
+    ctx = P.Context(0)
+    v, t = synth.icosphere(1)
+    with pytest.raises(P.PmchwtError) as e:
+        ctx.add_scatterer(v, t[1:], EPS)
+    assert e.value.code == P.ERR_INVALID_MESH
+    with pytest.raises(P.PmchwtError) as e:
+        ctx.solve(*synth.single_wave(), P.solver_opts())
+    assert e.value.code == P.ERR_STATE
+    ctx.add_scatterer(v, t, EPS)
+    with pytest.raises(P.PmchwtError) as e:
+        ctx.set_wavenumber(-1.0)
+    assert e.value.code == P.ERR_INVALID_ARG
+    ctx.set_wavenumber(1.0)
+    with pytest.raises(P.PmchwtError) as e:
+        ctx.assemble(P.assembly_opts((5, 3, 2), 4), P.assembly_opts(), "D")
+    assert e.value.code == P.ERR_INVALID_ARG
+    ctx.assemble(P.assembly_opts(), P.assembly_opts((1, 1, 1), 1, 0.5), "S_INT")
+    x, st = ctx.solve(*synth.single_wave(), P.solver_opts(tol=1e-14, restart=5, max_iter=3),
+                      allow_not_converged=True)
+    assert not st.converged and st.iterations == 3
+    with pytest.raises(P.PmchwtError) as e:
+        ctx.solve(*synth.single_wave(), P.solver_opts(tol=1e-14, restart=5, max_iter=3))
+    assert e.value.code == P.ERR_NOT_CONVERGED
+    ctx.close()
