@@ -53,7 +53,7 @@ def run(P, mesh, chi, dirs, pols, precision, steps, warmup):
         ctx.add_scatterer(v, t, EPS)
         ctx.set_wavenumber(K_EXT)
         oA = P.assembly_opts((4, 3, 2), 4, -1.0, P.MIXED if precision == "mixed" else P.FP64)
-        oP = P.assembly_opts((1, 1, 1), 1, chi, P.FP64)
+        oP = P.assembly_opts((1, 1, 1), 1, chi, P.MIXED if precision == "mixed" else P.FP64)
         so = P.solver_opts(tol=1e-5, restart=200, max_iter=2000, ir_max=2 if precision == "mixed" else 0)
         profs = []
         for s in range(warmup + steps):
@@ -66,8 +66,11 @@ def run(P, mesh, chi, dirs, pols, precision, steps, warmup):
                 lat.append(dt)
                 profs.append(ctx.profile())
             stats = st
-            print(f"[bench] {precision} step {s} {dt * 1e3:.1f} ms, GMRES iters {st.iterations}", file=sys.stderr,
-                  flush=True)
+            pf = ctx.profile()
+            print(f"[bench] {precision} step {s} {dt * 1e3:.1f} ms, GMRES iters {st.iterations}; wall setup "
+                  f"{pf['wall_setup']:.1f} A {pf['wall_A']:.1f} P {pf['wall_P']:.1f} mass {pf['wall_mass']:.1f} "
+                  f"solve {st.ms_solve:.1f} xs {(dt * 1e3 - pf['wall_setup'] - pf['wall_A'] - pf['wall_P'] - pf['wall_mass'] - st.ms_solve):.1f}",
+                  file=sys.stderr, flush=True)
     return lat, profs, stats, float(se[0]), float(ss[0])
 
 

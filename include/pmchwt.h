@@ -93,8 +93,11 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *   chi : near-field cutoff, absolute length; an entry (i, j) of P is kept iff
  *       the bounding boxes of the supports of functions i and j are at most
  *       chi apart; chi < 0 means infinity.  Ignored for A (always dense).
- *   precision : PMCHWT_FP64, or PMCHWT_MIXED = disjoint pairs and operator
- *       storage in FP32, singular pairs in FP64.                              */
+ *   precision : PMCHWT_FP64, or PMCHWT_MIXED.  For A: disjoint pairs and
+ *       operator storage in FP32, singular pairs in FP64.  For P: the
+ *       near-field values are always FP64; MIXED stores the inverted mass
+ *       matrices M_A^-1 and M_A^-T (computed in FP64) in FP32, which only
+ *       perturbs the preconditioner, not the system that is solved.          */
 typedef struct {
   int32_t q_near, q_medium, q_far;
   int32_t n_singular;
@@ -129,7 +132,8 @@ typedef struct {
  * algorithmic work of the last assemble / solve, for roofline reporting.     */
 typedef struct {
   double ms_assemble_A;      /* regular + singular + scatter kernels of A               */
-  double ms_assemble_regular;/* regular-pair kernel alone (sum over its launches)       */
+  double ms_assemble_regular;/* regular-pair kernel (pass 1) alone, sum over launches    */
+  double ms_regular_combine; /* slot-row combination (pass 2) of the regular pairs      */
   double ms_assemble_singular;
   double ms_assemble_P;      /* near-field BC kernel                                    */
   double ms_mass;            /* mass and Gram matrices and their inverses               */
@@ -139,8 +143,13 @@ typedef struct {
   int64_t singular_point_pairs;
   int64_t bary_pairs;        /* barycentric triangle pairs integrated for P             */
   int64_t nnz_P;             /* stored entries per BC operator                          */
-  int32_t regular_launches;
+  int32_t regular_launches;  /* launches of the regular-pair kernel                     */
   int32_t n_wavenumbers;     /* wavenumbers per regular pair in the A kernels           */
+  double recompute;          /* trial triangles integrated per test triangle / F        */
+  double wall_setup;         /* host wall time of assemble: topology and uploads        */
+  double wall_A;             /* ... assembly of A (host tables + kernels)               */
+  double wall_P;             /* ... preconditioner (near-field pattern + kernel)        */
+  double wall_mass;          /* ... mass / Gram matrices and the mass inverse           */
   double ms_matvec_total;    /* dense operator application kernels during the solve     */
   int64_t matvec_launches;
   int64_t matvec_bytes;      /* algorithmic operator bytes read by those launches       */

@@ -55,12 +55,15 @@ class pmchwt_solve_stats(ctypes.Structure):
 
 class pmchwt_profile(ctypes.Structure):
     _fields_ = [("ms_assemble_A", ctypes.c_double), ("ms_assemble_regular", ctypes.c_double),
+                ("ms_regular_combine", ctypes.c_double),
                 ("ms_assemble_singular", ctypes.c_double), ("ms_assemble_P", ctypes.c_double),
                 ("ms_mass", ctypes.c_double), ("regular_pairs", ctypes.c_int64),
                 ("regular_point_pairs", ctypes.c_int64), ("singular_pairs", ctypes.c_int64),
                 ("singular_point_pairs", ctypes.c_int64), ("bary_pairs", ctypes.c_int64),
                 ("nnz_P", ctypes.c_int64), ("regular_launches", ctypes.c_int32),
-                ("n_wavenumbers", ctypes.c_int32), ("ms_matvec_total", ctypes.c_double),
+                ("n_wavenumbers", ctypes.c_int32), ("recompute", ctypes.c_double),
+                ("wall_setup", ctypes.c_double), ("wall_A", ctypes.c_double), ("wall_P", ctypes.c_double),
+                ("wall_mass", ctypes.c_double), ("ms_matvec_total", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("matvec_bytes", ctypes.c_int64)]
 
 

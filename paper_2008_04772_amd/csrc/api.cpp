@@ -11,6 +11,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <array>
 #include <cmath>
 #include <complex>
@@ -75,6 +76,27 @@ struct Fail {
   std::string msg;
 };
 
+struct CellDev {
+  DBuf cell_ptr, ring, child_v, child_vid, child_cen, child_diam2, child_area, coef_ptr, coef, cell_scat;
+  DBuf child_cell, child_pos, child_parent, inc_ptr, inc_edges, edge_scat, edge_off;
+  int nchild = 0, ncell = 0;
+  CellParams params() const {
+    CellParams p{};
+    p.cell_ptr = cell_ptr.as<int32_t>();
+    p.ring = ring.as<int32_t>();
+    p.child_v = child_v.as<double>();
+    p.child_vid = child_vid.as<int32_t>();
+    p.child_cen = child_cen.as<double>();
+    p.child_diam2 = child_diam2.as<double>();
+    p.child_area = child_area.as<double>();
+    p.coef_ptr = coef_ptr.as<int64_t>();
+    p.coef = coef.as<double>();
+    p.cell_scat = cell_scat.as<int32_t>();
+    return p;
+  }
+};
+
+
 #define HIPCHK(x)                                                                          \
   do {                                                                                     \
     hipError_t e_ = (x);                                                                   \
@@ -87,11 +109,17 @@ struct pmchwt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t side = nullptr;  // look-ahead work of the mass-matrix inverse
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
   rocblas_handle blas = nullptr;
   std::string err;
   double k_ext = 0.0;
   std::vector<Scat> sc;
   int F_tot = 0, E_tot = 0, nv_tot = 0;
+  // leading dimensions of the dense operators, padded to a multiple of 4
+  // entries so that rows start on 16/32-byte boundaries for vector loads
+  int64_t ldE = 0;
+  std::vector<int64_t> ldI;
   bool geo_uploaded = false;
   // union geometry (SoA)
   DBuf tv, tcen, tdiam2, tarea, tvid, t2e, tsgn, tscat, edge_off, k_int;
@@ -111,20 +139,55 @@ struct pmchwt_ctx {
   std::vector<int32_t> h_col;
   // mass / Gram
   std::vector<DBuf> MA, Minv, MinvT, Glu, Gpiv;
+  bool mass_f32 = false;  // Minv / MinvT stored in FP32 (preconditioner assembled with MIXED precision)
   // work vectors
   DBuf work;
   size_t work_bytes = 0;
   pmchwt_profile prof{};
   int64_t count_key = -1, count_pairs = 0, count_pts = 0;
   int64_t calls_A = 0, calls_P = 0;  // operator applications (batched calls) since the last reset
+  // index tables that depend only on the meshes (and chi): built once, reused
+  // by every assembly of the same geometry (all integrals are recomputed)
+  struct {
+    bool valid = false;
+    double chi = 0;
+    bool cross = false;
+    DBuf cpairs, slot_off, slot_pos;
+    int64_t npairs = 0, bary_pairs = 0;
+  } nf;
+  struct {
+    int n = -1;
+    DBuf pairs, tab[4];
+    int npts[4] = {0, 0, 0, 0};
+    int64_t npairs = 0, point_pairs = 0;
+  } sing;
+  bool cells_valid = false;
+  CellDev cells;
+  std::vector<std::pair<int, int>> slabs;
+  size_t slab_elem = 0;
+  std::vector<DBuf> slab_rows, slab_rows_l, slab_sp, slab_sm;
+  std::vector<int> slab_nrows;
+  // trial-edge chunk tables of the atomic-free regular assembly (geometry only)
+  int chunk_size = 0, nchunks = 0, max_list = 0;
+  DBuf chunk_ptr, chunk_tri, edge_map, edge_scat_d;
+  double recompute = 0.0;
 
   ~pmchwt_ctx() {
     if (blas) rocblas_destroy_handle(blas);
+    if (ev_main) (void)hipEventDestroy(ev_main);
+    if (ev_side) (void)hipEventDestroy(ev_side);
+    if (side) (void)hipStreamDestroy(side);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
 
 namespace {
+
+int64_t padld(int64_t n) { return (n + 3) & ~int64_t(3); }
+
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 template <typename T>
 DBuf dalloc(size_t n) {
@@ -368,7 +431,7 @@ AsmParams<M> asm_params(pmchwt_ctx* c) {
   p.k_ext = c->k_ext;
   p.Se = c->Se.as<M>();
   p.Ce = c->Ce.as<M>();
-  p.ld_ext = c->E_tot;
+  p.ld_ext = c->ldE;
   p.Si = c->Si_ptr.as<M*>();
   p.Ci = c->Ci_ptr.as<M*>();
   p.ld_int = c->ld_int.as<int64_t>();
@@ -402,19 +465,22 @@ struct EvTimer {
 template <typename M>
 void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   const int64_t E = c->E_tot;
-  c->Se = dalloc<M>(size_t(2 * E * E));
-  c->Ce = dalloc<M>(size_t(2 * E * E));
+  c->ldE = padld(E);
+  c->Se = dalloc<M>(size_t(2 * E * c->ldE));
+  c->Ce = dalloc<M>(size_t(2 * E * c->ldE));
   std::vector<M*> sp, cp;
   std::vector<int64_t> lds;
   c->Si.clear();
   c->Ci.clear();
+  c->ldI.clear();
   for (auto& s : c->sc) {
-    const int64_t Em = s.topo.E;
-    c->Si.push_back(dalloc<M>(size_t(2 * Em * Em)));
-    c->Ci.push_back(dalloc<M>(size_t(2 * Em * Em)));
+    const int64_t Em = s.topo.E, ld = padld(Em);
+    c->Si.push_back(dalloc<M>(size_t(2 * Em * ld)));
+    c->Ci.push_back(dalloc<M>(size_t(2 * Em * ld)));
     sp.push_back(c->Si.back().as<M>());
     cp.push_back(c->Ci.back().as<M>());
-    lds.push_back(Em);
+    lds.push_back(ld);
+    c->ldI.push_back(ld);
   }
   c->Si_ptr = upload(c, sp);
   c->Ci_ptr = upload(c, cp);
@@ -435,51 +501,212 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   p.q_medium = o.q_medium;
   p.q_far = o.q_far;
 
-  // singular pair list: ordered pairs sharing at least one vertex
-  std::vector<std::vector<int32_t>> v2t(c->nv_tot);
+  // singular pair list (ordered pairs sharing at least one vertex) and the
+  // Sauter-Schwab tables of order n: index tables, built once per geometry
+  if (c->sing.n != o.n_singular) {
+    std::vector<std::vector<int32_t>> v2t(c->nv_tot);
+    for (auto& s : c->sc)
+      for (int f = 0; f < s.topo.F; ++f)
+        for (int a = 0; a < 3; ++a) v2t[s.vert_off + s.topo.t[3 * f + a]].push_back(s.tri_off + f);
+    std::vector<int32_t> pairs;
+    int64_t npts_sing = 0;
+    SSTables ss;
+    build_ss(c, o.n_singular, ss);
+    for (auto& s : c->sc)
+      for (int f = 0; f < s.topo.F; ++f) {
+        const int g = s.tri_off + f;
+        std::vector<int32_t> nb;
+        for (int a = 0; a < 3; ++a)
+          for (int t : v2t[s.vert_off + s.topo.t[3 * f + a]]) nb.push_back(t);
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        for (int t : nb) {
+          pairs.push_back(g);
+          pairs.push_back(t);
+          int shared = 0;
+          const int t_loc = t - s.tri_off;
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) shared += (s.topo.t[3 * f + a] == s.topo.t[3 * t_loc + b]);
+          npts_sing += ss.npts[shared];
+        }
+      }
+    c->sing.pairs = upload(c, pairs);
+    c->sing.npairs = int64_t(pairs.size() / 2);
+    c->sing.point_pairs = npts_sing;
+    for (int k = 1; k <= 3; ++k) {
+      c->sing.tab[k] = std::move(ss.tab[k]);
+      c->sing.npts[k] = ss.npts[k];
+    }
+    c->sing.n = o.n_singular;
+  }
+  SingParams sp_{};
+  sp_.npairs = c->sing.npairs;
+  sp_.pairs = c->sing.pairs.as<int32_t>();
+  for (int k = 1; k <= 3; ++k) {
+    sp_.tab[k] = c->sing.tab[k].as<double>();
+    sp_.npts[k] = c->sing.npts[k];
+  }
+  const int64_t npts_sing = c->sing.point_pairs;
+  // trial-edge chunks: distinct T+/T- triangles of each chunk of consecutive edges
+  // (FP64 moments are twice as large: halve the chunk to bound the LDS footprint)
+  const int CH = sizeof(M) == 8 ? 64 : 128;
+  if (c->chunk_size != CH) {
+    std::vector<int32_t> tp(c->E_tot), tm(c->E_tot), escat(c->E_tot);
+    std::vector<int8_t> bp(c->E_tot), bm(c->E_tot);
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      for (int f = 0; f < s.topo.F; ++f)
+        for (int a = 0; a < 3; ++a) {
+          const int e = s.edge_off + s.topo.t2e[3 * f + a];
+          if (s.topo.sgn[3 * f + a] > 0) {
+            tp[e] = s.tri_off + f;
+            bp[e] = int8_t(a);
+          } else {
+            tm[e] = s.tri_off + f;
+            bm[e] = int8_t(a);
+          }
+        }
+      for (int e = 0; e < s.topo.E; ++e) escat[s.edge_off + e] = int32_t(m);
+    }
+    const int nch = (c->E_tot + CH - 1) / CH;
+    std::vector<int32_t> cptr{0}, ctri;
+    std::vector<int16_t> emap(4 * size_t(c->E_tot));
+    std::unordered_map<int32_t, int16_t> pos;
+    int maxl = 0;
+    for (int ch = 0; ch < nch; ++ch) {
+      pos.clear();
+      const int j0 = ch * CH, j1 = std::min(c->E_tot, j0 + CH);
+      auto slot = [&](int32_t t) -> int16_t {
+        auto it = pos.find(t);
+        if (it != pos.end()) return it->second;
+        const int16_t q = int16_t(pos.size());
+        pos.emplace(t, q);
+        ctri.push_back(t);
+        return q;
+      };
+      for (int j = j0; j < j1; ++j) {
+        emap[4 * size_t(j) + 0] = slot(tp[j]);
+        emap[4 * size_t(j) + 1] = bp[j];
+        emap[4 * size_t(j) + 2] = slot(tm[j]);
+        emap[4 * size_t(j) + 3] = bm[j];
+      }
+      maxl = std::max(maxl, int(pos.size()));
+      cptr.push_back(int32_t(ctri.size()));
+    }
+    c->chunk_ptr = upload(c, cptr);
+    c->chunk_tri = upload(c, ctri);
+    c->edge_map = upload(c, emap);
+    c->edge_scat_d = upload(c, escat);
+    c->nchunks = nch;
+    c->max_list = maxl;
+    c->recompute = double(ctri.size()) / double(c->F_tot);
+    c->chunk_size = CH;
+  }
+  // slabs of test triangles inside one scatterer, sized for a bounded buffer
+  const double budget = 6.0e9;
+  const double row_bytes = 3.0 * 2 * sizeof(M) * 2;  // per test triangle per union column, S and C
+  std::vector<std::pair<int, int>> slabs;  // (t0, t1)
+  for (auto& s : c->sc) {
+    int per = int(std::max(1.0, budget / (row_bytes * (c->E_tot + s.topo.E))));
+    per = std::min(per, s.topo.F);
+    for (int t0 = 0; t0 < s.topo.F; t0 += per) slabs.push_back({s.tri_off + t0, s.tri_off + std::min(s.topo.F, t0 + per)});
+  }
+  const bool slabs_cached = (c->slabs == slabs && c->slab_elem == sizeof(M));
+  if (!slabs_cached) {
+    c->slabs = slabs;
+    c->slab_elem = sizeof(M);
+    c->slab_rows.clear();
+    c->slab_rows_l.clear();
+    c->slab_sp.clear();
+    c->slab_sm.clear();
+    c->slab_nrows.clear();
+  }
+  int max_slab = 0, max_Em = 0;
+  for (auto& sl : slabs) max_slab = std::max(max_slab, sl.second - sl.first);
+  for (auto& s : c->sc) max_Em = std::max(max_Em, s.topo.E);
+  DBuf HeS = dalloc<M>(size_t(2) * 3 * max_slab * c->E_tot), HeC = dalloc<M>(size_t(2) * 3 * max_slab * c->E_tot);
+  DBuf HiS = dalloc<M>(size_t(2) * 3 * max_slab * max_Em), HiC = dalloc<M>(size_t(2) * 3 * max_slab * max_Em);
+  HalfJob<M> hj{};
+  hj.chunk = CH;
+  hj.chunk_ptr = c->chunk_ptr.as<int32_t>();
+  hj.chunk_tri = c->chunk_tri.as<int32_t>();
+  hj.edge_map = c->edge_map.as<int16_t>();
+  hj.edge_scat = c->edge_scat_d.as<int32_t>();
+  hj.E_tot = c->E_tot;
+  hj.He_S = HeS.as<M>();
+  hj.He_C = HeC.as<M>();
+  hj.Hi_S = HiS.as<M>();
+  hj.Hi_C = HiC.as<M>();
+  // per union edge: T+ / T- (for the slot rows of pass 2)
+  std::vector<int32_t> etp(c->E_tot), etm(c->E_tot), eap(c->E_tot), eam(c->E_tot);
   for (auto& s : c->sc)
     for (int f = 0; f < s.topo.F; ++f)
-      for (int a = 0; a < 3; ++a) v2t[s.vert_off + s.topo.t[3 * f + a]].push_back(s.tri_off + f);
-  std::vector<int32_t> pairs;
-  int64_t npts_sing = 0;
-  SSTables ss;
-  build_ss(c, o.n_singular, ss);
-  for (auto& s : c->sc)
-    for (int f = 0; f < s.topo.F; ++f) {
-      const int g = s.tri_off + f;
-      std::vector<int32_t> nb;
-      for (int a = 0; a < 3; ++a)
-        for (int t : v2t[s.vert_off + s.topo.t[3 * f + a]]) nb.push_back(t);
-      std::sort(nb.begin(), nb.end());
-      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-      for (int t : nb) {
-        pairs.push_back(g);
-        pairs.push_back(t);
-        int shared = 0;
-        const int t_loc = t - s.tri_off;
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) shared += (s.topo.t[3 * f + a] == s.topo.t[3 * t_loc + b]);
-        npts_sing += ss.npts[shared];
+      for (int a = 0; a < 3; ++a) {
+        const int e = s.edge_off + s.topo.t2e[3 * f + a];
+        if (s.topo.sgn[3 * f + a] > 0) {
+          etp[e] = s.tri_off + f;
+          eap[e] = a;
+        } else {
+          etm[e] = s.tri_off + f;
+          eam[e] = a;
+        }
       }
-    }
-  DBuf dpairs = upload(c, pairs);
-  SingParams sp_{};
-  sp_.npairs = int64_t(pairs.size() / 2);
-  sp_.pairs = dpairs.as<int32_t>();
-  for (int k = 1; k <= 3; ++k) {
-    sp_.tab[k] = ss.tab[k].as<double>();
-    sp_.npts[k] = ss.npts[k];
-  }
+  double ms_pass1 = 0.0, ms_pass2 = 0.0;
   EvTimer all(c->stream);
-  {
-    EvTimer t(c->stream);
-    if (sizeof(M) == 8)
-      launch_regular<double, M>(p, 0, c->F_tot, c->stream);
-    else
-      launch_regular<float, M>(p, 0, c->F_tot, c->stream);
-    HIPCHK(hipGetLastError());
-    c->prof.ms_assemble_regular = t.stop();
+  for (auto& sl : slabs) {
+    const int t0 = sl.first, t1 = sl.second;
+    int m = 0;
+    while (m + 1 < int(c->sc.size()) && c->sc[m + 1].tri_off <= t0) ++m;
+    const Scat& s = c->sc[m];
+    hj.slab_t0 = t0;
+    hj.ld_i = s.topo.E;
+    hj.edge_off_i = s.edge_off;
+    {
+      EvTimer t(c->stream);
+      if (sizeof(M) == 8)
+        launch_regular_rows<double, M>(p, hj, t0, t1, c->nchunks, c->max_list, c->stream);
+      else
+        launch_regular_rows<float, M>(p, hj, t0, t1, c->nchunks, c->max_list, c->stream);
+      HIPCHK(hipGetLastError());
+      ms_pass1 += t.stop();
+    }
+    // rows touched by this slab: edges of scatterer m with T+ or T- inside
+    const size_t si = size_t(&sl - &slabs[0]);
+    if (!slabs_cached) {
+      std::vector<int32_t> rows, sp, smn, rows_l;
+      for (int e = s.edge_off; e < s.edge_off + s.topo.E; ++e) {
+        const bool ip = etp[e] >= t0 && etp[e] < t1, im = etm[e] >= t0 && etm[e] < t1;
+        if (!ip && !im) continue;
+        rows.push_back(e);
+        rows_l.push_back(e - s.edge_off);
+        sp.push_back(ip ? 3 * (etp[e] - t0) + eap[e] : -1);
+        smn.push_back(im ? 3 * (etm[e] - t0) + eam[e] : -1);
+      }
+      c->slab_rows.push_back(upload(c, rows));
+      c->slab_rows_l.push_back(upload(c, rows_l));
+      c->slab_sp.push_back(upload(c, sp));
+      c->slab_sm.push_back(upload(c, smn));
+      c->slab_nrows.push_back(int(rows.size()));
+    }
+    DBuf &drows = c->slab_rows[si], &drl = c->slab_rows_l[si], &dsp = c->slab_sp[si], &dsm = c->slab_sm[si];
+    const int nr = c->slab_nrows[si];
+    {
+      EvTimer t(c->stream);
+      launch_rows_combine<M>(c->Se.as<M>(), c->ldE, HeS.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream);
+      launch_rows_combine<M>(c->Ce.as<M>(), c->ldE, HeC.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream);
+      launch_rows_combine<M>(c->Si[m].as<M>(), c->ldI[m], HiS.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream);
+      launch_rows_combine<M>(c->Ci[m].as<M>(), c->ldI[m], HiC.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream);
+      HIPCHK(hipGetLastError());
+      ms_pass2 += t.stop();
+    }
   }
+  c->prof.ms_assemble_regular = ms_pass1;
+  c->prof.ms_regular_combine = ms_pass2;
+  c->prof.regular_launches = int(slabs.size());
   {
     EvTimer t(c->stream);
     launch_singular<M>(p, sp_, c->stream);
@@ -487,7 +714,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     c->prof.ms_assemble_singular = t.stop();
   }
   c->prof.ms_assemble_A = all.stop();
-  c->prof.regular_launches = (c->F_tot + 65534) / 65535;
+  c->prof.recompute = c->recompute;
   // work counters: disjoint ordered pairs by class (host count, same rule as
   // the kernel); pure metadata of the mesh and the rule orders, kept across
   // assemblies of the same geometry
@@ -548,25 +775,6 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
 // ---------------------------------------------------------------------------
 // Dual cells and near-field BC operators of P
 // ---------------------------------------------------------------------------
-struct CellDev {
-  DBuf cell_ptr, ring, child_v, child_vid, child_cen, child_diam2, child_area, coef_ptr, coef, cell_scat;
-  DBuf child_cell, child_pos, child_parent, inc_ptr, inc_edges, edge_scat, edge_off;
-  int nchild = 0, ncell = 0;
-  CellParams params() const {
-    CellParams p{};
-    p.cell_ptr = cell_ptr.as<int32_t>();
-    p.ring = ring.as<int32_t>();
-    p.child_v = child_v.as<double>();
-    p.child_vid = child_vid.as<int32_t>();
-    p.child_cen = child_cen.as<double>();
-    p.child_diam2 = child_diam2.as<double>();
-    p.child_area = child_area.as<double>();
-    p.coef_ptr = coef_ptr.as<int64_t>();
-    p.coef = coef.as<double>();
-    p.cell_scat = cell_scat.as<int32_t>();
-    return p;
-  }
-};
 
 void build_duals(pmchwt_ctx* c) {
   int cell_off = 0, child_off = 0, bvert_off = 0;
@@ -744,6 +952,9 @@ void build_pattern(pmchwt_ctx* c, double chi, bool cross, std::vector<int64_t>& 
   }
 }
 
+void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross);
+void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev& cells);
+
 void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, CellDev& cells) {
   c->PSi.release();
   c->PCi.release();
@@ -758,8 +969,33 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   c->prof.ms_assemble_P = 0;
   c->prof.bary_pairs = 0;
   if (kind == PMCHWT_P_I) return;
-  build_pattern(c, o.chi, c->P_cross, c->h_rowptr, c->h_col);
+  const double chi = o.chi < 0 ? -1.0 : o.chi;
+  if (!(c->nf.valid && c->nf.chi == chi && c->nf.cross == c->P_cross)) {
+    build_nearfield_tables(c, chi, c->P_cross);
+    c->nf.valid = true;
+    c->nf.chi = chi;
+    c->nf.cross = c->P_cross;
+  }
   c->nnzP = int64_t(c->h_col.size());
+  c->prof.bary_pairs = c->nf.bary_pairs;
+  auto vals = [&](DBuf& b) {
+    b = dalloc<double>(2 * size_t(c->nnzP));
+    launch_zero(b.as<double>(), 2 * c->nnzP, c->stream);
+  };
+  if (c->P_int) {
+    vals(c->PSi);
+    if (c->P_C) vals(c->PCi);
+  }
+  if (c->P_ext) {
+    vals(c->PSe);
+    if (c->P_C) vals(c->PCe);
+  }
+  run_nearfield_kernel(c, o, cells);
+}
+
+// Near-field pattern of P and the dual-cell pair tables of its kernel.
+void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross) {
+  build_pattern(c, chi, cross, c->h_rowptr, c->h_col);
   c->p_rowptr = upload(c, c->h_rowptr);
   c->p_col = upload(c, c->h_col);
   // per union edge: its two end cells and its slot in each
@@ -832,27 +1068,21 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   (void)eslot;
   int64_t bary_pairs = 0;
   for (size_t q = 0; q < cpairs.size(); q += 2) bary_pairs += int64_t(4) * cell_n[cpairs[q]] * cell_n[cpairs[q + 1]];
-  c->prof.bary_pairs = bary_pairs;
-  DBuf d_cp = upload(c, cpairs), d_so = upload(c, slot_off), d_sp = upload(c, slot_pos);
-  auto vals = [&](DBuf& b) {
-    b = dalloc<double>(2 * size_t(c->nnzP));
-    launch_zero(b.as<double>(), 2 * c->nnzP, c->stream);
-  };
-  if (c->P_int) {
-    vals(c->PSi);
-    if (c->P_C) vals(c->PCi);
-  }
-  if (c->P_ext) {
-    vals(c->PSe);
-    if (c->P_C) vals(c->PCe);
-  }
+  c->nf.bary_pairs = bary_pairs;
+  c->nf.npairs = int64_t(cpairs.size() / 2);
+  c->nf.cpairs = upload(c, cpairs);
+  c->nf.slot_off = upload(c, slot_off);
+  c->nf.slot_pos = upload(c, slot_pos);
+}
+
+void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev& cells) {
   SSTables ss;
   build_ss(c, o.n_singular, ss);
   BCJob j{};
-  j.npairs = int64_t(cpairs.size() / 2);
-  j.cpairs = d_cp.as<int32_t>();
-  j.slot_off = d_so.as<int64_t>();
-  j.slot_pos = d_sp.as<int64_t>();
+  j.npairs = c->nf.npairs;
+  j.cpairs = c->nf.cpairs.as<int32_t>();
+  j.slot_off = c->nf.slot_off.as<int64_t>();
+  j.slot_pos = c->nf.slot_pos.as<int64_t>();
   j.want_int = c->P_int;
   j.want_ext = c->P_ext;
   j.want_C = c->P_C;
@@ -886,22 +1116,57 @@ void rocsolver_check(rocblas_status s, const char* what) {
 // (one-workgroup kernel) and two rocBLAS GEMMs (row-block scaling and the
 // rank-128 update of the whole matrix).  Stable here because the symmetric
 // part of the mixed mass matrix is positive definite.
+// In-place blocked Gauss-Jordan inverse of the column-major n x n matrix X
+// (no pivoting: the mixed mass matrix has a positive definite symmetric
+// part).  With look-ahead: as soon as the next pivot column block has been
+// updated, its small block inverse runs on the side stream while the main
+// stream performs the rank update of the other columns.
 void gj_inverse(pmchwt_ctx* c, double* X, int n) {
   const int B = 128;
-  DBuf Pinv = dalloc<double>(size_t(B) * B), Cc = dalloc<double>(size_t(n) * B), R = dalloc<double>(size_t(B) * n);
+  DBuf Pinv[2] = {dalloc<double>(size_t(B) * B), dalloc<double>(size_t(B) * B)};
+  DBuf Cc[2] = {dalloc<double>(size_t(n) * B), dalloc<double>(size_t(n) * B)};
+  DBuf R = dalloc<double>(size_t(B) * n);
   const double one = 1.0, zero = 0.0, mone = -1.0;
+  auto prepare = [&](int p0, int slot, hipStream_t st) {
+    const int b = std::min(B, n - p0);
+    launch_gj_block_inverse(X + int64_t(p0) * n + p0, n, Pinv[slot].as<double>(), b, st);
+    launch_gj_take_columns(X, n, p0, b, Cc[slot].as<double>(), st);
+  };
+  auto update = [&](int slot, int b, int j0, int nj) {  // X[:, j0:j0+nj] -= C R[:, j0:j0+nj]
+    if (nj <= 0) return;
+    rocsolver_check(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, nj, b, &mone,
+                                  Cc[slot].as<double>(), n, R.as<double>() + int64_t(j0) * b, b, &one,
+                                  X + int64_t(j0) * n, n),
+                    "rocblas_dgemm(rank update)");
+  };
+  auto put_rows = [&](int p0, int b, int j0, int nj) {  // X[p0:p0+b, j0:j0+nj] = R[:, j0:j0+nj]
+    if (nj <= 0) return;
+    HIPCHK(hipMemcpy2DAsync(X + int64_t(j0) * n + p0, size_t(n) * 8, R.as<double>() + int64_t(j0) * b,
+                            size_t(b) * 8, size_t(b) * 8, size_t(nj), hipMemcpyDeviceToDevice, c->stream));
+  };
+  prepare(0, 0, c->stream);
+  int slot = 0;
   for (int p0 = 0; p0 < n; p0 += B) {
     const int b = std::min(B, n - p0);
-    launch_gj_block_inverse(X + int64_t(p0) * n + p0, n, Pinv.as<double>(), b, c->stream);
-    launch_gj_take_columns(X, n, p0, b, Cc.as<double>(), c->stream);
+    const int q0 = p0 + b, bq = std::min(B, n - q0);
     rocsolver_check(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, b, n, b, &one,
-                                  Pinv.as<double>(), b, X + p0, n, &zero, R.as<double>(), b),
+                                  Pinv[slot].as<double>(), b, X + p0, n, &zero, R.as<double>(), b),
                     "rocblas_dgemm(row block)");
-    rocsolver_check(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, n, b, &mone,
-                                  Cc.as<double>(), n, R.as<double>(), b, &one, X, n),
-                    "rocblas_dgemm(rank update)");
-    HIPCHK(hipMemcpy2DAsync(X + p0, size_t(n) * 8, R.p, size_t(b) * 8, size_t(b) * 8, size_t(n),
-                            hipMemcpyDeviceToDevice, c->stream));
+    if (bq > 0) {
+      update(slot, b, q0, bq);
+      put_rows(p0, b, q0, bq);
+      HIPCHK(hipEventRecord(c->ev_main, c->stream));
+      HIPCHK(hipStreamWaitEvent(c->side, c->ev_main, 0));
+      prepare(q0, slot ^ 1, c->side);
+      HIPCHK(hipEventRecord(c->ev_side, c->side));
+    }
+    const int nl = bq > 0 ? q0 : n;
+    update(slot, b, 0, nl);
+    update(slot, b, q0 + bq, n - q0 - bq);
+    put_rows(p0, b, 0, nl);
+    put_rows(p0, b, q0 + bq, n - q0 - bq);
+    if (bq > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
+    slot ^= 1;
   }
   HIPCHK(hipStreamSynchronize(c->stream));
 }
@@ -953,8 +1218,17 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
     c->MA.push_back(std::move(MA));
-    c->Minv.push_back(std::move(Mi));
-    c->MinvT.push_back(std::move(MiT));
+    if (c->mass_f32) {
+      DBuf Mf = dalloc<float>(nn), MfT = dalloc<float>(nn);
+      launch_to_f32(Mi.as<double>(), Mf.as<float>(), int64_t(nn), c->stream);
+      launch_to_f32(MiT.as<double>(), MfT.as<float>(), int64_t(nn), c->stream);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->Minv.push_back(std::move(Mf));
+      c->MinvT.push_back(std::move(MfT));
+    } else {
+      c->Minv.push_back(std::move(Mi));
+      c->MinvT.push_back(std::move(MiT));
+    }
     c->Glu.push_back(std::move(G));
   }
   HIPCHK(hipGetLastError());
@@ -999,22 +1273,22 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   launch_zero(y, 2 * vs * nrhs, c->stream);
   EvTimer t(c->stream);
   if (c->precA == PMCHWT_FP64) {
-    launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), E, int(E), int(E), c->k_ext, 0.0, x,
+    launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
     for (size_t m = 0; m < c->sc.size(); ++m) {
       const Scat& s = c->sc[m];
       const int64_t o = s.edge_off;
-      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), s.topo.E, s.topo.E, s.topo.E,
+      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), c->ldI[m], s.topo.E, s.topo.E,
                                  s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
                                  vs, c->stream);
     }
   } else {
-    launch_gemv_pmchwt<float>(c->Se.as<float>(), c->Ce.as<float>(), E, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
+    launch_gemv_pmchwt<float>(c->Se.as<float>(), c->Ce.as<float>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
                               y, y + 2 * E, nrhs, vs, c->stream);
     for (size_t m = 0; m < c->sc.size(); ++m) {
       const Scat& s = c->sc[m];
       const int64_t o = s.edge_off;
-      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), s.topo.E, s.topo.E, s.topo.E,
+      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), c->ldI[m], s.topo.E, s.topo.E,
                                 s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
                                 vs, c->stream);
     }
@@ -1038,8 +1312,12 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    launch_gemv_real2(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E,
-                      c->stream);
+    if (c->mass_f32)
+      launch_gemv_real2(c->Minv[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs,
+                        E, c->stream);
+    else
+      launch_gemv_real2(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs,
+                        E, c->stream);
   }
   launch_zero(t2, 2 * vs * nrhs, c->stream);
   const int64_t* rp = c->p_rowptr.as<int64_t>();
@@ -1059,8 +1337,12 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    launch_gemv_real2(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
-                      c->stream);
+    if (c->mass_f32)
+      launch_gemv_real2(c->MinvT[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs,
+                        E, c->stream);
+    else
+      launch_gemv_real2(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs,
+                        E, c->stream);
   }
   HIPCHK(hipGetLastError());
 }
@@ -1188,11 +1470,11 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
     const double* x = cinc.as<double>();
     double* y = t.as<double>();
     if (c->precA == PMCHWT_FP64)
-      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), s.topo.E, s.topo.E, s.topo.E,
+      launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), c->ldI[m], s.topo.E, s.topo.E,
                                  s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
                                  vs, c->stream);
     else
-      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, s.k.real(),
+      launch_gemv_pmchwt<float>(c->Si[m].as<float>(), c->Ci[m].as<float>(), c->ldI[m], s.topo.E, s.topo.E, s.k.real(),
                                 s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs,
                                 c->stream);
   }
@@ -1421,6 +1703,12 @@ int pmchwt_create(pmchwt_ctx** out, int device, void* hip_stream) {
     }
     c->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return PMCHWT_ERR_DEVICE;
+  }
   if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
     delete c;
     return PMCHWT_ERR_DEVICE;
@@ -1454,6 +1742,11 @@ int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const i
     c->geo_uploaded = false;
     c->have_A = false;
     c->count_key = -1;
+    c->chunk_size = 0;
+    c->nf.valid = false;
+    c->sing.n = -1;
+    c->cells_valid = false;
+    c->slabs.clear();
     if (id) *id = int32_t(c->sc.size() - 1);
     return PMCHWT_OK;
   });
@@ -1491,21 +1784,36 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
     if (int(kind) < 0 || int(kind) > 6) return fail(c, PMCHWT_ERR_INVALID_ARG, "unknown preconditioner");
     c->have_A = false;
     c->prof = pmchwt_profile{};
+    const double w0 = wall_ms();
     build_duals(c);
     upload_geometry(c);
     upload_k(c);
     c->optA = *A;
     c->optP = *P;
     c->precA = A->precision;
+    const double w1 = wall_ms();
     if (A->precision == PMCHWT_FP64)
       assemble_A_impl<double>(c, *A);
     else
       assemble_A_impl<float>(c, *A);
-    CellDev cells;
-    upload_cells(c, cells);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double w2 = wall_ms();
+    if (!c->cells_valid) {
+      upload_cells(c, c->cells);
+      c->cells_valid = true;
+    }
+    CellDev& cells = c->cells;
+    c->mass_f32 = P->precision == PMCHWT_MIXED;
     assemble_P_impl(c, *P, int(kind), cells);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double w3 = wall_ms();
     assemble_mass_impl(c, cells);
     HIPCHK(hipStreamSynchronize(c->stream));
+    const double w4 = wall_ms();
+    c->prof.wall_setup = w1 - w0;
+    c->prof.wall_A = w2 - w1;
+    c->prof.wall_P = w3 - w2;
+    c->prof.wall_mass = w4 - w3;
     c->have_A = true;
     return PMCHWT_OK;
   });
@@ -1527,12 +1835,12 @@ int pmchwt_get_block(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchwt_
       int64_t sld, r0, c0;
       if (med == PMCHWT_EXT) {
         src = op == PMCHWT_OP_S ? &c->Se : &c->Ce;
-        sld = c->E_tot;
+        sld = c->ldE;
         r0 = sm.edge_off;
         c0 = sl.edge_off;
       } else {
         src = op == PMCHWT_OP_S ? &c->Si[m] : &c->Ci[m];
-        sld = Em;
+        sld = c->ldI[m];
         r0 = 0;
         c0 = 0;
       }
@@ -1588,7 +1896,7 @@ int pmchwt_get_entries(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchw
     if (sp == PMCHWT_RWG) {
       const size_t es = c->precA == PMCHWT_FP64 ? 16 : 8;
       const DBuf* src = med == PMCHWT_EXT ? (op == PMCHWT_OP_S ? &c->Se : &c->Ce) : (op == PMCHWT_OP_S ? &c->Si[m] : &c->Ci[m]);
-      const int64_t sld = med == PMCHWT_EXT ? c->E_tot : sm.topo.E;
+      const int64_t sld = med == PMCHWT_EXT ? c->ldE : c->ldI[m];
       const int64_t r0 = med == PMCHWT_EXT ? sm.edge_off : 0, c0 = med == PMCHWT_EXT ? sl.edge_off : 0;
       for (int64_t q = 0; q < n; ++q) {
         char buf[16];
@@ -1768,8 +2076,10 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     DBuf dx = upload(c, h);
     std::vector<double> ho(obs, obs + 3 * size_t(nobs));
     DBuf dobs = upload(c, ho), dF = dalloc<double>(6 * size_t(nobs) * nrhs);
+    const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs);
+    DBuf wy = dalloc<double>(fp.n_ypts), wj = dalloc<double>(fp.n_J), wp = dalloc<double>(fp.n_part);
     launch_far_field(asm_params<double>(c), dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs,
-                     dF.as<double>(), c->stream);
+                     dF.as<double>(), fp, wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     HIPCHK(hipGetLastError());
     std::vector<double> hf(6 * size_t(nobs) * nrhs);
     HIPCHK(hipMemcpyAsync(hf.data(), dF.p, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1804,11 +2114,16 @@ int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs
     DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc<double>(6 * size_t(nobs) * nrhs),
          dsig = dalloc<double>(nrhs);
     AsmParams<double> g = asm_params<double>(c);
-    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs, dF.as<double>(), c->stream);
+    const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs), fpd = far_field_plan(c->F_tot, nrhs, nrhs);
+    DBuf wy = dalloc<double>(fp.n_ypts), wj = dalloc<double>(fp.n_J),
+         wp = dalloc<double>(std::max(fp.n_part, fpd.n_part));
+    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs, dF.as<double>(), fp,
+                     wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     launch_sigma_sca(dF.as<double>(), nobs, nrhs, dw.as<double>(), dsig.as<double>(), c->stream);
     std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
     DBuf dd = upload(c, hd), dFd = dalloc<double>(6 * size_t(nrhs) * nrhs);
-    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dd.as<double>(), nrhs, dFd.as<double>(), c->stream);
+    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dd.as<double>(), nrhs, dFd.as<double>(), fpd,
+                     wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     HIPCHK(hipGetLastError());
     std::vector<double> fd(6 * size_t(nrhs) * nrhs);
     HIPCHK(hipMemcpyAsync(ssca, dsig.p, 8 * size_t(nrhs), hipMemcpyDeviceToHost, c->stream));

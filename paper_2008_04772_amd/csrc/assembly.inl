@@ -52,108 +52,157 @@ __device__ __forceinline__ void add_entry(M* mat, int64_t ld, int i, int j, cons
 }
 
 // ---------------------------------------------------------------------------
-// Regular (disjoint) pairs: one thread per unordered pair t1 < t2.  The
-// tensor rule is symmetric in the two triangles, so the (t2, t1) block is the
-// transpose of the (t1, t2) block and is written from the same moments.
+// Regular (disjoint) pairs, pass 1: workgroup = (test triangle t1, chunk of
+// trial edges).  Phase A integrates the chunk's distinct trial triangles
+// against t1 (moments in LDS, zero for pairs sharing a vertex: those are the
+// singular kernel's); phase B contracts them for every trial edge of the
+// chunk and every RWG function of t1, summing the T+ and T- contributions,
+// and stores one complex value per (slot, edge, operator) - coalesced along
+// the edges, no atomics.
 // ---------------------------------------------------------------------------
+template <typename R>
+struct MomPair {
+  Moments<R> e, i;
+};
+
 template <typename R, typename M>
-__global__ __launch_bounds__(256) void k_regular(AsmParams<M> p, int t1_base) {
+__global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M> h, int t1_base) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  MomPair<R>* sm = reinterpret_cast<MomPair<R>*>(smem_raw);
   const int t1 = t1_base + blockIdx.y;
-  const int t2 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t2 >= p.F || t2 <= t1) return;
+  const int ch = blockIdx.x;
   const int F = p.F;
-  int va[3], vb[3];
+  const int l0 = h.chunk_ptr[ch], nl = h.chunk_ptr[ch + 1] - l0;
+  const int s1 = p.tscat[t1];
+  double c1[3];
+  for (int d = 0; d < 3; ++d) c1[d] = p.tcen[d * F + t1];
+  int va[3];
+  R P1[3][3];
   for (int k = 0; k < 3; ++k) {
     va[k] = p.tvid[k * F + t1];
-    vb[k] = p.tvid[k * F + t2];
+    for (int d = 0; d < 3; ++d) P1[k][d] = R(p.tv[(3 * k + d) * F + t1] - c1[d]);
   }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      if (va[i] == vb[j]) return;  // singular pair: handled by k_singular
-
-  double c1[3], c2[3];
-  for (int d = 0; d < 3; ++d) {
-    c1[d] = p.tcen[d * F + t1];
-    c2[d] = p.tcen[d * F + t2];
-  }
-  const int cls = classify_pair(c1, c2, p.tdiam2[t1], p.tdiam2[t2]);
-  const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
-  const int s1 = p.tscat[t1], s2 = p.tscat[t2];
-  const bool inner = (s1 == s2);
-
-  // vertex coordinates relative to the test centroid (local origin)
-  R P1[3][3], P2[3][3];
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) {
-      P1[k][d] = R(p.tv[(3 * k + d) * F + t1] - c1[d]);
-      P2[k][d] = R(p.tv[(3 * k + d) * F + t2] - c1[d]);
-    }
-  const double A1 = p.tarea[t1], A2 = p.tarea[t2];
+  const double A1 = p.tarea[t1], d1 = p.tdiam2[t1];
   const double ke_r = p.k_ext;
-  const double ki_r = inner ? p.k_int[2 * s1] : 0.0, ki_i = inner ? p.k_int[2 * s1 + 1] : 0.0;
+  const double ki_r = p.k_int[2 * s1], ki_i = p.k_int[2 * s1 + 1];
   const bool decay_i = ki_i != 0.0;
 
-  Moments<R> me, mi;
-  me.zero();
-  mi.zero();
-  const int off = c_rule_off[q], n = c_rule_n[q];
-  const R AA = R(A1 * A2);
-  for (int a = 0; a < n; ++a) {
-    R x[3];
-    const R la0 = R(c_rule_l[off + a][0]), la1 = R(c_rule_l[off + a][1]), la2 = R(c_rule_l[off + a][2]);
-    for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
-    const R wa = R(c_rule_w[off + a]) * AA;
-    for (int b = 0; b < n; ++b) {
-      R y[3];
-      const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
-      for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
-      const R w = wa * R(c_rule_w[off + b]);
-      const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-      const R r2 = dx * dx + dy * dy + dz * dz;
-      KernelVal<R> kv = helmholtz<R>(r2, R(ke_r), R(0), false, w);
-      me.add(kv, x, y, true);
+  // ---- phase A: moments of (t1, T) for every listed trial triangle T
+  for (int li = threadIdx.x; li < nl; li += blockDim.x) {
+    const int t2 = h.chunk_tri[l0 + li];
+    MomPair<R> m;
+    m.e.zero();
+    m.i.zero();
+    bool shared = false;
+    for (int k = 0; k < 3; ++k) {
+      const int vb = p.tvid[k * F + t2];
+      shared |= (vb == va[0]) | (vb == va[1]) | (vb == va[2]);
+    }
+    if (!shared) {
+      double c2[3];
+      for (int d = 0; d < 3; ++d) c2[d] = p.tcen[d * F + t2];
+      const int cls = classify_pair(c1, c2, d1, p.tdiam2[t2]);
+      const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
+      const bool inner = p.tscat[t2] == s1;
+      R P2[3][3];
+      for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) P2[k][d] = R(p.tv[(3 * k + d) * F + t2] - c1[d]);
+      const R AA = R(A1 * p.tarea[t2]);
+      const int off = c_rule_off[q], n = c_rule_n[q];
+      for (int a = 0; a < n; ++a) {
+        R x[3];
+        const R la0 = R(c_rule_l[off + a][0]), la1 = R(c_rule_l[off + a][1]), la2 = R(c_rule_l[off + a][2]);
+        for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
+        const R wa = R(c_rule_w[off + a]) * AA;
+        for (int b = 0; b < n; ++b) {
+          R y[3];
+          const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
+          for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
+          const R w = wa * R(c_rule_w[off + b]);
+          const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          KernelVal<R> kv = helmholtz<R>(r2, R(ke_r), R(0), false, w);
+          m.e.add(kv, x, y, true);
+          if (inner) {
+            KernelVal<R> kw = helmholtz<R>(r2, R(ki_r), R(ki_i), decay_i, w);
+            m.i.add(kw, x, y, true);
+          }
+        }
+      }
+    }
+    sm[li] = m;
+  }
+  __syncthreads();
+
+  // ---- phase B: one trial edge per thread
+  const int j0 = ch * h.chunk;
+  const int nj = min(h.chunk, h.E_tot - j0);
+  double al1[3], w1[3][3];
+  for (int a = 0; a < 3; ++a) {
+    al1[a] = p.tsgn[a * F + t1] / (2.0 * A1);
+    for (int d = 0; d < 3; ++d) w1[a][d] = al1[a] * double(P1[a][d]);
+  }
+  const int64_t slot0 = 3 * int64_t(t1 - h.slab_t0);
+  for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
+    const int j = j0 + jj;
+    const int16_t* em = h.edge_map + 4 * int64_t(j);
+    const bool inner = h.edge_scat[j] == s1;
+    cplx<double> Se[3] = {{0, 0}, {0, 0}, {0, 0}}, Ce[3] = {{0, 0}, {0, 0}, {0, 0}};
+    cplx<double> Si[3] = {{0, 0}, {0, 0}, {0, 0}}, Ci[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int side = 0; side < 2; ++side) {
+      const int pos = em[2 * side], b = em[2 * side + 1];
+      const int t2 = h.chunk_tri[l0 + pos];
+      const double A2 = p.tarea[t2];
+      const double al2 = p.tsgn[b * F + t2] / (2.0 * A2);
+      double w2[3];
+      for (int d = 0; d < 3; ++d) w2[d] = al2 * (p.tv[(3 * b + d) * F + t2] - c1[d]);
+      const MomPair<R>& m = sm[pos];
+      for (int a = 0; a < 3; ++a) {
+        cplx<double> S, C;
+        contract<R, double>(m.e, al1[a], w1[a], al2, w2, ke_r, 0.0, true, S, C);
+        Se[a].re += S.re;
+        Se[a].im += S.im;
+        Ce[a].re += C.re;
+        Ce[a].im += C.im;
+        if (inner) {
+          contract<R, double>(m.i, al1[a], w1[a], al2, w2, ki_r, ki_i, true, S, C);
+          Si[a].re += S.re;
+          Si[a].im += S.im;
+          Ci[a].re += C.re;
+          Ci[a].im += C.im;
+        }
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      const int64_t o = 2 * ((slot0 + a) * h.E_tot + j);
+      h.He_S[o] = M(Se[a].re);
+      h.He_S[o + 1] = M(Se[a].im);
+      h.He_C[o] = M(Ce[a].re);
+      h.He_C[o + 1] = M(Ce[a].im);
       if (inner) {
-        KernelVal<R> kw = helmholtz<R>(r2, R(ki_r), R(ki_i), decay_i, w);
-        mi.add(kw, x, y, true);
+        const int64_t oi = 2 * ((slot0 + a) * h.ld_i + (j - h.edge_off_i));
+        h.Hi_S[oi] = M(Si[a].re);
+        h.Hi_S[oi + 1] = M(Si[a].im);
+        h.Hi_C[oi] = M(Ci[a].re);
+        h.Hi_C[oi + 1] = M(Ci[a].im);
       }
     }
   }
-  // epilogue: RT0 coefficients of the local RWG functions, u = alpha x - w
-  double al1[3], w1[3][3], al2[3], w2[3][3];
-  for (int a = 0; a < 3; ++a) {
-    const double sa = p.tsgn[a * F + t1], sb = p.tsgn[a * F + t2];
-    al1[a] = sa / (2.0 * A1);
-    al2[a] = sb / (2.0 * A2);
-    for (int d = 0; d < 3; ++d) {
-      w1[a][d] = al1[a] * double(P1[a][d]);
-      w2[a][d] = al2[a] * double(P2[a][d]);
-    }
-  }
-  int e1[3], e2[3];
-  for (int a = 0; a < 3; ++a) {
-    e1[a] = p.t2e[a * F + t1];
-    e2[a] = p.t2e[a * F + t2];
-  }
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      cplx<double> S, C;
-      contract<R, double>(me, al1[a], w1[a], al2[b], w2[b], ke_r, 0.0, true, S, C);
-      add_entry(p.Se, p.ld_ext, e1[a], e2[b], S);
-      add_entry(p.Se, p.ld_ext, e2[b], e1[a], S);
-      add_entry(p.Ce, p.ld_ext, e1[a], e2[b], C);
-      add_entry(p.Ce, p.ld_ext, e2[b], e1[a], C);
-      if (inner) {
-        contract<R, double>(mi, al1[a], w1[a], al2[b], w2[b], ki_r, ki_i, true, S, C);
-        const int o = p.edge_off[s1];
-        const int64_t ld = p.ld_int[s1];
-        M* Si = p.Si[s1];
-        M* Ci = p.Ci[s1];
-        add_entry(Si, ld, e1[a] - o, e2[b] - o, S);
-        add_entry(Si, ld, e2[b] - o, e1[a] - o, S);
-        add_entry(Ci, ld, e1[a] - o, e2[b] - o, C);
-        add_entry(Ci, ld, e2[b] - o, e1[a] - o, C);
-      }
-    }
+}
+
+// Pass 2: A[rows[r]] += H[sp[r]] + H[sm[r]] over complex columns.
+template <typename M>
+__global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M* __restrict__ H, int64_t ldh,
+                                                      const int32_t* rows, const int32_t* sp, const int32_t* sm,
+                                                      int ncols) {
+  const int r = blockIdx.y;
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= 2 * int64_t(ncols)) return;
+  const int i = rows[r], a = sp[r], b = sm[r];
+  M v = A[2 * int64_t(i) * lda + q];
+  if (a >= 0) v += H[2 * int64_t(a) * ldh + q];
+  if (b >= 0) v += H[2 * int64_t(b) * ldh + q];
+  A[2 * int64_t(i) * lda + q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,12 +322,22 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
 }
 
 template <typename R, typename M>
-void launch_regular(const AsmParams<M>& p, int t1_begin, int t1_end, hipStream_t st) {
+void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begin, int t1_end, int nchunks,
+                         int max_list, hipStream_t st) {
+  const size_t lds = size_t(max_list) * sizeof(MomPair<R>);
   for (int t0 = t1_begin; t0 < t1_end; t0 += 65535) {
     const int rows = std::min(65535, t1_end - t0);
-    // only trial blocks that reach beyond t0 can hold pairs with t2 > t1
-    dim3 grid((p.F + 255) / 256, rows);
-    hipLaunchKernelGGL((k_regular<R, M>), grid, dim3(256), 0, st, p, t0);
+    hipLaunchKernelGGL((k_regular_rows<R, M>), dim3(nchunks, rows), dim3(128), lds, st, p, h, t0);
+  }
+}
+
+template <typename M>
+void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st) {
+  for (int r0 = 0; r0 < nrows; r0 += 65535) {
+    const int nr = std::min(65535, nrows - r0);
+    hipLaunchKernelGGL((k_rows_combine<M>), dim3(unsigned((2 * int64_t(ncols) + 255) / 256), nr), dim3(256), 0, st,
+                       A, lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
   }
 }
 
@@ -290,8 +349,14 @@ void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st)
   hipLaunchKernelGGL((k_singular<M>), dim3(unsigned(blocks)), dim3(256), 0, st, p, s);
 }
 
-template void launch_regular<double, double>(const AsmParams<double>&, int, int, hipStream_t);
-template void launch_regular<float, float>(const AsmParams<float>&, int, int, hipStream_t);
+template void launch_regular_rows<double, double>(const AsmParams<double>&, const HalfJob<double>&, int, int, int,
+                                                  int, hipStream_t);
+template void launch_regular_rows<float, float>(const AsmParams<float>&, const HalfJob<float>&, int, int, int, int,
+                                                hipStream_t);
+template void launch_rows_combine<double>(double*, int64_t, const double*, int64_t, const int32_t*, const int32_t*,
+                                          const int32_t*, int, int, hipStream_t);
+template void launch_rows_combine<float>(float*, int64_t, const float*, int64_t, const int32_t*, const int32_t*,
+                                         const int32_t*, int, int, hipStream_t);
 template void launch_singular<double>(const AsmParams<double>&, const SingParams&, hipStream_t);
 template void launch_singular<float>(const AsmParams<float>&, const SingParams&, hipStream_t);
 

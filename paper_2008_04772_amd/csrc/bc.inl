@@ -111,9 +111,20 @@ __device__ void pair_moments(const SmallGeom& a, const SmallGeom& b, const doubl
   }
 }
 
+// Half contraction over the trial side for one (test child u1, trial
+// function slot sj): with u = a1 x - w1, v = a2 y - w2 (pair origin),
+//   Sv = a1 Ta + w1 . Tb,  Sd = a1 Td,  C = a1 Tc + w1 . Te,
+//   Ta = sum (a2 Mxy - w2 . Mx),  Tb = sum (w2 M0 - a2 My),  Td = sum 4 a2 M0,
+//   Tc = -sum w2 . Nx,            Te = sum (a2 Nx - Nd x w2),
+// sums over the trial children u2 of the cell.
+struct HalfC {
+  double v[18];  // Ta(2) Tb(6) Td(2) Tc(2) Te(6)
+};
+
 __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
   __shared__ double s_mom[BC_CHUNK_PAIRS * 2 * MOM_D];
   __shared__ double s_org[BC_MAX_RING][3];
+  __shared__ HalfC s_half[BC_CHUNK_PAIRS / 2][2];
   __shared__ double s_acc[BC_MAX_RING * BC_MAX_RING / 4][8];
   const int lane = threadIdx.x;
   const int64_t pr = blockIdx.x;
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
   const bool do_int = j.want_int && sc1 == sc2;
   const bool do_ext = j.want_ext;
   int nk = 0;
-  double kr[2], ki[2];
+  double kr[2] = {0, 0}, ki[2] = {0, 0};
   if (do_int) {
     kr[nk] = j.k_int[2 * sc1];
     ki[nk] = j.k_int[2 * sc1 + 1];
@@ -146,6 +157,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     const int nr = min(rows_per_chunk, n1 - r0);
     const int np = nr * n2;
     __syncthreads();
+    // ---- A: moments of every child pair of this chunk
     for (int p = lane; p < np; p += 64) {
       const int u1 = r0 + p / n2, u2 = p % n2;
       SmallGeom ga, gb;
@@ -157,38 +169,77 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
         const double* f = reinterpret_cast<const double*>(&m[k]);
         for (int q = 0; q < MOM_D; ++q) s_mom[(p * 2 + k) * MOM_D + q] = f[q];
       }
-      if (p % n2 == 0)
+      if (u2 == 0)
         for (int d = 0; d < 3; ++d) s_org[u1 - r0][d] = ga.cen[d];
     }
     __syncthreads();
+    // ---- B1: half contraction over the trial children, one (u1, sj) per lane
+    const int nh = nr * N2;
+    for (int hq = lane; hq < nh; hq += 64) {
+      const int ur = hq / N2, sj = hq % N2;
+      const double* o = s_org[ur];
+      for (int k = 0; k < nk; ++k) {
+        double T[18];
+        for (int q = 0; q < 18; ++q) T[q] = 0.0;
+        for (int u2 = 0; u2 < n2; ++u2) {
+          const double* c2 = cw + 4 * (int64_t(sj) * n2 + u2);
+          const double a2 = c2[0];
+          const double w2[3] = {c2[1] - a2 * o[0], c2[2] - a2 * o[1], c2[3] - a2 * o[2]};
+          const Moments<double>& m =
+              *reinterpret_cast<const Moments<double>*>(&s_mom[((ur * n2 + u2) * 2 + k) * MOM_D]);
+          // Ta
+          T[0] += a2 * m.Mxy.re - (w2[0] * m.Mx[0].re + w2[1] * m.Mx[1].re + w2[2] * m.Mx[2].re);
+          T[1] += a2 * m.Mxy.im - (w2[0] * m.Mx[0].im + w2[1] * m.Mx[1].im + w2[2] * m.Mx[2].im);
+          for (int d = 0; d < 3; ++d) {  // Tb
+            T[2 + 2 * d] += w2[d] * m.M0.re - a2 * m.My[d].re;
+            T[3 + 2 * d] += w2[d] * m.M0.im - a2 * m.My[d].im;
+          }
+          T[8] += 4.0 * a2 * m.M0.re;  // Td
+          T[9] += 4.0 * a2 * m.M0.im;
+          if (withC) {
+            T[10] -= w2[0] * m.Nx[0].re + w2[1] * m.Nx[1].re + w2[2] * m.Nx[2].re;  // Tc
+            T[11] -= w2[0] * m.Nx[0].im + w2[1] * m.Nx[1].im + w2[2] * m.Nx[2].im;
+            for (int d = 0; d < 3; ++d) {  // Te = a2 Nx - Nd x w2
+              const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+              T[12 + 2 * d] += a2 * m.Nx[d].re - (m.Nd[d1].re * w2[d2] - m.Nd[d2].re * w2[d1]);
+              T[13 + 2 * d] += a2 * m.Nx[d].im - (m.Nd[d1].im * w2[d2] - m.Nd[d2].im * w2[d1]);
+            }
+          }
+        }
+        for (int q = 0; q < 18; ++q) s_half[hq][k].v[q] = T[q];
+      }
+    }
+    __syncthreads();
+    // ---- B2: test side, one (si, sj) per lane
     for (int s = lane; s < nslot; s += 64) {
       const int si = s / N2, sj = s % N2;
       double acc[8];
       for (int q = 0; q < 8; ++q) acc[q] = s_acc[s][q];
-      for (int p = 0; p < np; ++p) {
-        const int u1 = r0 + p / n2, u2 = p % n2;
-        const double* c1 = cv + 4 * (int64_t(si) * n1 + u1);
-        const double* c2 = cw + 4 * (int64_t(sj) * n2 + u2);
-        const double a1 = c1[0], a2 = c2[0];
-        if (a1 == 0.0 && c1[1] == 0.0 && c1[2] == 0.0 && c1[3] == 0.0) continue;
-        if (a2 == 0.0 && c2[1] == 0.0 && c2[2] == 0.0 && c2[3] == 0.0) continue;
-        const double* o = s_org[u1 - r0];
-        // shift the fields to the pair's origin: alpha x - w = alpha x' - (w - alpha o)
-        double w1[3], w2[3];
-        for (int d = 0; d < 3; ++d) {
-          w1[d] = c1[1 + d] - a1 * o[d];
-          w2[d] = c2[1 + d] - a2 * o[d];
+      for (int k = 0; k < nk; ++k) {
+        double sv_re = 0, sv_im = 0, sd_re = 0, sd_im = 0, cc_re = 0, cc_im = 0;
+        for (int ur = 0; ur < nr; ++ur) {
+          const double* c1 = cv + 4 * (int64_t(si) * n1 + r0 + ur);
+          const double a1 = c1[0];
+          const double* o = s_org[ur];
+          const double w1[3] = {c1[1] - a1 * o[0], c1[2] - a1 * o[1], c1[3] - a1 * o[2]};
+          const double* T = s_half[ur * N2 + sj][k].v;
+          sv_re += a1 * T[0] + w1[0] * T[2] + w1[1] * T[4] + w1[2] * T[6];
+          sv_im += a1 * T[1] + w1[0] * T[3] + w1[1] * T[5] + w1[2] * T[7];
+          sd_re += a1 * T[8];
+          sd_im += a1 * T[9];
+          if (withC) {
+            cc_re += a1 * T[10] + w1[0] * T[12] + w1[1] * T[14] + w1[2] * T[16];
+            cc_im += a1 * T[11] + w1[0] * T[13] + w1[1] * T[15] + w1[2] * T[17];
+          }
         }
-        for (int k = 0; k < nk; ++k) {
-          const Moments<double>& m = *reinterpret_cast<const Moments<double>*>(&s_mom[(p * 2 + k) * MOM_D]);
-          cplx<double> S, C;
-          contract<double, double>(m, a1, w1, a2, w2, kr[k], ki[k], withC, S, C);
-          const int slot = (do_int && k == 0) ? 0 : 4;
-          acc[slot + 0] += S.re;
-          acc[slot + 1] += S.im;
-          acc[slot + 2] += C.re;
-          acc[slot + 3] += C.im;
-        }
+        // S = -ik Sv - Sd/(ik) = (ki - i kr) Sv + i Sd conj(k)/|k|^2
+        const double k2 = kr[k] * kr[k] + ki[k] * ki[k];
+        const double t_re = (sd_re * kr[k] + sd_im * ki[k]) / k2, t_im = (sd_im * kr[k] - sd_re * ki[k]) / k2;
+        const int slot = (do_int && k == 0) ? 0 : 4;
+        acc[slot + 0] += ki[k] * sv_re + kr[k] * sv_im - t_im;
+        acc[slot + 1] += ki[k] * sv_im - kr[k] * sv_re + t_re;
+        acc[slot + 2] += cc_re;
+        acc[slot + 3] += cc_im;
       }
       for (int q = 0; q < 8; ++q) s_acc[s][q] = acc[q];
     }
@@ -366,7 +417,7 @@ __global__ void k_rhs(AsmParams<double> g, RhsJob j) {
       x[d] = c_rule_l[off + qi][0] * P[0][d] + c_rule_l[off + qi][1] * P[1][d] + c_rule_l[off + qi][2] * P[2][d];
     const double ph = j.k_ext * (dr[0] * x[0] + dr[1] * x[1] + dr[2] * x[2]);
     double sn, cs;
-    sincos(ph, &sn, &cs);
+    sincos_taylor(ph, &sn, &cs);
     const double wq = c_rule_w[off + qi] * A;
     // E = p e, H' = k (d x p) e ; uD = E x n ; uN = H' x n
     double Ere[3], Eim[3], Hre[3], Him[3];
@@ -441,74 +492,146 @@ void launch_rhs(const AsmParams<double>& geo, const RhsJob& j, hipStream_t st) {
 // Vectors x are [rhs][D (E_tot) ; N (E_tot)] complex128.  One thread per
 // (direction, wave), looping over the triangles.
 // ---------------------------------------------------------------------------
-__global__ void k_far(AsmParams<double> g, const double* x, int64_t E_tot, int nrhs, double k,
-                      const double* obs, int nobs, double* Fout) {
+// Far field in three passes.  The currents are RT0 fields, so on every
+// quadrature point y of the degree-4 rule the surface currents are known
+// vectors; the pattern is then a non-uniform Fourier sum over the points.
+//   pass 1: per point, y and the weighted currents w |T| (J_D, J_N)(y)
+//   pass 2: per observation direction and segment of points, the partial sums
+//           V = sum exp(-ik xh.y) J(y) (point tiles staged in LDS)
+//   pass 3: per direction, the sum over segments and
+//           F = -(i/4pi) (k xh x V_D + V_N - xh (xh.V_N)).
+constexpr int FAR_TILE = 256;   // points per LDS tile
+constexpr int FAR_BLOCK = 256;  // directions per workgroup
+
+__global__ void k_far_points(AsmParams<double> g, const double* x, int64_t E_tot, int nrhs, int64_t npts,
+                             double* ypts, double* J) {
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= npts) return;
+  const int F = g.F;
+  const int off = c_rule_off[4], nq = c_rule_n[4];
+  const int T = int(tid / nq), q = int(tid % nq);
+  double P[3][3];
+  for (int kk = 0; kk < 3; ++kk)
+    for (int d = 0; d < 3; ++d) P[kk][d] = g.tv[(3 * kk + d) * F + T];
+  const double A = g.tarea[T];
+  double y[3];
+  for (int d = 0; d < 3; ++d)
+    y[d] = c_rule_l[off + q][0] * P[0][d] + c_rule_l[off + q][1] * P[1][d] + c_rule_l[off + q][2] * P[2][d];
+  for (int d = 0; d < 3; ++d) ypts[4 * tid + d] = y[d];
+  ypts[4 * tid + 3] = 0.0;
+  const double wq = c_rule_w[off + q] * A;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* xD = x + 2 * (int64_t(r) * 2 * E_tot);
+    const double* xN = xD + 2 * E_tot;
+    double jv[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+      const int e = g.t2e[a * F + T];
+      const double s = wq * g.tsgn[a * F + T] / (2.0 * A);
+      for (int d = 0; d < 3; ++d) {
+        const double f = s * (y[d] - P[a][d]);
+        jv[2 * d] += f * xD[2 * e];
+        jv[2 * d + 1] += f * xD[2 * e + 1];
+        jv[6 + 2 * d] += f * xN[2 * e];
+        jv[6 + 2 * d + 1] += f * xN[2 * e + 1];
+      }
+    }
+    double* o = J + 12 * (int64_t(r) * npts + tid);
+    for (int c = 0; c < 12; ++c) o[c] = jv[c];
+  }
+}
+
+// grid (direction blocks, segments, rhs); partial sums at
+// part[((r * nseg + s) * 12 + c) * nobs + o]
+__global__ __launch_bounds__(FAR_BLOCK) void k_far_sum(const double* ypts, const double* J, int64_t npts,
+                                                       int64_t seg_len, int nseg, double k, const double* obs,
+                                                       int nobs, double* part) {
+  __shared__ double s_y[FAR_TILE][4];
+  __shared__ double s_j[FAR_TILE][12];
+  const int o = blockIdx.x * FAR_BLOCK + threadIdx.x;
+  const int sg = blockIdx.y, r = blockIdx.z;
+  const bool live = o < nobs;
+  double xh[3] = {0, 0, 0};
+  if (live)
+    for (int d = 0; d < 3; ++d) xh[d] = -k * obs[3 * o + d];
+  double V[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t p0 = int64_t(sg) * seg_len, p1 = min(npts, p0 + seg_len);
+  const double* Jr = J + 12 * (int64_t(r) * npts);
+  for (int64_t t0 = p0; t0 < p1; t0 += FAR_TILE) {
+    const int nt = int(min<int64_t>(FAR_TILE, p1 - t0));
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt * 4; i += FAR_BLOCK) s_y[i >> 2][i & 3] = ypts[4 * t0 + i];
+    for (int i = threadIdx.x; i < nt * 12; i += FAR_BLOCK) s_j[i / 12][i % 12] = Jr[12 * t0 + i];
+    __syncthreads();
+    for (int t = 0; t < nt; ++t) {
+      double sn, cs;
+      sincos_taylor(xh[0] * s_y[t][0] + xh[1] * s_y[t][1] + xh[2] * s_y[t][2], &sn, &cs);
+      for (int c = 0; c < 6; ++c) {
+        const double jr = s_j[t][2 * c], ji = s_j[t][2 * c + 1];
+        V[2 * c] += cs * jr - sn * ji;
+        V[2 * c + 1] += cs * ji + sn * jr;
+      }
+    }
+  }
+  if (!live) return;
+  double* out = part + (int64_t(r) * nseg + sg) * 12 * int64_t(nobs) + o;
+  for (int c = 0; c < 12; ++c) out[int64_t(c) * nobs] = V[c];
+}
+
+__global__ void k_far_finish(const double* part, int nseg, double k, const double* obs, int nobs, int nrhs,
+                             double* Fout) {
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (tid >= int64_t(nobs) * nrhs) return;
   const int o = int(tid % nobs), r = int(tid / nobs);
   const double xh[3] = {obs[3 * o], obs[3 * o + 1], obs[3 * o + 2]};
-  const double* xD = x + 2 * (int64_t(r) * 2 * E_tot);
-  const double* xN = xD + 2 * E_tot;
-  double VD[6] = {0, 0, 0, 0, 0, 0}, VN[6] = {0, 0, 0, 0, 0, 0};
-  const int F = g.F;
-  const int off = c_rule_off[4], nq = c_rule_n[4];
-  for (int T = 0; T < F; ++T) {
-    double P[3][3];
-    for (int kk = 0; kk < 3; ++kk)
-      for (int d = 0; d < 3; ++d) P[kk][d] = g.tv[(3 * kk + d) * F + T];
-    const double A = g.tarea[T];
-    double cD[3][2], cN[3][2], s[3];
-    for (int a = 0; a < 3; ++a) {
-      const int e = g.t2e[a * F + T];
-      s[a] = g.tsgn[a * F + T] / (2.0 * A);
-      cD[a][0] = xD[2 * e];
-      cD[a][1] = xD[2 * e + 1];
-      cN[a][0] = xN[2 * e];
-      cN[a][1] = xN[2 * e + 1];
-    }
-    for (int q = 0; q < nq; ++q) {
-      double y[3];
-      for (int d = 0; d < 3; ++d)
-        y[d] = c_rule_l[off + q][0] * P[0][d] + c_rule_l[off + q][1] * P[1][d] + c_rule_l[off + q][2] * P[2][d];
-      double sn, cs;
-      sincos(-k * (xh[0] * y[0] + xh[1] * y[1] + xh[2] * y[2]), &sn, &cs);
-      const double wq = c_rule_w[off + q] * A;
-      const double er = wq * cs, ei = wq * sn;
-      for (int a = 0; a < 3; ++a)
-        for (int d = 0; d < 3; ++d) {
-          const double f = s[a] * (y[d] - P[a][d]);
-          // (cD f) * e
-          VD[2 * d] += f * (cD[a][0] * er - cD[a][1] * ei);
-          VD[2 * d + 1] += f * (cD[a][0] * ei + cD[a][1] * er);
-          VN[2 * d] += f * (cN[a][0] * er - cN[a][1] * ei);
-          VN[2 * d + 1] += f * (cN[a][0] * ei + cN[a][1] * er);
-        }
-    }
+  double V[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int sg = 0; sg < nseg; ++sg) {
+    const double* pp = part + (int64_t(r) * nseg + sg) * 12 * int64_t(nobs) + o;
+    for (int c = 0; c < 12; ++c) V[c] += pp[int64_t(c) * nobs];
   }
-  // B = k xh x VD + VN - xh (xh . VN);  F = -(i/4pi) B
-  double xv_re = xh[0] * VN[0] + xh[1] * VN[2] + xh[2] * VN[4];
-  double xv_im = xh[0] * VN[1] + xh[1] * VN[3] + xh[2] * VN[5];
-  double B[6];
+  const double* VD = V;
+  const double* VN = V + 6;
+  const double xv_re = xh[0] * VN[0] + xh[1] * VN[2] + xh[2] * VN[4];
+  const double xv_im = xh[0] * VN[1] + xh[1] * VN[3] + xh[2] * VN[5];
+  double* out = Fout + 6 * (int64_t(r) * nobs + o);
   for (int d = 0; d < 3; ++d) {
     const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
     const double cr = xh[d1] * VD[2 * d2] - xh[d2] * VD[2 * d1];
     const double ci = xh[d1] * VD[2 * d2 + 1] - xh[d2] * VD[2 * d1 + 1];
-    B[2 * d] = k * cr + VN[2 * d] - xh[d] * xv_re;
-    B[2 * d + 1] = k * ci + VN[2 * d + 1] - xh[d] * xv_im;
-  }
-  double* out = Fout + 6 * (int64_t(r) * nobs + o);
-  for (int d = 0; d < 3; ++d) {
+    const double b_re = k * cr + VN[2 * d] - xh[d] * xv_re;
+    const double b_im = k * ci + VN[2 * d + 1] - xh[d] * xv_im;
     // -(i/4pi)(b_re + i b_im) = (b_im - i b_re)/(4pi)
-    out[2 * d] = B[2 * d + 1] * INV_FOUR_PI;
-    out[2 * d + 1] = -B[2 * d] * INV_FOUR_PI;
+    out[2 * d] = b_im * INV_FOUR_PI;
+    out[2 * d + 1] = -b_re * INV_FOUR_PI;
   }
 }
 
+FarPlan far_field_plan(int F, int nrhs, int nobs) {
+  FarPlan p;
+  p.npts = int64_t(F) * 6;
+  const int64_t oblocks = (nobs + FAR_BLOCK - 1) / FAR_BLOCK;
+  // about 8 waves per SIMD over the chip, at least one LDS tile per segment
+  const int64_t want = (8 * 1024 + oblocks * nrhs * (FAR_BLOCK / 64) - 1) / (oblocks * nrhs * (FAR_BLOCK / 64));
+  const int64_t max_seg = (p.npts + FAR_TILE - 1) / FAR_TILE;
+  p.nseg = int(std::max<int64_t>(1, std::min<int64_t>(want, max_seg)));
+  p.seg_len = (p.npts + p.nseg - 1) / p.nseg;
+  p.seg_len = (p.seg_len + FAR_TILE - 1) / FAR_TILE * FAR_TILE;
+  p.nseg = int((p.npts + p.seg_len - 1) / p.seg_len);
+  p.n_ypts = 4 * p.npts;
+  p.n_J = 12 * p.npts * nrhs;
+  p.n_part = int64_t(nrhs) * p.nseg * 12 * nobs;
+  return p;
+}
+
 void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
-                      const double* obs, int nobs, double* F_out, hipStream_t st) {
+                      const double* obs, int nobs, double* F_out, const FarPlan& plan, double* ypts, double* J,
+                      double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_far_points, dim3(unsigned((plan.npts + 255) / 256)), dim3(256), 0, st, geo, x, E_tot, nrhs,
+                     plan.npts, ypts, J);
+  hipLaunchKernelGGL(k_far_sum, dim3(unsigned((nobs + FAR_BLOCK - 1) / FAR_BLOCK), unsigned(plan.nseg), unsigned(nrhs)),
+                     dim3(FAR_BLOCK), 0, st, ypts, J, plan.npts, plan.seg_len, plan.nseg, k, obs, nobs, part);
   const int64_t n = int64_t(nobs) * nrhs;
-  hipLaunchKernelGGL(k_far, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, geo, x, E_tot, nrhs, k, obs, nobs,
-                     F_out);
+  hipLaunchKernelGGL(k_far_finish, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, part, plan.nseg, k, obs, nobs,
+                     nrhs, F_out);
 }
 
 // sigma_sca[r] = sum_o w_o |F_o|^2

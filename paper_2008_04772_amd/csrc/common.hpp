@@ -28,9 +28,71 @@ struct KernelVal {
   cplx<R> G, Fg;
 };
 
-__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+// FP64 sine and cosine for |x| < 2^30: Cody-Waite reduction by pi/2 (two-part
+// constant, fused multiply-add keeps the first subtraction exact) and the
+// Taylor series of sin and cos on |r| <= pi/4, truncated after r^17 / r^18
+// (truncation error below 1e-19).  Constants: pi/2 rounded to double and its
+// remainder; 1/n! rounded to double.
+__device__ __forceinline__ void sincos_taylor(double x, double* sn, double* cs) {
+  const double PIO2_HI = 1.5707963267948966, PIO2_LO = 6.123233995736766e-17, TWO_OVER_PI = 0.6366197723675814;
+  const double q = rint(x * TWO_OVER_PI);
+  double r = fma(-q, PIO2_HI, x);
+  r = fma(-q, PIO2_LO, r);
+  const double r2 = r * r;
+  // sin r = r + r^3 P(r^2),  P = -1/3! + r^2/5! - r^4/7! + ... + r^14/17!
+  double ps = 2.8114572543455206e-15;           //  1/17!
+  ps = fma(ps, r2, -7.647163731819816e-13);     // -1/15!
+  ps = fma(ps, r2, 1.6059043836821613e-10);     //  1/13!
+  ps = fma(ps, r2, -2.505210838544172e-08);     // -1/11!
+  ps = fma(ps, r2, 2.755731922398589e-06);      //  1/9!
+  ps = fma(ps, r2, -1.984126984126984e-04);     // -1/7!
+  ps = fma(ps, r2, 8.333333333333333e-03);      //  1/5!
+  ps = fma(ps, r2, -0.16666666666666666);       // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  // cos r = 1 - r^2 Q(r^2),  Q = 1/2! - r^2/4! + r^4/6! - ... + r^16/18!
+  double pc = 1.5619206968586225e-16;           //  1/18!
+  pc = fma(pc, r2, -4.779477332387385e-14);     // -1/16!
+  pc = fma(pc, r2, 1.1470745597729725e-11);     //  1/14!
+  pc = fma(pc, r2, -2.08767569878681e-09);      // -1/12!
+  pc = fma(pc, r2, 2.755731922398589e-07);      //  1/10!
+  pc = fma(pc, r2, -2.48015873015873e-05);      // -1/8!
+  pc = fma(pc, r2, 1.388888888888889e-03);      //  1/6!
+  pc = fma(pc, r2, -0.041666666666666664);      // -1/4!
+  pc = fma(pc, r2, 0.5);                        //  1/2!
+  const double cr = fma(-pc, r2, 1.0);
+  const int n = int(int64_t(q) & 3);
+  const double s0 = (n & 1) ? cr : sr, c0 = (n & 1) ? sr : cr;
+  *sn = (n & 2) ? -s0 : s0;
+  *cs = ((n + 1) & 2) ? -c0 : c0;
+}
+
+// FP64 exp(x) for -700 < x < 700: x = m ln2 + r, |r| <= ln2/2, Taylor series
+// of exp r through r^13 (truncation below 1e-17), scaled by 2^m.
+__device__ __forceinline__ double exp_taylor(double x) {
+  const double LN2_HI = 0.6931471805599453, LN2_LO = 2.3190468138462996e-17, INV_LN2 = 1.4426950408889634;
+  const double m = rint(x * INV_LN2);
+  double r = fma(-m, LN2_HI, x);
+  r = fma(-m, LN2_LO, r);
+  double p = 1.6059043836821613e-10;  // 1/13!
+  p = fma(p, r, 2.08767569878681e-09);
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.755731922398589e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 1.984126984126984e-04);
+  p = fma(p, r, 1.388888888888889e-03);
+  p = fma(p, r, 8.333333333333333e-03);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, int(m));
+}
+
+__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos_taylor(x, s, c); }
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { __sincosf(x, s, c); }
-__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+__device__ __forceinline__ double exp_r(double x) { return exp_taylor(x); }
 __device__ __forceinline__ float exp_r(float x) { return __expf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float rsqrt_r(float x) { return __frsqrt_rn(x); }

@@ -31,6 +31,31 @@ struct AsmParams {
   const int64_t* ld_int;
 };
 
+// Atomic-free regular-pair assembly.  Trial edges are cut into chunks of
+// consecutive edges; for each chunk the distinct trial triangles (T+ and T-
+// of its edges) are listed once.  Pass 1 (one workgroup per test triangle and
+// chunk) integrates the listed triangles against the test triangle, keeps the
+// moments in LDS and writes, for each trial edge j and each local basis a of
+// the test triangle, the sum over T+(j), T-(j): a half-reduced row in
+// "slot" space (3 slots per test triangle).  Pass 2 adds the two slot rows of
+// every test edge into the dense operator.
+template <typename M>
+struct HalfJob {
+  int chunk;                   // edges per chunk
+  const int32_t* chunk_ptr;    // nchunks+1, into chunk_tri
+  const int32_t* chunk_tri;    // distinct trial triangles of each chunk
+  const int16_t* edge_map;     // 4 per edge: list position of T+, basis b+, position of T-, basis b-
+  const int32_t* edge_scat;    // scatterer of each union edge
+  int E_tot;
+  int slab_t0;                 // first test triangle of the slab
+  M* He_S;                     // slab slot rows x E_tot (exterior S, C)
+  M* He_C;
+  M* Hi_S;                     // slab slot rows x E_m of the slab's scatterer (interior S, C)
+  M* Hi_C;
+  int64_t ld_i;                // E_m
+  int edge_off_i;              // first union edge of the slab's scatterer
+};
+
 // Sauter-Schwab tables per relation kind (1 vertex, 2 edge, 3 identical):
 // records (x1, x2, y1, y2, w) on That x That.
 struct SingParams {
@@ -100,7 +125,12 @@ struct RhsJob {
 hipError_t upload_rules(const double* l, const double* w, hipStream_t s);
 
 template <typename R, typename M>
-void launch_regular(const AsmParams<M>& p, int t1_begin, int t1_end, hipStream_t st);
+void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begin, int t1_end, int nchunks,
+                         int max_list, hipStream_t st);
+// A[rows[r]] += H[sp[r]] + H[sm[r]] (negative slot = absent), complex rows of ncols
+template <typename M>
+void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st);
 template <typename M>
 void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st);
 
@@ -128,9 +158,12 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
 void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
 void launch_transpose(const double* in, double* out, int n, hipStream_t st);
-// y = alpha M x for both trace components (second component at +cstride)
-void launch_gemv_real2(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+// y = alpha M x for both trace components (second component at +cstride);
+// M is double or float (accumulation in double)
+template <typename M>
+void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
 // blocked Gauss-Jordan inverse helpers (column-major, no pivoting)
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st);
 void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipStream_t st);
@@ -155,9 +188,18 @@ void launch_zero_f(float* p, int64_t n, hipStream_t st);
 void launch_pack_cols(const double* src, int64_t sstride, int E, int nvec, double* dst, hipStream_t st);
 void launch_unpack_cols(const double* src, int E, int nvec, double* dst, int64_t dstride, hipStream_t st);
 
-// Far field: per-triangle RT0 coefficients of the currents, then the pattern.
+// Far field: currents on the quadrature points (degree-4 rule, 6 per
+// triangle), then a segmented non-uniform Fourier sum.  Workspace sizes (in
+// doubles) come from far_field_plan.
+struct FarPlan {
+  int64_t npts = 0, seg_len = 0;
+  int nseg = 1;
+  int64_t n_ypts = 0, n_J = 0, n_part = 0;
+};
+FarPlan far_field_plan(int F, int nrhs, int nobs);
 void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
-                      const double* obs, int nobs, double* F_out, hipStream_t st);
+                      const double* obs, int nobs, double* F_out, const FarPlan& plan, double* ypts, double* J,
+                      double* part, hipStream_t st);
 void launch_sigma_sca(const double* F, int nobs, int nrhs, const double* w, double* out, hipStream_t st);
 
 }  // namespace pmchwt

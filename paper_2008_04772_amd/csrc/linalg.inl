@@ -21,56 +21,115 @@ struct Pair2 {
 };
 
 // ---------------------------------------------------------------------------
-// yD += C xD + (1/k) S xN ; yN += -k S xD + C xN, one wavefront per row.
+// yD += C xD + (1/k) S xN ; yN += -k S xD + C xN.  One wavefront per two
+// rows, so that every x load from L2 serves both rows; each lane loads two
+// consecutive complex entries of S and C per step with one vector load (rows
+// start on aligned boundaries: the leading dimension is a multiple of 4).
+// FP64 accumulation for either storage type.
 // ---------------------------------------------------------------------------
+template <typename M>
+struct CPair {};
+template <>
+struct CPair<float> {
+  typedef float4 T;
+};
+template <>
+struct CPair<double> {
+  typedef double4 T;
+};
+
 template <typename M, int NR>
 __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, const M* __restrict__ C,
                                                      int64_t ld, int rows, int cols, double kr, double ki,
                                                      const double* __restrict__ xD,
                                                      const double* __restrict__ xN, double* yD, double* yN,
                                                      int64_t vstride) {
+  constexpr int ROWS = 2;
+  typedef typename CPair<M>::T V;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (row >= rows) return;
-  double a[NR][8];
-  for (int r = 0; r < NR; ++r)
-    for (int q = 0; q < 8; ++q) a[r][q] = 0.0;
-  const Pair2<M>* Sr = reinterpret_cast<const Pair2<M>*>(S + 2 * int64_t(row) * ld);
-  const Pair2<M>* Cr = reinterpret_cast<const Pair2<M>*>(C + 2 * int64_t(row) * ld);
-  for (int j = lane; j < cols; j += 64) {
-    const Pair2<M> s = Sr[j], c = Cr[j];
-    const double sr = double(s.re), si = double(s.im), cr = double(c.re), ci = double(c.im);
+  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  if (row0 >= rows) return;
+  const V* Sv[ROWS];
+  const V* Cv[ROWS];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) {
+    const int r = min(row0 + h, rows - 1);
+    Sv[h] = reinterpret_cast<const V*>(S + 2 * int64_t(r) * ld);
+    Cv[h] = reinterpret_cast<const V*>(C + 2 * int64_t(r) * ld);
+  }
+  double a[ROWS][NR][8];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[h][r][q] = 0.0;
+  const int np = (cols + 1) >> 1;
+  for (int q = lane; q < np; q += 64) {
+    const int j = 2 * q;
+    const bool pair = j + 1 < cols;
+    double xd[NR][4], xn[NR][4];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double* pd = xD + 2 * (int64_t(r) * vstride + j);
-      const double* pn = xN + 2 * (int64_t(r) * vstride + j);
-      const double dr = pd[0], di = pd[1], nr = pn[0], ni = pn[1];
-      a[r][0] += cr * dr - ci * di;  // C xD
-      a[r][1] += cr * di + ci * dr;
-      a[r][2] += sr * nr - si * ni;  // S xN
-      a[r][3] += sr * ni + si * nr;
-      a[r][4] += sr * dr - si * di;  // S xD
-      a[r][5] += sr * di + si * dr;
-      a[r][6] += cr * nr - ci * ni;  // C xN
-      a[r][7] += cr * ni + ci * nr;
+      const double2* pd = reinterpret_cast<const double2*>(xD + 2 * (int64_t(r) * vstride + j));
+      const double2* pn = reinterpret_cast<const double2*>(xN + 2 * (int64_t(r) * vstride + j));
+      const double2 d0 = pd[0], n0 = pn[0];
+      const double2 d1 = pair ? pd[1] : double2{0.0, 0.0};
+      const double2 n1 = pair ? pn[1] : double2{0.0, 0.0};
+      xd[r][0] = d0.x;
+      xd[r][1] = d0.y;
+      xd[r][2] = d1.x;
+      xd[r][3] = d1.y;
+      xn[r][0] = n0.x;
+      xn[r][1] = n0.y;
+      xn[r][2] = n1.x;
+      xn[r][3] = n1.y;
+    }
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      const V sv = Sv[h][q], cv = Cv[h][q];
+      const double s4[4] = {double(sv.x), double(sv.y), double(sv.z), double(sv.w)};
+      const double c4[4] = {double(cv.x), double(cv.y), double(cv.z), double(cv.w)};
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double sr = s4[2 * u], si = s4[2 * u + 1], cr = c4[2 * u], ci = c4[2 * u + 1];
+          const double dr = xd[r][2 * u], di = xd[r][2 * u + 1], nr = xn[r][2 * u], ni = xn[r][2 * u + 1];
+          a[h][r][0] += cr * dr - ci * di;  // C xD
+          a[h][r][1] += cr * di + ci * dr;
+          a[h][r][2] += sr * nr - si * ni;  // S xN
+          a[h][r][3] += sr * ni + si * nr;
+          a[h][r][4] += sr * dr - si * di;  // S xD
+          a[h][r][5] += sr * di + si * dr;
+          a[h][r][6] += cr * nr - ci * ni;  // C xN
+          a[h][r][7] += cr * ni + ci * nr;
+        }
     }
   }
-  for (int r = 0; r < NR; ++r)
-    for (int q = 0; q < 8; ++q) a[r][q] = wsum(a[r][q]);
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[h][r][q] = wsum(a[h][r][q]);
   if (lane == 0) {
     const double k2 = kr * kr + ki * ki;
     const double ikr = kr / k2, iki = -ki / k2;  // 1/k
-    for (int r = 0; r < NR; ++r) {
-      double* yd = yD + 2 * (int64_t(r) * vstride + row);
-      double* yn = yN + 2 * (int64_t(r) * vstride + row);
-      // S xN / k
-      const double t_re = a[r][2] * ikr - a[r][3] * iki, t_im = a[r][2] * iki + a[r][3] * ikr;
-      // -k S xD
-      const double u_re = -(kr * a[r][4] - ki * a[r][5]), u_im = -(kr * a[r][5] + ki * a[r][4]);
-      yd[0] += a[r][0] + t_re;
-      yd[1] += a[r][1] + t_im;
-      yn[0] += u_re + a[r][6];
-      yn[1] += u_im + a[r][7];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      if (row0 + h >= rows) break;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double* yd = yD + 2 * (int64_t(r) * vstride + row0 + h);
+        double* yn = yN + 2 * (int64_t(r) * vstride + row0 + h);
+        const double t_re = a[h][r][2] * ikr - a[h][r][3] * iki, t_im = a[h][r][2] * iki + a[h][r][3] * ikr;
+        const double u_re = -(kr * a[h][r][4] - ki * a[h][r][5]), u_im = -(kr * a[h][r][5] + ki * a[h][r][4]);
+        yd[0] += a[h][r][0] + t_re;
+        yd[1] += a[h][r][1] + t_im;
+        yn[0] += u_re + a[h][r][6];
+        yn[1] += u_im + a[h][r][7];
+      }
     }
   }
 }
@@ -79,7 +138,7 @@ template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
                         hipStream_t st) {
-  const dim3 grid((rows + 3) / 4), block(256);
+  const dim3 grid((rows + 7) / 8), block(256);
   int r0 = 0;
   while (r0 < nrhs) {
     const int left = nrhs - r0;
@@ -440,44 +499,67 @@ namespace pmchwt {
 // ---------------------------------------------------------------------------
 constexpr int GJ_B = 128;
 
-__global__ __launch_bounds__(512) void k_gj_block_inverse(const double* __restrict__ X, int64_t ldx,
+// Thread t holds column j = t % 128, rows [64 (t / 128), +64) in registers.
+// Step k of the in-place Gauss-Jordan inverse is one rank-1 update
+//   a_ij -= u_i v_j,  u_i = a_ik - [i == k],  v_j = a_kj / a_kk (j != k), v_k = 1 / a_kk,
+// applied after column k has been reset to the unit vector e_k (checked
+// entrywise: row k becomes a_kj / a_kk, column k becomes -a_ik / a_kk, the
+// pivot 1 / a_kk).  The owner of column k+1 publishes u for the next step
+// and resets its registers; the owners of row k+1 publish that row; two LDS
+// buffers alternate, so one barrier per step suffices.  Entries beyond b are
+// padded with the identity and stay inert.
+__global__ __launch_bounds__(256) void k_gj_block_inverse(const double* __restrict__ X, int64_t ldx,
                                                           double* __restrict__ out, int b) {
-  __shared__ double s[GJ_B * GJ_B];
-  for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
-    const int i = q % b, j = q / b;
-    s[j * GJ_B + i] = X[int64_t(j) * ldx + i];
+  __shared__ double colk[2][GJ_B], rowk[2][GJ_B];
+  const int t = threadIdx.x, j = t & (GJ_B - 1), i0 = 64 * (t >> 7);
+  double a[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) {
+    const int i = i0 + r;
+    a[r] = (i < b && j < b) ? X[int64_t(j) * ldx + i] : (i == j ? 1.0 : 0.0);
   }
-  __syncthreads();
-  for (int k = 0; k < b; ++k) {
-    const double piv = s[k * GJ_B + k];
-    const double ip = 1.0 / piv;
-    __syncthreads();
-    // row k scaled; new pivot entry 1/piv
-    for (int j = threadIdx.x; j < b; j += blockDim.x)
-      if (j != k) s[j * GJ_B + k] *= ip;
-    __syncthreads();
-    for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
-      const int i = q % b, j = q / b;
-      if (i == k) continue;
-      const double f = s[k * GJ_B + i];
-      if (j == k)
-        continue;
-      s[j * GJ_B + i] -= f * s[j * GJ_B + k];
+  if (i0 == 0) rowk[0][j] = a[0];
+  if (j == 0) {
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+      colk[0][i0 + r] = a[r] - (i0 + r == 0 ? 1.0 : 0.0);
+      a[r] = (i0 + r == 0) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < b; i += blockDim.x)
-      if (i != k) s[k * GJ_B + i] = -s[k * GJ_B + i] * ip;
-    if (threadIdx.x == 0) s[k * GJ_B + k] = ip;
-    __syncthreads();
   }
-  for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
-    const int i = q % b, j = q / b;
-    out[int64_t(j) * b + i] = s[j * GJ_B + i];
+  for (int k = 0; k < b; ++k) {
+    const int buf = k & 1, nb = buf ^ 1;
+    const int kn = k + 1;
+    __syncthreads();
+    const double ip = 1.0 / (colk[buf][k] + 1.0);
+    const double v = (j == k) ? ip : rowk[buf][j] * ip;
+#pragma unroll
+    for (int r0 = 0; r0 < 64; r0 += 16) {
+      double u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = colk[buf][i0 + r0 + r];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        a[r0 + r] = fma(-u[r], v, a[r0 + r]);
+        if (i0 + r0 + r == kn) rowk[nb][j] = a[r0 + r];  // wave-uniform condition
+      }
+    }
+    if (j == kn) {
+#pragma unroll
+      for (int r = 0; r < 64; ++r) {
+        colk[nb][i0 + r] = a[r] - (i0 + r == kn ? 1.0 : 0.0);
+        a[r] = (i0 + r == kn) ? 1.0 : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 64; ++r) {
+    const int i = i0 + r;
+    if (i < b && j < b) out[int64_t(j) * b + i] = a[r];
   }
 }
 
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_block_inverse, dim3(1), dim3(512), 0, st, X, ldx, out, b);
+  hipLaunchKernelGGL(k_gj_block_inverse, dim3(1), dim3(256), 0, st, X, ldx, out, b);
 }
 
 // Column block p0..p0+b of X (col-major, n x n): copy it to C (n x b) with the
@@ -498,57 +580,95 @@ void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipS
 }
 
 // Dense complex vectors: y = alpha * M x for real dense M applied to the
-// two trace components at once (one read of M for D and N and all vectors).
-template <int NR>
-__global__ __launch_bounds__(256) void k_gemv_real2(const double* __restrict__ Mat, int64_t ld, int rows, int cols,
+// two trace components at once (one read of M for D and N and all vectors);
+// one wavefront per four rows, so that each x load serves four rows.
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, int64_t ld, int rows, int cols,
                                                     double alpha, const double* __restrict__ x, double* y,
                                                     int64_t vstride, int64_t cstride) {
+  constexpr int ROWS = 4;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (row >= rows) return;
-  double a[NR][4];
-  for (int r = 0; r < NR; ++r) a[r][0] = a[r][1] = a[r][2] = a[r][3] = 0.0;
-  const double* mr = Mat + int64_t(row) * ld;
+  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  if (row0 >= rows) return;
+  const M* mr[ROWS];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) mr[h] = Mat + int64_t(min(row0 + h, rows - 1)) * ld;
+  double a[ROWS][NR][4];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
   for (int j = lane; j < cols; j += 64) {
-    const double m = mr[j];
+    double m[ROWS];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) m[h] = double(mr[h][j]);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double* p0 = x + 2 * (int64_t(r) * vstride + j);
-      const double* p1 = p0 + 2 * cstride;
-      a[r][0] += m * p0[0];
-      a[r][1] += m * p0[1];
-      a[r][2] += m * p1[0];
-      a[r][3] += m * p1[1];
+      const double2 x0 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + j));
+      const double2 x1 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + cstride + j));
+#pragma unroll
+      for (int h = 0; h < ROWS; ++h) {
+        a[h][r][0] += m[h] * x0.x;
+        a[h][r][1] += m[h] * x0.y;
+        a[h][r][2] += m[h] * x1.x;
+        a[h][r][3] += m[h] * x1.y;
+      }
     }
   }
-  for (int r = 0; r < NR; ++r)
-    for (int q = 0; q < 4; ++q) a[r][q] = wsum(a[r][q]);
-  if (lane == 0)
-    for (int r = 0; r < NR; ++r) {
-      double* q0 = y + 2 * (int64_t(r) * vstride + row);
-      double* q1 = q0 + 2 * cstride;
-      q0[0] = alpha * a[r][0];
-      q0[1] = alpha * a[r][1];
-      q1[0] = alpha * a[r][2];
-      q1[1] = alpha * a[r][3];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[h][r][q] = wsum(a[h][r][q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      if (row0 + h >= rows) break;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double* q0 = y + 2 * (int64_t(r) * vstride + row0 + h);
+        double* q1 = q0 + 2 * cstride;
+        q0[0] = alpha * a[h][r][0];
+        q0[1] = alpha * a[h][r][1];
+        q1[0] = alpha * a[h][r][2];
+        q1[1] = alpha * a[h][r][3];
+      }
     }
+  }
 }
 
-void launch_gemv_real2(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+template <typename M>
+void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
-  const dim3 grid((rows + 3) / 4), block(256);
+  const dim3 grid((rows + 15) / 16), block(256);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const double* xx = x + 2 * int64_t(r0) * vstride;
     double* yy = y + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      hipLaunchKernelGGL((k_gemv_real2<4>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride);
+      hipLaunchKernelGGL((k_gemv_real2<M, 4>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
+                         cstride);
       r0 += 4;
     } else {
-      hipLaunchKernelGGL((k_gemv_real2<1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride);
+      hipLaunchKernelGGL((k_gemv_real2<M, 1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
+                         cstride);
       r0 += 1;
     }
   }
+}
+template void launch_gemv_real2<double>(const double*, int64_t, int, int, double, const double*, double*, int,
+                                        int64_t, int64_t, hipStream_t);
+template void launch_gemv_real2<float>(const float*, int64_t, int, int, double, const double*, double*, int, int64_t,
+                                       int64_t, hipStream_t);
+
+__global__ void k_to_f32(const double* in, float* out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = float(in[i]);
+}
+
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, in, out, n);
 }
 
 }  // namespace pmchwt

@@ -55,11 +55,13 @@ def test_three_cubes_parity_and_counter(P, kind):
 
 
 def test_mixed_precision_with_refinement(P):
-    """FP32 regular pairs and operators, FP64 singular pairs / Arnoldi /
-    refinement residual: cross sections within 1e-5 of the FP64 oracle."""
+    """FP32 regular pairs and operators, FP32 copies of the inverted mass
+    matrices, FP64 singular pairs / Arnoldi / refinement residual: cross
+    sections within 1e-5 of the FP64 oracle."""
     note("mixed precision solve, icosphere(2), k=2")
     mesh = synth.icosphere(2)
-    ctx = make_ctx(P, [mesh], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=0.6, precond="S_INT", precision=P.MIXED)
+    ctx = make_ctx(P, [mesh], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=0.6, precond="S_INT", precision=P.MIXED,
+                   precisionP=P.MIXED)
     d, p = synth.single_wave()
     x, st = ctx.solve(d, p, P.solver_opts(tol=1e-8, restart=200, max_iter=1000, ir_max=3))
     se, ss = ctx.cross_sections(x, d, p)
