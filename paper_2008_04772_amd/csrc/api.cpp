@@ -1218,16 +1218,22 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
     c->MA.push_back(std::move(MA));
+    // padded copies for the vector loads of the application kernel
+    const int64_t ldm = padld(n);
     if (c->mass_f32) {
-      DBuf Mf = dalloc<float>(nn), MfT = dalloc<float>(nn);
-      launch_to_f32(Mi.as<double>(), Mf.as<float>(), int64_t(nn), c->stream);
-      launch_to_f32(MiT.as<double>(), MfT.as<float>(), int64_t(nn), c->stream);
+      DBuf Mf = dalloc<float>(size_t(n) * ldm), MfT = dalloc<float>(size_t(n) * ldm);
+      launch_repack(Mi.as<double>(), n, Mf.as<float>(), ldm, c->stream);
+      launch_repack(MiT.as<double>(), n, MfT.as<float>(), ldm, c->stream);
       HIPCHK(hipStreamSynchronize(c->stream));
       c->Minv.push_back(std::move(Mf));
       c->MinvT.push_back(std::move(MfT));
     } else {
-      c->Minv.push_back(std::move(Mi));
-      c->MinvT.push_back(std::move(MiT));
+      DBuf Md = dalloc<double>(size_t(n) * ldm), MdT = dalloc<double>(size_t(n) * ldm);
+      launch_repack(Mi.as<double>(), n, Md.as<double>(), ldm, c->stream);
+      launch_repack(MiT.as<double>(), n, MdT.as<double>(), ldm, c->stream);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->Minv.push_back(std::move(Md));
+      c->MinvT.push_back(std::move(MdT));
     }
     c->Glu.push_back(std::move(G));
   }
@@ -1313,11 +1319,11 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
     if (c->mass_f32)
-      launch_gemv_real2(c->Minv[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs,
-                        E, c->stream);
+      launch_gemv_real2(c->Minv[m].as<float>(), padld(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
+                        nrhs, vs, E, c->stream);
     else
-      launch_gemv_real2(c->Minv[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs,
-                        E, c->stream);
+      launch_gemv_real2(c->Minv[m].as<double>(), padld(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
+                        nrhs, vs, E, c->stream);
   }
   launch_zero(t2, 2 * vs * nrhs, c->stream);
   const int64_t* rp = c->p_rowptr.as<int64_t>();
@@ -1338,11 +1344,11 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
     if (c->mass_f32)
-      launch_gemv_real2(c->MinvT[m].as<float>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs,
-                        E, c->stream);
+      launch_gemv_real2(c->MinvT[m].as<float>(), padld(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
+                        nrhs, vs, E, c->stream);
     else
-      launch_gemv_real2(c->MinvT[m].as<double>(), s.topo.E, s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs,
-                        E, c->stream);
+      launch_gemv_real2(c->MinvT[m].as<double>(), padld(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
+                        nrhs, vs, E, c->stream);
   }
   HIPCHK(hipGetLastError());
 }

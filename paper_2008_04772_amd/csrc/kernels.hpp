@@ -159,11 +159,14 @@ void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double 
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
 void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // y = alpha M x for both trace components (second component at +cstride);
-// M is double or float (accumulation in double)
+// M is double or float (accumulation in double); ld a multiple of 4 with
+// zero padding columns
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
-void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
+// n x n row-major (ld n) -> n x n with leading dimension ldo >= n, zero padding
+template <typename T>
+void launch_repack(const double* in, int n, T* out, int64_t ldo, hipStream_t st);
 // blocked Gauss-Jordan inverse helpers (column-major, no pivoting)
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st);
 void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipStream_t st);

@@ -21,21 +21,32 @@ struct Pair2 {
 };
 
 // ---------------------------------------------------------------------------
-// yD += C xD + (1/k) S xN ; yN += -k S xD + C xN.  One wavefront per two
-// rows, so that every x load from L2 serves both rows; each lane loads two
-// consecutive complex entries of S and C per step with one vector load (rows
-// start on aligned boundaries: the leading dimension is a multiple of 4).
-// FP64 accumulation for either storage type.
+// yD += C xD + S (xN / k) ; yN += C xN + S (-k xD).  The two scaled vectors
+// are formed per column in registers, so each row needs only two complex
+// accumulators.  One wavefront streams ROWS rows (every x load from L2
+// serves all of them); each lane loads two consecutive complex entries of S
+// and C per step with one vector load (rows start on aligned boundaries: the
+// leading dimension is a multiple of 4), marked non-temporal since the
+// operator is read once per application.  FP64 accumulation for either
+// storage type.
 // ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
 template <typename M>
 struct CPair {};
 template <>
 struct CPair<float> {
-  typedef float4 T;
+  typedef f4v T;
 };
 template <>
 struct CPair<double> {
-  typedef double4 T;
+  typedef d4v T;
+};
+
+// rows per wavefront for NR right-hand sides (register budget)
+template <typename M, int NR>
+struct GemvRows {
+  static constexpr int value = (sizeof(M) == 4 ? 8 : 4) / NR > 0 ? (sizeof(M) == 4 ? 8 : 4) / NR : 1;
 };
 
 template <typename M, int NR>
@@ -44,7 +55,7 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
                                                      const double* __restrict__ xD,
                                                      const double* __restrict__ xN, double* yD, double* yN,
                                                      int64_t vstride) {
-  constexpr int ROWS = 2;
+  constexpr int ROWS = GemvRows<M, NR>::value;
   typedef typename CPair<M>::T V;
   const int lane = threadIdx.x & 63;
   const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
@@ -57,18 +68,25 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
     Sv[h] = reinterpret_cast<const V*>(S + 2 * int64_t(r) * ld);
     Cv[h] = reinterpret_cast<const V*>(C + 2 * int64_t(r) * ld);
   }
-  double a[ROWS][NR][8];
+  const double k2 = kr * kr + ki * ki;
+  const double ikr = kr / k2, iki = -ki / k2;  // 1/k
+  double a[ROWS][NR][4];
 #pragma unroll
   for (int h = 0; h < ROWS; ++h)
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) a[h][r][q] = 0.0;
+    for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
   const int np = (cols + 1) >> 1;
   for (int q = lane; q < np; q += 64) {
+    V sv[ROWS], cv[ROWS];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      sv[h] = __builtin_nontemporal_load(&Sv[h][q]);
+      cv[h] = __builtin_nontemporal_load(&Cv[h][q]);
+    }
     const int j = 2 * q;
     const bool pair = j + 1 < cols;
-    double xd[NR][4], xn[NR][4];
+    // xd, xn and the scaled p = xN / k, m = -k xD; two columns each
+    double xd[NR][4], xn[NR][4], pv[NR][4], mv[NR][4];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const double2* pd = reinterpret_cast<const double2*>(xD + 2 * (int64_t(r) * vstride + j));
@@ -84,26 +102,27 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
       xn[r][1] = n0.y;
       xn[r][2] = n1.x;
       xn[r][3] = n1.y;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        pv[r][2 * u] = xn[r][2 * u] * ikr - xn[r][2 * u + 1] * iki;
+        pv[r][2 * u + 1] = xn[r][2 * u] * iki + xn[r][2 * u + 1] * ikr;
+        mv[r][2 * u] = -(kr * xd[r][2 * u] - ki * xd[r][2 * u + 1]);
+        mv[r][2 * u + 1] = -(kr * xd[r][2 * u + 1] + ki * xd[r][2 * u]);
+      }
     }
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
-      const V sv = Sv[h][q], cv = Cv[h][q];
-      const double s4[4] = {double(sv.x), double(sv.y), double(sv.z), double(sv.w)};
-      const double c4[4] = {double(cv.x), double(cv.y), double(cv.z), double(cv.w)};
+      const double s4[4] = {double(sv[h].x), double(sv[h].y), double(sv[h].z), double(sv[h].w)};
+      const double c4[4] = {double(cv[h].x), double(cv[h].y), double(cv[h].z), double(cv[h].w)};
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const double sr = s4[2 * u], si = s4[2 * u + 1], cr = c4[2 * u], ci = c4[2 * u + 1];
-          const double dr = xd[r][2 * u], di = xd[r][2 * u + 1], nr = xn[r][2 * u], ni = xn[r][2 * u + 1];
-          a[h][r][0] += cr * dr - ci * di;  // C xD
-          a[h][r][1] += cr * di + ci * dr;
-          a[h][r][2] += sr * nr - si * ni;  // S xN
-          a[h][r][3] += sr * ni + si * nr;
-          a[h][r][4] += sr * dr - si * di;  // S xD
-          a[h][r][5] += sr * di + si * dr;
-          a[h][r][6] += cr * nr - ci * ni;  // C xN
-          a[h][r][7] += cr * ni + ci * nr;
+          a[h][r][0] += cr * xd[r][2 * u] - ci * xd[r][2 * u + 1] + sr * pv[r][2 * u] - si * pv[r][2 * u + 1];
+          a[h][r][1] += cr * xd[r][2 * u + 1] + ci * xd[r][2 * u] + sr * pv[r][2 * u + 1] + si * pv[r][2 * u];
+          a[h][r][2] += cr * xn[r][2 * u] - ci * xn[r][2 * u + 1] + sr * mv[r][2 * u] - si * mv[r][2 * u + 1];
+          a[h][r][3] += cr * xn[r][2 * u + 1] + ci * xn[r][2 * u] + sr * mv[r][2 * u + 1] + si * mv[r][2 * u];
         }
     }
   }
@@ -112,10 +131,8 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[h][r][q] = wsum(a[h][r][q]);
+      for (int q = 0; q < 4; ++q) a[h][r][q] = wsum(a[h][r][q]);
   if (lane == 0) {
-    const double k2 = kr * kr + ki * ki;
-    const double ikr = kr / k2, iki = -ki / k2;  // 1/k
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
       if (row0 + h >= rows) break;
@@ -123,12 +140,10 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
       for (int r = 0; r < NR; ++r) {
         double* yd = yD + 2 * (int64_t(r) * vstride + row0 + h);
         double* yn = yN + 2 * (int64_t(r) * vstride + row0 + h);
-        const double t_re = a[h][r][2] * ikr - a[h][r][3] * iki, t_im = a[h][r][2] * iki + a[h][r][3] * ikr;
-        const double u_re = -(kr * a[h][r][4] - ki * a[h][r][5]), u_im = -(kr * a[h][r][5] + ki * a[h][r][4]);
-        yd[0] += a[h][r][0] + t_re;
-        yd[1] += a[h][r][1] + t_im;
-        yn[0] += u_re + a[h][r][6];
-        yn[1] += u_im + a[h][r][7];
+        yd[0] += a[h][r][0];
+        yd[1] += a[h][r][1];
+        yn[0] += a[h][r][2];
+        yn[1] += a[h][r][3];
       }
     }
   }
@@ -138,7 +153,8 @@ template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
                         hipStream_t st) {
-  const dim3 grid((rows + 7) / 8), block(256);
+  auto grid = [rows](int rpw) { return dim3(unsigned((rows + 4 * rpw - 1) / (4 * rpw))); };
+  const dim3 block(256);
   int r0 = 0;
   while (r0 < nrhs) {
     const int left = nrhs - r0;
@@ -147,16 +163,16 @@ void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, 
     double* yd = yD + 2 * int64_t(r0) * vstride;
     double* yn = yN + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      hipLaunchKernelGGL((k_gemv_pmchwt<M, 4>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
-                         vstride);
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 4>), grid(GemvRows<M, 4>::value), block, 0, st, S, C, ld, rows, cols, kr,
+                         ki, xd, xn, yd, yn, vstride);
       r0 += 4;
     } else if (left >= 2) {
-      hipLaunchKernelGGL((k_gemv_pmchwt<M, 2>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
-                         vstride);
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 2>), grid(GemvRows<M, 2>::value), block, 0, st, S, C, ld, rows, cols, kr,
+                         ki, xd, xn, yd, yn, vstride);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_gemv_pmchwt<M, 1>), grid, block, 0, st, S, C, ld, rows, cols, kr, ki, xd, xn, yd, yn,
-                         vstride);
+      hipLaunchKernelGGL((k_gemv_pmchwt<M, 1>), grid(GemvRows<M, 1>::value), block, 0, st, S, C, ld, rows, cols, kr,
+                         ki, xd, xn, yd, yn, vstride);
       r0 += 1;
     }
   }
@@ -581,39 +597,52 @@ void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipS
 
 // Dense complex vectors: y = alpha * M x for real dense M applied to the
 // two trace components at once (one read of M for D and N and all vectors);
-// one wavefront per four rows, so that each x load serves four rows.
+// one wavefront per 8 / NR rows, so that each x load serves several rows.
+// Each lane loads 16 bytes of a row at a time (4 floats or 2 doubles; the
+// leading dimension is a multiple of 4 and the padding columns are zero),
+// non-temporal since the matrix is streamed once per application.
 template <typename M, int NR>
 __global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, int64_t ld, int rows, int cols,
                                                     double alpha, const double* __restrict__ x, double* y,
                                                     int64_t vstride, int64_t cstride) {
-  constexpr int ROWS = 4;
+  constexpr int VEC = 16 / int(sizeof(M));
+  constexpr int ROWS = NR >= 8 ? 1 : 8 / NR;
+  typedef M Vt __attribute__((ext_vector_type(VEC)));
   const int lane = threadIdx.x & 63;
   const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
   if (row0 >= rows) return;
-  const M* mr[ROWS];
+  const Vt* mr[ROWS];
 #pragma unroll
-  for (int h = 0; h < ROWS; ++h) mr[h] = Mat + int64_t(min(row0 + h, rows - 1)) * ld;
+  for (int h = 0; h < ROWS; ++h) mr[h] = reinterpret_cast<const Vt*>(Mat + int64_t(min(row0 + h, rows - 1)) * ld);
   double a[ROWS][NR][4];
 #pragma unroll
   for (int h = 0; h < ROWS; ++h)
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
-  for (int j = lane; j < cols; j += 64) {
-    double m[ROWS];
+  const int nq = (cols + VEC - 1) / VEC;
+  for (int q = lane; q < nq; q += 64) {
+    Vt m[ROWS];
 #pragma unroll
-    for (int h = 0; h < ROWS; ++h) m[h] = double(mr[h][j]);
+    for (int h = 0; h < ROWS; ++h) m[h] = __builtin_nontemporal_load(&mr[h][q]);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double2 x0 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + j));
-      const double2 x1 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + cstride + j));
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int h = 0; h < ROWS; ++h) {
-        a[h][r][0] += m[h] * x0.x;
-        a[h][r][1] += m[h] * x0.y;
-        a[h][r][2] += m[h] * x1.x;
-        a[h][r][3] += m[h] * x1.y;
+      for (int v = 0; v < VEC; ++v) {
+        const int j = q * VEC + v;
+        double2 x0 = {0.0, 0.0}, x1 = {0.0, 0.0};
+        if (j < cols) {
+          x0 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + j));
+          x1 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + cstride + j));
+        }
+#pragma unroll
+        for (int h = 0; h < ROWS; ++h) {
+          const double mv = double(m[h][v]);
+          a[h][r][0] += mv * x0.x;
+          a[h][r][1] += mv * x0.y;
+          a[h][r][2] += mv * x1.x;
+          a[h][r][3] += mv * x1.y;
+        }
       }
-    }
   }
 #pragma unroll
   for (int h = 0; h < ROWS; ++h)
@@ -641,16 +670,18 @@ __global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, i
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
-  const dim3 grid((rows + 15) / 16), block(256);
+  const dim3 block(256);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const double* xx = x + 2 * int64_t(r0) * vstride;
     double* yy = y + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
+      const dim3 grid((rows + 7) / 8);
       hipLaunchKernelGGL((k_gemv_real2<M, 4>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
                          cstride);
       r0 += 4;
     } else {
+      const dim3 grid((rows + 31) / 32);
       hipLaunchKernelGGL((k_gemv_real2<M, 1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
                          cstride);
       r0 += 1;
@@ -662,14 +693,22 @@ template void launch_gemv_real2<double>(const double*, int64_t, int, int, double
 template void launch_gemv_real2<float>(const float*, int64_t, int, int, double, const double*, double*, int, int64_t,
                                        int64_t, hipStream_t);
 
-__global__ void k_to_f32(const double* in, float* out, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = float(in[i]);
+// out[i * ldo + j] = in[i * n + j] (j < n), 0 for n <= j < ldo
+template <typename T>
+__global__ void k_repack(const double* in, int n, T* out, int64_t ldo) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= int64_t(n) * ldo) return;
+  const int64_t i = q / ldo, j = q % ldo;
+  out[q] = j < n ? T(in[i * n + j]) : T(0);
 }
 
-void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+template <typename T>
+void launch_repack(const double* in, int n, T* out, int64_t ldo, hipStream_t st) {
+  const int64_t m = int64_t(n) * ldo;
+  hipLaunchKernelGGL((k_repack<T>), dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, in, n, out, ldo);
 }
+template void launch_repack<double>(const double*, int, double*, int64_t, hipStream_t);
+template void launch_repack<float>(const double*, int, float*, int64_t, hipStream_t);
 
 }  // namespace pmchwt
 
