@@ -32,11 +32,13 @@ hipError_t upload_rules(const double* l, const double* w, hipStream_t s) {
 }
 
 // Relative-distance class of a disjoint pair: 0 near, 1 medium, 2 far.
-// Evaluated in FP64 without contraction so that it reproduces a plain
-// IEEE evaluation of |c1 - c2|^2 < 4 max(d1^2, d2^2) (resp. 16).
-__device__ __noinline__ int classify_pair(const double* c1, const double* c2, double d1, double d2) {
+// Evaluated in FP64 without contraction (the pragma marks these operations
+// non-fusable, also once inlined) so that it reproduces a plain IEEE
+// evaluation of |c1 - c2|^2 < 4 max(d1^2, d2^2) (resp. 16).
+__device__ __forceinline__ int classify_pair(double c1x, double c1y, double c1z, double c2x, double c2y, double c2z,
+                                             double d1, double d2) {
 #pragma clang fp contract(off)
-  double dx = c1[0] - c2[0], dy = c1[1] - c2[1], dz = c1[2] - c2[2];
+  double dx = c1x - c2x, dy = c1y - c2y, dz = c1z - c2z;
   double dist2 = dx * dx + dy * dy + dz * dz;
   double m2 = d1 > d2 ? d1 : d2;
   if (dist2 < 4.0 * m2) return 0;
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
     if (!shared) {
       double c2[3];
       for (int d = 0; d < 3; ++d) c2[d] = p.tcen[d * F + t2];
-      const int cls = classify_pair(c1, c2, d1, p.tdiam2[t2]);
+      const int cls = classify_pair(c1[0], c1[1], c1[2], c2[0], c2[1], c2[2], d1, p.tdiam2[t2]);
       const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
       const bool inner = p.tscat[t2] == s1;
       R P2[3][3];
@@ -230,48 +232,37 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
     vb[k] = p.tvid[k * F + t2];
   }
   // reorder: common vertices first, in test-triangle order
-  int oa[3], ob[3], nc = 0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      if (va[i] == vb[j]) {
-        oa[nc] = i;
-        ob[nc] = j;
-        ++nc;
-      }
-  {
-    int ka = nc, kb = nc;
-    for (int i = 0; i < 3; ++i) {
-      bool c = false;
-      for (int j = 0; j < nc; ++j) c |= (oa[j] == i);
-      if (!c) oa[ka++] = i;
-    }
-    for (int i = 0; i < 3; ++i) {
-      bool c = false;
-      for (int j = 0; j < nc; ++j) c |= (ob[j] == i);
-      if (!c) ob[kb++] = i;
-    }
-  }
+  int oa, ob;
+  const int nc = shared_order(va, vb, oa, ob);
   double c1[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) c1[d] = p.tcen[d * F + t1];
   double P1[3][3], P2[3][3], Q1[3][3], Q2[3][3];
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       P1[k][d] = p.tv[(3 * k + d) * F + t1] - c1[d];
       P2[k][d] = p.tv[(3 * k + d) * F + t2] - c1[d];
     }
-  for (int k = 0; k < 3; ++k)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ia = (oa >> (2 * k)) & 3, ib = (ob >> (2 * k)) & 3;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Q1[k][d] = P1[oa[k]][d];
-      Q2[k][d] = P2[ob[k]][d];
+      const double u1[3] = {P1[0][d], P1[1][d], P1[2][d]}, u2[3] = {P2[0][d], P2[1][d], P2[2][d]};
+      Q1[k][d] = pick3(u1, ia);
+      Q2[k][d] = pick3(u2, ib);
     }
+  }
   const double A1 = p.tarea[t1], A2 = p.tarea[t2];
   const int sc = p.tscat[t1];
   const double ke_r = p.k_ext;
   const double ki_r = p.k_int[2 * sc], ki_i = p.k_int[2 * sc + 1];
   const bool decay_i = ki_i != 0.0;
-  const int kind = nc;  // 1 vertex, 2 edge, 3 identical
-  const double* tab = s.tab[kind];
-  const int npts = s.npts[kind];
+  // nc = 1 vertex, 2 edge, 3 identical
+  const double* tab = nc == 1 ? s.tab[1] : (nc == 2 ? s.tab[2] : s.tab[3]);
+  const int npts = nc == 1 ? s.npts[1] : (nc == 2 ? s.npts[2] : s.npts[3]);
   const double AA = 4.0 * A1 * A2;
 
   Moments<double> me, mi;
@@ -296,6 +287,7 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
   double* fe = reinterpret_cast<double*>(&me);
   double* fi = reinterpret_cast<double*>(&mi);
   constexpr int NM = sizeof(Moments<double>) / sizeof(double);
+#pragma unroll
   for (int i = 0; i < NM; ++i) {
     fe[i] = wave_sum(fe[i]);
     fi[i] = wave_sum(fi[i]);
@@ -305,9 +297,11 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
     const double sa = p.tsgn[a * F + t1], sb = p.tsgn[b * F + t2];
     const double al1 = sa / (2.0 * A1), al2 = sb / (2.0 * A2);
     double w1[3], w2[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      w1[d] = al1 * P1[a][d];
-      w2[d] = al2 * P2[b][d];
+      const double u1[3] = {P1[0][d], P1[1][d], P1[2][d]}, u2[3] = {P2[0][d], P2[1][d], P2[2][d]};
+      w1[d] = al1 * pick3(u1, a);
+      w2[d] = al2 * pick3(u2, b);
     }
     const int i = p.t2e[a * F + t1], j = p.t2e[b * F + t2];
     cplx<double> S, C;

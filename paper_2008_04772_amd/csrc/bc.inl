@@ -25,88 +25,90 @@ struct SmallGeom {
   double cen[3], diam2, area;
 };
 
-__device__ __forceinline__ void load_child(const CellParams& c, int ch, SmallGeom& g) {
+__device__ __forceinline__ SmallGeom load_child(const CellParams& c, int ch) {
+  SmallGeom g;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
+#pragma unroll
     for (int d = 0; d < 3; ++d) g.P[k][d] = c.child_v[9 * int64_t(ch) + 3 * k + d];
     g.vid[k] = c.child_vid[3 * int64_t(ch) + k];
   }
   for (int d = 0; d < 3; ++d) g.cen[d] = c.child_cen[3 * int64_t(ch) + d];
   g.diam2 = c.child_diam2[ch];
   g.area = c.child_area[ch];
+  return g;
 }
 
 // Moments of one (test, trial) triangle pair, origin = test centroid.
 // Identical / shared-edge / shared-vertex pairs use the Sauter-Schwab tables,
 // disjoint pairs the tensor rule of their distance class.
-__device__ void pair_moments(const SmallGeom& a, const SmallGeom& b, const double* const* tab,
-                             const int* npts, int qn, int qm, int qf, int nk, const double* kr,
-                             const double* ki, bool withC, Moments<double>* out) {
-  for (int k = 0; k < nk; ++k) out[k].zero();
+// Moments of one (test, trial) triangle pair at one wavenumber, origin = test
+// centroid.  Identical / shared-edge / shared-vertex pairs use the
+// Sauter-Schwab tables (tab1..tab3 with n1..n3 records), disjoint pairs the
+// tensor rule of their distance class.
+__device__ __forceinline__ void pair_moments(const SmallGeom a, const SmallGeom b, const double* tab1, const double* tab2,
+                             const double* tab3, int n1, int n2, int n3, int qn, int qm, int qf, double kr, double ki,
+                             bool withC, Moments<double>& out) {
+  out.zero();
   double P1[3][3], P2[3][3];
+#pragma unroll
   for (int v = 0; v < 3; ++v)
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       P1[v][d] = a.P[v][d] - a.cen[d];
       P2[v][d] = b.P[v][d] - a.cen[d];
     }
-  int oa[3], ob[3], nc = 0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      if (a.vid[i] == b.vid[j]) {
-        oa[nc] = i;
-        ob[nc] = j;
-        ++nc;
-      }
+  const bool decay = ki != 0.0;
+  int oa, ob;
+  const int nc = shared_order(a.vid, b.vid, oa, ob);
   if (nc > 0) {
-    int ka = nc, kb = nc;
-    for (int i = 0; i < 3; ++i) {
-      bool c = false;
-      for (int j = 0; j < nc; ++j) c |= (oa[j] == i);
-      if (!c) oa[ka++] = i;
+    double Q1[3][3], Q2[3][3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const int ia = (oa >> (2 * v)) & 3, ib = (ob >> (2 * v)) & 3;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double c1[3] = {P1[0][d], P1[1][d], P1[2][d]}, c2[3] = {P2[0][d], P2[1][d], P2[2][d]};
+        Q1[v][d] = pick3(c1, ia);
+        Q2[v][d] = pick3(c2, ib);
+      }
     }
-    for (int i = 0; i < 3; ++i) {
-      bool c = false;
-      for (int j = 0; j < nc; ++j) c |= (ob[j] == i);
-      if (!c) ob[kb++] = i;
-    }
-    const double* T = tab[nc];
-    const int n = npts[nc];
+    const double* T = nc == 1 ? tab1 : (nc == 2 ? tab2 : tab3);
+    const int n = nc == 1 ? n1 : (nc == 2 ? n2 : n3);
     const double AA = 4.0 * a.area * b.area;
     for (int q = 0; q < n; ++q) {
       const double x1 = T[5 * q], x2 = T[5 * q + 1], y1 = T[5 * q + 2], y2 = T[5 * q + 3];
       const double w = T[5 * q + 4] * AA;
       double x[3], y[3];
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
-        x[d] = P1[oa[0]][d] + x1 * (P1[oa[1]][d] - P1[oa[0]][d]) + x2 * (P1[oa[2]][d] - P1[oa[1]][d]);
-        y[d] = P2[ob[0]][d] + y1 * (P2[ob[1]][d] - P2[ob[0]][d]) + y2 * (P2[ob[2]][d] - P2[ob[1]][d]);
+        x[d] = Q1[0][d] + x1 * (Q1[1][d] - Q1[0][d]) + x2 * (Q1[2][d] - Q1[1][d]);
+        y[d] = Q2[0][d] + y1 * (Q2[1][d] - Q2[0][d]) + y2 * (Q2[2][d] - Q2[1][d]);
       }
       const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
       const double r2 = dx * dx + dy * dy + dz * dz;
-      for (int k = 0; k < nk; ++k) {
-        KernelVal<double> kv = helmholtz<double>(r2, kr[k], ki[k], ki[k] != 0.0, w);
-        out[k].add(kv, x, y, withC);
-      }
+      out.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, withC);
     }
     return;
   }
-  const int cls = classify_pair(a.cen, b.cen, a.diam2, b.diam2);
+  const int cls = classify_pair(a.cen[0], a.cen[1], a.cen[2], b.cen[0], b.cen[1], b.cen[2], a.diam2, b.diam2);
   const int q = cls == 0 ? qn : (cls == 1 ? qm : qf);
   const int off = c_rule_off[q], n = c_rule_n[q];
   const double AA = a.area * b.area;
   for (int i = 0; i < n; ++i) {
     double x[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d)
       x[d] = c_rule_l[off + i][0] * P1[0][d] + c_rule_l[off + i][1] * P1[1][d] + c_rule_l[off + i][2] * P1[2][d];
     for (int j = 0; j < n; ++j) {
       double y[3];
+#pragma unroll
       for (int d = 0; d < 3; ++d)
         y[d] = c_rule_l[off + j][0] * P2[0][d] + c_rule_l[off + j][1] * P2[1][d] + c_rule_l[off + j][2] * P2[2][d];
       const double w = c_rule_w[off + i] * c_rule_w[off + j] * AA;
       const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
       const double r2 = dx * dx + dy * dy + dz * dz;
-      for (int k = 0; k < nk; ++k) {
-        KernelVal<double> kv = helmholtz<double>(r2, kr[k], ki[k], ki[k] != 0.0, w);
-        out[k].add(kv, x, y, withC);
-      }
+      out.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, withC);
     }
   }
 }
@@ -135,18 +137,10 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
   const int sc1 = c.cell_scat[v], sc2 = c.cell_scat[w];
   const bool do_int = j.want_int && sc1 == sc2;
   const bool do_ext = j.want_ext;
-  int nk = 0;
-  double kr[2] = {0, 0}, ki[2] = {0, 0};
-  if (do_int) {
-    kr[nk] = j.k_int[2 * sc1];
-    ki[nk] = j.k_int[2 * sc1 + 1];
-    ++nk;
-  }
-  if (do_ext) {
-    kr[nk] = j.k_ext;
-    ki[nk] = 0.0;
-    ++nk;
-  }
+  // wavenumber 0 is the interior one when present, else the exterior one
+  const int nk = int(do_int) + int(do_ext);
+  const double kr0 = do_int ? j.k_int[2 * sc1] : j.k_ext, ki0 = do_int ? j.k_int[2 * sc1 + 1] : 0.0;
+  const double kr1 = j.k_ext, ki1 = 0.0;
   const bool withC = j.want_C;
   for (int s = lane; s < nslot; s += 64)
     for (int q = 0; q < 8; ++q) s_acc[s][q] = 0.0;
@@ -160,13 +154,14 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     // ---- A: moments of every child pair of this chunk
     for (int p = lane; p < np; p += 64) {
       const int u1 = r0 + p / n2, u2 = p % n2;
-      SmallGeom ga, gb;
-      load_child(c, c.ring[b1 + u1], ga);
-      load_child(c, c.ring[b2 + u2], gb);
-      Moments<double> m[2];
-      pair_moments(ga, gb, j.tab, j.npts, j.q_near, j.q_medium, j.q_far, nk, kr, ki, withC, m);
+      const SmallGeom ga = load_child(c, c.ring[b1 + u1]);
+      const SmallGeom gb = load_child(c, c.ring[b2 + u2]);
       for (int k = 0; k < nk; ++k) {
-        const double* f = reinterpret_cast<const double*>(&m[k]);
+        Moments<double> m;
+        pair_moments(ga, gb, j.tab[1], j.tab[2], j.tab[3], j.npts[1], j.npts[2], j.npts[3], j.q_near, j.q_medium,
+                     j.q_far, k == 0 ? kr0 : kr1, k == 0 ? ki0 : ki1, withC, m);
+        const double* f = reinterpret_cast<const double*>(&m);
+#pragma unroll
         for (int q = 0; q < MOM_D; ++q) s_mom[(p * 2 + k) * MOM_D + q] = f[q];
       }
       if (u2 == 0)
@@ -180,6 +175,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
       const double* o = s_org[ur];
       for (int k = 0; k < nk; ++k) {
         double T[18];
+#pragma unroll
         for (int q = 0; q < 18; ++q) T[q] = 0.0;
         for (int u2 = 0; u2 < n2; ++u2) {
           const double* c2 = cw + 4 * (int64_t(sj) * n2 + u2);
@@ -190,6 +186,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
           // Ta
           T[0] += a2 * m.Mxy.re - (w2[0] * m.Mx[0].re + w2[1] * m.Mx[1].re + w2[2] * m.Mx[2].re);
           T[1] += a2 * m.Mxy.im - (w2[0] * m.Mx[0].im + w2[1] * m.Mx[1].im + w2[2] * m.Mx[2].im);
+#pragma unroll
           for (int d = 0; d < 3; ++d) {  // Tb
             T[2 + 2 * d] += w2[d] * m.M0.re - a2 * m.My[d].re;
             T[3 + 2 * d] += w2[d] * m.M0.im - a2 * m.My[d].im;
@@ -199,6 +196,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
           if (withC) {
             T[10] -= w2[0] * m.Nx[0].re + w2[1] * m.Nx[1].re + w2[2] * m.Nx[2].re;  // Tc
             T[11] -= w2[0] * m.Nx[0].im + w2[1] * m.Nx[1].im + w2[2] * m.Nx[2].im;
+#pragma unroll
             for (int d = 0; d < 3; ++d) {  // Te = a2 Nx - Nd x w2
               const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
               T[12 + 2 * d] += a2 * m.Nx[d].re - (m.Nd[d1].re * w2[d2] - m.Nd[d2].re * w2[d1]);
@@ -206,6 +204,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
             }
           }
         }
+#pragma unroll
         for (int q = 0; q < 18; ++q) s_half[hq][k].v[q] = T[q];
       }
     }
@@ -214,6 +213,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     for (int s = lane; s < nslot; s += 64) {
       const int si = s / N2, sj = s % N2;
       double acc[8];
+#pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] = s_acc[s][q];
       for (int k = 0; k < nk; ++k) {
         double sv_re = 0, sv_im = 0, sd_re = 0, sd_im = 0, cc_re = 0, cc_im = 0;
@@ -233,14 +233,18 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
           }
         }
         // S = -ik Sv - Sd/(ik) = (ki - i kr) Sv + i Sd conj(k)/|k|^2
-        const double k2 = kr[k] * kr[k] + ki[k] * ki[k];
-        const double t_re = (sd_re * kr[k] + sd_im * ki[k]) / k2, t_im = (sd_im * kr[k] - sd_re * ki[k]) / k2;
-        const int slot = (do_int && k == 0) ? 0 : 4;
-        acc[slot + 0] += ki[k] * sv_re + kr[k] * sv_im - t_im;
-        acc[slot + 1] += ki[k] * sv_im - kr[k] * sv_re + t_re;
-        acc[slot + 2] += cc_re;
-        acc[slot + 3] += cc_im;
+        const double krk = k == 0 ? kr0 : kr1, kik = k == 0 ? ki0 : ki1;
+        const double k2 = krk * krk + kik * kik;
+        const double t_re = (sd_re * krk + sd_im * kik) / k2, t_im = (sd_im * krk - sd_re * kik) / k2;
+        const double v[4] = {kik * sv_re + krk * sv_im - t_im, kik * sv_im - krk * sv_re + t_re, cc_re, cc_im};
+        const bool to_int = do_int && k == 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q] += to_int ? v[q] : 0.0;
+          acc[4 + q] += to_int ? 0.0 : v[q];
+        }
       }
+#pragma unroll
       for (int q = 0; q < 8; ++q) s_acc[s][q] = acc[q];
     }
   }

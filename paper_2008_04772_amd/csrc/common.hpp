@@ -196,6 +196,51 @@ __device__ __forceinline__ void contract(const Moments<R>& m, A a1, const A w1[3
   }
 }
 
+// Vertex order for a pair that shares nc >= 1 vertices: the shared vertices
+// first, in the test triangle's order, then the remaining ones in ascending
+// local order.  Returned as 2-bit local indices packed into oa / ob (slot v
+// at bits 2v), computed with static indexing only so that everything stays
+// in registers.
+__device__ __forceinline__ int shared_order(const int va[3], const int vb[3], int& oa, int& ob) {
+  int jb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    int jj = -1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) jj = (va[i] == vb[j]) ? j : jj;
+    jb[i] = jj;
+  }
+  int pos = 0;
+  oa = 0;
+  ob = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (jb[i] >= 0) {
+      oa |= i << (2 * pos);
+      ob |= jb[i] << (2 * pos);
+      ++pos;
+    }
+  const int nc = pos;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (jb[i] < 0) {
+      oa |= i << (2 * pos);
+      ++pos;
+    }
+  pos = nc;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const bool sh = (va[0] == vb[j]) || (va[1] == vb[j]) || (va[2] == vb[j]);
+    if (!sh) {
+      ob |= j << (2 * pos);
+      ++pos;
+    }
+  }
+  return nc;
+}
+
+__device__ __forceinline__ double pick3(const double v[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+
 template <typename T>
 __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+from mie import mie_efficiencies
 from gpu_common import note, rel_fro, make_ctx
 from oracle import pmchwt as opm
 
@@ -52,6 +53,30 @@ def test_three_cubes_parity_and_counter(P, kind):
     note(f"  R={st.iterations} matvecs={st.matvecs} err={rel_fro(x, xr):.2e}")
     assert rel_fro(x, xr) < 1e-8
     assert st.matvecs == opm.table1_matvecs(kind, 3, st.iterations, 200)
+
+
+def test_small_sphere_full_calderon(P):
+    """The small sphere case (320 triangles, 960 unknowns, k_e = 1), FP64 dense
+    A, full Calderon preconditioner P = A on the barycentric mesh with
+    q = (4, 3, 2) and 4^4 singular points, GMRES tol 1e-6: currents and cross
+    sections against the oracle's direct FP64 solve, Q_ext near Mie."""
+    note("small sphere, full Calderon P = A, k=1")
+    mesh = synth.icosphere(2)
+    ctx = make_ctx(P, [mesh], EPS, 1.0, qP=(4, 3, 2), nP=4, chi=-1.0, precond="A")
+    d, p = synth.single_wave()
+    x, st = ctx.solve(d, p, P.solver_opts(tol=1e-6, restart=200, max_iter=400))
+    pr = opm.Problem([mesh], EPS, 1.0)
+    pr.assemble_A()
+    xr = pr.solve_direct(pr.rhs(d, p))
+    se, ss = ctx.cross_sections(x, d, p)
+    se_r, ss_r = pr.cross_sections(xr, d, p)
+    qm = mie_efficiencies(1.0, np.sqrt(EPS))
+    note(f"  iters={st.iterations} matvecs={st.matvecs} err={rel_fro(x, xr):.2e} "
+         f"Q_ext {se[0] / np.pi:.8f} (oracle {se_r[0] / np.pi:.8f}, Mie {qm[0]:.8f})")
+    assert st.converged and st.iterations <= 12
+    assert rel_fro(x, xr) < 1e-5
+    assert abs(se[0] - se_r[0]) < 1e-5 * abs(se_r[0]) and abs(ss[0] - ss_r[0]) < 1e-5 * abs(ss_r[0])
+    assert abs(se[0] / np.pi - qm[0]) < 0.08 * qm[0]
 
 
 def test_mixed_precision_with_refinement(P):
