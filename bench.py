@@ -29,29 +29,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "element-pair quadratures/s + PMCHWT solves/s (mixed vs FP64); p50/p99 latency"
 EPS = 3.17 + 0.01j
-K_EXT = 5.0
 # algorithmic FP operations per point pair of the regular kernel: 22 shared
 # (d, r^2, x.y, x cross y) + 78 per wavenumber (kernel value and gradient
 # factor, 14 complex moment updates); transcendental calls count as one
 FLOP_SHARED, FLOP_PER_K = 22, 78
-PEAK = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector TFLOP/s
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector TFLOP/s (FP32 matrix cores: also 157.3)
 HBM_PEAK = 8000.0  # GB/s
+# HBM bytes per launch of the dense operator product on the sphere workload,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy
+# (profiles/gemv_pmchwt_sphere5120_hbm_counters.md); valid for that kernel
+# version only
+GEMV_TRAFFIC = {"sphere5120": 946.3e6}
+
+WORKLOADS = {
+    "sphere5120": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, 1 plane wave; "
+                  "A dense q=(4,3,2,6); P = S^i near field chi=2h, q=(1,1,1,1); GMRES(200) tol 1e-5",
+    "prism10368": "hexagonal ice prism d=1 l=2.5, 10368 triangles (31104 unknowns), k_e=8, eps_r=3.17+0.01i, "
+                  "128 RHS (64 directions x 2 polarisations); A dense q=(4,3,2,6) on the FP32 matrix cores; "
+                  "P = S^i near field chi=2h, q=(1,1,1,1); GMRES(200) tol 1e-5",
+}
 
 
-def workload():
+def workload(name):
     import synth
-    v, t = synth.icosphere(4)
+    if name == "sphere5120":
+        v, t = synth.icosphere(4)
+        d, p = synth.single_wave()
+        k = 5.0
+    else:
+        v, t = synth.hex_prism(12, 60)
+        d, p = synth.plane_wave_set(64, seed=3)
+        k = 8.0
     chi = 2.0 * synth.mean_edge_length(v, t)
-    d, p = synth.single_wave()
-    return v, t, chi, d, p
+    return v, t, chi, d, p, k
 
 
-def run(P, mesh, chi, dirs, pols, precision, steps, warmup):
+def run(P, mesh, chi, dirs, pols, k_ext, precision, steps, warmup):
     v, t = mesh
     lat, stats = [], None
     with P.Context(0) as ctx:
         ctx.add_scatterer(v, t, EPS)
-        ctx.set_wavenumber(K_EXT)
+        ctx.set_wavenumber(k_ext)
         oA = P.assembly_opts((4, 3, 2), 4, -1.0, P.MIXED if precision == "mixed" else P.FP64)
         oP = P.assembly_opts((1, 1, 1), 1, chi, P.MIXED if precision == "mixed" else P.FP64)
         so = P.solver_opts(tol=1e-5, restart=200, max_iter=2000, ir_max=2 if precision == "mixed" else 0)
@@ -74,14 +92,14 @@ def run(P, mesh, chi, dirs, pols, precision, steps, warmup):
     return lat, profs, stats, float(se[0]), float(ss[0])
 
 
-def cpu_baseline(mesh, budget_s=15.0):
+def cpu_baseline(mesh, k_ext, budget_s=15.0):
     """The oracle, single-threaded, on a seeded sample of the workload's ordered triangle pairs."""
     from threadpoolctl import threadpool_limits
     from oracle.mesh import Topology
     from oracle import operators as ops
     T = Topology(*mesh)
     rng = np.random.default_rng(11)
-    k_i = K_EXT * np.sqrt(EPS)
+    k_i = k_ext * np.sqrt(EPS)
     done, t_used, n_pairs = 0, 0.0, 0
     with threadpool_limits(1):
         geom = ops._tri_geom(T)
@@ -92,13 +110,13 @@ def cpu_baseline(mesh, budget_s=15.0):
             t0 = time.perf_counter()
             for c in np.unique(rel):
                 s = rel == c
-                for k in (K_EXT, k_i):
+                for k in (k_ext, k_i):
                     ops.local_blocks(T, t1[s], t2[s], int(c), k)
             t_used += time.perf_counter() - t0
             done += 2 * len(t1)
             n_pairs += len(t1)
     return {"value": done / t_used, "unit": "element-pair quadratures/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_pairs} seeded random ordered triangle pairs of the 5120-triangle sphere, both "
+            "sample": f"{n_pairs} seeded random ordered triangle pairs of the workload mesh ({T.F} triangles), both "
                       f"wavenumbers, q = (4,3,2) and 4^4 Sauter-Schwab points, {t_used:.1f} s"}
 
 
@@ -136,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sphere5120",
+                    help="sphere5120: the benchmark workload; prism10368: the 128-RHS workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -144,41 +164,48 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import paper_2008_04772_amd as P
-    v, t, chi, dirs, pols = workload()
+    v, t, chi, dirs, pols, k_ext = workload(args.workload)
     results = {}
     for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
-        results[prec] = run(P, (v, t), chi, dirs, pols, prec, args.steps, args.warmup)
+        results[prec] = run(P, (v, t), chi, dirs, pols, k_ext, prec, args.steps, args.warmup)
     head = "mixed" if "mixed" in results else "fp64"
     lat, profs, st, se, ss = results[head]
     pr = profs[-1]
     quads = 2 * (pr["regular_pairs"] + pr["singular_pairs"]) + pr["bary_pairs"]
     ms = 1e3 * statistics.mean(lat)
     value = quads / (ms / 1e3)
-    # dominant kernel: the regular-pair assembly kernel or the dense operator application
-    reg_ms = statistics.mean(p["ms_assemble_regular"] for p in profs) / max(1, pr["regular_launches"])
-    mv_ms_total = statistics.mean(p["ms_matvec_total"] for p in profs)
+    # dominant kernel: the regular-pair assembly kernel, the dense operator
+    # GEMV or the matrix-core product, by total time per step
+    reg_total = statistics.mean(p["ms_assemble_regular"] for p in profs)
+    gemv_total = statistics.mean(p["ms_matvec_total"] - p["ms_mfma_total"] for p in profs)
+    mfma_total = statistics.mean(p["ms_mfma_total"] for p in profs)
     dtype_reg = "fp32" if head == "mixed" else "fp64"
-    if reg_ms * pr["regular_launches"] >= mv_ms_total:
+    dom = max((reg_total, "reg"), (gemv_total, "gemv"), (mfma_total, "mfma"))[1]
+    if dom == "reg":
         flops = (pr["regular_point_pairs"] / 2) * (FLOP_SHARED + 2 * FLOP_PER_K) / pr["regular_launches"]
-        ach = flops / (reg_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_regular", "bound": "alu", "achieved": ach, "peak": PEAK[dtype_reg],
+        ach = flops / (reg_total / pr["regular_launches"] * 1e-3) / 1e12
+        roof = {"kernel": "k_regular_rows", "bound": "alu", "achieved": ach, "peak": PEAK[dtype_reg],
                 "unit": "TFLOP/s", "frac": ach / PEAK[dtype_reg], "traffic": None}
-    else:
+    elif dom == "gemv":
         per = statistics.mean(p["ms_matvec_total"] / max(1, p["matvec_launches"]) for p in profs)
         byt = pr["matvec_bytes"] / max(1, pr["matvec_launches"])
         ach = byt / (per * 1e-3) / 1e9
+        traffic = GEMV_TRAFFIC.get(args.workload) if head == "mixed" else None
         roof = {"kernel": "k_gemv_pmchwt", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": ach / HBM_PEAK, "traffic": None}
+                "frac": ach / HBM_PEAK, "traffic": traffic}
+    else:
+        fl = statistics.mean(p["mfma_flops"] for p in profs)
+        ach = fl / (mfma_total * 1e-3) / 1e12
+        roof = {"kernel": "k_mfma_pmchwt", "bound": "mfma", "achieved": ach, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["fp32"], "traffic": None}
     out = {
         "metric": METRIC, "value": value, "unit": "element-pair quadratures/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32+fp64" if head == "mixed" else "fp64", "data": "synthetic",
-        "config": {"workload": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, "
-                               "1 plane wave; A dense q=(4,3,2,6); P = S^i near field chi=2h, q=(1,1,1,1); "
-                               "GMRES(200) tol 1e-5",
-                   "triangles": 5120, "unknowns": 15360, "n_rhs": 1},
-        "solves_per_s": 1e3 / ms,
+        "config": {"workload": WORKLOADS[args.workload], "triangles": int(len(t)), "unknowns": int(3 * len(t)),
+                   "n_rhs": int(len(dirs))},
+        "solves_per_s": len(dirs) * 1e3 / ms,
         "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
         "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
         "quadratures_per_step": quads,
@@ -186,7 +213,7 @@ def main():
         "assembly_ms": {"A": pr["ms_assemble_A"], "regular": pr["ms_assemble_regular"],
                         "singular": pr["ms_assemble_singular"], "P": pr["ms_assemble_P"], "mass": pr["ms_mass"]},
         "solve_ms": st.ms_solve,
-        "Q_ext": se / np.pi, "Q_sca": ss / np.pi,
+        "sigma_ext_rhs0": se, "sigma_sca_rhs0": ss,
         "roofline": roof,
     }
     if "fp64" in results and head == "mixed":
@@ -194,10 +221,10 @@ def main():
         out["fp64"] = {"ms_per_step": 1e3 * statistics.mean(l64),
                        "quadratures_per_s": quads / statistics.mean(l64),
                        "assembly_regular_ms": results["fp64"][1][-1]["ms_assemble_regular"],
-                       "Q_ext": results["fp64"][3] / np.pi}
+                       "sigma_ext_rhs0": results["fp64"][3]}
         out["mixed_speedup"] = statistics.mean(l64) / statistics.mean(lat)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline((v, t))
+        out["cpu_baseline"] = cpu_baseline((v, t), k_ext)
     if args.copy_calibration:
         copy_calibration()
     print(json.dumps(out), flush=True)

@@ -153,6 +153,9 @@ typedef struct {
   double ms_matvec_total;    /* dense operator application kernels during the solve     */
   int64_t matvec_launches;
   int64_t matvec_bytes;      /* algorithmic operator bytes read by those launches       */
+  double ms_mfma_total;      /* many-RHS operator products on the matrix cores          */
+  int64_t mfma_launches;
+  int64_t mfma_flops;        /* real flops of those GEMMs (8 per complex MAC)           */
 } pmchwt_profile;
 
 /* Version string of the library. */

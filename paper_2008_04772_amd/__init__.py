@@ -64,7 +64,9 @@ class pmchwt_profile(ctypes.Structure):
                 ("n_wavenumbers", ctypes.c_int32), ("recompute", ctypes.c_double),
                 ("wall_setup", ctypes.c_double), ("wall_A", ctypes.c_double), ("wall_P", ctypes.c_double),
                 ("wall_mass", ctypes.c_double), ("ms_matvec_total", ctypes.c_double),
-                ("matvec_launches", ctypes.c_int64), ("matvec_bytes", ctypes.c_int64)]
+                ("matvec_launches", ctypes.c_int64), ("matvec_bytes", ctypes.c_int64),
+                ("ms_mfma_total", ctypes.c_double), ("mfma_launches", ctypes.c_int64),
+                ("mfma_flops", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p

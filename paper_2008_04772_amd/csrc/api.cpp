@@ -116,8 +116,9 @@ struct pmchwt_ctx {
   double k_ext = 0.0;
   std::vector<Scat> sc;
   int F_tot = 0, E_tot = 0, nv_tot = 0;
-  // leading dimensions of the dense operators, padded to a multiple of 4
-  // entries so that rows start on 16/32-byte boundaries for vector loads
+  // leading dimensions of the dense operators, padded to a multiple of 16
+  // entries: rows start on 128/256-byte boundaries for vector loads, and the
+  // real K of the matrix-core product is a multiple of its 32-wide K tile
   int64_t ldE = 0;
   std::vector<int64_t> ldI;
   bool geo_uploaded = false;
@@ -138,11 +139,17 @@ struct pmchwt_ctx {
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_col;
   // mass / Gram
-  std::vector<DBuf> MA, Minv, MinvT, Glu, Gpiv;
+  std::vector<DBuf> MA, Minv, MinvT;
+  // RWG Gram matrix (5 nonzeros per row), CSR over union edges with
+  // scatterer-local column indices; pattern and slot map built once per geometry
+  bool gram_valid = false;
+  DBuf g_rowptr, g_col, g_pos, g_val;
   bool mass_f32 = false;  // Minv / MinvT stored in FP32 (preconditioner assembled with MIXED precision)
   // work vectors
   DBuf work;
   size_t work_bytes = 0;
+  DBuf mfma_ws;  // expanded right-hand blocks of the matrix-core product
+  size_t mfma_ws_bytes = 0;
   pmchwt_profile prof{};
   int64_t count_key = -1, count_pairs = 0, count_pts = 0;
   int64_t calls_A = 0, calls_P = 0;  // operator applications (batched calls) since the last reset
@@ -183,7 +190,14 @@ struct pmchwt_ctx {
 
 namespace {
 
-int64_t padld(int64_t n) { return (n + 3) & ~int64_t(3); }
+int64_t padld(int64_t n) { return (n + 15) & ~int64_t(15); }
+
+// leading dimension of the inverted mass matrices: a multiple of 32, the K
+// tile of the matrix-core product
+int64_t ldmass(int64_t n) { return (n + 31) & ~int64_t(31); }
+
+// right-hand sides from which FP32 operators are applied on the matrix cores
+constexpr int MFMA_MIN_RHS = 16;
 
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -1171,13 +1185,49 @@ void gj_inverse(pmchwt_ctx* c, double* X, int n) {
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
+// RWG Gram pattern: row i holds edge i and the other edges of its two
+// triangles (sorted, scatterer-local columns); g_pos maps local pair (a, b)
+// of every triangle to its CSR slot.
+void build_gram_pattern(pmchwt_ctx* c) {
+  std::vector<int64_t> rowptr(size_t(c->E_tot) + 1, 0), pos(9 * size_t(c->F_tot));
+  std::vector<int32_t> col;
+  for (const Scat& s : c->sc) {
+    const Topo& T = s.topo;
+    for (int e = 0; e < T.E; ++e) {
+      std::vector<int32_t> nb;
+      for (int tt : {T.tplus[e], T.tminus[e]})
+        for (int a = 0; a < 3; ++a) nb.push_back(T.t2e[3 * size_t(tt) + a]);
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      col.insert(col.end(), nb.begin(), nb.end());
+      rowptr[size_t(s.edge_off) + e + 1] = int64_t(col.size());
+    }
+  }
+  for (const Scat& s : c->sc) {
+    const Topo& T = s.topo;
+    for (int f = 0; f < T.F; ++f)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const int i = s.edge_off + T.t2e[3 * size_t(f) + a], jl = T.t2e[3 * size_t(f) + b];
+          auto beg = col.begin() + rowptr[i], end = col.begin() + rowptr[i + 1];
+          auto it = std::lower_bound(beg, end, jl);
+          if (it == end || *it != jl) throw Fail{PMCHWT_ERR_INVALID_MESH, "Gram pattern inconsistent with topology"};
+          pos[9 * size_t(s.tri_off + f) + 3 * a + b] = int64_t(it - col.begin());
+        }
+  }
+  c->g_rowptr = upload(c, rowptr);
+  c->g_col = upload(c, col);
+  c->g_pos = upload(c, pos);
+  c->g_val = dalloc<double>(col.size());
+  c->gram_valid = true;
+}
+
 void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   EvTimer t(c->stream);
   c->MA.clear();
   c->Minv.clear();
   c->MinvT.clear();
-  c->Glu.clear();
-  c->Gpiv.clear();
+  if (!c->gram_valid) build_gram_pattern(c);
   std::vector<int64_t> off, ld;
   int64_t tot = 0;
   for (auto& s : c->sc) {
@@ -1186,9 +1236,9 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     tot += int64_t(s.topo.E) * s.topo.E;
   }
   DBuf d_off = upload(c, off), d_ld = upload(c, ld);
-  DBuf mass = dalloc<double>(size_t(tot)), gram = dalloc<double>(size_t(tot));
+  DBuf mass = dalloc<double>(size_t(tot));
   launch_zero(mass.as<double>(), tot, c->stream);
-  launch_zero(gram.as<double>(), tot, c->stream);
+  launch_zero(c->g_val.as<double>(), int64_t(c->g_val.bytes / 8), c->stream);
   MassJob mj{};
   mj.nchild = cells.nchild;
   mj.child_cell = cells.child_cell.as<int32_t>();
@@ -1201,25 +1251,25 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   mj.mat_off = d_off.as<int64_t>();
   mj.ld = d_ld.as<int64_t>();
   mj.out = mass.as<double>();
+  mj.gram_pos = c->g_pos.as<int64_t>();
+  mj.gram_val = c->g_val.as<double>();
   AsmParams<double> g = asm_params<double>(c);
   launch_mass(g, cells.params(), mj, c->stream);
-  mj.out = gram.as<double>();
   launch_gram(g, mj, c->stream);
   HIPCHK(hipGetLastError());
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const int n = c->sc[m].topo.E;
     const size_t nn = size_t(n) * n;
-    DBuf MA = dalloc<double>(nn), Mi = dalloc<double>(nn), MiT = dalloc<double>(nn), G = dalloc<double>(nn);
+    DBuf MA = dalloc<double>(nn), Mi = dalloc<double>(nn), MiT = dalloc<double>(nn);
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(G.p, gram.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     // row-major M_A is column-major M_A^T; inverting it in place yields the
     // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
     gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
     c->MA.push_back(std::move(MA));
     // padded copies for the vector loads of the application kernel
-    const int64_t ldm = padld(n);
+    const int64_t ldm = ldmass(n);
     if (c->mass_f32) {
       DBuf Mf = dalloc<float>(size_t(n) * ldm), MfT = dalloc<float>(size_t(n) * ldm);
       launch_repack(Mi.as<double>(), n, Mf.as<float>(), ldm, c->stream);
@@ -1235,7 +1285,6 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
       c->Minv.push_back(std::move(Md));
       c->MinvT.push_back(std::move(MdT));
     }
-    c->Glu.push_back(std::move(G));
   }
   HIPCHK(hipGetLastError());
   c->prof.ms_mass = t.stop();
@@ -1272,6 +1321,18 @@ int64_t P_matvecs(const pmchwt_ctx* c) {
   }
 }
 
+// workspace of the matrix-core products: two expanded right-hand blocks of
+// 4 nrhs x 2 ldE floats (enough for the mass-inverse product as well)
+float* mfma_ws(pmchwt_ctx* c, int nrhs) {
+  const size_t need = size_t(2) * 4 * nrhs * 2 * size_t(std::max<int64_t>(c->ldE, ldmass(c->E_tot))) * sizeof(float);
+  if (c->mfma_ws_bytes < need) {
+    c->mfma_ws = DBuf();
+    c->mfma_ws = dalloc<float>(need / sizeof(float));
+    c->mfma_ws_bytes = need;
+  }
+  return c->mfma_ws.as<float>();
+}
+
 // y = A x (y overwritten)
 void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -1288,6 +1349,27 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
                                  s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
                                  vs, c->stream);
     }
+  } else if (nrhs >= MFMA_MIN_RHS) {
+    float* B1 = mfma_ws(c, nrhs);
+    float* B2 = B1 + size_t(4) * nrhs * 2 * size_t(c->ldE);
+    EvTimer tm(c->stream);
+    launch_mfma_pmchwt(c->Se.as<float>(), c->Ce.as<float>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E, y,
+                       y + 2 * E, nrhs, vs, B1, B2, c->stream);
+    int64_t flops = 32 * E * c->ldE * nrhs;
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_mfma_pmchwt(c->Si[m].as<float>(), c->Ci[m].as<float>(), c->ldI[m], s.topo.E, s.topo.E, s.k.real(),
+                         s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs, B1, B2,
+                         c->stream);
+      flops += 32 * int64_t(s.topo.E) * c->ldI[m] * nrhs;
+    }
+    HIPCHK(hipGetLastError());
+    c->prof.ms_mfma_total += tm.stop();
+    c->prof.mfma_launches += 1 + int64_t(c->sc.size());
+    c->prof.mfma_flops += flops;
+    c->prof.ms_matvec_total += t.stop();
+    return;
   } else {
     launch_gemv_pmchwt<float>(c->Se.as<float>(), c->Ce.as<float>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
                               y, y + 2 * E, nrhs, vs, c->stream);
@@ -1315,14 +1397,19 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     return;
   }
   c->calls_P += 1;
+  const bool mm = c->mass_f32 && nrhs >= MFMA_MIN_RHS;
+  float* Bw = mm ? mfma_ws(c, nrhs) : nullptr;
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    if (c->mass_f32)
-      launch_gemv_real2(c->Minv[m].as<float>(), padld(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
+    if (mm)
+      launch_mfma_real2(c->Minv[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
+                        nrhs, vs, E, Bw, c->stream);
+    else if (c->mass_f32)
+      launch_gemv_real2(c->Minv[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, c->stream);
     else
-      launch_gemv_real2(c->Minv[m].as<double>(), padld(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
+      launch_gemv_real2(c->Minv[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, c->stream);
   }
   launch_zero(t2, 2 * vs * nrhs, c->stream);
@@ -1343,11 +1430,14 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
-    if (c->mass_f32)
-      launch_gemv_real2(c->MinvT[m].as<float>(), padld(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
+    if (mm)
+      launch_mfma_real2(c->MinvT[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
+                        nrhs, vs, E, Bw, c->stream);
+    else if (c->mass_f32)
+      launch_gemv_real2(c->MinvT[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
                         nrhs, vs, E, c->stream);
     else
-      launch_gemv_real2(c->MinvT[m].as<double>(), padld(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
+      launch_gemv_real2(c->MinvT[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
                         nrhs, vs, E, c->stream);
   }
   HIPCHK(hipGetLastError());
@@ -1381,7 +1471,10 @@ void to_api(const pmchwt_ctx* c, const std::vector<double>& in, int nrhs, pmchwt
 
 // Solve G x_q = b_q for nvec complex vectors (length n, stride `stride`
 // complex) by conjugate gradients; G real symmetric positive definite, dense.
-void gram_cg(pmchwt_ctx* c, const double* G, int n, const double* b_in, double* x_out, int64_t in_stride, int nvec) {
+// x = G^-1 b for the rows [0, n) of one scatterer; rowptr points at its first
+// row (absolute offsets into col / val)
+void gram_cg(pmchwt_ctx* c, const int64_t* rowptr, int n, const double* b_in, double* x_out, int64_t in_stride,
+             int nvec) {
   // work on packed copies: vector q at q * n
   const int64_t stride = n;
   const size_t nd = 2 * size_t(stride) * nvec;
@@ -1408,7 +1501,8 @@ void gram_cg(pmchwt_ctx* c, const double* G, int n, const double* b_in, double* 
     bool done = true;
     for (int k = 0; k < nvec; ++k) done &= (rr[k] <= 1e-28 * rr0[k]);
     if (done) break;
-    launch_gemv_real(G, n, n, n, 1.0, p.as<double>(), q.as<double>(), nvec, stride, c->stream);
+    launch_spmv_real(rowptr, c->g_col.as<int32_t>(), c->g_val.as<double>(), n, p.as<double>(), q.as<double>(), nvec,
+                     stride, c->stream);
     launch_dots(p.as<double>(), 0, 1, q.as<double>(), stride, n, act.as<int32_t>(), nvec, stride, d, c->stream);
     HIPCHK(hipMemcpyAsync(pq.data(), d, 16 * nvec, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1465,7 +1559,7 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
     const Scat& s = c->sc[m];
     const int n = s.topo.E;
     const int nvec = 2 * nrhs;
-    gram_cg(c, c->Glu[m].as<double>(), n, h.as<double>() + 2 * int64_t(s.edge_off),
+    gram_cg(c, c->g_rowptr.as<int64_t>() + s.edge_off, n, h.as<double>() + 2 * int64_t(s.edge_off),
             cinc.as<double>() + 2 * int64_t(s.edge_off), E, nvec);
   }
   // b = g/2 - A^i c_inc
@@ -1752,6 +1846,7 @@ int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const i
     c->nf.valid = false;
     c->sing.n = -1;
     c->cells_valid = false;
+    c->gram_valid = false;
     c->slabs.clear();
     if (id) *id = int32_t(c->sc.size() - 1);
     return PMCHWT_OK;

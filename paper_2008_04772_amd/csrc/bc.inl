@@ -371,9 +371,9 @@ __global__ void k_gram(AsmParams<double> g, MassJob j) {
     for (int d = 0; d < 3; ++d) dot += (x[d] - P[a][d]) * (x[d] - P[b][d]);
     acc += dot / 3.0;
   }
-  const int sc = g.tscat[T];
-  const int i = g.t2e[a * F + T] - j.edge_off[sc], jj = g.t2e[b * F + T] - j.edge_off[sc];
-  atomic_add(&j.out[j.mat_off[sc] + int64_t(i) * j.ld[sc] + jj], acc * A * sa * sb);
+  // an off-diagonal entry has one contribution, a diagonal one two (whose
+  // sum does not depend on their order)
+  atomic_add(&j.gram_val[j.gram_pos[tid]], acc * A * sa * sb);
 }
 
 void launch_gram(const AsmParams<double>& geo, const MassJob& j, hipStream_t st) {

@@ -4,3 +4,4 @@
 #include "assembly.inl"
 #include "bc.inl"
 #include "linalg.inl"
+#include "mfma.inl"

@@ -110,6 +110,8 @@ struct MassJob {
   const int64_t* mat_off;      // per scatterer offset (elements) into mass storage
   const int64_t* ld;           // per scatterer E_m
   double* out;                 // dense FP64 matrices, row-major
+  const int64_t* gram_pos;     // RWG Gram: CSR position of local pair (a, b) of triangle t at 9 t + 3 a + b
+  double* gram_val;            // RWG Gram CSR values
 };
 
 struct RhsJob {
@@ -148,6 +150,17 @@ template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs,
                         int64_t vstride, hipStream_t st);
+// Many right-hand sides on the FP32 matrix cores: same product as
+// launch_gemv_pmchwt for FP32 operators with ld a multiple of 16; B1, B2 are
+// workspaces of 4 nrhs x 2 ld floats each.
+void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, int cols, double kr, double ki,
+                        const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
+                        float* B1, float* B2, hipStream_t st);
+// y = alpha M x for a real FP32 matrix (ld a multiple of 32, zero padding
+// columns) on both trace components, on the matrix cores; B is a workspace
+// of 4 nrhs x ld floats.
+void launch_mfma_real2(const float* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+                       int nrhs, int64_t vstride, int64_t cstride, float* B, hipStream_t st);
 // Same with a CSR pattern (rowptr, col) and value arrays S, C (either may be
 // null: treated as zero).
 template <typename M>
@@ -157,6 +170,10 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
 // y = alpha * Mreal x (dense real row-major, rows x cols), complex vectors
 void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
+// y_q = M x_q for a real CSR matrix (rowptr absolute into col / val) and nvec
+// complex vectors at stride vstride
+void launch_spmv_real(const int64_t* rowptr, const int32_t* col, const double* val, int rows, const double* x,
+                      double* y, int nvec, int64_t vstride, hipStream_t st);
 void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // y = alpha M x for both trace components (second component at +cstride);
 // M is double or float (accumulation in double); ld a multiple of 4 with

@@ -693,6 +693,30 @@ template void launch_gemv_real2<double>(const double*, int64_t, int, int, double
 template void launch_gemv_real2<float>(const float*, int64_t, int, int, double, const double*, double*, int, int64_t,
                                        int64_t, hipStream_t);
 
+__global__ void k_spmv_real(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, int rows, const double* __restrict__ x, double* y,
+                            int64_t vstride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= rows) return;
+  const double* xq = x + 2 * int64_t(q) * vstride;
+  double re = 0.0, im = 0.0;
+  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const double v = val[p];
+    const int jx = col[p];
+    re += v * xq[2 * jx];
+    im += v * xq[2 * jx + 1];
+  }
+  y[2 * (int64_t(q) * vstride + i)] = re;
+  y[2 * (int64_t(q) * vstride + i) + 1] = im;
+}
+
+void launch_spmv_real(const int64_t* rowptr, const int32_t* col, const double* val, int rows, const double* x,
+                      double* y, int nvec, int64_t vstride, hipStream_t st) {
+  hipLaunchKernelGGL(k_spmv_real, dim3(unsigned((rows + 255) / 256), unsigned(nvec)), dim3(256), 0, st, rowptr, col,
+                     val, rows, x, y, vstride);
+}
+
 // out[i * ldo + j] = in[i * n + j] (j < n), 0 for n <= j < ldo
 template <typename T>
 __global__ void k_repack(const double* in, int n, T* out, int64_t ldo) {

@@ -1,0 +1,218 @@
+// PMCHWT operator product for many right-hand sides on the FP32 matrix cores
+// (the block product of Section 3.2 applied to all incident fields at once).
+//
+// For one medium,  [Y_D | Y_N] = C [X_D | X_N] + S [X_N / k | -k X_D]
+// (Y_D = C X_D + (1/k) S X_N,  Y_N = -k S X_D + C X_N).
+// The complex product is one real GEMM: an operator stored as interleaved
+// (re, im) FP32 pairs is read as a real matrix Ahat (rows x 2 ld), and every
+// complex entry b of the right-hand block becomes the real 2 x 2 block
+// [[Re b, Im b], [-Im b, Re b]] of Bhat, so that column 2c of Ahat Bhat is
+// Re(A b_c) and column 2c + 1 is Im(A b_c) -- the interleaved complex result,
+// at the flop count of the complex product (8 real flops per complex MAC).
+// Bhat is stored transposed (real columns x K, K contiguous) so that both
+// operands stream along K.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pmchwt {
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef float mf16 __attribute__((ext_vector_type(16)));
+
+constexpr int MF_BM = 128, MF_BN = 128, MF_BK = 32, MF_LDK = MF_BK + 4;
+
+// Bhat^T for C (B1) and S (B2): real row 2c / 2c+1 for complex column c of
+// the right-hand block (c < n: D part of rhs c, else N part of rhs c - n);
+// real column 2k / 2k+1 for complex row k (zero for k >= E).
+__global__ void k_mfma_rhs(const double* __restrict__ xD, const double* __restrict__ xN, int64_t vstride, int E,
+                           int Kt, int nrhs, double kr, double ki, float* __restrict__ B1, float* __restrict__ B2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // complex row
+  const int c = blockIdx.y;                             // complex column
+  if (2 * k >= Kt) return;
+  double b1r = 0, b1i = 0, b2r = 0, b2i = 0;
+  if (k < E) {
+    const double k2 = kr * kr + ki * ki;
+    const double ikr = kr / k2, iki = -ki / k2;  // 1/k
+    if (c < nrhs) {
+      const double* d = xD + 2 * (int64_t(c) * vstride + k);
+      const double* n = xN + 2 * (int64_t(c) * vstride + k);
+      b1r = d[0];
+      b1i = d[1];
+      b2r = n[0] * ikr - n[1] * iki;  // xN / k
+      b2i = n[0] * iki + n[1] * ikr;
+    } else {
+      const double* d = xD + 2 * (int64_t(c - nrhs) * vstride + k);
+      const double* n = xN + 2 * (int64_t(c - nrhs) * vstride + k);
+      b1r = n[0];
+      b1i = n[1];
+      b2r = -(kr * d[0] - ki * d[1]);  // -k xD
+      b2i = -(kr * d[1] + ki * d[0]);
+    }
+  }
+  const int64_t r0 = int64_t(2 * c) * Kt + 2 * k, r1 = r0 + Kt;
+  B1[r0] = float(b1r);
+  B1[r0 + 1] = float(-b1i);
+  B1[r1] = float(b1i);
+  B1[r1 + 1] = float(b1r);
+  B2[r0] = float(b2r);
+  B2[r0 + 1] = float(-b2i);
+  B2[r1] = float(b2i);
+  B2[r1 + 1] = float(b2r);
+}
+
+// Output mappings of the real GEMM columns.
+// PMCHWT product: real column n -> complex column c = n/2, part n%2;
+// c < nrhs -> yD of rhs c, else yN of rhs c - nrhs; added to y.
+struct PmchwtOut {
+  double* yD;
+  double* yN;
+  int64_t vstride;
+  int nrhs;
+  __device__ __forceinline__ void put(int r, int n, float v) const {
+    const int cc = n >> 1, part = n & 1;
+    double* base = cc < nrhs ? yD + 2 * int64_t(cc) * vstride : yN + 2 * int64_t(cc - nrhs) * vstride;
+    base[2 * int64_t(r) + part] += double(v);
+  }
+};
+// Real matrix on complex vectors of two trace components: real column n ->
+// rhs n/4, component (n/2)%2 (second at +cstride), part n%2; y = alpha M x.
+struct Real2Out {
+  double* y;
+  int64_t vstride, cstride;
+  double alpha;
+  __device__ __forceinline__ void put(int r, int n, float v) const {
+    const int q = n >> 2, comp = (n >> 1) & 1, part = n & 1;
+    y[2 * (int64_t(q) * vstride + comp * cstride + r) + part] = alpha * double(v);
+  }
+};
+
+// out(rows x Nr) = A1 B1^T (K1) + A2 B2^T (K2), K1 and K2 multiples of 32
+// (K2 = 0 for a single product); B rows have stride K.
+// Workgroup tile 128 x 128, four wavefronts of 64 x 64 = 2 x 2 MFMA 32x32x2
+// tiles; K tiles of 32 double-buffered in LDS (rows padded to 36 floats),
+// the next tile prefetched into registers during the MFMAs.  Each lane feeds
+// the MFMA k-slot (lane / 32) with k = 16 (lane / 32) + step, the same
+// permutation of k for both operands, so its 16 values per tile are
+// contiguous in LDS.
+template <typename Out>
+__global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ A1, const float* __restrict__ B1,
+                                                      int K1, int64_t lda1, const float* __restrict__ A2,
+                                                      const float* __restrict__ B2, int K2, int64_t lda2, int rows,
+                                                      int Nr, Out out) {
+  __shared__ float As[2][MF_BM * MF_LDK];
+  __shared__ float Bs[2][MF_BN * MF_LDK];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * MF_BM, n0 = blockIdx.x * MF_BN;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  mf16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = mf16{};
+  const int lr = t >> 3, lc = (t & 7) * 4;
+  const int nt1 = K1 / MF_BK, nt = nt1 + K2 / MF_BK;
+  mf4 ra[4], rb[4];
+  auto gload = [&](int kt) {
+    const bool first = kt < nt1;
+    const float* A = first ? A1 : A2;
+    const float* B = first ? B1 : B2;
+    const int64_t la = first ? lda1 : lda2;
+    const int kb = first ? K1 : K2;
+    const int k0 = (first ? kt : kt - nt1) * MF_BK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = min(m0 + lr + 32 * q, rows - 1), c = min(n0 + lr + 32 * q, Nr - 1);
+      ra[q] = __builtin_nontemporal_load(reinterpret_cast<const mf4*>(A + int64_t(r) * la + k0 + lc));
+      rb[q] = *reinterpret_cast<const mf4*>(B + int64_t(c) * kb + k0 + lc);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<mf4*>(&As[buf][(lr + 32 * q) * MF_LDK + lc]) = ra[q];
+      *reinterpret_cast<mf4*>(&Bs[buf][(lr + 32 * q) * MF_LDK + lc]) = rb[q];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  for (int kt = 0; kt < nt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nt) gload(kt + 1);
+    float af[2][16], bf[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const mf4 a = *reinterpret_cast<const mf4*>(&As[buf][(wr + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        const mf4 b = *reinterpret_cast<const mf4*>(&Bs[buf][(wc + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        af[i][4 * q] = a.x;
+        af[i][4 * q + 1] = a.y;
+        af[i][4 * q + 2] = a.z;
+        af[i][4 * q + 3] = a.w;
+        bf[i][4 * q] = b.x;
+        bf[i][4 * q + 1] = b.y;
+        bf[i][4 * q + 2] = b.z;
+        bf[i][4 * q + 3] = b.w;
+      }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][kk], bf[j][kk], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nt) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: 32x32 accumulator element e of lane l is row 8 (e/4) + 4 (l/32) + e%4, column l%32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wc + 32 * j + l32;
+      if (n >= Nr) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = m0 + wr + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (r < rows) out.put(r, n, acc[i][j][e]);
+      }
+    }
+}
+
+// Xhat^T for a real matrix: row n = (rhs n/4, component (n/2)%2, part n%2),
+// column k < E the value, zero up to Kt.
+__global__ void k_mfma_rhs_real(const double* __restrict__ x, int64_t vstride, int64_t cstride, int E, int Kt,
+                                int nrhs, float* __restrict__ B) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (k >= Kt) return;
+  const int q = n >> 2, comp = (n >> 1) & 1, part = n & 1;
+  B[int64_t(n) * Kt + k] = k < E ? float(x[2 * (int64_t(q) * vstride + comp * cstride + k) + part]) : 0.0f;
+}
+
+void launch_mfma_real2(const float* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
+                       int nrhs, int64_t vstride, int64_t cstride, float* B, hipStream_t st) {
+  const int Kt = int(ld);  // a multiple of 32
+  const int Nr = 4 * nrhs;
+  hipLaunchKernelGGL(k_mfma_rhs_real, dim3(unsigned((Kt + 255) / 256), unsigned(Nr)), dim3(256), 0, st, x, vstride,
+                     cstride, cols, Kt, nrhs, B);
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
+  hipLaunchKernelGGL((k_mfma_gemm<Real2Out>), grid, dim3(256), 0, st, Mat, B, Kt, ld, Mat, B, 0, ld, rows, Nr,
+                     Real2Out{y, vstride, cstride, alpha});
+}
+
+void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, int cols, double kr, double ki,
+                        const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
+                        float* B1, float* B2, hipStream_t st) {
+  const int Kt = int(2 * ld);  // real K per operand (ld is a multiple of 16)
+  const int Nr = 4 * nrhs;     // real columns
+  hipLaunchKernelGGL(k_mfma_rhs, dim3(unsigned((Kt / 2 + 255) / 256), unsigned(2 * nrhs)), dim3(256), 0, st, xD, xN,
+                     vstride, cols, Kt, nrhs, kr, ki, B1, B2);
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
+  hipLaunchKernelGGL((k_mfma_gemm<PmchwtOut>), grid, dim3(256), 0, st, C, B1, Kt, 2 * ld, S, B2, Kt, 2 * ld, rows, Nr,
+                     PmchwtOut{yD, yN, vstride, nrhs});
+}
+
+}  // namespace pmchwt
