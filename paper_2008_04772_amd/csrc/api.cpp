@@ -1607,133 +1607,259 @@ void op_apply(pmchwt_ctx* c, const double* x, double* y, double* s1, double* s2,
   apply_Ptilde(c, s1, y, s2, s3, nrhs);
 }
 
-GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol, int rho, int max_iter) {
-  const int64_t vs = vlen(c);
-  const int n = int(vs);
-  const int64_t vecd = 2 * vs;  // doubles per vector
-  // workspace: V (rho+1) x nrhs vectors, w, r, 3 scratch
-  const size_t need = size_t(rho + 1 + 5) * nrhs * vecd + 4 * size_t(rho + 2) * nrhs + 16 * size_t(nrhs);
-  double* W = need_work(c, need);
-  double* V = W;
-  double* w = V + size_t(rho + 1) * nrhs * vecd;
-  double* r = w + nrhs * vecd;
-  double* s1 = r + nrhs * vecd;
-  double* s2 = s1 + nrhs * vecd;
-  double* s3 = s2 + nrhs * vecd;
-  double* dh = s3 + nrhs * vecd;            // nrhs x (rho+2) complex
-  double* dn = dh + 2 * size_t(rho + 2) * nrhs;
-  DBuf dact = dalloc<int32_t>(nrhs);
-  const int64_t vstep = int64_t(nrhs) * vs;  // complex offset between basis vectors
-  GmresOut out;
-  out.iters.assign(nrhs, 0);
-  out.restarts.assign(nrhs, 0);
-  out.relres.assign(nrhs, 1.0);
-  out.converged.assign(nrhs, 0);
-  launch_zero(x, vecd * nrhs, c->stream);
-  HIPCHK(hipMemcpyAsync(r, bt, size_t(vecd * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
-  std::vector<double> bnorm(nrhs), beta(nrhs), hn(nrhs);
-  launch_norms(bt, vs, n, nrhs, dn, c->stream);
-  HIPCHK(hipMemcpyAsync(bnorm.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  beta = bnorm;
-  std::vector<int32_t> active(nrhs);
-  for (int q = 0; q < nrhs; ++q) {
-    if (bnorm[q] == 0.0) {
-      out.converged[q] = 1;
-      out.relres[q] = 0.0;
+// Host buffers for the small per-iteration transfers, pinned so that the
+// copies are asynchronous and several runs can overlap on the device.
+struct PinnedBuf {
+  void* p = nullptr;
+  explicit PinnedBuf(size_t bytes) {
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{PMCHWT_ERR_OUT_OF_MEMORY, "pinned host allocation failed"};
     }
   }
-  std::vector<cd> H(size_t(rho + 1) * rho * nrhs), cs(size_t(rho) * nrhs), sn(size_t(rho) * nrhs),
-      g(size_t(rho + 1) * nrhs);
-  std::vector<double> hbuf(2 * size_t(rho + 2) * nrhs);
-  std::vector<double> scale(nrhs);
-  DBuf dscale = dalloc<double>(nrhs);
-  DBuf dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
-  auto Hm = [&](int q, int i, int j) -> cd& { return H[(size_t(q) * (rho + 1) + i) * rho + j]; };
-  int total = 0;
-  while (true) {
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// One restarted GMRES run as a resumable state machine.  Every step needs one
+// application of Op (input op_in(), output op_out(), done by the caller), then
+// stage1(), stage2(), stage3() in that order.  Between stages the run only
+// enqueues work on the context's stream and waits at the start of the next
+// stage for what it needs on the host, so several runs advanced stage by
+// stage overlap on the device.  The blocking gmres() below drives one run.
+struct GmresRun {
+  enum Phase { ITER, RESID, DONE };
+  pmchwt_ctx* c;
+  const double* bt;
+  double* x;
+  int nrhs, rho, max_iter;
+  double tol;
+  int64_t vs, vecd, vstep;
+  int n;
+  double *V, *w, *r, *s1, *s2, *s3, *dh, *dn;
+  DBuf dact, dscale, dy, dupd;
+  PinnedBuf hpin;
+  double *h_hbuf, *h_hn, *h_scale, *h_y, *h_beta;
+  int32_t *h_act, *h_upd;
+  hipEvent_t ev = nullptr;
+  GmresOut out;
+  std::vector<double> bnorm, beta, hsum;
+  std::vector<int32_t> active;
+  std::vector<cd> H, cs, sn, g;
+  std::vector<int> jend, done_cycle;
+  int total = 0, j = 0;
+  bool all_done = false;
+  Phase phase = DONE;
+  Phase step = DONE;  // phase in which the current step started (set by stage1)
+
+  static size_t pinned_bytes(int nrhs, int rho) {
+    return 8 * (2 * size_t(rho + 2) * nrhs + 2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs + nrhs) +
+           4 * 2 * size_t(nrhs) + 64;
+  }
+  cd& Hm(int q, int i, int jj) { return H[(size_t(q) * (rho + 1) + i) * rho + jj]; }
+
+  GmresRun(pmchwt_ctx* c_, const double* bt_, double* x_, int nrhs_, double tol_, int rho_, int max_iter_)
+      : c(c_), bt(bt_), x(x_), nrhs(nrhs_), rho(rho_), max_iter(max_iter_), tol(tol_),
+        hpin(pinned_bytes(nrhs_, rho_)) {
+    vs = vlen(c);
+    n = int(vs);
+    vecd = 2 * vs;
+    vstep = int64_t(nrhs) * vs;
+    const size_t need = size_t(rho + 1 + 5) * nrhs * vecd + 4 * size_t(rho + 2) * nrhs + 16 * size_t(nrhs);
+    double* W = need_work(c, need);
+    V = W;
+    w = V + size_t(rho + 1) * nrhs * vecd;
+    r = w + nrhs * vecd;
+    s1 = r + nrhs * vecd;
+    s2 = s1 + nrhs * vecd;
+    s3 = s2 + nrhs * vecd;
+    dh = s3 + nrhs * vecd;
+    dn = dh + 2 * size_t(rho + 2) * nrhs;
+    dact = dalloc<int32_t>(nrhs);
+    dupd = dalloc<int32_t>(nrhs);
+    dscale = dalloc<double>(nrhs);
+    dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
+    double* hp = static_cast<double*>(hpin.p);
+    h_hbuf = hp;
+    h_hn = h_hbuf + 2 * size_t(rho + 2) * nrhs;
+    h_scale = h_hn + nrhs;
+    h_y = h_scale + nrhs;
+    h_beta = h_y + 2 * size_t(rho + 1) * nrhs;
+    h_act = reinterpret_cast<int32_t*>(h_beta + nrhs);
+    h_upd = h_act + nrhs;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    out.iters.assign(nrhs, 0);
+    out.restarts.assign(nrhs, 0);
+    out.relres.assign(nrhs, 1.0);
+    out.converged.assign(nrhs, 0);
+    bnorm.assign(nrhs, 0.0);
+    beta.assign(nrhs, 0.0);
+    active.assign(nrhs, 0);
+    H.assign(size_t(rho + 1) * rho * nrhs, cd(0));
+    cs.assign(size_t(rho) * nrhs, cd(0));
+    sn.assign(size_t(rho) * nrhs, cd(0));
+    g.assign(size_t(rho + 1) * nrhs, cd(0));
+  }
+  GmresRun(const GmresRun&) = delete;
+  GmresRun& operator=(const GmresRun&) = delete;
+  ~GmresRun() {
+    // the pinned buffers and small device arrays may still feed queued copies
+    (void)hipStreamSynchronize(c->stream);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+
+  void wait() { HIPCHK(hipEventSynchronize(ev)); }
+  void mark() { HIPCHK(hipEventRecord(ev, c->stream)); }
+
+  // x = 0, r = bt, |bt| (synchronous), then the first cycle
+  void start() {
+    launch_zero(x, vecd * nrhs, c->stream);
+    HIPCHK(hipMemcpyAsync(r, bt, size_t(vecd * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
+    launch_norms(bt, vs, n, nrhs, dn, c->stream);
+    HIPCHK(hipMemcpyAsync(h_beta, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+    mark();
+    wait();
+    for (int q = 0; q < nrhs; ++q) {
+      bnorm[q] = beta[q] = h_beta[q];
+      if (bnorm[q] == 0.0) {
+        out.converged[q] = 1;
+        out.relres[q] = 0.0;
+      }
+    }
+    begin_cycle();
+  }
+
+  void begin_cycle() {
     bool any = false;
     for (int q = 0; q < nrhs; ++q) {
       active[q] = !out.converged[q];
       any |= bool(active[q]);
     }
-    if (!any || total >= max_iter) break;
-    HIPCHK(hipMemcpyAsync(dact.p, active.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
-    for (int q = 0; q < nrhs; ++q) scale[q] = active[q] ? 1.0 / beta[q] : 0.0;
-    HIPCHK(hipMemcpyAsync(dscale.p, scale.data(), 8 * nrhs, hipMemcpyHostToDevice, c->stream));
+    if (!any || total >= max_iter) {
+      phase = DONE;
+      return;
+    }
+    for (int q = 0; q < nrhs; ++q) {
+      h_act[q] = active[q];
+      h_scale[q] = active[q] ? 1.0 / beta[q] : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(dact.p, h_act, 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dscale.p, h_scale, 8 * nrhs, hipMemcpyHostToDevice, c->stream));
     launch_scale_copy(r, vs, V, vs, n, nrhs, dscale.as<double>(), c->stream);
     std::fill(H.begin(), H.end(), cd(0));
     std::fill(g.begin(), g.end(), cd(0));
     for (int q = 0; q < nrhs; ++q) g[size_t(q) * (rho + 1)] = beta[q];
-    std::vector<int> jend(nrhs, 0);
-    std::vector<int> done_cycle(nrhs, 0);
-    int j = 0;
-    for (; j < rho && total < max_iter; ++j) {
-      op_apply(c, V + size_t(j) * nrhs * vecd, w, s1, s2, s3, nrhs);
-      // CGS2
-      std::vector<double> hsum(2 * size_t(j + 1) * nrhs, 0.0);
-      for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
-        launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
-        HIPCHK(hipMemcpyAsync(hbuf.data(), dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += hbuf[k];
-      }
+    jend.assign(nrhs, 0);
+    done_cycle.assign(nrhs, 0);
+    j = 0;
+    phase = ITER;
+  }
+
+  const double* op_in() const { return phase == ITER ? V + size_t(j) * nrhs * vecd : x; }
+  double* op_out() const { return phase == ITER ? w : r; }
+
+  void stage1() {
+    step = phase;
+    if (step == ITER) {  // CGS2, first pass
+      hsum.assign(2 * size_t(j + 1) * nrhs, 0.0);
+      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
+      launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
+      HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
+      mark();
+    } else if (step == RESID) {  // r = bt - Op x
+      launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
+      launch_norms(r, vs, n, nrhs, dn, c->stream);
+      HIPCHK(hipMemcpyAsync(h_beta, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      mark();
+    }
+  }
+
+  void stage2() {
+    if (step == ITER) {  // second pass and the new vector's norm
+      wait();
+      for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += h_hbuf[k];
+      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
+      launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
+      HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
       launch_norms(w, vs, n, nrhs, dn, c->stream);
-      HIPCHK(hipMemcpyAsync(hn.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      for (int q = 0; q < nrhs; ++q) scale[q] = (active[q] && hn[q] > 0) ? 1.0 / hn[q] : 0.0;
-      HIPCHK(hipMemcpyAsync(dscale.p, scale.data(), 8 * nrhs, hipMemcpyHostToDevice, c->stream));
-      launch_scale_copy(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, dscale.as<double>(), c->stream);
-      ++total;
-      bool all_done = true;
+      HIPCHK(hipMemcpyAsync(h_hn, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      mark();
+    } else if (step == RESID) {
+      wait();
       for (int q = 0; q < nrhs; ++q) {
-        if (!active[q]) continue;
-        out.iters[q] += 1;
-        for (int i = 0; i <= j; ++i) Hm(q, i, j) = cd(hsum[2 * (size_t(q) * (j + 1) + i)], hsum[2 * (size_t(q) * (j + 1) + i) + 1]);
-        Hm(q, j + 1, j) = hn[q];
-        for (int i = 0; i < j; ++i) {
-          const cd a = Hm(q, i, j), b = Hm(q, i + 1, j);
-          const cd c_ = cs[size_t(q) * rho + i], s_ = sn[size_t(q) * rho + i];
-          Hm(q, i, j) = c_ * a + s_ * b;
-          Hm(q, i + 1, j) = -std::conj(s_) * a + std::conj(c_) * b;
-        }
-        const cd a = Hm(q, j, j), b = Hm(q, j + 1, j);
-        const double den = std::sqrt(std::norm(a) + std::norm(b));
-        const cd c_ = den > 0 ? std::conj(a) / den : cd(1), s_ = den > 0 ? std::conj(b) / den : cd(0);
-        cs[size_t(q) * rho + j] = c_;
-        sn[size_t(q) * rho + j] = s_;
-        Hm(q, j, j) = den;
-        Hm(q, j + 1, j) = 0;
-        cd& gj = g[size_t(q) * (rho + 1) + j];
-        g[size_t(q) * (rho + 1) + j + 1] = -std::conj(s_) * gj;
-        gj = c_ * gj;
-        const double res = std::abs(g[size_t(q) * (rho + 1) + j + 1]) / bnorm[q];
-        out.relres[q] = res;
-        jend[q] = j + 1;
-        // converged inside the cycle (a convergence exactly at the cycle end
-        // still goes through the cycle-end residual, as Table 1 counts it)
-        if (res <= tol && j + 1 < rho) {
-          done_cycle[q] = 1;
-          active[q] = 0;
-        } else {
-          all_done = false;
-        }
+        beta[q] = h_beta[q];
+        if (out.converged[q] || jend[q] == 0) continue;
+        out.restarts[q] += 1;
+        out.relres[q] = beta[q] / bnorm[q];
+        if (beta[q] / bnorm[q] <= tol) out.converged[q] = 1;
       }
-      HIPCHK(hipMemcpyAsync(dact.p, active.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
-      if (all_done) {
-        ++j;
-        break;
+      begin_cycle();
+    }
+  }
+
+  void stage3() {
+    if (step != ITER) return;
+    wait();
+    for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += h_hbuf[k];
+    for (int q = 0; q < nrhs; ++q) h_scale[q] = (active[q] && h_hn[q] > 0) ? 1.0 / h_hn[q] : 0.0;
+    HIPCHK(hipMemcpyAsync(dscale.p, h_scale, 8 * nrhs, hipMemcpyHostToDevice, c->stream));
+    launch_scale_copy(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, dscale.as<double>(), c->stream);
+    ++total;
+    all_done = true;
+    for (int q = 0; q < nrhs; ++q) {
+      if (!active[q]) continue;
+      out.iters[q] += 1;
+      for (int i = 0; i <= j; ++i)
+        Hm(q, i, j) = cd(hsum[2 * (size_t(q) * (j + 1) + i)], hsum[2 * (size_t(q) * (j + 1) + i) + 1]);
+      Hm(q, j + 1, j) = h_hn[q];
+      for (int i = 0; i < j; ++i) {
+        const cd a = Hm(q, i, j), b = Hm(q, i + 1, j);
+        const cd c_ = cs[size_t(q) * rho + i], s_ = sn[size_t(q) * rho + i];
+        Hm(q, i, j) = c_ * a + s_ * b;
+        Hm(q, i + 1, j) = -std::conj(s_) * a + std::conj(c_) * b;
+      }
+      const cd a = Hm(q, j, j), b = Hm(q, j + 1, j);
+      const double den = std::sqrt(std::norm(a) + std::norm(b));
+      const cd c_ = den > 0 ? std::conj(a) / den : cd(1), s_ = den > 0 ? std::conj(b) / den : cd(0);
+      cs[size_t(q) * rho + j] = c_;
+      sn[size_t(q) * rho + j] = s_;
+      Hm(q, j, j) = den;
+      Hm(q, j + 1, j) = 0;
+      cd& gj = g[size_t(q) * (rho + 1) + j];
+      g[size_t(q) * (rho + 1) + j + 1] = -std::conj(s_) * gj;
+      gj = c_ * gj;
+      const double res = std::abs(g[size_t(q) * (rho + 1) + j + 1]) / bnorm[q];
+      out.relres[q] = res;
+      jend[q] = j + 1;
+      // converged inside the cycle (a convergence exactly at the cycle end
+      // still goes through the cycle-end residual, as Table 1 counts it)
+      if (res <= tol && j + 1 < rho) {
+        done_cycle[q] = 1;
+        active[q] = 0;
+      } else {
+        all_done = false;
       }
     }
-    // x += V y for every right-hand side that iterated in this cycle
-    std::vector<double> ybuf(2 * size_t(rho + 1) * nrhs, 0.0);
-    std::vector<int32_t> upd(nrhs, 0);
+    for (int q = 0; q < nrhs; ++q) h_act[q] = active[q];
+    HIPCHK(hipMemcpyAsync(dact.p, h_act, 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+    if (all_done || j + 1 >= rho || total >= max_iter)
+      end_cycle();
+    else
+      ++j;
+  }
+
+  // x += V y for every right-hand side that iterated in this cycle; then the
+  // cycle-end residual, or done
+  void end_cycle() {
     int maxj = 0;
     for (int q = 0; q < nrhs; ++q) {
       const int m = jend[q];
+      h_upd[q] = m > 0;
+      for (int i = 0; i < 2 * (rho + 1); ++i) h_y[2 * size_t(q) * (rho + 1) + i] = 0.0;
       if (m == 0) continue;
-      upd[q] = 1;
       maxj = std::max(maxj, m);
       std::vector<cd> y(m);
       for (int i = m - 1; i >= 0; --i) {
@@ -1742,34 +1868,34 @@ GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol,
         y[i] = s / Hm(q, i, i);
       }
       for (int i = 0; i < m; ++i) {
-        ybuf[2 * (size_t(q) * (rho + 1) + i)] = y[i].real();
-        ybuf[2 * (size_t(q) * (rho + 1) + i) + 1] = y[i].imag();
+        h_y[2 * (size_t(q) * (rho + 1) + i)] = y[i].real();
+        h_y[2 * (size_t(q) * (rho + 1) + i) + 1] = y[i].imag();
       }
     }
     if (maxj > 0) {
-      HIPCHK(hipMemcpyAsync(dy.p, ybuf.data(), ybuf.size() * 8, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(hipMemcpyAsync(dact.p, upd.data(), 4 * nrhs, hipMemcpyHostToDevice, c->stream));
-      launch_update(V, vstep, maxj, x, vs, n, dact.as<int32_t>(), nrhs, vs, dy.as<double>(), rho + 1, 1.0, c->stream);
+      HIPCHK(hipMemcpyAsync(dy.p, h_y, 16 * size_t(rho + 1) * nrhs, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(dupd.p, h_upd, 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+      launch_update(V, vstep, maxj, x, vs, n, dupd.as<int32_t>(), nrhs, vs, dy.as<double>(), rho + 1, 1.0, c->stream);
     }
     for (int q = 0; q < nrhs; ++q)
       if (done_cycle[q]) out.converged[q] = 1;
     bool pending = false;
     for (int q = 0; q < nrhs; ++q) pending |= (!out.converged[q] && jend[q] > 0);
-    if (!pending) break;
-    // end of a full cycle: true residual r = bt - Op x
-    op_apply(c, x, r, s1, s2, s3, nrhs);
-    launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
-    launch_norms(r, vs, n, nrhs, dn, c->stream);
-    HIPCHK(hipMemcpyAsync(beta.data(), dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (int q = 0; q < nrhs; ++q) {
-      if (out.converged[q] || jend[q] == 0) continue;
-      out.restarts[q] += 1;
-      out.relres[q] = beta[q] / bnorm[q];
-      if (beta[q] / bnorm[q] <= tol) out.converged[q] = 1;
-    }
+    phase = pending ? RESID : DONE;
   }
-  return out;
+};
+
+GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol, int rho, int max_iter) {
+  GmresRun g(c, bt, x, nrhs, tol, rho, max_iter);
+  g.start();
+  while (g.phase != GmresRun::DONE) {
+    op_apply(c, g.op_in(), g.op_out(), g.s1, g.s2, g.s3, nrhs);
+    g.stage1();
+    g.stage2();
+    g.stage3();
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return g.out;
 }
 
 }  // namespace
