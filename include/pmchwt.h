@@ -63,7 +63,9 @@ typedef enum {
   PMCHWT_ERR_NOT_CONVERGED = -5, /* GMRES hit max_iter; outputs hold the last iterate */
   PMCHWT_ERR_OVER_BUDGET = -6,   /* request larger than the server's HBM budget */
   PMCHWT_ERR_CANCELLED = -7,     /* server request cancelled */
-  PMCHWT_ERR_STATE = -8          /* call out of order (e.g. solve before assemble) */
+  PMCHWT_ERR_STATE = -8,         /* call out of order (e.g. solve before assemble) */
+  PMCHWT_PENDING = 1,            /* server request waiting for admission */
+  PMCHWT_RUNNING = 2             /* server request admitted, not finished */
 } pmchwt_status;
 
 /* Preconditioning operator P (Section 3.1; cost per iteration in Table 1). */
@@ -255,6 +257,99 @@ const char *pmchwt_last_error(const pmchwt_ctx *ctx);
 
 /* Free every device and host resource of ctx.  NULL is allowed. */
 void pmchwt_destroy(pmchwt_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop on one GPU with continuous batching.
+ *
+ * Callers that submit many independent scattering problems (different
+ * meshes, sizes, wavenumbers, incident fields) and want them solved while
+ * others are still running.  A server owns two host threads:
+ *  - an admission thread takes requests in submission order.  It admits one
+ *    when the summed device-memory estimate of the live requests plus its own
+ *    stays within hbm_budget_bytes and fewer than max_live are live.  It then
+ *    assembles the request on its own context and stream (the same work as
+ *    pmchwt_assemble and the right-hand side of pmchwt_solve).
+ *  - an engine thread advances every live request by one Krylov step per round.
+ *    The operator products of all live requests with fewer than 16
+ *    right-hand sides go out in grouped launches (one kernel carries the
+ *    products of many requests); the rest of each step runs on the request's
+ *    stream, so the requests' work overlaps on the device.
+ * Assemblies of newly admitted requests overlap with the rounds.  A request's
+ * arithmetic does not depend on what else is live: its results are the same
+ * alone and in any mix.  Finished requests release their device memory
+ * before the next admission.
+ * The server functions are thread safe.
+ * ------------------------------------------------------------------------- */
+typedef struct pmchwt_server pmchwt_server;
+
+typedef struct {
+  size_t hbm_budget_bytes; /* admission limit on the summed device estimates   */
+  int32_t max_live;        /* requests admitted at once, 1..256                 */
+} pmchwt_server_opts;
+
+/* One scattering problem: the arguments of pmchwt_add_scatterer (per
+ * scatterer), pmchwt_set_wavenumber, pmchwt_assemble and pmchwt_solve.  All
+ * arrays are copied during pmchwt_server_submit.                               */
+typedef struct {
+  int32_t n_scatterers;
+  const double *const *verts;   /* [n_scatterers] -> double[nv[m]*3]            */
+  const int32_t *nv;
+  const int32_t *const *tris;   /* [n_scatterers] -> int32[nt[m]*3]             */
+  const int32_t *nt;
+  const pmchwt_complex *eps_r;  /* [n_scatterers]                               */
+  double k_ext;
+  int32_t nrhs;
+  const double *dirs;           /* nrhs*3 unit                                  */
+  const pmchwt_complex *pols;   /* nrhs*3, p.d = 0                              */
+  pmchwt_assembly_opts opts_A, opts_P;
+  int32_t precond;              /* pmchwt_precond                               */
+  pmchwt_solver_opts solver;
+} pmchwt_request;
+
+typedef struct {
+  int32_t status;          /* PMCHWT_PENDING, PMCHWT_RUNNING, PMCHWT_OK or an error
+                              (PMCHWT_ERR_NOT_CONVERGED: results still written) */
+  int32_t nrhs;
+  int64_t n_unknowns;      /* N = 2 sum_m E_m                                    */
+  int64_t device_bytes;    /* admission estimate                                 */
+  double ms_queued;        /* submission -> admission                            */
+  double ms_total;         /* submission -> results ready                        */
+  pmchwt_solve_stats stats;
+} pmchwt_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, live, pending;
+  int64_t rounds;           /* engine rounds                                      */
+  int64_t max_live_seen;    /* most requests live in one round                    */
+  int64_t grouped_launches; /* grouped operator launches                          */
+  int64_t grouped_jobs;     /* products carried by them                           */
+  int64_t bytes_in_use;     /* estimates of the live requests                     */
+} pmchwt_server_stats;
+
+/* Start a server on `device`.  Errors: INVALID_ARG, DEVICE, OUT_OF_MEMORY. */
+int pmchwt_server_create(pmchwt_server **out, int device, const pmchwt_server_opts *opts);
+/* Queue a request; *ticket identifies it.  Errors: INVALID_ARG (bad sizes or
+ * options), INVALID_MESH (detected before admission), OVER_BUDGET (the
+ * estimate alone exceeds the budget).                                         */
+int pmchwt_server_submit(pmchwt_server *s, const pmchwt_request *req, uint64_t *ticket);
+/* Current state of a request (res->status is PENDING, RUNNING, OK or an
+ * error).  Returns INVALID_ARG for an unknown ticket.                         */
+int pmchwt_server_poll(pmchwt_server *s, uint64_t ticket, pmchwt_result *res);
+/* Block until the request has finished or timeout_ms (< 0: no limit) passed;
+ * returns PMCHWT_OK when finished (res->status tells how), PMCHWT_RUNNING on
+ * timeout.                                                                    */
+int pmchwt_server_wait(pmchwt_server *s, uint64_t ticket, double timeout_ms, pmchwt_result *res);
+/* Copy the results of a finished request and forget it: currents[nrhs * N]
+ * (layout of pmchwt_solve), sigma_ext[nrhs], sigma_sca[nrhs]; any pointer may
+ * be NULL.  Errors: INVALID_ARG (unknown ticket), STATE (not finished).       */
+int pmchwt_server_fetch(pmchwt_server *s, uint64_t ticket, pmchwt_complex *currents, double *sigma_ext,
+                        double *sigma_sca);
+/* Cancel a pending or running request (its status becomes CANCELLED). */
+int pmchwt_server_cancel(pmchwt_server *s, uint64_t ticket);
+int pmchwt_server_get_stats(pmchwt_server *s, pmchwt_server_stats *out);
+/* Finish the live requests' current round, cancel the rest, join the threads
+ * and free everything.                                                        */
+void pmchwt_server_destroy(pmchwt_server *s);
 
 #ifdef __cplusplus
 }

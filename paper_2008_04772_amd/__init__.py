@@ -25,6 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK = 0
 ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_OUT_OF_MEMORY, ERR_DEVICE = -1, -2, -3, -4
 ERR_NOT_CONVERGED, ERR_OVER_BUDGET, ERR_CANCELLED, ERR_STATE = -5, -6, -7, -8
+PENDING, RUNNING = 1, 2
 
 PRECOND = {"I": 0, "A": 1, "D": 2, "D_INT": 3, "D_EXT": 4, "S_INT": 5, "S_EXT": 6}
 FP64, MIXED = 0, 1
@@ -69,6 +70,35 @@ class pmchwt_profile(ctypes.Structure):
                 ("mfma_flops", ctypes.c_int64)]
 
 
+class pmchwt_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_live", ctypes.c_int32)]
+
+
+class pmchwt_request(ctypes.Structure):
+    _fields_ = [("n_scatterers", ctypes.c_int32),
+                ("verts", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+                ("nv", ctypes.POINTER(ctypes.c_int32)),
+                ("tris", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
+                ("nt", ctypes.POINTER(ctypes.c_int32)),
+                ("eps_r", ctypes.POINTER(pmchwt_complex)),
+                ("k_ext", ctypes.c_double), ("nrhs", ctypes.c_int32),
+                ("dirs", ctypes.POINTER(ctypes.c_double)), ("pols", ctypes.POINTER(pmchwt_complex)),
+                ("opts_A", pmchwt_assembly_opts), ("opts_P", pmchwt_assembly_opts),
+                ("precond", ctypes.c_int32), ("solver", pmchwt_solver_opts)]
+
+
+class pmchwt_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("n_unknowns", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("ms_queued", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("stats", pmchwt_solve_stats)]
+
+
+class pmchwt_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "live", "pending", "rounds",
+                                              "max_live_seen", "grouped_launches", "grouped_jobs",
+                                              "bytes_in_use")]
+
+
 _P = ctypes.c_void_p
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -99,6 +129,14 @@ _SIGS = {
     "pmchwt_get_profile": ([_P, ctypes.POINTER(pmchwt_profile)], ctypes.c_int),
     "pmchwt_last_error": ([_P], ctypes.c_char_p),
     "pmchwt_destroy": ([_P], None),
+    "pmchwt_server_create": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(pmchwt_server_opts)], ctypes.c_int),
+    "pmchwt_server_submit": ([_P, ctypes.POINTER(pmchwt_request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "pmchwt_server_poll": ([_P, ctypes.c_uint64, ctypes.POINTER(pmchwt_result)], ctypes.c_int),
+    "pmchwt_server_wait": ([_P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(pmchwt_result)], ctypes.c_int),
+    "pmchwt_server_fetch": ([_P, ctypes.c_uint64, _pc, _pd, _pd], ctypes.c_int),
+    "pmchwt_server_cancel": ([_P, ctypes.c_uint64], ctypes.c_int),
+    "pmchwt_server_get_stats": ([_P, ctypes.POINTER(pmchwt_server_stats)], ctypes.c_int),
+    "pmchwt_server_destroy": ([_P], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -358,3 +396,126 @@ class Context:
 
     def profile(self):
         return pmchwt_get_profile(self.h)
+
+
+# ---------------------------------------------------------------------------
+# Serving (C ABI pmchwt_server_*)
+# ---------------------------------------------------------------------------
+def _result_dict(r):
+    st = r.stats
+    return {"status": r.status, "nrhs": r.nrhs, "n_unknowns": r.n_unknowns, "device_bytes": r.device_bytes,
+            "ms_queued": r.ms_queued, "ms_total": r.ms_total, "iterations": st.iterations,
+            "converged": bool(st.converged), "matvecs": st.matvecs, "rel_residual": st.rel_residual,
+            "ir_steps": st.ir_steps, "restarts": st.restarts, "ms_solve": st.ms_solve}
+
+
+def pmchwt_server_create(device, hbm_budget_bytes, max_live):
+    h = _P()
+    o = pmchwt_server_opts(int(hbm_budget_bytes), int(max_live))
+    rc = _lib.pmchwt_server_create(ctypes.byref(h), device, ctypes.byref(o))
+    if rc != OK:
+        raise PmchwtError(rc, "pmchwt_server_create failed")
+    return h
+
+
+def pmchwt_server_submit(srv, meshes, eps, k_ext, dirs, pols, optsA, optsP, precond, solver):
+    """meshes: [(verts, tris), ...]; eps: scalar or one per scatterer."""
+    d, p = _waves(dirs, pols)
+    M = len(meshes)
+    vs = [_f64(v).reshape(-1, 3) for v, _ in meshes]
+    ts = [np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3) for _, t in meshes]
+    eps = np.broadcast_to(np.asarray(eps, dtype=np.complex128), (M,))
+    vp = (ctypes.POINTER(ctypes.c_double) * M)(*[_ptr(v, _pd) for v in vs])
+    tp = (ctypes.POINTER(ctypes.c_int32) * M)(*[_ptr(t, _pi32) for t in ts])
+    nv = np.array([len(v) for v in vs], dtype=np.int32)
+    nt = np.array([len(t) for t in ts], dtype=np.int32)
+    ep = (pmchwt_complex * M)(*[pmchwt_complex(e.real, e.imag) for e in eps])
+    pc = _c128(p).reshape(-1)
+    req = pmchwt_request(M, ctypes.cast(vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))), _ptr(nv, _pi32),
+                         ctypes.cast(tp, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))), _ptr(nt, _pi32),
+                         ctypes.cast(ep, _pc), float(k_ext), len(d), _ptr(d, _pd), _ptr(pc, _pc),
+                         optsA, optsP, PRECOND[precond] if isinstance(precond, str) else int(precond), solver)
+    t = ctypes.c_uint64()
+    rc = _lib.pmchwt_server_submit(srv, ctypes.byref(req), ctypes.byref(t))
+    if rc != OK:
+        raise PmchwtError(rc, "pmchwt_server_submit failed")
+    return t.value
+
+
+def pmchwt_server_poll(srv, ticket):
+    r = pmchwt_result()
+    _check(None, _lib.pmchwt_server_poll(srv, ticket, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def pmchwt_server_wait(srv, ticket, timeout_ms=-1.0):
+    r = pmchwt_result()
+    rc = _lib.pmchwt_server_wait(srv, ticket, float(timeout_ms), ctypes.byref(r))
+    if rc not in (OK, RUNNING):
+        raise PmchwtError(rc, "pmchwt_server_wait failed")
+    return _result_dict(r)
+
+
+def pmchwt_server_fetch(srv, ticket, nrhs, n_unknowns):
+    cur = np.zeros(nrhs * n_unknowns, dtype=np.complex128)
+    se, ss = np.zeros(nrhs), np.zeros(nrhs)
+    _check(None, _lib.pmchwt_server_fetch(srv, ticket, _ptr(cur, _pc), _ptr(se, _pd), _ptr(ss, _pd)))
+    return cur.reshape(nrhs, n_unknowns), se, ss
+
+
+def pmchwt_server_cancel(srv, ticket):
+    _check(None, _lib.pmchwt_server_cancel(srv, ticket))
+
+
+def pmchwt_server_get_stats(srv):
+    s = pmchwt_server_stats()
+    _check(None, _lib.pmchwt_server_get_stats(srv, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in pmchwt_server_stats._fields_}
+
+
+def pmchwt_server_destroy(srv):
+    _lib.pmchwt_server_destroy(srv)
+
+
+class Server:
+    """A serving loop on one GPU (see pmchwt_server_* in include/pmchwt.h)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=64 << 30, max_live=16):
+        self.h = pmchwt_server_create(device, hbm_budget_bytes, max_live)
+
+    def submit(self, meshes, eps, k_ext, dirs, pols, optsA, optsP, precond="S_INT", solver=None):
+        solver = solver if solver is not None else solver_opts()
+        return pmchwt_server_submit(self.h, meshes, eps, k_ext, dirs, pols, optsA, optsP, precond, solver)
+
+    def poll(self, ticket):
+        return pmchwt_server_poll(self.h, ticket)
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        return pmchwt_server_wait(self.h, ticket, timeout_ms)
+
+    def fetch(self, ticket):
+        r = self.poll(ticket)
+        return pmchwt_server_fetch(self.h, ticket, r["nrhs"], r["n_unknowns"])
+
+    def cancel(self, ticket):
+        pmchwt_server_cancel(self.h, ticket)
+
+    def stats(self):
+        return pmchwt_server_get_stats(self.h)
+
+    def close(self):
+        if self.h:
+            pmchwt_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2417,3 +2417,5 @@ void pmchwt_destroy(pmchwt_ctx* c) {
 }
 
 }  // extern "C"
+
+#include "serve.inl"

@@ -150,6 +150,28 @@ template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs,
                         int64_t vstride, hipStream_t st);
+// One product of a grouped launch: the arguments of launch_gemv_pmchwt for
+// nr right-hand sides (1, 2 or 4; the same nr for every job of a launch) and
+// the first workgroup of the job (jobs sorted by block0).
+template <typename M>
+struct GemvJob {
+  const M* S;
+  const M* C;
+  int64_t ld;
+  int rows, cols;
+  double kr, ki;
+  const double* xD;
+  const double* xN;
+  double* yD;
+  double* yN;
+  int64_t vstride;
+  int block0;
+};
+// workgroups the product of `rows` rows takes with nr right-hand sides
+template <typename M>
+int gemv_blocks(int rows, int nr);
+template <typename M>
+void launch_gemv_pmchwt_grouped(const GemvJob<M>* jobs_dev, int njobs, int nr, int total_blocks, hipStream_t st);
 // Many right-hand sides on the FP32 matrix cores: same product as
 // launch_gemv_pmchwt for FP32 operators with ld a multiple of 16; B1, B2 are
 // workspaces of 4 nrhs x 2 ld floats each.

@@ -49,16 +49,16 @@ struct GemvRows {
   static constexpr int value = (sizeof(M) == 4 ? 8 : 4) / NR > 0 ? (sizeof(M) == 4 ? 8 : 4) / NR : 1;
 };
 
+// Rows of workgroup `blk` (four wavefronts of ROWS rows each).
 template <typename M, int NR>
-__global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, const M* __restrict__ C,
-                                                     int64_t ld, int rows, int cols, double kr, double ki,
-                                                     const double* __restrict__ xD,
-                                                     const double* __restrict__ xN, double* yD, double* yN,
-                                                     int64_t vstride) {
+__device__ __forceinline__ void gemv_pmchwt_rows(const M* __restrict__ S, const M* __restrict__ C, int64_t ld,
+                                                 int rows, int cols, double kr, double ki,
+                                                 const double* __restrict__ xD, const double* __restrict__ xN,
+                                                 double* yD, double* yN, int64_t vstride, int blk) {
   constexpr int ROWS = GemvRows<M, NR>::value;
   typedef typename CPair<M>::T V;
   const int lane = threadIdx.x & 63;
-  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  const int row0 = ROWS * (blk * (blockDim.x / 64) + threadIdx.x / 64);
   if (row0 >= rows) return;
   const V* Sv[ROWS];
   const V* Cv[ROWS];
@@ -148,6 +148,56 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, co
     }
   }
 }
+
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_gemv_pmchwt(const M* __restrict__ S, const M* __restrict__ C,
+                                                     int64_t ld, int rows, int cols, double kr, double ki,
+                                                     const double* __restrict__ xD,
+                                                     const double* __restrict__ xN, double* yD, double* yN,
+                                                     int64_t vstride) {
+  gemv_pmchwt_rows<M, NR>(S, C, ld, rows, cols, kr, ki, xD, xN, yD, yN, vstride, blockIdx.x);
+}
+
+// Several independent products in one launch (the operators of different
+// problems): workgroup b belongs to the job with block0 <= b < next block0
+// and runs exactly the rows a launch of that job alone would give it.
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_gemv_pmchwt_grouped(const GemvJob<M>* __restrict__ jobs, int njobs) {
+  int lo = 0, hi = njobs - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {  // last job with block0 <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemvJob<M> j = jobs[lo];
+  gemv_pmchwt_rows<M, NR>(j.S, j.C, j.ld, j.rows, j.cols, j.kr, j.ki, j.xD, j.xN, j.yD, j.yN, j.vstride,
+                          b - j.block0);
+}
+
+template <typename M>
+int gemv_blocks(int rows, int nr) {
+  const int rpw = nr >= 4 ? GemvRows<M, 4>::value : (nr >= 2 ? GemvRows<M, 2>::value : GemvRows<M, 1>::value);
+  return (rows + 4 * rpw - 1) / (4 * rpw);
+}
+
+template <typename M>
+void launch_gemv_pmchwt_grouped(const GemvJob<M>* jobs_dev, int njobs, int nr, int total_blocks, hipStream_t st) {
+  if (njobs == 0) return;
+  const dim3 grid{static_cast<unsigned>(total_blocks)}, block{256};
+  if (nr == 4)
+    hipLaunchKernelGGL((k_gemv_pmchwt_grouped<M, 4>), grid, block, 0, st, jobs_dev, njobs);
+  else if (nr == 2)
+    hipLaunchKernelGGL((k_gemv_pmchwt_grouped<M, 2>), grid, block, 0, st, jobs_dev, njobs);
+  else
+    hipLaunchKernelGGL((k_gemv_pmchwt_grouped<M, 1>), grid, block, 0, st, jobs_dev, njobs);
+}
+template void launch_gemv_pmchwt_grouped<float>(const GemvJob<float>*, int, int, int, hipStream_t);
+template void launch_gemv_pmchwt_grouped<double>(const GemvJob<double>*, int, int, int, hipStream_t);
+template int gemv_blocks<float>(int, int);
+template int gemv_blocks<double>(int, int);
 
 template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
