@@ -47,6 +47,11 @@ WORKLOADS = {
     "prism10368": "hexagonal ice prism d=1 l=2.5, 10368 triangles (31104 unknowns), k_e=8, eps_r=3.17+0.01i, "
                   "128 RHS (64 directions x 2 polarisations); A dense q=(4,3,2,6) on the FP32 matrix cores; "
                   "P = S^i near field chi=2h, q=(1,1,1,1); GMRES(200) tol 1e-5",
+    "serve200": "serving: seeded Poisson arrivals of requests mixing spheres, single prisms and 2-8-monomer "
+                "aggregates of 500-8000 triangles, k_e ~ U[1,10], eps_r=3.17+0.01i, 1-32 directions x 2 "
+                "polarisations; mixed precision, P = S^i near field chi=2h; GMRES(200) tol 1e-5, at most 500 "
+                "iterations; arrival rate "
+                "0.8 x the solo throughput of a calibration pass",
 }
 
 
@@ -90,6 +95,107 @@ def run(P, mesh, chi, dirs, pols, k_ext, precision, steps, warmup):
                   f"solve {st.ms_solve:.1f} xs {(dt * 1e3 - pf['wall_setup'] - pf['wall_A'] - pf['wall_P'] - pf['wall_mass'] - st.ms_solve):.1f}",
                   file=sys.stderr, flush=True)
     return lat, profs, stats, float(se[0]), float(ss[0])
+
+
+def _prism_sa(F):
+    """Divisions (s per hexagon side, a axially) of a prism with about F triangles (F = 12 s a + 12 s^2)."""
+    s = max(2, int(round(np.sqrt(F / 60.0))))
+    a = max(2, int(round((F / 12.0 - s * s) / s)))
+    return s, a
+
+
+def serve_requests(n, seed=5):
+    """Seeded request mix of the serving workload (meshes built before any timing)."""
+    import synth
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        kind = int(rng.integers(0, 3))
+        F = float(np.exp(rng.uniform(np.log(500.0), np.log(8000.0))))
+        k = float(rng.uniform(1.0, 10.0))
+        ndir = int(rng.integers(1, 33))
+        if kind == 0:
+            meshes = [synth.icosphere(3 if F < 2560 else 4)]
+        elif kind == 1:
+            meshes = [synth.hex_prism(*_prism_sa(F))]
+        else:
+            nm = int(rng.integers(2, 9))
+            meshes = synth.aggregate(nm, *_prism_sa(F / nm), seed=int(rng.integers(1 << 30)))
+        dirs, pols = synth.plane_wave_set(ndir, seed=int(rng.integers(1 << 30)))
+        v = np.concatenate([m[0] for m in meshes])
+        offs = np.cumsum([0] + [len(m[0]) for m in meshes])
+        t = np.concatenate([m[1] + offs[i] for i, m in enumerate(meshes)])
+        chi = 2.0 * synth.mean_edge_length(v, t)
+        out.append({"meshes": meshes, "k": k, "dirs": dirs, "pols": pols, "chi": chi,
+                    "F": int(sum(len(m[1]) for m in meshes))})
+    return out
+
+
+def run_serve(P, n_requests, budget_gb=200, max_live=16):
+    import threading
+    reqs = serve_requests(n_requests)
+    oA = P.assembly_opts((4, 3, 2), 4, -1.0, P.MIXED)
+    # at most 500 iterations: meshes under-resolved at high k stop there and
+    # count as served (status NOT_CONVERGED, reported separately)
+    so = P.solver_opts(tol=1e-5, restart=200, max_iter=500, ir_max=1)
+
+    def submit(srv, r):
+        oP = P.assembly_opts((1, 1, 1), 1, r["chi"], P.MIXED)
+        return srv.submit(r["meshes"], EPS, r["k"], r["dirs"], r["pols"], oA, oP, "S_INT", so)
+
+    with P.Server(0, budget_gb << 30, max_live) as srv:
+        # calibration: the first requests one at a time
+        ncal = min(8, n_requests)
+        t0 = time.perf_counter()
+        for r in reqs[:ncal]:
+            tk = submit(srv, r)
+            srv.wait(tk)
+            srv.fetch(tk)
+        solo = (time.perf_counter() - t0) / ncal
+        lam = 0.8 / solo
+        print(f"[bench] serve calibration: {ncal} requests alone, {solo * 1e3:.1f} ms each, "
+              f"arrival rate {lam:.2f}/s", file=sys.stderr, flush=True)
+        s0 = srv.stats()
+        rng = np.random.default_rng(5)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+        tickets = [None] * n_requests
+
+        def feeder():
+            base = time.perf_counter()
+            for i, r in enumerate(reqs):
+                dt = arrivals[i] - (time.perf_counter() - base)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = submit(srv, r)
+
+        t1 = time.perf_counter()
+        th = threading.Thread(target=feeder)
+        th.start()
+        results = []
+        for i in range(n_requests):
+            while tickets[i] is None:
+                time.sleep(0.001)
+            res = srv.wait(tickets[i])
+            srv.fetch(tickets[i])
+            results.append(res)
+            if (i + 1) % 20 == 0:
+                print(f"[bench] serve: {i + 1}/{n_requests} done", file=sys.stderr, flush=True)
+        th.join()
+        wall = time.perf_counter() - t1
+        s1 = srv.stats()
+    lat = np.array([r["ms_total"] for r in results])
+    ok = sum(1 for r in results if r["status"] == 0)
+    nc = sum(1 for r in results if r["status"] == P.ERR_NOT_CONVERGED)
+    solves = sum(r["nrhs"] for r in results if r["status"] in (0, P.ERR_NOT_CONVERGED))
+    return {
+        "wall_s": wall, "requests": n_requests, "ok": ok, "not_converged": nc,
+        "failed": n_requests - ok - nc, "solves": solves, "arrival_rate_per_s": lam,
+        "solo_ms_per_request": solo * 1e3,
+        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+        "max_live_seen": s1["max_live_seen"], "grouped_launches": s1["grouped_launches"] - s0["grouped_launches"],
+        "grouped_jobs": s1["grouped_jobs"] - s0["grouped_jobs"], "rounds": s1["rounds"] - s0["rounds"],
+        "triangles_mean": float(np.mean([r["F"] for r in reqs])),
+    }
 
 
 def cpu_baseline(mesh, k_ext, budget_s=15.0):
@@ -156,6 +262,7 @@ def main():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sphere5120",
                     help="sphere5120: the benchmark workload; prism10368: the 128-RHS workload")
+    ap.add_argument("--requests", type=int, default=200, help="requests of the serving workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -164,6 +271,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import paper_2008_04772_amd as P
+    if args.workload == "serve200":
+        sv = run_serve(P, args.requests)
+        out = {"metric": METRIC, "value": sv["solves"] / sv["wall_s"], "unit": "PMCHWT solves/s (RHS)",
+               "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sv["wall_s"] * 1e3, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
+               "config": {"workload": WORKLOADS["serve200"], "requests": args.requests},
+               "requests_per_s": sv["requests"] / sv["wall_s"],
+               "latency_ms_p50": sv["latency_ms_p50"], "latency_ms_p99": sv["latency_ms_p99"], "serve": sv}
+        print(json.dumps(out), flush=True)
+        return
     v, t, chi, dirs, pols, k_ext = workload(args.workload)
     results = {}
     for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
