@@ -97,9 +97,10 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       chi apart; chi < 0 means infinity.  Ignored for A (always dense).
  *   precision : PMCHWT_FP64, or PMCHWT_MIXED.  For A: disjoint pairs and
  *       operator storage in FP32, singular pairs in FP64.  For P: the
- *       near-field values are always FP64; MIXED stores the inverted mass
- *       matrices M_A^-1 and M_A^-T (computed in FP64) in FP32, which only
- *       perturbs the preconditioner, not the system that is solved.          */
+ *       near-field values are always FP64; MIXED computes and stores the
+ *       inverted mass matrices M_A^-1 and M_A^-T in FP32 (Gauss-Jordan with
+ *       its rank updates on the FP32 matrix cores), which only perturbs the
+ *       preconditioner, not the system that is solved.                       */
 typedef struct {
   int32_t q_near, q_medium, q_far;
   int32_t n_singular;

@@ -1185,6 +1185,58 @@ void gj_inverse(pmchwt_ctx* c, double* X, int n) {
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
+// The same inverse in FP32 on the matrix cores (n a multiple of 32, so that
+// every pivot block is a multiple of the 32-wide K tile).  Pivot blocks are
+// inverted row-major and the taken columns stored row-major, so that both
+// products are A B^T with K contiguous:
+//   R (n x b, = the b x n row block Pinv X[p,:] read column-major) = X[p,:]^T Pinv^T,
+//   X[:, J] -= C R[:, J]  as  (X^T)[J, :] -= R[J, :] C^T.
+void gj_inverse_f32(pmchwt_ctx* c, float* X, int n) {
+  const int B = 128;
+  DBuf Pinv[2] = {dalloc<float>(size_t(B) * B), dalloc<float>(size_t(B) * B)};
+  DBuf Cc[2] = {dalloc<float>(size_t(n) * B), dalloc<float>(size_t(n) * B)};
+  DBuf R = dalloc<float>(size_t(B) * n);
+  auto prepare = [&](int p0, int slot, hipStream_t st) {
+    const int b = std::min(B, n - p0);
+    launch_gj_block_inverse_f32(X + int64_t(p0) * n + p0, n, Pinv[slot].as<float>(), b, st);
+    launch_gj_take_columns_f32(X, n, p0, b, Cc[slot].as<float>(), st);
+  };
+  auto update = [&](int slot, int b, int j0, int nj) {
+    if (nj <= 0) return;
+    launch_mfma_f32(R.as<float>() + int64_t(j0) * b, b, Cc[slot].as<float>(), b, nj, n, X + int64_t(j0) * n, n, true,
+                    c->stream);
+  };
+  auto put_rows = [&](int p0, int b, int j0, int nj) {
+    if (nj <= 0) return;
+    HIPCHK(hipMemcpy2DAsync(X + int64_t(j0) * n + p0, size_t(n) * 4, R.as<float>() + int64_t(j0) * b, size_t(b) * 4,
+                            size_t(b) * 4, size_t(nj), hipMemcpyDeviceToDevice, c->stream));
+  };
+  prepare(0, 0, c->stream);
+  int slot = 0;
+  for (int p0 = 0; p0 < n; p0 += B) {
+    const int b = std::min(B, n - p0);
+    const int q0 = p0 + b, bq = std::min(B, n - q0);
+    launch_mfma_f32(X + p0, n, Pinv[slot].as<float>(), b, n, b, R.as<float>(), b, false, c->stream);
+    if (bq > 0) {
+      update(slot, b, q0, bq);
+      put_rows(p0, b, q0, bq);
+      HIPCHK(hipEventRecord(c->ev_main, c->stream));
+      HIPCHK(hipStreamWaitEvent(c->side, c->ev_main, 0));
+      prepare(q0, slot ^ 1, c->side);
+      HIPCHK(hipEventRecord(c->ev_side, c->side));
+    }
+    const int nl = bq > 0 ? q0 : n;
+    update(slot, b, 0, nl);
+    update(slot, b, q0 + bq, n - q0 - bq);
+    put_rows(p0, b, 0, nl);
+    put_rows(p0, b, q0 + bq, n - q0 - bq);
+    if (bq > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
+    slot ^= 1;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
 // RWG Gram pattern: row i holds edge i and the other edges of its two
 // triangles (sorted, scatterer-local columns); g_pos maps local pair (a, b)
 // of every triangle to its CSR slot.
@@ -1260,31 +1312,35 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const int n = c->sc[m].topo.E;
     const size_t nn = size_t(n) * n;
-    DBuf MA = dalloc<double>(nn), Mi = dalloc<double>(nn), MiT = dalloc<double>(nn);
+    DBuf MA = dalloc<double>(nn);
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    c->MA.push_back(std::move(MA));
+    const int64_t ldm = ldmass(n);
+    if (c->mass_f32) {
+      // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
+      // M_A^-1 with zero padding columns, the layout the products read
+      DBuf Mf = dalloc<float>(size_t(ldm) * ldm), MfT = dalloc<float>(size_t(ldm) * ldm);
+      launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
+      gj_inverse_f32(c, Mf.as<float>(), int(ldm));
+      launch_transpose_f32(Mf.as<float>(), MfT.as<float>(), int(ldm), c->stream);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->Minv.push_back(std::move(Mf));
+      c->MinvT.push_back(std::move(MfT));
+      continue;
+    }
+    DBuf Mi = dalloc<double>(nn), MiT = dalloc<double>(nn);
     HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     // row-major M_A is column-major M_A^T; inverting it in place yields the
     // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
     gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
-    c->MA.push_back(std::move(MA));
-    // padded copies for the vector loads of the application kernel
-    const int64_t ldm = ldmass(n);
-    if (c->mass_f32) {
-      DBuf Mf = dalloc<float>(size_t(n) * ldm), MfT = dalloc<float>(size_t(n) * ldm);
-      launch_repack(Mi.as<double>(), n, Mf.as<float>(), ldm, c->stream);
-      launch_repack(MiT.as<double>(), n, MfT.as<float>(), ldm, c->stream);
-      HIPCHK(hipStreamSynchronize(c->stream));
-      c->Minv.push_back(std::move(Mf));
-      c->MinvT.push_back(std::move(MfT));
-    } else {
-      DBuf Md = dalloc<double>(size_t(n) * ldm), MdT = dalloc<double>(size_t(n) * ldm);
-      launch_repack(Mi.as<double>(), n, Md.as<double>(), ldm, c->stream);
-      launch_repack(MiT.as<double>(), n, MdT.as<double>(), ldm, c->stream);
-      HIPCHK(hipStreamSynchronize(c->stream));
-      c->Minv.push_back(std::move(Md));
-      c->MinvT.push_back(std::move(MdT));
-    }
+    // padded copy for the vector loads of the application kernel
+    DBuf Md = dalloc<double>(size_t(n) * ldm), MdT = dalloc<double>(size_t(n) * ldm);
+    launch_repack(Mi.as<double>(), n, Md.as<double>(), ldm, c->stream);
+    launch_repack(MiT.as<double>(), n, MdT.as<double>(), ldm, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->Minv.push_back(std::move(Md));
+    c->MinvT.push_back(std::move(MdT));
   }
   HIPCHK(hipGetLastError());
   c->prof.ms_mass = t.stop();
@@ -1640,7 +1696,7 @@ struct GmresRun {
   int64_t vs, vecd, vstep;
   int n;
   double *V, *w, *r, *s1, *s2, *s3, *dh, *dn;
-  DBuf dact, dscale, dy, dupd;
+  DBuf dact, dscale, dy, dupd, dpart;
   PinnedBuf hpin;
   double *h_hbuf, *h_hn, *h_scale, *h_y, *h_beta;
   int32_t *h_act, *h_upd;
@@ -1682,6 +1738,7 @@ struct GmresRun {
     dupd = dalloc<int32_t>(nrhs);
     dscale = dalloc<double>(nrhs);
     dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
+    dpart = dalloc<double>(2 * (size_t(rho + 2) * nrhs + 1024));
     double* hp = static_cast<double*>(hpin.p);
     h_hbuf = hp;
     h_hn = h_hbuf + 2 * size_t(rho + 2) * nrhs;
@@ -1765,13 +1822,13 @@ struct GmresRun {
     step = phase;
     if (step == ITER) {  // CGS2, first pass
       hsum.assign(2 * size_t(j + 1) * nrhs, 0.0);
-      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
+      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream, dpart.as<double>());
       launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
       HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
       mark();
     } else if (step == RESID) {  // r = bt - Op x
       launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
-      launch_norms(r, vs, n, nrhs, dn, c->stream);
+      launch_norms(r, vs, n, nrhs, dn, c->stream, dpart.as<double>());
       HIPCHK(hipMemcpyAsync(h_beta, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
       mark();
     }
@@ -1781,10 +1838,10 @@ struct GmresRun {
     if (step == ITER) {  // second pass and the new vector's norm
       wait();
       for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += h_hbuf[k];
-      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream);
+      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream, dpart.as<double>());
       launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
       HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
-      launch_norms(w, vs, n, nrhs, dn, c->stream);
+      launch_norms(w, vs, n, nrhs, dn, c->stream, dpart.as<double>());
       HIPCHK(hipMemcpyAsync(h_hn, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
       mark();
     } else if (step == RESID) {

@@ -92,10 +92,8 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
   // ---- phase A: moments of (t1, T) for every listed trial triangle T
   for (int li = threadIdx.x; li < nl; li += blockDim.x) {
     const int t2 = h.chunk_tri[l0 + li];
-    MomPair<R> m;
-    m.e.zero();
-    m.i.zero();
     bool shared = false;
+    bool done_i = false, done_e = false;
     for (int k = 0; k < 3; ++k) {
       const int vb = p.tvid[k * F + t2];
       shared |= (vb == va[0]) | (vb == va[1]) | (vb == va[2]);
@@ -111,63 +109,82 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
         for (int d = 0; d < 3; ++d) P2[k][d] = R(p.tv[(3 * k + d) * F + t2] - c1[d]);
       const R AA = R(A1 * p.tarea[t2]);
       const int off = c_rule_off[q], n = c_rule_n[q];
-      for (int a = 0; a < n; ++a) {
-        R x[3];
-        const R la0 = R(c_rule_l[off + a][0]), la1 = R(c_rule_l[off + a][1]), la2 = R(c_rule_l[off + a][2]);
-        for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
-        const R wa = R(c_rule_w[off + a]) * AA;
-        for (int b = 0; b < n; ++b) {
-          R y[3];
-          const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
-          for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
-          const R w = wa * R(c_rule_w[off + b]);
-          const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          KernelVal<R> kv = helmholtz<R>(r2, R(ke_r), R(0), false, w);
-          m.e.add(kv, x, y, true);
-          if (inner) {
-            KernelVal<R> kw = helmholtz<R>(r2, R(ki_r), R(ki_i), decay_i, w);
-            m.i.add(kw, x, y, true);
+      // one wavenumber at a time keeps 14 complex accumulators live, not 28
+      for (int kk = 0; kk < (inner ? 2 : 1); ++kk) {
+        Moments<R> mm;
+        mm.zero();
+        const R kr = R(kk == 0 ? ke_r : ki_r), ki = R(kk == 0 ? 0.0 : ki_i);
+        const bool decay = kk == 0 ? false : decay_i;
+#pragma unroll 1
+        for (int a = 0; a < n; ++a) {
+          R x[3];
+          const R la0 = R(c_rule_l[off + a][0]), la1 = R(c_rule_l[off + a][1]), la2 = R(c_rule_l[off + a][2]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
+          const R wa = R(c_rule_w[off + a]) * AA;
+#pragma unroll 1
+          for (int b = 0; b < n; ++b) {
+            R y[3];
+            const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
+            const R w = wa * R(c_rule_w[off + b]);
+            const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            mm.add(helmholtz<R>(r2, kr, ki, decay, w), x, y, true);
           }
+        }
+        if (kk == 0) {
+          sm[li].e = mm;
+          done_e = true;
+        } else {
+          sm[li].i = mm;
+          done_i = true;
         }
       }
     }
-    sm[li] = m;
+    if (!done_e) sm[li].e.zero();
+    if (!done_i) sm[li].i.zero();
   }
   __syncthreads();
 
   // ---- phase B: one trial edge per thread
   const int j0 = ch * h.chunk;
   const int nj = min(h.chunk, h.E_tot - j0);
-  double al1[3], w1[3][3];
+  R al1[3], w1[3][3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    al1[a] = p.tsgn[a * F + t1] / (2.0 * A1);
-    for (int d = 0; d < 3; ++d) w1[a][d] = al1[a] * double(P1[a][d]);
+    al1[a] = R(p.tsgn[a * F + t1] / (2.0 * A1));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) w1[a][d] = al1[a] * P1[a][d];
   }
+  const R kre = R(ke_r), kri = R(ki_r), kii = R(ki_i);
   const int64_t slot0 = 3 * int64_t(t1 - h.slab_t0);
   for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
     const int j = j0 + jj;
     const int16_t* em = h.edge_map + 4 * int64_t(j);
     const bool inner = h.edge_scat[j] == s1;
-    cplx<double> Se[3] = {{0, 0}, {0, 0}, {0, 0}}, Ce[3] = {{0, 0}, {0, 0}, {0, 0}};
-    cplx<double> Si[3] = {{0, 0}, {0, 0}, {0, 0}}, Ci[3] = {{0, 0}, {0, 0}, {0, 0}};
+    cplx<R> Se[3] = {{0, 0}, {0, 0}, {0, 0}}, Ce[3] = {{0, 0}, {0, 0}, {0, 0}};
+    cplx<R> Si[3] = {{0, 0}, {0, 0}, {0, 0}}, Ci[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int side = 0; side < 2; ++side) {
       const int pos = em[2 * side], b = em[2 * side + 1];
       const int t2 = h.chunk_tri[l0 + pos];
       const double A2 = p.tarea[t2];
-      const double al2 = p.tsgn[b * F + t2] / (2.0 * A2);
-      double w2[3];
-      for (int d = 0; d < 3; ++d) w2[d] = al2 * (p.tv[(3 * b + d) * F + t2] - c1[d]);
+      const R al2 = R(p.tsgn[b * F + t2] / (2.0 * A2));
+      R w2[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) w2[d] = al2 * R(p.tv[(3 * b + d) * F + t2] - c1[d]);
       const MomPair<R>& m = sm[pos];
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cplx<double> S, C;
-        contract<R, double>(m.e, al1[a], w1[a], al2, w2, ke_r, 0.0, true, S, C);
+        cplx<R> S, C;
+        contract_r<R>(m.e, al1[a], w1[a], al2, w2, kre, R(0), S, C);
         Se[a].re += S.re;
         Se[a].im += S.im;
         Ce[a].re += C.re;
         Ce[a].im += C.im;
         if (inner) {
-          contract<R, double>(m.i, al1[a], w1[a], al2, w2, ki_r, ki_i, true, S, C);
+          contract_r<R>(m.i, al1[a], w1[a], al2, w2, kri, kii, S, C);
           Si[a].re += S.re;
           Si[a].im += S.im;
           Ci[a].re += C.re;
@@ -175,6 +192,7 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
         }
       }
     }
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int64_t o = 2 * ((slot0 + a) * h.E_tot + j);
       h.He_S[o] = M(Se[a].re);

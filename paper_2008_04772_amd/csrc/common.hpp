@@ -241,6 +241,40 @@ __device__ __forceinline__ int shared_order(const int va[3], const int vb[3], in
 
 __device__ __forceinline__ double pick3(const double v[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
 
+// The same contraction with all arithmetic in R (FP32 for FP32 operators,
+// whose entries are stored in FP32 anyway).
+template <typename R>
+__device__ __forceinline__ void contract_r(const Moments<R>& m, R a1, const R w1[3], R a2, const R w2[3], R kr, R ki,
+                                           cplx<R>& S, cplx<R>& C) {
+  const R ww = w1[0] * w2[0] + w1[1] * w2[1] + w1[2] * w2[2];
+  R w2Mx_re = 0, w2Mx_im = 0, w1My_re = 0, w1My_im = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    w2Mx_re += w2[d] * m.Mx[d].re;
+    w2Mx_im += w2[d] * m.Mx[d].im;
+    w1My_re += w1[d] * m.My[d].re;
+    w1My_im += w1[d] * m.My[d].im;
+  }
+  const R aa = a1 * a2;
+  const R sv_re = aa * m.Mxy.re - a1 * w2Mx_re - a2 * w1My_re + ww * m.M0.re;
+  const R sv_im = aa * m.Mxy.im - a1 * w2Mx_im - a2 * w1My_im + ww * m.M0.im;
+  const R sd_re = R(4) * aa * m.M0.re, sd_im = R(4) * aa * m.M0.im;
+  const R ik2 = R(1) / (kr * kr + ki * ki);
+  const R t_re = (sd_re * kr + sd_im * ki) * ik2, t_im = (sd_im * kr - sd_re * ki) * ik2;
+  S.re = ki * sv_re + kr * sv_im - t_im;
+  S.im = ki * sv_im - kr * sv_re + t_re;
+  const R wx[3] = {w2[1] * w1[2] - w2[2] * w1[1], w2[2] * w1[0] - w2[0] * w1[2], w2[0] * w1[1] - w2[1] * w1[0]};
+  R c_re = 0, c_im = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const R u = a1 * w2[d] - a2 * w1[d];
+    c_re += u * m.Nx[d].re + wx[d] * m.Nd[d].re;
+    c_im += u * m.Nx[d].im + wx[d] * m.Nd[d].im;
+  }
+  C.re = -c_re;
+  C.im = -c_im;
+}
+
 template <typename T>
 __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);

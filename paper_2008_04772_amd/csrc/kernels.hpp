@@ -209,18 +209,33 @@ void launch_repack(const double* in, int n, T* out, int64_t ldo, hipStream_t st)
 // blocked Gauss-Jordan inverse helpers (column-major, no pivoting)
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st);
 void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipStream_t st);
+// FP32 variants: the block inverse written row-major,
+// the taken columns row-major (n x b)
+void launch_gj_block_inverse_f32(const float* X, int64_t ldx, float* out_rowmajor, int b, hipStream_t st);
+void launch_gj_take_columns_f32(float* X, int64_t n, int p0, int b, float* C, hipStream_t st);
+// out (n2 x n2 FP32) = [[in, 0], [0, I]]
+void launch_embed_f32(const double* in, int n, float* out, int n2, hipStream_t st);
+void launch_transpose_f32(const float* in, float* out, int n, hipStream_t st);
+// y (rows x Nr, row stride ldy) = A B^T or y -= A B^T on the FP32 matrix cores;
+// A rows x K (stride lda), B Nr x K (stride K), K a multiple of 32
+void launch_mfma_f32(const float* A, int64_t lda, const float* B, int K, int rows, int Nr, float* y, int64_t ldy,
+                     bool subtract, hipStream_t st);
 // per-vector scaled updates for batched conjugate gradients
 void launch_axpy_vec(double* y, const double* x, int64_t stride, int n, int nvec, const double* a, double s,
                      hipStream_t st);
 void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec, const double* b, hipStream_t st);
 
 // GMRES helpers on batches of complex128 vectors of length n.
+// part (optional): scratch of 2 (nvec nrhs + 1024) doubles for a split reduction
 void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
-                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st);
+                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st,
+                 double* part = nullptr);
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride,
                    double sign, hipStream_t st);
-void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st);
+// part (optional): scratch of nrhs + 256 doubles for a split reduction
+void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st,
+                  double* part = nullptr);
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,

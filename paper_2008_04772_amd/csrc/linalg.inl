@@ -427,10 +427,72 @@ __global__ void k_dots(const double* V, int64_t vstep, const double* w, int64_t 
   }
 }
 
+// Dots split over S chunks of the vector length (more workgroups than one per
+// vector), partial sums part[((r nvec + i) S + s)], summed in a fixed order.
+__global__ void k_dots_part(const double* V, int64_t vstep, const double* w, int64_t wstride, int n,
+                            const int32_t* active, int64_t rstride_v, double* part, int nvec, int S, int chunk) {
+  const int i = blockIdx.x, sidx = blockIdx.y, r = blockIdx.z;
+  double* o = part + 2 * ((int64_t(r) * nvec + i) * S + sidx);
+  if (!active[r]) {
+    if (threadIdx.x == 0) o[0] = o[1] = 0.0;
+    return;
+  }
+  const double* v = V + 2 * (int64_t(i) * vstep + int64_t(r) * rstride_v);
+  const double* ww = w + 2 * int64_t(r) * wstride;
+  const int k0 = sidx * chunk, k1 = min(n, k0 + chunk);
+  double re = 0, im = 0;
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const double vr = v[2 * k], vi = v[2 * k + 1], xr = ww[2 * k], xi = ww[2 * k + 1];
+    re += vr * xr + vi * xi;
+    im += vr * xi - vi * xr;
+  }
+  __shared__ double sr[256], si[256];
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if (threadIdx.x < q) {
+      sr[threadIdx.x] += sr[threadIdx.x + q];
+      si[threadIdx.x] += si[threadIdx.x + q];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    o[0] = sr[0];
+    o[1] = si[0];
+  }
+}
+
+__global__ void k_dots_fin(const double* part, int S, int m, double* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double re = 0, im = 0;
+  for (int sidx = 0; sidx < S; ++sidx) {
+    re += part[2 * (int64_t(q) * S + sidx)];
+    im += part[2 * (int64_t(q) * S + sidx) + 1];
+  }
+  out[2 * q] = re;
+  out[2 * q + 1] = im;
+}
+
+int dots_splits(int nvec, int nrhs, int n) {
+  const int want = (1024 + nvec * nrhs - 1) / (nvec * nrhs);
+  return std::max(1, std::min({want, 64, (n + 255) / 256}));
+}
+
 void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
-                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(nvec, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v, out,
-                     nvec);
+                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st, double* part) {
+  const int S = part ? dots_splits(nvec, nrhs, n) : 1;
+  if (S == 1) {
+    hipLaunchKernelGGL(k_dots, dim3(nvec, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v, out,
+                       nvec);
+    return;
+  }
+  const int chunk = (n + S - 1) / S;
+  hipLaunchKernelGGL(k_dots_part, dim3(nvec, S, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v,
+                     part, nvec, S, chunk);
+  const int m = nvec * nrhs;
+  hipLaunchKernelGGL(k_dots_fin, dim3((m + 255) / 256), dim3(256), 0, st, part, S, m, out);
 }
 
 // w^r[k] += sign * sum_i V_i^r[k] h[r][i]
@@ -473,8 +535,39 @@ __global__ void k_norms(const double* w, int64_t wstride, int n, double* out) {
   if (threadIdx.x == 0) out[r] = sqrt(red[0]);
 }
 
-void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_norms, dim3(nrhs), dim3(256), 0, st, w, wstride, n, out);
+__global__ void k_norms_part(const double* w, int64_t wstride, int n, int S, int chunk, double* part) {
+  const int sidx = blockIdx.x, r = blockIdx.y;
+  const double* ww = w + 2 * int64_t(r) * wstride;
+  const int k0 = sidx * chunk, k1 = min(n, k0 + chunk);
+  double s = 0;
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += ww[2 * k] * ww[2 * k] + ww[2 * k + 1] * ww[2 * k + 1];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[int64_t(r) * S + sidx] = red[0];
+}
+
+__global__ void k_norms_fin(const double* part, int S, int nrhs, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double s = 0;
+  for (int sidx = 0; sidx < S; ++sidx) s += part[int64_t(r) * S + sidx];
+  out[r] = sqrt(s);
+}
+
+void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st, double* part) {
+  const int S = part ? std::max(1, std::min({(256 + nrhs - 1) / nrhs, 64, (n + 255) / 256})) : 1;
+  if (S == 1) {
+    hipLaunchKernelGGL(k_norms, dim3(nrhs), dim3(256), 0, st, w, wstride, n, out);
+    return;
+  }
+  const int chunk = (n + S - 1) / S;
+  hipLaunchKernelGGL(k_norms_part, dim3(S, nrhs), dim3(256), 0, st, w, wstride, n, S, chunk, part);
+  hipLaunchKernelGGL(k_norms_fin, dim3((nrhs + 255) / 256), dim3(256), 0, st, part, S, nrhs, out);
 }
 
 __global__ void k_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n,
@@ -564,6 +657,7 @@ namespace pmchwt {
 // safely invertible without row exchanges).
 // ---------------------------------------------------------------------------
 constexpr int GJ_B = 128;
+constexpr int GJ_B_F32 = 128;  // pivot block of the FP32 inverse
 
 // Thread t holds column j = t % 128, rows [64 (t / 128), +64) in registers.
 // Step k of the in-place Gauss-Jordan inverse is one rank-1 update
@@ -574,58 +668,187 @@ constexpr int GJ_B = 128;
 // and resets its registers; the owners of row k+1 publish that row; two LDS
 // buffers alternate, so one barrier per step suffices.  Entries beyond b are
 // padded with the identity and stay inert.
-__global__ __launch_bounds__(256) void k_gj_block_inverse(const double* __restrict__ X, int64_t ldx,
-                                                          double* __restrict__ out, int b) {
-  __shared__ double colk[2][GJ_B], rowk[2][GJ_B];
-  const int t = threadIdx.x, j = t & (GJ_B - 1), i0 = 64 * (t >> 7);
-  double a[64];
+// a[k] for a wave-uniform k: a switch on the scalar index (a few scalar
+// branches) keeps the array in registers, where a computed register index
+// would move it to scratch
+template <typename T>
+__device__ __forceinline__ T pick(const T (&a)[64], int k) {
+  switch (k) {
+    case 0: return a[0];
+    case 1: return a[1];
+    case 2: return a[2];
+    case 3: return a[3];
+    case 4: return a[4];
+    case 5: return a[5];
+    case 6: return a[6];
+    case 7: return a[7];
+    case 8: return a[8];
+    case 9: return a[9];
+    case 10: return a[10];
+    case 11: return a[11];
+    case 12: return a[12];
+    case 13: return a[13];
+    case 14: return a[14];
+    case 15: return a[15];
+    case 16: return a[16];
+    case 17: return a[17];
+    case 18: return a[18];
+    case 19: return a[19];
+    case 20: return a[20];
+    case 21: return a[21];
+    case 22: return a[22];
+    case 23: return a[23];
+    case 24: return a[24];
+    case 25: return a[25];
+    case 26: return a[26];
+    case 27: return a[27];
+    case 28: return a[28];
+    case 29: return a[29];
+    case 30: return a[30];
+    case 31: return a[31];
+    case 32: return a[32];
+    case 33: return a[33];
+    case 34: return a[34];
+    case 35: return a[35];
+    case 36: return a[36];
+    case 37: return a[37];
+    case 38: return a[38];
+    case 39: return a[39];
+    case 40: return a[40];
+    case 41: return a[41];
+    case 42: return a[42];
+    case 43: return a[43];
+    case 44: return a[44];
+    case 45: return a[45];
+    case 46: return a[46];
+    case 47: return a[47];
+    case 48: return a[48];
+    case 49: return a[49];
+    case 50: return a[50];
+    case 51: return a[51];
+    case 52: return a[52];
+    case 53: return a[53];
+    case 54: return a[54];
+    case 55: return a[55];
+    case 56: return a[56];
+    case 57: return a[57];
+    case 58: return a[58];
+    case 59: return a[59];
+    case 60: return a[60];
+    case 61: return a[61];
+    case 62: return a[62];
+    case 63: return a[63];
+    default: return T(0);
+  }
+}
+template <typename T, bool ROWMAJOR_OUT, int NB, int RPT>
+__global__ __launch_bounds__(NB * NB / RPT) void k_gj_block_inverse(const T* __restrict__ X, int64_t ldx,
+                                                                    T* __restrict__ out, int b) {
+  __shared__ T colk[2][NB], rowk[2][NB];
+  const int t = threadIdx.x, j = t % NB, i0 = RPT * (t / NB);
+  T a[RPT];
 #pragma unroll
-  for (int r = 0; r < 64; ++r) {
+  for (int r = 0; r < RPT; ++r) {
     const int i = i0 + r;
-    a[r] = (i < b && j < b) ? X[int64_t(j) * ldx + i] : (i == j ? 1.0 : 0.0);
+    a[r] = (i < b && j < b) ? X[int64_t(j) * ldx + i] : T(i == j ? 1 : 0);
   }
   if (i0 == 0) rowk[0][j] = a[0];
   if (j == 0) {
 #pragma unroll
-    for (int r = 0; r < 64; ++r) {
-      colk[0][i0 + r] = a[r] - (i0 + r == 0 ? 1.0 : 0.0);
-      a[r] = (i0 + r == 0) ? 1.0 : 0.0;
+    for (int r = 0; r < RPT; ++r) {
+      colk[0][i0 + r] = a[r] - T(i0 + r == 0 ? 1 : 0);
+      a[r] = T(i0 + r == 0 ? 1 : 0);
     }
   }
   for (int k = 0; k < b; ++k) {
     const int buf = k & 1, nb = buf ^ 1;
     const int kn = k + 1;
     __syncthreads();
-    const double ip = 1.0 / (colk[buf][k] + 1.0);
-    const double v = (j == k) ? ip : rowk[buf][j] * ip;
+    const T ip = T(1) / (colk[buf][k] + T(1));
+    const T v = (j == k) ? ip : rowk[buf][j] * ip;
 #pragma unroll
-    for (int r0 = 0; r0 < 64; r0 += 16) {
-      double u[16];
+    for (int r0 = 0; r0 < RPT; r0 += 16) {
+      T u[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) u[r] = colk[buf][i0 + r0 + r];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        a[r0 + r] = fma(-u[r], v, a[r0 + r]);
-        if (i0 + r0 + r == kn) rowk[nb][j] = a[r0 + r];  // wave-uniform condition
-      }
+      for (int r = 0; r < 16; ++r) a[r0 + r] = fma(-u[r], v, a[r0 + r]);
     }
+    // publish row k+1: register rk = k+1 - i0 (wave-uniform), picked by a
+    // select tree on its bits (a dynamic register index would go to scratch)
+    const int rk = kn - i0;
+    if (rk >= 0 && rk < RPT) rowk[nb][j] = pick(a, rk);
     if (j == kn) {
 #pragma unroll
-      for (int r = 0; r < 64; ++r) {
-        colk[nb][i0 + r] = a[r] - (i0 + r == kn ? 1.0 : 0.0);
-        a[r] = (i0 + r == kn) ? 1.0 : 0.0;
+      for (int r = 0; r < RPT; ++r) {
+        colk[nb][i0 + r] = a[r] - T(i0 + r == kn ? 1 : 0);
+        a[r] = T(i0 + r == kn ? 1 : 0);
       }
     }
   }
 #pragma unroll
-  for (int r = 0; r < 64; ++r) {
+  for (int r = 0; r < RPT; ++r) {
     const int i = i0 + r;
-    if (i < b && j < b) out[int64_t(j) * b + i] = a[r];
+    if (i < b && j < b) out[ROWMAJOR_OUT ? int64_t(i) * b + j : int64_t(j) * b + i] = a[r];
   }
 }
 
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_block_inverse, dim3(1), dim3(256), 0, st, X, ldx, out, b);
+  hipLaunchKernelGGL((k_gj_block_inverse<double, false, GJ_B, 64>), dim3(1), dim3(GJ_B * GJ_B / 64), 0, st, X, ldx,
+                     out, b);
+}
+
+void launch_gj_block_inverse_f32(const float* X, int64_t ldx, float* out_rowmajor, int b, hipStream_t st) {
+  constexpr int NB = GJ_B_F32;
+  hipLaunchKernelGGL((k_gj_block_inverse<float, true, NB, 64>), dim3(1), dim3(NB * NB / 64), 0, st, X, ldx,
+                     out_rowmajor, b);
+}
+
+// FP32 take-columns with C row-major (n x b, C[i * b + j]).
+__global__ void k_gj_take_columns_f32(float* X, int64_t n, int p0, int b, float* C) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n * b) return;
+  const int64_t i = q % n, j = q / n;
+  float* x = X + (p0 + j) * n + i;
+  const bool pr = (i >= p0 && i < p0 + b);
+  C[i * b + j] = pr ? 0.0f : *x;
+  *x = (pr && i - p0 == j) ? 1.0f : 0.0f;
+}
+
+void launch_gj_take_columns_f32(float* X, int64_t n, int p0, int b, float* C, hipStream_t st) {
+  const int64_t m = n * b;
+  hipLaunchKernelGGL(k_gj_take_columns_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, X, n, p0, b, C);
+}
+
+// out (n2 x n2, FP32) = [[in, 0], [0, I]] for in n x n FP64 row-major
+__global__ void k_embed_f32(const double* in, int n, float* out, int n2) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= int64_t(n2) * n2) return;
+  const int64_t i = q / n2, j = q % n2;
+  out[q] = (i < n && j < n) ? float(in[i * n + j]) : (i == j ? 1.0f : 0.0f);
+}
+
+void launch_embed_f32(const double* in, int n, float* out, int n2, hipStream_t st) {
+  const int64_t m = int64_t(n2) * n2;
+  hipLaunchKernelGGL(k_embed_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, in, n, out, n2);
+}
+
+__global__ void k_transpose_f32(const float* in, float* out, int n) {
+  __shared__ float tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = by + k, j = bx + threadIdx.x;
+    if (i < n && j < n) tile[k][threadIdx.x] = in[int64_t(i) * n + j];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = bx + k, j = by + threadIdx.x;
+    if (i < n && j < n) out[int64_t(i) * n + j] = tile[threadIdx.x][k];
+  }
+}
+
+void launch_transpose_f32(const float* in, float* out, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose_f32, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, in, out, n);
 }
 
 // Column block p0..p0+b of X (col-major, n x n): copy it to C (n x b) with the

@@ -86,6 +86,18 @@ struct Real2Out {
   }
 };
 
+// Plain FP32 matrices: y[r * ld + n] = v, or y[r * ld + n] -= v.
+struct StoreOut {
+  float* y;
+  int64_t ld;
+  __device__ __forceinline__ void put(int r, int n, float v) const { y[int64_t(r) * ld + n] = v; }
+};
+struct SubOut {
+  float* y;
+  int64_t ld;
+  __device__ __forceinline__ void put(int r, int n, float v) const { y[int64_t(r) * ld + n] -= v; }
+};
+
 // out(rows x Nr) = A1 B1^T (K1) + A2 B2^T (K2), K1 and K2 multiples of 32
 // (K2 = 0 for a single product); B rows have stride K.
 // Workgroup tile 128 x 128, four wavefronts of 64 x 64 = 2 x 2 MFMA 32x32x2
@@ -190,6 +202,17 @@ __global__ void k_mfma_rhs_real(const double* __restrict__ x, int64_t vstride, i
   if (k >= Kt) return;
   const int q = n >> 2, comp = (n >> 1) & 1, part = n & 1;
   B[int64_t(n) * Kt + k] = k < E ? float(x[2 * (int64_t(q) * vstride + comp * cstride + k) + part]) : 0.0f;
+}
+
+void launch_mfma_f32(const float* A, int64_t lda, const float* B, int K, int rows, int Nr, float* y, int64_t ldy,
+                     bool subtract, hipStream_t st) {
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
+  if (subtract)
+    hipLaunchKernelGGL((k_mfma_gemm<SubOut>), grid, dim3(256), 0, st, A, B, K, lda, A, B, 0, lda, rows, Nr,
+                       SubOut{y, ldy});
+  else
+    hipLaunchKernelGGL((k_mfma_gemm<StoreOut>), grid, dim3(256), 0, st, A, B, K, lda, A, B, 0, lda, rows, Nr,
+                       StoreOut{y, ldy});
 }
 
 void launch_mfma_real2(const float* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
