@@ -745,7 +745,9 @@ template <typename T, bool ROWMAJOR_OUT, int NB, int RPT>
 __global__ __launch_bounds__(NB * NB / RPT) void k_gj_block_inverse(const T* __restrict__ X, int64_t ldx,
                                                                     T* __restrict__ out, int b) {
   __shared__ T colk[2][NB], rowk[2][NB];
-  const int t = threadIdx.x, j = t % NB, i0 = RPT * (t / NB);
+  const int t = threadIdx.x, j = t % NB;
+  // the row group is the same for a whole wavefront (NB >= 64): keep it scalar
+  const int i0 = __builtin_amdgcn_readfirstlane(RPT * (t / NB));
   T a[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -765,7 +767,8 @@ __global__ __launch_bounds__(NB * NB / RPT) void k_gj_block_inverse(const T* __r
     const int kn = k + 1;
     __syncthreads();
     const T ip = T(1) / (colk[buf][k] + T(1));
-    const T v = (j == k) ? ip : rowk[buf][j] * ip;
+    const T rj = rowk[buf][j];
+    const T v = (j == k) ? ip : rj * ip;
 #pragma unroll
     for (int r0 = 0; r0 < RPT; r0 += 16) {
       T u[16];

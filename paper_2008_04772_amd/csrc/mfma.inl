@@ -64,6 +64,8 @@ __global__ void k_mfma_rhs(const double* __restrict__ xD, const double* __restri
 // PMCHWT product: real column n -> complex column c = n/2, part n%2;
 // c < nrhs -> yD of rhs c, else yN of rhs c - nrhs; added to y.
 struct PmchwtOut {
+  static constexpr bool kInit = false, kNegA = false;
+  __device__ __forceinline__ float init(int, int) const { return 0.0f; }
   double* yD;
   double* yN;
   int64_t vstride;
@@ -77,6 +79,8 @@ struct PmchwtOut {
 // Real matrix on complex vectors of two trace components: real column n ->
 // rhs n/4, component (n/2)%2 (second at +cstride), part n%2; y = alpha M x.
 struct Real2Out {
+  static constexpr bool kInit = false, kNegA = false;
+  __device__ __forceinline__ float init(int, int) const { return 0.0f; }
   double* y;
   int64_t vstride, cstride;
   double alpha;
@@ -87,15 +91,21 @@ struct Real2Out {
 };
 
 // Plain FP32 matrices: y[r * ld + n] = v, or y[r * ld + n] -= v.
+// (kInit: the accumulators start from init(r, n), and with kNegA the
+// product enters with a minus sign, so that y -= A B^T ends in plain stores)
 struct StoreOut {
+  static constexpr bool kInit = false, kNegA = false;
   float* y;
   int64_t ld;
+  __device__ __forceinline__ float init(int, int) const { return 0.0f; }
   __device__ __forceinline__ void put(int r, int n, float v) const { y[int64_t(r) * ld + n] = v; }
 };
 struct SubOut {
+  static constexpr bool kInit = true, kNegA = true;
   float* y;
   int64_t ld;
-  __device__ __forceinline__ void put(int r, int n, float v) const { y[int64_t(r) * ld + n] -= v; }
+  __device__ __forceinline__ float init(int r, int n) const { return y[int64_t(r) * ld + n]; }
+  __device__ __forceinline__ void put(int r, int n, float v) const { y[int64_t(r) * ld + n] = v; }
 };
 
 // out(rows x Nr) = A1 B1^T (K1) + A2 B2^T (K2), K1 and K2 multiples of 32
@@ -116,11 +126,22 @@ __global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * MF_BM, n0 = blockIdx.x * MF_BN;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int h = lane >> 5, l32 = lane & 31;
   mf16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = mf16{};
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = mf16{};
+      if constexpr (Out::kInit) {
+        const int n = n0 + wc + 32 * j + l32;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int r = m0 + wr + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+          if (r < rows && n < Nr) acc[i][j][e] = out.init(r, n);
+        }
+      }
+    }
   const int lr = t >> 3, lc = (t & 7) * 4;
   const int nt1 = K1 / MF_BK, nt = nt1 + K2 / MF_BK;
   mf4 ra[4], rb[4];
@@ -148,7 +169,6 @@ __global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ 
   gload(0);
   sstore(0);
   __syncthreads();
-  const int h = lane >> 5, l32 = lane & 31;
   for (int kt = 0; kt < nt; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nt) gload(kt + 1);
@@ -157,8 +177,9 @@ __global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const mf4 a = *reinterpret_cast<const mf4*>(&As[buf][(wr + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        mf4 a = *reinterpret_cast<const mf4*>(&As[buf][(wr + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
         const mf4 b = *reinterpret_cast<const mf4*>(&Bs[buf][(wc + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        if constexpr (Out::kNegA) a = -a;
         af[i][4 * q] = a.x;
         af[i][4 * q + 1] = a.y;
         af[i][4 * q + 2] = a.z;
