@@ -37,9 +37,9 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector TFLOP/s (FP32 matrix cores
 HBM_PEAK = 8000.0  # GB/s
 # HBM bytes per launch of the dense operator product on the sphere workload,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy
-# (profiles/gemv_pmchwt_sphere5120_hbm_counters.md); valid for that kernel
+# (profiles/gemv_pmchwt3_sphere5120_hbm_counters.md); valid for that kernel
 # version only
-GEMV_TRAFFIC = {"sphere5120": 946.3e6}
+GEMV_TRAFFIC = {"sphere5120": 1418.2e6}
 
 WORKLOADS = {
     "sphere5120": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, 1 plane wave; "
@@ -308,7 +308,7 @@ def main():
         byt = pr["matvec_bytes"] / max(1, pr["matvec_launches"])
         ach = byt / (per * 1e-3) / 1e9
         traffic = GEMV_TRAFFIC.get(args.workload) if head == "mixed" else None
-        roof = {"kernel": "k_gemv_pmchwt", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
+        roof = {"kernel": "k_gemv_pmchwt3", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": traffic}
     else:
         fl = statistics.mean(p["mfma_flops"] for p in profs)

@@ -130,6 +130,11 @@ struct pmchwt_ctx {
   DBuf Se, Ce;
   std::vector<DBuf> Si, Ci;
   DBuf Si_ptr, Ci_ptr, ld_int;
+  // single scatterer: A^e + A^i pre-combined into three matrices for the GEMV
+  // (not for contexts of the serving loop, whose grouped products read the
+  // four blocks)
+  bool comb = false, comb_ok = true;
+  DBuf AC, AS1, AS2;
   pmchwt_assembly_opts optA{}, optP{};
   // P (near-field BC operators, CSR over union edge indices)
   int precond = -1;
@@ -726,6 +731,22 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     launch_singular<M>(p, sp_, c->stream);
     HIPCHK(hipGetLastError());
     c->prof.ms_assemble_singular = t.stop();
+  }
+  if (c->sc.size() == 1 && c->comb_ok) {  // three combined matrices for the operator products
+    const Scat& s = c->sc[0];
+    const int64_t ne = E * c->ldE;
+    c->AC = dalloc<M>(size_t(2 * ne));
+    c->AS1 = dalloc<M>(size_t(2 * ne));
+    c->AS2 = dalloc<M>(size_t(2 * ne));
+    launch_combine3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), ne, c->k_ext, s.k.real(),
+                       s.k.imag(), c->AC.as<M>(), c->AS1.as<M>(), c->AS2.as<M>(), c->stream);
+    HIPCHK(hipGetLastError());
+    c->comb = true;
+  } else {
+    c->comb = false;
+    c->AC = DBuf();
+    c->AS1 = DBuf();
+    c->AS2 = DBuf();
   }
   c->prof.ms_assemble_A = all.stop();
   c->prof.recompute = c->recompute;
@@ -1395,6 +1416,19 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   c->calls_A += 1;
   launch_zero(y, 2 * vs * nrhs, c->stream);
   EvTimer t(c->stream);
+  if (c->comb && !(c->precA == PMCHWT_MIXED && nrhs >= MFMA_MIN_RHS)) {
+    if (c->precA == PMCHWT_FP64)
+      launch_gemv_pmchwt3<double>(c->AC.as<double>(), c->AS1.as<double>(), c->AS2.as<double>(), c->ldE, int(E), int(E),
+                                  x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+    else
+      launch_gemv_pmchwt3<float>(c->AC.as<float>(), c->AS1.as<float>(), c->AS2.as<float>(), c->ldE, int(E), int(E), x,
+                                 x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+    HIPCHK(hipGetLastError());
+    c->prof.ms_matvec_total += t.stop();
+    c->prof.matvec_launches += 1;
+    c->prof.matvec_bytes += 3 * E * E * (c->precA == PMCHWT_FP64 ? 16 : 8);
+    return;
+  }
   if (c->precA == PMCHWT_FP64) {
     launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);

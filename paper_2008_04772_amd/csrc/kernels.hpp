@@ -172,6 +172,14 @@ template <typename M>
 int gemv_blocks(int rows, int nr);
 template <typename M>
 void launch_gemv_pmchwt_grouped(const GemvJob<M>* jobs_dev, int njobs, int nr, int total_blocks, hipStream_t st);
+// Single scatterer: the same product from C = Ce + Ci, S1 = Se/ke + Si/ki,
+// S2 = -(ke Se + ki Si) (launch_combine3 builds them, n complex entries)
+template <typename M>
+void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int rows, int cols, const double* xD,
+                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st);
+template <typename M>
+void launch_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir, double kii,
+                     M* C, M* S1, M* S2, hipStream_t st);
 // Many right-hand sides on the FP32 matrix cores: same product as
 // launch_gemv_pmchwt for FP32 operators with ld a multiple of 16; B1, B2 are
 // workspaces of 4 nrhs x 2 ld floats each.

@@ -199,6 +199,163 @@ template void launch_gemv_pmchwt_grouped<double>(const GemvJob<double>*, int, in
 template int gemv_blocks<float>(int, int);
 template int gemv_blocks<double>(int, int);
 
+// Single scatterer: A = A^e + A^i applied from three pre-combined matrices
+//   C = C^e + C^i,  S1 = S^e/k_e + S^i/k_i,  S2 = -(k_e S^e + k_i S^i),
+//   yD += C xD + S1 xN,  yN += C xN + S2 xD
+// (three operator reads per row instead of four).
+template <typename M, int NR>
+__global__ __launch_bounds__(256) void k_gemv_pmchwt3(const M* __restrict__ C, const M* __restrict__ S1,
+                                                      const M* __restrict__ S2, int64_t ld, int rows, int cols,
+                                                      const double* __restrict__ xD, const double* __restrict__ xN,
+                                                      double* yD, double* yN, int64_t vstride) {
+  constexpr int ROWS = GemvRows<M, NR>::value;
+  typedef typename CPair<M>::T V;
+  const int lane = threadIdx.x & 63;
+  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  if (row0 >= rows) return;
+  const V* Cv[ROWS];
+  const V* Av[ROWS];
+  const V* Bv[ROWS];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) {
+    const int r = min(row0 + h, rows - 1);
+    Cv[h] = reinterpret_cast<const V*>(C + 2 * int64_t(r) * ld);
+    Av[h] = reinterpret_cast<const V*>(S1 + 2 * int64_t(r) * ld);
+    Bv[h] = reinterpret_cast<const V*>(S2 + 2 * int64_t(r) * ld);
+  }
+  double a[ROWS][NR][4];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
+  const int np = (cols + 1) >> 1;
+  for (int q = lane; q < np; q += 64) {
+    V cv[ROWS], av[ROWS], bv[ROWS];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      cv[h] = __builtin_nontemporal_load(&Cv[h][q]);
+      av[h] = __builtin_nontemporal_load(&Av[h][q]);
+      bv[h] = __builtin_nontemporal_load(&Bv[h][q]);
+    }
+    const int j = 2 * q;
+    const bool pair = j + 1 < cols;
+    double xd[NR][4], xn[NR][4];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double2* pd = reinterpret_cast<const double2*>(xD + 2 * (int64_t(r) * vstride + j));
+      const double2* pn = reinterpret_cast<const double2*>(xN + 2 * (int64_t(r) * vstride + j));
+      const double2 d0 = pd[0], n0 = pn[0];
+      const double2 d1 = pair ? pd[1] : double2{0.0, 0.0};
+      const double2 n1 = pair ? pn[1] : double2{0.0, 0.0};
+      xd[r][0] = d0.x;
+      xd[r][1] = d0.y;
+      xd[r][2] = d1.x;
+      xd[r][3] = d1.y;
+      xn[r][0] = n0.x;
+      xn[r][1] = n0.y;
+      xn[r][2] = n1.x;
+      xn[r][3] = n1.y;
+    }
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      const double c4[4] = {double(cv[h].x), double(cv[h].y), double(cv[h].z), double(cv[h].w)};
+      const double s4[4] = {double(av[h].x), double(av[h].y), double(av[h].z), double(av[h].w)};
+      const double t4[4] = {double(bv[h].x), double(bv[h].y), double(bv[h].z), double(bv[h].w)};
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double cr = c4[2 * u], ci = c4[2 * u + 1], sr = s4[2 * u], si = s4[2 * u + 1];
+          const double tr = t4[2 * u], ti = t4[2 * u + 1];
+          const double dr = xd[r][2 * u], di = xd[r][2 * u + 1], nr = xn[r][2 * u], ni = xn[r][2 * u + 1];
+          a[h][r][0] += cr * dr - ci * di + sr * nr - si * ni;
+          a[h][r][1] += cr * di + ci * dr + sr * ni + si * nr;
+          a[h][r][2] += cr * nr - ci * ni + tr * dr - ti * di;
+          a[h][r][3] += cr * ni + ci * nr + tr * di + ti * dr;
+        }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[h][r][q] = wsum(a[h][r][q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      if (row0 + h >= rows) break;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double* yd = yD + 2 * (int64_t(r) * vstride + row0 + h);
+        double* yn = yN + 2 * (int64_t(r) * vstride + row0 + h);
+        yd[0] += a[h][r][0];
+        yd[1] += a[h][r][1];
+        yn[0] += a[h][r][2];
+        yn[1] += a[h][r][3];
+      }
+    }
+  }
+}
+
+template <typename M>
+void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int rows, int cols, const double* xD,
+                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st) {
+  auto grid = [rows](int rpw) { return dim3(unsigned((rows + 4 * rpw - 1) / (4 * rpw))); };
+  const dim3 block(256);
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0;
+    const double* xd = xD + 2 * int64_t(r0) * vstride;
+    const double* xn = xN + 2 * int64_t(r0) * vstride;
+    double* yd = yD + 2 * int64_t(r0) * vstride;
+    double* yn = yN + 2 * int64_t(r0) * vstride;
+    if (left >= 4) {
+      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 4>), grid(GemvRows<M, 4>::value), block, 0, st, C, S1, S2, ld, rows, cols,
+                         xd, xn, yd, yn, vstride);
+      r0 += 4;
+    } else if (left >= 2) {
+      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 2>), grid(GemvRows<M, 2>::value), block, 0, st, C, S1, S2, ld, rows, cols,
+                         xd, xn, yd, yn, vstride);
+      r0 += 2;
+    } else {
+      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 1>), grid(GemvRows<M, 1>::value), block, 0, st, C, S1, S2, ld, rows, cols,
+                         xd, xn, yd, yn, vstride);
+      r0 += 1;
+    }
+  }
+}
+template void launch_gemv_pmchwt3<float>(const float*, const float*, const float*, int64_t, int, int, const double*,
+                                         const double*, double*, double*, int, int64_t, hipStream_t);
+template void launch_gemv_pmchwt3<double>(const double*, const double*, const double*, int64_t, int, int,
+                                          const double*, const double*, double*, double*, int, int64_t, hipStream_t);
+
+// C = Ce + Ci, S1 = Se/ke + Si/ki, S2 = -(ke Se + ki Si), per complex entry
+template <typename M>
+__global__ void k_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir,
+                           double kii, M* C, M* S1, M* S2) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double ser = Se[2 * q], sei = Se[2 * q + 1], sir = Si[2 * q], sii = Si[2 * q + 1];
+  C[2 * q] = M(double(Ce[2 * q]) + double(Ci[2 * q]));
+  C[2 * q + 1] = M(double(Ce[2 * q + 1]) + double(Ci[2 * q + 1]));
+  const double k2 = kir * kir + kii * kii, ir = kir / k2, ii = -kii / k2;  // 1/ki
+  S1[2 * q] = M(ser / ke + (sir * ir - sii * ii));
+  S1[2 * q + 1] = M(sei / ke + (sir * ii + sii * ir));
+  S2[2 * q] = M(-(ke * ser + (kir * sir - kii * sii)));
+  S2[2 * q + 1] = M(-(ke * sei + (kir * sii + kii * sir)));
+}
+
+template <typename M>
+void launch_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir, double kii,
+                     M* C, M* S1, M* S2, hipStream_t st) {
+  hipLaunchKernelGGL((k_combine3<M>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, Se, Ce, Si, Ci, n, ke, kir,
+                     kii, C, S1, S2);
+}
+template void launch_combine3<float>(const float*, const float*, const float*, const float*, int64_t, double, double,
+                                     double, float*, float*, float*, hipStream_t);
+template void launch_combine3<double>(const double*, const double*, const double*, const double*, int64_t, double,
+                                      double, double, double*, double*, double*, hipStream_t);
+
 template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,

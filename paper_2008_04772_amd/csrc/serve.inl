@@ -325,6 +325,7 @@ void pmchwt_server::admit_loop() {
     run->rec = rec;
     run->nrhs = rec->nrhs;
     int rc = pmchwt_create(&run->c, device, nullptr);
+    if (rc == PMCHWT_OK) run->c->comb_ok = false;
     for (size_t q = 0; rc == PMCHWT_OK && q < rec->verts.size(); ++q)
       rc = pmchwt_add_scatterer(run->c, rec->verts[q].data(), int32_t(rec->verts[q].size() / 3), rec->tris[q].data(),
                                 int32_t(rec->tris[q].size() / 3), rec->eps[q], nullptr);
