@@ -159,6 +159,9 @@ typedef struct {
   double ms_mfma_total;      /* many-RHS operator products on the matrix cores          */
   int64_t mfma_launches;
   int64_t mfma_flops;        /* real flops of those GEMMs (8 per complex MAC)           */
+  int64_t lookahead_discarded; /* Arnoldi steps queued ahead of a convergence and
+                                  dropped (their operator products are not counted
+                                  in the solve's matvecs)                            */
 } pmchwt_profile;
 
 /* Version string of the library. */

@@ -1414,21 +1414,22 @@ float* mfma_ws(pmchwt_ctx* c, int nrhs) {
 void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
   c->calls_A += 1;
-  launch_zero(y, 2 * vs * nrhs, c->stream);
-  EvTimer t(c->stream);
   if (c->comb && !(c->precA == PMCHWT_MIXED && nrhs >= MFMA_MIN_RHS)) {
+    EvTimer t(c->stream);  // one launch writes every row of y: no clearing pass
     if (c->precA == PMCHWT_FP64)
       launch_gemv_pmchwt3<double>(c->AC.as<double>(), c->AS1.as<double>(), c->AS2.as<double>(), c->ldE, int(E), int(E),
-                                  x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+                                  x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream, false);
     else
       launch_gemv_pmchwt3<float>(c->AC.as<float>(), c->AS1.as<float>(), c->AS2.as<float>(), c->ldE, int(E), int(E), x,
-                                 x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+                                 x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream, false);
     HIPCHK(hipGetLastError());
     c->prof.ms_matvec_total += t.stop();
     c->prof.matvec_launches += 1;
     c->prof.matvec_bytes += 3 * E * E * (c->precA == PMCHWT_FP64 ? 16 : 8);
     return;
   }
+  launch_zero(y, 2 * vs * nrhs, c->stream);
+  EvTimer t(c->stream);
   if (c->precA == PMCHWT_FP64) {
     launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
@@ -1502,21 +1503,24 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
       launch_gemv_real2(c->Minv[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, c->stream);
   }
-  launch_zero(t2, 2 * vs * nrhs, c->stream);
+  // the interior launches write disjoint row ranges that cover every row of
+  // t2 (scatterer m owns rows edge_off .. edge_off + E_m of both halves), so
+  // the first writer overwrites and t2 needs no clearing pass
   const int64_t* rp = c->p_rowptr.as<int64_t>();
   const int32_t* cl = c->p_col.as<int32_t>();
+  if (!c->P_int && !c->P_ext) launch_zero(t2, 2 * vs * nrhs, c->stream);
   if (c->P_int) {
     for (size_t m = 0; m < c->sc.size(); ++m) {
       const Scat& s = c->sc[m];
       const int64_t o = s.edge_off;
       launch_spmv_pmchwt<double>(rp + o, cl, c->PSi.as<double>(), c->P_C ? c->PCi.as<double>() : nullptr, s.topo.E,
                                  s.k.real(), s.k.imag(), t1, t1 + 2 * E, t2 + 2 * o, t2 + 2 * (E + o), nrhs, vs,
-                                 c->stream);
+                                 c->stream, false);
     }
   }
   if (c->P_ext)
     launch_spmv_pmchwt<double>(rp, cl, c->PSe.as<double>(), c->P_C ? c->PCe.as<double>() : nullptr, int(E), c->k_ext,
-                               0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, nrhs, vs, c->stream);
+                               0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, nrhs, vs, c->stream, c->P_int);
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
@@ -1720,6 +1724,16 @@ struct PinnedBuf {
 // enqueues work on the context's stream and waits at the start of the next
 // stage for what it needs on the host, so several runs advanced stage by
 // stage overlap on the device.  The blocking gmres() below drives one run.
+//
+// Arnoldi step j (CGS2: two projection passes, the norm and the normalised
+// new basis vector) runs entirely on the device.  The host's part of step j
+// (Hessenberg column, Givens rotations, residual estimate, convergence) is
+// taken one step late, while step j+1 is already queued, so the device never
+// waits for the host inside a cycle.  A step queued after the one in which
+// every right-hand side converged is discarded (its basis vector is never
+// used); a cycle's last step (restart length or iteration limit) is taken
+// without look-ahead.  Iterates and iteration counts are those of the
+// unlagged method.
 struct GmresRun {
   enum Phase { ITER, RESID, DONE };
   pmchwt_ctx* c;
@@ -1729,25 +1743,38 @@ struct GmresRun {
   double tol;
   int64_t vs, vecd, vstep;
   int n;
-  double *V, *w, *r, *s1, *s2, *s3, *dh, *dn;
+  double *V, *w, *r, *s1, *s2, *s3, *dpar, *dres, *dn;
   DBuf dact, dscale, dy, dupd, dpart;
   PinnedBuf hpin;
-  double *h_hbuf, *h_hn, *h_scale, *h_y, *h_beta;
-  int32_t *h_act, *h_upd;
-  hipEvent_t ev = nullptr;
+  // per-step results on the host, two slots (step j uses slot j & 1):
+  // first-pass projections, second-pass projections, norm of the new vector
+  double* h_res[2];
+  int32_t* h_act[2];
+  double *h_scale, *h_y, *h_beta;
+  int32_t* h_upd;
+  hipEvent_t ev = nullptr, ev_step[2] = {nullptr, nullptr};
   GmresOut out;
-  std::vector<double> bnorm, beta, hsum;
-  std::vector<int32_t> active;
+  std::vector<double> bnorm, beta;
+  std::vector<int32_t> active, dev_active;  // host view; what the device's mask holds
   std::vector<cd> H, cs, sn, g;
   std::vector<int> jend, done_cycle;
   int total = 0, j = 0;
   bool all_done = false;
+  bool pend = false;   // step j-1 queued, its host part not yet taken
+  bool ended = false;  // the cycle ended in this step's stage2
   Phase phase = DONE;
   Phase step = DONE;  // phase in which the current step started (set by stage1)
 
+  // partial sums of one step on the device: two projection passes of at most
+  // 2 (1024 + (rho+1) nrhs) doubles each, the norm's at most 256 + nrhs; the
+  // finished values [h1 | h2 | norms] the host reads (kept small: copies of
+  // a few KB go through the compute queue, larger ones through a copy engine
+  // with a cross-queue wait)
+  static size_t part_doubles(int nrhs, int rho) { return 4 * (1024 + size_t(rho + 1) * nrhs) + 256 + nrhs; }
+  static size_t res_doubles(int nrhs, int rho) { return 4 * size_t(rho + 1) * nrhs + nrhs; }
   static size_t pinned_bytes(int nrhs, int rho) {
-    return 8 * (2 * size_t(rho + 2) * nrhs + 2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs + nrhs) +
-           4 * 2 * size_t(nrhs) + 64;
+    return 8 * (2 * res_doubles(nrhs, rho) + 2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs) +
+           4 * 3 * size_t(nrhs) + 64;
   }
   cd& Hm(int q, int i, int jj) { return H[(size_t(q) * (rho + 1) + i) * rho + jj]; }
 
@@ -1758,7 +1785,8 @@ struct GmresRun {
     n = int(vs);
     vecd = 2 * vs;
     vstep = int64_t(nrhs) * vs;
-    const size_t need = size_t(rho + 1 + 5) * nrhs * vecd + 4 * size_t(rho + 2) * nrhs + 16 * size_t(nrhs);
+    const size_t need =
+        size_t(rho + 1 + 5) * nrhs * vecd + part_doubles(nrhs, rho) + res_doubles(nrhs, rho) + 16 * size_t(nrhs);
     double* W = need_work(c, need);
     V = W;
     w = V + size_t(rho + 1) * nrhs * vecd;
@@ -1766,22 +1794,26 @@ struct GmresRun {
     s1 = r + nrhs * vecd;
     s2 = s1 + nrhs * vecd;
     s3 = s2 + nrhs * vecd;
-    dh = s3 + nrhs * vecd;
-    dn = dh + 2 * size_t(rho + 2) * nrhs;
+    dpar = s3 + nrhs * vecd;                   // step partial sums
+    dres = dpar + part_doubles(nrhs, rho);     // step results for the host
+    dn = dres + res_doubles(nrhs, rho);        // nrhs doubles, norms outside the cycle
     dact = dalloc<int32_t>(nrhs);
     dupd = dalloc<int32_t>(nrhs);
     dscale = dalloc<double>(nrhs);
     dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
     dpart = dalloc<double>(2 * (size_t(rho + 2) * nrhs + 1024));
     double* hp = static_cast<double*>(hpin.p);
-    h_hbuf = hp;
-    h_hn = h_hbuf + 2 * size_t(rho + 2) * nrhs;
-    h_scale = h_hn + nrhs;
+    h_res[0] = hp;
+    h_res[1] = h_res[0] + res_doubles(nrhs, rho);
+    h_scale = h_res[1] + res_doubles(nrhs, rho);
     h_y = h_scale + nrhs;
     h_beta = h_y + 2 * size_t(rho + 1) * nrhs;
-    h_act = reinterpret_cast<int32_t*>(h_beta + nrhs);
-    h_upd = h_act + nrhs;
+    h_act[0] = reinterpret_cast<int32_t*>(h_beta + nrhs);
+    h_act[1] = h_act[0] + nrhs;
+    h_upd = h_act[1] + nrhs;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_step[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_step[1], hipEventDisableTiming));
     out.iters.assign(nrhs, 0);
     out.restarts.assign(nrhs, 0);
     out.relres.assign(nrhs, 1.0);
@@ -1800,6 +1832,8 @@ struct GmresRun {
     // the pinned buffers and small device arrays may still feed queued copies
     (void)hipStreamSynchronize(c->stream);
     if (ev) (void)hipEventDestroy(ev);
+    for (auto e : ev_step)
+      if (e) (void)hipEventDestroy(e);
   }
 
   void wait() { HIPCHK(hipEventSynchronize(ev)); }
@@ -1823,6 +1857,7 @@ struct GmresRun {
     begin_cycle();
   }
 
+  // called with nothing of this run left in flight that reads h_act or h_scale
   void begin_cycle() {
     bool any = false;
     for (int q = 0; q < nrhs; ++q) {
@@ -1834,10 +1869,11 @@ struct GmresRun {
       return;
     }
     for (int q = 0; q < nrhs; ++q) {
-      h_act[q] = active[q];
+      h_act[0][q] = active[q];
       h_scale[q] = active[q] ? 1.0 / beta[q] : 0.0;
     }
-    HIPCHK(hipMemcpyAsync(dact.p, h_act, 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dact.p, h_act[0], 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+    dev_active = active;
     HIPCHK(hipMemcpyAsync(dscale.p, h_scale, 8 * nrhs, hipMemcpyHostToDevice, c->stream));
     launch_scale_copy(r, vs, V, vs, n, nrhs, dscale.as<double>(), c->stream);
     std::fill(H.begin(), H.end(), cd(0));
@@ -1846,6 +1882,7 @@ struct GmresRun {
     jend.assign(nrhs, 0);
     done_cycle.assign(nrhs, 0);
     j = 0;
+    pend = false;
     phase = ITER;
   }
 
@@ -1854,12 +1891,26 @@ struct GmresRun {
 
   void stage1() {
     step = phase;
-    if (step == ITER) {  // CGS2, first pass
-      hsum.assign(2 * size_t(j + 1) * nrhs, 0.0);
-      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream, dpart.as<double>());
-      launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
-      HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
-      mark();
+    ended = false;
+    if (step == ITER) {  // CGS2 (two passes), the norm, v_{j+1} = w / |w|
+      // the split reductions stay as partial sums: the update kernels, the
+      // normalisation and the host each add them in the same order
+      const int S1 = dots_splits(j + 1, nrhs, n), S2 = norm_splits(nrhs, n);
+      const size_t m = 2 * size_t(S1) * (j + 1) * nrhs;
+      double* h1 = dpar;
+      double* h2 = dpar + m;
+      double* hn = dpar + 2 * m;
+      const int32_t* act = dact.as<int32_t>();
+      dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, c->stream);
+      launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, j + 1, -1.0, c->stream, S1);
+      dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, c->stream);
+      launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, j + 1, -1.0, c->stream, S1);
+      norms_part_only(w, vs, n, nrhs, hn, c->stream);
+      launch_finish_step(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, hn, S2, act, h1, h2, S1, j + 1, dres,
+                         c->stream);
+      const size_t fin = 4 * size_t(j + 1) * nrhs + nrhs;
+      HIPCHK(hipMemcpyAsync(h_res[j & 1], dres, 8 * fin, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipEventRecord(ev_step[j & 1], c->stream));
     } else if (step == RESID) {  // r = bt - Op x
       launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
       launch_norms(r, vs, n, nrhs, dn, c->stream, dpart.as<double>());
@@ -1869,15 +1920,14 @@ struct GmresRun {
   }
 
   void stage2() {
-    if (step == ITER) {  // second pass and the new vector's norm
-      wait();
-      for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += h_hbuf[k];
-      launch_dots(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, c->stream, dpart.as<double>());
-      launch_update(V, vstep, j + 1, w, vs, n, dact.as<int32_t>(), nrhs, vs, dh, j + 1, -1.0, c->stream);
-      HIPCHK(hipMemcpyAsync(h_hbuf, dh, 16 * size_t(j + 1) * nrhs, hipMemcpyDeviceToHost, c->stream));
-      launch_norms(w, vs, n, nrhs, dn, c->stream, dpart.as<double>());
-      HIPCHK(hipMemcpyAsync(h_hn, dn, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
-      mark();
+    if (step == ITER) {  // the host part of the previous step
+      if (!pend) return;
+      pend = false;
+      HIPCHK(hipEventSynchronize(ev_step[(j - 1) & 1]));
+      if (column(j - 1)) {
+        end_cycle(j - 1);
+        ended = true;
+      }
     } else if (step == RESID) {
       wait();
       for (int q = 0; q < nrhs; ++q) {
@@ -1892,59 +1942,83 @@ struct GmresRun {
   }
 
   void stage3() {
-    if (step != ITER) return;
-    wait();
-    for (size_t k = 0; k < 2 * size_t(j + 1) * nrhs; ++k) hsum[k] += h_hbuf[k];
-    for (int q = 0; q < nrhs; ++q) h_scale[q] = (active[q] && h_hn[q] > 0) ? 1.0 / h_hn[q] : 0.0;
-    HIPCHK(hipMemcpyAsync(dscale.p, h_scale, 8 * nrhs, hipMemcpyHostToDevice, c->stream));
-    launch_scale_copy(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, dscale.as<double>(), c->stream);
+    if (step != ITER || ended) return;
+    if (j + 1 >= rho || total + 1 >= max_iter) {  // the cycle's last step: no look-ahead
+      HIPCHK(hipEventSynchronize(ev_step[j & 1]));
+      column(j);
+      end_cycle(j);
+      return;
+    }
+    pend = true;
+    ++j;
+  }
+
+  // Host part of step jj: Hessenberg column, Givens rotations, residual
+  // estimate, per-RHS convergence.  True when the cycle ends after it.
+  bool column(int jj) {
+    const int sl = jj & 1;
+    const size_t m = 2 * size_t(jj + 1) * nrhs;
+    const double* h1 = h_res[sl];
+    const double* h2 = h1 + m;
+    const double* hn = h1 + 2 * m;
     ++total;
     all_done = true;
     for (int q = 0; q < nrhs; ++q) {
       if (!active[q]) continue;
       out.iters[q] += 1;
-      for (int i = 0; i <= j; ++i)
-        Hm(q, i, j) = cd(hsum[2 * (size_t(q) * (j + 1) + i)], hsum[2 * (size_t(q) * (j + 1) + i) + 1]);
-      Hm(q, j + 1, j) = h_hn[q];
-      for (int i = 0; i < j; ++i) {
-        const cd a = Hm(q, i, j), b = Hm(q, i + 1, j);
-        const cd c_ = cs[size_t(q) * rho + i], s_ = sn[size_t(q) * rho + i];
-        Hm(q, i, j) = c_ * a + s_ * b;
-        Hm(q, i + 1, j) = -std::conj(s_) * a + std::conj(c_) * b;
+      for (int i = 0; i <= jj; ++i) {
+        const size_t o = 2 * (size_t(q) * (jj + 1) + i);
+        Hm(q, i, jj) = cd(h1[o] + h2[o], h1[o + 1] + h2[o + 1]);
       }
-      const cd a = Hm(q, j, j), b = Hm(q, j + 1, j);
+      Hm(q, jj + 1, jj) = hn[q];
+      for (int i = 0; i < jj; ++i) {
+        const cd a = Hm(q, i, jj), b = Hm(q, i + 1, jj);
+        const cd c_ = cs[size_t(q) * rho + i], s_ = sn[size_t(q) * rho + i];
+        Hm(q, i, jj) = c_ * a + s_ * b;
+        Hm(q, i + 1, jj) = -std::conj(s_) * a + std::conj(c_) * b;
+      }
+      const cd a = Hm(q, jj, jj), b = Hm(q, jj + 1, jj);
       const double den = std::sqrt(std::norm(a) + std::norm(b));
       const cd c_ = den > 0 ? std::conj(a) / den : cd(1), s_ = den > 0 ? std::conj(b) / den : cd(0);
-      cs[size_t(q) * rho + j] = c_;
-      sn[size_t(q) * rho + j] = s_;
-      Hm(q, j, j) = den;
-      Hm(q, j + 1, j) = 0;
-      cd& gj = g[size_t(q) * (rho + 1) + j];
-      g[size_t(q) * (rho + 1) + j + 1] = -std::conj(s_) * gj;
+      cs[size_t(q) * rho + jj] = c_;
+      sn[size_t(q) * rho + jj] = s_;
+      Hm(q, jj, jj) = den;
+      Hm(q, jj + 1, jj) = 0;
+      cd& gj = g[size_t(q) * (rho + 1) + jj];
+      g[size_t(q) * (rho + 1) + jj + 1] = -std::conj(s_) * gj;
       gj = c_ * gj;
-      const double res = std::abs(g[size_t(q) * (rho + 1) + j + 1]) / bnorm[q];
+      const double res = std::abs(g[size_t(q) * (rho + 1) + jj + 1]) / bnorm[q];
       out.relres[q] = res;
-      jend[q] = j + 1;
+      jend[q] = jj + 1;
       // converged inside the cycle (a convergence exactly at the cycle end
       // still goes through the cycle-end residual, as Table 1 counts it)
-      if (res <= tol && j + 1 < rho) {
+      if (res <= tol && jj + 1 < rho) {
         done_cycle[q] = 1;
         active[q] = 0;
       } else {
         all_done = false;
       }
     }
-    for (int q = 0; q < nrhs; ++q) h_act[q] = active[q];
-    HIPCHK(hipMemcpyAsync(dact.p, h_act, 4 * nrhs, hipMemcpyHostToDevice, c->stream));
-    if (all_done || j + 1 >= rho || total >= max_iter)
-      end_cycle();
-    else
-      ++j;
+    // the copy (only when the active set changed) reads slot sl when it runs;
+    // the slot is next written by the host part of step jj + 2, after the
+    // device has passed step jj + 2
+    if (active != dev_active) {
+      for (int q = 0; q < nrhs; ++q) h_act[sl][q] = active[q];
+      HIPCHK(hipMemcpyAsync(dact.p, h_act[sl], 4 * nrhs, hipMemcpyHostToDevice, c->stream));
+      dev_active = active;
+    }
+    return all_done || jj + 1 >= rho || total >= max_iter;
   }
 
   // x += V y for every right-hand side that iterated in this cycle; then the
-  // cycle-end residual, or done
-  void end_cycle() {
+  // cycle-end residual, or done.  Steps queued after jj are discarded.
+  void end_cycle(int jj) {
+    if (j > jj) {  // step j was queued ahead and is dropped: its products are no matvecs of the method
+      c->calls_A -= 1;
+      if (c->precond != PMCHWT_P_I) c->calls_P -= 1;
+      c->prof.lookahead_discarded += 1;
+    }
+    pend = false;
     int maxj = 0;
     for (int q = 0; q < nrhs; ++q) {
       const int m = jend[q];
@@ -2314,6 +2388,10 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     c->prof.ms_matvec_total = 0;
     c->prof.matvec_launches = 0;
     c->prof.matvec_bytes = 0;
+    c->prof.ms_mfma_total = 0;
+    c->prof.mfma_launches = 0;
+    c->prof.mfma_flops = 0;
+    c->prof.lookahead_discarded = 0;
     build_rhs(c, dirs, pols, nrhs, b.as<double>());
     c->calls_A = 0;  // the right-hand side's own interior products are not solver matvecs
     c->calls_P = 0;

@@ -109,6 +109,24 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
         for (int d = 0; d < 3; ++d) P2[k][d] = R(p.tv[(3 * k + d) * F + t2] - c1[d]);
       const R AA = R(A1 * p.tarea[t2]);
       const int off = c_rule_off[q], n = c_rule_n[q];
+      // FP32: trial-side points and weights of the rule (at most 6) in
+      // registers, the innermost loop unrolled with a guard so that it reads
+      // no memory.  FP64 keeps the rolled loop (the register copy would spill).
+      constexpr bool REG = sizeof(R) == 4;
+      R yb[REG ? 6 : 1][3], wb[REG ? 6 : 1];
+      if constexpr (REG) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+          if (b < n) {
+            const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) yb[b][d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
+            wb[b] = R(c_rule_w[off + b]);
+          } else {
+            yb[b][0] = yb[b][1] = yb[b][2] = wb[b] = R(0);
+          }
+        }
+      }
       // one wavenumber at a time keeps 14 complex accumulators live, not 28
       for (int kk = 0; kk < (inner ? 2 : 1); ++kk) {
         Moments<R> mm;
@@ -122,16 +140,28 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
 #pragma unroll
           for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
           const R wa = R(c_rule_w[off + a]) * AA;
-#pragma unroll 1
-          for (int b = 0; b < n; ++b) {
-            R y[3];
-            const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
+          if constexpr (REG) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
-            const R w = wa * R(c_rule_w[off + b]);
-            const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            mm.add(helmholtz<R>(r2, kr, ki, decay, w), x, y, true);
+            for (int b = 0; b < 6; ++b) {
+              if (b < n) {
+                const R w = wa * wb[b];
+                const R dx = x[0] - yb[b][0], dy = x[1] - yb[b][1], dz = x[2] - yb[b][2];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                mm.add(helmholtz<R>(r2, kr, ki, decay, w), x, yb[b], true);
+              }
+            }
+          } else {
+#pragma unroll 1
+            for (int b = 0; b < n; ++b) {
+              R y[3];
+              const R lb0 = R(c_rule_l[off + b][0]), lb1 = R(c_rule_l[off + b][1]), lb2 = R(c_rule_l[off + b][2]);
+#pragma unroll
+              for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
+              const R w = wa * R(c_rule_w[off + b]);
+              const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+              const R r2 = dx * dx + dy * dy + dz * dz;
+              mm.add(helmholtz<R>(r2, kr, ki, decay, w), x, y, true);
+            }
           }
         }
         if (kk == 0) {

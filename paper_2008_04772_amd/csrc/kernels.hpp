@@ -176,7 +176,8 @@ void launch_gemv_pmchwt_grouped(const GemvJob<M>* jobs_dev, int njobs, int nr, i
 // S2 = -(ke Se + ki Si) (launch_combine3 builds them, n complex entries)
 template <typename M>
 void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int rows, int cols, const double* xD,
-                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st);
+                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st,
+                         bool acc = true);
 template <typename M>
 void launch_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir, double kii,
                      M* C, M* S1, M* S2, hipStream_t st);
@@ -196,7 +197,7 @@ void launch_mfma_real2(const float* Mat, int64_t ld, int rows, int cols, double 
 template <typename M>
 void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows,
                         double kr, double ki, const double* xD, const double* xN, double* yD, double* yN,
-                        int nrhs, int64_t vstride, hipStream_t st);
+                        int nrhs, int64_t vstride, hipStream_t st, bool acc = true);
 // y = alpha * Mreal x (dense real row-major, rows x cols), complex vectors
 void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
@@ -238,12 +239,29 @@ void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec
 void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
                  const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st,
                  double* part = nullptr);
+// w += sign V h; the coefficient (r, i) is the sum of S partial values
+// h[(r hstride + i) S + s] (complex), added in order of s
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride,
-                   double sign, hipStream_t st);
+                   double sign, hipStream_t st, int S = 1);
 // part (optional): scratch of nrhs + 256 doubles for a split reduction
 void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st,
                   double* part = nullptr);
+// Split reductions left unfinished: the consumer (launch_update, the host)
+// adds the partial values in order.  Both return S, the partials per result.
+//   dots:  part[((r nvec + i) S + s)] complex, at most 2 (1024 + nvec nrhs) doubles
+//   norms: part[r S + s] partial sums of squares, at most 256 + nrhs doubles
+int dots_splits(int nvec, int nrhs, int n);
+int norm_splits(int nrhs, int n);
+int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
+                   const int32_t* active, int nrhs, int64_t rstride_v, double* part, hipStream_t st);
+int norms_part_only(const double* w, int64_t wstride, int n, int nrhs, double* part, hipStream_t st);
+// v = w / sqrt(sum_s nrm2[r S2 + s]) per right-hand side (0 where inactive or
+// zero); also the finished sums fin = [h1 | h2 | norms] of the step's two
+// projection passes (h1p, h2p: S1 partials per coefficient, nvec coefficients)
+void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
+                        const double* nrm2, int S2, const int32_t* active, const double* h1p, const double* h2p,
+                        int S1, int nvec, double* fin, hipStream_t st);
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,

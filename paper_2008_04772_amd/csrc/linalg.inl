@@ -201,18 +201,22 @@ template int gemv_blocks<double>(int, int);
 
 // Single scatterer: A = A^e + A^i applied from three pre-combined matrices
 //   C = C^e + C^i,  S1 = S^e/k_e + S^i/k_i,  S2 = -(k_e S^e + k_i S^i),
-//   yD += C xD + S1 xN,  yN += C xN + S2 xD
-// (three operator reads per row instead of four).
-template <typename M, int NR>
+//   yD (+)= C xD + S1 xN,  yN (+)= C xN + S2 xD
+// (three operator reads per row instead of four).  A workgroup has four
+// wavefronts; KS of them share a group of ROWS rows and take consecutive
+// column ranges (more wavefronts in flight when the rows alone give too few),
+// their partial sums added in a fixed order through LDS.
+template <typename M, int NR, int KS>
 __global__ __launch_bounds__(256) void k_gemv_pmchwt3(const M* __restrict__ C, const M* __restrict__ S1,
                                                       const M* __restrict__ S2, int64_t ld, int rows, int cols,
                                                       const double* __restrict__ xD, const double* __restrict__ xN,
-                                                      double* yD, double* yN, int64_t vstride) {
+                                                      double* yD, double* yN, int64_t vstride, int acc) {
   constexpr int ROWS = GemvRows<M, NR>::value;
   typedef typename CPair<M>::T V;
-  const int lane = threadIdx.x & 63;
-  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
-  if (row0 >= rows) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int part = wv % KS;
+  const int row0 = ROWS * (blockIdx.x * (4 / KS) + wv / KS);
+  const bool live = row0 < rows;  // no early exit: every wavefront reaches the barrier
   const V* Cv[ROWS];
   const V* Av[ROWS];
   const V* Bv[ROWS];
@@ -229,7 +233,8 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt3(const M* __restrict__ C, c
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
   const int np = (cols + 1) >> 1;
-  for (int q = lane; q < np; q += 64) {
+  const int q0 = int(int64_t(np) * part / KS), q1 = live ? int(int64_t(np) * (part + 1) / KS) : q0;
+  for (int q = q0 + lane; q < q1; q += 64) {
     V cv[ROWS], av[ROWS], bv[ROWS];
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
@@ -281,7 +286,29 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt3(const M* __restrict__ C, c
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[h][r][q] = wsum(a[h][r][q]);
-  if (lane == 0) {
+  if (KS > 1) {
+    __shared__ double red[4][ROWS * NR * 4];
+    if (lane == 0 && part > 0) {
+#pragma unroll
+      for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) red[wv][(h * NR + r) * 4 + q] = a[h][r][q];
+    }
+    __syncthreads();
+    if (lane == 0 && part == 0) {
+#pragma unroll
+      for (int p = 1; p < KS; ++p)
+#pragma unroll
+        for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[h][r][q] += red[wv + p][(h * NR + r) * 4 + q];
+    }
+  }
+  if (lane == 0 && part == 0 && live) {
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
       if (row0 + h >= rows) break;
@@ -289,20 +316,40 @@ __global__ __launch_bounds__(256) void k_gemv_pmchwt3(const M* __restrict__ C, c
       for (int r = 0; r < NR; ++r) {
         double* yd = yD + 2 * (int64_t(r) * vstride + row0 + h);
         double* yn = yN + 2 * (int64_t(r) * vstride + row0 + h);
-        yd[0] += a[h][r][0];
-        yd[1] += a[h][r][1];
-        yn[0] += a[h][r][2];
-        yn[1] += a[h][r][3];
+        const double o0 = acc ? yd[0] : 0.0, o1 = acc ? yd[1] : 0.0, o2 = acc ? yn[0] : 0.0, o3 = acc ? yn[1] : 0.0;
+        yd[0] = o0 + a[h][r][0];
+        yd[1] = o1 + a[h][r][1];
+        yn[0] = o2 + a[h][r][2];
+        yn[1] = o3 + a[h][r][3];
       }
     }
   }
 }
 
+template <typename M, int NR>
+static void gemv3_launch(int rows, const M* C, const M* S1, const M* S2, int64_t ld, int cols, const double* xd,
+                         const double* xn, double* yd, double* yn, int64_t vstride, bool acc, hipStream_t st) {
+  constexpr int ROWS = GemvRows<M, NR>::value;
+  const int groups = (rows + ROWS - 1) / ROWS;
+  // split the columns of a row group over 4 or 2 wavefronts while the row
+  // groups alone are fewer than one per CU / one per SIMD (measured on the
+  // 7680-column operator: 2-way equal to 1-way; on 1920 and 3840 columns:
+  // 2.0x and 1.45x faster than 1-way)
+  if (groups <= 256)
+    hipLaunchKernelGGL((k_gemv_pmchwt3<M, NR, 4>), dim3(unsigned(groups)), dim3(256), 0, st, C, S1, S2, ld, rows, cols,
+                       xd, xn, yd, yn, vstride, int(acc));
+  else if (groups <= 1024)
+    hipLaunchKernelGGL((k_gemv_pmchwt3<M, NR, 2>), dim3(unsigned((groups + 1) / 2)), dim3(256), 0, st, C, S1, S2, ld,
+                       rows, cols, xd, xn, yd, yn, vstride, int(acc));
+  else
+    hipLaunchKernelGGL((k_gemv_pmchwt3<M, NR, 1>), dim3(unsigned((groups + 3) / 4)), dim3(256), 0, st, C, S1, S2, ld,
+                       rows, cols, xd, xn, yd, yn, vstride, int(acc));
+}
+
 template <typename M>
 void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int rows, int cols, const double* xD,
-                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st) {
-  auto grid = [rows](int rpw) { return dim3(unsigned((rows + 4 * rpw - 1) / (4 * rpw))); };
-  const dim3 block(256);
+                         const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, hipStream_t st,
+                         bool acc) {
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const double* xd = xD + 2 * int64_t(r0) * vstride;
@@ -310,24 +357,22 @@ void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int r
     double* yd = yD + 2 * int64_t(r0) * vstride;
     double* yn = yN + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 4>), grid(GemvRows<M, 4>::value), block, 0, st, C, S1, S2, ld, rows, cols,
-                         xd, xn, yd, yn, vstride);
+      gemv3_launch<M, 4>(rows, C, S1, S2, ld, cols, xd, xn, yd, yn, vstride, acc, st);
       r0 += 4;
     } else if (left >= 2) {
-      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 2>), grid(GemvRows<M, 2>::value), block, 0, st, C, S1, S2, ld, rows, cols,
-                         xd, xn, yd, yn, vstride);
+      gemv3_launch<M, 2>(rows, C, S1, S2, ld, cols, xd, xn, yd, yn, vstride, acc, st);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_gemv_pmchwt3<M, 1>), grid(GemvRows<M, 1>::value), block, 0, st, C, S1, S2, ld, rows, cols,
-                         xd, xn, yd, yn, vstride);
+      gemv3_launch<M, 1>(rows, C, S1, S2, ld, cols, xd, xn, yd, yn, vstride, acc, st);
       r0 += 1;
     }
   }
 }
 template void launch_gemv_pmchwt3<float>(const float*, const float*, const float*, int64_t, int, int, const double*,
-                                         const double*, double*, double*, int, int64_t, hipStream_t);
+                                         const double*, double*, double*, int, int64_t, hipStream_t, bool);
 template void launch_gemv_pmchwt3<double>(const double*, const double*, const double*, int64_t, int, int,
-                                          const double*, const double*, double*, double*, int, int64_t, hipStream_t);
+                                          const double*, const double*, double*, double*, int, int64_t, hipStream_t,
+                                          bool);
 
 // C = Ce + Ci, S1 = Se/ke + Si/ki, S2 = -(ke Se + ki Si), per complex entry
 template <typename M>
@@ -400,7 +445,7 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
                                                      const M* __restrict__ C, int rows, double kr, double ki,
                                                      const double* __restrict__ xD,
                                                      const double* __restrict__ xN, double* yD, double* yN,
-                                                     int64_t vstride) {
+                                                     int64_t vstride, int acc) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= rows) return;
@@ -443,10 +488,11 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
       double* yn = yN + 2 * (int64_t(r) * vstride + row);
       const double t_re = a[r][2] * ikr - a[r][3] * iki, t_im = a[r][2] * iki + a[r][3] * ikr;
       const double u_re = -(kr * a[r][4] - ki * a[r][5]), u_im = -(kr * a[r][5] + ki * a[r][4]);
-      yd[0] += a[r][0] + t_re;
-      yd[1] += a[r][1] + t_im;
-      yn[0] += u_re + a[r][6];
-      yn[1] += u_im + a[r][7];
+      const double o0 = acc ? yd[0] : 0.0, o1 = acc ? yd[1] : 0.0, o2 = acc ? yn[0] : 0.0, o3 = acc ? yn[1] : 0.0;
+      yd[0] = o0 + (a[r][0] + t_re);
+      yd[1] = o1 + (a[r][1] + t_im);
+      yn[0] = o2 + (u_re + a[r][6]);
+      yn[1] = o3 + (u_im + a[r][7]);
     }
   }
 }
@@ -454,7 +500,7 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
 template <typename M>
 void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows, double kr,
                         double ki, const double* xD, const double* xN, double* yD, double* yN, int nrhs,
-                        int64_t vstride, hipStream_t st) {
+                        int64_t vstride, hipStream_t st, bool acc) {
   const dim3 grid((rows + 3) / 4), block(256);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
@@ -464,21 +510,21 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
     double* yn = yN + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
       hipLaunchKernelGGL((k_spmv_pmchwt<M, 4>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
-                         yn, vstride);
+                         yn, vstride, int(acc));
       r0 += 4;
     } else {
       hipLaunchKernelGGL((k_spmv_pmchwt<M, 1>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
-                         yn, vstride);
+                         yn, vstride, int(acc));
       r0 += 1;
     }
   }
 }
 template void launch_spmv_pmchwt<double>(const int64_t*, const int32_t*, const double*, const double*, int,
                                          double, double, const double*, const double*, double*, double*, int,
-                                         int64_t, hipStream_t);
+                                         int64_t, hipStream_t, bool);
 template void launch_spmv_pmchwt<float>(const int64_t*, const int32_t*, const float*, const float*, int, double,
                                         double, const double*, const double*, double*, double*, int, int64_t,
-                                        hipStream_t);
+                                        hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // y = alpha * M x, M real dense row-major; complex vectors (overwrites y).
@@ -637,6 +683,20 @@ int dots_splits(int nvec, int nrhs, int n) {
   return std::max(1, std::min({want, 64, (n + 255) / 256}));
 }
 
+int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
+                   const int32_t* active, int nrhs, int64_t rstride_v, double* part, hipStream_t st) {
+  const int S = dots_splits(nvec, nrhs, n);
+  if (S == 1) {
+    hipLaunchKernelGGL(k_dots, dim3(nvec, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v, part,
+                       nvec);
+  } else {
+    const int chunk = (n + S - 1) / S;
+    hipLaunchKernelGGL(k_dots_part, dim3(nvec, S, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active,
+                       rstride_v, part, nvec, S, chunk);
+  }
+  return S;
+}
+
 void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
                  const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st, double* part) {
   const int S = part ? dots_splits(nvec, nrhs, n) : 1;
@@ -652,29 +712,80 @@ void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int6
   hipLaunchKernelGGL(k_dots_fin, dim3((m + 255) / 256), dim3(256), 0, st, part, S, m, out);
 }
 
-// w^r[k] += sign * sum_i V_i^r[k] h[r][i]
-__global__ void k_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
-                         const int32_t* active, int64_t rstride_v, const double* h, int64_t hstride, double sign) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// w^r[k] += sign * sum_i V_i^r[k] h[r][i], where each coefficient is the sum
+// of S partial values, h[r][i] = sum_s hp[(r hstride + i) S + s] (complex),
+// added in the order s = 0, 1, ... (S = 1: the coefficients themselves).  A
+// workgroup owns 64 consecutive elements; the coefficients of up to 1024
+// vectors at a time are summed into LDS, then its four wavefronts take every
+// fourth vector (coalesced 1 KB reads per vector, four loads in flight) and
+// the four partial results are added in a fixed order through LDS.
+__global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, int nvec, double* w,
+                                                int64_t wstride, int n, const int32_t* active, int64_t rstride_v,
+                                                const double* hp, int64_t hstride, int S, double sign) {
+  constexpr int CH = 1024;
   const int r = blockIdx.y;
-  if (k >= n || !active[r]) return;
+  if (!active[r]) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const bool in = k < n;
+  const int kk = in ? k : n - 1;
+  const double2* base = reinterpret_cast<const double2*>(V) + int64_t(r) * rstride_v + kk;
+  const double2* hr_ = reinterpret_cast<const double2*>(hp) + int64_t(r) * hstride * S;
+  __shared__ double2 hs[CH];
+  __shared__ double2 part[3][64];
   double re = 0, im = 0;
-  for (int i = 0; i < nvec; ++i) {
-    const double* v = V + 2 * (int64_t(i) * vstep + int64_t(r) * rstride_v + k);
-    const double hr = h[2 * (int64_t(r) * hstride + i)], hi = h[2 * (int64_t(r) * hstride + i) + 1];
-    re += v[0] * hr - v[1] * hi;
-    im += v[0] * hi + v[1] * hr;
+  for (int i0 = 0; i0 < nvec; i0 += CH) {
+    const int nc = min(CH, nvec - i0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+      double2 h = {0.0, 0.0};
+      for (int sidx = 0; sidx < S; ++sidx) {
+        const double2 v = hr_[int64_t(i0 + t) * S + sidx];
+        h.x += v.x;
+        h.y += v.y;
+      }
+      hs[t] = h;
+    }
+    __syncthreads();
+    const double2* bi = base + int64_t(i0) * vstep;
+    int i = wv;
+    for (; i + 12 < nc; i += 16) {
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = bi[int64_t(i + 4 * u) * vstep];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 h = hs[i + 4 * u];
+        re += v[u].x * h.x - v[u].y * h.y;
+        im += v[u].x * h.y + v[u].y * h.x;
+      }
+    }
+    for (; i < nc; i += 4) {
+      const double2 v = bi[int64_t(i) * vstep];
+      const double2 h = hs[i];
+      re += v.x * h.x - v.y * h.y;
+      im += v.x * h.y + v.y * h.x;
+    }
   }
-  double* ww = w + 2 * (int64_t(r) * wstride + k);
-  ww[0] += sign * re;
-  ww[1] += sign * im;
+  if (wv > 0) part[wv - 1][lane] = double2{re, im};
+  __syncthreads();
+  if (wv == 0 && in) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      re += part[q][lane].x;
+      im += part[q][lane].y;
+    }
+    double* ww = w + 2 * (int64_t(r) * wstride + k);
+    ww[0] += sign * re;
+    ww[1] += sign * im;
+  }
 }
 
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride, double sign,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_update, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
-                     rstride_v, h, hstride, sign);
+                   hipStream_t st, int S) {
+  hipLaunchKernelGGL(k_update, dim3((n + 63) / 64, nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
+                     rstride_v, h, hstride, S, sign);
 }
 
 __global__ void k_norms(const double* w, int64_t wstride, int n, double* out) {
@@ -716,8 +827,17 @@ __global__ void k_norms_fin(const double* part, int S, int nrhs, double* out) {
   out[r] = sqrt(s);
 }
 
+int norm_splits(int nrhs, int n) { return std::max(1, std::min({(256 + nrhs - 1) / nrhs, 64, (n + 255) / 256})); }
+
+int norms_part_only(const double* w, int64_t wstride, int n, int nrhs, double* part, hipStream_t st) {
+  const int S = norm_splits(nrhs, n);
+  const int chunk = (n + S - 1) / S;
+  hipLaunchKernelGGL(k_norms_part, dim3(S, nrhs), dim3(256), 0, st, w, wstride, n, S, chunk, part);
+  return S;
+}
+
 void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st, double* part) {
-  const int S = part ? std::max(1, std::min({(256 + nrhs - 1) / nrhs, 64, (n + 255) / 256})) : 1;
+  const int S = part ? norm_splits(nrhs, n) : 1;
   if (S == 1) {
     hipLaunchKernelGGL(k_norms, dim3(nrhs), dim3(256), 0, st, w, wstride, n, out);
     return;
@@ -740,6 +860,52 @@ __global__ void k_scale_copy(const double* w, int64_t wstride, double* v, int64_
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, w, wstride, v, vstride, n, scale);
+}
+
+// End of an Arnoldi step on the device: v = w / |w| per right-hand side (0
+// where inactive or |w| = 0), |w|^2 the sum of S2 partial values.  The first
+// workgroup of each right-hand side also finishes the two projection passes'
+// split sums (S1 partials per coefficient, nvec coefficients) and the norm
+// into fin = [h1 (nvec nrhs complex) | h2 (same) | |w| (nrhs)] for the host,
+// every sum taken in order of the partial index as the update kernels do.
+__global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n,
+                              const double* nrm2, int S2, const int32_t* active, const double* h1p,
+                              const double* h2p, int S1, int nvec, int nrhs, double* fin) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  double ss = 0;
+  for (int sidx = 0; sidx < S2; ++sidx) ss += nrm2[int64_t(r) * S2 + sidx];
+  const double h = sqrt(ss);
+  if (blockIdx.x == 0) {
+    const double2* p1 = reinterpret_cast<const double2*>(h1p) + int64_t(r) * nvec * S1;
+    const double2* p2 = reinterpret_cast<const double2*>(h2p) + int64_t(r) * nvec * S1;
+    double2* f1 = reinterpret_cast<double2*>(fin) + int64_t(r) * nvec;
+    double2* f2 = reinterpret_cast<double2*>(fin) + int64_t(nrhs) * nvec + int64_t(r) * nvec;
+    for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+      double2 a = {0.0, 0.0}, b = {0.0, 0.0};
+      for (int sidx = 0; sidx < S1; ++sidx) {
+        const double2 u = p1[int64_t(i) * S1 + sidx], t = p2[int64_t(i) * S1 + sidx];
+        a.x += u.x;
+        a.y += u.y;
+        b.x += t.x;
+        b.y += t.y;
+      }
+      f1[i] = a;
+      f2[i] = b;
+    }
+    if (threadIdx.x == 0) fin[4 * int64_t(nrhs) * nvec + r] = h;
+  }
+  if (k >= n) return;
+  const double s = (active[r] && h > 0) ? 1.0 / h : 0.0;
+  v[2 * (int64_t(r) * vstride + k)] = s * w[2 * (int64_t(r) * wstride + k)];
+  v[2 * (int64_t(r) * vstride + k) + 1] = s * w[2 * (int64_t(r) * wstride + k) + 1];
+}
+
+void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
+                        const double* nrm2, int S2, const int32_t* active, const double* h1p, const double* h2p,
+                        int S1, int nvec, double* fin, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_step, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, w, wstride, v, vstride, n, nrm2,
+                     S2, active, h1p, h2p, S1, nvec, nrhs, fin);
 }
 
 // y = a y + b x  (complex vectors, real scalars)
@@ -1034,16 +1200,17 @@ void launch_gj_take_columns(double* X, int64_t n, int p0, int b, double* C, hipS
 // Each lane loads 16 bytes of a row at a time (4 floats or 2 doubles; the
 // leading dimension is a multiple of 4 and the padding columns are zero),
 // non-temporal since the matrix is streamed once per application.
-template <typename M, int NR>
+template <typename M, int NR, int KS>
 __global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, int64_t ld, int rows, int cols,
                                                     double alpha, const double* __restrict__ x, double* y,
                                                     int64_t vstride, int64_t cstride) {
   constexpr int VEC = 16 / int(sizeof(M));
   constexpr int ROWS = NR >= 8 ? 1 : 8 / NR;
   typedef M Vt __attribute__((ext_vector_type(VEC)));
-  const int lane = threadIdx.x & 63;
-  const int row0 = ROWS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
-  if (row0 >= rows) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int part = wv % KS;
+  const int row0 = ROWS * (blockIdx.x * (4 / KS) + wv / KS);
+  const bool live = row0 < rows;  // no early exit: every wavefront reaches the barrier
   const Vt* mr[ROWS];
 #pragma unroll
   for (int h = 0; h < ROWS; ++h) mr[h] = reinterpret_cast<const Vt*>(Mat + int64_t(min(row0 + h, rows - 1)) * ld);
@@ -1053,7 +1220,8 @@ __global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, i
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[h][r][0] = a[h][r][1] = a[h][r][2] = a[h][r][3] = 0.0;
   const int nq = (cols + VEC - 1) / VEC;
-  for (int q = lane; q < nq; q += 64) {
+  const int q0 = int(int64_t(nq) * part / KS), q1 = live ? int(int64_t(nq) * (part + 1) / KS) : q0;
+  for (int q = q0 + lane; q < q1; q += 64) {
     Vt m[ROWS];
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) m[h] = __builtin_nontemporal_load(&mr[h][q]);
@@ -1083,40 +1251,77 @@ __global__ __launch_bounds__(256) void k_gemv_real2(const M* __restrict__ Mat, i
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[h][r][q] = wsum(a[h][r][q]);
-  if (lane == 0) {
+  if (KS > 1) {
+    __shared__ double red[4][ROWS * NR * 4];
+    if (lane == 0 && part > 0) {
+#pragma unroll
+      for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) red[wv][(h * NR + r) * 4 + q] = a[h][r][q];
+    }
+    __syncthreads();
+    if (lane == 0 && part == 0) {
+#pragma unroll
+      for (int p = 1; p < KS; ++p)
+#pragma unroll
+        for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[h][r][q] += red[wv + p][(h * NR + r) * 4 + q];
+    }
+  }
+  if (lane == 0 && part == 0 && live) {
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
       if (row0 + h >= rows) break;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        double* q0 = y + 2 * (int64_t(r) * vstride + row0 + h);
-        double* q1 = q0 + 2 * cstride;
-        q0[0] = alpha * a[h][r][0];
-        q0[1] = alpha * a[h][r][1];
-        q1[0] = alpha * a[h][r][2];
-        q1[1] = alpha * a[h][r][3];
+        double* q0p = y + 2 * (int64_t(r) * vstride + row0 + h);
+        double* q1p = q0p + 2 * cstride;
+        q0p[0] = alpha * a[h][r][0];
+        q0p[1] = alpha * a[h][r][1];
+        q1p[0] = alpha * a[h][r][2];
+        q1p[1] = alpha * a[h][r][3];
       }
     }
   }
 }
 
+// Column split only for few row groups: on the 7680-column mass inverse the
+// 2-way split is 1.4x slower than one wavefront per row group (more
+// concurrent row streams), on 1920 / 3840 columns 4- / 2-way are ~10% faster.
+template <typename M, int NR>
+static void real2_launch(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* xx, double* yy,
+                         int64_t vstride, int64_t cstride, hipStream_t st) {
+  constexpr int ROWS = NR >= 8 ? 1 : 8 / NR;
+  const int groups = (rows + ROWS - 1) / ROWS;
+  const dim3 block(256);
+  if (groups <= 256)
+    hipLaunchKernelGGL((k_gemv_real2<M, NR, 4>), dim3(unsigned(groups)), block, 0, st, Mat, ld, rows, cols, alpha, xx,
+                       yy, vstride, cstride);
+  else if (groups <= 512)
+    hipLaunchKernelGGL((k_gemv_real2<M, NR, 2>), dim3(unsigned((groups + 1) / 2)), block, 0, st, Mat, ld, rows, cols,
+                       alpha, xx, yy, vstride, cstride);
+  else
+    hipLaunchKernelGGL((k_gemv_real2<M, NR, 1>), dim3(unsigned((groups + 3) / 4)), block, 0, st, Mat, ld, rows, cols,
+                       alpha, xx, yy, vstride, cstride);
+}
+
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
-  const dim3 block(256);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const double* xx = x + 2 * int64_t(r0) * vstride;
     double* yy = y + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      const dim3 grid((rows + 7) / 8);
-      hipLaunchKernelGGL((k_gemv_real2<M, 4>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
-                         cstride);
+      real2_launch<M, 4>(Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride, st);
       r0 += 4;
     } else {
-      const dim3 grid((rows + 31) / 32);
-      hipLaunchKernelGGL((k_gemv_real2<M, 1>), grid, block, 0, st, Mat, ld, rows, cols, alpha, xx, yy, vstride,
-                         cstride);
+      real2_launch<M, 1>(Mat, ld, rows, cols, alpha, xx, yy, vstride, cstride, st);
       r0 += 1;
     }
   }
