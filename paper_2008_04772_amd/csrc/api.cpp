@@ -31,31 +31,85 @@ using cd = std::complex<double>;
 
 namespace {
 
+// Device blocks of one context, kept for reuse: a repeated assembly or solve
+// of the same problem then allocates and frees nothing (hipFree also waits for
+// the whole device).  Blocks are handed out again only within the context,
+// whose work is ordered on its stream (side-stream work is joined into it
+// before a block returns here), so a reused block is never still in use.
+struct BufPool {
+  std::multimap<size_t, void*> free;
+  size_t cached = 0;
+  static constexpr size_t CAP = size_t(96) << 30;  // cached bytes kept at most
+  BufPool() = default;
+  BufPool(const BufPool&) = delete;
+  BufPool& operator=(const BufPool&) = delete;
+  ~BufPool() { trim(0); }
+  void* take(size_t bytes) {
+    auto it = free.find(bytes);
+    if (it != free.end()) {
+      void* p = it->second;
+      free.erase(it);
+      cached -= bytes;
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) == hipSuccess) return p;
+    (void)hipGetLastError();
+    trim(0);  // give the cached blocks back and try once more
+    if (hipMalloc(&p, bytes) == hipSuccess) return p;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  void give(void* p, size_t bytes) {
+    free.emplace(bytes, p);
+    cached += bytes;
+    if (cached > CAP) trim(CAP / 2);
+  }
+  void trim(size_t keep) {  // largest blocks first
+    while (cached > keep && !free.empty()) {
+      auto it = std::prev(free.end());
+      (void)hipFree(it->second);
+      cached -= it->first;
+      free.erase(it);
+    }
+  }
+};
+
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  BufPool* pool = nullptr;  // owner of the block when it came from a context's pool
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), pool(o.pool) {
     o.p = nullptr;
     o.bytes = 0;
+    o.pool = nullptr;
   }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      pool = o.pool;
       o.p = nullptr;
       o.bytes = 0;
+      o.pool = nullptr;
     }
     return *this;
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (pool)
+        pool->give(p, bytes);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    pool = nullptr;
   }
   template <typename T>
   T* as() const {
@@ -106,6 +160,7 @@ struct CellDev {
 }  // namespace
 
 struct pmchwt_ctx {
+  BufPool pool;  // first member: destroyed after every buffer that returns to it
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -181,7 +236,7 @@ struct pmchwt_ctx {
   std::vector<int> slab_nrows;
   // trial-edge chunk tables of the atomic-free regular assembly (geometry only)
   int chunk_size = 0, nchunks = 0, max_list = 0;
-  DBuf chunk_ptr, chunk_tri, edge_map, edge_scat_d;
+  DBuf chunk_e, chunk_ptr, chunk_tri, edge_map, edge_scat_d;
   double recompute = 0.0;
 
   ~pmchwt_ctx() {
@@ -221,9 +276,29 @@ DBuf dalloc(size_t n) {
   return b;
 }
 
+// from the context's pool (see BufPool)
+template <typename T>
+DBuf dalloc_c(pmchwt_ctx* c, size_t n) {
+  DBuf b;
+  if (n == 0) n = 1;
+  b.p = c->pool.take(n * sizeof(T));
+  if (!b.p) throw Fail{PMCHWT_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+  b.bytes = n * sizeof(T);
+  b.pool = &c->pool;
+  return b;
+}
+
+// b = a pool block of n elements, the previous one returned first so that a
+// same-size block is reused in place
+template <typename T>
+void realloc_c(pmchwt_ctx* c, DBuf& b, size_t n) {
+  b.release();
+  b = dalloc_c<T>(c, n);
+}
+
 template <typename T>
 DBuf upload(pmchwt_ctx* c, const std::vector<T>& v) {
-  DBuf b = dalloc<T>(v.size());
+  DBuf b = dalloc_c<T>(c, v.size());
   if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
   return b;
 }
@@ -485,8 +560,8 @@ template <typename M>
 void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   const int64_t E = c->E_tot;
   c->ldE = padld(E);
-  c->Se = dalloc<M>(size_t(2 * E * c->ldE));
-  c->Ce = dalloc<M>(size_t(2 * E * c->ldE));
+  realloc_c<M>(c, c->Se, size_t(2 * E * c->ldE));
+  realloc_c<M>(c, c->Ce, size_t(2 * E * c->ldE));
   std::vector<M*> sp, cp;
   std::vector<int64_t> lds;
   c->Si.clear();
@@ -494,8 +569,8 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   c->ldI.clear();
   for (auto& s : c->sc) {
     const int64_t Em = s.topo.E, ld = padld(Em);
-    c->Si.push_back(dalloc<M>(size_t(2 * Em * ld)));
-    c->Ci.push_back(dalloc<M>(size_t(2 * Em * ld)));
+    c->Si.push_back(dalloc_c<M>(c, size_t(2 * Em * ld)));
+    c->Ci.push_back(dalloc_c<M>(c, size_t(2 * Em * ld)));
     sp.push_back(c->Si.back().as<M>());
     cp.push_back(c->Ci.back().as<M>());
     lds.push_back(ld);
@@ -566,9 +641,10 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     sp_.npts[k] = c->sing.npts[k];
   }
   const int64_t npts_sing = c->sing.point_pairs;
-  // trial-edge chunks: distinct T+/T- triangles of each chunk of consecutive edges
-  // (FP64 moments are twice as large: halve the chunk to bound the LDS footprint)
-  const int CH = sizeof(M) == 8 ? 64 : 128;
+  // trial-edge chunks: runs of consecutive edges whose distinct T+/T-
+  // triangles number at most the regular kernel's workgroup size (256 in
+  // FP32, 128 in FP64, where the moments take twice the LDS)
+  const int CH = regular_chunk_limit(sizeof(M) == 8);
   if (c->chunk_size != CH) {
     std::vector<int32_t> tp(c->E_tot), tm(c->E_tot), escat(c->E_tot);
     std::vector<int8_t> bp(c->E_tot), bm(c->E_tot);
@@ -587,31 +663,36 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
         }
       for (int e = 0; e < s.topo.E; ++e) escat[s.edge_off + e] = int32_t(m);
     }
-    const int nch = (c->E_tot + CH - 1) / CH;
-    std::vector<int32_t> cptr{0}, ctri;
+    std::vector<int32_t> cptr{0}, ctri, cedge{0};
     std::vector<int16_t> emap(4 * size_t(c->E_tot));
     std::unordered_map<int32_t, int16_t> pos;
     int maxl = 0;
-    for (int ch = 0; ch < nch; ++ch) {
-      pos.clear();
-      const int j0 = ch * CH, j1 = std::min(c->E_tot, j0 + CH);
-      auto slot = [&](int32_t t) -> int16_t {
-        auto it = pos.find(t);
-        if (it != pos.end()) return it->second;
-        const int16_t q = int16_t(pos.size());
-        pos.emplace(t, q);
-        ctri.push_back(t);
-        return q;
-      };
-      for (int j = j0; j < j1; ++j) {
-        emap[4 * size_t(j) + 0] = slot(tp[j]);
-        emap[4 * size_t(j) + 1] = bp[j];
-        emap[4 * size_t(j) + 2] = slot(tm[j]);
-        emap[4 * size_t(j) + 3] = bm[j];
+    auto slot = [&](int32_t t) -> int16_t {
+      auto it = pos.find(t);
+      if (it != pos.end()) return it->second;
+      const int16_t q = int16_t(pos.size());
+      pos.emplace(t, q);
+      ctri.push_back(t);
+      return q;
+    };
+    for (int j = 0; j < c->E_tot; ++j) {
+      const int add = int(!pos.count(tp[j])) + int(!pos.count(tm[j]));
+      if (int(pos.size()) + add > CH) {  // close the chunk before edge j
+        maxl = std::max(maxl, int(pos.size()));
+        cptr.push_back(int32_t(ctri.size()));
+        cedge.push_back(j);
+        pos.clear();
       }
-      maxl = std::max(maxl, int(pos.size()));
-      cptr.push_back(int32_t(ctri.size()));
+      emap[4 * size_t(j) + 0] = slot(tp[j]);
+      emap[4 * size_t(j) + 1] = bp[j];
+      emap[4 * size_t(j) + 2] = slot(tm[j]);
+      emap[4 * size_t(j) + 3] = bm[j];
     }
+    maxl = std::max(maxl, int(pos.size()));
+    cptr.push_back(int32_t(ctri.size()));
+    cedge.push_back(c->E_tot);
+    const int nch = int(cedge.size()) - 1;
+    c->chunk_e = upload(c, cedge);
     c->chunk_ptr = upload(c, cptr);
     c->chunk_tri = upload(c, ctri);
     c->edge_map = upload(c, emap);
@@ -643,10 +724,11 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   int max_slab = 0, max_Em = 0;
   for (auto& sl : slabs) max_slab = std::max(max_slab, sl.second - sl.first);
   for (auto& s : c->sc) max_Em = std::max(max_Em, s.topo.E);
-  DBuf HeS = dalloc<M>(size_t(2) * 3 * max_slab * c->E_tot), HeC = dalloc<M>(size_t(2) * 3 * max_slab * c->E_tot);
-  DBuf HiS = dalloc<M>(size_t(2) * 3 * max_slab * max_Em), HiC = dalloc<M>(size_t(2) * 3 * max_slab * max_Em);
+  DBuf HeS = dalloc_c<M>(c, size_t(2) * 3 * max_slab * c->E_tot),
+       HeC = dalloc_c<M>(c, size_t(2) * 3 * max_slab * c->E_tot);
+  DBuf HiS = dalloc_c<M>(c, size_t(2) * 3 * max_slab * max_Em), HiC = dalloc_c<M>(c, size_t(2) * 3 * max_slab * max_Em);
   HalfJob<M> hj{};
-  hj.chunk = CH;
+  hj.chunk_e = c->chunk_e.as<int32_t>();
   hj.chunk_ptr = c->chunk_ptr.as<int32_t>();
   hj.chunk_tri = c->chunk_tri.as<int32_t>();
   hj.edge_map = c->edge_map.as<int16_t>();
@@ -735,9 +817,9 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   if (c->sc.size() == 1 && c->comb_ok) {  // three combined matrices for the operator products
     const Scat& s = c->sc[0];
     const int64_t ne = E * c->ldE;
-    c->AC = dalloc<M>(size_t(2 * ne));
-    c->AS1 = dalloc<M>(size_t(2 * ne));
-    c->AS2 = dalloc<M>(size_t(2 * ne));
+    realloc_c<M>(c, c->AC, size_t(2 * ne));
+    realloc_c<M>(c, c->AS1, size_t(2 * ne));
+    realloc_c<M>(c, c->AS2, size_t(2 * ne));
     launch_combine3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), ne, c->k_ext, s.k.real(),
                        s.k.imag(), c->AC.as<M>(), c->AS1.as<M>(), c->AS2.as<M>(), c->stream);
     HIPCHK(hipGetLastError());
@@ -1014,7 +1096,7 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   c->nnzP = int64_t(c->h_col.size());
   c->prof.bary_pairs = c->nf.bary_pairs;
   auto vals = [&](DBuf& b) {
-    b = dalloc<double>(2 * size_t(c->nnzP));
+    realloc_c<double>(c, b, 2 * size_t(c->nnzP));
     launch_zero(b.as<double>(), 2 * c->nnzP, c->stream);
   };
   if (c->P_int) {
@@ -1158,9 +1240,9 @@ void rocsolver_check(rocblas_status s, const char* what) {
 // stream performs the rank update of the other columns.
 void gj_inverse(pmchwt_ctx* c, double* X, int n) {
   const int B = 128;
-  DBuf Pinv[2] = {dalloc<double>(size_t(B) * B), dalloc<double>(size_t(B) * B)};
-  DBuf Cc[2] = {dalloc<double>(size_t(n) * B), dalloc<double>(size_t(n) * B)};
-  DBuf R = dalloc<double>(size_t(B) * n);
+  DBuf Pinv[2] = {dalloc_c<double>(c, size_t(B) * B), dalloc_c<double>(c, size_t(B) * B)};
+  DBuf Cc[2] = {dalloc_c<double>(c, size_t(n) * B), dalloc_c<double>(c, size_t(n) * B)};
+  DBuf R = dalloc_c<double>(c, size_t(B) * n);
   const double one = 1.0, zero = 0.0, mone = -1.0;
   auto prepare = [&](int p0, int slot, hipStream_t st) {
     const int b = std::min(B, n - p0);
@@ -1203,7 +1285,7 @@ void gj_inverse(pmchwt_ctx* c, double* X, int n) {
     if (bq > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
     slot ^= 1;
   }
-  HIPCHK(hipStreamSynchronize(c->stream));
+  // look-ahead steps are joined into the stream; temporaries return to the pool
 }
 
 // The same inverse in FP32 on the matrix cores (n a multiple of 32, so that
@@ -1214,9 +1296,9 @@ void gj_inverse(pmchwt_ctx* c, double* X, int n) {
 //   X[:, J] -= C R[:, J]  as  (X^T)[J, :] -= R[J, :] C^T.
 void gj_inverse_f32(pmchwt_ctx* c, float* X, int n) {
   const int B = 128;
-  DBuf Pinv[2] = {dalloc<float>(size_t(B) * B), dalloc<float>(size_t(B) * B)};
-  DBuf Cc[2] = {dalloc<float>(size_t(n) * B), dalloc<float>(size_t(n) * B)};
-  DBuf R = dalloc<float>(size_t(B) * n);
+  DBuf Pinv[2] = {dalloc_c<float>(c, size_t(B) * B), dalloc_c<float>(c, size_t(B) * B)};
+  DBuf Cc[2] = {dalloc_c<float>(c, size_t(n) * B), dalloc_c<float>(c, size_t(n) * B)};
+  DBuf R = dalloc_c<float>(c, size_t(B) * n);
   auto prepare = [&](int p0, int slot, hipStream_t st) {
     const int b = std::min(B, n - p0);
     launch_gj_block_inverse_f32(X + int64_t(p0) * n + p0, n, Pinv[slot].as<float>(), b, st);
@@ -1254,8 +1336,9 @@ void gj_inverse_f32(pmchwt_ctx* c, float* X, int n) {
     if (bq > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
     slot ^= 1;
   }
+  // every look-ahead step has been joined into the stream: the temporaries go
+  // back to the pool without a host wait
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->stream));
 }
 
 // RWG Gram pattern: row i holds edge i and the other edges of its two
@@ -1309,7 +1392,7 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     tot += int64_t(s.topo.E) * s.topo.E;
   }
   DBuf d_off = upload(c, off), d_ld = upload(c, ld);
-  DBuf mass = dalloc<double>(size_t(tot));
+  DBuf mass = dalloc_c<double>(c, size_t(tot));
   launch_zero(mass.as<double>(), tot, c->stream);
   launch_zero(c->g_val.as<double>(), int64_t(c->g_val.bytes / 8), c->stream);
   MassJob mj{};
@@ -1333,33 +1416,31 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const int n = c->sc[m].topo.E;
     const size_t nn = size_t(n) * n;
-    DBuf MA = dalloc<double>(nn);
+    DBuf MA = dalloc_c<double>(c, nn);
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     c->MA.push_back(std::move(MA));
     const int64_t ldm = ldmass(n);
     if (c->mass_f32) {
       // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
       // M_A^-1 with zero padding columns, the layout the products read
-      DBuf Mf = dalloc<float>(size_t(ldm) * ldm), MfT = dalloc<float>(size_t(ldm) * ldm);
+      DBuf Mf = dalloc_c<float>(c, size_t(ldm) * ldm), MfT = dalloc_c<float>(c, size_t(ldm) * ldm);
       launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
       gj_inverse_f32(c, Mf.as<float>(), int(ldm));
       launch_transpose_f32(Mf.as<float>(), MfT.as<float>(), int(ldm), c->stream);
-      HIPCHK(hipStreamSynchronize(c->stream));
       c->Minv.push_back(std::move(Mf));
       c->MinvT.push_back(std::move(MfT));
       continue;
     }
-    DBuf Mi = dalloc<double>(nn), MiT = dalloc<double>(nn);
+    DBuf Mi = dalloc_c<double>(c, nn), MiT = dalloc_c<double>(c, nn);
     HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     // row-major M_A is column-major M_A^T; inverting it in place yields the
     // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
     gj_inverse(c, Mi.as<double>(), n);
     launch_transpose(Mi.as<double>(), MiT.as<double>(), n, c->stream);
     // padded copy for the vector loads of the application kernel
-    DBuf Md = dalloc<double>(size_t(n) * ldm), MdT = dalloc<double>(size_t(n) * ldm);
+    DBuf Md = dalloc_c<double>(c, size_t(n) * ldm), MdT = dalloc_c<double>(c, size_t(n) * ldm);
     launch_repack(Mi.as<double>(), n, Md.as<double>(), ldm, c->stream);
     launch_repack(MiT.as<double>(), n, MdT.as<double>(), ldm, c->stream);
-    HIPCHK(hipStreamSynchronize(c->stream));
     c->Minv.push_back(std::move(Md));
     c->MinvT.push_back(std::move(MdT));
   }
@@ -1572,9 +1653,9 @@ void gram_cg(pmchwt_ctx* c, const int64_t* rowptr, int n, const double* b_in, do
   // work on packed copies: vector q at q * n
   const int64_t stride = n;
   const size_t nd = 2 * size_t(stride) * nvec;
-  DBuf r = dalloc<double>(nd), p = dalloc<double>(nd), q = dalloc<double>(nd), xb = dalloc<double>(nd),
-       sc = dalloc<double>(4 * nvec);
-  DBuf act = dalloc<int32_t>(nvec);
+  DBuf r = dalloc_c<double>(c, nd), p = dalloc_c<double>(c, nd), q = dalloc_c<double>(c, nd),
+       xb = dalloc_c<double>(c, nd), sc = dalloc_c<double>(c, 4 * nvec);
+  DBuf act = dalloc_c<int32_t>(c, nvec);
   double* x = xb.as<double>();
   std::vector<int32_t> on(nvec, 1);
   HIPCHK(hipMemcpyAsync(act.p, on.data(), 4 * nvec, hipMemcpyHostToDevice, c->stream));
@@ -1632,8 +1713,8 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
     }
   std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
   DBuf dd = upload(c, hd), dp = upload(c, hp);
-  DBuf g = dalloc<double>(size_t(2 * vs * nrhs)), h = dalloc<double>(size_t(2 * vs * nrhs)),
-       cinc = dalloc<double>(size_t(2 * vs * nrhs)), t = dalloc<double>(size_t(2 * vs * nrhs));
+  DBuf g = dalloc_c<double>(c, size_t(2 * vs * nrhs)), h = dalloc_c<double>(c, size_t(2 * vs * nrhs)),
+       cinc = dalloc_c<double>(c, size_t(2 * vs * nrhs)), t = dalloc_c<double>(c, size_t(2 * vs * nrhs));
   launch_zero(g.as<double>(), 2 * vs * nrhs, c->stream);
   launch_zero(h.as<double>(), 2 * vs * nrhs, c->stream);
   RhsJob j{};
@@ -1797,11 +1878,11 @@ struct GmresRun {
     dpar = s3 + nrhs * vecd;                   // step partial sums
     dres = dpar + part_doubles(nrhs, rho);     // step results for the host
     dn = dres + res_doubles(nrhs, rho);        // nrhs doubles, norms outside the cycle
-    dact = dalloc<int32_t>(nrhs);
-    dupd = dalloc<int32_t>(nrhs);
-    dscale = dalloc<double>(nrhs);
-    dy = dalloc<double>(2 * size_t(rho + 1) * nrhs);
-    dpart = dalloc<double>(2 * (size_t(rho + 2) * nrhs + 1024));
+    dact = dalloc_c<int32_t>(c, nrhs);
+    dupd = dalloc_c<int32_t>(c, nrhs);
+    dscale = dalloc_c<double>(c, nrhs);
+    dy = dalloc_c<double>(c, 2 * size_t(rho + 1) * nrhs);
+    dpart = dalloc_c<double>(c, 2 * (size_t(rho + 2) * nrhs + 1024));
     double* hp = static_cast<double*>(hpin.p);
     h_res[0] = hp;
     h_res[1] = h_res[0] + res_doubles(nrhs, rho);
@@ -2343,7 +2424,7 @@ int pmchwt_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
     if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
     if (nrhs <= 0 || !dirs || !pols || !b_out) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
     const int64_t vs = vlen(c);
-    DBuf b = dalloc<double>(size_t(2 * vs * nrhs));
+    DBuf b = dalloc_c<double>(c, size_t(2 * vs * nrhs));
     build_rhs(c, dirs, pols, nrhs, b.as<double>());
     std::vector<double> h(size_t(2 * vs * nrhs));
     HIPCHK(hipMemcpy(h.data(), b.p, h.size() * 8, hipMemcpyDeviceToHost));
@@ -2359,8 +2440,8 @@ int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t 
     const int64_t vs = vlen(c);
     std::vector<double> h;
     to_internal(c, x, nrhs, h);
-    DBuf dx = upload(c, h), dy = dalloc<double>(h.size()), s1 = dalloc<double>(h.size()), s2 = dalloc<double>(h.size()),
-         s3 = dalloc<double>(h.size());
+    DBuf dx = upload(c, h), dy = dalloc_c<double>(c, h.size()), s1 = dalloc_c<double>(c, h.size()),
+         s2 = dalloc_c<double>(c, h.size()), s3 = dalloc_c<double>(c, h.size());
     if (which == 0)
       apply_A(c, dx.as<double>(), dy.as<double>(), nrhs);
     else
@@ -2382,8 +2463,9 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       return fail(c, PMCHWT_ERR_INVALID_ARG, "bad solver options");
     const int64_t vs = vlen(c);
     const size_t nd = size_t(2 * vs * nrhs);
-    DBuf b = dalloc<double>(nd), bt = dalloc<double>(nd), x = dalloc<double>(nd), s1 = dalloc<double>(nd),
-         s2 = dalloc<double>(nd), d = dalloc<double>(nd), r = dalloc<double>(nd);
+    DBuf b = dalloc_c<double>(c, nd), bt = dalloc_c<double>(c, nd), x = dalloc_c<double>(c, nd),
+         s1 = dalloc_c<double>(c, nd), s2 = dalloc_c<double>(c, nd), d = dalloc_c<double>(c, nd),
+         r = dalloc_c<double>(c, nd);
     EvTimer tm(c->stream);
     c->prof.ms_matvec_total = 0;
     c->prof.matvec_launches = 0;
@@ -2413,7 +2495,7 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
       apply_Ptilde(c, r.as<double>(), s1.as<double>(), s2.as<double>(), d.as<double>(), nrhs);
       std::vector<double> nr(nrhs), nb(nrhs);
-      DBuf dn = dalloc<double>(2 * nrhs);
+      DBuf dn = dalloc_c<double>(c, 2 * nrhs);
       launch_norms(s1.as<double>(), vs, int(vs), nrhs, dn.as<double>(), c->stream);
       launch_norms(bt.as<double>(), vs, int(vs), nrhs, dn.as<double>() + nrhs, c->stream);
       HIPCHK(hipMemcpyAsync(nr.data(), dn.p, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
@@ -2471,9 +2553,9 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     to_internal(c, cur, nrhs, h);
     DBuf dx = upload(c, h);
     std::vector<double> ho(obs, obs + 3 * size_t(nobs));
-    DBuf dobs = upload(c, ho), dF = dalloc<double>(6 * size_t(nobs) * nrhs);
+    DBuf dobs = upload(c, ho), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs);
     const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs);
-    DBuf wy = dalloc<double>(fp.n_ypts), wj = dalloc<double>(fp.n_J), wp = dalloc<double>(fp.n_part);
+    DBuf wy = dalloc_c<double>(c, fp.n_ypts), wj = dalloc_c<double>(c, fp.n_J), wp = dalloc_c<double>(c, fp.n_part);
     launch_far_field(asm_params<double>(c), dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs,
                      dF.as<double>(), fp, wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     HIPCHK(hipGetLastError());
@@ -2507,17 +2589,17 @@ int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs
       }
     std::vector<double> h;
     to_internal(c, cur, nrhs, h);
-    DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc<double>(6 * size_t(nobs) * nrhs),
-         dsig = dalloc<double>(nrhs);
+    DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs),
+         dsig = dalloc_c<double>(c, nrhs);
     AsmParams<double> g = asm_params<double>(c);
     const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs), fpd = far_field_plan(c->F_tot, nrhs, nrhs);
-    DBuf wy = dalloc<double>(fp.n_ypts), wj = dalloc<double>(fp.n_J),
-         wp = dalloc<double>(std::max(fp.n_part, fpd.n_part));
+    DBuf wy = dalloc_c<double>(c, fp.n_ypts), wj = dalloc_c<double>(c, fp.n_J),
+         wp = dalloc_c<double>(c, std::max(fp.n_part, fpd.n_part));
     launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs, dF.as<double>(), fp,
                      wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     launch_sigma_sca(dF.as<double>(), nobs, nrhs, dw.as<double>(), dsig.as<double>(), c->stream);
     std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
-    DBuf dd = upload(c, hd), dFd = dalloc<double>(6 * size_t(nrhs) * nrhs);
+    DBuf dd = upload(c, hd), dFd = dalloc_c<double>(c, 6 * size_t(nrhs) * nrhs);
     launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dd.as<double>(), nrhs, dFd.as<double>(), fpd,
                      wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
     HIPCHK(hipGetLastError());

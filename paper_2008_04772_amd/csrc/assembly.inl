@@ -67,8 +67,17 @@ struct MomPair {
   Moments<R> e, i;
 };
 
+// Threads per workgroup of the regular kernel; a chunk of trial edges holds at
+// most this many distinct trial triangles, so phase A takes one pass.
+template <typename R>
+struct RegularThreads {
+  static constexpr int value = sizeof(R) == 4 ? 256 : 128;
+};
+int regular_chunk_limit(bool fp64) { return fp64 ? RegularThreads<double>::value : RegularThreads<float>::value; }
+
 template <typename R, typename M>
-__global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M> h, int t1_base) {
+__global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmParams<M> p, HalfJob<M> h,
+                                                                            int t1_base) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   MomPair<R>* sm = reinterpret_cast<MomPair<R>*>(smem_raw);
   const int t1 = t1_base + blockIdx.y;
@@ -179,8 +188,8 @@ __global__ __launch_bounds__(128) void k_regular_rows(AsmParams<M> p, HalfJob<M>
   __syncthreads();
 
   // ---- phase B: one trial edge per thread
-  const int j0 = ch * h.chunk;
-  const int nj = min(h.chunk, h.E_tot - j0);
+  const int j0 = h.chunk_e[ch];
+  const int nj = h.chunk_e[ch + 1] - j0;
   R al1[3], w1[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -369,7 +378,8 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
   const size_t lds = size_t(max_list) * sizeof(MomPair<R>);
   for (int t0 = t1_begin; t0 < t1_end; t0 += 65535) {
     const int rows = std::min(65535, t1_end - t0);
-    hipLaunchKernelGGL((k_regular_rows<R, M>), dim3(nchunks, rows), dim3(128), lds, st, p, h, t0);
+    hipLaunchKernelGGL((k_regular_rows<R, M>), dim3(nchunks, rows), dim3(RegularThreads<R>::value), lds, st, p, h,
+                       t0);
   }
 }
 

@@ -41,7 +41,7 @@ struct AsmParams {
 // every test edge into the dense operator.
 template <typename M>
 struct HalfJob {
-  int chunk;                   // edges per chunk
+  const int32_t* chunk_e;      // nchunks+1: first trial edge of each chunk
   const int32_t* chunk_ptr;    // nchunks+1, into chunk_tri
   const int32_t* chunk_tri;    // distinct trial triangles of each chunk
   const int16_t* edge_map;     // 4 per edge: list position of T+, basis b+, position of T-, basis b-
@@ -126,6 +126,9 @@ struct RhsJob {
 
 hipError_t upload_rules(const double* l, const double* w, hipStream_t s);
 
+// Workgroup size of the regular kernel = the most distinct trial triangles a
+// chunk of trial edges may hold
+int regular_chunk_limit(bool fp64);
 template <typename R, typename M>
 void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begin, int t1_end, int nchunks,
                          int max_list, hipStream_t st);
