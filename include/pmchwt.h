@@ -96,10 +96,11 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       the bounding boxes of the supports of functions i and j are at most
  *       chi apart; chi < 0 means infinity.  Ignored for A (always dense).
  *   precision : PMCHWT_FP64, or PMCHWT_MIXED.  For A: disjoint pairs and
- *       operator storage in FP32, singular pairs in FP64.  For P: the
- *       near-field values are always FP64; MIXED computes and stores the
- *       inverted mass matrices M_A^-1 and M_A^-T in FP32 (Gauss-Jordan with
- *       its rank updates on the FP32 matrix cores), which only perturbs the
+ *       operator storage in FP32, singular pairs in FP64.  For P: MIXED
+ *       integrates the near-field BC entries in FP32 (pair classification in
+ *       FP64, entries stored in FP64) and computes and stores the inverted
+ *       mass matrices M_A^-1 and M_A^-T in FP32 (Gauss-Jordan with its rank
+ *       updates on the FP32 matrix cores); both only perturb the
  *       preconditioner, not the system that is solved.                       */
 typedef struct {
   int32_t q_near, q_medium, q_far;

@@ -1203,6 +1203,7 @@ void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev&
   j.want_int = c->P_int;
   j.want_ext = c->P_ext;
   j.want_C = c->P_C;
+  j.fp32 = o.precision == PMCHWT_MIXED;  // mixed-precision P: FP32 integrals, FP64 entries
   j.k_int = c->k_int.as<double>();
   j.k_ext = c->k_ext;
   j.q_near = o.q_near;

@@ -39,76 +39,77 @@ __device__ __forceinline__ SmallGeom load_child(const CellParams& c, int ch) {
   return g;
 }
 
-// Moments of one (test, trial) triangle pair, origin = test centroid.
-// Identical / shared-edge / shared-vertex pairs use the Sauter-Schwab tables,
-// disjoint pairs the tensor rule of their distance class.
 // Moments of one (test, trial) triangle pair at one wavenumber, origin = test
-// centroid.  Identical / shared-edge / shared-vertex pairs use the
-// Sauter-Schwab tables (tab1..tab3 with n1..n3 records), disjoint pairs the
-// tensor rule of their distance class.
-__device__ __forceinline__ void pair_moments(const SmallGeom a, const SmallGeom b, const double* tab1, const double* tab2,
-                             const double* tab3, int n1, int n2, int n3, int qn, int qm, int qf, double kr, double ki,
-                             bool withC, Moments<double>& out) {
+// centroid, accumulated in precision R (coordinates are made relative to the
+// test centroid in FP64 first).  Identical / shared-edge / shared-vertex pairs
+// use the Sauter-Schwab tables (tab1..tab3 with n1..n3 records), disjoint
+// pairs the tensor rule of their distance class (classified in FP64).
+template <typename R>
+__device__ __forceinline__ void pair_moments(const SmallGeom a, const SmallGeom b, const double* tab1,
+                                             const double* tab2, const double* tab3, int n1, int n2, int n3, int qn,
+                                             int qm, int qf, R kr, R ki, bool withC, Moments<R>& out) {
   out.zero();
-  double P1[3][3], P2[3][3];
+  R P1[3][3], P2[3][3];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      P1[v][d] = a.P[v][d] - a.cen[d];
-      P2[v][d] = b.P[v][d] - a.cen[d];
+      P1[v][d] = R(a.P[v][d] - a.cen[d]);
+      P2[v][d] = R(b.P[v][d] - a.cen[d]);
     }
-  const bool decay = ki != 0.0;
+  const bool decay = ki != R(0);
   int oa, ob;
   const int nc = shared_order(a.vid, b.vid, oa, ob);
   if (nc > 0) {
-    double Q1[3][3], Q2[3][3];
+    R Q1[3][3], Q2[3][3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       const int ia = (oa >> (2 * v)) & 3, ib = (ob >> (2 * v)) & 3;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double c1[3] = {P1[0][d], P1[1][d], P1[2][d]}, c2[3] = {P2[0][d], P2[1][d], P2[2][d]};
+        const R c1[3] = {P1[0][d], P1[1][d], P1[2][d]}, c2[3] = {P2[0][d], P2[1][d], P2[2][d]};
         Q1[v][d] = pick3(c1, ia);
         Q2[v][d] = pick3(c2, ib);
       }
     }
     const double* T = nc == 1 ? tab1 : (nc == 2 ? tab2 : tab3);
     const int n = nc == 1 ? n1 : (nc == 2 ? n2 : n3);
-    const double AA = 4.0 * a.area * b.area;
+    const R AA = R(4.0 * a.area * b.area);
     for (int q = 0; q < n; ++q) {
-      const double x1 = T[5 * q], x2 = T[5 * q + 1], y1 = T[5 * q + 2], y2 = T[5 * q + 3];
-      const double w = T[5 * q + 4] * AA;
-      double x[3], y[3];
+      const R x1 = R(T[5 * q]), x2 = R(T[5 * q + 1]), y1 = R(T[5 * q + 2]), y2 = R(T[5 * q + 3]);
+      const R w = R(T[5 * q + 4]) * AA;
+      R x[3], y[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         x[d] = Q1[0][d] + x1 * (Q1[1][d] - Q1[0][d]) + x2 * (Q1[2][d] - Q1[1][d]);
         y[d] = Q2[0][d] + y1 * (Q2[1][d] - Q2[0][d]) + y2 * (Q2[2][d] - Q2[1][d]);
       }
-      const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      out.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, withC);
+      const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      out.add(helmholtz<R>(r2, kr, ki, decay, w), x, y, withC);
     }
     return;
   }
   const int cls = classify_pair(a.cen[0], a.cen[1], a.cen[2], b.cen[0], b.cen[1], b.cen[2], a.diam2, b.diam2);
   const int q = cls == 0 ? qn : (cls == 1 ? qm : qf);
   const int off = c_rule_off[q], n = c_rule_n[q];
-  const double AA = a.area * b.area;
+  const R AA = R(a.area * b.area);
   for (int i = 0; i < n; ++i) {
-    double x[3];
+    R x[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      x[d] = c_rule_l[off + i][0] * P1[0][d] + c_rule_l[off + i][1] * P1[1][d] + c_rule_l[off + i][2] * P1[2][d];
-    for (int j = 0; j < n; ++j) {
-      double y[3];
+      x[d] = R(c_rule_l[off + i][0]) * P1[0][d] + R(c_rule_l[off + i][1]) * P1[1][d] +
+             R(c_rule_l[off + i][2]) * P1[2][d];
+    for (int jq = 0; jq < n; ++jq) {
+      R y[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        y[d] = c_rule_l[off + j][0] * P2[0][d] + c_rule_l[off + j][1] * P2[1][d] + c_rule_l[off + j][2] * P2[2][d];
-      const double w = c_rule_w[off + i] * c_rule_w[off + j] * AA;
-      const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      out.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, withC);
+        y[d] = R(c_rule_l[off + jq][0]) * P2[0][d] + R(c_rule_l[off + jq][1]) * P2[1][d] +
+               R(c_rule_l[off + jq][2]) * P2[2][d];
+      const R w = R(c_rule_w[off + i] * c_rule_w[off + jq]) * AA;
+      const R dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      out.add(helmholtz<R>(r2, kr, ki, decay, w), x, y, withC);
     }
   }
 }
@@ -119,15 +120,19 @@ __device__ __forceinline__ void pair_moments(const SmallGeom a, const SmallGeom 
 //   Ta = sum (a2 Mxy - w2 . Mx),  Tb = sum (w2 M0 - a2 My),  Td = sum 4 a2 M0,
 //   Tc = -sum w2 . Nx,            Te = sum (a2 Nx - Nd x w2),
 // sums over the trial children u2 of the cell.
+template <typename R>
 struct HalfC {
-  double v[18];  // Ta(2) Tb(6) Td(2) Tc(2) Te(6)
+  R v[18];  // Ta(2) Tb(6) Td(2) Tc(2) Te(6)
 };
 
+// R: precision of the pair moments and contractions (FP64, or FP32 for a
+// mixed-precision preconditioner); the kept entries are added in FP64.
+template <typename R>
 __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
-  __shared__ double s_mom[BC_CHUNK_PAIRS * 2 * MOM_D];
+  __shared__ R s_mom[BC_CHUNK_PAIRS * 2 * MOM_D];
   __shared__ double s_org[BC_MAX_RING][3];
-  __shared__ HalfC s_half[BC_CHUNK_PAIRS / 2][2];
-  __shared__ double s_acc[BC_MAX_RING * BC_MAX_RING / 4][8];
+  __shared__ HalfC<R> s_half[BC_CHUNK_PAIRS / 2][2];
+  __shared__ R s_acc[BC_MAX_RING * BC_MAX_RING / 4][8];
   const int lane = threadIdx.x;
   const int64_t pr = blockIdx.x;
   const int v = j.cpairs[2 * pr], w = j.cpairs[2 * pr + 1];
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
   const double kr1 = j.k_ext, ki1 = 0.0;
   const bool withC = j.want_C;
   for (int s = lane; s < nslot; s += 64)
-    for (int q = 0; q < 8; ++q) s_acc[s][q] = 0.0;
+    for (int q = 0; q < 8; ++q) s_acc[s][q] = R(0);
   const int rows_per_chunk = max(1, BC_CHUNK_PAIRS / n2);
   const double* cv = c.coef + 4 * c.coef_ptr[v];
   const double* cw = c.coef + 4 * c.coef_ptr[w];
@@ -157,10 +162,10 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
       const SmallGeom ga = load_child(c, c.ring[b1 + u1]);
       const SmallGeom gb = load_child(c, c.ring[b2 + u2]);
       for (int k = 0; k < nk; ++k) {
-        Moments<double> m;
-        pair_moments(ga, gb, j.tab[1], j.tab[2], j.tab[3], j.npts[1], j.npts[2], j.npts[3], j.q_near, j.q_medium,
-                     j.q_far, k == 0 ? kr0 : kr1, k == 0 ? ki0 : ki1, withC, m);
-        const double* f = reinterpret_cast<const double*>(&m);
+        Moments<R> m;
+        pair_moments<R>(ga, gb, j.tab[1], j.tab[2], j.tab[3], j.npts[1], j.npts[2], j.npts[3], j.q_near, j.q_medium,
+                        j.q_far, R(k == 0 ? kr0 : kr1), R(k == 0 ? ki0 : ki1), withC, m);
+        const R* f = reinterpret_cast<const R*>(&m);
 #pragma unroll
         for (int q = 0; q < MOM_D; ++q) s_mom[(p * 2 + k) * MOM_D + q] = f[q];
       }
@@ -174,15 +179,14 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
       const int ur = hq / N2, sj = hq % N2;
       const double* o = s_org[ur];
       for (int k = 0; k < nk; ++k) {
-        double T[18];
+        R T[18];
 #pragma unroll
-        for (int q = 0; q < 18; ++q) T[q] = 0.0;
+        for (int q = 0; q < 18; ++q) T[q] = R(0);
         for (int u2 = 0; u2 < n2; ++u2) {
           const double* c2 = cw + 4 * (int64_t(sj) * n2 + u2);
-          const double a2 = c2[0];
-          const double w2[3] = {c2[1] - a2 * o[0], c2[2] - a2 * o[1], c2[3] - a2 * o[2]};
-          const Moments<double>& m =
-              *reinterpret_cast<const Moments<double>*>(&s_mom[((ur * n2 + u2) * 2 + k) * MOM_D]);
+          const R a2 = R(c2[0]);
+          const R w2[3] = {R(c2[1] - c2[0] * o[0]), R(c2[2] - c2[0] * o[1]), R(c2[3] - c2[0] * o[2])};
+          const Moments<R>& m = *reinterpret_cast<const Moments<R>*>(&s_mom[((ur * n2 + u2) * 2 + k) * MOM_D]);
           // Ta
           T[0] += a2 * m.Mxy.re - (w2[0] * m.Mx[0].re + w2[1] * m.Mx[1].re + w2[2] * m.Mx[2].re);
           T[1] += a2 * m.Mxy.im - (w2[0] * m.Mx[0].im + w2[1] * m.Mx[1].im + w2[2] * m.Mx[2].im);
@@ -191,8 +195,8 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
             T[2 + 2 * d] += w2[d] * m.M0.re - a2 * m.My[d].re;
             T[3 + 2 * d] += w2[d] * m.M0.im - a2 * m.My[d].im;
           }
-          T[8] += 4.0 * a2 * m.M0.re;  // Td
-          T[9] += 4.0 * a2 * m.M0.im;
+          T[8] += R(4) * a2 * m.M0.re;  // Td
+          T[9] += R(4) * a2 * m.M0.im;
           if (withC) {
             T[10] -= w2[0] * m.Nx[0].re + w2[1] * m.Nx[1].re + w2[2] * m.Nx[2].re;  // Tc
             T[11] -= w2[0] * m.Nx[0].im + w2[1] * m.Nx[1].im + w2[2] * m.Nx[2].im;
@@ -212,17 +216,17 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     // ---- B2: test side, one (si, sj) per lane
     for (int s = lane; s < nslot; s += 64) {
       const int si = s / N2, sj = s % N2;
-      double acc[8];
+      R acc[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] = s_acc[s][q];
       for (int k = 0; k < nk; ++k) {
-        double sv_re = 0, sv_im = 0, sd_re = 0, sd_im = 0, cc_re = 0, cc_im = 0;
+        R sv_re = 0, sv_im = 0, sd_re = 0, sd_im = 0, cc_re = 0, cc_im = 0;
         for (int ur = 0; ur < nr; ++ur) {
           const double* c1 = cv + 4 * (int64_t(si) * n1 + r0 + ur);
-          const double a1 = c1[0];
+          const R a1 = R(c1[0]);
           const double* o = s_org[ur];
-          const double w1[3] = {c1[1] - a1 * o[0], c1[2] - a1 * o[1], c1[3] - a1 * o[2]};
-          const double* T = s_half[ur * N2 + sj][k].v;
+          const R w1[3] = {R(c1[1] - c1[0] * o[0]), R(c1[2] - c1[0] * o[1]), R(c1[3] - c1[0] * o[2])};
+          const R* T = s_half[ur * N2 + sj][k].v;
           sv_re += a1 * T[0] + w1[0] * T[2] + w1[1] * T[4] + w1[2] * T[6];
           sv_im += a1 * T[1] + w1[0] * T[3] + w1[1] * T[5] + w1[2] * T[7];
           sd_re += a1 * T[8];
@@ -240,8 +244,8 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
         const bool to_int = do_int && k == 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          acc[q] += to_int ? v[q] : 0.0;
-          acc[4 + q] += to_int ? 0.0 : v[q];
+          acc[q] += to_int ? R(v[q]) : R(0);
+          acc[4 + q] += to_int ? R(0) : R(v[q]);
         }
       }
 #pragma unroll
@@ -254,19 +258,19 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     const int64_t ps = pos[s];
     if (ps < 0) continue;
     if (do_int) {
-      atomic_add(&j.out_Si[2 * ps], s_acc[s][0]);
-      atomic_add(&j.out_Si[2 * ps + 1], s_acc[s][1]);
+      atomic_add(&j.out_Si[2 * ps], double(s_acc[s][0]));
+      atomic_add(&j.out_Si[2 * ps + 1], double(s_acc[s][1]));
       if (withC) {
-        atomic_add(&j.out_Ci[2 * ps], s_acc[s][2]);
-        atomic_add(&j.out_Ci[2 * ps + 1], s_acc[s][3]);
+        atomic_add(&j.out_Ci[2 * ps], double(s_acc[s][2]));
+        atomic_add(&j.out_Ci[2 * ps + 1], double(s_acc[s][3]));
       }
     }
     if (do_ext) {
-      atomic_add(&j.out_Se[2 * ps], s_acc[s][4]);
-      atomic_add(&j.out_Se[2 * ps + 1], s_acc[s][5]);
+      atomic_add(&j.out_Se[2 * ps], double(s_acc[s][4]));
+      atomic_add(&j.out_Se[2 * ps + 1], double(s_acc[s][5]));
       if (withC) {
-        atomic_add(&j.out_Ce[2 * ps], s_acc[s][6]);
-        atomic_add(&j.out_Ce[2 * ps + 1], s_acc[s][7]);
+        atomic_add(&j.out_Ce[2 * ps], double(s_acc[s][6]));
+        atomic_add(&j.out_Ce[2 * ps + 1], double(s_acc[s][7]));
       }
     }
   }
@@ -279,7 +283,10 @@ void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, cons
     jj.npairs = std::min<int64_t>(j.npairs - p0, int64_t(1) << 30);
     jj.cpairs = j.cpairs + 2 * p0;
     jj.slot_off = j.slot_off + p0;
-    hipLaunchKernelGGL(k_bc_nearfield, dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+    if (j.fp32)
+      hipLaunchKernelGGL(k_bc_nearfield<float>, dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+    else
+      hipLaunchKernelGGL(k_bc_nearfield<double>, dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
   }
 }
 

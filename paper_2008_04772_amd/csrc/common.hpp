@@ -239,7 +239,8 @@ __device__ __forceinline__ int shared_order(const int va[3], const int vb[3], in
   return nc;
 }
 
-__device__ __forceinline__ double pick3(const double v[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+template <typename T>
+__device__ __forceinline__ T pick3(const T v[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
 
 // The same contraction with all arithmetic in R (FP32 for FP32 operators,
 // whose entries are stored in FP32 anyway).

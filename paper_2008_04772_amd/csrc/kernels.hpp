@@ -86,6 +86,7 @@ struct BCJob {
   const int64_t* slot_off;     // npairs+1: offsets into slot_pos
   const int64_t* slot_pos;     // N_v x N_w CSR positions, -1 = dropped by the near-field cutoff
   int want_int, want_ext, want_C;
+  int fp32;                    // pair moments and contractions in FP32 (mixed-precision P)
   const double* k_int;         // per scatterer (re, im)
   double k_ext;
   int q_near, q_medium, q_far, n_sing;

@@ -92,10 +92,11 @@ def test_fullsize_A_entries(P, mesh, topo, precision, tol):
             assert err < tol
 
 
-def test_fullsize_P_entries(P, mesh, topo):
-    note("full-size near-field S^i on BC: icosphere(4), chi = 2h")
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-4)])
+def test_fullsize_P_entries(P, mesh, topo, precision, tol):
+    note(f"full-size near-field S^i on BC: icosphere(4), chi = 2h, precision {precision}")
     v, t, chi = mesh
-    ctx = _ctx(P, mesh, 0)
+    ctx = _ctx(P, mesh, precision)
     bary = Barycentric(topo)
     lo, hi = ops.bc_bboxes(bary)
     rng = np.random.default_rng(22)
@@ -119,7 +120,7 @@ def test_fullsize_P_entries(P, mesh, topo):
     ref = ops.bc_entries(bary, K * np.sqrt(EPS), rows[keep], cols[keep], q=(1, 1, 1), n_sing=1, want=("S",))["S"]
     err = rel_max(got[keep], ref)
     note(f"  kept entries: max rel {err:.2e}")
-    assert err < 1e-10
+    assert err < tol
 
 
 def test_fullsize_solve_mixed_vs_fp64_and_mie(P, mesh):
