@@ -1289,7 +1289,20 @@ void gj_inverse(pmchwt_ctx* c, double* X, int n) {
   // look-ahead steps are joined into the stream; temporaries return to the pool
 }
 
-// The same inverse in FP32 on the matrix cores (n a multiple of 32, so that
+// y (rows x Nr, row-major, ldy) = [y -] A (rows x K, row-major, lda) B^T
+// (B: Nr x K row-major) with rocBLAS SGEMM on the context's stream: a plain
+// GEMM, where the library's FP32 matrix-core kernels outrun the fused product
+// kernel at K = 128 (about 100 vs 73 TFLOP/s on the 7680 x 7680 update).
+void sgemm_abt(pmchwt_ctx* c, const float* A, int64_t lda, const float* Bm, int K, int rows, int Nr, float* y,
+               int64_t ldy, bool subtract) {
+  const float alpha = subtract ? -1.0f : 1.0f, beta = subtract ? 1.0f : 0.0f;
+  // column-major view: y^T (Nr x rows) = B (Nr x K) A^T, i.e. op(B-as-stored) = T
+  rocsolver_check(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, Nr, rows, K, &alpha, Bm,
+                                K, A, int(lda), &beta, y, int(ldy)),
+                  "rocblas_sgemm");
+}
+
+// The same inverse in FP32 on the matrix cores (rank updates by SGEMM) (n a multiple of 32, so that
 // every pivot block is a multiple of the 32-wide K tile).  Pivot blocks are
 // inverted row-major and the taken columns stored row-major, so that both
 // products are A B^T with K contiguous:
@@ -1307,8 +1320,7 @@ void gj_inverse_f32(pmchwt_ctx* c, float* X, int n) {
   };
   auto update = [&](int slot, int b, int j0, int nj) {
     if (nj <= 0) return;
-    launch_mfma_f32(R.as<float>() + int64_t(j0) * b, b, Cc[slot].as<float>(), b, nj, n, X + int64_t(j0) * n, n, true,
-                    c->stream);
+    sgemm_abt(c, R.as<float>() + int64_t(j0) * b, b, Cc[slot].as<float>(), b, nj, n, X + int64_t(j0) * n, n, true);
   };
   auto put_rows = [&](int p0, int b, int j0, int nj) {
     if (nj <= 0) return;
@@ -1320,7 +1332,7 @@ void gj_inverse_f32(pmchwt_ctx* c, float* X, int n) {
   for (int p0 = 0; p0 < n; p0 += B) {
     const int b = std::min(B, n - p0);
     const int q0 = p0 + b, bq = std::min(B, n - q0);
-    launch_mfma_f32(X + p0, n, Pinv[slot].as<float>(), b, n, b, R.as<float>(), b, false, c->stream);
+    sgemm_abt(c, X + p0, n, Pinv[slot].as<float>(), b, n, b, R.as<float>(), b, false);
     if (bq > 0) {
       update(slot, b, q0, bq);
       put_rows(p0, b, q0, bq);

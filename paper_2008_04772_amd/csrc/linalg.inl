@@ -1119,15 +1119,90 @@ __global__ __launch_bounds__(NB * NB / RPT) void k_gj_block_inverse(const T* __r
   }
 }
 
+// The same elimination with the 128 x 128 block tiled 8 x 8 per thread (a
+// 16 x 16 grid of threads): row k+1 and column k+1 are then published by 16
+// threads with vector stores of 8 values each, every thread reads 8 + 8
+// values per step, and with the pivot loop unrolled by 8 the register row /
+// column of the next pivot is a compile-time index.  Padded steps beyond b
+// (up to the next multiple of 8) act on identity rows and change nothing.
+template <typename T, bool ROWMAJOR_OUT>
+__global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict__ X, int64_t ldx,
+                                                            T* __restrict__ out, int b) {
+  constexpr int NB = 128;
+  __shared__ T colk[2][NB], rowk[2][NB];
+  const int t = threadIdx.x;
+  const int ti = t >> 4, tj = t & 15;  // rows 8 ti .. +8, columns 8 tj .. +8
+  const int r0 = 8 * ti, c0 = 8 * tj;
+  T a[8][8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = r0 + r, j = c0 + c;
+      a[r][c] = (i < b && j < b) ? X[int64_t(j) * ldx + i] : T(i == j ? 1 : 0);
+    }
+  // publish row 0 and column 0 (reset to e_0)
+  if (ti == 0) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rowk[0][c0 + c] = a[0][c];
+  }
+  if (tj == 0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      colk[0][r0 + r] = a[r][0] - T(r0 + r == 0 ? 1 : 0);
+      a[r][0] = T(r0 + r == 0 ? 1 : 0);
+    }
+  }
+  const int steps = (b + 7) & ~7;
+  for (int g = 0; g < steps; g += 8) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = g + s, kn = k + 1;
+      const int buf = s & 1, nb = buf ^ 1;  // k parity (g is a multiple of 8)
+      __syncthreads();
+      const T ip = T(1) / (colk[buf][k] + T(1));
+      T u[8], v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) u[r] = colk[buf][r0 + r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = (c0 + c == k) ? ip : rowk[buf][c0 + c] * ip;
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[r][c] = fma(-u[r], v[c], a[r][c]);
+      // next pivot: register row / column sn of the thread row / column gn
+      const int sn = (s + 1) & 7;
+      const int gn = kn >> 3;
+      if (kn < NB) {
+        if (ti == gn) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) rowk[nb][c0 + c] = a[sn][c];
+        }
+        if (tj == gn) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            colk[nb][r0 + r] = a[r][sn] - T(r0 + r == kn ? 1 : 0);
+            a[r][sn] = T(r0 + r == kn ? 1 : 0);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = r0 + r, j = c0 + c;
+      if (i < b && j < b) out[ROWMAJOR_OUT ? int64_t(i) * b + j : int64_t(j) * b + i] = a[r][c];
+    }
+}
+
 void launch_gj_block_inverse(const double* X, int64_t ldx, double* out, int b, hipStream_t st) {
-  hipLaunchKernelGGL((k_gj_block_inverse<double, false, GJ_B, 64>), dim3(1), dim3(GJ_B * GJ_B / 64), 0, st, X, ldx,
-                     out, b);
+  hipLaunchKernelGGL((k_gj_block_inverse_t<double, false>), dim3(1), dim3(256), 0, st, X, ldx, out, b);
 }
 
 void launch_gj_block_inverse_f32(const float* X, int64_t ldx, float* out_rowmajor, int b, hipStream_t st) {
-  constexpr int NB = GJ_B_F32;
-  hipLaunchKernelGGL((k_gj_block_inverse<float, true, NB, 64>), dim3(1), dim3(NB * NB / 64), 0, st, X, ldx,
-                     out_rowmajor, b);
+  hipLaunchKernelGGL((k_gj_block_inverse_t<float, true>), dim3(1), dim3(256), 0, st, X, ldx, out_rowmajor, b);
 }
 
 // FP32 take-columns with C row-major (n x b, C[i * b + j]).
