@@ -974,157 +974,26 @@ namespace pmchwt {
 
 // ---------------------------------------------------------------------------
 // In-place inverse of a b x b column-major block (b <= 128) by Gauss-Jordan
-// elimination without pivoting, one workgroup, block held in LDS.  Used on
+// elimination without pivoting, one workgroup, block held in registers.  Used on
 // the diagonal blocks of the blocked Gauss-Jordan inverse of the mixed mass
 // matrix, whose symmetric part is positive definite (every leading block is
 // safely invertible without row exchanges).
 // ---------------------------------------------------------------------------
-constexpr int GJ_B = 128;
-constexpr int GJ_B_F32 = 128;  // pivot block of the FP32 inverse
-
-// Thread t holds column j = t % 128, rows [64 (t / 128), +64) in registers.
-// Step k of the in-place Gauss-Jordan inverse is one rank-1 update
+// Thread (ti, tj) of a 16 x 16 grid holds the 8 x 8 tile of rows 8 ti.. and
+// columns 8 tj.. in registers.  Step k of the in-place Gauss-Jordan inverse
+// is one rank-1 update
 //   a_ij -= u_i v_j,  u_i = a_ik - [i == k],  v_j = a_kj / a_kk (j != k), v_k = 1 / a_kk,
 // applied after column k has been reset to the unit vector e_k (checked
 // entrywise: row k becomes a_kj / a_kk, column k becomes -a_ik / a_kk, the
-// pivot 1 / a_kk).  The owner of column k+1 publishes u for the next step
-// and resets its registers; the owners of row k+1 publish that row; two LDS
+// pivot 1 / a_kk).  The owners of column k+1 publish u for the next step and
+// reset their registers; the owners of row k+1 publish that row; two LDS
 // buffers alternate, so one barrier per step suffices.  Entries beyond b are
 // padded with the identity and stay inert.
-// a[k] for a wave-uniform k: a switch on the scalar index (a few scalar
-// branches) keeps the array in registers, where a computed register index
-// would move it to scratch
-template <typename T>
-__device__ __forceinline__ T pick(const T (&a)[64], int k) {
-  switch (k) {
-    case 0: return a[0];
-    case 1: return a[1];
-    case 2: return a[2];
-    case 3: return a[3];
-    case 4: return a[4];
-    case 5: return a[5];
-    case 6: return a[6];
-    case 7: return a[7];
-    case 8: return a[8];
-    case 9: return a[9];
-    case 10: return a[10];
-    case 11: return a[11];
-    case 12: return a[12];
-    case 13: return a[13];
-    case 14: return a[14];
-    case 15: return a[15];
-    case 16: return a[16];
-    case 17: return a[17];
-    case 18: return a[18];
-    case 19: return a[19];
-    case 20: return a[20];
-    case 21: return a[21];
-    case 22: return a[22];
-    case 23: return a[23];
-    case 24: return a[24];
-    case 25: return a[25];
-    case 26: return a[26];
-    case 27: return a[27];
-    case 28: return a[28];
-    case 29: return a[29];
-    case 30: return a[30];
-    case 31: return a[31];
-    case 32: return a[32];
-    case 33: return a[33];
-    case 34: return a[34];
-    case 35: return a[35];
-    case 36: return a[36];
-    case 37: return a[37];
-    case 38: return a[38];
-    case 39: return a[39];
-    case 40: return a[40];
-    case 41: return a[41];
-    case 42: return a[42];
-    case 43: return a[43];
-    case 44: return a[44];
-    case 45: return a[45];
-    case 46: return a[46];
-    case 47: return a[47];
-    case 48: return a[48];
-    case 49: return a[49];
-    case 50: return a[50];
-    case 51: return a[51];
-    case 52: return a[52];
-    case 53: return a[53];
-    case 54: return a[54];
-    case 55: return a[55];
-    case 56: return a[56];
-    case 57: return a[57];
-    case 58: return a[58];
-    case 59: return a[59];
-    case 60: return a[60];
-    case 61: return a[61];
-    case 62: return a[62];
-    case 63: return a[63];
-    default: return T(0);
-  }
-}
-template <typename T, bool ROWMAJOR_OUT, int NB, int RPT>
-__global__ __launch_bounds__(NB * NB / RPT) void k_gj_block_inverse(const T* __restrict__ X, int64_t ldx,
-                                                                    T* __restrict__ out, int b) {
-  __shared__ T colk[2][NB], rowk[2][NB];
-  const int t = threadIdx.x, j = t % NB;
-  // the row group is the same for a whole wavefront (NB >= 64): keep it scalar
-  const int i0 = __builtin_amdgcn_readfirstlane(RPT * (t / NB));
-  T a[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = i0 + r;
-    a[r] = (i < b && j < b) ? X[int64_t(j) * ldx + i] : T(i == j ? 1 : 0);
-  }
-  if (i0 == 0) rowk[0][j] = a[0];
-  if (j == 0) {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      colk[0][i0 + r] = a[r] - T(i0 + r == 0 ? 1 : 0);
-      a[r] = T(i0 + r == 0 ? 1 : 0);
-    }
-  }
-  for (int k = 0; k < b; ++k) {
-    const int buf = k & 1, nb = buf ^ 1;
-    const int kn = k + 1;
-    __syncthreads();
-    const T ip = T(1) / (colk[buf][k] + T(1));
-    const T rj = rowk[buf][j];
-    const T v = (j == k) ? ip : rj * ip;
-#pragma unroll
-    for (int r0 = 0; r0 < RPT; r0 += 16) {
-      T u[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) u[r] = colk[buf][i0 + r0 + r];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) a[r0 + r] = fma(-u[r], v, a[r0 + r]);
-    }
-    // publish row k+1: register rk = k+1 - i0 (wave-uniform), picked by a
-    // select tree on its bits (a dynamic register index would go to scratch)
-    const int rk = kn - i0;
-    if (rk >= 0 && rk < RPT) rowk[nb][j] = pick(a, rk);
-    if (j == kn) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        colk[nb][i0 + r] = a[r] - T(i0 + r == kn ? 1 : 0);
-        a[r] = T(i0 + r == kn ? 1 : 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = i0 + r;
-    if (i < b && j < b) out[ROWMAJOR_OUT ? int64_t(i) * b + j : int64_t(j) * b + i] = a[r];
-  }
-}
-
-// The same elimination with the 128 x 128 block tiled 8 x 8 per thread (a
-// 16 x 16 grid of threads): row k+1 and column k+1 are then published by 16
-// threads with vector stores of 8 values each, every thread reads 8 + 8
-// values per step, and with the pivot loop unrolled by 8 the register row /
-// column of the next pivot is a compile-time index.  Padded steps beyond b
-// (up to the next multiple of 8) act on identity rows and change nothing.
+// Row k+1 and column k+1 are published by 16 threads with vector stores of 8
+// values each, every thread reads 8 + 8 values per step, and with the pivot
+// loop unrolled by 8 the register row / column of the next pivot is a
+// compile-time index.  Padded steps beyond b (up to the next multiple of 8)
+// act on identity rows and change nothing.
 template <typename T, bool ROWMAJOR_OUT>
 __global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict__ X, int64_t ldx,
                                                             T* __restrict__ out, int b) {
