@@ -1860,11 +1860,11 @@ struct GmresRun {
   Phase step = DONE;  // phase in which the current step started (set by stage1)
 
   // partial sums of one step on the device: two projection passes of at most
-  // 2 (1024 + (rho+1) nrhs) doubles each, the norm's at most 256 + nrhs; the
+  // 2 (1024 + (rho+1) nrhs) doubles each, the norm's update_blocks(n) nrhs; the
   // finished values [h1 | h2 | norms] the host reads (kept small: copies of
   // a few KB go through the compute queue, larger ones through a copy engine
   // with a cross-queue wait)
-  static size_t part_doubles(int nrhs, int rho) { return 4 * (1024 + size_t(rho + 1) * nrhs) + 256 + nrhs; }
+  size_t part_doubles() const { return 4 * (1024 + size_t(rho + 1) * nrhs) + size_t(update_blocks(n)) * nrhs; }
   static size_t res_doubles(int nrhs, int rho) { return 4 * size_t(rho + 1) * nrhs + nrhs; }
   static size_t pinned_bytes(int nrhs, int rho) {
     return 8 * (2 * res_doubles(nrhs, rho) + 2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs) +
@@ -1880,7 +1880,7 @@ struct GmresRun {
     vecd = 2 * vs;
     vstep = int64_t(nrhs) * vs;
     const size_t need =
-        size_t(rho + 1 + 5) * nrhs * vecd + part_doubles(nrhs, rho) + res_doubles(nrhs, rho) + 16 * size_t(nrhs);
+        size_t(rho + 1 + 5) * nrhs * vecd + part_doubles() + res_doubles(nrhs, rho) + 16 * size_t(nrhs);
     double* W = need_work(c, need);
     V = W;
     w = V + size_t(rho + 1) * nrhs * vecd;
@@ -1889,7 +1889,7 @@ struct GmresRun {
     s2 = s1 + nrhs * vecd;
     s3 = s2 + nrhs * vecd;
     dpar = s3 + nrhs * vecd;                   // step partial sums
-    dres = dpar + part_doubles(nrhs, rho);     // step results for the host
+    dres = dpar + part_doubles();              // step results for the host
     dn = dres + res_doubles(nrhs, rho);        // nrhs doubles, norms outside the cycle
     dact = dalloc_c<int32_t>(c, nrhs);
     dupd = dalloc_c<int32_t>(c, nrhs);
@@ -1989,7 +1989,8 @@ struct GmresRun {
     if (step == ITER) {  // CGS2 (two passes), the norm, v_{j+1} = w / |w|
       // the split reductions stay as partial sums: the update kernels, the
       // normalisation and the host each add them in the same order
-      const int S1 = dots_splits(j + 1, nrhs, n), S2 = norm_splits(nrhs, n);
+      // (the second update also leaves the partial sums of the new norm)
+      const int S1 = dots_splits(j + 1, nrhs, n), S2 = update_blocks(n);
       const size_t m = 2 * size_t(S1) * (j + 1) * nrhs;
       double* h1 = dpar;
       double* h2 = dpar + m;
@@ -1998,8 +1999,7 @@ struct GmresRun {
       dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, c->stream);
       launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, j + 1, -1.0, c->stream, S1);
       dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, c->stream);
-      launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, j + 1, -1.0, c->stream, S1);
-      norms_part_only(w, vs, n, nrhs, hn, c->stream);
+      launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, j + 1, -1.0, c->stream, S1, hn);
       launch_finish_step(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, hn, S2, act, h1, h2, S1, j + 1, dres,
                          c->stream);
       const size_t fin = 4 * size_t(j + 1) * nrhs + nrhs;

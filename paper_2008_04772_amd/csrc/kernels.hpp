@@ -244,22 +244,22 @@ void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int6
                  const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st,
                  double* part = nullptr);
 // w += sign V h; the coefficient (r, i) is the sum of S partial values
-// h[(r hstride + i) S + s] (complex), added in order of s
+// h[(r hstride + i) S + s] (complex), added in order of s.  nrm2 (optional):
+// partial sums of |w|^2 of the result, update_blocks(n) per right-hand side
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride,
-                   double sign, hipStream_t st, int S = 1);
+                   double sign, hipStream_t st, int S = 1, double* nrm2 = nullptr);
+int update_blocks(int n);
 // part (optional): scratch of nrhs + 256 doubles for a split reduction
 void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st,
                   double* part = nullptr);
-// Split reductions left unfinished: the consumer (launch_update, the host)
-// adds the partial values in order.  Both return S, the partials per result.
-//   dots:  part[((r nvec + i) S + s)] complex, at most 2 (1024 + nvec nrhs) doubles
-//   norms: part[r S + s] partial sums of squares, at most 256 + nrhs doubles
+// Split reduction left unfinished: the consumers (launch_update,
+// launch_finish_step) add the partial values in order.  Returns S, the
+// partials per result: part[((r nvec + i) S + s)] complex, at most
+// 2 (1024 + nvec nrhs) doubles.
 int dots_splits(int nvec, int nrhs, int n);
-int norm_splits(int nrhs, int n);
 int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, double* part, hipStream_t st);
-int norms_part_only(const double* w, int64_t wstride, int n, int nrhs, double* part, hipStream_t st);
 // v = w / sqrt(sum_s nrm2[r S2 + s]) per right-hand side (0 where inactive or
 // zero); also the finished sums fin = [h1 | h2 | norms] of the step's two
 // projection passes (h1p, h2p: S1 partials per coefficient, nvec coefficients)

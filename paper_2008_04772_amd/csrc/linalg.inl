@@ -719,12 +719,19 @@ void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int6
 // vectors at a time are summed into LDS, then its four wavefronts take every
 // fourth vector (coalesced 1 KB reads per vector, four loads in flight) and
 // the four partial results are added in a fixed order through LDS.
+// With nrm2 given, the workgroup also stores the sum of |w|^2 over its 64
+// updated elements at nrm2[r gridDim.x + blockIdx.x] (0 for an inactive
+// right-hand side): the partial sums of the new vector's norm.
 __global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, int nvec, double* w,
                                                 int64_t wstride, int n, const int32_t* active, int64_t rstride_v,
-                                                const double* hp, int64_t hstride, int S, double sign) {
+                                                const double* hp, int64_t hstride, int S, double sign,
+                                                double* nrm2) {
   constexpr int CH = 1024;
   const int r = blockIdx.y;
-  if (!active[r]) return;
+  if (!active[r]) {
+    if (nrm2 && threadIdx.x == 0) nrm2[int64_t(r) * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
   const bool in = k < n;
@@ -769,23 +776,34 @@ __global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, 
   }
   if (wv > 0) part[wv - 1][lane] = double2{re, im};
   __syncthreads();
-  if (wv == 0 && in) {
+  if (wv == 0) {
+    double sq = 0.0;
+    if (in) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      re += part[q][lane].x;
-      im += part[q][lane].y;
+      for (int q = 0; q < 3; ++q) {
+        re += part[q][lane].x;
+        im += part[q][lane].y;
+      }
+      double* ww = w + 2 * (int64_t(r) * wstride + k);
+      const double nr = ww[0] + sign * re, ni = ww[1] + sign * im;
+      ww[0] = nr;
+      ww[1] = ni;
+      sq = nr * nr + ni * ni;
     }
-    double* ww = w + 2 * (int64_t(r) * wstride + k);
-    ww[0] += sign * re;
-    ww[1] += sign * im;
+    if (nrm2) {
+      sq = wsum(sq);
+      if (lane == 0) nrm2[int64_t(r) * gridDim.x + blockIdx.x] = sq;
+    }
   }
 }
 
+int update_blocks(int n) { return (n + 63) / 64; }
+
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride, double sign,
-                   hipStream_t st, int S) {
-  hipLaunchKernelGGL(k_update, dim3((n + 63) / 64, nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
-                     rstride_v, h, hstride, S, sign);
+                   hipStream_t st, int S, double* nrm2) {
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(n), nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
+                     rstride_v, h, hstride, S, sign, nrm2);
 }
 
 __global__ void k_norms(const double* w, int64_t wstride, int n, double* out) {
@@ -828,13 +846,6 @@ __global__ void k_norms_fin(const double* part, int S, int nrhs, double* out) {
 }
 
 int norm_splits(int nrhs, int n) { return std::max(1, std::min({(256 + nrhs - 1) / nrhs, 64, (n + 255) / 256})); }
-
-int norms_part_only(const double* w, int64_t wstride, int n, int nrhs, double* part, hipStream_t st) {
-  const int S = norm_splits(nrhs, n);
-  const int chunk = (n + S - 1) / S;
-  hipLaunchKernelGGL(k_norms_part, dim3(S, nrhs), dim3(256), 0, st, w, wstride, n, S, chunk, part);
-  return S;
-}
 
 void launch_norms(const double* w, int64_t wstride, int n, int nrhs, double* out, hipStream_t st, double* part) {
   const int S = part ? norm_splits(nrhs, n) : 1;
