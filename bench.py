@@ -39,7 +39,7 @@ HBM_PEAK = 8000.0  # GB/s
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy
 # (profiles/gemv_pmchwt3_sphere5120_hbm_counters.md); valid for that kernel
 # version only
-GEMV_TRAFFIC = {"sphere5120": 1418.2e6}
+GEMV_TRAFFIC = {"sphere5120": 1417.9e6}
 
 WORKLOADS = {
     "sphere5120": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, 1 plane wave; "

@@ -884,9 +884,18 @@ __global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64
                               const double* h2p, int S1, int nvec, int nrhs, double* fin) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
+  // |w|^2 from its partial sums: strided per thread, then a fixed tree over
+  // the workgroup (the same order in every workgroup)
+  __shared__ double red[256];
   double ss = 0;
-  for (int sidx = 0; sidx < S2; ++sidx) ss += nrm2[int64_t(r) * S2 + sidx];
-  const double h = sqrt(ss);
+  for (int sidx = threadIdx.x; sidx < S2; sidx += blockDim.x) ss += nrm2[int64_t(r) * S2 + sidx];
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  const double h = sqrt(red[0]);
   if (blockIdx.x == 0) {
     const double2* p1 = reinterpret_cast<const double2*>(h1p) + int64_t(r) * nvec * S1;
     const double2* p2 = reinterpret_cast<const double2*>(h2p) + int64_t(r) * nvec * S1;
