@@ -1014,11 +1014,16 @@ namespace pmchwt {
 // loop unrolled by 8 the register row / column of the next pivot is a
 // compile-time index.  Padded steps beyond b (up to the next multiple of 8)
 // act on identity rows and change nothing.
+// Reciprocal of a pivot: the hardware reciprocal in FP32 (1 ulp; the FP32
+// inverse only preconditions), the IEEE quotient in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename T, bool ROWMAJOR_OUT>
 __global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict__ X, int64_t ldx,
                                                             T* __restrict__ out, int b) {
   constexpr int NB = 128;
-  __shared__ T colk[2][NB], rowk[2][NB];
+  __shared__ T colk[2][NB], rowk[2][NB], pinv[2];
   const int t = threadIdx.x;
   const int ti = t >> 4, tj = t & 15;  // rows 8 ti .. +8, columns 8 tj .. +8
   const int r0 = 8 * ti, c0 = 8 * tj;
@@ -1036,6 +1041,7 @@ __global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict_
     for (int c = 0; c < 8; ++c) rowk[0][c0 + c] = a[0][c];
   }
   if (tj == 0) {
+    if (ti == 0) pinv[0] = recip(a[0][0]);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       colk[0][r0 + r] = a[r][0] - T(r0 + r == 0 ? 1 : 0);
@@ -1049,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict_
       const int k = g + s, kn = k + 1;
       const int buf = s & 1, nb = buf ^ 1;  // k parity (g is a multiple of 8)
       __syncthreads();
-      const T ip = T(1) / (colk[buf][k] + T(1));
+      const T ip = pinv[buf];
       T u[8], v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) u[r] = colk[buf][r0 + r];
@@ -1068,6 +1074,9 @@ __global__ __launch_bounds__(256) void k_gj_block_inverse_t(const T* __restrict_
           for (int c = 0; c < 8; ++c) rowk[nb][c0 + c] = a[sn][c];
         }
         if (tj == gn) {
+          // the owner of the next pivot publishes its reciprocal, so that no
+          // thread divides between the barrier and its update
+          if (ti == gn) pinv[nb] = recip(a[sn][sn]);
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
             colk[nb][r0 + r] = a[r][sn] - T(r0 + r == kn ? 1 : 0);
