@@ -200,6 +200,13 @@ struct pmchwt_ctx {
   std::vector<int32_t> h_col;
   // mass / Gram
   std::vector<DBuf> MA, Minv, MinvT;
+  // truncated CSR copies of the FP32 inverses (mixed-precision P): the
+  // products for fewer than 16 right-hand sides read these
+  struct SparseInv {
+    DBuf rowptr, col, val;
+    int64_t nnz = 0;
+  };
+  std::vector<SparseInv> MinvS, MinvTS;
   // RWG Gram matrix (5 nonzeros per row), CSR over union edges with
   // scatterer-local column indices; pattern and slot map built once per geometry
   bool gram_valid = false;
@@ -1391,11 +1398,31 @@ void build_gram_pattern(pmchwt_ctx* c) {
   c->gram_valid = true;
 }
 
+// Truncated CSR copy of an FP32 inverse (entries of at least 2^-27 of their
+// row's largest; the rest lies below the FP32 rounding of the stored
+// inverse).  One host wait for the entry count.
+pmchwt_ctx::SparseInv truncated_inverse(pmchwt_ctx* c, const float* A, int64_t ld, int n) {
+  pmchwt_ctx::SparseInv t;
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<float>(c, size_t(n));
+  t.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  build_truncated_inverse(A, ld, n, 0x1p-27f, cnt.as<int32_t>(), thr.as<float>(), t.rowptr.as<int64_t>(), c->stream);
+  HIPCHK(hipMemcpyAsync(&t.nnz, t.rowptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  t.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(1, t.nnz)));
+  t.val = dalloc_c<float>(c, size_t(std::max<int64_t>(1, t.nnz)));
+  fill_truncated_inverse(A, ld, n, thr.as<float>(), t.rowptr.as<int64_t>(), t.col.as<int32_t>(), t.val.as<float>(),
+                         c->stream);
+  HIPCHK(hipGetLastError());
+  return t;
+}
+
 void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   EvTimer t(c->stream);
   c->MA.clear();
   c->Minv.clear();
   c->MinvT.clear();
+  c->MinvS.clear();
+  c->MinvTS.clear();
   if (!c->gram_valid) build_gram_pattern(c);
   std::vector<int64_t> off, ld;
   int64_t tot = 0;
@@ -1440,6 +1467,8 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
       launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
       gj_inverse_f32(c, Mf.as<float>(), int(ldm));
       launch_transpose_f32(Mf.as<float>(), MfT.as<float>(), int(ldm), c->stream);
+      c->MinvS.push_back(truncated_inverse(c, Mf.as<float>(), ldm, n));
+      c->MinvTS.push_back(truncated_inverse(c, MfT.as<float>(), ldm, n));
       c->Minv.push_back(std::move(Mf));
       c->MinvT.push_back(std::move(MfT));
       continue;
@@ -1591,8 +1620,8 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
       launch_mfma_real2(c->Minv[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, Bw, c->stream);
     else if (c->mass_f32)
-      launch_gemv_real2(c->Minv[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
-                        nrhs, vs, E, c->stream);
+      launch_spmv_real2_csr(c->MinvS[m].rowptr.as<int64_t>(), c->MinvS[m].col.as<int32_t>(),
+                            c->MinvS[m].val.as<float>(), s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E, c->stream);
     else
       launch_gemv_real2(c->Minv[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, c->stream);
@@ -1622,8 +1651,9 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
       launch_mfma_real2(c->MinvT[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
                         nrhs, vs, E, Bw, c->stream);
     else if (c->mass_f32)
-      launch_gemv_real2(c->MinvT[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
-                        nrhs, vs, E, c->stream);
+      launch_spmv_real2_csr(c->MinvTS[m].rowptr.as<int64_t>(), c->MinvTS[m].col.as<int32_t>(),
+                            c->MinvTS[m].val.as<float>(), s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
+                            c->stream);
     else
       launch_gemv_real2(c->MinvT[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
                         nrhs, vs, E, c->stream);

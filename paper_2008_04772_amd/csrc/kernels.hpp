@@ -213,6 +213,17 @@ void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // y = alpha M x for both trace components (second component at +cstride);
 // M is double or float (accumulation in double); ld a multiple of 4 with
 // zero padding columns
+// Truncated CSR copy of an FP32 inverse (n x n, row-major, ld): entries of at
+// least rel x their row's largest, ascending columns.  build_*: counts (cnt,
+// n ints), thresholds (thr, n floats) and rowptr (n + 1); fill_*: col / val of
+// rowptr[n] entries.  launch_spmv_real2_csr: the launch_gemv_real2 product
+// from that copy.
+void build_truncated_inverse(const float* A, int64_t ld, int n, float rel, int32_t* cnt, float* thr, int64_t* rowptr,
+                             hipStream_t st);
+void fill_truncated_inverse(const float* A, int64_t ld, int n, const float* thr, const int64_t* rowptr, int32_t* col,
+                            float* val, hipStream_t st);
+void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);

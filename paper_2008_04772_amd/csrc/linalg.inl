@@ -1304,6 +1304,163 @@ template void launch_gemv_real2<double>(const double*, int64_t, int, int, double
 template void launch_gemv_real2<float>(const float*, int64_t, int, int, double, const double*, double*, int, int64_t,
                                        int64_t, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Truncated sparse copy of an FP32 inverse mass matrix (mixed-precision P).
+// The inverse of the well-conditioned mixed mass matrix decays with the
+// graph distance between functions; entries below 2^-27 of their row's
+// largest lie under the FP32 rounding of the stored inverse and are dropped
+// (on the 7680-edge sphere: 584 of 7680 per row kept, product error 5e-8
+// against 3e-8 for the dense FP32 copy).  One wavefront per row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trunc_count(const float* __restrict__ A, int64_t ld, int rows, int cols,
+                                                     float rel, int32_t* cnt, float* thr) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* a = A + int64_t(row) * ld;
+  float mx = 0.0f;
+  for (int j = lane; j < cols; j += 64) mx = fmaxf(mx, fabsf(a[j]));
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  const float t = rel * mx;
+  int c = 0;
+  for (int j = lane; j < cols; j += 64) c += (fabsf(a[j]) >= t && a[j] != 0.0f) ? 1 : 0;
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) {
+    cnt[row] = c;
+    thr[row] = t;
+  }
+}
+
+// rowptr[0] = 0, rowptr[i + 1] = cnt[0] + ... + cnt[i]: one workgroup, each
+// thread sums a contiguous run of rows, then the run totals are scanned in
+// order by one thread
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* cnt, int rows, int64_t* rowptr) {
+  __shared__ int64_t tot[1024];
+  const int t = threadIdx.x;
+  const int per = (rows + 1023) / 1024;
+  const int r0 = min(rows, t * per), r1 = min(rows, r0 + per);
+  int64_t s = 0;
+  for (int r = r0; r < r1; ++r) s += cnt[r];
+  tot[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < 1024; ++q) {
+      const int64_t v = tot[q];
+      tot[q] = run;
+      run += v;
+    }
+    rowptr[0] = 0;
+  }
+  __syncthreads();
+  int64_t run = tot[t];
+  for (int r = r0; r < r1; ++r) {
+    run += cnt[r];
+    rowptr[r + 1] = run;
+  }
+}
+
+// kept entries of each row in ascending column order (wavefront ballot)
+__global__ __launch_bounds__(256) void k_trunc_fill(const float* __restrict__ A, int64_t ld, int rows, int cols,
+                                                    const float* thr, const int64_t* rowptr, int32_t* col,
+                                                    float* val) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* a = A + int64_t(row) * ld;
+  const float t = thr[row];
+  int64_t base = rowptr[row];
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  for (int j0 = 0; j0 < cols; j0 += 64) {
+    const int j = j0 + lane;
+    const float v = j < cols ? a[j] : 0.0f;
+    const bool keep = j < cols && fabsf(v) >= t && v != 0.0f;
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int64_t pos = base + __popcll(m & below);
+      col[pos] = j;
+      val[pos] = v;
+    }
+    base += __popcll(m);
+  }
+}
+
+void build_truncated_inverse(const float* A, int64_t ld, int n, float rel, int32_t* cnt, float* thr, int64_t* rowptr,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_trunc_count, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, rel, cnt, thr);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, n, rowptr);
+}
+
+void fill_truncated_inverse(const float* A, int64_t ld, int n, const float* thr, const int64_t* rowptr, int32_t* col,
+                            float* val, hipStream_t st) {
+  hipLaunchKernelGGL(k_trunc_fill, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, thr, rowptr, col, val);
+}
+
+// y = alpha * M x (M real CSR) on the two trace components of NR complex
+// vectors: the same product as k_gemv_real2 from the truncated inverse.  One
+// wavefront per row, lanes over the row's entries.
+template <int NR>
+__global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const float* __restrict__ val, int rows, double alpha,
+                                                        const double* __restrict__ x, double* y, int64_t vstride,
+                                                        int64_t cstride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  double acc[NR][4];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+  const int64_t p1 = rowptr[row + 1];
+  for (int64_t p = rowptr[row] + lane; p < p1; p += 64) {
+    const int c = col[p];
+    const double v = double(val[p]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double2 x0 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + c));
+      const double2 x1 = *reinterpret_cast<const double2*>(x + 2 * (int64_t(r) * vstride + cstride + c));
+      acc[r][0] += v * x0.x;
+      acc[r][1] += v * x0.y;
+      acc[r][2] += v * x1.x;
+      acc[r][3] += v * x1.y;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = wsum(acc[r][q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double* q0 = y + 2 * (int64_t(r) * vstride + row);
+      double* q1 = q0 + 2 * cstride;
+      q0[0] = alpha * acc[r][0];
+      q0[1] = alpha * acc[r][1];
+      q1[0] = alpha * acc[r][2];
+      q1[1] = alpha * acc[r][3];
+    }
+  }
+}
+
+void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
+  const dim3 grid(unsigned((rows + 3) / 4)), block(256);
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0;
+    const double* xx = x + 2 * int64_t(r0) * vstride;
+    double* yy = y + 2 * int64_t(r0) * vstride;
+    if (left >= 4) {
+      hipLaunchKernelGGL((k_spmv_real2_csr<4>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy, vstride,
+                         cstride);
+      r0 += 4;
+    } else {
+      hipLaunchKernelGGL((k_spmv_real2_csr<1>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy, vstride,
+                         cstride);
+      r0 += 1;
+    }
+  }
+}
+
 __global__ void k_spmv_real(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                             const double* __restrict__ val, int rows, const double* __restrict__ x, double* y,
                             int64_t vstride) {
