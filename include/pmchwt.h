@@ -99,8 +99,11 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       operator storage in FP32, singular pairs in FP64.  For P: MIXED
  *       integrates the near-field BC entries in FP32 (pair classification in
  *       FP64, entries stored in FP64) and computes and stores the inverted
- *       mass matrices M_A^-1 and M_A^-T in FP32 (Gauss-Jordan with its rank
- *       updates on the FP32 matrix cores); both only perturb the
+ *       mass matrices M_A^-1 and M_A^-T in FP32 (a Chebyshev iteration on
+ *       the sparse M_A, stopped at ||I - X M_A||_F / sqrt(n) <= 1e-6, else
+ *       Gauss-Jordan with its rank updates on the matrix cores); products
+ *       with fewer than 16 right-hand sides read a copy without the entries
+ *       below 2^-27 of their row's largest.  All of this only perturbs the
  *       preconditioner, not the system that is solved.                       */
 typedef struct {
   int32_t q_near, q_medium, q_far;
@@ -160,6 +163,9 @@ typedef struct {
   double ms_mfma_total;      /* many-RHS operator products on the matrix cores          */
   int64_t mfma_launches;
   int64_t mfma_flops;        /* real flops of those GEMMs (8 per complex MAC)           */
+  int32_t mass_iterations;   /* Chebyshev steps of the last FP32 mass-matrix inverse
+                                (0: Gauss-Jordan, always the case for FP64)          */
+  double mass_residual;      /* ||I - X M_A||_F / sqrt(n) at its last check          */
   int64_t lookahead_discarded; /* Arnoldi steps queued ahead of a convergence and
                                   dropped (their operator products are not counted
                                   in the solve's matvecs)                            */

@@ -67,7 +67,8 @@ class pmchwt_profile(ctypes.Structure):
                 ("wall_mass", ctypes.c_double), ("ms_matvec_total", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("matvec_bytes", ctypes.c_int64),
                 ("ms_mfma_total", ctypes.c_double), ("mfma_launches", ctypes.c_int64),
-                ("mfma_flops", ctypes.c_int64), ("lookahead_discarded", ctypes.c_int64)]
+                ("mfma_flops", ctypes.c_int64), ("mass_iterations", ctypes.c_int32),
+                ("mass_residual", ctypes.c_double), ("lookahead_discarded", ctypes.c_int64)]
 
 
 class pmchwt_server_opts(ctypes.Structure):

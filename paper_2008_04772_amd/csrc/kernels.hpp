@@ -218,10 +218,28 @@ void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // n ints), thresholds (thr, n floats) and rowptr (n + 1); fill_*: col / val of
 // rowptr[n] entries.  launch_spmv_real2_csr: the launch_gemv_real2 product
 // from that copy.
-void build_truncated_inverse(const float* A, int64_t ld, int n, float rel, int32_t* cnt, float* thr, int64_t* rowptr,
+template <typename T>
+void build_truncated_inverse(const T* A, int64_t ld, int n, T rel, int32_t* cnt, T* thr, int64_t* rowptr,
                              hipStream_t st);
-void fill_truncated_inverse(const float* A, int64_t ld, int n, const float* thr, const int64_t* rowptr, int32_t* col,
-                            float* val, hipStream_t st);
+template <typename T>
+void fill_truncated_inverse(const T* A, int64_t ld, int n, const T* thr, const int64_t* rowptr, int32_t* col, T* val,
+                            hipStream_t st);
+// One step of the Chebyshev iteration for the inverse of M (n x n; its columns
+// as an ELL copy of W slots, entry-major, from launch_csc_to_ell) on X and D
+// (n rows, ld); rn_part: one partial sum of ||I - X M||_F^2 per workgroup,
+// (n + cheb_rows(n) - 1) / cheb_rows(n) of them.  cheb_width: the ELL width
+// for the longest column (0: more than 64 entries)
+template <typename T>
+int cheb_rows(int n);
+int cheb_width(int maxcount);
+template <typename T>
+void launch_csc_to_ell(const int64_t* colptr, const int32_t* rowidx, const double* val, int n, int W, int32_t* eidx,
+                       T* eval, hipStream_t st);
+template <typename T>
+void launch_cheb_step(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const T* eval, int W, double cD, double cR,
+                      double inv_d, bool first, double* rn_part, hipStream_t st);
+template <typename T>
+void launch_identity_tail(T* X, int64_t ld, int n, hipStream_t st);
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
 template <typename M>

@@ -1312,18 +1312,19 @@ template void launch_gemv_real2<float>(const float*, int64_t, int, int, double, 
 // (on the 7680-edge sphere: 584 of 7680 per row kept, product error 5e-8
 // against 3e-8 for the dense FP32 copy).  One wavefront per row.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trunc_count(const float* __restrict__ A, int64_t ld, int rows, int cols,
-                                                     float rel, int32_t* cnt, float* thr) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_trunc_count(const T* __restrict__ A, int64_t ld, int rows, int cols, T rel,
+                                                     int32_t* cnt, T* thr) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const float* a = A + int64_t(row) * ld;
-  float mx = 0.0f;
-  for (int j = lane; j < cols; j += 64) mx = fmaxf(mx, fabsf(a[j]));
-  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  const float t = rel * mx;
+  const T* a = A + int64_t(row) * ld;
+  T mx = T(0);
+  for (int j = lane; j < cols; j += 64) mx = fmax(mx, fabs(a[j]));
+  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  const T t = rel * mx;
   int c = 0;
-  for (int j = lane; j < cols; j += 64) c += (fabsf(a[j]) >= t && a[j] != 0.0f) ? 1 : 0;
+  for (int j = lane; j < cols; j += 64) c += (fabs(a[j]) >= t && a[j] != T(0)) ? 1 : 0;
   for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
   if (lane == 0) {
     cnt[row] = c;
@@ -1361,20 +1362,20 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* cnt, int ro
 }
 
 // kept entries of each row in ascending column order (wavefront ballot)
-__global__ __launch_bounds__(256) void k_trunc_fill(const float* __restrict__ A, int64_t ld, int rows, int cols,
-                                                    const float* thr, const int64_t* rowptr, int32_t* col,
-                                                    float* val) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_trunc_fill(const T* __restrict__ A, int64_t ld, int rows, int cols,
+                                                    const T* thr, const int64_t* rowptr, int32_t* col, T* val) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const float* a = A + int64_t(row) * ld;
-  const float t = thr[row];
+  const T* a = A + int64_t(row) * ld;
+  const T t = thr[row];
   int64_t base = rowptr[row];
   const uint64_t below = (uint64_t(1) << lane) - 1;
   for (int j0 = 0; j0 < cols; j0 += 64) {
     const int j = j0 + lane;
-    const float v = j < cols ? a[j] : 0.0f;
-    const bool keep = j < cols && fabsf(v) >= t && v != 0.0f;
+    const T v = j < cols ? a[j] : T(0);
+    const bool keep = j < cols && fabs(v) >= t && v != T(0);
     const uint64_t m = __ballot(keep);
     if (keep) {
       const int64_t pos = base + __popcll(m & below);
@@ -1385,16 +1386,194 @@ __global__ __launch_bounds__(256) void k_trunc_fill(const float* __restrict__ A,
   }
 }
 
-void build_truncated_inverse(const float* A, int64_t ld, int n, float rel, int32_t* cnt, float* thr, int64_t* rowptr,
+template <typename T>
+void build_truncated_inverse(const T* A, int64_t ld, int n, T rel, int32_t* cnt, T* thr, int64_t* rowptr,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_trunc_count, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, rel, cnt, thr);
+  hipLaunchKernelGGL((k_trunc_count<T>), dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, rel, cnt, thr);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, n, rowptr);
 }
+template void build_truncated_inverse<float>(const float*, int64_t, int, float, int32_t*, float*, int64_t*,
+                                             hipStream_t);
+template void build_truncated_inverse<double>(const double*, int64_t, int, double, int32_t*, double*, int64_t*,
+                                              hipStream_t);
 
-void fill_truncated_inverse(const float* A, int64_t ld, int n, const float* thr, const int64_t* rowptr, int32_t* col,
-                            float* val, hipStream_t st) {
-  hipLaunchKernelGGL(k_trunc_fill, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, thr, rowptr, col, val);
+template <typename T>
+void fill_truncated_inverse(const T* A, int64_t ld, int n, const T* thr, const int64_t* rowptr, int32_t* col, T* val,
+                            hipStream_t st) {
+  hipLaunchKernelGGL((k_trunc_fill<T>), dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, n, thr, rowptr, col,
+                     val);
 }
+template void fill_truncated_inverse<float>(const float*, int64_t, int, const float*, const int64_t*, int32_t*,
+                                            float*, hipStream_t);
+template void fill_truncated_inverse<double>(const double*, int64_t, int, const double*, const int64_t*, int32_t*,
+                                             double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Inverse of the mixed mass matrix by a Chebyshev iteration from the right,
+//   R_k = I - X_k M,  D_k = rho_k rho_{k-1} D_{k-1} + (2 rho_k / c) R_k,
+//   X_{k+1} = X_k + D_k,  rho_k = 1 / (2 sigma - rho_{k-1}),
+// for a spectrum inside [d - c, d + c] (sigma = d / c), starting from
+// X_1 = D_0 = I / d.  Row i of the iteration involves row i of X only, so a
+// workgroup keeps RB rows of X in LDS and forms (X M)_ij for every column j
+// from the CSC of the sparse M (about 19 entries per column), accumulating in
+// FP64.  Each launch is one step over all rows; it also leaves the partial
+// sums of ||R_k||_F^2 per workgroup.  first: X_1 and D_0 are generated.
+// ---------------------------------------------------------------------------
+template <typename T, int RB>
+struct RowPack {
+  T v[RB];
+};
+
+template <typename T, int RB, int W>
+__global__ __launch_bounds__(512) void k_cheb_step(T* X, T* D, int64_t ld, int n, const int32_t* __restrict__ eidx,
+                                                    const T* __restrict__ eval, double cD, double cR, double inv_d,
+                                                    int first, double* rn_part) {
+  extern __shared__ __align__(16) unsigned char cheb_raw[];
+  // rows interleaved: xs[k] holds X[row0 + r][k] for the RB rows, one vector read per entry of M
+  RowPack<T, RB>* xs = reinterpret_cast<RowPack<T, RB>*>(cheb_raw);
+  __shared__ double red[512];
+  const int row0 = blockIdx.x * RB;
+  const int nr = min(RB, n - row0);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    RowPack<T, RB> pk;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      pk.v[r] = r >= nr ? T(0) : (first ? T(j == row0 + r ? inv_d : 0.0) : X[int64_t(row0 + r) * ld + j]);
+    xs[j] = pk;
+  }
+  __syncthreads();
+  double ss = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    // column j of M, W slots (zero-padded), entry-major: coalesced over j
+    int kk[W];
+    T vv[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      kk[q] = eidx[int64_t(q) * n + j];
+      vv[q] = eval[int64_t(q) * n + j];
+    }
+    double t[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) t[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const RowPack<T, RB> xk = xs[kk[q]];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) t[r] += double(xk.v[r]) * double(vv[q]);
+    }
+    const RowPack<T, RB> xj = xs[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r >= nr) break;
+      const int i = row0 + r;
+      const int64_t o = int64_t(i) * ld + j;
+      const double Rv = (j == i ? 1.0 : 0.0) - t[r];
+      const double dprev = first ? (j == i ? inv_d : 0.0) : double(D[o]);
+      const double dn = cD * dprev + cR * Rv;
+      D[o] = T(dn);
+      X[o] = T(double(xj.v[r]) + dn);
+      ss += Rv * Rv;
+    }
+  }
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rn_part[blockIdx.x] = red[0];
+}
+
+// ELL copy (W slots per column, entry-major, padding: index j, value 0) of
+// the CSC colptr / rowidx / val
+template <typename T>
+__global__ void k_csc_to_ell(const int64_t* colptr, const int32_t* rowidx, const double* val, int n, int W,
+                             int32_t* eidx, T* eval) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t p0 = colptr[j];
+  const int c = int(colptr[j + 1] - p0);
+  for (int q = 0; q < W; ++q) {
+    eidx[int64_t(q) * n + j] = q < c ? rowidx[p0 + q] : j;
+    eval[int64_t(q) * n + j] = q < c ? T(val[p0 + q]) : T(0);
+  }
+}
+template <typename T>
+void launch_csc_to_ell(const int64_t* colptr, const int32_t* rowidx, const double* val, int n, int W, int32_t* eidx,
+                       T* eval, hipStream_t st) {
+  hipLaunchKernelGGL((k_csc_to_ell<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, colptr, rowidx, val, n, W,
+                     eidx, eval);
+}
+template void launch_csc_to_ell<float>(const int64_t*, const int32_t*, const double*, int, int, int32_t*, float*,
+                                       hipStream_t);
+
+// rows per workgroup: as many rows of X as fit in 136 KB of LDS (at most 4)
+template <typename T>
+int cheb_rows(int n) {
+  const int64_t per = int64_t(n) * sizeof(T);
+  const int rb = int(std::min<int64_t>(4, (136 * 1024) / std::max<int64_t>(per, 1)));
+  return rb >= 4 ? 4 : (rb >= 2 ? 2 : rb);
+}
+template int cheb_rows<float>(int);
+
+template <typename T, int RB, int W>
+static void cheb_launch(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const T* eval, double cD, double cR,
+                        double inv_d, bool first, double* rn_part, hipStream_t st) {
+  static bool attr = false;  // beyond the default dynamic LDS limit
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cheb_step<T, RB, W>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 136 * 1024);
+    attr = true;
+  }
+  const dim3 grid(unsigned((n + RB - 1) / RB)), block(512);
+  hipLaunchKernelGGL((k_cheb_step<T, RB, W>), grid, block, size_t(RB) * n * sizeof(T), st, X, D, ld, n, eidx, eval, cD,
+                     cR, inv_d, int(first), rn_part);
+}
+
+template <typename T, int W>
+static void cheb_launch_rb(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const T* eval, double cD, double cR,
+                           double inv_d, bool first, double* rn_part, hipStream_t st) {
+  const int rb = cheb_rows<T>(n);
+  if (rb == 4)
+    cheb_launch<T, 4, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
+  else if (rb == 2)
+    cheb_launch<T, 2, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
+  else
+    cheb_launch<T, 1, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
+}
+
+int cheb_width(int maxcount) {
+  for (int w : {16, 24, 32, 48, 64})
+    if (maxcount <= w) return w;
+  return 0;
+}
+
+template <typename T>
+void launch_cheb_step(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const T* eval, int W, double cD, double cR,
+                      double inv_d, bool first, double* rn_part, hipStream_t st) {
+  switch (W) {
+    case 16: cheb_launch_rb<T, 16>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st); break;
+    case 24: cheb_launch_rb<T, 24>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st); break;
+    case 32: cheb_launch_rb<T, 32>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st); break;
+    case 48: cheb_launch_rb<T, 48>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st); break;
+    default: cheb_launch_rb<T, 64>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st); break;
+  }
+}
+template void launch_cheb_step<float>(float*, float*, int64_t, int, const int32_t*, const float*, int, double, double,
+                                      double, bool, double*, hipStream_t);
+
+// X[i][i] = 1 for the padding rows n <= i < ld (the inverse of [[M, 0], [0, I]])
+template <typename T>
+__global__ void k_identity_tail(T* X, int64_t ld, int n) {
+  const int64_t i = n + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < ld) X[i * ld + i] = T(1);
+}
+template <typename T>
+void launch_identity_tail(T* X, int64_t ld, int n, hipStream_t st) {
+  if (ld > n) hipLaunchKernelGGL((k_identity_tail<T>), dim3(unsigned((ld - n + 255) / 256)), dim3(256), 0, st, X, ld, n);
+}
+template void launch_identity_tail<float>(float*, int64_t, int, hipStream_t);
+
 
 // y = alpha * M x (M real CSR) on the two trace components of NR complex
 // vectors: the same product as k_gemv_real2 from the truncated inverse.  One

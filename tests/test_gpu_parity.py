@@ -113,3 +113,32 @@ def test_rhs_apply_solve_cross_sections(P, sphere1, oracle_sphere1):
     obs = synth.plane_wave_set(3, seed=9)[0]
     F = ctx.far_field(xs, obs)
     assert rel_fro(F, pr.far_field(x_ref, obs)) < 1e-9
+
+
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_mass_inverse_paths(P, sphere1, prec, bar):
+    """The FP32 inverse mixed mass matrix comes from the Chebyshev iteration
+    (its residual ||I - X M_A||_F / sqrt(n) below the stopping tolerance
+    1e-6), the FP64 one from Gauss-Jordan; the preconditioned operator built
+    from either matches the oracle's exact one (FP64 1e-10, mixed 1e-4; the
+    mixed form applies the truncated copy of the FP32 inverse for these 2
+    right-hand sides)."""
+    note(f"mass inverse, precision {prec}")
+    ctx = make_ctx(P, [sphere1], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=0.5, precond="S_INT", precision=prec,
+                   precisionP=prec)
+    prof = ctx.profile()
+    note(f"  Chebyshev steps {prof['mass_iterations']}, residual {prof['mass_residual']:.2e}")
+    if prec == 1:
+        assert prof["mass_iterations"] > 0 and prof["mass_residual"] <= 1e-6
+    else:
+        assert prof["mass_iterations"] == 0
+    pr = opm.Problem([sphere1], EPS, 2.0, qP=(1, 1, 1), nP=1, chiP=0.5, precond="S_INT")
+    pr.assemble_A()
+    pr.assemble_P()
+    pr.assemble_mass()
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(2, pr.N)) + 1j * rng.normal(size=(2, pr.N))
+    y = ctx.apply(1, x)
+    e = rel_fro(y, x @ (pr.precond_matrix() @ pr.A).T)
+    note(f"  Ptilde A vs oracle {e:.2e}")
+    assert e < bar
