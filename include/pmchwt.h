@@ -104,12 +104,16 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       Gauss-Jordan with its rank updates on the matrix cores); products
  *       with fewer than 16 right-hand sides read a copy without the entries
  *       below 2^-27 of their row's largest.  All of this only perturbs the
- *       preconditioner, not the system that is solved.                       */
+ *       preconditioner, not the system that is solved.
+ *   mass_method : for P with MIXED precision, 0 = the Chebyshev iteration
+ *       with the Gauss-Jordan fall-back, 1 = Gauss-Jordan only.  Ignored
+ *       otherwise; zero-initialised structs get 0.                           */
 typedef struct {
   int32_t q_near, q_medium, q_far;
   int32_t n_singular;
   double chi;
   int32_t precision;
+  int32_t mass_method;
 } pmchwt_assembly_opts;
 
 /* Restarted GMRES (Section 4: tol 1e-5, restart 200).

@@ -40,7 +40,8 @@ class pmchwt_complex(ctypes.Structure):
 
 class pmchwt_assembly_opts(ctypes.Structure):
     _fields_ = [("q_near", ctypes.c_int32), ("q_medium", ctypes.c_int32), ("q_far", ctypes.c_int32),
-                ("n_singular", ctypes.c_int32), ("chi", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("n_singular", ctypes.c_int32), ("chi", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("mass_method", ctypes.c_int32)]
 
 
 class pmchwt_solver_opts(ctypes.Structure):
@@ -221,9 +222,10 @@ def pmchwt_num_edges(ctx, m):
     return E.value
 
 
-def assembly_opts(q=(4, 3, 2), n_singular=4, chi=-1.0, precision=FP64):
+def assembly_opts(q=(4, 3, 2), n_singular=4, chi=-1.0, precision=FP64, mass_method=0):
     return pmchwt_assembly_opts(int(q[0]), int(q[1]), int(q[2]), int(n_singular),
-                                float(chi) if chi is not None and np.isfinite(chi) else -1.0, int(precision))
+                                float(chi) if chi is not None and np.isfinite(chi) else -1.0, int(precision),
+                                int(mass_method))
 
 
 def pmchwt_assemble(ctx, optsA, optsP, precond="S_INT"):

@@ -452,6 +452,8 @@ void check_opts(const pmchwt_assembly_opts* o, const char* which) {
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": n_singular must be 1..8"};
   if (o->precision != PMCHWT_FP64 && o->precision != PMCHWT_MIXED)
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": unknown precision"};
+  if (o->mass_method != 0 && o->mass_method != 1)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_method must be 0 or 1"};
 }
 
 // ---------------------------------------------------------------------------
@@ -1538,7 +1540,7 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
       // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
       // M_A^-1 with zero padding columns, the layout the products read
       DBuf Mf = dalloc_c<float>(c, size_t(ldm) * ldm), MfT = dalloc_c<float>(c, size_t(ldm) * ldm);
-      if (!cheb_inverse<float>(c, mass.as<double>() + off[m], n, ldm, Mf.as<float>(), true)) {
+      if (c->optP.mass_method == 1 || !cheb_inverse<float>(c, mass.as<double>() + off[m], n, ldm, Mf.as<float>(), true)) {
         launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
         gj_inverse_f32(c, Mf.as<float>(), int(ldm));
         c->prof.mass_iterations = 0;

@@ -115,20 +115,24 @@ def test_rhs_apply_solve_cross_sections(P, sphere1, oracle_sphere1):
     assert rel_fro(F, pr.far_field(x_ref, obs)) < 1e-9
 
 
-@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
-def test_mass_inverse_paths(P, sphere1, prec, bar):
+@pytest.mark.parametrize("prec,method,bar", [(0, 0, 1e-10), (1, 0, 1e-4), (1, 1, 1e-4)])
+def test_mass_inverse_paths(P, sphere1, prec, method, bar):
     """The FP32 inverse mixed mass matrix comes from the Chebyshev iteration
     (its residual ||I - X M_A||_F / sqrt(n) below the stopping tolerance
-    1e-6), the FP64 one from Gauss-Jordan; the preconditioned operator built
-    from either matches the oracle's exact one (FP64 1e-10, mixed 1e-4; the
-    mixed form applies the truncated copy of the FP32 inverse for these 2
-    right-hand sides)."""
-    note(f"mass inverse, precision {prec}")
-    ctx = make_ctx(P, [sphere1], EPS, 2.0, qP=(1, 1, 1), nP=1, chi=0.5, precond="S_INT", precision=prec,
-                   precisionP=prec)
+    1e-6), the FP64 one from Gauss-Jordan (also the FP32 one on request,
+    mass_method = 1); the preconditioned operator built from any of them
+    matches the oracle's exact one (FP64 1e-10, mixed 1e-4; the mixed form
+    applies the truncated copy of the FP32 inverse for these 2 right-hand
+    sides)."""
+    note(f"mass inverse, precision {prec}, method {method}")
+    ctx = P.Context(0)
+    ctx.add_scatterer(*sphere1, EPS)
+    ctx.set_wavenumber(2.0)
+    ctx.assemble(P.assembly_opts((4, 3, 2), 4, -1.0, prec),
+                 P.assembly_opts((1, 1, 1), 1, 0.5, prec, mass_method=method), "S_INT")
     prof = ctx.profile()
     note(f"  Chebyshev steps {prof['mass_iterations']}, residual {prof['mass_residual']:.2e}")
-    if prec == 1:
+    if prec == 1 and method == 0:
         assert prof["mass_iterations"] > 0 and prof["mass_residual"] <= 1e-6
     else:
         assert prof["mass_iterations"] == 0
