@@ -1414,7 +1414,7 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
   static_assert(sizeof(T) == 4, "the Chebyshev inverse serves the FP32 (mixed) preconditioner");
   if (cheb_rows<T>(n) < 1) return false;
   const double tol = 1e-6;
-  const int kmin = 10, kmax = 48, every = 3;
+  const int kmin = 12, kmax = 48, every = 2;
   // CSC of M = CSR of M^T (nonzero entries)
   DBuf Mt = dalloc_c<double>(c, size_t(n) * n);
   launch_transpose(Mrow, Mt.as<double>(), n, c->stream);
