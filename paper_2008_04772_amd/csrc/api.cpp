@@ -1911,8 +1911,9 @@ void op_apply(pmchwt_ctx* c, const double* x, double* y, double* s1, double* s2,
 // copies are asynchronous and several runs can overlap on the device.
 struct PinnedBuf {
   void* p = nullptr;
-  explicit PinnedBuf(size_t bytes) {
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+  void* dev = nullptr;  // the device's address of the same memory
+  explicit PinnedBuf(size_t bytes, unsigned flags = hipHostMallocDefault) {
+    if (hipHostMalloc(&p, bytes, flags) != hipSuccess || hipHostGetDevicePointer(&dev, p, 0) != hipSuccess) {
       (void)hipGetLastError();
       throw Fail{PMCHWT_ERR_OUT_OF_MEMORY, "pinned host allocation failed"};
     }
@@ -1949,12 +1950,16 @@ struct GmresRun {
   double tol;
   int64_t vs, vecd, vstep;
   int n;
-  double *V, *w, *r, *s1, *s2, *s3, *dpar, *dres, *dn;
+  double *V, *w, *r, *s1, *s2, *s3, *dpar, *dn;
   DBuf dact, dscale, dy, dupd, dpart;
   PinnedBuf hpin;
+  // the two result slots, coherent host memory that the step's last kernel
+  // writes directly (no copy launch per step)
+  PinnedBuf hres;
   // per-step results on the host, two slots (step j uses slot j & 1):
   // first-pass projections, second-pass projections, norm of the new vector
   double* h_res[2];
+  double* d_res[2];  // the same slots as the device addresses them
   int32_t* h_act[2];
   double *h_scale, *h_y, *h_beta;
   int32_t* h_upd;
@@ -1979,20 +1984,19 @@ struct GmresRun {
   size_t part_doubles() const { return 4 * (1024 + size_t(rho + 1) * nrhs) + size_t(update_blocks(n)) * nrhs; }
   static size_t res_doubles(int nrhs, int rho) { return 4 * size_t(rho + 1) * nrhs + nrhs; }
   static size_t pinned_bytes(int nrhs, int rho) {
-    return 8 * (2 * res_doubles(nrhs, rho) + 2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs) +
-           4 * 3 * size_t(nrhs) + 64;
+    return 8 * (2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs) + 4 * 3 * size_t(nrhs) + 64;
   }
   cd& Hm(int q, int i, int jj) { return H[(size_t(q) * (rho + 1) + i) * rho + jj]; }
 
   GmresRun(pmchwt_ctx* c_, const double* bt_, double* x_, int nrhs_, double tol_, int rho_, int max_iter_)
       : c(c_), bt(bt_), x(x_), nrhs(nrhs_), rho(rho_), max_iter(max_iter_), tol(tol_),
-        hpin(pinned_bytes(nrhs_, rho_)) {
+        hpin(pinned_bytes(nrhs_, rho_)), hres(2 * 8 * res_doubles(nrhs_, rho_), hipHostMallocCoherent) {
     vs = vlen(c);
     n = int(vs);
     vecd = 2 * vs;
     vstep = int64_t(nrhs) * vs;
     const size_t need =
-        size_t(rho + 1 + 5) * nrhs * vecd + part_doubles() + res_doubles(nrhs, rho) + 16 * size_t(nrhs);
+        size_t(rho + 1 + 5) * nrhs * vecd + part_doubles() + 16 * size_t(nrhs);
     double* W = need_work(c, need);
     V = W;
     w = V + size_t(rho + 1) * nrhs * vecd;
@@ -2001,17 +2005,18 @@ struct GmresRun {
     s2 = s1 + nrhs * vecd;
     s3 = s2 + nrhs * vecd;
     dpar = s3 + nrhs * vecd;                   // step partial sums
-    dres = dpar + part_doubles();              // step results for the host
-    dn = dres + res_doubles(nrhs, rho);        // nrhs doubles, norms outside the cycle
+    dn = dpar + part_doubles();                // nrhs doubles, norms outside the cycle
     dact = dalloc_c<int32_t>(c, nrhs);
     dupd = dalloc_c<int32_t>(c, nrhs);
     dscale = dalloc_c<double>(c, nrhs);
     dy = dalloc_c<double>(c, 2 * size_t(rho + 1) * nrhs);
     dpart = dalloc_c<double>(c, 2 * (size_t(rho + 2) * nrhs + 1024));
     double* hp = static_cast<double*>(hpin.p);
-    h_res[0] = hp;
+    h_res[0] = static_cast<double*>(hres.p);
     h_res[1] = h_res[0] + res_doubles(nrhs, rho);
-    h_scale = h_res[1] + res_doubles(nrhs, rho);
+    d_res[0] = static_cast<double*>(hres.dev);
+    d_res[1] = d_res[0] + res_doubles(nrhs, rho);
+    h_scale = hp;
     h_y = h_scale + nrhs;
     h_beta = h_y + 2 * size_t(rho + 1) * nrhs;
     h_act[0] = reinterpret_cast<int32_t*>(h_beta + nrhs);
@@ -2112,10 +2117,8 @@ struct GmresRun {
       launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, j + 1, -1.0, c->stream, S1);
       dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, c->stream);
       launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, j + 1, -1.0, c->stream, S1, hn);
-      launch_finish_step(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, hn, S2, act, h1, h2, S1, j + 1, dres,
-                         c->stream);
-      const size_t fin = 4 * size_t(j + 1) * nrhs + nrhs;
-      HIPCHK(hipMemcpyAsync(h_res[j & 1], dres, 8 * fin, hipMemcpyDeviceToHost, c->stream));
+      launch_finish_step(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, hn, S2, act, h1, h2, S1, j + 1,
+                         d_res[j & 1], c->stream);
       HIPCHK(hipEventRecord(ev_step[j & 1], c->stream));
     } else if (step == RESID) {  // r = bt - Op x
       launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
