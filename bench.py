@@ -35,11 +35,10 @@ EPS = 3.17 + 0.01j
 FLOP_SHARED, FLOP_PER_K = 22, 78
 PEAK = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector TFLOP/s (FP32 matrix cores: also 157.3)
 HBM_PEAK = 8000.0  # GB/s
-# HBM bytes per launch of the dense operator product on the sphere workload,
+# HBM bytes per launch of the dense operator product, by (workload, kernel),
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy
-# (profiles/gemv_pmchwt3_sphere5120_hbm_counters.md); valid for that kernel
-# version only
-GEMV_TRAFFIC = {"sphere5120": 1417.9e6}
+# (the summaries under profiles/); valid for that kernel version only
+GEMV_TRAFFIC = {}
 
 WORKLOADS = {
     "sphere5120": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, 1 plane wave; "
@@ -307,8 +306,11 @@ def main():
         per = statistics.mean(p["ms_matvec_total"] / max(1, p["matvec_launches"]) for p in profs)
         byt = pr["matvec_bytes"] / max(1, pr["matvec_launches"])
         ach = byt / (per * 1e-3) / 1e9
-        traffic = GEMV_TRAFFIC.get(args.workload) if head == "mixed" else None
-        roof = {"kernel": "k_gemv_pmchwt3", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
+        # one right-hand side on one scatterer of 4096+ edges: the symmetric
+        # tiles (their reduction kernel is timed apart and not counted here)
+        kname = "k_gemv_sym3" if pr["ms_matvec_reduce"] > 0 else "k_gemv_pmchwt3"
+        traffic = GEMV_TRAFFIC.get((args.workload, kname)) if head == "mixed" else None
+        roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": traffic}
     else:
         fl = statistics.mean(p["mfma_flops"] for p in profs)

@@ -107,13 +107,21 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       preconditioner, not the system that is solved.
  *   mass_method : for P with MIXED precision, 0 = the Chebyshev iteration
  *       with the Gauss-Jordan fall-back, 1 = Gauss-Jordan only.  Ignored
- *       otherwise; zero-initialised structs get 0.                           */
+ *       otherwise; zero-initialised structs get 0.
+ *   operator_form : for A of a single scatterer, how products with one or
+ *       two right-hand sides read it.  0 = automatic (symmetric tiles from
+ *       4096 edges on), 1 = full rows, 2 = symmetric tiles: the upper
+ *       128 x 128 tiles of the combined matrices (half the bytes; the
+ *       operators are complex symmetric except where the singular rules
+ *       give X_rc != X_cr, which a sparse correction restores exactly).
+ *       Ignored for P and for several scatterers; 0 when zero-initialised. */
 typedef struct {
   int32_t q_near, q_medium, q_far;
   int32_t n_singular;
   double chi;
   int32_t precision;
   int32_t mass_method;
+  int32_t operator_form;
 } pmchwt_assembly_opts;
 
 /* Restarted GMRES (Section 4: tol 1e-5, restart 200).
@@ -173,6 +181,9 @@ typedef struct {
   int64_t lookahead_discarded; /* Arnoldi steps queued ahead of a convergence and
                                   dropped (their operator products are not counted
                                   in the solve's matvecs)                            */
+  double ms_matvec_reduce;   /* symmetric-tile products: the partial-sum and
+                                correction kernel (ms_matvec_total counts the
+                                tile kernel alone)                               */
 } pmchwt_profile;
 
 /* Version string of the library. */

@@ -190,6 +190,18 @@ struct pmchwt_ctx {
   // four blocks)
   bool comb = false, comb_ok = true;
   DBuf AC, AS1, AS2;
+  // single scatterer, one right-hand side: the same three matrices as upper
+  // tiles plus a sparse correction where singular pairs break the symmetry
+  // (index tables per geometry, values per assembly); the full combined
+  // matrices are then built only when a product with more right-hand sides
+  // asks for them
+  struct {
+    int n = -1, nt = 0;
+    int64_t ntiles = 0, nnz = 0;
+    DBuf tij, rowptr, crow, col;
+    DBuf pack, val, part;
+    bool ready = false;
+  } sym;
   pmchwt_assembly_opts optA{}, optP{};
   // P (near-field BC operators, CSR over union edge indices)
   int precond = -1;
@@ -246,7 +258,21 @@ struct pmchwt_ctx {
   DBuf chunk_e, chunk_ptr, chunk_tri, edge_map, edge_scat_d;
   double recompute = 0.0;
 
+  // event timings of the solver's operator products, read when the solve ends
+  // (or the profile is fetched) instead of waiting on the device per product
+  struct PendTime {
+    hipEvent_t a, b;
+    double* dst;
+  };
+  std::vector<PendTime> ptimes;
+  std::vector<hipEvent_t> evpool;
+
   ~pmchwt_ctx() {
+    for (auto& p : ptimes) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : evpool) (void)hipEventDestroy(e);
     if (blas) rocblas_destroy_handle(blas);
     if (ev_main) (void)hipEventDestroy(ev_main);
     if (ev_side) (void)hipEventDestroy(ev_side);
@@ -265,6 +291,9 @@ int64_t ldmass(int64_t n) { return (n + 31) & ~int64_t(31); }
 
 // right-hand sides from which FP32 operators are applied on the matrix cores
 constexpr int MFMA_MIN_RHS = 16;
+// automatic choice of the symmetric-tile product: from this many edges on
+// (528 tiles of 128 x 128 and up)
+constexpr int64_t SYM_MIN_EDGES = 4096;
 
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -454,6 +483,8 @@ void check_opts(const pmchwt_assembly_opts* o, const char* which) {
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": unknown precision"};
   if (o->mass_method != 0 && o->mass_method != 1)
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_method must be 0 or 1"};
+  if (o->operator_form < 0 || o->operator_form > 2)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": operator_form must be 0, 1 or 2"};
 }
 
 // ---------------------------------------------------------------------------
@@ -541,6 +572,48 @@ AsmParams<M> asm_params(pmchwt_ctx* c) {
   return p;
 }
 
+// Timer whose result is added to *dst later (flush_times): no host wait.
+struct LazyTimer {
+  pmchwt_ctx* c;
+  hipEvent_t a = nullptr;
+  static hipEvent_t take(pmchwt_ctx* c) {
+    if (!c->evpool.empty()) {
+      hipEvent_t e = c->evpool.back();
+      c->evpool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  explicit LazyTimer(pmchwt_ctx* c_) : c(c_) {
+    a = take(c);
+    HIPCHK(hipEventRecord(a, c->stream));
+  }
+  void stop(double* dst) {
+    hipEvent_t b = take(c);
+    c->ptimes.push_back({a, b, dst});
+    a = nullptr;
+    HIPCHK(hipEventRecord(b, c->stream));
+  }
+  ~LazyTimer() {
+    if (a) c->evpool.push_back(a);
+  }
+};
+
+// add the pending timings to their counters (waits for their events)
+void flush_times(pmchwt_ctx* c) {
+  for (auto& p : c->ptimes) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    *p.dst += ms;
+    c->evpool.push_back(p.a);
+    c->evpool.push_back(p.b);
+  }
+  c->ptimes.clear();
+}
+
 struct EvTimer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
@@ -565,6 +638,75 @@ struct EvTimer {
 // ---------------------------------------------------------------------------
 // Assembly of A
 // ---------------------------------------------------------------------------
+// the full combined matrices C, S1, S2 of a single scatterer
+template <typename M>
+void build_comb(pmchwt_ctx* c) {
+  const Scat& s = c->sc[0];
+  const int64_t ne = c->E_tot * c->ldE;
+  realloc_c<M>(c, c->AC, size_t(2 * ne));
+  realloc_c<M>(c, c->AS1, size_t(2 * ne));
+  realloc_c<M>(c, c->AS2, size_t(2 * ne));
+  launch_combine3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), ne, c->k_ext, s.k.real(),
+                     s.k.imag(), c->AC.as<M>(), c->AS1.as<M>(), c->AS2.as<M>(), c->stream);
+  HIPCHK(hipGetLastError());
+  c->comb = true;
+}
+
+// Index tables of the symmetric-tile form (one scatterer, geometry only):
+// the upper tiles in row-major order and the correction pattern, i.e. every
+// entry (r, c) below the diagonal tiles that a pair of triangles sharing a
+// vertex (the Sauter-Schwab pairs) contributes to.
+void sym_tables(pmchwt_ctx* c) {
+  const int n = int(c->E_tot);
+  if (c->sym.n == n) return;
+  const Topo& T = c->sc[0].topo;
+  const int nt = (n + SYM_T - 1) / SYM_T;
+  std::vector<int32_t> tij;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) {
+      tij.push_back(I);
+      tij.push_back(J);
+    }
+  std::vector<std::vector<int32_t>> v2t(T.nv);
+  for (int f = 0; f < T.F; ++f)
+    for (int a = 0; a < 3; ++a) v2t[T.t[3 * f + a]].push_back(f);
+  std::vector<std::vector<int32_t>> rows(n);
+  std::vector<int32_t> nb;
+  for (int f = 0; f < T.F; ++f) {
+    nb.clear();
+    for (int a = 0; a < 3; ++a)
+      for (int g : v2t[T.t[3 * f + a]]) nb.push_back(g);
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    for (int g : nb)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const int r = T.t2e[3 * f + a], cc = T.t2e[3 * g + b];
+          if (r / SYM_T > cc / SYM_T) rows[r].push_back(cc);
+        }
+  }
+  std::vector<int64_t> rowptr(n + 1, 0);
+  std::vector<int32_t> crow, col;
+  for (int r = 0; r < n; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int cc : v) {
+      crow.push_back(r);
+      col.push_back(cc);
+    }
+    rowptr[r + 1] = int64_t(col.size());
+  }
+  c->sym.nt = nt;
+  c->sym.ntiles = int64_t(tij.size() / 2);
+  c->sym.nnz = int64_t(col.size());
+  c->sym.tij = upload(c, tij);
+  c->sym.rowptr = upload(c, rowptr);
+  c->sym.crow = upload(c, crow);
+  c->sym.col = upload(c, col);
+  c->sym.n = n;
+}
+
 template <typename M>
 void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   const int64_t E = c->E_tot;
@@ -823,21 +965,34 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     HIPCHK(hipGetLastError());
     c->prof.ms_assemble_singular = t.stop();
   }
+  c->comb = false;
+  c->sym.ready = false;
+  c->AC = DBuf();
+  c->AS1 = DBuf();
+  c->AS2 = DBuf();
   if (c->sc.size() == 1 && c->comb_ok) {  // three combined matrices for the operator products
-    const Scat& s = c->sc[0];
-    const int64_t ne = E * c->ldE;
-    realloc_c<M>(c, c->AC, size_t(2 * ne));
-    realloc_c<M>(c, c->AS1, size_t(2 * ne));
-    realloc_c<M>(c, c->AS2, size_t(2 * ne));
-    launch_combine3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), ne, c->k_ext, s.k.real(),
-                       s.k.imag(), c->AC.as<M>(), c->AS1.as<M>(), c->AS2.as<M>(), c->stream);
-    HIPCHK(hipGetLastError());
-    c->comb = true;
+    const int form = c->optA.operator_form;
+    if (form == 2 || (form == 0 && E >= SYM_MIN_EDGES)) {
+      const Scat& s = c->sc[0];
+      sym_tables(c);
+      realloc_c<M>(c, c->sym.pack, size_t(c->sym.ntiles) * 3 * SYM_T * SYM_T * 2);
+      realloc_c<M>(c, c->sym.val, size_t(std::max<int64_t>(c->sym.nnz, 1)) * 6);
+      realloc_c<double>(c, c->sym.part, size_t(c->sym.nt) * c->sym.nt * SYM_T * 4);
+      launch_pack_sym3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), c->ldE, int(E),
+                          c->sym.tij.as<int32_t>(), c->sym.ntiles, c->k_ext, s.k.real(), s.k.imag(),
+                          c->sym.pack.as<M>(), c->stream);
+      launch_sym_corr<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), c->ldE,
+                         c->sym.crow.as<int32_t>(), c->sym.col.as<int32_t>(), c->sym.nnz, c->k_ext, s.k.real(),
+                         s.k.imag(), c->sym.val.as<M>(), c->stream);
+      HIPCHK(hipGetLastError());
+      c->sym.ready = true;
+    } else {
+      build_comb<M>(c);
+    }
   } else {
-    c->comb = false;
-    c->AC = DBuf();
-    c->AS1 = DBuf();
-    c->AS2 = DBuf();
+    c->sym.pack = DBuf();
+    c->sym.val = DBuf();
+    c->sym.part = DBuf();
   }
   c->prof.ms_assemble_A = all.stop();
   c->prof.recompute = c->recompute;
@@ -1618,23 +1773,59 @@ float* mfma_ws(pmchwt_ctx* c, int nrhs) {
 // y = A x (y overwritten)
 void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
+  const bool f64 = c->precA == PMCHWT_FP64;
   c->calls_A += 1;
-  if (c->comb && !(c->precA == PMCHWT_MIXED && nrhs >= MFMA_MIN_RHS)) {
-    EvTimer t(c->stream);  // one launch writes every row of y: no clearing pass
-    if (c->precA == PMCHWT_FP64)
+  if (c->sym.ready && nrhs <= 2) {  // symmetric tiles, one right-hand side per pass
+    const int n = int(E), nt = c->sym.nt;
+    for (int q = 0; q < nrhs; ++q) {
+      const double* xq = x + 2 * int64_t(q) * vs;
+      double* yq = y + 2 * int64_t(q) * vs;
+      LazyTimer t(c);
+      if (f64)
+        launch_gemv_sym3<double>(c->sym.pack.as<double>(), c->sym.tij.as<int32_t>(), c->sym.ntiles, nt, n, xq,
+                                 xq + 2 * E, c->sym.part.as<double>(), c->stream);
+      else
+        launch_gemv_sym3<float>(c->sym.pack.as<float>(), c->sym.tij.as<int32_t>(), c->sym.ntiles, nt, n, xq,
+                                xq + 2 * E, c->sym.part.as<double>(), c->stream);
+      t.stop(&c->prof.ms_matvec_total);
+      LazyTimer t2(c);
+      if (f64)
+        launch_sym_reduce<double>(c->sym.part.as<double>(), nt, n, c->sym.rowptr.as<int64_t>(),
+                                  c->sym.col.as<int32_t>(), c->sym.val.as<double>(), xq, xq + 2 * E, yq, yq + 2 * E,
+                                  c->stream);
+      else
+        launch_sym_reduce<float>(c->sym.part.as<double>(), nt, n, c->sym.rowptr.as<int64_t>(),
+                                 c->sym.col.as<int32_t>(), c->sym.val.as<float>(), xq, xq + 2 * E, yq, yq + 2 * E,
+                                 c->stream);
+      t2.stop(&c->prof.ms_matvec_reduce);
+      HIPCHK(hipGetLastError());
+    }
+    c->prof.matvec_launches += nrhs;
+    c->prof.matvec_bytes += nrhs * c->sym.ntiles * 3 * SYM_T * SYM_T * (f64 ? 16 : 8);
+    return;
+  }
+  if (c->sym.ready && !c->comb && !(!f64 && nrhs >= MFMA_MIN_RHS)) {
+    if (f64)
+      build_comb<double>(c);
+    else
+      build_comb<float>(c);
+  }
+  if (c->comb && !(!f64 && nrhs >= MFMA_MIN_RHS)) {
+    LazyTimer t(c);  // one launch writes every row of y: no clearing pass
+    if (f64)
       launch_gemv_pmchwt3<double>(c->AC.as<double>(), c->AS1.as<double>(), c->AS2.as<double>(), c->ldE, int(E), int(E),
                                   x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream, false);
     else
       launch_gemv_pmchwt3<float>(c->AC.as<float>(), c->AS1.as<float>(), c->AS2.as<float>(), c->ldE, int(E), int(E), x,
                                  x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream, false);
     HIPCHK(hipGetLastError());
-    c->prof.ms_matvec_total += t.stop();
+    t.stop(&c->prof.ms_matvec_total);
     c->prof.matvec_launches += 1;
-    c->prof.matvec_bytes += 3 * E * E * (c->precA == PMCHWT_FP64 ? 16 : 8);
+    c->prof.matvec_bytes += 3 * E * E * (f64 ? 16 : 8);
     return;
   }
   launch_zero(y, 2 * vs * nrhs, c->stream);
-  EvTimer t(c->stream);
+  LazyTimer t(c);
   if (c->precA == PMCHWT_FP64) {
     launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
@@ -1648,7 +1839,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   } else if (nrhs >= MFMA_MIN_RHS) {
     float* B1 = mfma_ws(c, nrhs);
     float* B2 = B1 + size_t(4) * nrhs * 2 * size_t(c->ldE);
-    EvTimer tm(c->stream);
+    LazyTimer tm(c);
     launch_mfma_pmchwt(c->Se.as<float>(), c->Ce.as<float>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E, y,
                        y + 2 * E, nrhs, vs, B1, B2, c->stream);
     int64_t flops = 32 * E * c->ldE * nrhs;
@@ -1661,10 +1852,10 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
       flops += 32 * int64_t(s.topo.E) * c->ldI[m] * nrhs;
     }
     HIPCHK(hipGetLastError());
-    c->prof.ms_mfma_total += tm.stop();
+    tm.stop(&c->prof.ms_mfma_total);
     c->prof.mfma_launches += 1 + int64_t(c->sc.size());
     c->prof.mfma_flops += flops;
-    c->prof.ms_matvec_total += t.stop();
+    t.stop(&c->prof.ms_matvec_total);
     return;
   } else {
     launch_gemv_pmchwt<float>(c->Se.as<float>(), c->Ce.as<float>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
@@ -1678,7 +1869,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
     }
   }
   HIPCHK(hipGetLastError());
-  c->prof.ms_matvec_total += t.stop();
+  t.stop(&c->prof.ms_matvec_total);
   c->prof.matvec_launches += 1 + int64_t(c->sc.size());
   int64_t bytes = 2 * E * E;
   for (auto& s : c->sc) bytes += 2 * int64_t(s.topo.E) * s.topo.E;
@@ -2345,6 +2536,7 @@ int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const i
     c->chunk_size = 0;
     c->nf.valid = false;
     c->sing.n = -1;
+    c->sym.n = -1;
     c->cells_valid = false;
     c->gram_valid = false;
     c->slabs.clear();
@@ -2384,6 +2576,7 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
     check_opts(P, "P");
     if (int(kind) < 0 || int(kind) > 6) return fail(c, PMCHWT_ERR_INVALID_ARG, "unknown preconditioner");
     c->have_A = false;
+    flush_times(c);
     c->prof = pmchwt_profile{};
     const double w0 = wall_ms();
     build_duals(c);
@@ -2594,8 +2787,10 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     DBuf b = dalloc_c<double>(c, nd), bt = dalloc_c<double>(c, nd), x = dalloc_c<double>(c, nd),
          s1 = dalloc_c<double>(c, nd), s2 = dalloc_c<double>(c, nd), d = dalloc_c<double>(c, nd),
          r = dalloc_c<double>(c, nd);
+    flush_times(c);
     EvTimer tm(c->stream);
     c->prof.ms_matvec_total = 0;
+    c->prof.ms_matvec_reduce = 0;
     c->prof.matvec_launches = 0;
     c->prof.matvec_bytes = 0;
     c->prof.ms_mfma_total = 0;
@@ -2646,6 +2841,7 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       it_max += mi;
     }
     const double ms = tm.stop();
+    flush_times(c);
     mv_max = c->calls_A * A_matvecs(c) + c->calls_P * P_matvecs(c);
     std::vector<double> h(nd);
     HIPCHK(hipMemcpyAsync(h.data(), x.p, nd * 8, hipMemcpyDeviceToHost, c->stream));
@@ -2782,8 +2978,12 @@ int pmchwt_bc_fields(const double* verts, int32_t nv, const int32_t* tris, int32
 
 int pmchwt_get_profile(const pmchwt_ctx* c, pmchwt_profile* out) {
   if (!c || !out) return PMCHWT_ERR_INVALID_ARG;
-  *out = c->prof;
-  return PMCHWT_OK;
+  pmchwt_ctx* m = const_cast<pmchwt_ctx*>(c);  // pending event timings are part of the profile
+  return guarded(m, [&]() -> int {
+    flush_times(m);
+    *out = c->prof;
+    return PMCHWT_OK;
+  });
 }
 
 const char* pmchwt_last_error(const pmchwt_ctx* c) { return c ? c->err.c_str() : "null context"; }

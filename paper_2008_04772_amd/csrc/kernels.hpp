@@ -185,6 +185,24 @@ void launch_gemv_pmchwt3(const M* C, const M* S1, const M* S2, int64_t ld, int r
 template <typename M>
 void launch_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir, double kii,
                      M* C, M* S1, M* S2, hipStream_t st);
+// Symmetric-tile form of the same three matrices for one right-hand side:
+// upper SYM_T x SYM_T tiles (tij: tile t -> (I, J), I <= J), a CSR correction
+// (crow/col: row and column of each entry, rowptr over rows) holding
+// X_rc - X_cr where singular pairs make the matrices unsymmetric, and
+// nt x nt x SYM_T x 4 doubles of partial sums (nt = ceil(n / SYM_T)).
+constexpr int SYM_T = 128;
+template <typename M>
+void launch_pack_sym3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t ld, int n, const int32_t* tij,
+                      int64_t ntiles, double ke, double kir, double kii, M* P, hipStream_t st);
+template <typename M>
+void launch_sym_corr(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t ld, const int32_t* crow,
+                     const int32_t* col, int64_t nnz, double ke, double kir, double kii, M* val, hipStream_t st);
+template <typename M>
+void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, int n, const double* xD,
+                      const double* xN, double* part, hipStream_t st);
+template <typename M>
+void launch_sym_reduce(const double* part, int nt, int n, const int64_t* rowptr, const int32_t* col, const M* val,
+                       const double* xD, const double* xN, double* yD, double* yN, hipStream_t st);
 // Many right-hand sides on the FP32 matrix cores: same product as
 // launch_gemv_pmchwt for FP32 operators with ld a multiple of 16; B1, B2 are
 // workspaces of 4 nrhs x 2 ld floats each.

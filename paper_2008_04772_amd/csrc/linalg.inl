@@ -374,20 +374,34 @@ template void launch_gemv_pmchwt3<double>(const double*, const double*, const do
                                           const double*, const double*, double*, double*, int, int64_t, hipStream_t,
                                           bool);
 
-// C = Ce + Ci, S1 = Se/ke + Si/ki, S2 = -(ke Se + ki Si), per complex entry
+// C = Ce + Ci, S1 = Se/ke + Si/ki, S2 = -(ke Se + ki Si) of complex entry q
+// (out: C, S1, S2 as re/im pairs, rounded to the storage type)
+template <typename M>
+__device__ __forceinline__ void combine_entry(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t q,
+                                              double ke, double kir, double kii, M out[6]) {
+  const double ser = Se[2 * q], sei = Se[2 * q + 1], sir = Si[2 * q], sii = Si[2 * q + 1];
+  out[0] = M(double(Ce[2 * q]) + double(Ci[2 * q]));
+  out[1] = M(double(Ce[2 * q + 1]) + double(Ci[2 * q + 1]));
+  const double k2 = kir * kir + kii * kii, ir = kir / k2, ii = -kii / k2;  // 1/ki
+  out[2] = M(ser / ke + (sir * ir - sii * ii));
+  out[3] = M(sei / ke + (sir * ii + sii * ir));
+  out[4] = M(-(ke * ser + (kir * sir - kii * sii)));
+  out[5] = M(-(ke * sei + (kir * sii + kii * sir)));
+}
+
 template <typename M>
 __global__ void k_combine3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t n, double ke, double kir,
                            double kii, M* C, M* S1, M* S2) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= n) return;
-  const double ser = Se[2 * q], sei = Se[2 * q + 1], sir = Si[2 * q], sii = Si[2 * q + 1];
-  C[2 * q] = M(double(Ce[2 * q]) + double(Ci[2 * q]));
-  C[2 * q + 1] = M(double(Ce[2 * q + 1]) + double(Ci[2 * q + 1]));
-  const double k2 = kir * kir + kii * kii, ir = kir / k2, ii = -kii / k2;  // 1/ki
-  S1[2 * q] = M(ser / ke + (sir * ir - sii * ii));
-  S1[2 * q + 1] = M(sei / ke + (sir * ii + sii * ir));
-  S2[2 * q] = M(-(ke * ser + (kir * sir - kii * sii)));
-  S2[2 * q + 1] = M(-(ke * sei + (kir * sii + kii * sir)));
+  M o[6];
+  combine_entry(Se, Ce, Si, Ci, q, ke, kir, kii, o);
+  C[2 * q] = o[0];
+  C[2 * q + 1] = o[1];
+  S1[2 * q] = o[2];
+  S1[2 * q + 1] = o[3];
+  S2[2 * q] = o[4];
+  S2[2 * q + 1] = o[5];
 }
 
 template <typename M>
@@ -400,6 +414,257 @@ template void launch_combine3<float>(const float*, const float*, const float*, c
                                      double, float*, float*, float*, hipStream_t);
 template void launch_combine3<double>(const double*, const double*, const double*, const double*, int64_t, double,
                                       double, double, double*, double*, double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Symmetric-tile product for one right-hand side.
+//
+// C, S1 and S2 are complex symmetric up to the quadrature of the singular
+// pairs: S and C are symmetric bilinear forms on one space (test = trial,
+// Section 3.1), every regular pair is integrated with the same rule from
+// either side, and only the Sauter-Schwab rules of pairs sharing a vertex
+// give X_rc != X_cr.  The operator is stored as its upper SYM_T x SYM_T tiles
+// (I <= J; diagonal tiles whole), so one product reads half the bytes: tile
+// (I, J) gives row sums for block row I and, transposed, column sums for block
+// row J.  Entries below the diagonal tiles that singular pairs touch get the
+// exact difference X_rc - X_cr from a CSR correction, so the product equals
+// the one with the full matrices up to rounding.
+//
+// Tile t = (I, J) holds three T x T row-major complex blocks (C, S1, S2);
+// entries outside the n x n operator are zero.  Partial sums: slot (K, s) of
+// T rows x 4 doubles (yD re/im, yN re/im) is written by exactly one tile
+// (row sums of (K, s) for K <= s, column sums of (s, K) for K > s) and added
+// in slot order by k_sym_reduce.
+// ---------------------------------------------------------------------------
+template <typename M, int T>
+__global__ void k_pack_sym3(const M* __restrict__ Se, const M* __restrict__ Ce, const M* __restrict__ Si,
+                            const M* __restrict__ Ci, int64_t ld, int n, const int32_t* __restrict__ tij,
+                            double ke, double kir, double kii, M* __restrict__ P) {
+  constexpr int64_t MAT = int64_t(T) * T * 2;
+  const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;  // T*T is a multiple of 256: no tail
+  const int64_t t = q / (int64_t(T) * T);
+  const int w = int(q - t * T * T), r = w / T, cc = w - r * T;
+  const int R = tij[2 * t] * T + r, Cc = tij[2 * t + 1] * T + cc;
+  M o[6] = {M(0), M(0), M(0), M(0), M(0), M(0)};
+  if (R < n && Cc < n) combine_entry(Se, Ce, Si, Ci, int64_t(R) * ld + Cc, ke, kir, kii, o);
+  M* b = P + t * 3 * MAT + 2 * w;
+  b[0] = o[0];
+  b[1] = o[1];
+  b[MAT] = o[2];
+  b[MAT + 1] = o[3];
+  b[2 * MAT] = o[4];
+  b[2 * MAT + 1] = o[5];
+}
+
+// correction entry k at (R, Cc), tile(R) > tile(Cc): X_RCc - X_CcR for the
+// three combined matrices, both taken as stored (rounded to M)
+template <typename M>
+__global__ void k_sym_corr(const M* __restrict__ Se, const M* __restrict__ Ce, const M* __restrict__ Si,
+                           const M* __restrict__ Ci, int64_t ld, const int32_t* __restrict__ crow,
+                           const int32_t* __restrict__ col, int64_t nnz, double ke, double kir, double kii,
+                           M* __restrict__ val) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int R = crow[k], Cc = col[k];
+  M a[6], b[6];
+  combine_entry(Se, Ce, Si, Ci, int64_t(R) * ld + Cc, ke, kir, kii, a);
+  combine_entry(Se, Ce, Si, Ci, int64_t(Cc) * ld + R, ke, kir, kii, b);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) val[6 * k + q] = M(double(a[q]) - double(b[q]));
+}
+
+// One workgroup per tile.  Wavefront w takes rows [w T/4, (w+1) T/4) four at a
+// time: the 16 lanes of row group g = lane/16 read one row, lane cl holding
+// columns 2(cl + 16k) + {0, 1}, k < T/32, of all three blocks (contiguous
+// 16-lane segments per load).  Row sums: FP64 per lane, then over the 16
+// lanes.  Column sums: per lane over its rows, then over the four row groups
+// (shuffles) and the four wavefronts (LDS), in that fixed order.
+template <typename M, int T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemv_sym3(const M* __restrict__ P, const int32_t* __restrict__ tij, int nt,
+                                                   int n, const double* __restrict__ xD,
+                                                   const double* __restrict__ xN, double* __restrict__ part) {
+  typedef typename CPair<M>::T V;  // two complex entries
+  constexpr int NU = T / 32;       // vector loads per lane, row and block
+  constexpr int RW = T / 4;        // rows per wavefront
+  constexpr int64_t MATV = int64_t(T) * T / 2;
+  const int t = blockIdx.x;
+  const int I = tij[2 * t], J = tij[2 * t + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+  __shared__ double xr[T][4];  // x of the tile's rows (block row I)
+  __shared__ double xk[T][4];  // x of the tile's columns (block row J)
+  __shared__ double cred[4][T][4];
+  for (int i = threadIdx.x; i < 2 * T; i += 256) {
+    const int R = (i < T ? I * T + i : J * T + i - T);
+    const bool in = R < n;
+    double* d = i < T ? xr[i] : xk[i - T];
+    d[0] = in ? xD[2 * int64_t(R)] : 0.0;
+    d[1] = in ? xD[2 * int64_t(R) + 1] : 0.0;
+    d[2] = in ? xN[2 * int64_t(R)] : 0.0;
+    d[3] = in ? xN[2 * int64_t(R) + 1] : 0.0;
+  }
+  double ca[NU][2][4];
+#pragma unroll
+  for (int k = 0; k < NU; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) ca[k][u][0] = ca[k][u][1] = ca[k][u][2] = ca[k][u][3] = 0.0;
+  const V* base = reinterpret_cast<const V*>(P) + int64_t(t) * 3 * MATV;
+  __syncthreads();
+  for (int s = 0; s < RW / 4; ++s) {
+    // column x values are re-read from LDS every step rather than held in 64
+    // registers across the loop (two wavefronts per SIMD instead of one)
+    asm volatile("" ::: "memory");
+    const int r = wv * RW + 4 * s + g;
+    const V* rc = base + int64_t(r) * (T / 2) + cl;
+    V cv[NU], av[NU], bv[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      cv[k] = __builtin_nontemporal_load(rc + 16 * k);
+      av[k] = __builtin_nontemporal_load(rc + MATV + 16 * k);
+      bv[k] = __builtin_nontemporal_load(rc + 2 * MATV + 16 * k);
+    }
+    const double dr = xr[r][0], di = xr[r][1], nr = xr[r][2], ni = xr[r][3];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double cr = double(cv[k][2 * u]), ci = double(cv[k][2 * u + 1]);
+        const double sr = double(av[k][2 * u]), si = double(av[k][2 * u + 1]);
+        const double tr = double(bv[k][2 * u]), ti = double(bv[k][2 * u + 1]);
+        const double* xq = xk[2 * (cl + 16 * k) + u];
+        const double xdr = xq[0], xdi = xq[1], xnr = xq[2], xni = xq[3];
+        a0 += cr * xdr - ci * xdi + sr * xnr - si * xni;
+        a1 += cr * xdi + ci * xdr + sr * xni + si * xnr;
+        a2 += cr * xnr - ci * xni + tr * xdr - ti * xdi;
+        a3 += cr * xni + ci * xnr + tr * xdi + ti * xdr;
+        ca[k][u][0] += cr * dr - ci * di + sr * nr - si * ni;
+        ca[k][u][1] += cr * di + ci * dr + sr * ni + si * nr;
+        ca[k][u][2] += cr * nr - ci * ni + tr * dr - ti * di;
+        ca[k][u][3] += cr * ni + ci * nr + tr * di + ti * dr;
+      }
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {
+      a0 += __shfl_xor(a0, o, WAVE);
+      a1 += __shfl_xor(a1, o, WAVE);
+      a2 += __shfl_xor(a2, o, WAVE);
+      a3 += __shfl_xor(a3, o, WAVE);
+    }
+    if (cl == 0) {
+      double* p = part + ((int64_t(I) * nt + J) * T + r) * 4;
+      p[0] = a0;
+      p[1] = a1;
+      p[2] = a2;
+      p[3] = a3;
+    }
+  }
+  if (I == J) return;  // uniform per workgroup; the diagonal tile is whole and gives row sums only
+#pragma unroll
+  for (int k = 0; k < NU; ++k)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = ca[k][u][q];
+        v += __shfl_xor(v, 16, WAVE);
+        v += __shfl_xor(v, 32, WAVE);
+        if (g == 0) cred[wv][2 * (cl + 16 * k) + u][q] = v;
+      }
+  __syncthreads();
+  double* p = part + (int64_t(J) * nt + I) * T * 4;
+  for (int i = threadIdx.x; i < T * 4; i += 256) {
+    const int c = i >> 2, q = i & 3;
+    p[i] = ((cred[0][c][q] + cred[1][c][q]) + cred[2][c][q]) + cred[3][c][q];
+  }
+}
+
+// y = sum of the partial slots of each row, slot order, plus the correction
+// row; four threads per row split the slots and the correction entries.
+template <typename M, int T>
+__global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ part, int nt, int n,
+                                                    const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col, const M* __restrict__ val,
+                                                    const double* __restrict__ xD, const double* __restrict__ xN,
+                                                    double* __restrict__ yD, double* __restrict__ yN) {
+  const int rr = threadIdx.x & 63, qq = threadIdx.x >> 6;
+  const int R = blockIdx.x * 64 + rr;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (R < n) {
+    const int K = R / T, r = R - K * T;
+    for (int s = qq; s < nt; s += 4) {
+      const d4v v = *reinterpret_cast<const d4v*>(part + ((int64_t(K) * nt + s) * T + r) * 4);
+      a0 += v[0];
+      a1 += v[1];
+      a2 += v[2];
+      a3 += v[3];
+    }
+    for (int64_t k = rowptr[R] + qq; k < rowptr[R + 1]; k += 4) {
+      const int64_t c = col[k];
+      const double dr = xD[2 * c], di = xD[2 * c + 1], nr = xN[2 * c], ni = xN[2 * c + 1];
+      const M* v = val + 6 * k;
+      const double cr = v[0], ci = v[1], sr = v[2], si = v[3], tr = v[4], ti = v[5];
+      a0 += cr * dr - ci * di + sr * nr - si * ni;
+      a1 += cr * di + ci * dr + sr * ni + si * nr;
+      a2 += cr * nr - ci * ni + tr * dr - ti * di;
+      a3 += cr * ni + ci * nr + tr * di + ti * dr;
+    }
+  }
+  __shared__ double red[4][64][4];
+  red[qq][rr][0] = a0;
+  red[qq][rr][1] = a1;
+  red[qq][rr][2] = a2;
+  red[qq][rr][3] = a3;
+  __syncthreads();
+  if (qq == 0 && R < n) {
+    double o[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = ((red[0][rr][q] + red[1][rr][q]) + red[2][rr][q]) + red[3][rr][q];
+    yD[2 * int64_t(R)] = o[0];
+    yD[2 * int64_t(R) + 1] = o[1];
+    yN[2 * int64_t(R)] = o[2];
+    yN[2 * int64_t(R) + 1] = o[3];
+  }
+}
+
+template <typename M>
+void launch_pack_sym3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t ld, int n, const int32_t* tij,
+                      int64_t ntiles, double ke, double kir, double kii, M* P, hipStream_t st) {
+  const int64_t blocks = ntiles * SYM_T * SYM_T / 256;
+  hipLaunchKernelGGL((k_pack_sym3<M, SYM_T>), dim3(unsigned(blocks)), dim3(256), 0, st, Se, Ce, Si, Ci, ld, n, tij,
+                     ke, kir, kii, P);
+}
+
+template <typename M>
+void launch_sym_corr(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t ld, const int32_t* crow,
+                     const int32_t* col, int64_t nnz, double ke, double kir, double kii, M* val, hipStream_t st) {
+  if (nnz == 0) return;
+  hipLaunchKernelGGL((k_sym_corr<M>), dim3(unsigned((nnz + 255) / 256)), dim3(256), 0, st, Se, Ce, Si, Ci, ld, crow,
+                     col, nnz, ke, kir, kii, val);
+}
+
+template <typename M>
+void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, int n, const double* xD,
+                      const double* xN, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij, nt, n, xD, xN, part);
+}
+
+template <typename M>
+void launch_sym_reduce(const double* part, int nt, int n, const int64_t* rowptr, const int32_t* col, const M* val,
+                       const double* xD, const double* xN, double* yD, double* yN, hipStream_t st) {
+  hipLaunchKernelGGL((k_sym_reduce<M, SYM_T>), dim3(unsigned((n + 63) / 64)), dim3(256), 0, st, part, nt, n, rowptr,
+                     col, val, xD, xN, yD, yN);
+}
+
+#define PMCHWT_SYM_INST(M)                                                                                          \
+  template void launch_pack_sym3<M>(const M*, const M*, const M*, const M*, int64_t, int, const int32_t*, int64_t, \
+                                    double, double, double, M*, hipStream_t);                                      \
+  template void launch_sym_corr<M>(const M*, const M*, const M*, const M*, int64_t, const int32_t*, const int32_t*, \
+                                   int64_t, double, double, double, M*, hipStream_t);                              \
+  template void launch_gemv_sym3<M>(const M*, const int32_t*, int64_t, int, int, const double*, const double*,      \
+                                    double*, hipStream_t);                                                          \
+  template void launch_sym_reduce<M>(const double*, int, int, const int64_t*, const int32_t*, const M*,            \
+                                     const double*, const double*, double*, double*, hipStream_t);
+PMCHWT_SYM_INST(float)
+PMCHWT_SYM_INST(double)
+#undef PMCHWT_SYM_INST
 
 template <typename M>
 void launch_gemv_pmchwt(const M* S, const M* C, int64_t ld, int rows, int cols, double kr, double ki,

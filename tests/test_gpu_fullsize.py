@@ -123,6 +123,32 @@ def test_fullsize_P_entries(P, mesh, topo, precision, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("precision,bar", [(0, 1e-13), (1, 1e-5)])
+def test_fullsize_symmetric_product(P, mesh, precision, bar):
+    """The benchmark's product (upper 128 x 128 tiles plus the singular-pair
+    correction, chosen automatically at 7680 edges) against the full-row
+    product of the same assembly, one and two right-hand sides.  Bars as for
+    the small meshes: FP64 1e-13, mixed 1e-5 (X_cr for X_rc, each rounded to
+    FP32); the full-row form itself is tied to the oracle entry by entry
+    above."""
+    v, t, chi = mesh
+    res = []
+    for form in (0, 1):
+        ctx = P.Context(0)
+        ctx.add_scatterer(v, t, EPS)
+        ctx.set_wavenumber(K)
+        ctx.assemble(P.assembly_opts((4, 3, 2), 4, -1.0, precision, operator_form=form),
+                     P.assembly_opts((1, 1, 1), 1, chi, precision), "S_INT")
+        rng = np.random.default_rng(5)
+        n = 2 * ctx.num_edges(0)
+        x = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
+        res.append((ctx.apply(0, x[:1]), ctx.apply(0, x)))
+    for q in range(2):
+        e = float(np.linalg.norm(res[0][q] - res[1][q]) / np.linalg.norm(res[1][q]))
+        note(f"  precision {precision}, {q + 1} RHS: symmetric tiles vs full rows {e:.2e}")
+        assert e < bar
+
+
 def test_fullsize_solve_mixed_vs_fp64_and_mie(P, mesh):
     note("full-size solves: mixed vs FP64, against Mie (x = 5)")
     d, p = synth.single_wave()
