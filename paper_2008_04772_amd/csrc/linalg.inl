@@ -472,23 +472,52 @@ __global__ void k_sym_corr(const M* __restrict__ Se, const M* __restrict__ Ce, c
   for (int q = 0; q < 6; ++q) val[6 * k + q] = M(double(a[q]) - double(b[q]));
 }
 
-// One workgroup per tile.  Wavefront w takes rows [w T/4, (w+1) T/4) four at a
-// time: the 16 lanes of row group g = lane/16 read one row, lane cl holding
-// columns 2(cl + 16k) + {0, 1}, k < T/32, of all three blocks (contiguous
-// 16-lane segments per load).  Row sums: FP64 per lane, then over the 16
-// lanes.  Column sums: per lane over its rows, then over the four row groups
+// lane v of a 16-lane row moved by a DPP pattern (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(uint32_t(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(uint32_t(uint64_t(b) >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+// sum over aligned groups of L lanes, every lane of a group gets it; L = 16
+// by DPP within the rows of 16 lanes (swap neighbours, swap pairs, mirror
+// halves of 8, mirror the row), wider groups by shuffles
+template <int L>
+__device__ __forceinline__ double row_sum(double v) {
+  if constexpr (L == 16) {
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+  } else {
+#pragma unroll
+    for (int o = L / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  }
+  return v;
+}
+
+// One workgroup per tile.  Wavefront w takes rows [w T/4, (w+1) T/4), G RPS
+// at a time (G = 64 / LPR row groups of LPR lanes): row group g = lane / LPR
+// reads rows g, g + G, ..., lane cl = lane % LPR holding columns
+// 2(cl + LPR k) + {0, 1}, k < T / (2 LPR), of all three blocks (contiguous
+// LPR-lane segments per load).  Row sums: FP64 per lane, then over the LPR
+// lanes.  Column sums: per lane over its rows, then over the G row groups
 // (shuffles) and the four wavefronts (LDS), in that fixed order.
-template <typename M, int T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemv_sym3(const M* __restrict__ P, const int32_t* __restrict__ tij, int nt,
+template <typename M, int T, int LPR, int RPS, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemv_sym3(const M* __restrict__ P, const int32_t* __restrict__ tij, int nt,
                                                    int n, const double* __restrict__ xD,
                                                    const double* __restrict__ xN, double* __restrict__ part) {
   typedef typename CPair<M>::T V;  // two complex entries
-  constexpr int NU = T / 32;       // vector loads per lane, row and block
+  constexpr int G = 64 / LPR;      // row groups per wavefront
+  constexpr int NU = T / (2 * LPR);  // vector loads per lane, row and block
   constexpr int RW = T / 4;        // rows per wavefront
   constexpr int64_t MATV = int64_t(T) * T / 2;
+  static_assert(NU >= 1 && RW % (G * RPS) == 0, "tile, lanes per row and rows per step do not fit");
   const int t = blockIdx.x;
   const int I = tij[2 * t], J = tij[2 * t + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane / LPR, cl = lane % LPR;
   __shared__ double xr[T][4];  // x of the tile's rows (block row I)
   __shared__ double xk[T][4];  // x of the tile's columns (block row J)
   __shared__ double cred[4][T][4];
@@ -508,52 +537,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int u = 0; u < 2; ++u) ca[k][u][0] = ca[k][u][1] = ca[k][u][2] = ca[k][u][3] = 0.0;
   const V* base = reinterpret_cast<const V*>(P) + int64_t(t) * 3 * MATV;
   __syncthreads();
-  for (int s = 0; s < RW / 4; ++s) {
-    // column x values are re-read from LDS every step rather than held in 64
-    // registers across the loop (two wavefronts per SIMD instead of one)
+  for (int s = 0; s < RW / (G * RPS); ++s) {
+    // column x values are re-read from LDS every step rather than held in
+    // registers across the loop
     asm volatile("" ::: "memory");
-    const int r = wv * RW + 4 * s + g;
-    const V* rc = base + int64_t(r) * (T / 2) + cl;
-    V cv[NU], av[NU], bv[NU];
+    const int r0 = wv * RW + G * RPS * s + g;
+    V cv[RPS][NU], av[RPS][NU], bv[RPS][NU];
 #pragma unroll
-    for (int k = 0; k < NU; ++k) {
-      cv[k] = __builtin_nontemporal_load(rc + 16 * k);
-      av[k] = __builtin_nontemporal_load(rc + MATV + 16 * k);
-      bv[k] = __builtin_nontemporal_load(rc + 2 * MATV + 16 * k);
-    }
-    const double dr = xr[r][0], di = xr[r][1], nr = xr[r][2], ni = xr[r][3];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int j = 0; j < RPS; ++j) {
+      const V* rc = base + int64_t(r0 + G * j) * (T / 2) + cl;
 #pragma unroll
-    for (int k = 0; k < NU; ++k)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const double cr = double(cv[k][2 * u]), ci = double(cv[k][2 * u + 1]);
-        const double sr = double(av[k][2 * u]), si = double(av[k][2 * u + 1]);
-        const double tr = double(bv[k][2 * u]), ti = double(bv[k][2 * u + 1]);
-        const double* xq = xk[2 * (cl + 16 * k) + u];
-        const double xdr = xq[0], xdi = xq[1], xnr = xq[2], xni = xq[3];
-        a0 += cr * xdr - ci * xdi + sr * xnr - si * xni;
-        a1 += cr * xdi + ci * xdr + sr * xni + si * xnr;
-        a2 += cr * xnr - ci * xni + tr * xdr - ti * xdi;
-        a3 += cr * xni + ci * xnr + tr * xdi + ti * xdr;
-        ca[k][u][0] += cr * dr - ci * di + sr * nr - si * ni;
-        ca[k][u][1] += cr * di + ci * dr + sr * ni + si * nr;
-        ca[k][u][2] += cr * nr - ci * ni + tr * dr - ti * di;
-        ca[k][u][3] += cr * ni + ci * nr + tr * di + ti * dr;
+      for (int k = 0; k < NU; ++k) {
+        cv[j][k] = __builtin_nontemporal_load(rc + LPR * k);
+        av[j][k] = __builtin_nontemporal_load(rc + MATV + LPR * k);
+        bv[j][k] = __builtin_nontemporal_load(rc + 2 * MATV + LPR * k);
       }
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
-      a0 += __shfl_xor(a0, o, WAVE);
-      a1 += __shfl_xor(a1, o, WAVE);
-      a2 += __shfl_xor(a2, o, WAVE);
-      a3 += __shfl_xor(a3, o, WAVE);
     }
-    if (cl == 0) {
-      double* p = part + ((int64_t(I) * nt + J) * T + r) * 4;
-      p[0] = a0;
-      p[1] = a1;
-      p[2] = a2;
-      p[3] = a3;
+    double a[RPS][4];
+#pragma unroll
+    for (int j = 0; j < RPS; ++j) {
+      const int r = r0 + G * j;
+      const double dr = xr[r][0], di = xr[r][1], nr = xr[r][2], ni = xr[r][3];
+      a[j][0] = a[j][1] = a[j][2] = a[j][3] = 0.0;
+#pragma unroll
+      for (int k = 0; k < NU; ++k)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double cr = double(cv[j][k][2 * u]), ci = double(cv[j][k][2 * u + 1]);
+          const double sr = double(av[j][k][2 * u]), si = double(av[j][k][2 * u + 1]);
+          const double tr = double(bv[j][k][2 * u]), ti = double(bv[j][k][2 * u + 1]);
+          const double* xq = xk[2 * (cl + LPR * k) + u];
+          const double xdr = xq[0], xdi = xq[1], xnr = xq[2], xni = xq[3];
+          // chains of fused multiply-adds (four per accumulator and entry)
+          a[j][0] = fma(-si, xni, fma(sr, xnr, fma(-ci, xdi, fma(cr, xdr, a[j][0]))));
+          a[j][1] = fma(si, xnr, fma(sr, xni, fma(ci, xdr, fma(cr, xdi, a[j][1]))));
+          a[j][2] = fma(-ti, xdi, fma(tr, xdr, fma(-ci, xni, fma(cr, xnr, a[j][2]))));
+          a[j][3] = fma(ti, xdr, fma(tr, xdi, fma(ci, xnr, fma(cr, xni, a[j][3]))));
+          ca[k][u][0] = fma(-si, ni, fma(sr, nr, fma(-ci, di, fma(cr, dr, ca[k][u][0]))));
+          ca[k][u][1] = fma(si, nr, fma(sr, ni, fma(ci, dr, fma(cr, di, ca[k][u][1]))));
+          ca[k][u][2] = fma(-ti, di, fma(tr, dr, fma(-ci, ni, fma(cr, nr, ca[k][u][2]))));
+          ca[k][u][3] = fma(ti, dr, fma(tr, di, fma(ci, nr, fma(cr, ni, ca[k][u][3]))));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RPS; ++j) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[j][q] = row_sum<LPR>(a[j][q]);
+      if (cl == 0) {
+        double* p = part + ((int64_t(I) * nt + J) * T + r0 + G * j) * 4;
+        p[0] = a[j][0];
+        p[1] = a[j][1];
+        p[2] = a[j][2];
+        p[3] = a[j][3];
+      }
     }
   }
   if (I == J) return;  // uniform per workgroup; the diagonal tile is whole and gives row sums only
@@ -564,9 +600,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         double v = ca[k][u][q];
-        v += __shfl_xor(v, 16, WAVE);
-        v += __shfl_xor(v, 32, WAVE);
-        if (g == 0) cred[wv][2 * (cl + 16 * k) + u][q] = v;
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, WAVE);
+        if (g == 0) cred[wv][2 * (cl + LPR * k) + u][q] = v;
       }
   __syncthreads();
   double* p = part + (int64_t(J) * nt + I) * T * 4;
@@ -643,7 +679,8 @@ void launch_sym_corr(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t
 template <typename M>
 void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, int n, const double* xD,
                       const double* xN, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij, nt, n, xD, xN, part);
+  hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T, 16, 1>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij, nt, n, xD, xN,
+                     part);
 }
 
 template <typename M>
