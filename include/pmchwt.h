@@ -169,9 +169,12 @@ typedef struct {
   double wall_A;             /* ... assembly of A (host tables + kernels)               */
   double wall_P;             /* ... preconditioner (near-field pattern + kernel)        */
   double wall_mass;          /* ... mass / Gram matrices and the mass inverse           */
-  double ms_matvec_total;    /* dense operator application kernels during the solve     */
+  double ms_matvec_total;    /* dense operator application kernels during the solve,
+                                summed over the timed launches (matvec_timed: one
+                                product in eight is timed, and every matrix-core
+                                product)                                          */
   int64_t matvec_launches;
-  int64_t matvec_bytes;      /* algorithmic operator bytes read by those launches       */
+  int64_t matvec_bytes;      /* algorithmic operator bytes read by all those launches  */
   double ms_mfma_total;      /* many-RHS operator products on the matrix cores          */
   int64_t mfma_launches;
   int64_t mfma_flops;        /* real flops of those GEMMs (8 per complex MAC)           */
@@ -182,8 +185,9 @@ typedef struct {
                                   dropped (their operator products are not counted
                                   in the solve's matvecs)                            */
   double ms_matvec_reduce;   /* symmetric-tile products: the partial-sum and
-                                correction kernel (ms_matvec_total counts the
-                                tile kernel alone)                               */
+                                correction kernel of the timed launches
+                                (ms_matvec_total counts the tile kernel alone)    */
+  int64_t matvec_timed;      /* GEMV launches whose time is in ms_matvec_total       */
 } pmchwt_profile;
 
 /* Version string of the library. */

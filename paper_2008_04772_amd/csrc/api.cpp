@@ -11,6 +11,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <array>
 #include <cmath>
@@ -266,6 +267,7 @@ struct pmchwt_ctx {
   };
   std::vector<PendTime> ptimes;
   std::vector<hipEvent_t> evpool;
+  int64_t matvec_seq = 0;  // dense products so far (which of them are timed)
 
   ~pmchwt_ctx() {
     for (auto& p : ptimes) {
@@ -586,11 +588,13 @@ struct LazyTimer {
     HIPCHK(hipEventCreate(&e));
     return e;
   }
-  explicit LazyTimer(pmchwt_ctx* c_) : c(c_) {
+  explicit LazyTimer(pmchwt_ctx* c_, bool on = true) : c(c_) {
+    if (!on) return;
     a = take(c);
     HIPCHK(hipEventRecord(a, c->stream));
   }
   void stop(double* dst) {
+    if (!a) return;
     hipEvent_t b = take(c);
     c->ptimes.push_back({a, b, dst});
     a = nullptr;
@@ -600,6 +604,11 @@ struct LazyTimer {
     if (a) c->evpool.push_back(a);
   }
 };
+
+// Dense products timed: one in MATVEC_SAMPLE (a pair of timing events
+// between two kernels costs a few microseconds of idle device time)
+constexpr int MATVEC_SAMPLE = 8;
+bool sample_matvec(pmchwt_ctx* c) { return c->matvec_seq++ % MATVEC_SAMPLE == 0; }
 
 // add the pending timings to their counters (waits for their events)
 void flush_times(pmchwt_ctx* c) {
@@ -1775,12 +1784,13 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
   const bool f64 = c->precA == PMCHWT_FP64;
   c->calls_A += 1;
+  const bool timed = sample_matvec(c) || (!f64 && nrhs >= MFMA_MIN_RHS);
   if (c->sym.ready && nrhs <= 2) {  // symmetric tiles, one right-hand side per pass
     const int n = int(E), nt = c->sym.nt;
     for (int q = 0; q < nrhs; ++q) {
       const double* xq = x + 2 * int64_t(q) * vs;
       double* yq = y + 2 * int64_t(q) * vs;
-      LazyTimer t(c);
+      LazyTimer t(c, timed);
       if (f64)
         launch_gemv_sym3<double>(c->sym.pack.as<double>(), c->sym.tij.as<int32_t>(), c->sym.ntiles, nt, n, xq,
                                  xq + 2 * E, c->sym.part.as<double>(), c->stream);
@@ -1788,7 +1798,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
         launch_gemv_sym3<float>(c->sym.pack.as<float>(), c->sym.tij.as<int32_t>(), c->sym.ntiles, nt, n, xq,
                                 xq + 2 * E, c->sym.part.as<double>(), c->stream);
       t.stop(&c->prof.ms_matvec_total);
-      LazyTimer t2(c);
+      LazyTimer t2(c, timed);
       if (f64)
         launch_sym_reduce<double>(c->sym.part.as<double>(), nt, n, c->sym.rowptr.as<int64_t>(),
                                   c->sym.col.as<int32_t>(), c->sym.val.as<double>(), xq, xq + 2 * E, yq, yq + 2 * E,
@@ -1801,6 +1811,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
       HIPCHK(hipGetLastError());
     }
     c->prof.matvec_launches += nrhs;
+    c->prof.matvec_timed += timed ? nrhs : 0;
     c->prof.matvec_bytes += nrhs * c->sym.ntiles * 3 * SYM_T * SYM_T * (f64 ? 16 : 8);
     return;
   }
@@ -1811,7 +1822,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
       build_comb<float>(c);
   }
   if (c->comb && !(!f64 && nrhs >= MFMA_MIN_RHS)) {
-    LazyTimer t(c);  // one launch writes every row of y: no clearing pass
+    LazyTimer t(c, timed);  // one launch writes every row of y: no clearing pass
     if (f64)
       launch_gemv_pmchwt3<double>(c->AC.as<double>(), c->AS1.as<double>(), c->AS2.as<double>(), c->ldE, int(E), int(E),
                                   x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream, false);
@@ -1821,11 +1832,12 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
     HIPCHK(hipGetLastError());
     t.stop(&c->prof.ms_matvec_total);
     c->prof.matvec_launches += 1;
+    c->prof.matvec_timed += timed ? 1 : 0;
     c->prof.matvec_bytes += 3 * E * E * (f64 ? 16 : 8);
     return;
   }
   launch_zero(y, 2 * vs * nrhs, c->stream);
-  LazyTimer t(c);
+  LazyTimer t(c, timed);
   if (c->precA == PMCHWT_FP64) {
     launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
@@ -1871,6 +1883,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   HIPCHK(hipGetLastError());
   t.stop(&c->prof.ms_matvec_total);
   c->prof.matvec_launches += 1 + int64_t(c->sc.size());
+  c->prof.matvec_timed += timed ? 1 + int64_t(c->sc.size()) : 0;
   int64_t bytes = 2 * E * E;
   for (auto& s : c->sc) bytes += 2 * int64_t(s.topo.E) * s.topo.E;
   c->prof.matvec_bytes += bytes * (c->precA == PMCHWT_FP64 ? 16 : 8);
@@ -2154,7 +2167,8 @@ struct GmresRun {
   int32_t* h_act[2];
   double *h_scale, *h_y, *h_beta;
   int32_t* h_upd;
-  hipEvent_t ev = nullptr, ev_step[2] = {nullptr, nullptr};
+  hipEvent_t ev = nullptr;
+  double seqno = 0, slot_seq[2] = {-1, -1};  // step numbers: last issued, expected per slot
   GmresOut out;
   std::vector<double> bnorm, beta;
   std::vector<int32_t> active, dev_active;  // host view; what the device's mask holds
@@ -2173,7 +2187,10 @@ struct GmresRun {
   // a few KB go through the compute queue, larger ones through a copy engine
   // with a cross-queue wait)
   size_t part_doubles() const { return 4 * (1024 + size_t(rho + 1) * nrhs) + size_t(update_blocks(n)) * nrhs; }
-  static size_t res_doubles(int nrhs, int rho) { return 4 * size_t(rho + 1) * nrhs + nrhs; }
+  // [h1 | h2 | norms | flags]: the finish kernel sets flags[r] to the step's
+  // number after the rest of the slot
+  static size_t flag_off(int nrhs, int rho) { return 4 * size_t(rho + 1) * nrhs + nrhs; }
+  static size_t res_doubles(int nrhs, int rho) { return flag_off(nrhs, rho) + nrhs; }
   static size_t pinned_bytes(int nrhs, int rho) {
     return 8 * (2 * size_t(nrhs) + 2 * size_t(rho + 1) * nrhs) + 4 * 3 * size_t(nrhs) + 64;
   }
@@ -2214,8 +2231,8 @@ struct GmresRun {
     h_act[1] = h_act[0] + nrhs;
     h_upd = h_act[1] + nrhs;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_step[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_step[1], hipEventDisableTiming));
+    for (int sl = 0; sl < 2; ++sl)
+      for (int q = 0; q < nrhs; ++q) h_res[sl][flag_off(nrhs, rho) + q] = -1.0;
     out.iters.assign(nrhs, 0);
     out.restarts.assign(nrhs, 0);
     out.relres.assign(nrhs, 1.0);
@@ -2234,11 +2251,29 @@ struct GmresRun {
     // the pinned buffers and small device arrays may still feed queued copies
     (void)hipStreamSynchronize(c->stream);
     if (ev) (void)hipEventDestroy(ev);
-    for (auto e : ev_step)
-      if (e) (void)hipEventDestroy(e);
   }
 
   void wait() { HIPCHK(hipEventSynchronize(ev)); }
+  // Wait for the results of the step in slot sl: spin on its flags in host
+  // memory (no event on the stream between steps).  A stream that has gone
+  // idle, or failed, without setting them ends the wait with an error.
+  void wait_step(int sl) {
+    const volatile double* f = h_res[sl] + flag_off(nrhs, rho);
+    const double want = slot_seq[sl];
+    auto ready = [&]() {
+      for (int q = 0; q < nrhs; ++q)
+        if (f[q] != want) return false;
+      return true;
+    };
+    for (int64_t spin = 1; !ready(); ++spin) {
+      if ((spin & 1023) != 0) continue;
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipErrorNotReady) continue;
+      HIPCHK(e);
+      if (!ready()) throw Fail{PMCHWT_ERR_DEVICE, "Arnoldi step results did not arrive"};
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+  }
   void mark() { HIPCHK(hipEventRecord(ev, c->stream)); }
 
   // x = 0, r = bt, |bt| (synchronous), then the first cycle
@@ -2308,9 +2343,9 @@ struct GmresRun {
       launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h1, j + 1, -1.0, c->stream, S1);
       dots_part_only(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, c->stream);
       launch_update(V, vstep, j + 1, w, vs, n, act, nrhs, vs, h2, j + 1, -1.0, c->stream, S1, hn);
+      slot_seq[j & 1] = ++seqno;
       launch_finish_step(w, vs, V + size_t(j + 1) * nrhs * vecd, vs, n, nrhs, hn, S2, act, h1, h2, S1, j + 1,
-                         d_res[j & 1], c->stream);
-      HIPCHK(hipEventRecord(ev_step[j & 1], c->stream));
+                         d_res[j & 1], d_res[j & 1] + flag_off(nrhs, rho), seqno, c->stream);
     } else if (step == RESID) {  // r = bt - Op x
       launch_axpby(r, bt, vs, n, nrhs, -1.0, 1.0, c->stream);
       launch_norms(r, vs, n, nrhs, dn, c->stream, dpart.as<double>());
@@ -2323,7 +2358,7 @@ struct GmresRun {
     if (step == ITER) {  // the host part of the previous step
       if (!pend) return;
       pend = false;
-      HIPCHK(hipEventSynchronize(ev_step[(j - 1) & 1]));
+      wait_step((j - 1) & 1);
       if (column(j - 1)) {
         end_cycle(j - 1);
         ended = true;
@@ -2344,7 +2379,7 @@ struct GmresRun {
   void stage3() {
     if (step != ITER || ended) return;
     if (j + 1 >= rho || total + 1 >= max_iter) {  // the cycle's last step: no look-ahead
-      HIPCHK(hipEventSynchronize(ev_step[j & 1]));
+      wait_step(j & 1);
       column(j);
       end_cycle(j);
       return;
@@ -2792,6 +2827,7 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     c->prof.ms_matvec_total = 0;
     c->prof.ms_matvec_reduce = 0;
     c->prof.matvec_launches = 0;
+    c->prof.matvec_timed = 0;
     c->prof.matvec_bytes = 0;
     c->prof.ms_mfma_total = 0;
     c->prof.mfma_launches = 0;

@@ -310,9 +310,11 @@ int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, in
 // v = w / sqrt(sum_s nrm2[r S2 + s]) per right-hand side (0 where inactive or
 // zero); also the finished sums fin = [h1 | h2 | norms] of the step's two
 // projection passes (h1p, h2p: S1 partials per coefficient, nvec coefficients)
+// and, once those are visible system-wide, flags[r] = seq (fin and flags may
+// be host memory mapped for the device)
 void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                         const double* nrm2, int S2, const int32_t* active, const double* h1p, const double* h2p,
-                        int S1, int nvec, double* fin, hipStream_t st);
+                        int S1, int nvec, double* fin, double* flags, double seq, hipStream_t st);
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,

@@ -1183,7 +1183,8 @@ void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstr
 // every sum taken in order of the partial index as the update kernels do.
 __global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n,
                               const double* nrm2, int S2, const int32_t* active, const double* h1p,
-                              const double* h2p, int S1, int nvec, int nrhs, double* fin) {
+                              const double* h2p, int S1, int nvec, int nrhs, double* fin, double* flags,
+                              double seq) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   // |w|^2 from its partial sums: strided per thread, then a fixed tree over
@@ -1216,6 +1217,10 @@ __global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64
       f2[i] = b;
     }
     if (threadIdx.x == 0) fin[4 * int64_t(nrhs) * nvec + r] = h;
+    // the step number after the values, once they are visible to the host
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) *reinterpret_cast<volatile double*>(flags + r) = seq;
   }
   if (k >= n) return;
   const double s = (active[r] && h > 0) ? 1.0 / h : 0.0;
@@ -1225,9 +1230,9 @@ __global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64
 
 void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                         const double* nrm2, int S2, const int32_t* active, const double* h1p, const double* h2p,
-                        int S1, int nvec, double* fin, hipStream_t st) {
+                        int S1, int nvec, double* fin, double* flags, double seq, hipStream_t st) {
   hipLaunchKernelGGL(k_finish_step, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, w, wstride, v, vstride, n, nrm2,
-                     S2, active, h1p, h2p, S1, nvec, nrhs, fin);
+                     S2, active, h1p, h2p, S1, nvec, nrhs, fin, flags, seq);
 }
 
 // y = a y + b x  (complex vectors, real scalars)
