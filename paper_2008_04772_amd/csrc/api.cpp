@@ -216,7 +216,7 @@ struct pmchwt_ctx {
   // truncated CSR copies of the FP32 inverses (mixed-precision P): the
   // products for fewer than 16 right-hand sides read these
   struct SparseInv {
-    DBuf rowptr, col, val;
+    DBuf rowptr, col, val;  // val: float for an FP32 inverse, double for FP64
     int64_t nnz = 0;
   };
   std::vector<SparseInv> MinvS, MinvTS;
@@ -1638,22 +1638,29 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
   return ok;
 }
 
-// Truncated CSR copy of an FP32 inverse (entries of at least 2^-27 of their
-// row's largest; the rest lies below the FP32 rounding of the stored
-// inverse).  One host wait for the entry count.
-pmchwt_ctx::SparseInv truncated_inverse(pmchwt_ctx* c, const float* A, int64_t ld, int n) {
-  pmchwt_ctx::SparseInv t;
-  DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<float>(c, size_t(n));
+// Truncated CSR copy of an inverse: entries of at least rel times their
+// row's largest (2^-27 for an FP32 inverse, 2^-52 for FP64: what is dropped
+// lies below the rounding of the stored inverse).  One host wait for the
+// entry count; the copy is kept (true) only if it has fewer than
+// max_fill * n^2 entries.
+template <typename T>
+bool truncated_inverse(pmchwt_ctx* c, const T* A, int64_t ld, int n, T rel, double max_fill,
+                       pmchwt_ctx::SparseInv& t) {
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<T>(c, size_t(n));
   t.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
-  build_truncated_inverse(A, ld, n, 0x1p-27f, cnt.as<int32_t>(), thr.as<float>(), t.rowptr.as<int64_t>(), c->stream);
+  build_truncated_inverse(A, ld, n, rel, cnt.as<int32_t>(), thr.as<T>(), t.rowptr.as<int64_t>(), c->stream);
   HIPCHK(hipMemcpyAsync(&t.nnz, t.rowptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (double(t.nnz) >= max_fill * double(n) * n) {
+    t = pmchwt_ctx::SparseInv();
+    return false;
+  }
   t.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(1, t.nnz)));
-  t.val = dalloc_c<float>(c, size_t(std::max<int64_t>(1, t.nnz)));
-  fill_truncated_inverse(A, ld, n, thr.as<float>(), t.rowptr.as<int64_t>(), t.col.as<int32_t>(), t.val.as<float>(),
+  t.val = dalloc_c<T>(c, size_t(std::max<int64_t>(1, t.nnz)));
+  fill_truncated_inverse(A, ld, n, thr.as<T>(), t.rowptr.as<int64_t>(), t.col.as<int32_t>(), t.val.as<T>(),
                          c->stream);
   HIPCHK(hipGetLastError());
-  return t;
+  return true;
 }
 
 void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
@@ -1710,8 +1717,10 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
         c->prof.mass_iterations = 0;
       }
       launch_transpose_f32(Mf.as<float>(), MfT.as<float>(), int(ldm), c->stream);
-      c->MinvS.push_back(truncated_inverse(c, Mf.as<float>(), ldm, n));
-      c->MinvTS.push_back(truncated_inverse(c, MfT.as<float>(), ldm, n));
+      c->MinvS.emplace_back();
+      c->MinvTS.emplace_back();
+      truncated_inverse<float>(c, Mf.as<float>(), ldm, n, 0x1p-27f, 2.0, c->MinvS.back());
+      truncated_inverse<float>(c, MfT.as<float>(), ldm, n, 0x1p-27f, 2.0, c->MinvTS.back());
       c->Minv.push_back(std::move(Mf));
       c->MinvT.push_back(std::move(MfT));
       continue;
@@ -1729,8 +1738,21 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     DBuf Md = dalloc_c<double>(c, size_t(n) * ldm), MdT = dalloc_c<double>(c, size_t(n) * ldm);
     launch_repack(Mi.as<double>(), n, Md.as<double>(), ldm, c->stream);
     launch_repack(MiT.as<double>(), n, MdT.as<double>(), ldm, c->stream);
+    // truncated copies where they are sparse enough to read fewer bytes
+    // (12 B per kept entry against 8 B per dense entry)
+    pmchwt_ctx::SparseInv a, b;
+    if (truncated_inverse<double>(c, Md.as<double>(), ldm, n, 0x1p-52, 0.4, a) &&
+        truncated_inverse<double>(c, MdT.as<double>(), ldm, n, 0x1p-52, 0.4, b)) {
+      c->MinvS.push_back(std::move(a));
+      c->MinvTS.push_back(std::move(b));
+    }
     c->Minv.push_back(std::move(Md));
     c->MinvT.push_back(std::move(MdT));
+  }
+  // FP64 truncated copies only if every scatterer has them
+  if (!c->mass_f32 && c->MinvS.size() != c->sc.size()) {
+    c->MinvS.clear();
+    c->MinvTS.clear();
   }
   HIPCHK(hipGetLastError());
   c->prof.ms_mass = t.stop();
@@ -1908,6 +1930,10 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     else if (c->mass_f32)
       launch_spmv_real2_csr(c->MinvS[m].rowptr.as<int64_t>(), c->MinvS[m].col.as<int32_t>(),
                             c->MinvS[m].val.as<float>(), s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E, c->stream);
+    else if (!c->MinvS.empty())
+      launch_spmv_real2_csr(c->MinvS[m].rowptr.as<int64_t>(), c->MinvS[m].col.as<int32_t>(),
+                            c->MinvS[m].val.as<double>(), s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E,
+                            c->stream);
     else
       launch_gemv_real2(c->Minv[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
                         nrhs, vs, E, c->stream);
@@ -1939,6 +1965,10 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     else if (c->mass_f32)
       launch_spmv_real2_csr(c->MinvTS[m].rowptr.as<int64_t>(), c->MinvTS[m].col.as<int32_t>(),
                             c->MinvTS[m].val.as<float>(), s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
+                            c->stream);
+    else if (!c->MinvTS.empty())
+      launch_spmv_real2_csr(c->MinvTS[m].rowptr.as<int64_t>(), c->MinvTS[m].col.as<int32_t>(),
+                            c->MinvTS[m].val.as<double>(), s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
                             c->stream);
     else
       launch_gemv_real2(c->MinvT[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,

@@ -231,7 +231,7 @@ void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // y = alpha M x for both trace components (second component at +cstride);
 // M is double or float (accumulation in double); ld a multiple of 4 with
 // zero padding columns
-// Truncated CSR copy of an FP32 inverse (n x n, row-major, ld): entries of at
+// Truncated CSR copy of an inverse (n x n, row-major, ld): entries of at
 // least rel x their row's largest, ascending columns.  build_*: counts (cnt,
 // n ints), thresholds (thr, n floats) and rowptr (n + 1); fill_*: col / val of
 // rowptr[n] entries.  launch_spmv_real2_csr: the launch_gemv_real2 product
@@ -259,6 +259,8 @@ void launch_cheb_step(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const 
 template <typename T>
 void launch_identity_tail(T* X, int64_t ld, int n, hipStream_t st);
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
+void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,

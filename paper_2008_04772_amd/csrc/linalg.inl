@@ -612,27 +612,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   }
 }
 
-// y = sum of the partial slots of each row, slot order, plus the correction
-// row; four threads per row split the slots and the correction entries.
+// y = sum of the partial slots of each row plus the correction row.  A
+// workgroup takes 16 rows; thread (q, r) (r fastest: consecutive threads read
+// consecutive rows of a slot) adds slots q, q + 16, ... and correction entries
+// q, q + 16, ... of its row, then the 16 sums are added in q order.
 template <typename M, int T>
 __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ part, int nt, int n,
                                                     const int64_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col, const M* __restrict__ val,
                                                     const double* __restrict__ xD, const double* __restrict__ xN,
                                                     double* __restrict__ yD, double* __restrict__ yN) {
-  const int rr = threadIdx.x & 63, qq = threadIdx.x >> 6;
-  const int R = blockIdx.x * 64 + rr;
+  const int rr = threadIdx.x & 15, qq = threadIdx.x >> 4;
+  const int R = blockIdx.x * 16 + rr;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (R < n) {
     const int K = R / T, r = R - K * T;
-    for (int s = qq; s < nt; s += 4) {
+    for (int s = qq; s < nt; s += 16) {
       const d4v v = *reinterpret_cast<const d4v*>(part + ((int64_t(K) * nt + s) * T + r) * 4);
       a0 += v[0];
       a1 += v[1];
       a2 += v[2];
       a3 += v[3];
     }
-    for (int64_t k = rowptr[R] + qq; k < rowptr[R + 1]; k += 4) {
+    for (int64_t k = rowptr[R] + qq; k < rowptr[R + 1]; k += 16) {
       const int64_t c = col[k];
       const double dr = xD[2 * c], di = xD[2 * c + 1], nr = xN[2 * c], ni = xN[2 * c + 1];
       const M* v = val + 6 * k;
@@ -643,16 +645,18 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ p
       a3 += cr * ni + ci * nr + tr * di + ti * dr;
     }
   }
-  __shared__ double red[4][64][4];
+  __shared__ double red[16][16][4];
   red[qq][rr][0] = a0;
   red[qq][rr][1] = a1;
   red[qq][rr][2] = a2;
   red[qq][rr][3] = a3;
   __syncthreads();
   if (qq == 0 && R < n) {
-    double o[4];
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = ((red[0][rr][q] + red[1][rr][q]) + red[2][rr][q]) + red[3][rr][q];
+    for (int p = 0; p < 16; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] += red[p][rr][q];
     yD[2 * int64_t(R)] = o[0];
     yD[2 * int64_t(R) + 1] = o[1];
     yN[2 * int64_t(R)] = o[2];
@@ -686,7 +690,7 @@ void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, in
 template <typename M>
 void launch_sym_reduce(const double* part, int nt, int n, const int64_t* rowptr, const int32_t* col, const M* val,
                        const double* xD, const double* xN, double* yD, double* yN, hipStream_t st) {
-  hipLaunchKernelGGL((k_sym_reduce<M, SYM_T>), dim3(unsigned((n + 63) / 64)), dim3(256), 0, st, part, nt, n, rowptr,
+  hipLaunchKernelGGL((k_sym_reduce<M, SYM_T>), dim3(unsigned((n + 15) / 16)), dim3(256), 0, st, part, nt, n, rowptr,
                      col, val, xD, xN, yD, yN);
 }
 
@@ -1885,10 +1889,10 @@ template void launch_identity_tail<float>(float*, int64_t, int, hipStream_t);
 // y = alpha * M x (M real CSR) on the two trace components of NR complex
 // vectors: the same product as k_gemv_real2 from the truncated inverse.  One
 // wavefront per row, lanes over the row's entries.
-template <int NR>
+template <int NR, typename VT>
 __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
-                                                        const float* __restrict__ val, int rows, double alpha,
+                                                        const VT* __restrict__ val, int rows, double alpha,
                                                         const double* __restrict__ x, double* y, int64_t vstride,
                                                         int64_t cstride) {
   const int lane = threadIdx.x & 63;
@@ -1928,7 +1932,8 @@ __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restric
   }
 }
 
-void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
+template <typename VT>
+static void spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const VT* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
   const dim3 grid(unsigned((rows + 3) / 4)), block(256);
   for (int r0 = 0; r0 < nrhs;) {
@@ -1936,15 +1941,23 @@ void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const floa
     const double* xx = x + 2 * int64_t(r0) * vstride;
     double* yy = y + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      hipLaunchKernelGGL((k_spmv_real2_csr<4>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy, vstride,
-                         cstride);
+      hipLaunchKernelGGL((k_spmv_real2_csr<4, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
+                         vstride, cstride);
       r0 += 4;
     } else {
-      hipLaunchKernelGGL((k_spmv_real2_csr<1>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy, vstride,
-                         cstride);
+      hipLaunchKernelGGL((k_spmv_real2_csr<1, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
+                         vstride, cstride);
       r0 += 1;
     }
   }
+}
+void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
+  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st);
+}
+void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
+  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st);
 }
 
 __global__ void k_spmv_real(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
