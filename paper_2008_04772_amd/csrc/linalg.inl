@@ -481,16 +481,17 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
-// sum over aligned groups of L lanes, every lane of a group gets it; L = 16
-// by DPP within the rows of 16 lanes (swap neighbours, swap pairs, mirror
-// halves of 8, mirror the row), wider groups by shuffles
+// sum over aligned groups of L lanes, every lane of a group gets it; within
+// the rows of 16 lanes by DPP (swap neighbours, swap pairs, mirror halves of
+// 8, mirror the row), across rows by shuffles
 template <int L>
 __device__ __forceinline__ double row_sum(double v) {
-  if constexpr (L == 16) {
+  if constexpr (L == 16 || L == 32) {
     v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_move<0x141>(v);  // row_half_mirror
     v += dpp_move<0x140>(v);  // row_mirror
+    if constexpr (L == 32) v += __shfl_xor(v, 16, WAVE);
   } else {
 #pragma unroll
     for (int o = L / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -504,8 +505,11 @@ __device__ __forceinline__ double row_sum(double v) {
 // 2(cl + LPR k) + {0, 1}, k < T / (2 LPR), of all three blocks (contiguous
 // LPR-lane segments per load).  Row sums: FP64 per lane, then over the LPR
 // lanes.  Column sums: per lane over its rows, then over the G row groups
-// (shuffles) and the four wavefronts (LDS), in that fixed order.
-template <typename M, int T, int LPR, int RPS, int WPE = 1>
+// (shuffles) and the four wavefronts (LDS), in that fixed order.  XREG keeps
+// the lane's column x values in registers (else they are re-read from LDS
+// every step); WPE is a minimum of wavefronts per SIMD for the register
+// allocator.
+template <typename M, int T, int LPR, int RPS, int WPE = 1, bool XREG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemv_sym3(const M* __restrict__ P, const int32_t* __restrict__ tij, int nt,
                                                    int n, const double* __restrict__ xD,
                                                    const double* __restrict__ xN, double* __restrict__ part) {
@@ -537,10 +541,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     for (int u = 0; u < 2; ++u) ca[k][u][0] = ca[k][u][1] = ca[k][u][2] = ca[k][u][3] = 0.0;
   const V* base = reinterpret_cast<const V*>(P) + int64_t(t) * 3 * MATV;
   __syncthreads();
+  double xc[XREG ? NU : 1][2][4];
+  if constexpr (XREG) {
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xc[k][u][q] = xk[2 * (cl + LPR * k) + u][q];
+  }
   for (int s = 0; s < RW / (G * RPS); ++s) {
     // column x values are re-read from LDS every step rather than held in
     // registers across the loop
-    asm volatile("" ::: "memory");
+    if constexpr (!XREG) asm volatile("" ::: "memory");
     const int r0 = wv * RW + G * RPS * s + g;
     V cv[RPS][NU], av[RPS][NU], bv[RPS][NU];
 #pragma unroll
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
           const double cr = double(cv[j][k][2 * u]), ci = double(cv[j][k][2 * u + 1]);
           const double sr = double(av[j][k][2 * u]), si = double(av[j][k][2 * u + 1]);
           const double tr = double(bv[j][k][2 * u]), ti = double(bv[j][k][2 * u + 1]);
-          const double* xq = xk[2 * (cl + LPR * k) + u];
+          const double* xq = XREG ? xc[XREG ? k : 0][u] : xk[2 * (cl + LPR * k) + u];
           const double xdr = xq[0], xdi = xq[1], xnr = xq[2], xni = xq[3];
           // chains of fused multiply-adds (four per accumulator and entry)
           a[j][0] = fma(-si, xni, fma(sr, xnr, fma(-ci, xdi, fma(cr, xdr, a[j][0]))));
@@ -683,8 +696,14 @@ void launch_sym_corr(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t
 template <typename M>
 void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, int n, const double* xD,
                       const double* xN, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T, 16, 1>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij, nt, n, xD, xN,
-                     part);
+  // measured on the 7680-edge operator: FP32 best with 32 lanes per row and
+  // the column x values in registers, FP64 with 16 lanes per row
+  if constexpr (sizeof(M) == 4)
+    hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T, 32, 1, 1, true>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij, nt,
+                       n, xD, xN, part);
+  else
+    hipLaunchKernelGGL((k_gemv_sym3<M, SYM_T, 16, 1, 1, false>), dim3(unsigned(ntiles)), dim3(256), 0, st, P, tij,
+                       nt, n, xD, xN, part);
 }
 
 template <typename M>
