@@ -293,6 +293,9 @@ int64_t ldmass(int64_t n) { return (n + 31) & ~int64_t(31); }
 
 // right-hand sides from which FP32 operators are applied on the matrix cores
 constexpr int MFMA_MIN_RHS = 16;
+// device bytes of the slot rows of one slab of the regular assembly (pass 1
+// output); one slab per scatterer up to this size lets pass 2 overwrite
+constexpr double SLAB_BUDGET = 16.0e9;
 // automatic choice of the symmetric-tile product: from this many edges on
 // (528 tiles of 128 x 128 and up)
 constexpr int64_t SYM_MIN_EDGES = 4096;
@@ -745,11 +748,6 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     else
       launch_zero_f(reinterpret_cast<float*>(b.p), int64_t(b.bytes / 4), c->stream);
   };
-  zero(c->Se);
-  zero(c->Ce);
-  for (auto& b : c->Si) zero(b);
-  for (auto& b : c->Ci) zero(b);
-
   AsmParams<M> p = asm_params<M>(c);
   p.q_near = o.q_near;
   p.q_medium = o.q_medium;
@@ -863,7 +861,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     c->chunk_size = CH;
   }
   // slabs of test triangles inside one scatterer, sized for a bounded buffer
-  const double budget = 6.0e9;
+  const double budget = SLAB_BUDGET;
   const double row_bytes = 3.0 * 2 * sizeof(M) * 2;  // per test triangle per union column, S and C
   std::vector<std::pair<int, int>> slabs;  // (t0, t1)
   for (auto& s : c->sc) {
@@ -912,6 +910,16 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
           eam[e] = a;
         }
       }
+  // one slab per scatterer: pass 2 writes every row of every block once, so
+  // it overwrites (and zeroes the padding columns) instead of adding to
+  // cleared matrices
+  const bool overwrite = slabs.size() == c->sc.size();
+  if (!overwrite) {
+    zero(c->Se);
+    zero(c->Ce);
+    for (auto& b : c->Si) zero(b);
+    for (auto& b : c->Ci) zero(b);
+  }
   double ms_pass1 = 0.0, ms_pass2 = 0.0;
   EvTimer all(c->stream);
   for (auto& sl : slabs) {
@@ -954,13 +962,13 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     {
       EvTimer t(c->stream);
       launch_rows_combine<M>(c->Se.as<M>(), c->ldE, HeS.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, c->E_tot, c->stream);
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite);
       launch_rows_combine<M>(c->Ce.as<M>(), c->ldE, HeC.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, c->E_tot, c->stream);
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite);
       launch_rows_combine<M>(c->Si[m].as<M>(), c->ldI[m], HiS.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, s.topo.E, c->stream);
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite);
       launch_rows_combine<M>(c->Ci[m].as<M>(), c->ldI[m], HiC.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, s.topo.E, c->stream);
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite);
       HIPCHK(hipGetLastError());
       ms_pass2 += t.stop();
     }

@@ -249,18 +249,22 @@ __global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmPa
   }
 }
 
-// Pass 2: A[rows[r]] += H[sp[r]] + H[sm[r]] over complex columns.
-template <typename M>
+// Pass 2: A[rows[r]] += H[sp[r]] + H[sm[r]] over complex columns, or with OW
+// A[rows[r]] = H[sp[r]] + H[sm[r]] and zero padding columns up to lda (rows
+// that no other slab touches: no clearing pass before, same sums).
+template <typename M, bool OW>
 __global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M* __restrict__ H, int64_t ldh,
                                                       const int32_t* rows, const int32_t* sp, const int32_t* sm,
                                                       int ncols) {
   const int r = blockIdx.y;
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= 2 * int64_t(ncols)) return;
+  if (q >= (OW ? 2 * lda : 2 * int64_t(ncols))) return;
   const int i = rows[r], a = sp[r], b = sm[r];
-  M v = A[2 * int64_t(i) * lda + q];
-  if (a >= 0) v += H[2 * int64_t(a) * ldh + q];
-  if (b >= 0) v += H[2 * int64_t(b) * ldh + q];
+  M v = OW ? M(0) : A[2 * int64_t(i) * lda + q];
+  if (!OW || q < 2 * int64_t(ncols)) {
+    if (a >= 0) v += H[2 * int64_t(a) * ldh + q];
+    if (b >= 0) v += H[2 * int64_t(b) * ldh + q];
+  }
   A[2 * int64_t(i) * lda + q] = v;
 }
 
@@ -385,11 +389,15 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
 
 template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
-                         const int32_t* sm, int nrows, int ncols, hipStream_t st) {
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite) {
   for (int r0 = 0; r0 < nrows; r0 += 65535) {
     const int nr = std::min(65535, nrows - r0);
-    hipLaunchKernelGGL((k_rows_combine<M>), dim3(unsigned((2 * int64_t(ncols) + 255) / 256), nr), dim3(256), 0, st,
-                       A, lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
+    if (overwrite)
+      hipLaunchKernelGGL((k_rows_combine<M, true>), dim3(unsigned((2 * lda + 255) / 256), nr), dim3(256), 0, st, A,
+                         lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
+    else
+      hipLaunchKernelGGL((k_rows_combine<M, false>), dim3(unsigned((2 * int64_t(ncols) + 255) / 256), nr), dim3(256),
+                         0, st, A, lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
   }
 }
 
@@ -406,9 +414,9 @@ template void launch_regular_rows<double, double>(const AsmParams<double>&, cons
 template void launch_regular_rows<float, float>(const AsmParams<float>&, const HalfJob<float>&, int, int, int, int,
                                                 hipStream_t);
 template void launch_rows_combine<double>(double*, int64_t, const double*, int64_t, const int32_t*, const int32_t*,
-                                          const int32_t*, int, int, hipStream_t);
+                                          const int32_t*, int, int, hipStream_t, bool);
 template void launch_rows_combine<float>(float*, int64_t, const float*, int64_t, const int32_t*, const int32_t*,
-                                         const int32_t*, int, int, hipStream_t);
+                                         const int32_t*, int, int, hipStream_t, bool);
 template void launch_singular<double>(const AsmParams<double>&, const SingParams&, hipStream_t);
 template void launch_singular<float>(const AsmParams<float>&, const SingParams&, hipStream_t);
 

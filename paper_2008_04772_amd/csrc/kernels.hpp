@@ -136,7 +136,7 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
 // A[rows[r]] += H[sp[r]] + H[sm[r]] (negative slot = absent), complex rows of ncols
 template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
-                         const int32_t* sm, int nrows, int ncols, hipStream_t st);
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite = false);
 template <typename M>
 void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st);
 

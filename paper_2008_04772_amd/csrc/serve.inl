@@ -56,7 +56,7 @@ int64_t serve_estimate(const ServeRecord& r) {
     const double E = 1.5 * double(t.size() / 3), F = double(t.size() / 3);
     Aint += 2.0 * E * double(padld(int64_t(E))) * elt;
     mass += 4.0 * E * E * 8.0 + 2.0 * E * double(ldmass(int64_t(E))) * 8.0 + 4.0 * E * 128.0 * 8.0;
-    slab = std::max(slab, std::min(6.0e9, F * 3.0 * 2.0 * (elt / 2.0) * 2.0 * (Etot + E)));
+    slab = std::max(slab, std::min(SLAB_BUDGET, F * 3.0 * 2.0 * (elt / 2.0) * 2.0 * (Etot + E)));
   }
   const double A = 2.0 * Etot * double(padld(int64_t(Etot))) * elt + Aint;
   const double nnz = std::isfinite(r.oP.chi) && r.oP.chi >= 0 ? Etot * std::min(Etot, 800.0) : Etot * Etot;
