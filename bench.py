@@ -38,7 +38,7 @@ HBM_PEAK = 8000.0  # GB/s
 # HBM bytes per launch of the dense operator product, by (workload, kernel),
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB device copy
 # (the summaries under profiles/); valid for that kernel version only
-GEMV_TRAFFIC = {}
+GEMV_TRAFFIC = {("sphere5120", "k_gemv_sym3"): 736.6e6}
 
 WORKLOADS = {
     "sphere5120": "dielectric sphere r=1, 5120 triangles (15360 unknowns), k_e=5, eps_r=3.17+0.01i, 1 plane wave; "

@@ -252,20 +252,26 @@ __global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmPa
 // Pass 2: A[rows[r]] += H[sp[r]] + H[sm[r]] over complex columns, or with OW
 // A[rows[r]] = H[sp[r]] + H[sm[r]] and zero padding columns up to lda (rows
 // that no other slab touches: no clearing pass before, same sums).
+// One workgroup per row, striding over its columns.
 template <typename M, bool OW>
 __global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M* __restrict__ H, int64_t ldh,
                                                       const int32_t* rows, const int32_t* sp, const int32_t* sm,
                                                       int ncols) {
-  const int r = blockIdx.y;
-  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= (OW ? 2 * lda : 2 * int64_t(ncols))) return;
+  const int r = blockIdx.x;
   const int i = rows[r], a = sp[r], b = sm[r];
-  M v = OW ? M(0) : A[2 * int64_t(i) * lda + q];
-  if (!OW || q < 2 * int64_t(ncols)) {
-    if (a >= 0) v += H[2 * int64_t(a) * ldh + q];
-    if (b >= 0) v += H[2 * int64_t(b) * ldh + q];
+  M* Ar = A + 2 * int64_t(i) * lda;
+  const M* Ha = H + 2 * int64_t(a >= 0 ? a : 0) * ldh;
+  const M* Hb = H + 2 * int64_t(b >= 0 ? b : 0) * ldh;
+  const int64_t nc = 2 * int64_t(ncols), end = OW ? 2 * lda : nc;
+#pragma unroll 4
+  for (int64_t q = threadIdx.x; q < end; q += 256) {
+    M v = OW ? M(0) : Ar[q];
+    if (!OW || q < nc) {
+      if (a >= 0) v += Ha[q];
+      if (b >= 0) v += Hb[q];
+    }
+    Ar[q] = v;
   }
-  A[2 * int64_t(i) * lda + q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -390,15 +396,13 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
 template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
                          const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite) {
-  for (int r0 = 0; r0 < nrows; r0 += 65535) {
-    const int nr = std::min(65535, nrows - r0);
-    if (overwrite)
-      hipLaunchKernelGGL((k_rows_combine<M, true>), dim3(unsigned((2 * lda + 255) / 256), nr), dim3(256), 0, st, A,
-                         lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
-    else
-      hipLaunchKernelGGL((k_rows_combine<M, false>), dim3(unsigned((2 * int64_t(ncols) + 255) / 256), nr), dim3(256),
-                         0, st, A, lda, H, ldh, rows + r0, sp + r0, sm + r0, ncols);
-  }
+  if (nrows <= 0) return;
+  if (overwrite)
+    hipLaunchKernelGGL((k_rows_combine<M, true>), dim3(unsigned(nrows)), dim3(256), 0, st, A, lda, H, ldh, rows, sp,
+                       sm, ncols);
+  else
+    hipLaunchKernelGGL((k_rows_combine<M, false>), dim3(unsigned(nrows)), dim3(256), 0, st, A, lda, H, ldh, rows, sp,
+                       sm, ncols);
 }
 
 template <typename M>
