@@ -319,6 +319,10 @@ void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vst
                         int S1, int nvec, double* fin, double* flags, double seq, hipStream_t st);
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st);
+// conjugate-gradient scalars on the device (see k_cg_coef): mode 0 alpha,
+// mode 1 beta (updates rr), mode 2 start (rr = rr0 = nr^2)
+void launch_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0, double tol2,
+                    double* out, hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,
                   hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);

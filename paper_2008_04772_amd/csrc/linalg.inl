@@ -1258,6 +1258,38 @@ void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vst
                      S2, active, h1p, h2p, S1, nvec, nrhs, fin, flags, seq);
 }
 
+// Conjugate-gradient coefficients per vector k, on the device: mode 0
+// alpha = |r|^2 / Re(p^H G p) (pq: complex dots), mode 1 beta = |r_new|^2 /
+// |r|^2 and |r|^2 updated (nr: new residual norms), mode 2 the start
+// (|r|^2 = |r0|^2 = nr^2).  A vector with |r|^2 <= tol2 |r0|^2 gets 0 and
+// keeps its |r|^2: its iterate no longer changes.
+__global__ void k_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0,
+                          double tol2, double* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nvec) return;
+  if (mode == 2) {
+    rr[k] = nr[k] * nr[k];
+    rr0[k] = rr[k];
+    return;
+  }
+  const bool on = rr[k] > tol2 * rr0[k];
+  if (mode == 0) {
+    out[k] = (on && pq[2 * k] > 0) ? rr[k] / pq[2 * k] : 0.0;
+  } else if (on) {
+    const double rn = nr[k] * nr[k];
+    out[k] = rr[k] > 0 ? rn / rr[k] : 0.0;
+    rr[k] = rn;
+  } else {
+    out[k] = 0.0;
+  }
+}
+
+void launch_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0, double tol2,
+                    double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_coef, dim3(unsigned((nvec + 63) / 64)), dim3(64), 0, st, nvec, mode, pq, nr, rr, rr0, tol2,
+                     out);
+}
+
 // y = a y + b x  (complex vectors, real scalars)
 __global__ void k_axpby(double* y, const double* x, int64_t stride, int n, double a, double b) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
