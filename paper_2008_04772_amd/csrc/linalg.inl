@@ -1869,12 +1869,16 @@ void launch_csc_to_ell(const int64_t* colptr, const int32_t* rowidx, const doubl
 template void launch_csc_to_ell<float>(const int64_t*, const int32_t*, const double*, int, int, int32_t*, float*,
                                        hipStream_t);
 
-// rows per workgroup: as many rows of X as fit in 136 KB of LDS (at most 4)
+// rows per workgroup: 2 when two rows of X fit in 136 KB of LDS, else 1
+// (0: a row does not fit).  Measured on the 7680-edge sphere, whole inverse:
+// 4 rows (one workgroup per CU) 8.6 ms, 2 rows (two per CU, their load and
+// gather phases overlap) 7.2 ms, 1 row (the ELL copy of M_A re-read by twice
+// as many workgroups) 9.7 ms.
 template <typename T>
 int cheb_rows(int n) {
   const int64_t per = int64_t(n) * sizeof(T);
-  const int rb = int(std::min<int64_t>(4, (136 * 1024) / std::max<int64_t>(per, 1)));
-  return rb >= 4 ? 4 : (rb >= 2 ? 2 : rb);
+  const int rb = int(std::min<int64_t>(2, (136 * 1024) / std::max<int64_t>(per, 1)));
+  return rb >= 2 ? 2 : rb;
 }
 template int cheb_rows<float>(int);
 
@@ -1896,9 +1900,7 @@ template <typename T, int W>
 static void cheb_launch_rb(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const T* eval, double cD, double cR,
                            double inv_d, bool first, double* rn_part, hipStream_t st) {
   const int rb = cheb_rows<T>(n);
-  if (rb == 4)
-    cheb_launch<T, 4, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
-  else if (rb == 2)
+  if (rb == 2)
     cheb_launch<T, 2, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
   else
     cheb_launch<T, 1, W>(X, D, ld, n, eidx, eval, cD, cR, inv_d, first, rn_part, st);
