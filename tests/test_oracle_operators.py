@@ -4,7 +4,8 @@
   self integral of 1/r (fixes weights and Jacobians of the singular path);
 * a regular pair at the paper's orders against a converged composite rule;
 * complex symmetry of S and C (same test and trial space), converging with
-  the singular order;
+  the singular order, and exact up to rounding outside the entries that
+  vertex-sharing (singular) pairs touch;
 * C vanishes on coplanar pairs;
 * loop null spaces: vertex loops of RWG and dual loops of BC are divergence
   free, so the div-div part of S annihilates them;
@@ -88,6 +89,40 @@ def test_symmetry_converges_with_singular_order():
         asym.append([np.abs(M - M.T).max() / np.abs(M).max() for M in (d["S"], d["C"])])
     assert asym[1][0] < 1e-10 and asym[1][1] < 1e-7
     assert asym[1][0] < 1e-3 * asym[0][0] and asym[1][1] < 1e-2 * asym[0][1]
+
+
+def _vertex_sharing_pattern(T):
+    """Entries (i, j) that some pair of triangles sharing a vertex (the
+    Sauter-Schwab classes: identical, shared edge, shared vertex) touches."""
+    v2t = [[] for _ in range(len(T.verts))]
+    for f, tri in enumerate(T.tris):
+        for a in tri:
+            v2t[a].append(f)
+    pat = np.zeros((T.E, T.E), bool)
+    for f, tri in enumerate(T.tris):
+        for g in {g for a in tri for g in v2t[a]}:
+            pat[np.ix_(T.t2e[f], T.t2e[g])] = True
+    return pat
+
+
+@pytest.mark.parametrize("mesh", ["icosphere1", "prism23"])
+def test_asymmetry_only_on_vertex_sharing_pairs(mesh):
+    """S and C are symmetric forms on one space and every disjoint pair is
+    integrated with the same product rule from either side, so the
+    assembled matrices are symmetric to rounding except where a singular
+    (Sauter-Schwab) rule integrates a vertex-sharing pair, which it does not
+    do symmetrically in the two triangles.  A product that stores one
+    triangle of the matrix relies on exactly this, with a correction on the
+    vertex-sharing pattern."""
+    v, t = synth.icosphere(1) if mesh == "icosphere1" else synth.hex_prism(2, 3)
+    T = Topology(v, t)
+    pat = _vertex_sharing_pattern(T)
+    d = ops.assemble_rwg(T, 2.0 * np.sqrt(3.17 + 0.01j), n_sing=4)
+    for name in ("S", "C"):
+        M = d[name]
+        D = np.abs(M - M.T) / np.abs(M).max()
+        assert D[~pat].max() < 1e-14, name
+        assert D[pat].max() > 1e-8, name  # the correction is needed
 
 
 def test_C_vanishes_on_coplanar_pairs():
