@@ -251,21 +251,24 @@ __global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmPa
 
 // Pass 2: A[rows[r]] += H[sp[r]] + H[sm[r]] over complex columns, or with OW
 // A[rows[r]] = H[sp[r]] + H[sm[r]] and zero padding columns up to lda (rows
-// that no other slab touches: no clearing pass before, same sums).
-// One workgroup per row, striding over its columns.
-template <typename M, bool OW>
+// that no other slab touches: no clearing pass before, same sums).  One
+// workgroup per row, striding over its columns in units of U values: U = 1,
+// or 16-byte vectors when both rows start on 16-byte boundaries and the
+// column counts are whole vectors.
+template <typename M, bool OW, int U>
 __global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M* __restrict__ H, int64_t ldh,
                                                       const int32_t* rows, const int32_t* sp, const int32_t* sm,
                                                       int ncols) {
+  typedef M VU __attribute__((ext_vector_type(U)));
   const int r = blockIdx.x;
   const int i = rows[r], a = sp[r], b = sm[r];
-  M* Ar = A + 2 * int64_t(i) * lda;
-  const M* Ha = H + 2 * int64_t(a >= 0 ? a : 0) * ldh;
-  const M* Hb = H + 2 * int64_t(b >= 0 ? b : 0) * ldh;
-  const int64_t nc = 2 * int64_t(ncols), end = OW ? 2 * lda : nc;
+  VU* Ar = reinterpret_cast<VU*>(A + 2 * int64_t(i) * lda);
+  const VU* Ha = reinterpret_cast<const VU*>(H + 2 * int64_t(a >= 0 ? a : 0) * ldh);
+  const VU* Hb = reinterpret_cast<const VU*>(H + 2 * int64_t(b >= 0 ? b : 0) * ldh);
+  const int64_t nc = 2 * int64_t(ncols) / U, end = OW ? 2 * lda / U : nc;
 #pragma unroll 4
   for (int64_t q = threadIdx.x; q < end; q += 256) {
-    M v = OW ? M(0) : Ar[q];
+    VU v = OW ? VU(M(0)) : Ar[q];
     if (!OW || q < nc) {
       if (a >= 0) v += Ha[q];
       if (b >= 0) v += Hb[q];
@@ -397,12 +400,19 @@ template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
                          const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite) {
   if (nrows <= 0) return;
-  if (overwrite)
-    hipLaunchKernelGGL((k_rows_combine<M, true>), dim3(unsigned(nrows)), dim3(256), 0, st, A, lda, H, ldh, rows, sp,
-                       sm, ncols);
+  constexpr int U = 16 / sizeof(M);
+  // 16-byte units: row starts (2 ldh, 2 lda values apart) and the column
+  // counts must be whole units
+  const bool vec = (2 * ldh) % U == 0 && (2 * lda) % U == 0 && (2 * int64_t(ncols)) % U == 0;
+  const dim3 grid{static_cast<unsigned>(nrows)}, block{256};
+  if (vec && overwrite)
+    hipLaunchKernelGGL((k_rows_combine<M, true, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+  else if (vec)
+    hipLaunchKernelGGL((k_rows_combine<M, false, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+  else if (overwrite)
+    hipLaunchKernelGGL((k_rows_combine<M, true, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
   else
-    hipLaunchKernelGGL((k_rows_combine<M, false>), dim3(unsigned(nrows)), dim3(256), 0, st, A, lda, H, ldh, rows, sp,
-                       sm, ncols);
+    hipLaunchKernelGGL((k_rows_combine<M, false, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
 }
 
 template <typename M>
