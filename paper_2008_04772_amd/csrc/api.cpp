@@ -577,6 +577,8 @@ AsmParams<M> asm_params(pmchwt_ctx* c) {
   return p;
 }
 
+void flush_times(pmchwt_ctx* c);
+
 // Timer whose result is added to *dst later (flush_times): no host wait.
 struct LazyTimer {
   pmchwt_ctx* c;
@@ -602,6 +604,7 @@ struct LazyTimer {
     c->ptimes.push_back({a, b, dst});
     a = nullptr;
     HIPCHK(hipEventRecord(b, c->stream));
+    if (c->ptimes.size() >= 4096) flush_times(c);  // bounded between solves too
   }
   ~LazyTimer() {
     if (a) c->evpool.push_back(a);
