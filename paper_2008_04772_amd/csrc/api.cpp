@@ -2149,8 +2149,9 @@ void op_apply(pmchwt_ctx* c, const double* x, double* y, double* s1, double* s2,
   apply_Ptilde(c, s1, y, s2, s3, nrhs);
 }
 
-// Host buffers for the small per-iteration transfers, pinned so that the
-// copies are asynchronous and several runs can overlap on the device.
+// Pinned host buffers for the small per-iteration transfers: copies from and
+// to them are asynchronous (several runs can overlap on the device), and with
+// hipHostMallocCoherent the device writes them directly through `dev`.
 struct PinnedBuf {
   void* p = nullptr;
   void* dev = nullptr;  // the device's address of the same memory
@@ -2220,10 +2221,8 @@ struct GmresRun {
   Phase step = DONE;  // phase in which the current step started (set by stage1)
 
   // partial sums of one step on the device: two projection passes of at most
-  // 2 (1024 + (rho+1) nrhs) doubles each, the norm's update_blocks(n) nrhs; the
-  // finished values [h1 | h2 | norms] the host reads (kept small: copies of
-  // a few KB go through the compute queue, larger ones through a copy engine
-  // with a cross-queue wait)
+  // 2 (1024 + (rho+1) nrhs) doubles each, the norm's update_blocks(n) nrhs;
+  // the finished values [h1 | h2 | norms] go to the host slots (hres)
   size_t part_doubles() const { return 4 * (1024 + size_t(rho + 1) * nrhs) + size_t(update_blocks(n)) * nrhs; }
   // [h1 | h2 | norms | flags]: the finish kernel sets flags[r] to the step's
   // number after the rest of the slot
