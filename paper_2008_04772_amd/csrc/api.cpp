@@ -2020,52 +2020,10 @@ void to_api(const pmchwt_ctx* c, const std::vector<double>& in, int nrhs, pmchwt
 // row (absolute offsets into col / val)
 void gram_cg(pmchwt_ctx* c, const int64_t* rowptr, int n, const double* b_in, double* x_out, int64_t in_stride,
              int nvec) {
-  // work on packed copies: vector q at q * n
-  const int64_t stride = n;
-  const size_t nd = 2 * size_t(stride) * nvec;
-  DBuf r = dalloc_c<double>(c, nd), p = dalloc_c<double>(c, nd), q = dalloc_c<double>(c, nd),
-       xb = dalloc_c<double>(c, nd), sc = dalloc_c<double>(c, 7 * size_t(nvec));
-  DBuf act = dalloc_c<int32_t>(c, nvec);
-  double* x = xb.as<double>();
-  std::vector<int32_t> on(nvec, 1);
-  HIPCHK(hipMemcpyAsync(act.p, on.data(), 4 * nvec, hipMemcpyHostToDevice, c->stream));
-  launch_zero(x, 2 * int64_t(stride) * nvec, c->stream);
-  HIPCHK(hipMemcpy2DAsync(r.p, size_t(n) * 16, b_in, size_t(in_stride) * 16, size_t(n) * 16, size_t(nvec),
-                          hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(p.p, r.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
-  // scalars on the device: pq (2 nvec), residual norms, alpha, beta, |r|^2, |r0|^2
-  double* pq = sc.as<double>();
-  double* nr = pq + 2 * nvec;
-  double* al = nr + nvec;
-  double* be = al + nvec;
-  double* rr = be + nvec;
-  double* rr0 = rr + nvec;
-  const double tol2 = 1e-28;
-  launch_norms(r.as<double>(), stride, n, nvec, nr, c->stream);
-  launch_cg_coef(nvec, 2, pq, nr, rr, rr0, tol2, nullptr, c->stream);
-  std::vector<double> h(2 * size_t(nvec));
-  for (int it = 0; it < 1000; ++it) {
-    // converged vectors stop changing on the device; the host looks every
-    // eighth iteration whether all have
-    if (it % 8 == 0) {
-      HIPCHK(hipMemcpyAsync(h.data(), rr, 16 * size_t(nvec), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      bool done = true;
-      for (int k = 0; k < nvec; ++k) done &= (h[k] <= tol2 * h[nvec + k]);
-      if (done) break;
-    }
-    launch_spmv_real(rowptr, c->g_col.as<int32_t>(), c->g_val.as<double>(), n, p.as<double>(), q.as<double>(), nvec,
-                     stride, c->stream);
-    launch_dots(p.as<double>(), 0, 1, q.as<double>(), stride, n, act.as<int32_t>(), nvec, stride, pq, c->stream);
-    launch_cg_coef(nvec, 0, pq, nr, rr, rr0, tol2, al, c->stream);
-    launch_axpy_vec(x, p.as<double>(), stride, n, nvec, al, 1.0, c->stream);
-    launch_axpy_vec(r.as<double>(), q.as<double>(), stride, n, nvec, al, -1.0, c->stream);
-    launch_norms(r.as<double>(), stride, n, nvec, nr, c->stream);
-    launch_cg_coef(nvec, 1, pq, nr, rr, rr0, tol2, be, c->stream);
-    launch_xpby_vec(p.as<double>(), r.as<double>(), stride, n, nvec, be, c->stream);
-  }
-  HIPCHK(hipMemcpy2DAsync(x_out, size_t(in_stride) * 16, x, size_t(n) * 16, size_t(n) * 16, size_t(nvec),
-                          hipMemcpyDeviceToDevice, c->stream));
+  // one workgroup per vector runs the whole iteration: no host round trip
+  DBuf work = dalloc_c<double>(c, 6 * size_t(n) * nvec);
+  launch_gram_cg(rowptr, c->g_col.as<int32_t>(), c->g_val.as<double>(), n, b_in, in_stride, x_out, in_stride, nvec,
+                 work.as<double>(), 1e-28, 1000, c->stream);
   HIPCHK(hipGetLastError());
 }
 

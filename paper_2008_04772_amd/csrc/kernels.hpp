@@ -319,10 +319,12 @@ void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vst
                         int S1, int nvec, double* fin, double* flags, double seq, hipStream_t st);
 void launch_scale_copy(const double* w, int64_t wstride, double* v, int64_t vstride, int n, int nrhs,
                        const double* scale, hipStream_t st);
-// conjugate-gradient scalars on the device (see k_cg_coef): mode 0 alpha,
-// mode 1 beta (updates rr), mode 2 start (rr = rr0 = nr^2)
-void launch_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0, double tol2,
-                    double* out, hipStream_t st);
+// G x = b by conjugate gradients (G: real SPD CSR of n rows; b, x complex,
+// per-vector strides in complex entries), one workgroup per vector; work:
+// 6 n nvec doubles
+void launch_gram_cg(const int64_t* rowptr, const int32_t* col, const double* val, int n, const double* b,
+                    int64_t bstride, double* x, int64_t xstride, int nvec, double* work, double tol2, int maxit,
+                    hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,
                   hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);

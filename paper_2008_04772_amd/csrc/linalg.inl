@@ -1258,38 +1258,6 @@ void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vst
                      S2, active, h1p, h2p, S1, nvec, nrhs, fin, flags, seq);
 }
 
-// Conjugate-gradient coefficients per vector k, on the device: mode 0
-// alpha = |r|^2 / Re(p^H G p) (pq: complex dots), mode 1 beta = |r_new|^2 /
-// |r|^2 and |r|^2 updated (nr: new residual norms), mode 2 the start
-// (|r|^2 = |r0|^2 = nr^2).  A vector with |r|^2 <= tol2 |r0|^2 gets 0 and
-// keeps its |r|^2: its iterate no longer changes.
-__global__ void k_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0,
-                          double tol2, double* out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nvec) return;
-  if (mode == 2) {
-    rr[k] = nr[k] * nr[k];
-    rr0[k] = rr[k];
-    return;
-  }
-  const bool on = rr[k] > tol2 * rr0[k];
-  if (mode == 0) {
-    out[k] = (on && pq[2 * k] > 0) ? rr[k] / pq[2 * k] : 0.0;
-  } else if (on) {
-    const double rn = nr[k] * nr[k];
-    out[k] = rr[k] > 0 ? rn / rr[k] : 0.0;
-    rr[k] = rn;
-  } else {
-    out[k] = 0.0;
-  }
-}
-
-void launch_cg_coef(int nvec, int mode, const double* pq, const double* nr, double* rr, double* rr0, double tol2,
-                    double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_coef, dim3(unsigned((nvec + 63) / 64)), dim3(64), 0, st, nvec, mode, pq, nr, rr, rr0, tol2,
-                     out);
-}
-
 // y = a y + b x  (complex vectors, real scalars)
 __global__ void k_axpby(double* y, const double* x, int64_t stride, int n, double a, double b) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2011,6 +1979,94 @@ void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const floa
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
   spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st);
+}
+
+// sum of v over the 1024 threads of the workgroup, in a fixed tree order;
+// every thread gets it (red: 1024 doubles of LDS)
+__device__ __forceinline__ double block_sum1024(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double t = red[0];
+  __syncthreads();
+  return t;
+}
+
+// Conjugate gradients for G x = b with G real symmetric positive definite
+// (CSR; rowptr of this block, col and val global) and complex b, one
+// workgroup of 1024 threads per right-hand side, from x = 0 until
+// |r|^2 <= tol2 |b|^2 or maxit steps.  Each thread takes every 1024-th
+// element; the sums go through block_sum1024, so the iterates do not depend
+// on timing.  work: r, p, q (2n doubles each) per right-hand side.
+__global__ __launch_bounds__(1024) void k_gram_cg(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, int n, const double* b,
+                                                  int64_t bstride, double* x, int64_t xstride, double* work,
+                                                  double tol2, int maxit) {
+  __shared__ double red[1024];
+  const int v = blockIdx.x;
+  const double* bv = b + 2 * int64_t(v) * bstride;
+  double* xv = x + 2 * int64_t(v) * xstride;
+  double* r = work + 6 * int64_t(v) * n;
+  double* p = r + 2 * int64_t(n);
+  double* q = p + 2 * int64_t(n);
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double br = bv[2 * i], bi = bv[2 * i + 1];
+    xv[2 * i] = 0.0;
+    xv[2 * i + 1] = 0.0;
+    r[2 * i] = br;
+    r[2 * i + 1] = bi;
+    p[2 * i] = br;
+    p[2 * i + 1] = bi;
+    sum += br * br + bi * bi;
+  }
+  double rr = block_sum1024(sum, red);  // its barriers also publish r and p to the workgroup
+  const double rr0 = rr;
+  for (int it = 0; it < maxit && rr > tol2 * rr0; ++it) {  // rr is the same in every thread
+    sum = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+      double qr = 0.0, qi = 0.0;
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const double g = val[k];
+        const int j = col[k];
+        qr += g * p[2 * j];
+        qi += g * p[2 * j + 1];
+      }
+      q[2 * i] = qr;
+      q[2 * i + 1] = qi;
+      sum += p[2 * i] * qr + p[2 * i + 1] * qi;
+    }
+    const double pq = block_sum1024(sum, red);
+    const double al = pq > 0 ? rr / pq : 0.0;
+    sum = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+      xv[2 * i] += al * p[2 * i];
+      xv[2 * i + 1] += al * p[2 * i + 1];
+      const double rr_ = r[2 * i] - al * q[2 * i], ri_ = r[2 * i + 1] - al * q[2 * i + 1];
+      r[2 * i] = rr_;
+      r[2 * i + 1] = ri_;
+      sum += rr_ * rr_ + ri_ * ri_;
+    }
+    const double rn = block_sum1024(sum, red);
+    const double be = rr > 0 ? rn / rr : 0.0;
+    rr = rn;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+      p[2 * i] = r[2 * i] + be * p[2 * i];
+      p[2 * i + 1] = r[2 * i + 1] + be * p[2 * i + 1];
+    }
+    __syncthreads();  // p complete before the next product reads it
+  }
+}
+
+void launch_gram_cg(const int64_t* rowptr, const int32_t* col, const double* val, int n, const double* b,
+                    int64_t bstride, double* x, int64_t xstride, int nvec, double* work, double tol2, int maxit,
+                    hipStream_t st) {
+  if (n <= 0 || nvec <= 0) return;
+  hipLaunchKernelGGL(k_gram_cg, dim3(unsigned(nvec)), dim3(1024), 0, st, rowptr, col, val, n, b, bstride, x, xstride,
+                     work, tol2, maxit);
 }
 
 __global__ void k_spmv_real(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
