@@ -223,10 +223,6 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
 // y = alpha * Mreal x (dense real row-major, rows x cols), complex vectors
 void launch_gemv_real(const double* Mat, int64_t ld, int rows, int cols, double alpha, const double* x,
                       double* y, int nrhs, int64_t vstride, hipStream_t st);
-// y_q = M x_q for a real CSR matrix (rowptr absolute into col / val) and nvec
-// complex vectors at stride vstride
-void launch_spmv_real(const int64_t* rowptr, const int32_t* col, const double* val, int rows, const double* x,
-                      double* y, int nvec, int64_t vstride, hipStream_t st);
 void launch_transpose(const double* in, double* out, int n, hipStream_t st);
 // y = alpha M x for both trace components (second component at +cstride);
 // M is double or float (accumulation in double); ld a multiple of 4 with
@@ -282,16 +278,8 @@ void launch_transpose_f32(const float* in, float* out, int n, hipStream_t st);
 // A rows x K (stride lda), B Nr x K (stride K), K a multiple of 32
 void launch_mfma_f32(const float* A, int64_t lda, const float* B, int K, int rows, int Nr, float* y, int64_t ldy,
                      bool subtract, hipStream_t st);
-// per-vector scaled updates for batched conjugate gradients
-void launch_axpy_vec(double* y, const double* x, int64_t stride, int n, int nvec, const double* a, double s,
-                     hipStream_t st);
-void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec, const double* b, hipStream_t st);
 
 // GMRES helpers on batches of complex128 vectors of length n.
-// part (optional): scratch of 2 (nvec nrhs + 1024) doubles for a split reduction
-void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
-                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st,
-                 double* part = nullptr);
 // w += sign V h; the coefficient (r, i) is the sum of S partial values
 // h[(r hstride + i) S + s] (complex), added in order of s.  nrm2 (optional):
 // partial sums of |w|^2 of the result, update_blocks(n) per right-hand side

@@ -991,18 +991,6 @@ __global__ void k_dots_part(const double* V, int64_t vstep, const double* w, int
   }
 }
 
-__global__ void k_dots_fin(const double* part, int S, int m, double* out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  double re = 0, im = 0;
-  for (int sidx = 0; sidx < S; ++sidx) {
-    re += part[2 * (int64_t(q) * S + sidx)];
-    im += part[2 * (int64_t(q) * S + sidx) + 1];
-  }
-  out[2 * q] = re;
-  out[2 * q + 1] = im;
-}
-
 int dots_splits(int nvec, int nrhs, int n) {
   const int want = (1024 + nvec * nrhs - 1) / (nvec * nrhs);
   return std::max(1, std::min({want, 64, (n + 255) / 256}));
@@ -1020,21 +1008,6 @@ int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, in
                        rstride_v, part, nvec, S, chunk);
   }
   return S;
-}
-
-void launch_dots(const double* V, int64_t vstep, int nvec, const double* w, int64_t wstride, int n,
-                 const int32_t* active, int nrhs, int64_t rstride_v, double* out, hipStream_t st, double* part) {
-  const int S = part ? dots_splits(nvec, nrhs, n) : 1;
-  if (S == 1) {
-    hipLaunchKernelGGL(k_dots, dim3(nvec, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v, out,
-                       nvec);
-    return;
-  }
-  const int chunk = (n + S - 1) / S;
-  hipLaunchKernelGGL(k_dots_part, dim3(nvec, S, nrhs), dim3(256), 0, st, V, vstep, w, wstride, n, active, rstride_v,
-                     part, nvec, S, chunk);
-  const int m = nvec * nrhs;
-  hipLaunchKernelGGL(k_dots_fin, dim3((m + 255) / 256), dim3(256), 0, st, part, S, m, out);
 }
 
 // w^r[k] += sign * sum_i V_i^r[k] h[r][i], where each coefficient is the sum
@@ -2069,30 +2042,6 @@ void launch_gram_cg(const int64_t* rowptr, const int32_t* col, const double* val
                      work, tol2, maxit);
 }
 
-__global__ void k_spmv_real(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                            const double* __restrict__ val, int rows, const double* __restrict__ x, double* y,
-                            int64_t vstride) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (i >= rows) return;
-  const double* xq = x + 2 * int64_t(q) * vstride;
-  double re = 0.0, im = 0.0;
-  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-    const double v = val[p];
-    const int jx = col[p];
-    re += v * xq[2 * jx];
-    im += v * xq[2 * jx + 1];
-  }
-  y[2 * (int64_t(q) * vstride + i)] = re;
-  y[2 * (int64_t(q) * vstride + i) + 1] = im;
-}
-
-void launch_spmv_real(const int64_t* rowptr, const int32_t* col, const double* val, int rows, const double* x,
-                      double* y, int nvec, int64_t vstride, hipStream_t st) {
-  hipLaunchKernelGGL(k_spmv_real, dim3(unsigned((rows + 255) / 256), unsigned(nvec)), dim3(256), 0, st, rowptr, col,
-                     val, rows, x, y, vstride);
-}
-
 // out[i * ldo + j] = in[i * n + j] (j < n), 0 for n <= j < ldo
 template <typename T>
 __global__ void k_repack(const double* in, int n, T* out, int64_t ldo) {
@@ -2112,29 +2061,4 @@ template void launch_repack<float>(const double*, int, float*, int64_t, hipStrea
 
 }  // namespace pmchwt
 
-namespace pmchwt {
-// y_q = y_q + s * a_q x_q, a_q real per vector (complex vectors of length n, stride)
-__global__ void k_axpy_vec(double* y, const double* x, int64_t stride, int n, const double* a, double s) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (k >= 2 * int64_t(n)) return;
-  y[2 * int64_t(q) * stride + k] += s * a[q] * x[2 * int64_t(q) * stride + k];
-}
-// p_q = z_q + b_q p_q
-__global__ void k_xpby_vec(double* p, const double* z, int64_t stride, int n, const double* b) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (k >= 2 * int64_t(n)) return;
-  const int64_t o = 2 * int64_t(q) * stride + k;
-  p[o] = z[o] + b[q] * p[o];
-}
-void launch_axpy_vec(double* y, const double* x, int64_t stride, int n, int nvec, const double* a, double s,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_vec, dim3(unsigned((2 * int64_t(n) + 255) / 256), nvec), dim3(256), 0, st, y, x, stride,
-                     n, a, s);
-}
-void launch_xpby_vec(double* p, const double* z, int64_t stride, int n, int nvec, const double* b, hipStream_t st) {
-  hipLaunchKernelGGL(k_xpby_vec, dim3(unsigned((2 * int64_t(n) + 255) / 256), nvec), dim3(256), 0, st, p, z, stride,
-                     n, b);
-}
-}  // namespace pmchwt
+
