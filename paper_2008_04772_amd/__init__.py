@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpmchwt.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libpmchwt.so is not built; run `python -m paper_2008_04772_amd.build` "
+        "libpmchwt.so is not built; run `python paper_2008_04772_amd/build.py` "
         "(or __graft_entry__.build()) first")
 
 _lib = ctypes.CDLL(LIB_PATH)

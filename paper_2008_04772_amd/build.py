@@ -1,6 +1,6 @@
 """Build libpmchwt.so (HIP, gfx950) in place.
 
-    python -m paper_2008_04772_amd.build      # or build() from Python
+    python paper_2008_04772_amd/build.py      # or __graft_entry__.build()
 
 Compiles the device translation unit and the host sources with hipcc and
 links them against rocSOLVER / rocBLAS.  Every call rebuilds.
