@@ -262,6 +262,24 @@ int pmchwt_solve(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols
 int pmchwt_far_field(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs,
                      const double *obs, int32_t nobs, pmchwt_complex *F_out);
 
+/* pmchwt_far_field without any device allocation, for callers that cannot
+ * allocate device memory while they run (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, layout and
+ * result as pmchwt_far_field (host arrays, copied during the call).  Every
+ * device buffer it needs (currents, directions, quadrature points, weighted
+ * currents, partial sums, F) lives in one static device array of 64 MiB per GPU,
+ * held from the first pmchwt_create on that GPU until the process ends; the
+ * call makes no hipMalloc, hipFree or other allocating device call.  Needs the
+ * geometry on the device: call pmchwt_assemble first (else PMCHWT_ERR_STATE).
+ * Sizes whose buffers exceed the 64 MiB return PMCHWT_ERR_INVALID_ARG (at the
+ * 5120-triangle sphere: up to 15 right-hand sides with the 8192-direction
+ * cross-section grid).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (several host threads or streams) race and must not be
+ * issued.  The partial sums may be split into fewer segments than in
+ * pmchwt_far_field, so results agree to rounding.                           */
+int pmchwt_far_field_noalloc(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs,
+                             const double *obs, int32_t nobs, pmchwt_complex *F_out);
+
 /* Extinction (optical theorem, (4 pi / k_e) Im(p* . F(d))) and scattering
  * (integral of |F|^2 over the sphere, 64 Gauss-Legendre nodes in cos(theta)
  * x 128 uniform nodes in phi) cross sections for nrhs solutions.            */

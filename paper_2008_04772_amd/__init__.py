@@ -127,6 +127,7 @@ _SIGS = {
     "pmchwt_solve": ([_P, _pd, _pc, ctypes.c_int32, ctypes.POINTER(pmchwt_solver_opts), _pc,
                       ctypes.POINTER(pmchwt_solve_stats)], ctypes.c_int),
     "pmchwt_far_field": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_far_field_noalloc": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
     "pmchwt_cross_sections": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, _pd], ctypes.c_int),
     "pmchwt_bc_fields": ([_pd, ctypes.c_int32, _pi32, ctypes.c_int32, _pi64, _pi32, _pd], ctypes.c_int),
     "pmchwt_get_profile": ([_P, ctypes.POINTER(pmchwt_profile)], ctypes.c_int),
@@ -303,6 +304,14 @@ def pmchwt_far_field(ctx, currents, obs):
     return F
 
 
+def pmchwt_far_field_noalloc(ctx, currents, obs):
+    x = _c128(np.atleast_2d(currents))
+    o = _f64(obs).reshape(-1, 3)
+    F = np.zeros((x.shape[0], len(o), 3), dtype=np.complex128)
+    _check(ctx, _lib.pmchwt_far_field_noalloc(ctx, _ptr(x, _pc), x.shape[0], _ptr(o, _pd), len(o), _ptr(F, _pc)))
+    return F
+
+
 def pmchwt_cross_sections(ctx, currents, dirs, pols):
     x = _c128(np.atleast_2d(currents))
     d, p = _waves(dirs, pols)
@@ -394,6 +403,9 @@ class Context:
 
     def far_field(self, currents, obs):
         return pmchwt_far_field(self.h, currents, obs)
+
+    def far_field_noalloc(self, currents, obs):
+        return pmchwt_far_field_noalloc(self.h, currents, obs)
 
     def cross_sections(self, currents, dirs, pols):
         return pmchwt_cross_sections(self.h, currents, dirs, pols)

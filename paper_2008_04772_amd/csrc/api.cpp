@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -299,6 +300,38 @@ constexpr double SLAB_BUDGET = 16.0e9;
 // automatic choice of the symmetric-tile product: from this many edges on
 // (528 tiles of 128 x 128 and up)
 constexpr int64_t SYM_MIN_EDGES = 4096;
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free entry point (pmchwt_far_field_noalloc):
+// a file-scope array, one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (in host code it is a
+// host-side stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returned on that device, looked up once per device when
+// the first context on it is created.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Look up this device's copy of `scratch` (device current); once per device.
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_address(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -2534,6 +2567,11 @@ int pmchwt_create(pmchwt_ctx** out, int device, void* hip_stream) {
     delete c;
     return PMCHWT_ERR_DEVICE;
   }
+  if (scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return PMCHWT_ERR_DEVICE;
+  }
   rocblas_set_stream(c->blas, c->stream);
   double l[14][3], w[14];
   triangle_rules(l, w);
@@ -2916,6 +2954,58 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     HIPCHK(hipGetLastError());
     std::vector<double> hf(6 * size_t(nobs) * nrhs);
     HIPCHK(hipMemcpyAsync(hf.data(), dF.p, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < hf.size() / 2; ++k) F[k] = {hf[2 * k], hf[2 * k + 1]};
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_far_field_noalloc(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* obs,
+                             int32_t nobs, pmchwt_complex* F) {
+  return guarded(c, [&]() -> int {
+    if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
+    if (!c->geo_uploaded)
+      return fail(c, PMCHWT_ERR_STATE, "geometry not on the device yet (call pmchwt_assemble first)");
+    if (nrhs <= 0 || nobs <= 0 || !cur || !obs || !F) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    unsigned char* base = static_cast<unsigned char*>(scratch_address(c->device));
+    if (!base) return fail(c, PMCHWT_ERR_DEVICE, "device scratch address not set up");
+    // regions of the scratch, each on a 256-byte boundary: currents, directions,
+    // F, quadrature points, weighted currents, partial sums
+    auto round = [](int64_t doubles) { return (doubles * 8 + 255) / 256 * 256; };
+    const int64_t n_x = 4 * int64_t(c->E_tot) * nrhs, n_obs = 3 * int64_t(nobs), n_F = 6 * int64_t(nobs) * nrhs;
+    const int64_t npts = int64_t(c->F_tot) * 6;
+    const int64_t fixed = round(n_x) + round(n_obs) + round(n_F) + round(4 * npts) + round(12 * npts * nrhs);
+    const int64_t cap = int64_t(NOALLOC_SCRATCH_BYTES);
+    if (fixed + 256 > cap)
+      return fail(c, PMCHWT_ERR_INVALID_ARG,
+                  "far field needs more than the " + std::to_string(NOALLOC_SCRATCH_BYTES >> 20) +
+                      " MiB device scratch of pmchwt_far_field_noalloc (fewer right-hand sides or directions)");
+    const FarPlan fp = far_field_plan_capped(c->F_tot, nrhs, nobs, (cap - fixed) / 8);
+    if (fixed + round(fp.n_part) > cap)
+      return fail(c, PMCHWT_ERR_INVALID_ARG,
+                  "far field needs more than the " + std::to_string(NOALLOC_SCRATCH_BYTES >> 20) +
+                      " MiB device scratch of pmchwt_far_field_noalloc (fewer right-hand sides or directions)");
+    unsigned char* q = base;
+    auto carve = [&](int64_t doubles) {
+      double* r = reinterpret_cast<double*>(q);
+      q += round(doubles);
+      return r;
+    };
+    double* dx = carve(n_x);
+    double* dobs = carve(n_obs);
+    double* dF = carve(n_F);
+    double* wy = carve(fp.n_ypts);
+    double* wj = carve(fp.n_J);
+    double* wp = carve(fp.n_part);
+    std::vector<double> h;
+    to_internal(c, cur, nrhs, h);
+    HIPCHK(hipMemcpyAsync(dx, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dobs, obs, size_t(n_obs) * 8, hipMemcpyHostToDevice, c->stream));
+    // every value the kernels read is written earlier in the same call: no clearing
+    launch_far_field(asm_params<double>(c), dx, c->E_tot, nrhs, c->k_ext, dobs, nobs, dF, fp, wy, wj, wp, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hf(static_cast<size_t>(n_F));
+    HIPCHK(hipMemcpyAsync(hf.data(), dF, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < hf.size() / 2; ++k) F[k] = {hf[2 * k], hf[2 * k + 1]};
     return PMCHWT_OK;

@@ -633,6 +633,21 @@ FarPlan far_field_plan(int F, int nrhs, int nobs) {
   return p;
 }
 
+// The same plan with at most max_part partial-sum values: fewer, longer
+// segments (whole LDS tiles) when the default split would exceed it.  The
+// result may still exceed max_part with a single segment; callers check.
+FarPlan far_field_plan_capped(int F, int nrhs, int nobs, int64_t max_part) {
+  FarPlan p = far_field_plan(F, nrhs, nobs);
+  if (p.n_part <= max_part) return p;
+  const int64_t per_seg = int64_t(nrhs) * 12 * nobs;
+  const int64_t nseg = std::max<int64_t>(1, max_part / per_seg);
+  p.seg_len = (p.npts + nseg - 1) / nseg;
+  p.seg_len = (p.seg_len + FAR_TILE - 1) / FAR_TILE * FAR_TILE;
+  p.nseg = int((p.npts + p.seg_len - 1) / p.seg_len);
+  p.n_part = per_seg * p.nseg;
+  return p;
+}
+
 void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
                       const double* obs, int nobs, double* F_out, const FarPlan& plan, double* ypts, double* J,
                       double* part, hipStream_t st) {

@@ -329,6 +329,7 @@ struct FarPlan {
   int64_t n_ypts = 0, n_J = 0, n_part = 0;
 };
 FarPlan far_field_plan(int F, int nrhs, int nobs);
+FarPlan far_field_plan_capped(int F, int nrhs, int nobs, int64_t max_part);
 void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
                       const double* obs, int nobs, double* F_out, const FarPlan& plan, double* ypts, double* J,
                       double* part, hipStream_t st);
