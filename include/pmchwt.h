@@ -129,7 +129,11 @@ typedef struct {
  *   restart  : rho, Krylov vectors per cycle (1..1024)
  *   max_iter : total iteration cap
  *   ir_max   : outer iterative-refinement steps with an FP64 residual
- *              b - A x (0 = none)                                          */
+ *              b - A x (0 = none).  With an A assembled in MIXED precision
+ *              and ir_max > 0 the solve targets the FP64 system: the right-
+ *              hand side's interior product and every residual use the
+ *              matrix-free FP64 product of pmchwt_apply (which = 2, 3), and
+ *              GMRES on the FP32 operators solves the correction equations. */
 typedef struct {
   double tol;
   int32_t restart;
@@ -188,6 +192,10 @@ typedef struct {
                                 correction kernel of the timed launches
                                 (ms_matvec_total counts the tile kernel alone)    */
   int64_t matvec_timed;      /* GEMV launches whose time is in ms_matvec_total       */
+  double ms_free_apply;      /* matrix-free FP64 products of a MIXED solve with
+                                refinement: the FP64 right-hand side and the
+                                refinement residuals                             */
+  int64_t free_launches;
 } pmchwt_profile;
 
 /* Version string of the library. */
@@ -244,7 +252,10 @@ int pmchwt_rhs(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols, 
                pmchwt_complex *b_out);
 
 /* y = Op x for nrhs vectors of length N.  which = 0: A, 1: the preconditioned
- * product M_P^-1 P M_A^-1 A (A alone for P = I).                              */
+ * product M_P^-1 P M_A^-1 A (A alone for P = I), 2: A and 3: A^i (the
+ * interior blocks of Section 2) with every entry integrated again in FP64 and
+ * applied without storing it (the product of the FP64 Galerkin matrix also
+ * when A is stored in FP32; it refines MIXED solves).                        */
 int pmchwt_apply(pmchwt_ctx *ctx, int32_t which, const pmchwt_complex *x, int32_t nrhs,
                  pmchwt_complex *y);
 

@@ -248,7 +248,14 @@ struct pmchwt_ctx {
     DBuf pairs, tab[4];
     int npts[4] = {0, 0, 0, 0};
     int64_t npairs = 0, point_pairs = 0;
+    // pairs of each test triangle (the list is sorted by it) and the slot of
+    // T+ / T- of every union edge: tables of the matrix-free FP64 product
+    DBuf ptr, edge_slots;
+    // FP64 local blocks of the singular pairs (MIXED A only; the FP64
+    // product reads them)
+    DBuf blk;
   } sing;
+  DBuf free_slots;  // pass-1 output of the matrix-free FP64 product
   bool cells_valid = false;
   CellDev cells;
   std::vector<std::pair<int, int>> slabs;
@@ -820,6 +827,18 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
       }
     c->sing.pairs = upload(c, pairs);
     c->sing.npairs = int64_t(pairs.size() / 2);
+    std::vector<int64_t> sptr(size_t(c->F_tot) + 1, 0);
+    for (size_t q = 0; q < pairs.size() / 2; ++q) ++sptr[size_t(pairs[2 * q]) + 1];
+    for (int t = 0; t < c->F_tot; ++t) sptr[t + 1] += sptr[t];
+    c->sing.ptr = upload(c, sptr);
+    std::vector<int32_t> eslot(2 * size_t(c->E_tot), 0);
+    for (auto& sc : c->sc)
+      for (int f = 0; f < sc.topo.F; ++f)
+        for (int a = 0; a < 3; ++a) {
+          const int e = sc.edge_off + sc.topo.t2e[3 * f + a];
+          eslot[2 * size_t(e) + (sc.topo.sgn[3 * f + a] > 0 ? 0 : 1)] = 3 * (sc.tri_off + f) + a;
+        }
+    c->sing.edge_slots = upload(c, eslot);
     c->sing.point_pairs = npts_sing;
     for (int k = 1; k <= 3; ++k) {
       c->sing.tab[k] = std::move(ss.tab[k]);
@@ -1012,6 +1031,9 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   c->prof.ms_assemble_regular = ms_pass1;
   c->prof.ms_regular_combine = ms_pass2;
   c->prof.regular_launches = int(slabs.size());
+  // the FP64 singular blocks, kept for the matrix-free FP64 product
+  realloc_c<double>(c, c->sing.blk, size_t(std::max<int64_t>(c->sing.npairs, 1)) * 72);
+  sp_.blk = c->sing.blk.as<double>();
   {
     EvTimer t(c->stream);
     launch_singular<M>(p, sp_, c->stream);
@@ -1955,6 +1977,40 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   c->prof.matvec_bytes += bytes * (c->precA == PMCHWT_FP64 ? 16 : 8);
 }
 
+// y = A x (use_ext) or y = A^i x with every entry integrated again in FP64
+// (y overwritten): the product with the FP64 Galerkin matrix when the stored
+// operators are FP32.  Counts as one operator application.
+void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_ext) {
+  if (!c->sing.blk.p) throw Fail{PMCHWT_ERR_STATE, "A not assembled"};
+  const int64_t vs = vlen(c);
+  const size_t need = size_t(nrhs) * 3 * size_t(c->F_tot) * 4;
+  if (c->free_slots.bytes < need * 8) realloc_c<double>(c, c->free_slots, need);
+  AsmParams<double> p = asm_params<double>(c);
+  p.q_near = c->optA.q_near;
+  p.q_medium = c->optA.q_medium;
+  p.q_far = c->optA.q_far;
+  FreeJob f{};
+  f.use_ext = use_ext ? 1 : 0;
+  f.nrhs = nrhs;
+  f.E_tot = c->E_tot;
+  f.vs = vs;
+  f.x = x;
+  f.sing_ptr = c->sing.ptr.as<int64_t>();
+  f.sing_pairs = c->sing.pairs.as<int32_t>();
+  f.sing_blk = c->sing.blk.as<double>();
+  f.slots = c->free_slots.as<double>();
+  f.edge_slots = c->sing.edge_slots.as<int32_t>();
+  f.y = y;
+  {
+    LazyTimer t(c, true);
+    launch_free_apply(p, f, c->stream);
+    HIPCHK(hipGetLastError());
+    t.stop(&c->prof.ms_free_apply);
+  }
+  c->prof.free_launches += 1;
+  if (use_ext) c->calls_A += 1;
+}
+
 // z = M_P^-1 P M_A^-1 y  (z overwritten; tmp: 2 vectors of scratch)
 void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double* t2, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -2061,7 +2117,8 @@ void gram_cg(pmchwt_ctx* c, const int64_t* rowptr, int n, const double* b_in, do
 }
 
 // Galerkin right-hand side into device buffer b (internal layout)
-void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b) {
+void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b,
+               bool fp64_interior = false) {
   const int64_t E = c->E_tot, vs = vlen(c);
   std::vector<double> hp(6 * size_t(nrhs));
   for (int r = 0; r < nrhs; ++r)
@@ -2096,8 +2153,12 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
             cinc.as<double>() + 2 * int64_t(s.edge_off), E, nvec);
   }
   // b = g/2 - A^i c_inc
-  launch_zero(t.as<double>(), 2 * vs * nrhs, c->stream);
-  for (size_t m = 0; m < c->sc.size(); ++m) {
+  if (fp64_interior) {
+    apply_A_free(c, cinc.as<double>(), t.as<double>(), nrhs, false);
+  } else {
+    launch_zero(t.as<double>(), 2 * vs * nrhs, c->stream);
+  }
+  for (size_t m = 0; m < c->sc.size() && !fp64_interior; ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
     const double* x = cinc.as<double>();
@@ -2825,7 +2886,7 @@ int pmchwt_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
 int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t nrhs, pmchwt_complex* y) {
   return guarded(c, [&]() -> int {
     if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
-    if (nrhs <= 0 || !x || !y || (which != 0 && which != 1)) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    if (nrhs <= 0 || !x || !y || which < 0 || which > 3) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
     const int64_t vs = vlen(c);
     std::vector<double> h;
     to_internal(c, x, nrhs, h);
@@ -2833,6 +2894,8 @@ int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t 
          s2 = dalloc_c<double>(c, h.size()), s3 = dalloc_c<double>(c, h.size());
     if (which == 0)
       apply_A(c, dx.as<double>(), dy.as<double>(), nrhs);
+    else if (which >= 2)
+      apply_A_free(c, dx.as<double>(), dy.as<double>(), nrhs, which == 2);
     else
       op_apply(c, dx.as<double>(), dy.as<double>(), s1.as<double>(), s2.as<double>(), s3.as<double>(), nrhs);
     HIPCHK(hipMemcpyAsync(h.data(), dy.p, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
@@ -2866,7 +2929,12 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     c->prof.mfma_launches = 0;
     c->prof.mfma_flops = 0;
     c->prof.lookahead_discarded = 0;
-    build_rhs(c, dirs, pols, nrhs, b.as<double>());
+    c->prof.ms_free_apply = 0;
+    c->prof.free_launches = 0;
+    // a MIXED operator with refinement solves the FP64 system: its right-hand
+    // side and refinement residuals use matrix-free FP64 products
+    const bool fp64_ir = c->precA == PMCHWT_MIXED && o->ir_max > 0;
+    build_rhs(c, dirs, pols, nrhs, b.as<double>(), fp64_ir);
     c->calls_A = 0;  // the right-hand side's own interior products are not solver matvecs
     c->calls_P = 0;
     // bt = Ptilde b
@@ -2880,10 +2948,16 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       it_max = std::max(it_max, g.iters[q]);
       restarts = std::max(restarts, g.restarts[q]);
     }
-    // iterative refinement: r = b - A x in FP64 accumulation, correction solve
+    // iterative refinement: r = b - A x in FP64 accumulation, then a
+    // correction solve while the preconditioned residual exceeds tol, at most
+    // ir_max corrections; with refinement the final convergence flag and
+    // residual are those of this FP64 check
     int ir = 0;
-    for (; ir < o->ir_max; ++ir) {
-      apply_A(c, x.as<double>(), r.as<double>(), nrhs);
+    while (o->ir_max > 0) {
+      if (fp64_ir)
+        apply_A_free(c, x.as<double>(), r.as<double>(), nrhs, true);
+      else
+        apply_A(c, x.as<double>(), r.as<double>(), nrhs);
       launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
       apply_Ptilde(c, r.as<double>(), s1.as<double>(), s2.as<double>(), d.as<double>(), nrhs);
       std::vector<double> nr(nrhs), nb(nrhs);
@@ -2894,20 +2968,20 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       HIPCHK(hipMemcpyAsync(nb.data(), dn.as<double>() + nrhs, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       bool ok = true;
-      for (int q = 0; q < nrhs; ++q) ok &= (nr[q] <= o->tol * nb[q]);
-      mv_max += A_matvecs(c) + P_matvecs(c);
-      if (ok) break;
+      for (int q = 0; q < nrhs; ++q) {
+        const bool okq = nr[q] <= o->tol * nb[q];
+        ok &= okq;
+        g.relres[q] = nb[q] > 0 ? nr[q] / nb[q] : 0.0;
+        g.converged[q] = okq ? 1 : 0;
+      }
+      if (ok || ir == o->ir_max) break;
       HIPCHK(hipMemcpyAsync(r.p, s1.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
       GmresOut g2 = gmres(c, r.as<double>(), d.as<double>(), nrhs, o->tol, o->restart, o->max_iter);
       launch_axpby(x.as<double>(), d.as<double>(), vs, int(vs), nrhs, 1.0, 1.0, c->stream);
       int mi = 0;
-      for (int q = 0; q < nrhs; ++q) {
-        mi = std::max(mi, g2.iters[q]);
-        mv_max += (A_matvecs(c) + P_matvecs(c)) * (g2.iters[q] + g2.restarts[q]);
-        g.converged[q] = g2.converged[q];
-        g.relres[q] = g2.relres[q];
-      }
+      for (int q = 0; q < nrhs; ++q) mi = std::max(mi, g2.iters[q]);
       it_max += mi;
+      ++ir;
     }
     const double ms = tm.stop();
     flush_times(c);

@@ -382,6 +382,19 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
     const int o = p.edge_off[sc];
     add_entry(p.Si[sc], p.ld_int[sc], i - o, j - o, S);
     add_entry(p.Ci[sc], p.ld_int[sc], i - o, j - o, C);
+    if (s.blk) {
+      double* q = s.blk + 8 * (9 * pair + lane);
+      cplx<double> Se, Ce;
+      contract<double, double>(me, al1, w1, al2, w2, ke_r, 0.0, true, Se, Ce);
+      q[0] = Se.re;
+      q[1] = Se.im;
+      q[2] = Ce.re;
+      q[3] = Ce.im;
+      q[4] = S.re;
+      q[5] = S.im;
+      q[6] = C.re;
+      q[7] = C.im;
+    }
   }
 }
 

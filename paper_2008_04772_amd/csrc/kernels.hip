@@ -5,3 +5,4 @@
 #include "bc.inl"
 #include "linalg.inl"
 #include "mfma.inl"
+#include "refine.inl"

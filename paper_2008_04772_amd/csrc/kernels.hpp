@@ -63,7 +63,27 @@ struct SingParams {
   const int32_t* pairs;        // 2*npairs (t1, t2), ordered
   const double* tab[4];
   int npts[4];
+  double* blk;                 // optional FP64 local blocks: per pair, 9 (3a+b) x 4 (Se, Ce, Si, Ci) complex
 };
+
+// Matrix-free FP64 product y = A x (use_ext = 1) or y = A^i x (use_ext = 0)
+// over all scatterers; vectors [rhs][D (E_tot); N (E_tot)] complex, vs
+// complex entries apart.  Regular pairs are integrated again with the rule
+// orders of AsmParams; singular pairs read sing_blk.
+struct FreeJob {
+  int use_ext;
+  int nrhs;
+  int E_tot;
+  int64_t vs;
+  const double* x;
+  const int64_t* sing_ptr;     // F+1: singular pairs of test triangle t at [sing_ptr[t], sing_ptr[t+1])
+  const int32_t* sing_pairs;   // 2 per pair (t1, t2), sorted by t1
+  const double* sing_blk;      // SingParams::blk of the same pairs
+  double* slots;               // [rhs][3F][yD re, yD im, yN re, yN im]
+  const int32_t* edge_slots;   // 2 per union edge: slot 3t+a of T+ and of T-
+  double* y;
+};
+void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t st);
 
 // Dual cells (barycentric rings) of all scatterers.
 struct CellParams {
