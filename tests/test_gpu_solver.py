@@ -1,5 +1,6 @@
-"""GPU solver checks: Table 1 matvec accounting, preconditioner family, multi-
-scatterer parity, mixed precision with refinement, error paths."""
+"""GPU solver checks: Table 1 matvec accounting on one sphere, the small-sphere
+full Calderon case, mixed precision with refinement, error paths (the
+three-cube preconditioner family is in test_gpu_precond_family.py)."""
 
 import numpy as np
 import pytest
@@ -35,24 +36,6 @@ def test_table1_counter_single_sphere(P, kind):
     assert st.converged and st.restarts >= 1
     assert st.restarts == st.iterations // rho
     assert st.matvecs == opm.table1_matvecs(kind, 1, st.iterations, rho)
-
-
-@pytest.mark.parametrize("kind", ["D", "A", "S_INT"])
-def test_three_cubes_parity_and_counter(P, kind):
-    """Three disjoint cubes (Section 4's array, M = 3): currents against the
-    oracle's direct solve, and Table 1's count for M = 3."""
-    note(f"three cubes k_e=2.1, P = {kind}")
-    cubes = synth.three_cubes(2.1)
-    eps = 1.311 ** 2
-    ctx = make_ctx(P, cubes, eps, 2.1, qP=(4, 3, 2), nP=4, chi=-1.0, precond=kind)
-    d, p = synth.single_wave((1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
-    x, st = ctx.solve(d, p, P.solver_opts(tol=1e-11, restart=200, max_iter=1000))
-    pr = opm.Problem(cubes, eps, 2.1)
-    pr.assemble_A()
-    xr = pr.solve_direct(pr.rhs(d, p))
-    note(f"  R={st.iterations} matvecs={st.matvecs} err={rel_fro(x, xr):.2e}")
-    assert rel_fro(x, xr) < 1e-8
-    assert st.matvecs == opm.table1_matvecs(kind, 3, st.iterations, 200)
 
 
 def test_small_sphere_full_calderon(P):
