@@ -34,6 +34,7 @@ struct ServeRecord {
   // state (guarded by the server mutex)
   int status = PMCHWT_PENDING;
   bool cancel = false;
+  int skipped = 0;  // times a later request was admitted ahead of this one at the head
   double t_submit = 0, t_admit = 0, t_done = 0;
   pmchwt_solve_stats stats{};
   std::vector<pmchwt_complex> currents;
@@ -102,22 +103,27 @@ struct ServeRun {
     if (c) pmchwt_destroy(c);
   }
 
+  // MIXED operators with refinement: FP64 right-hand side and residuals
+  // (matrix-free FP64 products), as in pmchwt_solve
+  bool fp64_ir = false;
+
   void init() {
     const pmchwt_solver_opts& o = rec->so;
     vs = vlen(c);
     nd = size_t(2 * vs * nrhs);
-    b = dalloc<double>(nd);
-    bt = dalloc<double>(nd);
-    x = dalloc<double>(nd);
-    s1 = dalloc<double>(nd);
-    s2 = dalloc<double>(nd);
-    d = dalloc<double>(nd);
-    r = dalloc<double>(nd);
-    sA = dalloc<double>(nd);
+    b = dalloc_c<double>(c, nd);
+    bt = dalloc_c<double>(c, nd);
+    x = dalloc_c<double>(c, nd);
+    s1 = dalloc_c<double>(c, nd);
+    s2 = dalloc_c<double>(c, nd);
+    d = dalloc_c<double>(c, nd);
+    r = dalloc_c<double>(c, nd);
+    sA = dalloc_c<double>(c, nd);
     hn.reset(new PinnedBuf(16 * size_t(nrhs)));
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     t0 = now_ms();
-    build_rhs(c, rec->dirs.data(), rec->pols.data(), nrhs, b.as<double>());
+    fp64_ir = c->precA == PMCHWT_MIXED && o.ir_max > 0;
+    build_rhs(c, rec->dirs.data(), rec->pols.data(), nrhs, b.as<double>(), fp64_ir);
     c->calls_A = 0;
     c->calls_P = 0;
     apply_Ptilde(c, b.as<double>(), bt.as<double>(), s1.as<double>(), s2.as<double>(), nrhs);
@@ -144,7 +150,7 @@ struct ServeRun {
       ++ir;
     }
     g.reset();
-    st = ir < rec->so.ir_max ? IR_CHECK : FINISHED;
+    st = rec->so.ir_max > 0 ? IR_CHECK : FINISHED;
   }
 
   bool stepping() const { return st != FINISHED; }
@@ -188,8 +194,13 @@ struct ServeRun {
     HIPCHK(hipEventSynchronize(ev));
     const double* h = static_cast<const double*>(hn->p);
     bool ok = true;
-    for (int q = 0; q < nrhs; ++q) ok &= (h[q] <= rec->so.tol * h[nrhs + q]);
-    if (ok) {
+    for (int q = 0; q < nrhs; ++q) {
+      const bool okq = h[q] <= rec->so.tol * h[nrhs + q];
+      ok &= okq;
+      conv[q] = okq ? 1 : 0;
+      relres[q] = h[nrhs + q] > 0 ? h[q] / h[nrhs + q] : 0.0;
+    }
+    if (ok || ir == rec->so.ir_max) {
       st = FINISHED;
       return;
     }
@@ -251,15 +262,29 @@ struct pmchwt_server {
   int live_count = 0;  // admitted (assembling or in the engine)
   int64_t used = 0;
   pmchwt_server_stats st{};
-  std::thread admit_thr, engine_thr;
+  std::thread admit_thr, engine_thr, reap_thr;
   hipStream_t es = nullptr;  // engine stream (grouped launches)
-  hipEvent_t eev = nullptr;
+  struct JobStage {
+    std::unique_ptr<PinnedBuf> h;
+    DBuf d;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+  } jst[2];
+  int jcur = 0;
+  // finished or cancelled runs: copied out, their contexts destroyed and their
+  // budget released by the reaper thread (hipFree waits for the whole
+  // device, which the engine must not)
+  std::deque<std::unique_ptr<ServeRun>> reap;
+  std::condition_variable cv_reap;
   std::string err;
 
   void admit_loop();
   void engine_loop();
+  void reap_loop();
   void round(std::vector<std::unique_ptr<ServeRun>>& live);
   void complete(const std::shared_ptr<ServeRecord>& rec, int status);
+  int pick_admissible();
 };
 
 namespace {
@@ -295,6 +320,58 @@ void pmchwt_server::complete(const std::shared_ptr<ServeRecord>& rec, int status
   cv_done.notify_all();
 }
 
+// Index of the pending request to admit next, or -1 (server mutex held).
+// First fit in submission order: a later request that fits the remaining
+// budget may pass a head request that does not, until the head has been
+// passed HEAD_PASS_LIMIT times; from then on only the head is admitted, so a
+// large request is never starved.
+constexpr int HEAD_PASS_LIMIT = 8;
+int pmchwt_server::pick_admissible() {
+  if (live_count >= max_live || pending.empty()) return -1;
+  const int64_t room = int64_t(budget) - used;
+  if (pending.front()->est <= room) return 0;
+  if (pending.front()->skipped >= HEAD_PASS_LIMIT) return -1;
+  for (size_t i = 1; i < pending.size(); ++i)
+    if (!pending[i]->cancel && pending[i]->est <= room) return int(i);
+  return -1;
+}
+
+void pmchwt_server::reap_loop() {
+  (void)hipSetDevice(device);
+  while (true) {
+    std::unique_ptr<ServeRun> up;
+    {
+      std::unique_lock<std::mutex> lk(m);
+      cv_reap.wait(lk, [&] { return stop || !reap.empty(); });
+      if (reap.empty()) return;  // stopping with nothing left
+      up = std::move(reap.front());
+      reap.pop_front();
+    }
+    std::shared_ptr<ServeRecord> rec = up->rec;
+    bool cancel;
+    {
+      std::lock_guard<std::mutex> lk(m);
+      cancel = rec->cancel;
+    }
+    int status = PMCHWT_ERR_CANCELLED;
+    if (!cancel) {
+      status = guarded(up->c, [&]() -> int {
+        up->finish();
+        return rec->stats.converged ? PMCHWT_OK : PMCHWT_ERR_NOT_CONVERGED;
+      });
+    }
+    const int64_t est = rec->est;
+    up.reset();  // frees the request's device memory
+    {
+      std::lock_guard<std::mutex> lk(m);
+      live_count--;
+      used -= est;
+    }
+    complete(rec, status);
+    cv_admit.notify_all();
+  }
+}
+
 void pmchwt_server::admit_loop() {
   (void)hipSetDevice(device);
   while (true) {
@@ -303,19 +380,25 @@ void pmchwt_server::admit_loop() {
       std::unique_lock<std::mutex> lk(m);
       cv_admit.wait(lk, [&] {
         if (stop) return true;
-        while (!pending.empty() && pending.front()->cancel) {  // drop cancelled ones
-          auto p = pending.front();
-          pending.pop_front();
+        for (size_t i = 0; i < pending.size();) {  // drop cancelled ones
+          if (!pending[i]->cancel) {
+            ++i;
+            continue;
+          }
+          auto p = pending[i];
+          pending.erase(pending.begin() + i);
           p->status = PMCHWT_ERR_CANCELLED;
           p->t_done = now_ms();
           st.failed++;
           cv_done.notify_all();
         }
-        return !pending.empty() && live_count < max_live && used + pending.front()->est <= int64_t(budget);
+        return pick_admissible() >= 0;
       });
       if (stop) return;
-      rec = pending.front();
-      pending.pop_front();
+      const int pick = pick_admissible();
+      rec = pending[size_t(pick)];
+      pending.erase(pending.begin() + pick);
+      if (pick > 0) pending.front()->skipped++;
       rec->status = PMCHWT_RUNNING;
       rec->t_admit = now_ms();
       live_count++;
@@ -365,6 +448,11 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
     R.a_io(in, out);
     const int64_t E = c->E_tot, vs = R.vs;
     R.grouped = !(c->precA == PMCHWT_MIXED && R.nrhs >= MFMA_MIN_RHS);
+    if (R.st == ServeRun::IR_CHECK && R.fp64_ir) {  // FP64 refinement residual on the run's stream
+      R.grouped = false;
+      apply_A_free(c, in, out, R.nrhs, true);
+      continue;
+    }
     if (!R.grouped) {
       apply_A(c, in, out, R.nrhs);
       continue;
@@ -401,9 +489,21 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
     for (int k = 0; k < 3; ++k)
       bytes += jf.j[part][k].size() * sizeof(GemvJob<float>) + jd.j[part][k].size() * sizeof(GemvJob<double>);
   if (bytes > 0) {
-    PinnedBuf hj(bytes);
-    DBuf dj = dalloc<char>(bytes);
-    char* hp = static_cast<char*>(hj.p);
+    // the job table goes through one of two staging pairs (pinned host and
+    // device), used in alternate rounds and grown geometrically: a pair is
+    // rewritten only after the launches of its previous round have finished,
+    // which its event tells without stopping the engine stream
+    JobStage& J = jst[jcur];
+    jcur ^= 1;
+    if (J.used) HIPCHK(hipEventSynchronize(J.done));
+    if (J.cap < bytes) {
+      const size_t cap = std::max<size_t>({bytes, 2 * J.cap, size_t(64) << 10});
+      J.h.reset(new PinnedBuf(cap));
+      J.d = dalloc<char>(cap);
+      J.cap = cap;
+    }
+    DBuf& dj = J.d;
+    char* hp = static_cast<char*>(J.h->p);
     size_t off = 0;
     struct L {
       size_t off;
@@ -424,7 +524,7 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
           off += jd.j[part][k].size() * sizeof(GemvJob<double>);
         }
       }
-    HIPCHK(hipMemcpyAsync(dj.p, hj.p, bytes, hipMemcpyHostToDevice, es));
+    HIPCHK(hipMemcpyAsync(dj.p, J.h->p, bytes, hipMemcpyHostToDevice, es));
     for (int part = 0; part < 2; ++part)
       for (const L& l : ls) {
         if (l.part != part) continue;
@@ -439,11 +539,10 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
         st.grouped_launches++;
         st.grouped_jobs += l.n;
       }
-    HIPCHK(hipEventRecord(eev, es));
+    HIPCHK(hipEventRecord(J.done, es));
+    J.used = true;
     for (auto& up : live)
-      if (up->grouped) HIPCHK(hipStreamWaitEvent(up->c->stream, eev, 0));
-    // the job table and its pinned staging must outlive the launches
-    HIPCHK(hipStreamSynchronize(es));
+      if (up->grouped) HIPCHK(hipStreamWaitEvent(up->c->stream, J.done, 0));
   }
   // 3. the rest of the step, stage by stage over all runs
   for (auto& up : live) up->post_A();
@@ -475,23 +574,9 @@ void pmchwt_server::engine_loop() {
         cancel = up->rec->cancel;
       }
       if (cancel || !up->stepping()) {
-        int status = PMCHWT_ERR_CANCELLED;
-        std::shared_ptr<ServeRecord> rec = up->rec;
-        if (!cancel) {
-          status = guarded(up->c, [&]() -> int {
-            up->finish();
-            return rec->stats.converged ? PMCHWT_OK : PMCHWT_ERR_NOT_CONVERGED;
-          });
-        }
-        const int64_t est = rec->est;
-        up.reset();  // frees the request's device memory
-        {
-          std::lock_guard<std::mutex> lk(m);
-          live_count--;
-          used -= est;
-        }
-        complete(rec, status);
-        cv_admit.notify_all();
+        std::lock_guard<std::mutex> lk(m);
+        reap.push_back(std::move(up));
+        cv_reap.notify_all();
       } else {
         keep.push_back(std::move(up));
       }
@@ -535,12 +620,16 @@ int pmchwt_server_create(pmchwt_server** out, int device, const pmchwt_server_op
   s->budget = opts->hbm_budget_bytes;
   s->max_live = opts->max_live;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&s->es, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->eev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&s->jst[0].done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->jst[1].done, hipEventDisableTiming) != hipSuccess) {
+    if (s->jst[0].done) (void)hipEventDestroy(s->jst[0].done);
+    if (s->es) (void)hipStreamDestroy(s->es);
     delete s;
     return PMCHWT_ERR_DEVICE;
   }
   s->admit_thr = std::thread([s] { s->admit_loop(); });
   s->engine_thr = std::thread([s] { s->engine_loop(); });
+  s->reap_thr = std::thread([s] { s->reap_loop(); });
   *out = s;
   return PMCHWT_OK;
 }
@@ -666,8 +755,16 @@ void pmchwt_server_destroy(pmchwt_server* s) {
   s->cv_engine.notify_all();
   if (s->admit_thr.joinable()) s->admit_thr.join();
   if (s->engine_thr.joinable()) s->engine_thr.join();
+  s->cv_reap.notify_all();
+  if (s->reap_thr.joinable()) s->reap_thr.join();  // drains the runs handed over before the stop
+  s->reap.clear();  // any run handed over after the reaper ended
   s->ready.clear();
-  if (s->eev) (void)hipEventDestroy(s->eev);
+  if (s->es) (void)hipStreamSynchronize(s->es);
+  for (auto& J : s->jst) {
+    J.h.reset();
+    J.d = DBuf();
+    if (J.done) (void)hipEventDestroy(J.done);
+  }
   if (s->es) (void)hipStreamDestroy(s->es);
   delete s;
 }
