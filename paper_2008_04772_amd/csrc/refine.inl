@@ -48,8 +48,10 @@ __device__ __forceinline__ void apply_block(cplx<double> (&acc)[RC][3][2], int a
 }
 
 template <int RC>
-__global__ __launch_bounds__(FREE_THREADS) void k_free_apply(AsmParams<double> p, FreeJob f) {
+__global__ __launch_bounds__(FREE_THREADS, 2) void k_free_apply(AsmParams<double> p, FreeJob f) {
   __shared__ double red[FREE_THREADS / WAVE][RC * 12];
+  __shared__ double s_t1[3][4];  // per test basis a of t1: alpha, w (RT0 field alpha x - w)
+  __shared__ double s_x[14][4];  // points of every triangle rule on t1 (relative to its centroid), weight x A1
   const int t1 = blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int F = p.F;
@@ -58,28 +60,30 @@ __global__ __launch_bounds__(FREE_THREADS) void k_free_apply(AsmParams<double> p
 #pragma unroll
   for (int d = 0; d < 3; ++d) c1[d] = p.tcen[d * F + t1];
   int va[3];
-  double P1[3][3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    va[k] = p.tvid[k * F + t1];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) P1[k][d] = p.tv[(3 * k + d) * F + t1] - c1[d];
-  }
+  for (int k = 0; k < 3; ++k) va[k] = p.tvid[k * F + t1];
   const double A1 = p.tarea[t1], d1 = p.tdiam2[t1];
-  double al1[3], w1[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    al1[a] = p.tsgn[a * F + t1] / (2.0 * A1);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) w1[a][d] = al1[a] * P1[a][d];
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    const double al = p.tsgn[a * F + t1] / (2.0 * A1);
+    s_t1[a][0] = al;
+    for (int d = 0; d < 3; ++d) s_t1[a][1 + d] = al * (p.tv[(3 * a + d) * F + t1] - c1[d]);
+  } else if (threadIdx.x >= 32 && threadIdx.x < 46) {
+    const int i = threadIdx.x - 32;
+    for (int d = 0; d < 3; ++d) {
+      double x = 0.0;
+      for (int k = 0; k < 3; ++k) x += c_rule_l[i][k] * (p.tv[(3 * k + d) * F + t1] - c1[d]);
+      s_x[i][d] = x;
+    }
+    s_x[i][3] = c_rule_w[i] * A1;
   }
+  __syncthreads();
   const double ke = p.k_ext;
   const double kir = p.k_int[2 * s1], kii = p.k_int[2 * s1 + 1];
   // combination factors: 1/k and -k for the exterior and interior wavenumbers
   const cplx<double> fe1 = {1.0 / ke, 0.0}, fe2 = {-ke, 0.0};
   const double kim2 = kir * kir + kii * kii;
   const cplx<double> fi1 = {kir / kim2, -kii / kim2}, fi2 = {-kir, -kii};
-  const bool decay_i = kii != 0.0;
 
   cplx<double> acc[RC][3][2];
 #pragma unroll
@@ -88,50 +92,38 @@ __global__ __launch_bounds__(FREE_THREADS) void k_free_apply(AsmParams<double> p
     for (int a = 0; a < 3; ++a) acc[r][a][0] = acc[r][a][1] = {0.0, 0.0};
   const int nr = min(RC, f.nrhs - r0);
 
-  for (int t2 = threadIdx.x; t2 < F; t2 += FREE_THREADS) {
-    const bool inner = p.tscat[t2] == s1;
-    if (!f.use_ext && !inner) continue;
-    bool shared = false;
+  // one wavenumber per sweep over the trial triangles: only one set of
+  // moments and the accumulators stay live
+  for (int kk = f.use_ext ? 0 : 1; kk < 2; ++kk) {
+    const double kr = kk == 0 ? ke : kir, ki = kk == 0 ? 0.0 : kii;
+    const bool decay = kk == 1 && kii != 0.0;
+    const double ik2 = 1.0 / (kr * kr + ki * ki);
+    const cplx<double> g1 = kk == 0 ? fe1 : fi1, g2 = kk == 0 ? fe2 : fi2;
+    for (int t2 = threadIdx.x; t2 < F; t2 += FREE_THREADS) {
+      if (kk == 1 && p.tscat[t2] != s1) continue;  // interior operators: one scatterer
+      bool shared = false;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int vb = p.tvid[k * F + t2];
-      shared |= (vb == va[0]) | (vb == va[1]) | (vb == va[2]);
-    }
-    if (shared) continue;  // singular pair: read below from the FP64 blocks
-    double c2[3];
+      for (int k = 0; k < 3; ++k) {
+        const int vb = p.tvid[k * F + t2];
+        shared |= (vb == va[0]) | (vb == va[1]) | (vb == va[2]);
+      }
+      if (shared) continue;  // singular pair: read below from the FP64 blocks
+      const int cls = classify_pair(c1[0], c1[1], c1[2], p.tcen[t2], p.tcen[F + t2], p.tcen[2 * F + t2], d1,
+                                    p.tdiam2[t2]);
+      const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
+      const int off = c_rule_off[q], n = c_rule_n[q];
+      double P2[3][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) c2[d] = p.tcen[d * F + t2];
-    const int cls = classify_pair(c1[0], c1[1], c1[2], c2[0], c2[1], c2[2], d1, p.tdiam2[t2]);
-    const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
-    const int off = c_rule_off[q], n = c_rule_n[q];
-    double P2[3][3];
+      for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) P2[k][d] = p.tv[(3 * k + d) * F + t2] - c1[d];
-    const double A2 = p.tarea[t2];
-    const double AA = A1 * A2;
-    double al2[3], w2[3][3];
-    int jb[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      al2[b] = p.tsgn[b * F + t2] / (2.0 * A2);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) w2[b][d] = al2[b] * P2[b][d];
-      jb[b] = p.t2e[b * F + t2];
-    }
-    for (int kk = f.use_ext ? 0 : 1; kk < (inner ? 2 : 1); ++kk) {
-      const double kr = kk == 0 ? ke : kir, ki = kk == 0 ? 0.0 : kii;
-      const bool decay = kk == 0 ? false : decay_i;
+        for (int d = 0; d < 3; ++d) P2[k][d] = p.tv[(3 * k + d) * F + t2] - c1[d];
+      const double A2 = p.tarea[t2];
       Moments<double> mm;
       mm.zero();
 #pragma unroll 1
       for (int a = 0; a < n; ++a) {
-        double x[3];
-        const double la0 = c_rule_l[off + a][0], la1 = c_rule_l[off + a][1], la2 = c_rule_l[off + a][2];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] = la0 * P1[0][d] + la1 * P1[1][d] + la2 * P1[2][d];
-        const double wa = c_rule_w[off + a] * AA;
+        const double x[3] = {s_x[off + a][0], s_x[off + a][1], s_x[off + a][2]};
+        const double wa = s_x[off + a][3] * A2;
 #pragma unroll 1
         for (int b = 0; b < n; ++b) {
           double y[3];
@@ -144,21 +136,69 @@ __global__ __launch_bounds__(FREE_THREADS) void k_free_apply(AsmParams<double> p
           mm.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, true);
         }
       }
-      const cplx<double> g1 = kk == 0 ? fe1 : fi1, g2 = kk == 0 ? fe2 : fi2;
-#pragma unroll
+      // contraction against the RT0 fields of both triangles, one trial basis
+      // b at a time (its b-only terms once, then the three test bases):
+      //   Sv = a1 a2 Mxy - a1 (w2.Mx) - a2 (w1.My) + (w1.w2) M0,  Sd = 4 a1 a2 M0,
+      //   S = -ik Sv - Sd/(ik),  C = -[a1 (w2.Nx) - a2 (w1.Nx) + w1.(Nd x w2)]
+#pragma unroll 1
       for (int b = 0; b < 3; ++b) {
-        cplx<double> xD[RC], xN[RC];
+        const int jb = p.t2e[b * F + t2];
+        const double al2 = p.tsgn[b * F + t2] / (2.0 * A2);
+        double w2[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) w2[d] = al2 * (p.tv[(3 * b + d) * F + t2] - c1[d]);
+        cplx<double> Pb = {0, 0}, Qb = {0, 0}, Rb[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          Pb.re += w2[d] * mm.Mx[d].re;
+          Pb.im += w2[d] * mm.Mx[d].im;
+          Qb.re += w2[d] * mm.Nx[d].re;
+          Qb.im += w2[d] * mm.Nx[d].im;
+        }
+        Rb[0] = {mm.Nd[1].re * w2[2] - mm.Nd[2].re * w2[1], mm.Nd[1].im * w2[2] - mm.Nd[2].im * w2[1]};
+        Rb[1] = {mm.Nd[2].re * w2[0] - mm.Nd[0].re * w2[2], mm.Nd[2].im * w2[0] - mm.Nd[0].im * w2[2]};
+        Rb[2] = {mm.Nd[0].re * w2[1] - mm.Nd[1].re * w2[0], mm.Nd[0].im * w2[1] - mm.Nd[1].im * w2[0]};
+        cplx<double> gxN[RC], gxD[RC], xD[RC], xN[RC];
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
           const double* xr = f.x + 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
-          xD[r] = {xr[2 * jb[b]], xr[2 * jb[b] + 1]};
-          xN[r] = {xr[2 * (f.E_tot + jb[b])], xr[2 * (f.E_tot + jb[b]) + 1]};
+          xD[r] = {xr[2 * jb], xr[2 * jb + 1]};
+          xN[r] = {xr[2 * (f.E_tot + jb)], xr[2 * (f.E_tot + jb) + 1]};
+          gxN[r] = cmul(g1, xN[r]);
+          gxD[r] = cmul(g2, xD[r]);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          cplx<double> S, C;
-          contract<double, double>(mm, al1[a], w1[a], al2[b], w2[b], kr, ki, true, S, C);
-          apply_block<RC>(acc, a, S, C, g1, g2, xD, xN);
+          const double al1 = s_t1[a][0];
+          const double w1[3] = {s_t1[a][1], s_t1[a][2], s_t1[a][3]};
+          cplx<double> Ua = {0, 0}, Va = {0, 0}, wR = {0, 0};
+          double ww = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            Ua.re += w1[d] * mm.My[d].re;
+            Ua.im += w1[d] * mm.My[d].im;
+            Va.re += w1[d] * mm.Nx[d].re;
+            Va.im += w1[d] * mm.Nx[d].im;
+            wR.re += w1[d] * Rb[d].re;
+            wR.im += w1[d] * Rb[d].im;
+            ww += w1[d] * w2[d];
+          }
+          const double aa = al1 * al2;
+          const double sv_re = aa * mm.Mxy.re - al1 * Pb.re - al2 * Ua.re + ww * mm.M0.re;
+          const double sv_im = aa * mm.Mxy.im - al1 * Pb.im - al2 * Ua.im + ww * mm.M0.im;
+          const double sd_re = 4.0 * aa * mm.M0.re, sd_im = 4.0 * aa * mm.M0.im;
+          const double t_re = (sd_re * kr + sd_im * ki) * ik2, t_im = (sd_im * kr - sd_re * ki) * ik2;
+          const cplx<double> S = {ki * sv_re + kr * sv_im - t_im, ki * sv_im - kr * sv_re + t_re};
+          const cplx<double> C = {-(al1 * Qb.re - al2 * Va.re + wR.re), -(al1 * Qb.im - al2 * Va.im + wR.im)};
+#pragma unroll
+          for (int r = 0; r < RC; ++r) {
+            const cplx<double> a1 = cmul(C, xD[r]), a2 = cmul(S, gxN[r]);
+            const cplx<double> b1 = cmul(C, xN[r]), b2 = cmul(S, gxD[r]);
+            acc[r][a][0].re += a1.re + a2.re;
+            acc[r][a][0].im += a1.im + a2.im;
+            acc[r][a][1].re += b1.re + b2.re;
+            acc[r][a][1].im += b1.im + b2.im;
+          }
         }
       }
     }
