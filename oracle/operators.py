@@ -133,12 +133,21 @@ def local_blocks(topo, t1, t2, rel, k, q=(4, 3, 2), n_sing=4, want=("S", "C")):
 
 def assemble_rwg(topo, k, q=(4, 3, 2), n_sing=4, want=("S", "C"), chunk=48):
     """Dense Galerkin matrices (E x E) of S and/or C on the RWG space of ``topo``."""
+    return assemble_rwg_tests(topo, k, 0, topo.F, q, n_sing, want, chunk)
+
+
+def assemble_rwg_tests(topo, k, t_begin, t_end, q=(4, 3, 2), n_sing=4, want=("S", "C"), chunk=48):
+    """The part of the dense matrices that test triangles t_begin..t_end-1
+    contribute (every trial triangle): summed over a partition of the test
+    triangles these give assemble_rwg's matrices (up to the order of the
+    additions), which lets a caller spread the assembly over processes."""
     E, F = topo.E, topo.F
     out = {op: np.zeros((E, E), dtype=np.complex128) for op in want}
     geom = _tri_geom(topo)
-    for s0 in range(0, F, chunk):
-        t1 = np.repeat(np.arange(s0, min(F, s0 + chunk)), F)
-        t2 = np.tile(np.arange(F), min(F, s0 + chunk) - s0)
+    for s0 in range(t_begin, t_end, chunk):
+        s1 = min(t_end, s0 + chunk)
+        t1 = np.repeat(np.arange(s0, s1), F)
+        t2 = np.tile(np.arange(F), s1 - s0)
         _accumulate(topo, t1, t2, k, q, n_sing, want, out, geom)
     return out
 

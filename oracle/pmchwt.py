@@ -77,12 +77,16 @@ class Problem:
         self.N = 2 * int(self.offs[-1])
 
     # ---- Galerkin matrices --------------------------------------------------
-    def assemble_A(self):
-        ext = ops.assemble_rwg(self.union, self.k_e, self.qA, self.nA)
+    def assemble_A(self, assemble=None):
+        """A = A^e + A^i (Section 2).  ``assemble`` replaces ops.assemble_rwg
+        (same arguments and result), e.g. by one that spreads the same
+        quadrature sums over processes."""
+        assemble = assemble or ops.assemble_rwg
+        ext = assemble(self.union, self.k_e, self.qA, self.nA)
         self.Se, self.Ce = ext["S"], ext["C"]
         self.Si, self.Ci = [], []
         for T, k in zip(self.topos, self.k_i):
-            d = ops.assemble_rwg(T, k, self.qA, self.nA)
+            d = assemble(T, k, self.qA, self.nA)
             self.Si.append(d["S"])
             self.Ci.append(d["C"])
         A = np.zeros((self.N, self.N), dtype=np.complex128)

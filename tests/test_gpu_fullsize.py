@@ -168,3 +168,36 @@ def test_fullsize_solve_mixed_vs_fp64_and_mie(P, mesh):
     for prec in (0, 1):
         assert abs(res[prec][0] - qe) < 0.02 * qe
         assert abs(res[prec][1] - qs) < 0.02 * qs
+
+
+def _golden_sphere5120():
+    """Cross sections of the oracle's exact discrete solution at this size
+    (tests/golden/sphere5120_sigma.txt, written by tests/golden/make_sphere5120.py)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere5120_sigma.txt")
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        vals[k] = float(v)
+    return vals["sigma_ext"], vals["sigma_sca"]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fullsize_cross_sections_vs_oracle_golden(P, mesh, prec):
+    """FP64, and MIXED with FP64 refinement, solved to 1e-10 on the full
+    benchmark problem: cross sections against the oracle's exact discrete
+    solution to 1e-8 (refinement makes the mixed form solve the FP64 system)."""
+    se_o, ss_o = _golden_sphere5120()
+    note(f"full-size cross sections vs the oracle's golden values, precision={prec}")
+    d, p = synth.single_wave()
+    ctx = _ctx(P, mesh, prec)
+    so = P.solver_opts(tol=1e-10, restart=200, max_iter=3000, ir_max=4 if prec else 0)
+    x, st = ctx.solve(d, p, so)
+    se, ss = ctx.cross_sections(x, d, p)
+    e1, e2 = abs(se[0] - se_o) / se_o, abs(ss[0] - ss_o) / ss_o
+    note(f"  iters {st.iterations} ir {st.ir_steps}: sigma_ext {se[0]:.12f} (oracle {se_o:.12f}) rel {e1:.2e}; "
+         f"sigma_sca {ss[0]:.12f} (oracle {ss_o:.12f}) rel {e2:.2e}")
+    assert st.converged
+    assert e1 < 1e-8 and e2 < 1e-8
