@@ -98,16 +98,23 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *   precision : PMCHWT_FP64, or PMCHWT_MIXED.  For A: disjoint pairs and
  *       operator storage in FP32, singular pairs in FP64.  For P: MIXED
  *       integrates the near-field BC entries in FP32 (pair classification in
- *       FP64, entries stored in FP64) and computes and stores the inverted
- *       mass matrices M_A^-1 and M_A^-T in FP32 (a Chebyshev iteration on
- *       the sparse M_A, stopped at ||I - X M_A||_F / sqrt(n) <= 1e-6, else
- *       Gauss-Jordan with its rank updates on the matrix cores); products
- *       with fewer than 16 right-hand sides read a copy without the entries
- *       below 2^-27 of their row's largest.  All of this only perturbs the
+ *       FP64, entries stored in FP64) and stores the inverted mass matrices
+ *       M_A^-1 and M_A^-T in FP32.  All of this only perturbs the
  *       preconditioner, not the system that is solved.
- *   mass_method : for P with MIXED precision, 0 = the Chebyshev iteration
- *       with the Gauss-Jordan fall-back, 1 = Gauss-Jordan only.  Ignored
- *       otherwise; zero-initialised structs get 0.
+ *   mass_method : how P's products apply M_A^-1 and M_A^-T (Section 3.2).
+ *       0 = dense inverse: MIXED by a Chebyshev iteration on the sparse M_A,
+ *       stopped at ||I - X M_A||_F / sqrt(n) <= 1e-6, Gauss-Jordan if it does
+ *       not get there; FP64 by Gauss-Jordan (rank updates on the matrix
+ *       cores).  1 = dense Gauss-Jordan inverse.  2 = sparse inverse: row i
+ *       of the inverse on the columns within a fixed number of steps of
+ *       M_A's sparsity graph (8 for MIXED, 16 for FP64), by a Chebyshev
+ *       iteration on the spectrum interval [0.3, 1.05] (14 / 28 steps;
+ *       entries within about 1e-7 / 1e-13 of the row maximum); a dense
+ *       inverse replaces it if a row's column set exceeds 1024 / 2048.
+ *       Dense inverses are read through a
+ *       truncated CSR copy (entries below 2^-27 (MIXED) or 2^-52 (FP64, kept
+ *       if under 40% dense) of their row's largest dropped) by products with
+ *       fewer than 16 right-hand sides.  Zero-initialised structs get 0.
  *   operator_form : for A of a single scatterer, how products with one or
  *       two right-hand sides read it.  0 = automatic (symmetric tiles from
  *       4096 edges on), 1 = full rows, 2 = symmetric tiles: the upper

@@ -201,8 +201,14 @@ struct pmchwt_ctx {
     int n = -1, nt = 0;
     int64_t ntiles = 0, nnz = 0;
     DBuf tij, rowptr, crow, col;
+    // per correction entry, the singular local-block entries that make it
+    // (CSR over the entries; item = block entry << 1 | negate)
+    DBuf iptr, item;
     DBuf pack, val, part;
     bool ready = false;
+    // the assembly wrote only the upper tiles of Se, Ce, Si, Ci: their lower
+    // tiles are filled by mirroring when something first reads them
+    bool lower_stale[4] = {false, false, false, false};
   } sym;
   pmchwt_assembly_opts optA{}, optP{};
   // P (near-field BC operators, CSR over union edge indices)
@@ -251,9 +257,10 @@ struct pmchwt_ctx {
     // pairs of each test triangle (the list is sorted by it) and the slot of
     // T+ / T- of every union edge: tables of the matrix-free FP64 product
     DBuf ptr, edge_slots;
-    // FP64 local blocks of the singular pairs (MIXED A only; the FP64
-    // product reads them)
+    // FP64 local blocks of the singular pairs (the matrix-free FP64 product
+    // and the symmetric-tile correction read them)
     DBuf blk;
+    std::vector<int32_t> h_pairs;  // host copy of the pair list
   } sing;
   DBuf free_slots;  // pass-1 output of the matrix-free FP64 product
   bool cells_valid = false;
@@ -265,6 +272,8 @@ struct pmchwt_ctx {
   // trial-edge chunk tables of the atomic-free regular assembly (geometry only)
   int chunk_size = 0, nchunks = 0, max_list = 0;
   DBuf chunk_e, chunk_ptr, chunk_tri, edge_map, edge_scat_d;
+  DBuf t1_tmin, ch_tmax;  // tile index bounds of triangles and chunks (upper-tile assembly)
+  std::vector<DBuf> slab_cs;  // per slab row: first column of its upper tiles
   double recompute = 0.0;
 
   // event timings of the solver's operator products, read when the solve ends
@@ -526,8 +535,8 @@ void check_opts(const pmchwt_assembly_opts* o, const char* which) {
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": n_singular must be 1..8"};
   if (o->precision != PMCHWT_FP64 && o->precision != PMCHWT_MIXED)
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": unknown precision"};
-  if (o->mass_method != 0 && o->mass_method != 1)
-    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_method must be 0 or 1"};
+  if (o->mass_method < 0 || o->mass_method > 2)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_method must be 0, 1 or 2"};
   if (o->operator_form < 0 || o->operator_form > 2)
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": operator_form must be 0, 1 or 2"};
 }
@@ -617,6 +626,28 @@ AsmParams<M> asm_params(pmchwt_ctx* c) {
   return p;
 }
 
+// Fill the lower tiles of the operators in `mask` (1 Se, 2 Ce, 4 Si, 8 Ci)
+// that an upper-tile assembly left stale (one scatterer): the mirror of the
+// upper tiles plus the singular pairs' asymmetry on the correction entries.
+void ensure_lower(pmchwt_ctx* c, int mask) {
+  const int n = c->E_tot;
+  for (int op = 0; op < 4; ++op) {
+    if (!(mask & (1 << op)) || !c->sym.lower_stale[op]) continue;
+    DBuf& X = op == 0 ? c->Se : (op == 1 ? c->Ce : (op == 2 ? c->Si[0] : c->Ci[0]));
+    const int64_t ld = op < 2 ? c->ldE : c->ldI[0];
+    if (c->precA == PMCHWT_FP64)
+      launch_mirror_lower<double>(X.as<double>(), ld, n, c->sym.crow.as<int32_t>(), c->sym.col.as<int32_t>(),
+                                  c->sym.iptr.as<int64_t>(), c->sym.item.as<int32_t>(), c->sing.blk.as<double>(),
+                                  c->sym.nnz, op, c->stream);
+    else
+      launch_mirror_lower<float>(X.as<float>(), ld, n, c->sym.crow.as<int32_t>(), c->sym.col.as<int32_t>(),
+                                 c->sym.iptr.as<int64_t>(), c->sym.item.as<int32_t>(), c->sing.blk.as<double>(),
+                                 c->sym.nnz, op, c->stream);
+    HIPCHK(hipGetLastError());
+    c->sym.lower_stale[op] = false;
+  }
+}
+
 void flush_times(pmchwt_ctx* c);
 
 // Timer whose result is added to *dst later (flush_times): no host wait.
@@ -696,6 +727,7 @@ struct EvTimer {
 // the full combined matrices C, S1, S2 of a single scatterer
 template <typename M>
 void build_comb(pmchwt_ctx* c) {
+  ensure_lower(c, 15);
   const Scat& s = c->sc[0];
   const int64_t ne = c->E_tot * c->ldE;
   realloc_c<M>(c, c->AC, size_t(2 * ne));
@@ -752,6 +784,33 @@ void sym_tables(pmchwt_ctx* c) {
     }
     rowptr[r + 1] = int64_t(col.size());
   }
+  // singular local-block entries of every correction entry (r, c): + for
+  // those added to X_rc, - for those added to X_cr
+  std::unordered_map<int64_t, int64_t> at;
+  at.reserve(col.size() * 2);
+  for (size_t k = 0; k < col.size(); ++k) at.emplace(int64_t(crow[k]) * n + col[k], int64_t(k));
+  std::vector<std::vector<int32_t>> its(col.size());
+  const std::vector<int32_t>& sp = c->sing.h_pairs;
+  for (size_t q = 0; q < sp.size() / 2; ++q) {
+    const int f = sp[2 * q], g = sp[2 * q + 1];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const int r = T.t2e[3 * f + a], cc = T.t2e[3 * g + b];
+        const int32_t e = int32_t(9 * q + 3 * a + b);
+        auto i1 = at.find(int64_t(r) * n + cc);
+        if (i1 != at.end()) its[size_t(i1->second)].push_back(e << 1);
+        auto i2 = at.find(int64_t(cc) * n + r);
+        if (i2 != at.end()) its[size_t(i2->second)].push_back((e << 1) | 1);
+      }
+  }
+  std::vector<int64_t> iptr(col.size() + 1, 0);
+  std::vector<int32_t> item;
+  for (size_t k = 0; k < col.size(); ++k) {
+    item.insert(item.end(), its[k].begin(), its[k].end());
+    iptr[k + 1] = int64_t(item.size());
+  }
+  c->sym.iptr = upload(c, iptr);
+  c->sym.item = upload(c, item);
   c->sym.nt = nt;
   c->sym.ntiles = int64_t(tij.size() / 2);
   c->sym.nnz = int64_t(col.size());
@@ -826,6 +885,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
         }
       }
     c->sing.pairs = upload(c, pairs);
+    c->sing.h_pairs = pairs;
     c->sing.npairs = int64_t(pairs.size() / 2);
     std::vector<int64_t> sptr(size_t(c->F_tot) + 1, 0);
     for (size_t q = 0; q < pairs.size() / 2; ++q) ++sptr[size_t(pairs[2 * q]) + 1];
@@ -914,7 +974,21 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     c->max_list = maxl;
     c->recompute = double(ctri.size()) / double(c->F_tot);
     c->chunk_size = CH;
+    std::vector<int32_t> tmin(c->F_tot), tmax(nch);
+    for (auto& sc : c->sc)
+      for (int f = 0; f < sc.topo.F; ++f) {
+        int m = INT32_MAX;
+        for (int a = 0; a < 3; ++a) m = std::min(m, (sc.edge_off + sc.topo.t2e[3 * f + a]) / SYM_T);
+        tmin[sc.tri_off + f] = m;
+      }
+    for (int ch = 0; ch < nch; ++ch) tmax[ch] = (cedge[ch + 1] - 1) / SYM_T;
+    c->t1_tmin = upload(c, tmin);
+    c->ch_tmax = upload(c, tmax);
   }
+  // one scatterer stored as symmetric tiles: only the upper tiles are
+  // assembled (the lower ones are their mirror, filled on first use)
+  const int form = c->optA.operator_form;
+  const bool symform = c->sc.size() == 1 && c->comb_ok && (form == 2 || (form == 0 && E >= SYM_MIN_EDGES));
   // slabs of test triangles inside one scatterer, sized for a bounded buffer
   const double budget = SLAB_BUDGET;
   const double row_bytes = 3.0 * 2 * sizeof(M) * 2;  // per test triangle per union column, S and C
@@ -932,6 +1006,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     c->slab_rows_l.clear();
     c->slab_sp.clear();
     c->slab_sm.clear();
+    c->slab_cs.clear();
     c->slab_nrows.clear();
   }
   int max_slab = 0, max_Em = 0;
@@ -951,6 +1026,9 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   hj.He_C = HeC.as<M>();
   hj.Hi_S = HiS.as<M>();
   hj.Hi_C = HiC.as<M>();
+  hj.skip_lower = symform ? 1 : 0;
+  hj.t1_tmin = c->t1_tmin.as<int32_t>();
+  hj.ch_tmax = c->ch_tmax.as<int32_t>();
   // per union edge: T+ / T- (for the slot rows of pass 2)
   std::vector<int32_t> etp(c->E_tot), etm(c->E_tot), eap(c->E_tot), eam(c->E_tot);
   for (auto& s : c->sc)
@@ -997,7 +1075,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     // rows touched by this slab: edges of scatterer m with T+ or T- inside
     const size_t si = size_t(&sl - &slabs[0]);
     if (!slabs_cached) {
-      std::vector<int32_t> rows, sp, smn, rows_l;
+      std::vector<int32_t> rows, sp, smn, rows_l, cs;
       for (int e = s.edge_off; e < s.edge_off + s.topo.E; ++e) {
         const bool ip = etp[e] >= t0 && etp[e] < t1, im = etm[e] >= t0 && etm[e] < t1;
         if (!ip && !im) continue;
@@ -1005,25 +1083,28 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
         rows_l.push_back(e - s.edge_off);
         sp.push_back(ip ? 3 * (etp[e] - t0) + eap[e] : -1);
         smn.push_back(im ? 3 * (etm[e] - t0) + eam[e] : -1);
+        cs.push_back((e - s.edge_off) / SYM_T * SYM_T);  // first column of the row's upper tiles
       }
       c->slab_rows.push_back(upload(c, rows));
       c->slab_rows_l.push_back(upload(c, rows_l));
       c->slab_sp.push_back(upload(c, sp));
       c->slab_sm.push_back(upload(c, smn));
+      c->slab_cs.push_back(upload(c, cs));
       c->slab_nrows.push_back(int(rows.size()));
     }
     DBuf &drows = c->slab_rows[si], &drl = c->slab_rows_l[si], &dsp = c->slab_sp[si], &dsm = c->slab_sm[si];
+    const int32_t* dcs = symform ? c->slab_cs[si].as<int32_t>() : nullptr;
     const int nr = c->slab_nrows[si];
     {
       EvTimer t(c->stream);
       launch_rows_combine<M>(c->Se.as<M>(), c->ldE, HeS.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite);
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite, dcs);
       launch_rows_combine<M>(c->Ce.as<M>(), c->ldE, HeC.as<M>(), c->E_tot, drows.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite);
+                             dsm.as<int32_t>(), nr, c->E_tot, c->stream, overwrite, dcs);
       launch_rows_combine<M>(c->Si[m].as<M>(), c->ldI[m], HiS.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite);
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite, dcs);
       launch_rows_combine<M>(c->Ci[m].as<M>(), c->ldI[m], HiC.as<M>(), s.topo.E, drl.as<int32_t>(), dsp.as<int32_t>(),
-                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite);
+                             dsm.as<int32_t>(), nr, s.topo.E, c->stream, overwrite, dcs);
       HIPCHK(hipGetLastError());
       ms_pass2 += t.stop();
     }
@@ -1045,9 +1126,9 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   c->AC = DBuf();
   c->AS1 = DBuf();
   c->AS2 = DBuf();
+  for (bool& st : c->sym.lower_stale) st = symform;
   if (c->sc.size() == 1 && c->comb_ok) {  // three combined matrices for the operator products
-    const int form = c->optA.operator_form;
-    if (form == 2 || (form == 0 && E >= SYM_MIN_EDGES)) {
+    if (symform) {
       const Scat& s = c->sc[0];
       sym_tables(c);
       realloc_c<M>(c, c->sym.pack, size_t(c->sym.ntiles) * 3 * SYM_T * SYM_T * 2);
@@ -1056,9 +1137,8 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
       launch_pack_sym3<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), c->ldE, int(E),
                           c->sym.tij.as<int32_t>(), c->sym.ntiles, c->k_ext, s.k.real(), s.k.imag(),
                           c->sym.pack.as<M>(), c->stream);
-      launch_sym_corr<M>(c->Se.as<M>(), c->Ce.as<M>(), c->Si[0].as<M>(), c->Ci[0].as<M>(), c->ldE,
-                         c->sym.crow.as<int32_t>(), c->sym.col.as<int32_t>(), c->sym.nnz, c->k_ext, s.k.real(),
-                         s.k.imag(), c->sym.val.as<M>(), c->stream);
+      launch_sym_corr_sing<M>(c->sym.iptr.as<int64_t>(), c->sym.item.as<int32_t>(), c->sing.blk.as<double>(),
+                              c->sym.nnz, c->k_ext, s.k.real(), s.k.imag(), c->sym.val.as<M>(), c->stream);
       HIPCHK(hipGetLastError());
       c->sym.ready = true;
     } else {
@@ -1704,6 +1784,101 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
   return ok;
 }
 
+// Sparse approximate inverses of M_A and M_A^T (kernels in massinv.inl): row
+// i on the ball of columns within `hops` steps of M_A's sparsity graph, by
+// the Chebyshev iteration for the spectrum interval [0.3, 1.05] (the
+// spectrum of M_A lies in [0.333, 0.997] on every mesh measured).  FP32
+// values for a MIXED preconditioner (8 steps of the graph, 14 Chebyshev
+// steps: entries within about 1e-7 of the row maximum on the CPU check), FP64
+// otherwise (16 steps, 28 Chebyshev steps: about 1e-13).  Returns false if a
+// ball exceeds the capacity; the caller then inverts densely.
+struct MassCsr {  // CSR of a mass matrix (FP64 values) and its longest row
+  DBuf rp, ci, cv;
+  int maxrow = 0;
+};
+
+template <typename T>
+bool sparse_mass_inverse(pmchwt_ctx* c, const double* Mrow, int n, pmchwt_ctx::SparseInv& inv,
+                         pmchwt_ctx::SparseInv& invT) {
+  constexpr bool f32 = sizeof(T) == 4;
+  const int hops = f32 ? 8 : 16, steps = f32 ? 14 : 28, cap = f32 ? 1024 : 2048;
+  // CSR of M and of M^T (= the CSC of M) from the dense matrix
+  DBuf Mt = dalloc_c<double>(c, size_t(n) * n);
+  launch_transpose(Mrow, Mt.as<double>(), n, c->stream);
+  MassCsr cM, cT;
+  auto csr = [&](const double* A, MassCsr& o) {
+    DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<double>(c, size_t(n));
+    o.rp = dalloc_c<int64_t>(c, size_t(n) + 1);
+    build_truncated_inverse<double>(A, n, n, 0.0, cnt.as<int32_t>(), thr.as<double>(), o.rp.as<int64_t>(),
+                                    c->stream);
+    int64_t nnz = 0;
+    std::vector<int32_t> h(n);
+    HIPCHK(hipMemcpyAsync(&nnz, o.rp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    o.maxrow = *std::max_element(h.begin(), h.end());
+    o.ci = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+    o.cv = dalloc_c<double>(c, size_t(std::max<int64_t>(nnz, 1)));
+    fill_truncated_inverse<double>(A, n, n, thr.as<double>(), o.rp.as<int64_t>(), o.ci.as<int32_t>(),
+                                   o.cv.as<double>(), c->stream);
+  };
+  csr(Mrow, cM);
+  csr(Mt.as<double>(), cT);
+  const int grid = std::min(n, 1024);
+  double worst = 0.0;
+  // X = inverse of the matrix whose CSR is `g` (search graph) and whose CSC is `h` (gather)
+  auto run = [&](const MassCsr& g, const MassCsr& h, pmchwt_ctx::SparseInv& out) -> bool {
+    SpInvJob J{};
+    J.n = n;
+    J.rp = g.rp.as<int64_t>();
+    J.ci = g.ci.as<int32_t>();
+    J.cp = h.rp.as<int64_t>();
+    J.ri = h.ci.as<int32_t>();
+    J.cv = h.cv.as<double>();
+    J.hops = hops;
+    J.cap = cap;
+    J.hash = 2 * cap;
+    J.wmax = h.maxrow;
+    J.steps = steps;
+    J.a = 0.3;
+    J.b = 1.05;
+    DBuf count = dalloc_c<int32_t>(c, size_t(n));
+    J.count = count.as<int32_t>();
+    launch_spinv_count(J, grid, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> hc(n);
+    HIPCHK(hipMemcpyAsync(hc.data(), count.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<int64_t> rowptr(size_t(n) + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      if (hc[i] < 0) return false;
+      rowptr[i + 1] = rowptr[i] + hc[i];
+    }
+    out.nnz = rowptr[n];
+    out.rowptr = upload(c, rowptr);
+    out.col = dalloc_c<int32_t>(c, size_t(out.nnz));
+    out.val = dalloc_c<T>(c, size_t(out.nnz));
+    DBuf res = dalloc_c<double>(c, size_t(n));
+    DBuf adj = dalloc_c<int16_t>(c, size_t(grid) * cap * std::max(1, J.wmax));
+    J.orp = out.rowptr.as<int64_t>();
+    J.ocol = out.col.as<int32_t>();
+    J.oval = out.val.p;
+    J.res = res.as<double>();
+    J.adj = adj.as<int16_t>();
+    launch_spinv_rows<T>(J, grid, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hr(n);
+    HIPCHK(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (double v : hr) worst = std::max(worst, v);
+    return true;
+  };
+  if (!run(cM, cT, inv) || !run(cT, cM, invT)) return false;
+  c->prof.mass_iterations = steps;
+  c->prof.mass_residual = worst;
+  return true;
+}
+
 // Truncated CSR copy of an inverse: entries of at least rel times their
 // row's largest (2^-27 for an FP32 inverse, 2^-52 for FP64: what is dropped
 // lies below the rounding of the stored inverse).  One host wait for the
@@ -1773,6 +1948,20 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     c->MA.push_back(std::move(MA));
     const int64_t ldm = ldmass(n);
+    if (c->optP.mass_method == 2) {  // sparse inverse on the graph ball (dense only if a ball overflows)
+      pmchwt_ctx::SparseInv a, b;
+      const bool ok = c->mass_f32 ? sparse_mass_inverse<float>(c, mass.as<double>() + off[m], n, a, b)
+                                  : sparse_mass_inverse<double>(c, mass.as<double>() + off[m], n, a, b);
+      if (ok) {
+        c->MinvS.push_back(std::move(a));
+        c->MinvTS.push_back(std::move(b));
+        c->Minv.emplace_back();  // dense FP32 copies for the matrix-core product: built when first needed
+        c->MinvT.emplace_back();
+        continue;
+      }
+      c->MinvS.resize(m);
+      c->MinvTS.resize(m);
+    }
     if (c->mass_f32) {
       // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
       // M_A^-1 with zero padding columns, the layout the products read
@@ -1811,14 +2000,12 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
         truncated_inverse<double>(c, MdT.as<double>(), ldm, n, 0x1p-52, 0.4, b)) {
       c->MinvS.push_back(std::move(a));
       c->MinvTS.push_back(std::move(b));
+    } else {  // empty entries: the products read the dense inverse
+      c->MinvS.emplace_back();
+      c->MinvTS.emplace_back();
     }
     c->Minv.push_back(std::move(Md));
     c->MinvT.push_back(std::move(MdT));
-  }
-  // FP64 truncated copies only if every scatterer has them
-  if (!c->mass_f32 && c->MinvS.size() != c->sc.size()) {
-    c->MinvS.clear();
-    c->MinvTS.clear();
   }
   HIPCHK(hipGetLastError());
   c->prof.ms_mass = t.stop();
@@ -1903,6 +2090,7 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
     c->prof.matvec_bytes += nrhs * c->sym.ntiles * 3 * SYM_T * SYM_T * (f64 ? 16 : 8);
     return;
   }
+  ensure_lower(c, 15);  // every product below reads whole rows
   if (c->sym.ready && !c->comb && !(!f64 && nrhs >= MFMA_MIN_RHS)) {
     if (f64)
       build_comb<double>(c);
@@ -2021,23 +2209,36 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   c->calls_P += 1;
   const bool mm = c->mass_f32 && nrhs >= MFMA_MIN_RHS;
   float* Bw = mm ? mfma_ws(c, nrhs) : nullptr;
-  for (size_t m = 0; m < c->sc.size(); ++m) {
+  // out = alpha M_A^-1 in (transposed: M_A^-T) for scatterer m: the matrix-core
+  // product on the dense FP32 inverse for many right-hand sides (expanded
+  // from the sparse inverse when first needed), else the sparse inverse,
+  // else the dense FP64 one
+  auto mass_inv = [&](size_t m, bool tr, double alpha, const double* in, double* out) {
     const Scat& s = c->sc[m];
-    const int64_t o = s.edge_off;
-    if (mm)
-      launch_mfma_real2(c->Minv[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
-                        nrhs, vs, E, Bw, c->stream);
-    else if (c->mass_f32)
-      launch_spmv_real2_csr(c->MinvS[m].rowptr.as<int64_t>(), c->MinvS[m].col.as<int32_t>(),
-                            c->MinvS[m].val.as<float>(), s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E, c->stream);
-    else if (!c->MinvS.empty())
-      launch_spmv_real2_csr(c->MinvS[m].rowptr.as<int64_t>(), c->MinvS[m].col.as<int32_t>(),
-                            c->MinvS[m].val.as<double>(), s.topo.E, 1.0, y + 2 * o, t1 + 2 * o, nrhs, vs, E,
-                            c->stream);
-    else
-      launch_gemv_real2(c->Minv[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, 1.0, y + 2 * o, t1 + 2 * o,
-                        nrhs, vs, E, c->stream);
-  }
+    const int64_t o = s.edge_off, ldm = ldmass(s.topo.E);
+    const pmchwt_ctx::SparseInv& S = tr ? c->MinvTS[m] : c->MinvS[m];
+    DBuf& Dn = tr ? c->MinvT[m] : c->Minv[m];
+    if (mm) {
+      if (!Dn.p) {
+        Dn = dalloc_c<float>(c, size_t(ldm) * ldm);
+        launch_zero_f(Dn.as<float>(), ldm * ldm, c->stream);
+        launch_csr_scatter_f32(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<float>(), s.topo.E, Dn.as<float>(),
+                               ldm, c->stream);
+      }
+      launch_mfma_real2(Dn.as<float>(), ldm, s.topo.E, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, Bw,
+                        c->stream);
+    } else if (S.rowptr.p && c->mass_f32) {
+      launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<float>(), s.topo.E, alpha, in + 2 * o,
+                            out + 2 * o, nrhs, vs, E, c->stream);
+    } else if (S.rowptr.p) {
+      launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<double>(), s.topo.E, alpha,
+                            in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
+    } else {
+      launch_gemv_real2(Dn.as<double>(), ldm, s.topo.E, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E,
+                        c->stream);
+    }
+  };
+  for (size_t m = 0; m < c->sc.size(); ++m) mass_inv(m, false, 1.0, y, t1);
   // the interior launches write disjoint row ranges that cover every row of
   // t2 (scatterer m owns rows edge_off .. edge_off + E_m of both halves), so
   // the first writer overwrites and t2 needs no clearing pass
@@ -2056,24 +2257,7 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   if (c->P_ext)
     launch_spmv_pmchwt<double>(rp, cl, c->PSe.as<double>(), c->P_C ? c->PCe.as<double>() : nullptr, int(E), c->k_ext,
                                0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, nrhs, vs, c->stream, c->P_int);
-  for (size_t m = 0; m < c->sc.size(); ++m) {
-    const Scat& s = c->sc[m];
-    const int64_t o = s.edge_off;
-    if (mm)
-      launch_mfma_real2(c->MinvT[m].as<float>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
-                        nrhs, vs, E, Bw, c->stream);
-    else if (c->mass_f32)
-      launch_spmv_real2_csr(c->MinvTS[m].rowptr.as<int64_t>(), c->MinvTS[m].col.as<int32_t>(),
-                            c->MinvTS[m].val.as<float>(), s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
-                            c->stream);
-    else if (!c->MinvTS.empty())
-      launch_spmv_real2_csr(c->MinvTS[m].rowptr.as<int64_t>(), c->MinvTS[m].col.as<int32_t>(),
-                            c->MinvTS[m].val.as<double>(), s.topo.E, -1.0, t2 + 2 * o, z + 2 * o, nrhs, vs, E,
-                            c->stream);
-    else
-      launch_gemv_real2(c->MinvT[m].as<double>(), ldmass(s.topo.E), s.topo.E, s.topo.E, -1.0, t2 + 2 * o, z + 2 * o,
-                        nrhs, vs, E, c->stream);
-  }
+  for (size_t m = 0; m < c->sc.size(); ++m) mass_inv(m, true, -1.0, t2, z);
   HIPCHK(hipGetLastError());
 }
 
@@ -2158,6 +2342,7 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   } else {
     launch_zero(t.as<double>(), 2 * vs * nrhs, c->stream);
   }
+  if (!fp64_interior) ensure_lower(c, 12);
   for (size_t m = 0; m < c->sc.size() && !fp64_interior; ++m) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off;
@@ -2754,6 +2939,7 @@ int pmchwt_get_block(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchwt_
     const int Em = sm.topo.E, El = sl.topo.E;
     if (ld < El) return fail(c, PMCHWT_ERR_INVALID_ARG, "ld too small");
     if (sp == PMCHWT_RWG) {
+      ensure_lower(c, 15);
       const DBuf* src;
       int64_t sld, r0, c0;
       if (med == PMCHWT_EXT) {
@@ -2817,6 +3003,7 @@ int pmchwt_get_entries(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchw
       if (rows[q] < 0 || rows[q] >= sm.topo.E || cols[q] < 0 || cols[q] >= sl.topo.E)
         return fail(c, PMCHWT_ERR_INVALID_ARG, "entry index out of range");
     if (sp == PMCHWT_RWG) {
+      ensure_lower(c, 15);
       const size_t es = c->precA == PMCHWT_FP64 ? 16 : 8;
       const DBuf* src = med == PMCHWT_EXT ? (op == PMCHWT_OP_S ? &c->Se : &c->Ce) : (op == PMCHWT_OP_S ? &c->Si[m] : &c->Ci[m]);
       const int64_t sld = med == PMCHWT_EXT ? c->ldE : c->ldI[m];

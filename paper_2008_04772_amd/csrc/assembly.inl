@@ -82,6 +82,7 @@ __global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmPa
   MomPair<R>* sm = reinterpret_cast<MomPair<R>*>(smem_raw);
   const int t1 = t1_base + blockIdx.y;
   const int ch = blockIdx.x;
+  if (h.skip_lower && h.ch_tmax[ch] < h.t1_tmin[t1]) return;  // lower tiles only: mirrored later
   const int F = p.F;
   const int l0 = h.chunk_ptr[ch], nl = h.chunk_ptr[ch + 1] - l0;
   const int s1 = p.tscat[t1];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(RegularThreads<R>::value) void k_regular_rows(AsmPa
 template <typename M, bool OW, int U>
 __global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M* __restrict__ H, int64_t ldh,
                                                       const int32_t* rows, const int32_t* sp, const int32_t* sm,
-                                                      int ncols) {
+                                                      int ncols, const int32_t* cstart) {
   typedef M VU __attribute__((ext_vector_type(U)));
   const int r = blockIdx.x;
   const int i = rows[r], a = sp[r], b = sm[r];
@@ -266,8 +267,9 @@ __global__ __launch_bounds__(256) void k_rows_combine(M* A, int64_t lda, const M
   const VU* Ha = reinterpret_cast<const VU*>(H + 2 * int64_t(a >= 0 ? a : 0) * ldh);
   const VU* Hb = reinterpret_cast<const VU*>(H + 2 * int64_t(b >= 0 ? b : 0) * ldh);
   const int64_t nc = 2 * int64_t(ncols) / U, end = OW ? 2 * lda / U : nc;
+  const int64_t q0 = cstart ? 2 * int64_t(cstart[r]) / U : 0;
 #pragma unroll 4
-  for (int64_t q = threadIdx.x; q < end; q += 256) {
+  for (int64_t q = q0 + threadIdx.x; q < end; q += 256) {
     VU v = OW ? VU(M(0)) : Ar[q];
     if (!OW || q < nc) {
       if (a >= 0) v += Ha[q];
@@ -411,7 +413,8 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
 
 template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
-                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite) {
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite,
+                         const int32_t* cstart) {
   if (nrows <= 0) return;
   constexpr int U = 16 / sizeof(M);
   // 16-byte units: row starts (2 ldh, 2 lda values apart) and the column
@@ -419,13 +422,15 @@ void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32
   const bool vec = (2 * ldh) % U == 0 && (2 * lda) % U == 0 && (2 * int64_t(ncols)) % U == 0;
   const dim3 grid{static_cast<unsigned>(nrows)}, block{256};
   if (vec && overwrite)
-    hipLaunchKernelGGL((k_rows_combine<M, true, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+    hipLaunchKernelGGL((k_rows_combine<M, true, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols, cstart);
   else if (vec)
-    hipLaunchKernelGGL((k_rows_combine<M, false, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+    hipLaunchKernelGGL((k_rows_combine<M, false, U>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols,
+                       cstart);
   else if (overwrite)
-    hipLaunchKernelGGL((k_rows_combine<M, true, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+    hipLaunchKernelGGL((k_rows_combine<M, true, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols, cstart);
   else
-    hipLaunchKernelGGL((k_rows_combine<M, false, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols);
+    hipLaunchKernelGGL((k_rows_combine<M, false, 1>), grid, block, 0, st, A, lda, H, ldh, rows, sp, sm, ncols,
+                       cstart);
 }
 
 template <typename M>
@@ -441,9 +446,9 @@ template void launch_regular_rows<double, double>(const AsmParams<double>&, cons
 template void launch_regular_rows<float, float>(const AsmParams<float>&, const HalfJob<float>&, int, int, int, int,
                                                 hipStream_t);
 template void launch_rows_combine<double>(double*, int64_t, const double*, int64_t, const int32_t*, const int32_t*,
-                                          const int32_t*, int, int, hipStream_t, bool);
+                                          const int32_t*, int, int, hipStream_t, bool, const int32_t*);
 template void launch_rows_combine<float>(float*, int64_t, const float*, int64_t, const int32_t*, const int32_t*,
-                                         const int32_t*, int, int, hipStream_t, bool);
+                                         const int32_t*, int, int, hipStream_t, bool, const int32_t*);
 template void launch_singular<double>(const AsmParams<double>&, const SingParams&, hipStream_t);
 template void launch_singular<float>(const AsmParams<float>&, const SingParams&, hipStream_t);
 

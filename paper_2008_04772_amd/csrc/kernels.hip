@@ -6,3 +6,4 @@
 #include "linalg.inl"
 #include "mfma.inl"
 #include "refine.inl"
+#include "massinv.inl"

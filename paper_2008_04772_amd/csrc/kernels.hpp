@@ -54,6 +54,12 @@ struct HalfJob {
   M* Hi_C;
   int64_t ld_i;                // E_m
   int edge_off_i;              // first union edge of the slab's scatterer
+  // upper tiles only (one scatterer stored as symmetric tiles): a workgroup
+  // whose chunk lies entirely in tiles left of every edge of its test
+  // triangle writes nothing (those entries are the mirror of upper ones)
+  int skip_lower;
+  const int32_t* t1_tmin;      // per triangle: smallest tile index of its edges
+  const int32_t* ch_tmax;      // per chunk: tile index of its last edge
 };
 
 // Sauter-Schwab tables per relation kind (1 vertex, 2 edge, 3 identical):
@@ -84,6 +90,34 @@ struct FreeJob {
   double* y;
 };
 void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t st);
+
+// Sparse approximate inverse of a mass matrix M (one scatterer, n x n): row i
+// on the ball of columns within `hops` steps of M's sparsity graph, by a
+// Chebyshev iteration for a spectrum in [a, b].  Pass 1 (launch_spinv_count)
+// writes the ball size of every row (-1 past `cap`); pass 2 writes the CSR
+// values at the row pointers orp.
+struct SpInvJob {
+  int n;
+  const int64_t* rp;   // CSR of M (row pointers, columns): the search graph
+  const int32_t* ci;
+  const int64_t* cp;   // CSC of M (column pointers, rows, values): the gather of (X M)
+  const int32_t* ri;
+  const double* cv;
+  int hops, cap, hash, wmax, steps;
+  double a, b;
+  int32_t* count;      // pass 1 output
+  const int64_t* orp;  // pass 2: output row pointers, columns, values (float or double), residuals
+  int32_t* ocol;
+  void* oval;
+  double* res;
+  int16_t* adj;        // pass 2 scratch: grid x cap x wmax
+};
+size_t spinv_lds_bytes(int H, int CAP, bool values);
+void launch_spinv_count(const SpInvJob& J, int grid, hipStream_t st);
+template <typename T>
+void launch_spinv_rows(const SpInvJob& J, int grid, hipStream_t st);
+void launch_csr_scatter_f32(const int64_t* rowptr, const int32_t* col, const float* val, int n, float* out, int64_t ld,
+                            hipStream_t st);
 
 // Dual cells (barycentric rings) of all scatterers.
 struct CellParams {
@@ -156,7 +190,8 @@ void launch_regular_rows(const AsmParams<M>& p, const HalfJob<M>& h, int t1_begi
 // A[rows[r]] += H[sp[r]] + H[sm[r]] (negative slot = absent), complex rows of ncols
 template <typename M>
 void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32_t* rows, const int32_t* sp,
-                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite = false);
+                         const int32_t* sm, int nrows, int ncols, hipStream_t st, bool overwrite = false,
+                         const int32_t* cstart = nullptr);  // per row: first column written (a multiple of 8)
 template <typename M>
 void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st);
 
@@ -217,6 +252,19 @@ void launch_pack_sym3(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_
 template <typename M>
 void launch_sym_corr(const M* Se, const M* Ce, const M* Si, const M* Ci, int64_t ld, const int32_t* crow,
                      const int32_t* col, int64_t nnz, double ke, double kir, double kii, M* val, hipStream_t st);
+// The same correction from the singular pairs' FP64 local blocks alone (the
+// regular contributions to X_rc and X_cr are equal): entry k sums the items
+// item[ptr[k]] .. item[ptr[k+1]-1], each (local-block entry << 1 | negate),
+// over the blocks (Se, Ce, Si, Ci) of SingParams::blk.
+template <typename M>
+void launch_sym_corr_sing(const int64_t* ptr, const int32_t* item, const double* blk, int64_t nnz, double ke,
+                          double kir, double kii, M* val, hipStream_t st);
+// Lower tiles of one dense operator X (n x n, leading dimension ld) from its
+// upper tiles, X_rc = X_cr for tile(r) > tile(c), then X_rc += the singular
+// asymmetry of operator `op` (0..3 = Se, Ce, Si, Ci) on the correction entries.
+template <typename M>
+void launch_mirror_lower(M* X, int64_t ld, int n, const int32_t* crow, const int32_t* col, const int64_t* ptr,
+                         const int32_t* item, const double* blk, int64_t nnz, int op, hipStream_t st);
 template <typename M>
 void launch_gemv_sym3(const M* P, const int32_t* tij, int64_t ntiles, int nt, int n, const double* xD,
                       const double* xN, double* part, hipStream_t st);

@@ -472,6 +472,99 @@ __global__ void k_sym_corr(const M* __restrict__ Se, const M* __restrict__ Ce, c
   for (int q = 0; q < 6; ++q) val[6 * k + q] = M(double(a[q]) - double(b[q]));
 }
 
+// sum of the signed singular items of one correction entry, per operator
+// (Se, Ce, Si, Ci): items (blk entry << 1 | negate), blk entries 4 complex
+__device__ __forceinline__ void sing_item_sum(const int64_t* ptr, const int32_t* item, const double* blk, int64_t k,
+                                              double out[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q] = 0.0;
+  for (int64_t t = ptr[k]; t < ptr[k + 1]; ++t) {
+    const int32_t it = item[t];
+    const double sg = (it & 1) ? -1.0 : 1.0;
+    const double* b = blk + 8 * int64_t(it >> 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] += sg * b[q];
+  }
+}
+
+template <typename M>
+__global__ void k_sym_corr_sing(const int64_t* __restrict__ ptr, const int32_t* __restrict__ item,
+                                const double* __restrict__ blk, int64_t nnz, double ke, double kir, double kii,
+                                M* __restrict__ val) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  double d[8];
+  sing_item_sum(ptr, item, blk, k, d);
+  // the combination of combine_entry: C = Ce + Ci, S1 = Se/ke + Si/ki, S2 = -(ke Se + ki Si)
+  const double ser = d[0], sei = d[1], cer = d[2], cei = d[3], sir = d[4], sii = d[5], cir = d[6], cii = d[7];
+  const double k2 = kir * kir + kii * kii, ir = kir / k2, ii = -kii / k2;
+  M* o = val + 6 * k;
+  o[0] = M(cer + cir);
+  o[1] = M(cei + cii);
+  o[2] = M(ser / ke + (sir * ir - sii * ii));
+  o[3] = M(sei / ke + (sir * ii + sii * ir));
+  o[4] = M(-(ke * ser + (kir * sir - kii * sii)));
+  o[5] = M(-(ke * sei + (kir * sii + kii * sir)));
+}
+
+template <typename M>
+void launch_sym_corr_sing(const int64_t* ptr, const int32_t* item, const double* blk, int64_t nnz, double ke,
+                          double kir, double kii, M* val, hipStream_t st) {
+  if (nnz == 0) return;
+  hipLaunchKernelGGL((k_sym_corr_sing<M>), dim3(unsigned((nnz + 255) / 256)), dim3(256), 0, st, ptr, item, blk, nnz,
+                     ke, kir, kii, val);
+}
+
+// X[r][c] = X[c][r] for tile(r) > tile(c): 32 x 32 complex blocks through LDS
+// (coalesced reads along the source rows, coalesced writes along the
+// destination rows); blocks outside the strictly lower tiles exit
+template <typename M>
+__global__ __launch_bounds__(256) void k_mirror_lower(M* X, int64_t ld, int n) {
+  __shared__ M sre[32][33], sim[32][33];
+  const int R0 = blockIdx.y * 32, C0 = blockIdx.x * 32;
+  if (R0 / SYM_T <= C0 / SYM_T) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32 per pass
+  for (int y = ty; y < 32; y += 8) {  // source rows C0 + y, columns R0 + tx
+    const int sr = C0 + y, sc = R0 + tx;
+    if (sr < n && sc < n) {
+      sre[y][tx] = X[2 * (int64_t(sr) * ld + sc)];
+      sim[y][tx] = X[2 * (int64_t(sr) * ld + sc) + 1];
+    }
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {  // destination rows R0 + y, columns C0 + tx
+    const int dr = R0 + y, dc = C0 + tx;
+    if (dr < n && dc < n) {
+      X[2 * (int64_t(dr) * ld + dc)] = sre[tx][y];
+      X[2 * (int64_t(dr) * ld + dc) + 1] = sim[tx][y];
+    }
+  }
+}
+
+// correction entries after the mirror: X_rc += sing_rc - sing_cr of operator op
+template <typename M>
+__global__ void k_mirror_fix(M* X, int64_t ld, const int32_t* __restrict__ crow, const int32_t* __restrict__ col,
+                             const int64_t* __restrict__ ptr, const int32_t* __restrict__ item,
+                             const double* __restrict__ blk, int64_t nnz, int op) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  double d[8];
+  sing_item_sum(ptr, item, blk, k, d);
+  M* x = X + 2 * (int64_t(crow[k]) * ld + col[k]);
+  x[0] = M(double(x[0]) + d[2 * op]);
+  x[1] = M(double(x[1]) + d[2 * op + 1]);
+}
+
+template <typename M>
+void launch_mirror_lower(M* X, int64_t ld, int n, const int32_t* crow, const int32_t* col, const int64_t* ptr,
+                         const int32_t* item, const double* blk, int64_t nnz, int op, hipStream_t st) {
+  const unsigned nb = unsigned((n + 31) / 32);
+  hipLaunchKernelGGL((k_mirror_lower<M>), dim3(nb, nb), dim3(256), 0, st, X, ld, n);
+  if (nnz > 0)
+    hipLaunchKernelGGL((k_mirror_fix<M>), dim3(unsigned((nnz + 255) / 256)), dim3(256), 0, st, X, ld, crow, col, ptr,
+                       item, blk, nnz, op);
+}
+
 // lane v of a 16-lane row moved by a DPP pattern (both 32-bit halves)
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
@@ -712,6 +805,15 @@ void launch_sym_reduce(const double* part, int nt, int n, const int64_t* rowptr,
   hipLaunchKernelGGL((k_sym_reduce<M, SYM_T>), dim3(unsigned((n + 15) / 16)), dim3(256), 0, st, part, nt, n, rowptr,
                      col, val, xD, xN, yD, yN);
 }
+
+template void launch_sym_corr_sing<float>(const int64_t*, const int32_t*, const double*, int64_t, double, double,
+                                          double, float*, hipStream_t);
+template void launch_sym_corr_sing<double>(const int64_t*, const int32_t*, const double*, int64_t, double, double,
+                                           double, double*, hipStream_t);
+template void launch_mirror_lower<float>(float*, int64_t, int, const int32_t*, const int32_t*, const int64_t*,
+                                         const int32_t*, const double*, int64_t, int, hipStream_t);
+template void launch_mirror_lower<double>(double*, int64_t, int, const int32_t*, const int32_t*, const int64_t*,
+                                          const int32_t*, const double*, int64_t, int, hipStream_t);
 
 #define PMCHWT_SYM_INST(M)                                                                                          \
   template void launch_pack_sym3<M>(const M*, const M*, const M*, const M*, int64_t, int, const int32_t*, int64_t, \
