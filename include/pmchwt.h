@@ -102,16 +102,17 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       M_A^-1 and M_A^-T in FP32.  All of this only perturbs the
  *       preconditioner, not the system that is solved.
  *   mass_method : how P's products apply M_A^-1 and M_A^-T (Section 3.2).
- *       0 = dense inverse: MIXED by a Chebyshev iteration on the sparse M_A,
- *       stopped at ||I - X M_A||_F / sqrt(n) <= 1e-6, Gauss-Jordan if it does
- *       not get there; FP64 by Gauss-Jordan (rank updates on the matrix
- *       cores).  1 = dense Gauss-Jordan inverse.  2 = sparse inverse: row i
- *       of the inverse on the columns within a fixed number of steps of
- *       M_A's sparsity graph (8 for MIXED, 16 for FP64), by a Chebyshev
- *       iteration on the spectrum interval [0.3, 1.05] (14 / 28 steps;
- *       entries within about 1e-7 / 1e-13 of the row maximum); a dense
- *       inverse replaces it if a row's column set exceeds 1024 / 2048.
- *       Dense inverses are read through a
+ *       0 = sparse inverse (FP32 values): row i of the inverse on the
+ *       columns within 8 steps of M_A's sparsity graph, by 14 steps of a
+ *       Chebyshev iteration on the spectrum interval [0.3, 1.05] (entries
+ *       within about 1e-7 of the row maximum); an FP64 preconditioner refines
+ *       each product once against the FP64 M_A (error squared).  A dense
+ *       inverse replaces it if a row's column set exceeds 1024 or a column of
+ *       M_A holds more than 24 entries.  1 = dense Gauss-Jordan inverse (rank
+ *       updates on the matrix cores).  2 = dense inverse, MIXED by a
+ *       Chebyshev iteration on the sparse M_A stopped at
+ *       ||I - X M_A||_F / sqrt(n) <= 1e-6 (Gauss-Jordan if it does not get
+ *       there), FP64 by Gauss-Jordan.  Dense inverses are read through a
  *       truncated CSR copy (entries below 2^-27 (MIXED) or 2^-52 (FP64, kept
  *       if under 40% dense) of their row's largest dropped) by products with
  *       fewer than 16 right-hand sides.  Zero-initialised structs get 0.

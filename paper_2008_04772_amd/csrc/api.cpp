@@ -227,6 +227,10 @@ struct pmchwt_ctx {
     int64_t nnz = 0;
   };
   std::vector<SparseInv> MinvS, MinvTS;
+  // FP64 CSR of M_A and M_A^T per scatterer when the inverses are the sparse
+  // FP32 ones (an FP64 preconditioner refines their products against them)
+  std::vector<SparseInv> MS, MTS;
+  DBuf mass_tmp;  // one vector set of scratch for that refinement
   // RWG Gram matrix (5 nonzeros per row), CSR over union edges with
   // scatterer-local column indices; pattern and slot map built once per geometry
   bool gram_valid = false;
@@ -1785,97 +1789,91 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
 }
 
 // Sparse approximate inverses of M_A and M_A^T (kernels in massinv.inl): row
-// i on the ball of columns within `hops` steps of M_A's sparsity graph, by
-// the Chebyshev iteration for the spectrum interval [0.3, 1.05] (the
-// spectrum of M_A lies in [0.333, 0.997] on every mesh measured).  FP32
-// values for a MIXED preconditioner (8 steps of the graph, 14 Chebyshev
-// steps: entries within about 1e-7 of the row maximum on the CPU check), FP64
-// otherwise (16 steps, 28 Chebyshev steps: about 1e-13).  Returns false if a
-// ball exceeds the capacity; the caller then inverts densely.
-struct MassCsr {  // CSR of a mass matrix (FP64 values) and its longest row
-  DBuf rp, ci, cv;
-  int maxrow = 0;
-};
-
-template <typename T>
+// i on the ball of columns within 8 steps of M_A's sparsity graph, 14 steps
+// of the Chebyshev iteration for the spectrum interval [0.3, 1.05] (the
+// spectrum of M_A lies in [0.333, 0.997] on every mesh measured): entries
+// within about 6e-8 of the row maximum on the CPU check, stored in FP32.
+// An FP64 preconditioner applies them with one refinement step against the
+// FP64 M_A (kept as CSR in MS / MTS), which squares that error.  Returns
+// false if a ball or a column of M_A exceeds the kernels' capacity; the
+// caller then inverts densely.
 bool sparse_mass_inverse(pmchwt_ctx* c, const double* Mrow, int n, pmchwt_ctx::SparseInv& inv,
-                         pmchwt_ctx::SparseInv& invT) {
-  constexpr bool f32 = sizeof(T) == 4;
-  const int hops = f32 ? 8 : 16, steps = f32 ? 14 : 28, cap = f32 ? 1024 : 2048;
+                         pmchwt_ctx::SparseInv& invT, pmchwt_ctx::SparseInv& Mcsr, pmchwt_ctx::SparseInv& MTcsr) {
+  const int hops = 8, steps = 14;
   // CSR of M and of M^T (= the CSC of M) from the dense matrix
   DBuf Mt = dalloc_c<double>(c, size_t(n) * n);
   launch_transpose(Mrow, Mt.as<double>(), n, c->stream);
-  MassCsr cM, cT;
-  auto csr = [&](const double* A, MassCsr& o) {
+  auto csr = [&](const double* A, pmchwt_ctx::SparseInv& o, int& maxrow) {
     DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<double>(c, size_t(n));
-    o.rp = dalloc_c<int64_t>(c, size_t(n) + 1);
-    build_truncated_inverse<double>(A, n, n, 0.0, cnt.as<int32_t>(), thr.as<double>(), o.rp.as<int64_t>(),
+    o.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+    build_truncated_inverse<double>(A, n, n, 0.0, cnt.as<int32_t>(), thr.as<double>(), o.rowptr.as<int64_t>(),
                                     c->stream);
-    int64_t nnz = 0;
     std::vector<int32_t> h(n);
-    HIPCHK(hipMemcpyAsync(&nnz, o.rp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&o.nnz, o.rowptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    o.maxrow = *std::max_element(h.begin(), h.end());
-    o.ci = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
-    o.cv = dalloc_c<double>(c, size_t(std::max<int64_t>(nnz, 1)));
-    fill_truncated_inverse<double>(A, n, n, thr.as<double>(), o.rp.as<int64_t>(), o.ci.as<int32_t>(),
-                                   o.cv.as<double>(), c->stream);
+    maxrow = *std::max_element(h.begin(), h.end());
+    o.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+    o.val = dalloc_c<double>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+    fill_truncated_inverse<double>(A, n, n, thr.as<double>(), o.rowptr.as<int64_t>(), o.col.as<int32_t>(),
+                                   o.val.as<double>(), c->stream);
   };
-  csr(Mrow, cM);
-  csr(Mt.as<double>(), cT);
-  const int grid = std::min(n, 1024);
-  double worst = 0.0;
-  // X = inverse of the matrix whose CSR is `g` (search graph) and whose CSC is `h` (gather)
-  auto run = [&](const MassCsr& g, const MassCsr& h, pmchwt_ctx::SparseInv& out) -> bool {
+  int maxM = 0, maxT = 0;
+  csr(Mrow, Mcsr, maxM);
+  csr(Mt.as<double>(), MTcsr, maxT);
+  if (maxM > spinv_wmax() || maxT > spinv_wmax()) return false;
+  const int cap = spinv_cap();
+  DBuf count = dalloc_c<int32_t>(c, 2 * size_t(n)), ball = dalloc_c<int32_t>(c, 2 * size_t(n) * cap);
+  // pass 1 for both inverses, then one wait for the ball sizes
+  auto job = [&](const pmchwt_ctx::SparseInv& g, const pmchwt_ctx::SparseInv& h, int which) {
     SpInvJob J{};
     J.n = n;
-    J.rp = g.rp.as<int64_t>();
-    J.ci = g.ci.as<int32_t>();
-    J.cp = h.rp.as<int64_t>();
-    J.ri = h.ci.as<int32_t>();
-    J.cv = h.cv.as<double>();
+    J.rp = g.rowptr.as<int64_t>();  // search graph: CSR of the matrix inverted
+    J.ci = g.col.as<int32_t>();
+    J.cp = h.rowptr.as<int64_t>();  // gather: its CSC = the CSR of its transpose
+    J.ri = h.col.as<int32_t>();
+    J.cv = h.val.as<double>();
     J.hops = hops;
-    J.cap = cap;
-    J.hash = 2 * cap;
-    J.wmax = h.maxrow;
     J.steps = steps;
     J.a = 0.3;
     J.b = 1.05;
-    DBuf count = dalloc_c<int32_t>(c, size_t(n));
-    J.count = count.as<int32_t>();
-    launch_spinv_count(J, grid, c->stream);
-    HIPCHK(hipGetLastError());
-    std::vector<int32_t> hc(n);
-    HIPCHK(hipMemcpyAsync(hc.data(), count.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    J.count = count.as<int32_t>() + size_t(which) * n;
+    J.ball = ball.as<int32_t>() + size_t(which) * n * cap;
+    return J;
+  };
+  SpInvJob J0 = job(Mcsr, MTcsr, 0), J1 = job(MTcsr, Mcsr, 1);
+  launch_spinv_ball(J0, std::min(n, 4096), c->stream);
+  launch_spinv_ball(J1, std::min(n, 4096), c->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> hc(2 * size_t(n));
+  HIPCHK(hipMemcpyAsync(hc.data(), count.p, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  DBuf res = dalloc_c<double>(c, 2 * size_t(n));
+  for (int which = 0; which < 2; ++which) {
+    pmchwt_ctx::SparseInv& out = which == 0 ? inv : invT;
     std::vector<int64_t> rowptr(size_t(n) + 1, 0);
     for (int i = 0; i < n; ++i) {
-      if (hc[i] < 0) return false;
-      rowptr[i + 1] = rowptr[i] + hc[i];
+      const int b = hc[size_t(which) * n + i];
+      if (b < 0) return false;
+      rowptr[i + 1] = rowptr[i] + b;
     }
     out.nnz = rowptr[n];
     out.rowptr = upload(c, rowptr);
     out.col = dalloc_c<int32_t>(c, size_t(out.nnz));
-    out.val = dalloc_c<T>(c, size_t(out.nnz));
-    DBuf res = dalloc_c<double>(c, size_t(n));
-    DBuf adj = dalloc_c<int16_t>(c, size_t(grid) * cap * std::max(1, J.wmax));
+    out.val = dalloc_c<float>(c, size_t(out.nnz));
+    SpInvJob& J = which == 0 ? J0 : J1;
     J.orp = out.rowptr.as<int64_t>();
     J.ocol = out.col.as<int32_t>();
     J.oval = out.val.p;
-    J.res = res.as<double>();
-    J.adj = adj.as<int16_t>();
-    launch_spinv_rows<T>(J, grid, c->stream);
+    J.res = res.as<double>() + size_t(which) * n;
+    launch_spinv_vals<float>(J, std::min(n, 1024), c->stream);
     HIPCHK(hipGetLastError());
-    std::vector<double> hr(n);
-    HIPCHK(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (double v : hr) worst = std::max(worst, v);
-    return true;
-  };
-  if (!run(cM, cT, inv) || !run(cT, cM, invT)) return false;
+  }
+  std::vector<double> hr(2 * size_t(n));
+  HIPCHK(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   c->prof.mass_iterations = steps;
-  c->prof.mass_residual = worst;
+  c->prof.mass_residual = *std::max_element(hr.begin(), hr.end());
   return true;
 }
 
@@ -1911,6 +1909,8 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   c->MinvT.clear();
   c->MinvS.clear();
   c->MinvTS.clear();
+  c->MS.clear();
+  c->MTS.clear();
   if (!c->gram_valid) build_gram_pattern(c);
   std::vector<int64_t> off, ld;
   int64_t tot = 0;
@@ -1948,13 +1948,13 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
     c->MA.push_back(std::move(MA));
     const int64_t ldm = ldmass(n);
-    if (c->optP.mass_method == 2) {  // sparse inverse on the graph ball (dense only if a ball overflows)
-      pmchwt_ctx::SparseInv a, b;
-      const bool ok = c->mass_f32 ? sparse_mass_inverse<float>(c, mass.as<double>() + off[m], n, a, b)
-                                  : sparse_mass_inverse<double>(c, mass.as<double>() + off[m], n, a, b);
-      if (ok) {
+    if (c->optP.mass_method == 0) {  // sparse inverse on the graph ball (dense only if a ball overflows)
+      pmchwt_ctx::SparseInv a, b, ma, mt;
+      if (sparse_mass_inverse(c, mass.as<double>() + off[m], n, a, b, ma, mt)) {
         c->MinvS.push_back(std::move(a));
         c->MinvTS.push_back(std::move(b));
+        c->MS.push_back(std::move(ma));
+        c->MTS.push_back(std::move(mt));
         c->Minv.emplace_back();  // dense FP32 copies for the matrix-core product: built when first needed
         c->MinvT.emplace_back();
         continue;
@@ -1962,11 +1962,13 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
       c->MinvS.resize(m);
       c->MinvTS.resize(m);
     }
+    c->MS.emplace_back();  // dense path: no refinement CSR
+    c->MTS.emplace_back();
     if (c->mass_f32) {
       // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
       // M_A^-1 with zero padding columns, the layout the products read
       DBuf Mf = dalloc_c<float>(c, size_t(ldm) * ldm), MfT = dalloc_c<float>(c, size_t(ldm) * ldm);
-      if (c->optP.mass_method == 1 || !cheb_inverse<float>(c, mass.as<double>() + off[m], n, ldm, Mf.as<float>(), true)) {
+      if (c->optP.mass_method != 2 || !cheb_inverse<float>(c, mass.as<double>() + off[m], n, ldm, Mf.as<float>(), true)) {
         launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
         gj_inverse_f32(c, Mf.as<float>(), int(ldm));
         c->prof.mass_iterations = 0;
@@ -2230,6 +2232,20 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     } else if (S.rowptr.p && c->mass_f32) {
       launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<float>(), s.topo.E, alpha, in + 2 * o,
                             out + 2 * o, nrhs, vs, E, c->stream);
+    } else if (S.rowptr.p && !c->MS.empty() && c->MS[m].rowptr.p) {
+      // FP64 preconditioner, sparse FP32 inverse X: out = alpha (X in + X (in - M X in))
+      const pmchwt_ctx::SparseInv& Mm = tr ? c->MTS[m] : c->MS[m];
+      const size_t need = size_t(2 * vs * nrhs);
+      if (c->mass_tmp.bytes < need * 8) realloc_c<double>(c, c->mass_tmp, need);
+      double* tmp = c->mass_tmp.as<double>();
+      const int64_t* rp = S.rowptr.as<int64_t>();
+      const int32_t* cl = S.col.as<int32_t>();
+      const float* vl = S.val.as<float>();
+      launch_spmv_real2_csr(rp, cl, vl, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
+      launch_spmv_real2_csr(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), s.topo.E, -1.0,
+                            out + 2 * o, tmp + 2 * o, nrhs, vs, E, c->stream);
+      launch_axpby_rows(tmp + 2 * o, in + 2 * o, vs, s.topo.E, E, nrhs, 1.0, alpha, c->stream);
+      launch_spmv_real2_csr(rp, cl, vl, s.topo.E, 1.0, tmp + 2 * o, out + 2 * o, nrhs, vs, E, c->stream, 1.0);
     } else if (S.rowptr.p) {
       launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<double>(), s.topo.E, alpha,
                             in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);

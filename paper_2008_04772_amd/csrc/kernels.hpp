@@ -93,9 +93,11 @@ void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t
 
 // Sparse approximate inverse of a mass matrix M (one scatterer, n x n): row i
 // on the ball of columns within `hops` steps of M's sparsity graph, by a
-// Chebyshev iteration for a spectrum in [a, b].  Pass 1 (launch_spinv_count)
-// writes the ball size of every row (-1 past `cap`); pass 2 writes the CSR
-// values at the row pointers orp.
+// Chebyshev iteration for a spectrum in [a, b].  Pass 1 (launch_spinv_ball)
+// writes the sorted ball of every row (spinv_cap() columns per row at most)
+// and its size (-1 past the capacity); pass 2 (launch_spinv_vals) the CSR
+// values at the row pointers orp.  Columns of M may hold spinv_wmax() entries
+// at most.
 struct SpInvJob {
   int n;
   const int64_t* rp;   // CSR of M (row pointers, columns): the search graph
@@ -103,19 +105,20 @@ struct SpInvJob {
   const int64_t* cp;   // CSC of M (column pointers, rows, values): the gather of (X M)
   const int32_t* ri;
   const double* cv;
-  int hops, cap, hash, wmax, steps;
+  int hops, steps;
   double a, b;
-  int32_t* count;      // pass 1 output
+  int32_t* count;      // pass 1: ball sizes
+  int32_t* ball;       // pass 1: n x spinv_cap() sorted columns
   const int64_t* orp;  // pass 2: output row pointers, columns, values (float or double), residuals
   int32_t* ocol;
   void* oval;
   double* res;
-  int16_t* adj;        // pass 2 scratch: grid x cap x wmax
 };
-size_t spinv_lds_bytes(int H, int CAP, bool values);
-void launch_spinv_count(const SpInvJob& J, int grid, hipStream_t st);
+int spinv_cap();
+int spinv_wmax();
+void launch_spinv_ball(const SpInvJob& J, int grid, hipStream_t st);
 template <typename T>
-void launch_spinv_rows(const SpInvJob& J, int grid, hipStream_t st);
+void launch_spinv_vals(const SpInvJob& J, int grid, hipStream_t st);
 void launch_csr_scatter_f32(const int64_t* rowptr, const int32_t* col, const float* val, int n, float* out, int64_t ld,
                             hipStream_t st);
 
@@ -322,10 +325,13 @@ void launch_cheb_step(T* X, T* D, int64_t ld, int n, const int32_t* eidx, const 
                       double inv_d, bool first, double* rn_part, hipStream_t st);
 template <typename T>
 void launch_identity_tail(T* X, int64_t ld, int n, hipStream_t st);
+// y = alpha A x + beta y (beta = 0: y overwritten) for both components
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
-                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
+                           double beta = 0.0);
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
-                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
+                           double beta = 0.0);
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);
@@ -383,6 +389,9 @@ void launch_gram_cg(const int64_t* rowptr, const int32_t* col, const double* val
                     hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b,
                   hipStream_t st);
+// the same on rows [0, rows) of both components (component stride cstride)
+void launch_axpby_rows(double* y, const double* x, int64_t vstride, int rows, int64_t cstride, int nrhs, double a,
+                       double b, hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);
 void launch_zero_f(float* p, int64_t n, hipStream_t st);
 void launch_pack_cols(const double* src, int64_t sstride, int E, int nvec, double* dst, hipStream_t st);

@@ -1342,6 +1342,23 @@ __global__ void k_axpby(double* y, const double* x, int64_t stride, int n, doubl
   y[o] = a * y[o] + b * x[o];
 }
 
+// rows [0, rows) of both components: element k < 4 rows (re/im, D/N)
+__global__ void k_axpby_rows(double* y, const double* x, int64_t vstride, int rows, int64_t cstride, double a,
+                             double b) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= 4 * int64_t(rows)) return;
+  const int64_t part = k / (2 * int64_t(rows)), w = k - part * 2 * int64_t(rows);
+  const int64_t o = 2 * (int64_t(r) * vstride + part * cstride) + w;
+  y[o] = a * y[o] + b * x[o];
+}
+
+void launch_axpby_rows(double* y, const double* x, int64_t vstride, int rows, int64_t cstride, int nrhs, double a,
+                       double b, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby_rows, dim3(unsigned((4 * int64_t(rows) + 255) / 256), nrhs), dim3(256), 0, st, y, x,
+                     vstride, rows, cstride, a, b);
+}
+
 void launch_axpby(double* y, const double* x, int64_t stride, int n, int nrhs, double a, double b, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, dim3(unsigned((2 * int64_t(n) + 255) / 256), nrhs), dim3(256), 0, st, y, x, stride, n,
                      a, b);
@@ -1990,7 +2007,7 @@ __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restric
                                                         const int32_t* __restrict__ col,
                                                         const VT* __restrict__ val, int rows, double alpha,
                                                         const double* __restrict__ x, double* y, int64_t vstride,
-                                                        int64_t cstride) {
+                                                        int64_t cstride, double beta) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
@@ -2020,17 +2037,25 @@ __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restric
     for (int r = 0; r < NR; ++r) {
       double* q0 = y + 2 * (int64_t(r) * vstride + row);
       double* q1 = q0 + 2 * cstride;
-      q0[0] = alpha * acc[r][0];
-      q0[1] = alpha * acc[r][1];
-      q1[0] = alpha * acc[r][2];
-      q1[1] = alpha * acc[r][3];
+      if (beta == 0.0) {
+        q0[0] = alpha * acc[r][0];
+        q0[1] = alpha * acc[r][1];
+        q1[0] = alpha * acc[r][2];
+        q1[1] = alpha * acc[r][3];
+      } else {
+        q0[0] = alpha * acc[r][0] + beta * q0[0];
+        q0[1] = alpha * acc[r][1] + beta * q0[1];
+        q1[0] = alpha * acc[r][2] + beta * q1[0];
+        q1[1] = alpha * acc[r][3] + beta * q1[1];
+      }
     }
   }
 }
 
 template <typename VT>
 static void spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const VT* val, int rows, double alpha,
-                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
+                           double beta) {
   const dim3 grid(unsigned((rows + 3) / 4)), block(256);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
@@ -2038,22 +2063,24 @@ static void spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const VT* 
     double* yy = y + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
       hipLaunchKernelGGL((k_spmv_real2_csr<4, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
-                         vstride, cstride);
+                         vstride, cstride, beta);
       r0 += 4;
     } else {
       hipLaunchKernelGGL((k_spmv_real2_csr<1, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
-                         vstride, cstride);
+                         vstride, cstride, beta);
       r0 += 1;
     }
   }
 }
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
-                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
-  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st);
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
+                           double beta) {
+  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st, beta);
 }
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
-                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st) {
-  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st);
+                           const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
+                           double beta) {
+  spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st, beta);
 }
 
 // sum of v over the 1024 threads of the workgroup, in a fixed tree order;
