@@ -8,13 +8,12 @@ preconditioner leaves unchanged.
 
 Calls only oracle/ (and synth/ for the mesh and the wave).  The dense
 assembly is spread over processes by ranges of test triangles
-(oracle.operators.assemble_rwg_tests); the direct solve uses all cores.
+(oracle.parallel); the direct solve uses all cores.
 
     python tests/golden/make_sphere5120.py [--procs N]
 """
 
 import argparse
-import multiprocessing as mp
 import os
 import platform
 import sys
@@ -26,37 +25,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle import operators as ops  # noqa: E402
+from oracle import parallel  # noqa: E402
 from oracle import pmchwt as opm  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sphere5120_sigma.txt")
 EPS, K_E = 3.17 + 0.01j, 5.0
-_JOB = {}
-
-
-def _part(args):
-    t0, t1 = args
-    from threadpoolctl import threadpool_limits
-    topo, k, q, n = _JOB["topo"], _JOB["k"], _JOB["q"], _JOB["n"]
-    with threadpool_limits(1):
-        d = ops.assemble_rwg_tests(topo, k, t0, t1, q, n)
-    rows = np.unique(topo.t2e[t0:t1])
-    return rows, d["S"][rows], d["C"][rows]
-
-
-def make_parallel_assembler(procs):
-    def assemble(topo, k, q, n):
-        _JOB.update(topo=topo, k=k, q=q, n=n)
-        step = max(1, topo.F // (4 * procs))
-        ranges = [(t, min(topo.F, t + step)) for t in range(0, topo.F, step)]
-        S = np.zeros((topo.E, topo.E), dtype=np.complex128)
-        C = np.zeros((topo.E, topo.E), dtype=np.complex128)
-        with mp.get_context("fork").Pool(procs) as pool:
-            for rows, s, c in pool.imap_unordered(_part, ranges):
-                S[rows] += s
-                C[rows] += c
-        return {"S": S, "C": C}
-    return assemble
 
 
 def main():
@@ -67,7 +40,7 @@ def main():
     d, p = synth.single_wave()
     t0 = time.perf_counter()
     pr = opm.Problem([mesh], EPS, K_E)
-    pr.assemble_A(make_parallel_assembler(args.procs))
+    pr.assemble_A(parallel.parallel_assembler(args.procs))
     t_asm = time.perf_counter() - t0
     b = pr.rhs(d, p)
     t_rhs = time.perf_counter() - t0 - t_asm
