@@ -281,6 +281,24 @@ int pmchwt_solve(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols
 int pmchwt_far_field(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs,
                      const double *obs, int32_t nobs, pmchwt_complex *F_out);
 
+/* Total electric field at npts points (the Stratton-Chu representation of
+ * Section 2 with the solved traces; the field maps of Section 5).  Outside
+ * every scatterer E = E^inc + E^s, E^s = -sum_m [H^e(gamma_D E^s) +
+ * E^e(gamma_N E^s)] at k_e; inside scatterer m the interior field
+ * H^i_m(gamma_D E^i) + E^i_m(gamma_N E^i) at k_m, whose traces are the
+ * solved ones plus the L2 projection of the incident traces onto RWG (the
+ * transmission conditions).  currents[nrhs * N] as pmchwt_solve returned them
+ * for the plane waves dirs / pols (same conventions); points double[npts*3];
+ * E_out[nrhs * npts * 3] (point-major per right-hand side); region_out
+ * int32[npts] or NULL: -1 outside, m inside scatterer m (decided by the solid
+ * angle each closed surface subtends).  The surface integrals use the 6-point
+ * rule on every triangle: accurate at points farther from the surface than
+ * about one triangle size.  Errors: STATE before pmchwt_assemble,
+ * INVALID_ARG.                                                                */
+int pmchwt_near_field(pmchwt_ctx *ctx, const pmchwt_complex *currents, int32_t nrhs, const double *dirs,
+                      const pmchwt_complex *pols, const double *points, int32_t npts, pmchwt_complex *E_out,
+                      int32_t *region_out);
+
 /* pmchwt_far_field without any device allocation, for callers that cannot
  * allocate device memory while they run (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc).  Same arguments, layout and

@@ -129,6 +129,7 @@ _SIGS = {
                       ctypes.POINTER(pmchwt_solve_stats)], ctypes.c_int),
     "pmchwt_far_field": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
     "pmchwt_far_field_noalloc": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_near_field": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, ctypes.c_int32, _pc, _pi32], ctypes.c_int),
     "pmchwt_cross_sections": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, _pd], ctypes.c_int),
     "pmchwt_bc_fields": ([_pd, ctypes.c_int32, _pi32, ctypes.c_int32, _pi64, _pi32, _pd], ctypes.c_int),
     "pmchwt_get_profile": ([_P, ctypes.POINTER(pmchwt_profile)], ctypes.c_int),
@@ -313,6 +314,17 @@ def pmchwt_far_field_noalloc(ctx, currents, obs):
     return F
 
 
+def pmchwt_near_field(ctx, currents, dirs, pols, points):
+    x = _c128(np.atleast_2d(currents))
+    d, p = _waves(dirs, pols)
+    pts = _f64(points).reshape(-1, 3)
+    E = np.zeros((x.shape[0], len(pts), 3), dtype=np.complex128)
+    reg = np.zeros(len(pts), dtype=np.int32)
+    _check(ctx, _lib.pmchwt_near_field(ctx, _ptr(x, _pc), x.shape[0], _ptr(d, _pd), _ptr(p, _pc), _ptr(pts, _pd),
+                                       len(pts), _ptr(E, _pc), _ptr(reg, _pi32)))
+    return E, reg
+
+
 def pmchwt_cross_sections(ctx, currents, dirs, pols):
     x = _c128(np.atleast_2d(currents))
     d, p = _waves(dirs, pols)
@@ -407,6 +419,9 @@ class Context:
 
     def far_field_noalloc(self, currents, obs):
         return pmchwt_far_field_noalloc(self.h, currents, obs)
+
+    def near_field(self, currents, dirs, pols, points):
+        return pmchwt_near_field(self.h, currents, dirs, pols, points)
 
     def cross_sections(self, currents, dirs, pols):
         return pmchwt_cross_sections(self.h, currents, dirs, pols)

@@ -2317,9 +2317,9 @@ void gram_cg(pmchwt_ctx* c, const int64_t* rowptr, int n, const double* b_in, do
 }
 
 // Galerkin right-hand side into device buffer b (internal layout)
-void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b,
-               bool fp64_interior = false) {
-  const int64_t E = c->E_tot, vs = vlen(c);
+// Plane-wave data on the device: directions (3 per wave) and polarisations
+// (re, im per component)
+void upload_waves(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, DBuf& dd, DBuf& dp) {
   std::vector<double> hp(6 * size_t(nrhs));
   for (int r = 0; r < nrhs; ++r)
     for (int d = 0; d < 3; ++d) {
@@ -2327,10 +2327,20 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
       hp[6 * r + 2 * d + 1] = pols[3 * r + d].im;
     }
   std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
-  DBuf dd = upload(c, hd), dp = upload(c, hp);
-  DBuf g = dalloc_c<double>(c, size_t(2 * vs * nrhs)), h = dalloc_c<double>(c, size_t(2 * vs * nrhs)),
-       cinc = dalloc_c<double>(c, size_t(2 * vs * nrhs)), t = dalloc_c<double>(c, size_t(2 * vs * nrhs));
-  launch_zero(g.as<double>(), 2 * vs * nrhs, c->stream);
+  dd = upload(c, hd);
+  dp = upload(c, hp);
+}
+
+// Incident-field projections (device buffers, internal layout): g_i = int
+// u^inc . (n x rwg_i) and c_inc = G^-1 int u^inc . rwg_i (the L2 projection
+// onto RWG, G the RWG Gram matrix)
+void incident_projection(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* g_out,
+                         double* cinc_out) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  DBuf dd, dp;
+  upload_waves(c, dirs, pols, nrhs, dd, dp);
+  DBuf h = dalloc_c<double>(c, size_t(2 * vs * nrhs));
+  launch_zero(g_out, 2 * vs * nrhs, c->stream);
   launch_zero(h.as<double>(), 2 * vs * nrhs, c->stream);
   RhsJob j{};
   j.F = c->F_tot;
@@ -2339,7 +2349,7 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   j.pols = dp.as<double>();
   j.k_ext = c->k_ext;
   j.E_tot = E;
-  j.g = g.as<double>();
+  j.g = g_out;
   j.h = h.as<double>();
   launch_rhs(asm_params<double>(c), j, c->stream);
   HIPCHK(hipGetLastError());
@@ -2347,11 +2357,17 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   // RWG Gram matrix (both components of every wave at once)
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
-    const int n = s.topo.E;
-    const int nvec = 2 * nrhs;
-    gram_cg(c, c->g_rowptr.as<int64_t>() + s.edge_off, n, h.as<double>() + 2 * int64_t(s.edge_off),
-            cinc.as<double>() + 2 * int64_t(s.edge_off), E, nvec);
+    gram_cg(c, c->g_rowptr.as<int64_t>() + s.edge_off, s.topo.E, h.as<double>() + 2 * int64_t(s.edge_off),
+            cinc_out + 2 * int64_t(s.edge_off), E, 2 * nrhs);
   }
+}
+
+void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b,
+               bool fp64_interior = false) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  DBuf g = dalloc_c<double>(c, size_t(2 * vs * nrhs)), cinc = dalloc_c<double>(c, size_t(2 * vs * nrhs)),
+       t = dalloc_c<double>(c, size_t(2 * vs * nrhs));
+  incident_projection(c, dirs, pols, nrhs, g.as<double>(), cinc.as<double>());
   // b = g/2 - A^i c_inc
   if (fp64_interior) {
     apply_A_free(c, cinc.as<double>(), t.as<double>(), nrhs, false);
@@ -3233,6 +3249,43 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     HIPCHK(hipMemcpyAsync(hf.data(), dF.p, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < hf.size() / 2; ++k) F[k] = {hf[2 * k], hf[2 * k + 1]};
+    return PMCHWT_OK;
+  });
+}
+
+int pmchwt_near_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* dirs,
+                      const pmchwt_complex* pols, const double* pts, int32_t npts, pmchwt_complex* E_out,
+                      int32_t* region_out) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (nrhs <= 0 || npts <= 0 || !cur || !dirs || !pols || !pts || !E_out)
+      return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    const int64_t vs = vlen(c), nd = 2 * vs * nrhs;
+    std::vector<double> h;
+    to_internal(c, cur, nrhs, h);
+    DBuf dx = upload(c, h), g = dalloc_c<double>(c, size_t(nd)), cinc = dalloc_c<double>(c, size_t(nd));
+    incident_projection(c, dirs, pols, nrhs, g.as<double>(), cinc.as<double>());
+    DBuf dd, dp;
+    upload_waves(c, dirs, pols, nrhs, dd, dp);
+    std::vector<int32_t> toff;
+    for (auto& s : c->sc) toff.push_back(s.tri_off);
+    toff.push_back(c->F_tot);
+    std::vector<double> hp(pts, pts + 3 * size_t(npts));
+    DBuf dtoff = upload(c, toff), dpts = upload(c, hp), dreg = dalloc_c<int32_t>(c, size_t(npts));
+    const int64_t nq = int64_t(c->F_tot) * 6;
+    DBuf yp = dalloc_c<double>(c, size_t(4 * nq)), J = dalloc_c<double>(c, size_t(near_j_doubles() * nq * nrhs)),
+         dE = dalloc_c<double>(c, 6 * size_t(npts) * nrhs);
+    launch_near_field(asm_params<double>(c), dtoff.as<int32_t>(), int(c->sc.size()), dx.as<double>(),
+                      cinc.as<double>(), c->E_tot, nrhs, dpts.as<double>(), npts, dd.as<double>(), dp.as<double>(),
+                      c->k_ext, c->k_int.as<double>(), dreg.as<int32_t>(), yp.as<double>(), J.as<double>(),
+                      dE.as<double>(), c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hE(6 * size_t(npts) * nrhs);
+    HIPCHK(hipMemcpyAsync(hE.data(), dE.p, hE.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    if (region_out)
+      HIPCHK(hipMemcpyAsync(region_out, dreg.p, 4 * size_t(npts), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < hE.size() / 2; ++k) E_out[k] = {hE[2 * k], hE[2 * k + 1]};
     return PMCHWT_OK;
   });
 }

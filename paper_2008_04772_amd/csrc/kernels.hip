@@ -7,3 +7,4 @@
 #include "mfma.inl"
 #include "refine.inl"
 #include "massinv.inl"
+#include "nearfield.inl"

@@ -407,6 +407,14 @@ struct FarPlan {
 };
 FarPlan far_field_plan(int F, int nrhs, int nobs);
 FarPlan far_field_plan_capped(int F, int nrhs, int nobs, int64_t max_part);
+// Total electric field at points (region per point, rule-point data and the
+// sums; ypts: 4 doubles per rule point, J: near_j_doubles() per rhs and rule
+// point, 6 F rule points)
+void launch_near_field(const AsmParams<double>& g, const int32_t* tri_off, int nscat, const double* x,
+                       const double* cinc, int64_t E_tot, int nrhs, const double* pts, int npts,
+                       const double* dirs, const double* pols, double k_ext, const double* k_int, int32_t* region,
+                       double* ypts, double* J, double* Eout, hipStream_t st);
+int near_j_doubles();
 void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
                       const double* obs, int nobs, double* F_out, const FarPlan& plan, double* ypts, double* J,
                       double* part, hipStream_t st);
