@@ -251,7 +251,8 @@ struct pmchwt_ctx {
     double chi = 0;
     bool cross = false;
     DBuf cpairs, slot_off, slot_pos;
-    int64_t npairs = 0, bary_pairs = 0;
+    int64_t npairs = 0, bary_pairs = 0, nnz = 0;
+    bool host_valid = false;  // h_rowptr / h_col hold the device pattern
   } nf;
   struct {
     int n = -1;
@@ -264,7 +265,6 @@ struct pmchwt_ctx {
     // FP64 local blocks of the singular pairs (the matrix-free FP64 product
     // and the symmetric-tile correction read them)
     DBuf blk;
-    std::vector<int32_t> h_pairs;  // host copy of the pair list
   } sing;
   DBuf free_slots;  // pass-1 output of the matrix-free FP64 product
   bool cells_valid = false;
@@ -743,14 +743,28 @@ void build_comb(pmchwt_ctx* c) {
   c->comb = true;
 }
 
+// Copies of a few device scalars to the host (one synchronisation).
+void read_scalars(pmchwt_ctx* c, std::initializer_list<std::pair<void*, std::pair<const void*, size_t>>> items) {
+  for (auto& it : items) HIPCHK(hipMemcpyAsync(it.first, it.second.first, it.second.second, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+int pow2_ceil(int64_t n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
 // Index tables of the symmetric-tile form (one scatterer, geometry only):
-// the upper tiles in row-major order and the correction pattern, i.e. every
-// entry (r, c) below the diagonal tiles that a pair of triangles sharing a
-// vertex (the Sauter-Schwab pairs) contributes to.
+// the upper tiles in row-major order (host) and the correction pattern, i.e.
+// every entry (r, c) below the diagonal tiles that a pair of triangles
+// sharing a vertex (the Sauter-Schwab pairs) contributes to, with the
+// singular local-block entries that make it: + for those added to X_rc, -
+// for those added to X_cr (classification kernels, from the device pair list).
 void sym_tables(pmchwt_ctx* c) {
   const int n = int(c->E_tot);
   if (c->sym.n == n) return;
-  const Topo& T = c->sc[0].topo;
+  hipStream_t st = c->stream;
   const int nt = (n + SYM_T - 1) / SYM_T;
   std::vector<int32_t> tij;
   for (int I = 0; I < nt; ++I)
@@ -758,71 +772,109 @@ void sym_tables(pmchwt_ctx* c) {
       tij.push_back(I);
       tij.push_back(J);
     }
-  std::vector<std::vector<int32_t>> v2t(T.nv);
-  for (int f = 0; f < T.F; ++f)
-    for (int a = 0; a < 3; ++a) v2t[T.t[3 * f + a]].push_back(f);
-  std::vector<std::vector<int32_t>> rows(n);
-  std::vector<int32_t> nb;
-  for (int f = 0; f < T.F; ++f) {
-    nb.clear();
-    for (int a = 0; a < 3; ++a)
-      for (int g : v2t[T.t[3 * f + a]]) nb.push_back(g);
-    std::sort(nb.begin(), nb.end());
-    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-    for (int g : nb)
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-          const int r = T.t2e[3 * f + a], cc = T.t2e[3 * g + b];
-          if (r / SYM_T > cc / SYM_T) rows[r].push_back(cc);
-        }
-  }
-  std::vector<int64_t> rowptr(n + 1, 0);
-  std::vector<int32_t> crow, col;
-  for (int r = 0; r < n; ++r) {
-    auto& v = rows[r];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    for (int cc : v) {
-      crow.push_back(r);
-      col.push_back(cc);
-    }
-    rowptr[r + 1] = int64_t(col.size());
-  }
-  // singular local-block entries of every correction entry (r, c): + for
-  // those added to X_rc, - for those added to X_cr
-  std::unordered_map<int64_t, int64_t> at;
-  at.reserve(col.size() * 2);
-  for (size_t k = 0; k < col.size(); ++k) at.emplace(int64_t(crow[k]) * n + col[k], int64_t(k));
-  std::vector<std::vector<int32_t>> its(col.size());
-  const std::vector<int32_t>& sp = c->sing.h_pairs;
-  for (size_t q = 0; q < sp.size() / 2; ++q) {
-    const int f = sp[2 * q], g = sp[2 * q + 1];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const int r = T.t2e[3 * f + a], cc = T.t2e[3 * g + b];
-        const int32_t e = int32_t(9 * q + 3 * a + b);
-        auto i1 = at.find(int64_t(r) * n + cc);
-        if (i1 != at.end()) its[size_t(i1->second)].push_back(e << 1);
-        auto i2 = at.find(int64_t(cc) * n + r);
-        if (i2 != at.end()) its[size_t(i2->second)].push_back((e << 1) | 1);
-      }
-  }
-  std::vector<int64_t> iptr(col.size() + 1, 0);
-  std::vector<int32_t> item;
-  for (size_t k = 0; k < col.size(); ++k) {
-    item.insert(item.end(), its[k].begin(), its[k].end());
-    iptr[k + 1] = int64_t(item.size());
-  }
-  c->sym.iptr = upload(c, iptr);
-  c->sym.item = upload(c, item);
+  SymRecJob J{};
+  J.npairs = c->sing.npairs;
+  J.pairs = c->sing.pairs.as<int32_t>();
+  J.t2e = c->t2e.as<int32_t>();
+  J.F = c->F_tot;
+  J.tile = SYM_T;
+  J.n = n;
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), stats = dalloc_c<int32_t>(c, 4);
+  DBuf recptr = dalloc_c<int64_t>(c, size_t(n) + 1), rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  launch_cls_fill_i32(cnt.as<int32_t>(), n, 0, st);
+  launch_cls_fill_i32(stats.as<int32_t>(), 4, 0, st);
+  J.cnt = cnt.as<int32_t>();
+  J.maxrec = stats.as<int32_t>();
+  launch_sym_records(J, 0, st);
+  launch_scan_i32(cnt.as<int32_t>(), n, recptr.as<int64_t>(), st);
+  HIPCHK(hipGetLastError());
+  int64_t nrec = 0;
+  int32_t maxrec = 0;
+  read_scalars(c, {{&nrec, {recptr.as<int64_t>() + n, 8}}, {&maxrec, {stats.as<int32_t>(), 4}}});
+  if (maxrec > 4096) throw Fail{PMCHWT_ERR_INVALID_MESH, "vertex valence too high for the symmetric-tile tables"};
+  DBuf rec = dalloc_c<int64_t>(c, size_t(std::max<int64_t>(nrec, 1)));
+  launch_cls_fill_i32(cnt.as<int32_t>(), n, 0, st);
+  J.recptr = recptr.as<int64_t>();
+  J.cur = cnt.as<int32_t>();
+  J.rec = rec.as<int64_t>();
+  launch_sym_records(J, 1, st);
+  launch_sym_sort(J, pow2_ceil(std::max(maxrec, 1)), st);
+  launch_scan_i32(cnt.as<int32_t>(), n, rowptr.as<int64_t>(), st);
+  HIPCHK(hipGetLastError());
+  int64_t nnz = 0;
+  read_scalars(c, {{&nnz, {rowptr.as<int64_t>() + n, 8}}});
+  c->sym.crow = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+  c->sym.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+  c->sym.iptr = dalloc_c<int64_t>(c, size_t(nnz) + 1);
+  c->sym.item = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nrec, 1)));
+  J.rowptr = rowptr.as<int64_t>();
+  J.crow = c->sym.crow.as<int32_t>();
+  J.col = c->sym.col.as<int32_t>();
+  J.iptr = c->sym.iptr.as<int64_t>();
+  J.item = c->sym.item.as<int32_t>();
+  launch_sym_emit(J, st);
+  launch_cls_set_i64(c->sym.iptr.as<int64_t>() + nnz, nrec, st);
+  HIPCHK(hipGetLastError());
   c->sym.nt = nt;
   c->sym.ntiles = int64_t(tij.size() / 2);
-  c->sym.nnz = int64_t(col.size());
+  c->sym.nnz = nnz;
   c->sym.tij = upload(c, tij);
-  c->sym.rowptr = upload(c, rowptr);
-  c->sym.crow = upload(c, crow);
-  c->sym.col = upload(c, col);
+  c->sym.rowptr = std::move(rowptr);
   c->sym.n = n;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Singular pairs (ordered triangle pairs sharing at least one vertex; the
+// pairs of a test triangle contiguous, trial triangles ascending) and their
+// Sauter-Schwab point pairs, by the classification kernels.  The host only
+// lists the triangles at each vertex (counting sort, O(F)).
+void singular_list(pmchwt_ctx* c, const int* npts) {
+  hipStream_t st = c->stream;
+  const int F = c->F_tot;
+  std::vector<int32_t> vptr(size_t(c->nv_tot) + 1, 0), v2t(3 * size_t(F));
+  for (auto& s : c->sc)
+    for (int f = 0; f < s.topo.F; ++f)
+      for (int a = 0; a < 3; ++a) ++vptr[size_t(s.vert_off + s.topo.t[3 * size_t(f) + a]) + 1];
+  for (size_t v = 0; v + 1 < vptr.size(); ++v) vptr[v + 1] += vptr[v];
+  {
+    std::vector<int32_t> cur(vptr.begin(), vptr.end() - 1);
+    for (auto& s : c->sc)
+      for (int f = 0; f < s.topo.F; ++f)
+        for (int a = 0; a < 3; ++a) v2t[size_t(cur[size_t(s.vert_off + s.topo.t[3 * size_t(f) + a])]++)] = s.tri_off + f;
+  }
+  DBuf d_vptr = upload(c, vptr), d_v2t = upload(c, v2t);
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(F)), stats = dalloc_c<int32_t>(c, 4), pts = dalloc_c<int64_t>(c, 1);
+  DBuf sptr = dalloc_c<int64_t>(c, size_t(F) + 1);
+  launch_cls_fill_i32(stats.as<int32_t>(), 4, 0, st);
+  launch_cls_set_i64(pts.as<int64_t>(), 0, st);
+  SingListJob J{};
+  J.F = F;
+  J.tvid = c->tvid.as<int32_t>();
+  J.v2t_ptr = d_vptr.as<int32_t>();
+  J.v2t = d_v2t.as<int32_t>();
+  J.cnt = cnt.as<int32_t>();
+  J.flag = stats.as<int32_t>();
+  for (int k = 0; k < 4; ++k) J.npts[k] = npts[k];
+  launch_sing_list(J, false, st);
+  launch_scan_i32(cnt.as<int32_t>(), F, sptr.as<int64_t>(), st);
+  HIPCHK(hipGetLastError());
+  int64_t npairs = 0;
+  int32_t over = 0;
+  read_scalars(c, {{&npairs, {sptr.as<int64_t>() + F, 8}}, {&over, {stats.as<int32_t>(), 4}}});
+  if (over)
+    throw Fail{PMCHWT_ERR_INVALID_MESH, "a triangle shares a vertex with more than " +
+                                            std::to_string(sing_neighbour_capacity()) + " triangles"};
+  c->sing.pairs = dalloc_c<int32_t>(c, size_t(2 * std::max<int64_t>(npairs, 1)));
+  J.sptr = sptr.as<int64_t>();
+  J.pairs = c->sing.pairs.as<int32_t>();
+  J.point_pairs = reinterpret_cast<unsigned long long*>(pts.p);
+  launch_sing_list(J, true, st);
+  HIPCHK(hipGetLastError());
+  int64_t np = 0;
+  read_scalars(c, {{&np, {pts.p, 8}}});
+  c->sing.ptr = std::move(sptr);
+  c->sing.npairs = npairs;
+  c->sing.point_pairs = np;
 }
 
 template <typename M>
@@ -862,39 +914,10 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   // singular pair list (ordered pairs sharing at least one vertex) and the
   // Sauter-Schwab tables of order n: index tables, built once per geometry
   if (c->sing.n != o.n_singular) {
-    std::vector<std::vector<int32_t>> v2t(c->nv_tot);
-    for (auto& s : c->sc)
-      for (int f = 0; f < s.topo.F; ++f)
-        for (int a = 0; a < 3; ++a) v2t[s.vert_off + s.topo.t[3 * f + a]].push_back(s.tri_off + f);
-    std::vector<int32_t> pairs;
-    int64_t npts_sing = 0;
     SSTables ss;
     build_ss(c, o.n_singular, ss);
-    for (auto& s : c->sc)
-      for (int f = 0; f < s.topo.F; ++f) {
-        const int g = s.tri_off + f;
-        std::vector<int32_t> nb;
-        for (int a = 0; a < 3; ++a)
-          for (int t : v2t[s.vert_off + s.topo.t[3 * f + a]]) nb.push_back(t);
-        std::sort(nb.begin(), nb.end());
-        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-        for (int t : nb) {
-          pairs.push_back(g);
-          pairs.push_back(t);
-          int shared = 0;
-          const int t_loc = t - s.tri_off;
-          for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) shared += (s.topo.t[3 * f + a] == s.topo.t[3 * t_loc + b]);
-          npts_sing += ss.npts[shared];
-        }
-      }
-    c->sing.pairs = upload(c, pairs);
-    c->sing.h_pairs = pairs;
-    c->sing.npairs = int64_t(pairs.size() / 2);
-    std::vector<int64_t> sptr(size_t(c->F_tot) + 1, 0);
-    for (size_t q = 0; q < pairs.size() / 2; ++q) ++sptr[size_t(pairs[2 * q]) + 1];
-    for (int t = 0; t < c->F_tot; ++t) sptr[t + 1] += sptr[t];
-    c->sing.ptr = upload(c, sptr);
+    const int npts_by_shared[4] = {0, ss.npts[1], ss.npts[2], ss.npts[3]};
+    singular_list(c, npts_by_shared);
     std::vector<int32_t> eslot(2 * size_t(c->E_tot), 0);
     for (auto& sc : c->sc)
       for (int f = 0; f < sc.topo.F; ++f)
@@ -903,7 +926,6 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
           eslot[2 * size_t(e) + (sc.topo.sgn[3 * f + a] > 0 ? 0 : 1)] = 3 * (sc.tri_off + f) + a;
         }
     c->sing.edge_slots = upload(c, eslot);
-    c->sing.point_pairs = npts_sing;
     for (int k = 1; k <= 3; ++k) {
       c->sing.tab[k] = std::move(ss.tab[k]);
       c->sing.npts[k] = ss.npts[k];
@@ -942,30 +964,33 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     }
     std::vector<int32_t> cptr{0}, ctri, cedge{0};
     std::vector<int16_t> emap(4 * size_t(c->E_tot));
-    std::unordered_map<int32_t, int16_t> pos;
-    int maxl = 0;
+    // chunk membership of each trial triangle by stamp (the chunk index)
+    std::vector<int32_t> stamp(size_t(c->F_tot), -1);
+    std::vector<int16_t> spos(size_t(c->F_tot), 0);
+    int chunk = 0, held = 0, maxl = 0;
     auto slot = [&](int32_t t) -> int16_t {
-      auto it = pos.find(t);
-      if (it != pos.end()) return it->second;
-      const int16_t q = int16_t(pos.size());
-      pos.emplace(t, q);
-      ctri.push_back(t);
-      return q;
+      if (stamp[t] != chunk) {
+        stamp[t] = chunk;
+        spos[t] = int16_t(held++);
+        ctri.push_back(t);
+      }
+      return spos[t];
     };
     for (int j = 0; j < c->E_tot; ++j) {
-      const int add = int(!pos.count(tp[j])) + int(!pos.count(tm[j]));
-      if (int(pos.size()) + add > CH) {  // close the chunk before edge j
-        maxl = std::max(maxl, int(pos.size()));
+      const int add = int(stamp[tp[j]] != chunk) + int(stamp[tm[j]] != chunk);
+      if (held + add > CH) {  // close the chunk before edge j
+        maxl = std::max(maxl, held);
         cptr.push_back(int32_t(ctri.size()));
         cedge.push_back(j);
-        pos.clear();
+        ++chunk;
+        held = 0;
       }
       emap[4 * size_t(j) + 0] = slot(tp[j]);
       emap[4 * size_t(j) + 1] = bp[j];
       emap[4 * size_t(j) + 2] = slot(tm[j]);
       emap[4 * size_t(j) + 3] = bm[j];
     }
-    maxl = std::max(maxl, int(pos.size()));
+    maxl = std::max(maxl, held);
     cptr.push_back(int32_t(ctri.size()));
     cedge.push_back(c->E_tot);
     const int nch = int(cedge.size()) - 1;
@@ -1155,8 +1180,8 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   }
   c->prof.ms_assemble_A = all.stop();
   c->prof.recompute = c->recompute;
-  // work counters: disjoint ordered pairs by class (host count, same rule as
-  // the kernel); pure metadata of the mesh and the rule orders, kept across
+  // work counters: disjoint ordered pairs by class (same rule as the
+  // kernel); pure metadata of the mesh and the rule orders, kept across
   // assemblies of the same geometry
   const int64_t ckey = (int64_t(c->F_tot) << 12) | (o.q_near << 8) | (o.q_medium << 4) | o.q_far;
   int64_t reg_pairs = 0, reg_pts = 0;
@@ -1164,43 +1189,16 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     reg_pairs = c->count_pairs;
     reg_pts = c->count_pts;
   } else {
-    const int F = c->F_tot;
-    std::vector<double> cen(3 * size_t(F)), dm(F);
-    std::vector<std::array<int32_t, 3>> vid(F);
-    std::vector<int32_t> scat(F);
-    for (size_t m = 0; m < c->sc.size(); ++m) {
-      const Scat& s = c->sc[m];
-      for (int f = 0; f < s.topo.F; ++f) {
-        const int g = s.tri_off + f;
-        double P[3][3];
-        for (int k = 0; k < 3; ++k)
-          for (int d = 0; d < 3; ++d) P[k][d] = s.topo.v[3 * size_t(s.topo.t[3 * f + k]) + d];
-        for (int d = 0; d < 3; ++d) cen[3 * size_t(g) + d] = (P[0][d] + P[1][d] + P[2][d]) / 3.0;
-        double mm = 0;
-        const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
-        for (auto& q : pr) {
-          const double ex = P[q[0]][0] - P[q[1]][0], ey = P[q[0]][1] - P[q[1]][1], ez = P[q[0]][2] - P[q[1]][2];
-          mm = std::max(mm, ex * ex + ey * ey + ez * ez);
-        }
-        dm[g] = mm;
-        for (int a = 0; a < 3; ++a) vid[g][a] = s.vert_off + s.topo.t[3 * f + a];
-      }
-    }
+    // exact count over all unordered pairs on the device, with the class rule
+    // of the regular kernel
     const int np[5] = {0, 1, 3, 4, 6};
-    const int qs[3] = {o.q_near, o.q_medium, o.q_far};
-    // sample-free exact count over all pairs (host, O(F^2) integer/compare work)
-    for (int a = 0; a < F; ++a)
-      for (int b = a + 1; b < F; ++b) {
-        bool sh = false;
-        for (int i = 0; i < 3 && !sh; ++i)
-          for (int j = 0; j < 3; ++j) sh |= (vid[a][i] == vid[b][j]);
-        if (sh) continue;
-        const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1], dz = cen[3 * a + 2] - cen[3 * b + 2];
-        const double d2 = dx * dx + dy * dy + dz * dz, m2 = std::max(dm[a], dm[b]);
-        const int cls = d2 < 4.0 * m2 ? 0 : (d2 < 16.0 * m2 ? 1 : 2);
-        reg_pairs += 2;
-        reg_pts += 2 * int64_t(np[qs[cls]]) * np[qs[cls]];
-      }
+    DBuf cntd = dalloc_c<int64_t>(c, 2);
+    launch_cls_set_i64(cntd.as<int64_t>(), 0, c->stream);
+    launch_cls_set_i64(cntd.as<int64_t>() + 1, 0, c->stream);
+    launch_count_regular(c->F_tot, c->tcen.as<double>(), c->tdiam2.as<double>(), c->tvid.as<int32_t>(), np[o.q_near],
+                         np[o.q_medium], np[o.q_far], reinterpret_cast<unsigned long long*>(cntd.p), c->stream);
+    HIPCHK(hipGetLastError());
+    read_scalars(c, {{&reg_pairs, {cntd.as<int64_t>(), 8}}, {&reg_pts, {cntd.as<int64_t>() + 1, 8}}});
     c->count_key = ckey;
     c->count_pairs = reg_pairs;
     c->count_pts = reg_pts;
@@ -1310,89 +1308,7 @@ void upload_cells(pmchwt_ctx* c, CellDev& d) {
   d.edge_off = upload(c, eoff);
 }
 
-// Kept entries of P: (i, j) with dist(bbox_i, bbox_j) <= chi (chi < 0: all),
-// restricted to diagonal scatterer blocks unless `cross`.
-void build_pattern(pmchwt_ctx* c, double chi, bool cross, std::vector<int64_t>& rowptr, std::vector<int32_t>& col) {
-  const int E = c->E_tot;
-  std::vector<double> lo(3 * size_t(E)), hi(3 * size_t(E));
-  std::vector<int32_t> scat(E);
-  for (size_t m = 0; m < c->sc.size(); ++m) {
-    const Scat& s = c->sc[m];
-    for (int e = 0; e < s.topo.E; ++e) {
-      for (int d = 0; d < 3; ++d) {
-        lo[3 * size_t(s.edge_off + e) + d] = s.dual.bbox[6 * size_t(e) + d];
-        hi[3 * size_t(s.edge_off + e) + d] = s.dual.bbox[6 * size_t(e) + 3 + d];
-      }
-      scat[s.edge_off + e] = int32_t(m);
-    }
-  }
-  rowptr.assign(1, 0);
-  col.clear();
-  auto keep = [&](int i, int j) {
-    if (!cross && scat[i] != scat[j]) return false;
-    if (chi < 0) return true;
-    double g2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      const double g = std::max(0.0, std::max(lo[3 * size_t(j) + d] - hi[3 * size_t(i) + d],
-                                              lo[3 * size_t(i) + d] - hi[3 * size_t(j) + d]));
-      g2 = g2 + g * g;
-    }
-    return std::sqrt(g2) <= chi;
-  };
-  if (chi < 0) {
-    for (int i = 0; i < E; ++i) {
-      for (int j = 0; j < E; ++j)
-        if (keep(i, j)) col.push_back(j);
-      rowptr.push_back(int64_t(col.size()));
-    }
-    return;
-  }
-  // uniform grid on box centres; cell size >= chi + largest box extent
-  double ext = 0.0, gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {-1e300, -1e300, -1e300};
-  for (int e = 0; e < E; ++e)
-    for (int d = 0; d < 3; ++d) {
-      ext = std::max(ext, hi[3 * size_t(e) + d] - lo[3 * size_t(e) + d]);
-      const double ce = 0.5 * (lo[3 * size_t(e) + d] + hi[3 * size_t(e) + d]);
-      gmin[d] = std::min(gmin[d], ce);
-      gmax[d] = std::max(gmax[d], ce);
-    }
-  const double h = chi + ext + 1e-12;
-  int dims[3];
-  for (int d = 0; d < 3; ++d) dims[d] = std::max(1, std::min(1024, int((gmax[d] - gmin[d]) / h) + 1));
-  auto cell_of = [&](int e, int* ijk) {
-    for (int d = 0; d < 3; ++d) {
-      const double ce = 0.5 * (lo[3 * size_t(e) + d] + hi[3 * size_t(e) + d]);
-      ijk[d] = std::min(dims[d] - 1, std::max(0, int((ce - gmin[d]) / h)));
-    }
-  };
-  std::unordered_map<int64_t, std::vector<int32_t>> grid;
-  for (int e = 0; e < E; ++e) {
-    int ijk[3];
-    cell_of(e, ijk);
-    grid[(int64_t(ijk[0]) * dims[1] + ijk[1]) * dims[2] + ijk[2]].push_back(e);
-  }
-  std::vector<int32_t> row;
-  for (int i = 0; i < E; ++i) {
-    int ijk[3];
-    cell_of(i, ijk);
-    row.clear();
-    for (int a = -1; a <= 1; ++a)
-      for (int b = -1; b <= 1; ++b)
-        for (int q = -1; q <= 1; ++q) {
-          const int x = ijk[0] + a, y = ijk[1] + b, z = ijk[2] + q;
-          if (x < 0 || y < 0 || z < 0 || x >= dims[0] || y >= dims[1] || z >= dims[2]) continue;
-          auto it = grid.find((int64_t(x) * dims[1] + y) * dims[2] + z);
-          if (it == grid.end()) continue;
-          for (int j : it->second)
-            if (keep(i, j)) row.push_back(j);
-        }
-    std::sort(row.begin(), row.end());
-    col.insert(col.end(), row.begin(), row.end());
-    rowptr.push_back(int64_t(col.size()));
-  }
-}
-
-void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross);
+void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross, const CellDev& cells);
 void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev& cells);
 
 void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, CellDev& cells) {
@@ -1411,12 +1327,12 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   if (kind == PMCHWT_P_I) return;
   const double chi = o.chi < 0 ? -1.0 : o.chi;
   if (!(c->nf.valid && c->nf.chi == chi && c->nf.cross == c->P_cross)) {
-    build_nearfield_tables(c, chi, c->P_cross);
+    build_nearfield_tables(c, chi, c->P_cross, cells);
     c->nf.valid = true;
     c->nf.chi = chi;
     c->nf.cross = c->P_cross;
   }
-  c->nnzP = int64_t(c->h_col.size());
+  c->nnzP = c->nf.nnz;
   c->prof.bary_pairs = c->nf.bary_pairs;
   auto vals = [&](DBuf& b) {
     realloc_c<double>(c, b, 2 * size_t(c->nnzP));
@@ -1433,86 +1349,156 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   run_nearfield_kernel(c, o, cells);
 }
 
-// Near-field pattern of P and the dual-cell pair tables of its kernel.
-void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross) {
-  build_pattern(c, chi, cross, c->h_rowptr, c->h_col);
-  c->p_rowptr = upload(c, c->h_rowptr);
-  c->p_col = upload(c, c->h_col);
-  // per union edge: its two end cells and its slot in each
+// Near-field pattern of P (entries (i, j), i and j in one scatterer unless
+// `cross`, whose BC support boxes are within chi; chi < 0 keeps all) and the
+// dual-cell pair tables of its kernel, built by the classification kernels.
+// The host only lays out the per-edge boxes and end cells (O(E)) and sizes
+// the grid and the outputs.
+void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross, const CellDev& cells) {
   const int E = c->E_tot;
-  std::vector<int32_t> ecell(2 * size_t(E)), eslot(2 * size_t(E)), cell_n;
-  std::vector<int32_t> cell_first_child;
-  for (auto& s : c->sc) {
-    const DualCells& D = s.dual;
-    for (int v = 0; v < s.topo.nv; ++v) {
-      cell_n.push_back((D.cell_ptr[v + 1] - D.cell_ptr[v]) / 2);
-      for (int q = D.inc_ptr[v]; q < D.inc_ptr[v + 1]; ++q) {
-        const int e = s.edge_off + D.inc_edges[q];
-        const int end = (s.topo.edges[2 * size_t(D.inc_edges[q])] == v) ? 0 : 1;
-        ecell[2 * size_t(e) + end] = s.cell_off + v;
-        eslot[2 * size_t(e) + end] = q - D.inc_ptr[v];
+  hipStream_t st = c->stream;
+  std::vector<double> box(6 * size_t(E));
+  std::vector<int32_t> escat(E), ecell(2 * size_t(E)), sc_first, sc_n;
+  double ext = 0.0, gmin[3] = {1e300, 1e300, 1e300}, gmax[3] = {-1e300, -1e300, -1e300};
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    for (int e = 0; e < s.topo.E; ++e) {
+      const size_t g = size_t(s.edge_off + e);
+      for (int q = 0; q < 6; ++q) box[6 * g + q] = s.dual.bbox[6 * size_t(e) + q];
+      for (int d = 0; d < 3; ++d) {
+        const double lo = box[6 * g + d], hi = box[6 * g + 3 + d], ce = 0.5 * (lo + hi);
+        ext = std::max(ext, hi - lo);
+        gmin[d] = std::min(gmin[d], ce);
+        gmax[d] = std::max(gmax[d], ce);
       }
+      escat[g] = int32_t(m);
+      ecell[2 * g] = s.cell_off + s.topo.edges[2 * size_t(e)];
+      ecell[2 * g + 1] = s.cell_off + s.topo.edges[2 * size_t(e) + 1];
     }
+    sc_first.push_back(s.edge_off);
+    sc_n.push_back(s.topo.E);
   }
-  // cell pairs: (cv, cw) such that some kept (i, j) has an end point in cv
-  // and one in cw; per pair an N_cv x N_cw table of CSR positions
-  std::vector<int32_t> cpairs;
-  std::vector<int64_t> slot_off{0}, slot_pos;
-  const int ncell = int(cell_n.size());
-  std::vector<int32_t> cell_edges_ptr(ncell + 1, 0), cell_edges;
-  for (auto& s : c->sc)
-    for (int v = 0; v < s.topo.nv; ++v) {
-      for (int q = s.dual.inc_ptr[v]; q < s.dual.inc_ptr[v + 1]; ++q) cell_edges.push_back(s.edge_off + s.dual.inc_edges[q]);
-      cell_edges_ptr[s.cell_off + v + 1] = int32_t(cell_edges.size());
-    }
-  std::vector<int32_t> stamp(ncell, -1);
-  std::vector<int64_t> colpos(E, -1);
-  std::vector<int32_t> cws;
-  for (int cv = 0; cv < ncell; ++cv) {
-    cws.clear();
-    for (int q = cell_edges_ptr[cv]; q < cell_edges_ptr[cv + 1]; ++q) {
-      const int i = cell_edges[q];
-      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) {
-        const int j = c->h_col[p];
-        for (int b = 0; b < 2; ++b) {
-          const int cw = ecell[2 * size_t(j) + b];
-          if (stamp[cw] != cv) {
-            stamp[cw] = cv;
-            cws.push_back(cw);
-          }
-        }
+  DBuf d_box = upload(c, box), d_escat = upload(c, escat), d_ecell = upload(c, ecell);
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(E)), stats = dalloc_c<int32_t>(c, 4);
+  DBuf rowptr = dalloc_c<int64_t>(c, size_t(E) + 1);
+  launch_cls_fill_i32(stats.as<int32_t>(), 4, 0, st);
+  DBuf d_first = upload(c, sc_first), d_n = upload(c, sc_n);
+  DBuf gcell, gcnt, gstart, gitem;
+  NfJob J{};
+  if (chi < 0) {
+    launch_nf_dense(E, d_escat.as<int32_t>(), d_first.as<int32_t>(), d_n.as<int32_t>(), cross ? 1 : 0,
+                    cnt.as<int32_t>(), stats.as<int32_t>(), st);
+  } else {
+    // cells of at least chi + the largest box extent (slightly enlarged against
+    // rounding), coarsened until there are at most about 2 E of them
+    NfGrid g{};
+    double h = (chi + ext) * (1.0 + 1e-9) + 1e-300;
+    int64_t ncells = 0;
+    for (;;) {
+      ncells = 1;
+      for (int d = 0; d < 3; ++d) {
+        g.dims[d] = int(std::max(1.0, std::min(1024.0, std::floor((gmax[d] - gmin[d]) / h) + 1.0)));
+        ncells *= g.dims[d];
       }
+      if (ncells <= 2 * int64_t(E) + 64) break;
+      h *= 1.25;
     }
-    std::sort(cws.begin(), cws.end());
-    const int Nv = cell_n[cv];
-    const size_t first = cpairs.size() / 2;
-    for (int cw : cws) {
-      cpairs.push_back(cv);
-      cpairs.push_back(cw);
-      const int64_t ns = int64_t(Nv) * cell_n[cw];
-      slot_off.push_back(slot_off.back() + ns);
-    }
-    slot_pos.resize(size_t(slot_off.back()), -1);
-    for (int si = 0; si < Nv; ++si) {
-      const int i = cell_edges[cell_edges_ptr[cv] + si];
-      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) colpos[c->h_col[p]] = p;
-      for (size_t k = 0; k < cws.size(); ++k) {
-        const int cw = cws[k];
-        const int Nw = cell_n[cw];
-        const int64_t base = slot_off[first + k] + int64_t(si) * Nw;
-        for (int sj = 0; sj < Nw; ++sj) slot_pos[base + sj] = colpos[cell_edges[cell_edges_ptr[cw] + sj]];
-      }
-      for (int64_t p = c->h_rowptr[i]; p < c->h_rowptr[i + 1]; ++p) colpos[c->h_col[p]] = -1;
-    }
+    for (int d = 0; d < 3; ++d) g.gmin[d] = gmin[d];
+    g.h = h;
+    gcell = dalloc_c<int32_t>(c, size_t(E));
+    gcnt = dalloc_c<int32_t>(c, size_t(ncells));
+    gstart = dalloc_c<int64_t>(c, size_t(ncells) + 1);
+    gitem = dalloc_c<int32_t>(c, size_t(E));
+    launch_cls_fill_i32(gcnt.as<int32_t>(), ncells, 0, st);
+    launch_nf_bin(d_box.as<double>(), E, g, gcell.as<int32_t>(), gcnt.as<int32_t>(), st);
+    launch_scan_i32(gcnt.as<int32_t>(), int(ncells), gstart.as<int64_t>(), st);
+    launch_cls_fill_i32(gcnt.as<int32_t>(), ncells, 0, st);
+    launch_nf_bin_fill(gcell.as<int32_t>(), E, gstart.as<int64_t>(), gcnt.as<int32_t>(), gitem.as<int32_t>(), st);
+    J.E = E;
+    J.box = d_box.as<double>();
+    J.escat = d_escat.as<int32_t>();
+    J.g = g;
+    J.gcell = gcell.as<int32_t>();
+    J.gstart = gstart.as<int64_t>();
+    J.gitem = gitem.as<int32_t>();
+    J.chi = chi;
+    J.cross = cross ? 1 : 0;
+    launch_nf_count(J, cnt.as<int32_t>(), stats.as<int32_t>(), st);
   }
-  (void)eslot;
-  int64_t bary_pairs = 0;
-  for (size_t q = 0; q < cpairs.size(); q += 2) bary_pairs += int64_t(4) * cell_n[cpairs[q]] * cell_n[cpairs[q + 1]];
-  c->nf.bary_pairs = bary_pairs;
-  c->nf.npairs = int64_t(cpairs.size() / 2);
-  c->nf.cpairs = upload(c, cpairs);
-  c->nf.slot_off = upload(c, slot_off);
-  c->nf.slot_pos = upload(c, slot_pos);
+  launch_scan_i32(cnt.as<int32_t>(), E, rowptr.as<int64_t>(), st);
+  HIPCHK(hipGetLastError());
+  int64_t nnz = 0;
+  int32_t maxc = 0;
+  read_scalars(c, {{&nnz, {rowptr.as<int64_t>() + E, 8}}, {&maxc, {stats.as<int32_t>(), 4}}});
+  if (chi >= 0 && maxc > nf_row_capacity())
+    throw Fail{PMCHWT_ERR_INVALID_ARG, "near-field cutoff keeps " + std::to_string(maxc) +
+                                           " entries in one row of P (at most " + std::to_string(nf_row_capacity()) +
+                                           "): chi too large for a sparse preconditioner"};
+  DBuf col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+  if (chi < 0)
+    launch_nf_dense_fill(E, d_escat.as<int32_t>(), d_first.as<int32_t>(), cross ? 1 : 0, rowptr.as<int64_t>(),
+                         col.as<int32_t>(), st);
+  else
+    launch_nf_fill(J, rowptr.as<int64_t>(), pow2_ceil(std::max(maxc, 1)), col.as<int32_t>(), st);
+  HIPCHK(hipGetLastError());
+  c->p_rowptr = std::move(rowptr);
+  c->p_col = std::move(col);
+  c->nf.nnz = nnz;
+  c->nf.host_valid = false;
+  c->h_rowptr.clear();
+  c->h_col.clear();
+  // dual-cell pairs: count, scan, fill
+  const int ncell = cells.ncell;
+  DBuf ncw = dalloc_c<int32_t>(c, size_t(ncell)), nslot = dalloc_c<int32_t>(c, size_t(ncell));
+  DBuf pairoff = dalloc_c<int64_t>(c, size_t(ncell) + 1), slotbase = dalloc_c<int64_t>(c, size_t(ncell) + 1);
+  CellPairJob P{};
+  P.inc_ptr = cells.inc_ptr.as<int32_t>();
+  P.inc_edges = cells.inc_edges.as<int32_t>();
+  P.rowptr = c->p_rowptr.as<int64_t>();
+  P.col = c->p_col.as<int32_t>();
+  P.ecell = d_ecell.as<int32_t>();
+  P.ncw = ncw.as<int32_t>();
+  P.nslot = nslot.as<int32_t>();
+  P.flag = stats.as<int32_t>() + 1;
+  launch_cell_pairs(P, ncell, false, st);
+  launch_scan_i32(ncw.as<int32_t>(), ncell, pairoff.as<int64_t>(), st);
+  launch_scan_i32(nslot.as<int32_t>(), ncell, slotbase.as<int64_t>(), st);
+  HIPCHK(hipGetLastError());
+  int64_t npairs = 0, nslots = 0;
+  int32_t over = 0;
+  read_scalars(c, {{&npairs, {pairoff.as<int64_t>() + ncell, 8}},
+                   {&nslots, {slotbase.as<int64_t>() + ncell, 8}},
+                   {&over, {stats.as<int32_t>() + 1, 4}}});
+  if (over)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, "near-field cutoff joins a dual cell to more than " +
+                                           std::to_string(cell_pair_capacity()) +
+                                           " others: chi too large for a sparse preconditioner"};
+  c->nf.cpairs = dalloc_c<int32_t>(c, size_t(2 * std::max<int64_t>(npairs, 1)));
+  c->nf.slot_off = dalloc_c<int64_t>(c, size_t(npairs) + 1);
+  c->nf.slot_pos = dalloc_c<int64_t>(c, size_t(std::max<int64_t>(nslots, 1)));
+  P.pairoff = pairoff.as<int64_t>();
+  P.slotbase = slotbase.as<int64_t>();
+  P.cpairs = c->nf.cpairs.as<int32_t>();
+  P.slot_off = c->nf.slot_off.as<int64_t>();
+  P.slot_pos = c->nf.slot_pos.as<int64_t>();
+  launch_cell_pairs(P, ncell, true, st);
+  launch_cls_set_i64(c->nf.slot_off.as<int64_t>() + npairs, nslots, st);
+  HIPCHK(hipGetLastError());
+  c->nf.bary_pairs = 4 * nslots;  // 4 barycentric pairs per (slot of v) x (slot of w)
+  c->nf.npairs = npairs;
+  HIPCHK(hipStreamSynchronize(st));  // the host inputs above go out of scope
+}
+
+// Host copy of the pattern of P, for the block and entry accessors.
+void host_pattern(pmchwt_ctx* c) {
+  if (c->nf.host_valid) return;
+  c->h_rowptr.resize(size_t(c->E_tot) + 1);
+  c->h_col.resize(size_t(c->nf.nnz));
+  HIPCHK(hipMemcpyAsync(c->h_rowptr.data(), c->p_rowptr.p, c->h_rowptr.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  if (c->nf.nnz > 0)
+    HIPCHK(hipMemcpyAsync(c->h_col.data(), c->p_col.p, c->h_col.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->nf.host_valid = true;
 }
 
 void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev& cells) {
@@ -3006,6 +2992,7 @@ int pmchwt_get_block(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchwt_
     if (med == PMCHWT_INT) v = op == PMCHWT_OP_S ? &c->PSi : &c->PCi;
     else v = op == PMCHWT_OP_S ? &c->PSe : &c->PCe;
     if (!v->p) return fail(c, PMCHWT_ERR_STATE, "this BC operator is not part of the preconditioner");
+    host_pattern(c);
     std::vector<double> vals(2 * size_t(c->nnzP));
     HIPCHK(hipMemcpyAsync(vals.data(), v->p, vals.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -3059,6 +3046,7 @@ int pmchwt_get_entries(pmchwt_ctx* c, pmchwt_opkind op, pmchwt_medium med, pmchw
     }
     const DBuf* v = med == PMCHWT_INT ? (op == PMCHWT_OP_S ? &c->PSi : &c->PCi) : (op == PMCHWT_OP_S ? &c->PSe : &c->PCe);
     if (!v->p) return fail(c, PMCHWT_ERR_STATE, "this BC operator is not part of the preconditioner");
+    host_pattern(c);
     for (int64_t q = 0; q < n; ++q) {
       const int gi = sm.edge_off + rows[q], gj = sl.edge_off + cols[q];
       auto b = c->h_col.begin() + c->h_rowptr[gi], e = c->h_col.begin() + c->h_rowptr[gi + 1];

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <thread>
 #include <unordered_map>
 
 namespace pmchwt {
@@ -157,7 +158,8 @@ bool build_dual(const Topo& T, DualCells& D, std::string& err) {
   // the two radial edges of a child in cell v are (v, m) and (v, g); a child
   // is identified by its "other endpoints" (m, g).  The boundary edge (m, g)
   // is opposite v.
-  for (int v = 0; v < nv; ++v) {
+  // one dual cell (independent of the others: disjoint output ranges)
+  auto cell = [&](int v, std::string& err) -> bool {
     const std::vector<int32_t>& cl = cells[v];
     int n2 = int(cl.size()), N = n2 / 2;
     std::map<int32_t, std::vector<int32_t>> by_key;  // other endpoint -> children
@@ -268,7 +270,31 @@ bool build_dual(const Topo& T, DualCells& D, std::string& err) {
         D.coef[4 * rec + 3] = w[2];
       }
     }
+    return true;
+  };
+  // cells in parallel ranges on large meshes
+  const int nthreads = nv >= 2048 ? int(std::max(1u, std::min(8u, std::thread::hardware_concurrency()))) : 1;
+  std::vector<std::string> errs(nthreads);
+  std::vector<char> ok(nthreads, 1);
+  auto range = [&](int w) {
+    for (int v = int(int64_t(nv) * w / nthreads); v < int(int64_t(nv) * (w + 1) / nthreads); ++v)
+      if (!cell(v, errs[w])) {
+        ok[w] = 0;
+        return;
+      }
+  };
+  if (nthreads == 1) {
+    range(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nthreads; ++w) pool.emplace_back(range, w);
+    for (auto& t : pool) t.join();
   }
+  for (int w = 0; w < nthreads; ++w)
+    if (!ok[w]) {
+      err = errs[w];
+      return false;
+    }
   // bounding boxes of BC supports: both dual cells
   for (int e = 0; e < E; ++e) {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

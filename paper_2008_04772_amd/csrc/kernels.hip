@@ -8,3 +8,4 @@
 #include "refine.inl"
 #include "massinv.inl"
 #include "nearfield.inl"
+#include "classify.inl"

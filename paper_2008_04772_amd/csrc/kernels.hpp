@@ -420,4 +420,94 @@ void launch_far_field(const AsmParams<double>& geo, const double* x, int64_t E_t
                       double* part, hipStream_t st);
 void launch_sigma_sca(const double* F, int nobs, int nrhs, const double* w, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Geometric classification tables (count pass, scan, fill pass each)
+// ---------------------------------------------------------------------------
+// uniform grid on the centres of the BC support boxes, cell size h >= chi +
+// the largest box extent, so that the 27 cells around a box's own hold every
+// box within chi of it
+struct NfGrid {
+  double gmin[3];
+  double h;
+  int dims[3];
+};
+struct NfJob {
+  int E;
+  const double* box;       // 6 per union edge: lo xyz, hi xyz of the BC support
+  const int32_t* escat;    // scatterer of each union edge
+  NfGrid g;
+  const int32_t* gcell;    // grid cell of each edge
+  const int64_t* gstart;   // ncells+1 into gitem
+  const int32_t* gitem;    // edges grouped by grid cell
+  double chi;
+  int cross;               // keep pairs of different scatterers
+};
+struct CellPairJob {
+  const int32_t* inc_ptr;   // ncell+1 into inc_edges (dual cell = primal vertex)
+  const int32_t* inc_edges; // union edges incident to each cell, slot order
+  const int64_t* rowptr;    // near-field pattern of P
+  const int32_t* col;
+  const int32_t* ecell;     // 2 per union edge: cells of its end points
+  int32_t* ncw;             // count pass: partner cells per cell
+  int32_t* nslot;           // count pass: N_v * sum N_w per cell
+  int32_t* flag;            // set when a cell has too many partners
+  const int64_t* pairoff;   // fill pass: scans of ncw and nslot
+  const int64_t* slotbase;
+  int32_t* cpairs;          // 2 per pair
+  int64_t* slot_off;        // per pair
+  int64_t* slot_pos;        // N_v x N_w CSR positions per pair, -1 = cut off
+};
+struct SingListJob {
+  int F;
+  const int32_t* tvid;     // 3*F vertex ids (global), SoA
+  const int32_t* v2t_ptr;  // per global vertex, into v2t
+  const int32_t* v2t;      // triangles at each vertex
+  int32_t* cnt;            // count pass: pairs per test triangle
+  int32_t* flag;           // set when a triangle has too many neighbours
+  const int64_t* sptr;     // fill pass: scan of cnt
+  int32_t* pairs;          // 2 per pair (test, trial)
+  int npts[4];             // Sauter-Schwab points by number of shared vertices
+  unsigned long long* point_pairs;
+};
+struct SymRecJob {
+  int64_t npairs;          // singular pairs
+  const int32_t* pairs;
+  const int32_t* t2e;      // 3*F union edge of local basis a, SoA
+  int F, tile, n;          // triangles, tile size, rows (edges)
+  int32_t* cnt;            // records, then entries, per row
+  int32_t* maxrec;         // longest record list of a row
+  const int64_t* recptr;   // n+1
+  int32_t* cur;            // per-row cursor of the record fill
+  int64_t* rec;            // (column << 32) | item
+  const int64_t* rowptr;   // n+1 entry offsets
+  int32_t* crow;
+  int32_t* col;
+  int64_t* iptr;           // first record of each entry
+  int32_t* item;
+};
+void launch_cls_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_cls_set_i64(int64_t* p, int64_t v, hipStream_t st);
+void launch_scan_i32(const int32_t* cnt, int n, int64_t* rowptr, hipStream_t st);
+void launch_nf_bin(const double* box, int E, const NfGrid& g, int32_t* gcell, int32_t* gcnt, hipStream_t st);
+void launch_nf_bin_fill(const int32_t* gcell, int E, const int64_t* gstart, int32_t* gcur, int32_t* gitem,
+                        hipStream_t st);
+void launch_nf_count(const NfJob& J, int32_t* cnt, int32_t* maxcnt, hipStream_t st);
+// cap: a power of two >= the longest row, at most nf_row_capacity()
+void launch_nf_fill(const NfJob& J, const int64_t* rowptr, int cap, int32_t* col, hipStream_t st);
+void launch_nf_dense(int E, const int32_t* escat, const int32_t* sc_first, const int32_t* sc_n, int cross,
+                     int32_t* cnt, int32_t* maxcnt, hipStream_t st);
+void launch_nf_dense_fill(int E, const int32_t* escat, const int32_t* sc_first, int cross, const int64_t* rowptr,
+                          int32_t* col, hipStream_t st);
+void launch_cell_pairs(const CellPairJob& J, int ncell, bool fill, hipStream_t st);
+void launch_sing_list(const SingListJob& J, bool fill, hipStream_t st);
+void launch_sym_records(const SymRecJob& J, int pass, hipStream_t st);
+// cap: a power of two >= the longest record list
+void launch_sym_sort(const SymRecJob& J, int cap, hipStream_t st);
+void launch_sym_emit(const SymRecJob& J, hipStream_t st);
+void launch_count_regular(int F, const double* tcen, const double* tdiam2, const int32_t* tvid, int n_near,
+                          int n_medium, int n_far, unsigned long long* out, hipStream_t st);
+int cell_pair_capacity();
+int nf_row_capacity();
+int sing_neighbour_capacity();
+
 }  // namespace pmchwt
