@@ -204,6 +204,11 @@ typedef struct {
                                 refinement: the FP64 right-hand side and the
                                 refinement residuals                             */
   int64_t free_launches;
+  double wall_tables_A;      /* host wall time of the geometry tables of A built by this
+                                assemble (classification kernels with their scans and
+                                read-backs, host layout work); 0 when reused          */
+  double wall_tables_P;      /* ... of P: dual-cell upload, near-field pattern and
+                                dual-cell pair tables                                 */
 } pmchwt_profile;
 
 /* Version string of the library. */

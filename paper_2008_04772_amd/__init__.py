@@ -71,7 +71,8 @@ class pmchwt_profile(ctypes.Structure):
                 ("mfma_flops", ctypes.c_int64), ("mass_iterations", ctypes.c_int32),
                 ("mass_residual", ctypes.c_double), ("lookahead_discarded", ctypes.c_int64),
                 ("ms_matvec_reduce", ctypes.c_double), ("matvec_timed", ctypes.c_int64),
-                ("ms_free_apply", ctypes.c_double), ("free_launches", ctypes.c_int64)]
+                ("ms_free_apply", ctypes.c_double), ("free_launches", ctypes.c_int64),
+                ("wall_tables_A", ctypes.c_double), ("wall_tables_P", ctypes.c_double)]
 
 
 class pmchwt_server_opts(ctypes.Structure):

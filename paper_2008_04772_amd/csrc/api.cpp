@@ -914,6 +914,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   // singular pair list (ordered pairs sharing at least one vertex) and the
   // Sauter-Schwab tables of order n: index tables, built once per geometry
   if (c->sing.n != o.n_singular) {
+    const double wt = wall_ms();
     SSTables ss;
     build_ss(c, o.n_singular, ss);
     const int npts_by_shared[4] = {0, ss.npts[1], ss.npts[2], ss.npts[3]};
@@ -931,6 +932,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
       c->sing.npts[k] = ss.npts[k];
     }
     c->sing.n = o.n_singular;
+    c->prof.wall_tables_A += wall_ms() - wt;
   }
   SingParams sp_{};
   sp_.npairs = c->sing.npairs;
@@ -945,6 +947,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   // FP32, 128 in FP64, where the moments take twice the LDS)
   const int CH = regular_chunk_limit(sizeof(M) == 8);
   if (c->chunk_size != CH) {
+    const double wt = wall_ms();
     std::vector<int32_t> tp(c->E_tot), tm(c->E_tot), escat(c->E_tot);
     std::vector<int8_t> bp(c->E_tot), bm(c->E_tot);
     for (size_t m = 0; m < c->sc.size(); ++m) {
@@ -1013,6 +1016,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     for (int ch = 0; ch < nch; ++ch) tmax[ch] = (cedge[ch + 1] - 1) / SYM_T;
     c->t1_tmin = upload(c, tmin);
     c->ch_tmax = upload(c, tmax);
+    c->prof.wall_tables_A += wall_ms() - wt;
   }
   // one scatterer stored as symmetric tiles: only the upper tiles are
   // assembled (the lower ones are their mirror, filled on first use)
@@ -1159,7 +1163,12 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   if (c->sc.size() == 1 && c->comb_ok) {  // three combined matrices for the operator products
     if (symform) {
       const Scat& s = c->sc[0];
-      sym_tables(c);
+      {
+        const double wt = wall_ms();
+        const bool fresh = c->sym.n != int(E);
+        sym_tables(c);
+        if (fresh) c->prof.wall_tables_A += wall_ms() - wt;
+      }
       realloc_c<M>(c, c->sym.pack, size_t(c->sym.ntiles) * 3 * SYM_T * SYM_T * 2);
       realloc_c<M>(c, c->sym.val, size_t(std::max<int64_t>(c->sym.nnz, 1)) * 6);
       realloc_c<double>(c, c->sym.part, size_t(c->sym.nt) * c->sym.nt * SYM_T * 4);
@@ -1189,6 +1198,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     reg_pairs = c->count_pairs;
     reg_pts = c->count_pts;
   } else {
+    const double wt = wall_ms();
     // exact count over all unordered pairs on the device, with the class rule
     // of the regular kernel
     const int np[5] = {0, 1, 3, 4, 6};
@@ -1199,6 +1209,7 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
                          np[o.q_medium], np[o.q_far], reinterpret_cast<unsigned long long*>(cntd.p), c->stream);
     HIPCHK(hipGetLastError());
     read_scalars(c, {{&reg_pairs, {cntd.as<int64_t>(), 8}}, {&reg_pts, {cntd.as<int64_t>() + 1, 8}}});
+    c->prof.wall_tables_A += wall_ms() - wt;
     c->count_key = ckey;
     c->count_pairs = reg_pairs;
     c->count_pts = reg_pts;
@@ -1327,7 +1338,9 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   if (kind == PMCHWT_P_I) return;
   const double chi = o.chi < 0 ? -1.0 : o.chi;
   if (!(c->nf.valid && c->nf.chi == chi && c->nf.cross == c->P_cross)) {
+    const double wt = wall_ms();
     build_nearfield_tables(c, chi, c->P_cross, cells);
+    c->prof.wall_tables_P += wall_ms() - wt;
     c->nf.valid = true;
     c->nf.chi = chi;
     c->nf.cross = c->P_cross;
@@ -2925,8 +2938,10 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
     HIPCHK(hipStreamSynchronize(c->stream));
     const double w2 = wall_ms();
     if (!c->cells_valid) {
+      const double wt = wall_ms();
       upload_cells(c, c->cells);
       c->cells_valid = true;
+      c->prof.wall_tables_P += wall_ms() - wt;
     }
     CellDev& cells = c->cells;
     c->mass_f32 = P->precision == PMCHWT_MIXED;
