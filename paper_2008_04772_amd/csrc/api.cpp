@@ -219,7 +219,7 @@ struct pmchwt_ctx {
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_col;
   // mass / Gram
-  std::vector<DBuf> MA, Minv, MinvT;
+  std::vector<DBuf> Minv, MinvT;
   // truncated CSR copies of the FP32 inverses (mixed-precision P): the
   // products for fewer than 16 right-hand sides read these
   struct SparseInv {
@@ -227,9 +227,18 @@ struct pmchwt_ctx {
     int64_t nnz = 0;
   };
   std::vector<SparseInv> MinvS, MinvTS;
-  // FP64 CSR of M_A and M_A^T per scatterer when the inverses are the sparse
-  // FP32 ones (an FP64 preconditioner refines their products against them)
-  std::vector<SparseInv> MS, MTS;
+  // FP64 M_A and M_A^T per scatterer (CSR, scatterer-local indices); when
+  // mass_sparse[m], the inverses are the sparse FP32 ones and an FP64
+  // preconditioner refines their products against these
+  std::vector<SparseInv> MAcsr, MATcsr;
+  std::vector<char> mass_sparse;
+  // structural patterns of M_A and M_A^T over the union edges (geometry only)
+  struct {
+    bool valid = false;
+    DBuf rowptr, col, trowptr, tcol;
+    std::vector<int64_t> h_rowptr, h_trowptr;
+    int maxrow = 0, maxtrow = 0;
+  } mp;
   DBuf mass_tmp;  // one vector set of scratch for that refinement
   // RWG Gram matrix (5 nonzeros per row), CSR over union edges with
   // scatterer-local column indices; pattern and slot map built once per geometry
@@ -1793,33 +1802,13 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
 // spectrum of M_A lies in [0.333, 0.997] on every mesh measured): entries
 // within about 6e-8 of the row maximum on the CPU check, stored in FP32.
 // An FP64 preconditioner applies them with one refinement step against the
-// FP64 M_A (kept as CSR in MS / MTS), which squares that error.  Returns
+// FP64 M_A (MAcsr / MATcsr), which squares that error.  Returns
 // false if a ball or a column of M_A exceeds the kernels' capacity; the
-// caller then inverts densely.
-bool sparse_mass_inverse(pmchwt_ctx* c, const double* Mrow, int n, pmchwt_ctx::SparseInv& inv,
-                         pmchwt_ctx::SparseInv& invT, pmchwt_ctx::SparseInv& Mcsr, pmchwt_ctx::SparseInv& MTcsr) {
+// caller then inverts densely.  Mcsr / MTcsr: FP64 CSR of M_A and M_A^T
+// (scatterer-local), maxM / maxT their longest rows.
+bool sparse_mass_inverse(pmchwt_ctx* c, const pmchwt_ctx::SparseInv& Mcsr, const pmchwt_ctx::SparseInv& MTcsr, int n,
+                         int maxM, int maxT, pmchwt_ctx::SparseInv& inv, pmchwt_ctx::SparseInv& invT) {
   const int hops = 8, steps = 14;
-  // CSR of M and of M^T (= the CSC of M) from the dense matrix
-  DBuf Mt = dalloc_c<double>(c, size_t(n) * n);
-  launch_transpose(Mrow, Mt.as<double>(), n, c->stream);
-  auto csr = [&](const double* A, pmchwt_ctx::SparseInv& o, int& maxrow) {
-    DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), thr = dalloc_c<double>(c, size_t(n));
-    o.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
-    build_truncated_inverse<double>(A, n, n, 0.0, cnt.as<int32_t>(), thr.as<double>(), o.rowptr.as<int64_t>(),
-                                    c->stream);
-    std::vector<int32_t> h(n);
-    HIPCHK(hipMemcpyAsync(&o.nnz, o.rowptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    maxrow = *std::max_element(h.begin(), h.end());
-    o.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(o.nnz, 1)));
-    o.val = dalloc_c<double>(c, size_t(std::max<int64_t>(o.nnz, 1)));
-    fill_truncated_inverse<double>(A, n, n, thr.as<double>(), o.rowptr.as<int64_t>(), o.col.as<int32_t>(),
-                                   o.val.as<double>(), c->stream);
-  };
-  int maxM = 0, maxT = 0;
-  csr(Mrow, Mcsr, maxM);
-  csr(Mt.as<double>(), MTcsr, maxT);
   if (maxM > spinv_wmax() || maxT > spinv_wmax()) return false;
   const int cap = spinv_cap();
   DBuf count = dalloc_c<int32_t>(c, 2 * size_t(n)), ball = dalloc_c<int32_t>(c, 2 * size_t(n) * cap);
@@ -1901,26 +1890,112 @@ bool truncated_inverse(pmchwt_ctx* c, const T* A, int64_t ld, int n, T rel, doub
   return true;
 }
 
+// Structural patterns of M_A and M_A^T over the union edges (pattern
+// kernels; the host lists the end points and the triangles at each vertex).
+void build_mass_pattern(pmchwt_ctx* c, const CellDev& cells) {
+  hipStream_t st = c->stream;
+  const int E = c->E_tot, F = c->F_tot;
+  std::vector<int32_t> ends(2 * size_t(E)), escat(E), eoff, vptr(size_t(c->nv_tot) + 1, 0), v2t(3 * size_t(F));
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    for (int e = 0; e < s.topo.E; ++e) {
+      ends[2 * size_t(s.edge_off + e)] = s.vert_off + s.topo.edges[2 * size_t(e)];
+      ends[2 * size_t(s.edge_off + e) + 1] = s.vert_off + s.topo.edges[2 * size_t(e) + 1];
+      escat[s.edge_off + e] = int32_t(m);
+    }
+    eoff.push_back(s.edge_off);
+    for (int f = 0; f < s.topo.F; ++f)
+      for (int a = 0; a < 3; ++a) ++vptr[size_t(s.vert_off + s.topo.t[3 * size_t(f) + a]) + 1];
+  }
+  for (size_t v = 0; v + 1 < vptr.size(); ++v) vptr[v + 1] += vptr[v];
+  {
+    std::vector<int32_t> cur(vptr.begin(), vptr.end() - 1);
+    for (auto& s : c->sc)
+      for (int f = 0; f < s.topo.F; ++f)
+        for (int a = 0; a < 3; ++a) v2t[size_t(cur[size_t(s.vert_off + s.topo.t[3 * size_t(f) + a])]++)] = s.tri_off + f;
+  }
+  DBuf d_ends = upload(c, ends), d_escat = upload(c, escat), d_eoff = upload(c, eoff), d_vptr = upload(c, vptr),
+       d_v2t = upload(c, v2t);
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(E)), stats = dalloc_c<int32_t>(c, 4);
+  MassPatternJob J{};
+  J.E = E;
+  J.F = F;
+  J.edge_slots = c->sing.edge_slots.as<int32_t>();
+  J.tvid = c->tvid.as<int32_t>();
+  J.t2e = c->t2e.as<int32_t>();
+  J.inc_ptr = cells.inc_ptr.as<int32_t>();
+  J.inc_edges = cells.inc_edges.as<int32_t>();
+  J.v2t_ptr = d_vptr.as<int32_t>();
+  J.v2t = d_v2t.as<int32_t>();
+  J.ends = d_ends.as<int32_t>();
+  J.edge_scat = d_escat.as<int32_t>();
+  J.edge_off = d_eoff.as<int32_t>();
+  J.cnt = cnt.as<int32_t>();
+  J.stats = stats.as<int32_t>();
+  for (int trans = 0; trans < 2; ++trans) {
+    DBuf& rp = trans ? c->mp.trowptr : c->mp.rowptr;
+    DBuf& cl = trans ? c->mp.tcol : c->mp.col;
+    std::vector<int64_t>& hrp = trans ? c->mp.h_trowptr : c->mp.h_rowptr;
+    J.trans = trans;
+    launch_cls_fill_i32(stats.as<int32_t>(), 4, 0, st);
+    launch_mass_pattern(J, false, st);
+    rp = dalloc_c<int64_t>(c, size_t(E) + 1);
+    launch_scan_i32(cnt.as<int32_t>(), E, rp.as<int64_t>(), st);
+    HIPCHK(hipGetLastError());
+    hrp.resize(size_t(E) + 1);
+    int32_t hs[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hrp.data(), rp.p, hrp.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs, stats.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hs[1]) throw Fail{PMCHWT_ERR_INVALID_MESH, "vertex valence too high for the mass-matrix pattern"};
+    (trans ? c->mp.maxtrow : c->mp.maxrow) = hs[0];
+    cl = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(hrp[E], 1)));
+    J.rowptr = rp.as<int64_t>();
+    J.col = cl.as<int32_t>();
+    launch_mass_pattern(J, true, st);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(st));  // the host inputs above go out of scope
+  c->mp.valid = true;
+}
+
+// Rows [r0, r0 + n) of a union CSR as a CSR of their own (row offsets from 0).
+pmchwt_ctx::SparseInv csr_rows(pmchwt_ctx* c, const DBuf& rowptr, const std::vector<int64_t>& h_rowptr,
+                               const DBuf& col, const DBuf& val, int r0, int n) {
+  pmchwt_ctx::SparseInv o;
+  const int64_t b = h_rowptr[size_t(r0)];
+  o.nnz = h_rowptr[size_t(r0) + n] - b;
+  o.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  launch_rebase_i64(rowptr.as<int64_t>() + r0, n, o.rowptr.as<int64_t>(), c->stream);
+  o.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+  o.val = dalloc_c<double>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+  if (o.nnz > 0) {
+    HIPCHK(hipMemcpyAsync(o.col.p, col.as<int32_t>() + b, size_t(o.nnz) * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(o.val.p, val.as<double>() + b, size_t(o.nnz) * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return o;
+}
+
+// M_A and M_A^T as CSR (values added into their structural patterns), the
+// RWG Gram matrices, and the inverses the preconditioner applies: the sparse
+// FP32 inverse on the graph ball by default, else (another mass_method, or a
+// ball over the kernels' capacity) a dense inverse of the densified M_A.
 void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   EvTimer t(c->stream);
-  c->MA.clear();
+  c->MAcsr.clear();
+  c->MATcsr.clear();
+  c->mass_sparse.clear();
   c->Minv.clear();
   c->MinvT.clear();
   c->MinvS.clear();
   c->MinvTS.clear();
-  c->MS.clear();
-  c->MTS.clear();
   if (!c->gram_valid) build_gram_pattern(c);
-  std::vector<int64_t> off, ld;
-  int64_t tot = 0;
-  for (auto& s : c->sc) {
-    off.push_back(tot);
-    ld.push_back(s.topo.E);
-    tot += int64_t(s.topo.E) * s.topo.E;
-  }
-  DBuf d_off = upload(c, off), d_ld = upload(c, ld);
-  DBuf mass = dalloc_c<double>(c, size_t(tot));
-  launch_zero(mass.as<double>(), tot, c->stream);
+  if (!c->mp.valid) build_mass_pattern(c, cells);
+  const int64_t nnzM = c->mp.h_rowptr.back(), nnzT = c->mp.h_trowptr.back();
+  DBuf mval = dalloc_c<double>(c, size_t(std::max<int64_t>(nnzM, 1))),
+       tval = dalloc_c<double>(c, size_t(std::max<int64_t>(nnzT, 1)));
+  launch_zero(mval.as<double>(), std::max<int64_t>(nnzM, 1), c->stream);
+  launch_zero(tval.as<double>(), std::max<int64_t>(nnzT, 1), c->stream);
   launch_zero(c->g_val.as<double>(), int64_t(c->g_val.bytes / 8), c->stream);
   MassJob mj{};
   mj.nchild = cells.nchild;
@@ -1931,9 +2006,12 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   mj.inc_edges = cells.inc_edges.as<int32_t>();
   mj.edge_scat = cells.edge_scat.as<int32_t>();
   mj.edge_off = cells.edge_off.as<int32_t>();
-  mj.mat_off = d_off.as<int64_t>();
-  mj.ld = d_ld.as<int64_t>();
-  mj.out = mass.as<double>();
+  mj.m_rowptr = c->mp.rowptr.as<int64_t>();
+  mj.m_col = c->mp.col.as<int32_t>();
+  mj.m_val = mval.as<double>();
+  mj.t_rowptr = c->mp.trowptr.as<int64_t>();
+  mj.t_col = c->mp.tcol.as<int32_t>();
+  mj.t_val = tval.as<double>();
   mj.gram_pos = c->g_pos.as<int64_t>();
   mj.gram_val = c->g_val.as<double>();
   AsmParams<double> g = asm_params<double>(c);
@@ -1941,19 +2019,37 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   launch_gram(g, mj, c->stream);
   HIPCHK(hipGetLastError());
   for (size_t m = 0; m < c->sc.size(); ++m) {
-    const int n = c->sc[m].topo.E;
+    const Scat& s = c->sc[m];
+    const int n = s.topo.E;
     const size_t nn = size_t(n) * n;
-    DBuf MA = dalloc_c<double>(c, nn);
-    HIPCHK(hipMemcpyAsync(MA.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
-    c->MA.push_back(std::move(MA));
+    if (c->sc.size() == 1) {  // the union CSR is the scatterer's: keep it
+      pmchwt_ctx::SparseInv a, b;
+      a.nnz = nnzM;
+      b.nnz = nnzT;
+      a.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+      b.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+      HIPCHK(hipMemcpyAsync(a.rowptr.p, c->mp.rowptr.p, (size_t(n) + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(b.rowptr.p, c->mp.trowptr.p, (size_t(n) + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
+      a.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnzM, 1)));
+      b.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnzT, 1)));
+      HIPCHK(hipMemcpyAsync(a.col.p, c->mp.col.p, size_t(nnzM) * 4, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(b.col.p, c->mp.tcol.p, size_t(nnzT) * 4, hipMemcpyDeviceToDevice, c->stream));
+      a.val = std::move(mval);
+      b.val = std::move(tval);
+      c->MAcsr.push_back(std::move(a));
+      c->MATcsr.push_back(std::move(b));
+    } else {
+      c->MAcsr.push_back(csr_rows(c, c->mp.rowptr, c->mp.h_rowptr, c->mp.col, mval, s.edge_off, n));
+      c->MATcsr.push_back(csr_rows(c, c->mp.trowptr, c->mp.h_trowptr, c->mp.tcol, tval, s.edge_off, n));
+    }
+    const pmchwt_ctx::SparseInv& Mm = c->MAcsr.back();
     const int64_t ldm = ldmass(n);
     if (c->optP.mass_method == 0) {  // sparse inverse on the graph ball (dense only if a ball overflows)
-      pmchwt_ctx::SparseInv a, b, ma, mt;
-      if (sparse_mass_inverse(c, mass.as<double>() + off[m], n, a, b, ma, mt)) {
+      pmchwt_ctx::SparseInv a, b;
+      if (sparse_mass_inverse(c, Mm, c->MATcsr.back(), n, c->mp.maxrow, c->mp.maxtrow, a, b)) {
         c->MinvS.push_back(std::move(a));
         c->MinvTS.push_back(std::move(b));
-        c->MS.push_back(std::move(ma));
-        c->MTS.push_back(std::move(mt));
+        c->mass_sparse.push_back(1);
         c->Minv.emplace_back();  // dense FP32 copies for the matrix-core product: built when first needed
         c->MinvT.emplace_back();
         continue;
@@ -1961,14 +2057,18 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
       c->MinvS.resize(m);
       c->MinvTS.resize(m);
     }
-    c->MS.emplace_back();  // dense path: no refinement CSR
-    c->MTS.emplace_back();
+    c->mass_sparse.push_back(0);
+    // dense M_A of this scatterer for the dense inverses
+    DBuf Md0 = dalloc_c<double>(c, nn);
+    launch_zero(Md0.as<double>(), int64_t(nn), c->stream);
+    launch_csr_to_dense(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), n, Md0.as<double>(), n,
+                        c->stream);
     if (c->mass_f32) {
       // FP32 inverse of [[M_A, 0], [0, I]] (ldm x ldm); its top-left block is
       // M_A^-1 with zero padding columns, the layout the products read
       DBuf Mf = dalloc_c<float>(c, size_t(ldm) * ldm), MfT = dalloc_c<float>(c, size_t(ldm) * ldm);
-      if (c->optP.mass_method != 2 || !cheb_inverse<float>(c, mass.as<double>() + off[m], n, ldm, Mf.as<float>(), true)) {
-        launch_embed_f32(mass.as<double>() + off[m], n, Mf.as<float>(), int(ldm), c->stream);
+      if (c->optP.mass_method != 2 || !cheb_inverse<float>(c, Md0.as<double>(), n, ldm, Mf.as<float>(), true)) {
+        launch_embed_f32(Md0.as<double>(), n, Mf.as<float>(), int(ldm), c->stream);
         gj_inverse_f32(c, Mf.as<float>(), int(ldm));
         c->prof.mass_iterations = 0;
       }
@@ -1983,8 +2083,7 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     }
     // FP64: Gauss-Jordan (the Chebyshev iteration needs about 30 FP64 steps
     // here, each streaming X and D twice: slower than the blocked inverse)
-    DBuf Mi = dalloc_c<double>(c, nn), MiT = dalloc_c<double>(c, nn);
-    HIPCHK(hipMemcpyAsync(Mi.p, mass.as<double>() + off[m], nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    DBuf Mi = std::move(Md0), MiT = dalloc_c<double>(c, nn);
     // row-major M_A is column-major M_A^T; inverting it in place yields the
     // column-major (M_A^T)^-1, i.e. the row-major M_A^-1.
     gj_inverse(c, Mi.as<double>(), n);
@@ -2231,9 +2330,9 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     } else if (S.rowptr.p && c->mass_f32) {
       launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<float>(), s.topo.E, alpha, in + 2 * o,
                             out + 2 * o, nrhs, vs, E, c->stream);
-    } else if (S.rowptr.p && !c->MS.empty() && c->MS[m].rowptr.p) {
+    } else if (S.rowptr.p && m < c->mass_sparse.size() && c->mass_sparse[m]) {
       // FP64 preconditioner, sparse FP32 inverse X: out = alpha (X in + X (in - M X in))
-      const pmchwt_ctx::SparseInv& Mm = tr ? c->MTS[m] : c->MS[m];
+      const pmchwt_ctx::SparseInv& Mm = tr ? c->MATcsr[m] : c->MAcsr[m];
       const size_t need = size_t(2 * vs * nrhs);
       if (c->mass_tmp.bytes < need * 8) realloc_c<double>(c, c->mass_tmp, need);
       double* tmp = c->mass_tmp.as<double>();
@@ -2884,6 +2983,7 @@ int pmchwt_add_scatterer(pmchwt_ctx* c, const double* verts, int32_t nv, const i
     c->sym.n = -1;
     c->cells_valid = false;
     c->gram_valid = false;
+    c->mp.valid = false;
     c->slabs.clear();
     if (id) *id = int32_t(c->sc.size() - 1);
     return PMCHWT_OK;
@@ -3084,9 +3184,18 @@ int pmchwt_get_mass(pmchwt_ctx* c, int32_t m, double* out) {
   return guarded(c, [&]() -> int {
     if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
     if (!out || m < 0 || m >= int32_t(c->sc.size())) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
-    const size_t n = size_t(c->sc[m].topo.E);
-    HIPCHK(hipMemcpyAsync(out, c->MA[m].p, n * n * 8, hipMemcpyDeviceToHost, c->stream));
+    const int n = c->sc[m].topo.E;
+    const pmchwt_ctx::SparseInv& M = c->MAcsr[m];
+    std::vector<int64_t> rp(size_t(n) + 1);
+    std::vector<int32_t> col(size_t(std::max<int64_t>(M.nnz, 1)));
+    std::vector<double> val(size_t(std::max<int64_t>(M.nnz, 1)));
+    HIPCHK(hipMemcpyAsync(rp.data(), M.rowptr.p, rp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(col.data(), M.col.p, size_t(M.nnz) * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(val.data(), M.val.p, size_t(M.nnz) * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::fill(out, out + size_t(n) * n, 0.0);
+    for (int r = 0; r < n; ++r)
+      for (int64_t p = rp[r]; p < rp[r + 1]; ++p) out[size_t(r) * n + col[p]] = val[p];
     return PMCHWT_OK;
   });
 }

@@ -331,11 +331,11 @@ __global__ void k_mass(AsmParams<double> g, CellParams c, MassJob j) {
              l2 = (q == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
       xq[q][d] = l0 * X[0][d] + l1 * X[1][d] + l2 * X[2][d];
     }
-  double* out = j.out + j.mat_off[sc];
-  const int64_t ld = j.ld[sc];
+  const int64_t mb = j.m_rowptr[i], me = j.m_rowptr[i + 1];
   for (int s = 0; s < N; ++s) {
     const double* cf = c.coef + 4 * (c.coef_ptr[cell] + int64_t(s) * n2 + pos);
-    const int jj = j.inc_edges[j.inc_ptr[cell] + s] - j.edge_off[sc];
+    const int jg = j.inc_edges[j.inc_ptr[cell] + s];
+    const int jj = jg - j.edge_off[sc];
     double acc = 0.0;
     for (int q = 0; q < 3; ++q) {
       double b[3], r[3];
@@ -346,8 +346,114 @@ __global__ void k_mass(AsmParams<double> g, CellParams c, MassJob j) {
       double nr[3] = {n[1] * r[2] - n[2] * r[1], n[2] * r[0] - n[0] * r[2], n[0] * r[1] - n[1] * r[0]};
       acc += (b[0] * nr[0] + b[1] * nr[1] + b[2] * nr[2]) / 3.0;
     }
-    atomic_add(&out[int64_t(il) * ld + jj], acc * Ac);
+    // CSR positions of (i, jj) in M_A and (jg, il) in M_A^T (ascending rows)
+    int64_t a0 = mb, a1 = me;
+    while (a0 < a1) {
+      const int64_t m = (a0 + a1) >> 1;
+      if (j.m_col[m] < jj)
+        a0 = m + 1;
+      else
+        a1 = m;
+    }
+    int64_t b0 = j.t_rowptr[jg], b1 = j.t_rowptr[jg + 1];
+    while (b0 < b1) {
+      const int64_t m = (b0 + b1) >> 1;
+      if (j.t_col[m] < il)
+        b0 = m + 1;
+      else
+        b1 = m;
+    }
+    if (a0 < me && j.m_col[a0] == jj) atomic_add(&j.m_val[a0], acc * Ac);
+    if (b0 < j.t_rowptr[jg + 1] && j.t_col[b0] == il) atomic_add(&j.t_val[b0], acc * Ac);
   }
+}
+
+constexpr int MASS_ROW_CAP = 128;  // candidate columns of one row of M_A or M_A^T
+
+__global__ void k_mass_pattern(MassPatternJob J, int fill) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= J.E) return;
+  int cand[MASS_ROW_CAP];
+  int n = 0;
+  bool over = false;
+  const int off = J.edge_off[J.edge_scat[r]];
+  if (!J.trans) {
+    for (int side = 0; side < 2; ++side) {
+      const int T = J.edge_slots[2 * r + side] / 3;
+      for (int a = 0; a < 3; ++a) {
+        const int v = J.tvid[a * J.F + T];
+        for (int p = J.inc_ptr[v]; p < J.inc_ptr[v + 1]; ++p) {
+          if (n < MASS_ROW_CAP)
+            cand[n++] = J.inc_edges[p] - off;
+          else
+            over = true;
+        }
+      }
+    }
+  } else {
+    for (int end = 0; end < 2; ++end) {
+      const int v = J.ends[2 * r + end];
+      for (int p = J.v2t_ptr[v]; p < J.v2t_ptr[v + 1]; ++p) {
+        const int T = J.v2t[p];
+        for (int a = 0; a < 3; ++a) {
+          if (n < MASS_ROW_CAP)
+            cand[n++] = J.t2e[a * J.F + T] - off;
+          else
+            over = true;
+        }
+      }
+    }
+  }
+  for (int k = 1; k < n; ++k) {  // insertion sort
+    const int v = cand[k];
+    int q = k - 1;
+    while (q >= 0 && cand[q] > v) {
+      cand[q + 1] = cand[q];
+      --q;
+    }
+    cand[q + 1] = v;
+  }
+  int m = 0;
+  for (int k = 0; k < n; ++k)
+    if (k == 0 || cand[k] != cand[k - 1]) cand[m++] = cand[k];
+  if (!fill) {
+    J.cnt[r] = m;
+    atomicMax(&J.stats[0], m);
+    if (over) atomicMax(&J.stats[1], 1);
+    return;
+  }
+  const int64_t b = J.rowptr[r];
+  for (int k = 0; k < m; ++k) J.col[b + k] = cand[k];
+}
+
+void launch_mass_pattern(const MassPatternJob& J, bool fill, hipStream_t st) {
+  if (J.E > 0)
+    hipLaunchKernelGGL(k_mass_pattern, dim3(unsigned((J.E + 127) / 128)), dim3(128), 0, st, J, fill ? 1 : 0);
+}
+
+// one thread per row: the row's entries into a zeroed dense row-major matrix
+__global__ void k_csr_to_dense(const int64_t* rowptr, const int32_t* col, const double* val, int n, double* out,
+                               int64_t ld) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) out[int64_t(r) * ld + col[p]] = val[p];
+}
+
+void launch_csr_to_dense(const int64_t* rowptr, const int32_t* col, const double* val, int n, double* out,
+                         int64_t ld, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_csr_to_dense, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, rowptr, col, val, n, out,
+                       ld);
+}
+
+// out[k] = in[k] - in[0], k <= n
+__global__ void k_rebase_i64(const int64_t* in, int64_t n, int64_t* out) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k <= n) out[k] = in[k] - in[0];
+}
+
+void launch_rebase_i64(const int64_t* in, int64_t n, int64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rebase_i64, dim3(unsigned((n + 256) / 256)), dim3(256), 0, st, in, n, out);
 }
 
 void launch_mass(const AsmParams<double>& geo, const CellParams& c, const MassJob& j, hipStream_t st) {

@@ -165,12 +165,45 @@ struct MassJob {
   const int32_t* inc_edges;    // union edge ids
   const int32_t* edge_scat;    // scatterer of each union edge
   const int32_t* edge_off;     // per scatterer
-  const int64_t* mat_off;      // per scatterer offset (elements) into mass storage
-  const int64_t* ld;           // per scatterer E_m
-  double* out;                 // dense FP64 matrices, row-major
+  // M_A (rows: RWG union edge, columns: scatterer-local BC edge) and M_A^T
+  // (rows: BC union edge, columns: scatterer-local RWG edge) as CSR with
+  // ascending columns, structural patterns from the mesh adjacency
+  const int64_t* m_rowptr;
+  const int32_t* m_col;
+  double* m_val;
+  const int64_t* t_rowptr;
+  const int32_t* t_col;
+  double* t_val;
   const int64_t* gram_pos;     // RWG Gram: CSR position of local pair (a, b) of triangle t at 9 t + 3 a + b
   double* gram_val;            // RWG Gram CSR values
 };
+
+// Structural patterns of M_A and M_A^T (count pass, scan, fill pass).
+// Row i of M_A: the BC functions of every edge at a vertex of T+(i) or
+// T-(i); row j of M_A^T: the RWG functions of every triangle at an end point
+// of edge j.  Columns scatterer-local, ascending.
+struct MassPatternJob {
+  int E, F;
+  int trans;                   // 0: M_A, 1: M_A^T
+  const int32_t* edge_slots;   // 2 per union edge: 3 T+ + a, 3 T- + a
+  const int32_t* tvid;         // 3*F SoA global vertex ids
+  const int32_t* t2e;          // 3*F SoA union edge ids
+  const int32_t* inc_ptr;      // per global vertex (cell): edges at it
+  const int32_t* inc_edges;
+  const int32_t* v2t_ptr;      // per global vertex: triangles at it
+  const int32_t* v2t;
+  const int32_t* ends;         // 2 per union edge: global end vertices
+  const int32_t* edge_scat;
+  const int32_t* edge_off;
+  int32_t* cnt;
+  int32_t* stats;              // [0] longest row, [1] overflow flag
+  const int64_t* rowptr;
+  int32_t* col;
+};
+void launch_mass_pattern(const MassPatternJob& J, bool fill, hipStream_t st);
+void launch_csr_to_dense(const int64_t* rowptr, const int32_t* col, const double* val, int n, double* out,
+                         int64_t ld, hipStream_t st);
+void launch_rebase_i64(const int64_t* in, int64_t n, int64_t* out, hipStream_t st);
 
 struct RhsJob {
   int F, nrhs;
