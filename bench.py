@@ -117,11 +117,11 @@ def run_cold(P, mesh, chi, dirs, pols, k_ext, precision, steps):
         dt = time.perf_counter() - t0
         lat.append(dt)
         ph = {"setup": pf["wall_setup"], "A": pf["wall_A"], "P": pf["wall_P"], "mass": pf["wall_mass"],
-              "solve": st.ms_solve, "tables_A": pf["wall_tables_A"], "tables_P": pf["wall_tables_P"]}
+              "solve": st.ms_solve, "tables_A": pf["wall_tables_A"], "tables_P": pf["wall_tables_P"], "dual": pf["wall_dual"]}
         phases.append(ph)
         print(f"[bench] {precision} cold step {s} {dt * 1e3:.1f} ms; wall setup {ph['setup']:.1f} A {ph['A']:.1f} "
               f"P {ph['P']:.1f} mass {ph['mass']:.1f} solve {ph['solve']:.1f}; tables A {ph['tables_A']:.2f} "
-              f"P {ph['tables_P']:.2f}", file=sys.stderr, flush=True)
+              f"P {ph['tables_P']:.2f}; dual cells {ph['dual']:.2f}", file=sys.stderr, flush=True)
     return lat, phases
 
 
@@ -445,7 +445,7 @@ def main():
         cl, cph = run_cold(P, (v, t), chi, dirs, pols, k_ext, head, args.cold_steps)
         out["cold"] = {"ms_per_step": 1e3 * statistics.mean(cl), "steps": args.cold_steps,
                        "phases_wall_ms_last": cph[-1],
-                       "note": "new context per step: mesh tables (tables_A, tables_P: the classification kernels with their read-backs and the host layout work), allocations, assembly, solve, cross sections"}
+                       "note": "new context per step: mesh tables (tables_A, tables_P: the classification kernels with their read-backs and the host layout work; dual: barycentric refinement and dual-cell upload), allocations, assembly, solve, cross sections"}
     if "fp64" in results and head == "mixed":
         l64 = results["fp64"][0]
         out["fp64"] = {"ms_per_step": 1e3 * statistics.mean(l64),

@@ -103,9 +103,9 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       preconditioner, not the system that is solved.
  *   mass_method : how P's products apply M_A^-1 and M_A^-T (Section 3.2).
  *       0 = sparse inverse (FP32 values): row i of the inverse on the
- *       columns within 8 steps of M_A's sparsity graph, by 14 steps of a
+ *       columns within mass_hops steps of M_A's sparsity graph, by a
  *       Chebyshev iteration on the spectrum interval [0.3, 1.05] (entries
- *       within about 1e-7 of the row maximum); an FP64 preconditioner refines
+ *       within about 1e-7 of the row maximum at 8 steps); an FP64 preconditioner refines
  *       each product once against the FP64 M_A (error squared).  A dense
  *       inverse replaces it if a row's column set exceeds 1024 or a column of
  *       M_A holds more than 24 entries.  1 = dense Gauss-Jordan inverse (rank
@@ -122,7 +122,15 @@ typedef enum { PMCHWT_RWG = 0, PMCHWT_BC = 1 } pmchwt_space;
  *       128 x 128 tiles of the combined matrices (half the bytes; the
  *       operators are complex symmetric except where the singular rules
  *       give X_rc != X_cr, which a sparse correction restores exactly).
- *       Ignored for P and for several scatterers; 0 when zero-initialised. */
+ *       Ignored for P and for several scatterers; 0 when zero-initialised.
+ *   mass_hops : radius (steps of M_A's sparsity graph) of the column set of
+ *       each row of the sparse inverse (mass_method 0), 1..8, with hops + 6
+ *       Chebyshev steps.  0 = default: 8 for an FP64 preconditioner (entries
+ *       within about 1e-7 of the row maximum, squared by the refinement), 6
+ *       for MIXED (about 1e-6: the FP32 preconditioner only approximates P~,
+ *       here to about 2e-5; GMRES needs the same iterations for radii 3..8
+ *       on the benchmark sphere, and the smaller rows cut the bytes each
+ *       product reads by about 1.7x).  Ignored for A.                        */
 typedef struct {
   int32_t q_near, q_medium, q_far;
   int32_t n_singular;
@@ -130,6 +138,7 @@ typedef struct {
   int32_t precision;
   int32_t mass_method;
   int32_t operator_form;
+  int32_t mass_hops;
 } pmchwt_assembly_opts;
 
 /* Restarted GMRES (Section 4: tol 1e-5, restart 200).
@@ -207,8 +216,10 @@ typedef struct {
   double wall_tables_A;      /* host wall time of the geometry tables of A built by this
                                 assemble (classification kernels with their scans and
                                 read-backs, host layout work); 0 when reused          */
-  double wall_tables_P;      /* ... of P: dual-cell upload, near-field pattern and
-                                dual-cell pair tables                                 */
+  double wall_tables_P;      /* ... of P: near-field pattern and dual-cell pair tables  */
+  double wall_dual;          /* host wall time of the barycentric refinement and the
+                                upload of its dual-cell tables (first assemble of a
+                                geometry)                                             */
 } pmchwt_profile;
 
 /* Version string of the library. */

@@ -41,7 +41,7 @@ class pmchwt_complex(ctypes.Structure):
 class pmchwt_assembly_opts(ctypes.Structure):
     _fields_ = [("q_near", ctypes.c_int32), ("q_medium", ctypes.c_int32), ("q_far", ctypes.c_int32),
                 ("n_singular", ctypes.c_int32), ("chi", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("mass_method", ctypes.c_int32), ("operator_form", ctypes.c_int32)]
+                ("mass_method", ctypes.c_int32), ("operator_form", ctypes.c_int32), ("mass_hops", ctypes.c_int32)]
 
 
 class pmchwt_solver_opts(ctypes.Structure):
@@ -72,7 +72,8 @@ class pmchwt_profile(ctypes.Structure):
                 ("mass_residual", ctypes.c_double), ("lookahead_discarded", ctypes.c_int64),
                 ("ms_matvec_reduce", ctypes.c_double), ("matvec_timed", ctypes.c_int64),
                 ("ms_free_apply", ctypes.c_double), ("free_launches", ctypes.c_int64),
-                ("wall_tables_A", ctypes.c_double), ("wall_tables_P", ctypes.c_double)]
+                ("wall_tables_A", ctypes.c_double), ("wall_tables_P", ctypes.c_double),
+                ("wall_dual", ctypes.c_double)]
 
 
 class pmchwt_server_opts(ctypes.Structure):
@@ -227,10 +228,11 @@ def pmchwt_num_edges(ctx, m):
     return E.value
 
 
-def assembly_opts(q=(4, 3, 2), n_singular=4, chi=-1.0, precision=FP64, mass_method=0, operator_form=0):
+def assembly_opts(q=(4, 3, 2), n_singular=4, chi=-1.0, precision=FP64, mass_method=0, operator_form=0,
+                  mass_hops=0):
     return pmchwt_assembly_opts(int(q[0]), int(q[1]), int(q[2]), int(n_singular),
                                 float(chi) if chi is not None and np.isfinite(chi) else -1.0, int(precision),
-                                int(mass_method), int(operator_form))
+                                int(mass_method), int(operator_form), int(mass_hops))
 
 
 def pmchwt_assemble(ctx, optsA, optsP, precond="S_INT"):

@@ -552,6 +552,8 @@ void check_opts(const pmchwt_assembly_opts* o, const char* which) {
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_method must be 0, 1 or 2"};
   if (o->operator_form < 0 || o->operator_form > 2)
     throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": operator_form must be 0, 1 or 2"};
+  if (o->mass_hops < 0 || o->mass_hops > 8)
+    throw Fail{PMCHWT_ERR_INVALID_ARG, std::string(which) + ": mass_hops must be 0..8"};
 }
 
 // ---------------------------------------------------------------------------
@@ -1253,62 +1255,78 @@ void build_duals(pmchwt_ctx* c) {
 }
 
 void upload_cells(pmchwt_ctx* c, CellDev& d) {
-  std::vector<int32_t> cell_ptr{0}, ring, child_vid, cell_scat, child_cell, child_pos, child_parent, inc_ptr{0},
-      inc_edges, edge_scat;
-  std::vector<double> child_v, child_cen, child_diam2, child_area, coef;
-  std::vector<int64_t> coef_ptr{0};
-  std::vector<int32_t> eoff;
+  // sizes first, then every table filled by index (bulk copies with offsets)
+  size_t ncell = 0, nchild = 0, nring = 0, ninc = 0, nrec = 0, E = 0;
+  for (const Scat& s : c->sc) {
+    ncell += size_t(s.topo.nv);
+    nchild += 6 * size_t(s.topo.F);
+    nring += size_t(s.dual.cell_ptr[s.topo.nv]);
+    ninc += size_t(s.dual.inc_ptr[s.topo.nv]);
+    nrec += size_t(s.dual.coef_ptr[s.topo.nv]);
+    E += size_t(s.topo.E);
+  }
+  std::vector<int32_t> cell_ptr(ncell + 1), ring(nring), child_vid(3 * nchild), cell_scat(ncell), child_cell(nchild),
+      child_pos(nchild), child_parent(nchild), inc_ptr(ncell + 1), inc_edges(ninc), edge_scat(E), eoff;
+  std::vector<double> child_v(9 * nchild), child_cen(3 * nchild), child_diam2(nchild), child_area(nchild),
+      coef(4 * nrec);
+  std::vector<int64_t> coef_ptr(ncell + 1);
+  cell_ptr[0] = 0;
+  inc_ptr[0] = 0;
+  coef_ptr[0] = 0;
+  size_t ring0 = 0, inc0 = 0, rec0 = 0;
   for (size_t m = 0; m < c->sc.size(); ++m) {
     const Scat& s = c->sc[m];
     const DualCells& D = s.dual;
     const Topo& T = s.topo;
     eoff.push_back(s.edge_off);
-    for (int e = 0; e < T.E; ++e) edge_scat.push_back(int32_t(m));
+    std::fill(edge_scat.begin() + s.edge_off, edge_scat.begin() + s.edge_off + T.E, int32_t(m));
     for (int ch = 0; ch < 6 * T.F; ++ch) {
+      const size_t g = size_t(s.child_off + ch);
       double P[3][3];
       for (int k = 0; k < 3; ++k) {
         const int id = D.child_vid[3 * size_t(ch) + k];
-        child_vid.push_back(s.bvert_off + id);
+        child_vid[3 * g + k] = s.bvert_off + id;
         for (int dd = 0; dd < 3; ++dd) {
           P[k][dd] = D.bv[3 * size_t(id) + dd];
-          child_v.push_back(P[k][dd]);
+          child_v[9 * g + 3 * k + dd] = P[k][dd];
         }
       }
-      for (int dd = 0; dd < 3; ++dd) child_cen.push_back((P[0][dd] + P[1][dd] + P[2][dd]) / 3.0);
+      for (int dd = 0; dd < 3; ++dd) child_cen[3 * g + dd] = (P[0][dd] + P[1][dd] + P[2][dd]) / 3.0;
       double mm = 0;
       const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
       for (auto& q : pr) {
         const double ex = P[q[0]][0] - P[q[1]][0], ey = P[q[0]][1] - P[q[1]][1], ez = P[q[0]][2] - P[q[1]][2];
         mm = std::max(mm, ex * ex + ey * ey + ez * ez);
       }
-      child_diam2.push_back(mm);
+      child_diam2[g] = mm;
       const double u[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
       const double w[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
       const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
-      child_area.push_back(0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]));
-      child_parent.push_back(s.tri_off + ch / 6);
+      child_area[g] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      child_parent[g] = s.tri_off + ch / 6;
     }
-    child_cell.resize(child_cell.size() + 6 * size_t(T.F));
-    child_pos.resize(child_pos.size() + 6 * size_t(T.F));
     for (int v = 0; v < T.nv; ++v) {
-      const int n2 = D.cell_ptr[v + 1] - D.cell_ptr[v];
+      const size_t cv = size_t(s.cell_off + v);
+      const int r0 = D.cell_ptr[v], n2 = D.cell_ptr[v + 1] - r0;
       for (int i = 0; i < n2; ++i) {
-        const int ch = D.ring[D.cell_ptr[v] + i];
-        ring.push_back(s.child_off + ch);
-        child_cell[s.child_off + ch] = s.cell_off + v;
-        child_pos[s.child_off + ch] = i;
+        const int ch = D.ring[size_t(r0) + i];
+        ring[ring0 + size_t(r0) + i] = s.child_off + ch;
+        child_cell[size_t(s.child_off + ch)] = int32_t(cv);
+        child_pos[size_t(s.child_off + ch)] = i;
       }
-      cell_ptr.push_back(cell_ptr.back() + n2);
-      for (int q = D.inc_ptr[v]; q < D.inc_ptr[v + 1]; ++q) inc_edges.push_back(s.edge_off + D.inc_edges[q]);
-      inc_ptr.push_back(int32_t(inc_edges.size()));
-      const int64_t recs = D.coef_ptr[v + 1] - D.coef_ptr[v];
-      for (int64_t r = 0; r < 4 * recs; ++r) coef.push_back(D.coef[4 * size_t(D.coef_ptr[v]) + r]);
-      coef_ptr.push_back(coef_ptr.back() + recs);
-      cell_scat.push_back(int32_t(m));
+      cell_ptr[cv + 1] = int32_t(ring0) + D.cell_ptr[v + 1];
+      inc_ptr[cv + 1] = int32_t(inc0) + D.inc_ptr[v + 1];
+      coef_ptr[cv + 1] = int64_t(rec0) + D.coef_ptr[v + 1];
+      cell_scat[cv] = int32_t(m);
     }
+    for (int q = 0; q < D.inc_ptr[T.nv]; ++q) inc_edges[inc0 + size_t(q)] = s.edge_off + D.inc_edges[q];
+    std::copy(D.coef.begin(), D.coef.begin() + 4 * D.coef_ptr[T.nv], coef.begin() + 4 * rec0);
+    ring0 += size_t(D.cell_ptr[T.nv]);
+    inc0 += size_t(D.inc_ptr[T.nv]);
+    rec0 += size_t(D.coef_ptr[T.nv]);
   }
-  d.ncell = int(cell_scat.size());
-  d.nchild = int(child_area.size());
+  d.ncell = int(ncell);
+  d.nchild = int(nchild);
   d.cell_ptr = upload(c, cell_ptr);
   d.ring = upload(c, ring);
   d.child_v = upload(c, child_v);
@@ -1797,18 +1815,19 @@ bool cheb_inverse(pmchwt_ctx* c, const double* Mrow, int n, int64_t ld, T* X, bo
 }
 
 // Sparse approximate inverses of M_A and M_A^T (kernels in massinv.inl): row
-// i on the ball of columns within 8 steps of M_A's sparsity graph, 14 steps
-// of the Chebyshev iteration for the spectrum interval [0.3, 1.05] (the
-// spectrum of M_A lies in [0.333, 0.997] on every mesh measured): entries
-// within about 6e-8 of the row maximum on the CPU check, stored in FP32.
+// i on the ball of columns within `hops` steps of M_A's sparsity graph,
+// hops + 6 steps of the Chebyshev iteration for the spectrum interval
+// [0.3, 1.05] (the spectrum of M_A lies in [0.333, 0.997] on every mesh
+// measured): at 8 steps entries within about 6e-8 of the row maximum on the
+// CPU check, stored in FP32.
 // An FP64 preconditioner applies them with one refinement step against the
 // FP64 M_A (MAcsr / MATcsr), which squares that error.  Returns
 // false if a ball or a column of M_A exceeds the kernels' capacity; the
 // caller then inverts densely.  Mcsr / MTcsr: FP64 CSR of M_A and M_A^T
 // (scatterer-local), maxM / maxT their longest rows.
 bool sparse_mass_inverse(pmchwt_ctx* c, const pmchwt_ctx::SparseInv& Mcsr, const pmchwt_ctx::SparseInv& MTcsr, int n,
-                         int maxM, int maxT, pmchwt_ctx::SparseInv& inv, pmchwt_ctx::SparseInv& invT) {
-  const int hops = 8, steps = 14;
+                         int maxM, int maxT, int hops, pmchwt_ctx::SparseInv& inv, pmchwt_ctx::SparseInv& invT) {
+  const int steps = hops + 6;
   if (maxM > spinv_wmax() || maxT > spinv_wmax()) return false;
   const int cap = spinv_cap();
   DBuf count = dalloc_c<int32_t>(c, 2 * size_t(n)), ball = dalloc_c<int32_t>(c, 2 * size_t(n) * cap);
@@ -2046,7 +2065,8 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
     const int64_t ldm = ldmass(n);
     if (c->optP.mass_method == 0) {  // sparse inverse on the graph ball (dense only if a ball overflows)
       pmchwt_ctx::SparseInv a, b;
-      if (sparse_mass_inverse(c, Mm, c->MATcsr.back(), n, c->mp.maxrow, c->mp.maxtrow, a, b)) {
+      const int hops = c->optP.mass_hops > 0 ? c->optP.mass_hops : (c->mass_f32 ? 6 : 8);
+      if (sparse_mass_inverse(c, Mm, c->MATcsr.back(), n, c->mp.maxrow, c->mp.maxtrow, hops, a, b)) {
         c->MinvS.push_back(std::move(a));
         c->MinvTS.push_back(std::move(b));
         c->mass_sparse.push_back(1);
@@ -3025,6 +3045,7 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
     c->prof = pmchwt_profile{};
     const double w0 = wall_ms();
     build_duals(c);
+    c->prof.wall_dual = wall_ms() - w0;
     upload_geometry(c);
     upload_k(c);
     c->optA = *A;
@@ -3041,7 +3062,7 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
       const double wt = wall_ms();
       upload_cells(c, c->cells);
       c->cells_valid = true;
-      c->prof.wall_tables_P += wall_ms() - wt;
+      c->prof.wall_dual += wall_ms() - wt;
     }
     CellDev& cells = c->cells;
     c->mass_f32 = P->precision == PMCHWT_MIXED;

@@ -118,9 +118,10 @@ def test_rhs_apply_solve_cross_sections(P, sphere1, oracle_sphere1):
 @pytest.mark.parametrize("prec,method,bar", [(0, 0, 1e-10), (0, 1, 1e-10), (1, 0, 1e-4), (1, 1, 1e-4), (1, 2, 1e-4)])
 def test_mass_inverse_paths(P, sphere1, prec, method, bar):
     """Every way of applying M_A^-1: the sparse FP32 inverse on the graph
-    ball (mass_method 0, the default; 14 Chebyshev steps, its last-step
-    residual over the ball small; an FP64 preconditioner refines each of its
-    products once against the FP64 M_A), dense Gauss-Jordan (1), the dense
+    ball (mass_method 0, the default; radius 8 and 14 Chebyshev steps for an
+    FP64 preconditioner, which refines each of its products once against the
+    FP64 M_A; radius 6 and 12 steps for MIXED; its last-step residual over
+    the ball small), dense Gauss-Jordan (1), the dense
     inverse of mass_method 2 (FP32 by the Chebyshev iteration, its residual
     ||I - X M_A||_F / sqrt(n) below the stopping tolerance 1e-6; FP64 by
     Gauss-Jordan).  The preconditioned operator built from any of them
@@ -134,7 +135,8 @@ def test_mass_inverse_paths(P, sphere1, prec, method, bar):
     prof = ctx.profile()
     note(f"  Chebyshev steps {prof['mass_iterations']}, residual {prof['mass_residual']:.2e}")
     if method == 0:
-        assert prof["mass_iterations"] == 14 and prof["mass_residual"] <= 1e-5
+        assert prof["mass_iterations"] == (14 if prec == 0 else 12)
+        assert prof["mass_residual"] <= (1e-6 if prec == 0 else 1e-5)
     elif method == 2 and prec == 1:
         assert prof["mass_iterations"] > 0 and prof["mass_residual"] <= 1e-6
     else:
@@ -149,6 +151,39 @@ def test_mass_inverse_paths(P, sphere1, prec, method, bar):
     e = rel_fro(y, x @ (pr.precond_matrix() @ pr.A).T)
     note(f"  Ptilde A vs oracle {e:.2e}")
     assert e < bar
+
+
+def test_mass_inverse_radius(P, sphere1):
+    """The radius of the sparse inverse's column sets (mass_hops) against
+    the oracle's exact preconditioned operator: the error of P~ A falls with
+    the radius (mixed precision, down to its FP32 floor; the default radius 6
+    within the 1e-4 bar of the mixed preconditioner), and one refinement
+    step against the FP64 M_A squares it (FP64 at radius 4 against the
+    square of the mixed error at radius 4)."""
+    pr = opm.Problem([sphere1], EPS, 2.0, qP=(1, 1, 1), nP=1, chiP=0.5, precond="S_INT")
+    pr.assemble_A()
+    pr.assemble_P()
+    pr.assemble_mass()
+    ref_op = pr.precond_matrix() @ pr.A
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(2, pr.N)) + 1j * rng.normal(size=(2, pr.N))
+    ref = x @ ref_op.T
+    err = {}
+    for prec, hops in ((1, 2), (1, 4), (1, 6), (1, 8), (0, 4)):
+        ctx = P.Context(0)
+        ctx.add_scatterer(*sphere1, EPS)
+        ctx.set_wavenumber(2.0)
+        ctx.assemble(P.assembly_opts((4, 3, 2), 4, -1.0, prec),
+                     P.assembly_opts((1, 1, 1), 1, 0.5, prec, mass_hops=hops), "S_INT")
+        prof = ctx.profile()
+        err[(prec, hops)] = rel_fro(ctx.apply(1, x), ref)
+        note(f"  precision {prec}, radius {hops}: steps {prof['mass_iterations']}, "
+             f"residual {prof['mass_residual']:.2e}, Ptilde A vs oracle {err[(prec, hops)]:.2e}")
+        assert prof["mass_iterations"] == hops + 6
+        ctx.close()
+    assert err[(1, 2)] > err[(1, 4)] > err[(1, 6)] > err[(1, 8)]
+    assert err[(1, 6)] < 1e-4 and err[(1, 8)] < 2e-6
+    assert err[(0, 4)] < 2.0 * err[(1, 4)] ** 2 + 1e-12
 
 
 _SYM_MESHES = {"ico1": lambda: synth.icosphere(1), "ico2": lambda: synth.icosphere(2),
