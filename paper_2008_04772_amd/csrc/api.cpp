@@ -2288,7 +2288,10 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
 // y = A x (use_ext) or y = A^i x with every entry integrated again in FP64
 // (y overwritten): the product with the FP64 Galerkin matrix when the stored
 // operators are FP32.  Counts as one operator application.
-void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_ext) {
+// y = A x in FP64 without stored operators (use_ext: exterior and interior
+// operators; else the interior ones); xi: input of the interior operators
+// when it differs from x (else null)
+void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_ext, const double* xi = nullptr) {
   if (!c->sing.blk.p) throw Fail{PMCHWT_ERR_STATE, "A not assembled"};
   const int64_t vs = vlen(c);
   const size_t need = size_t(nrhs) * 3 * size_t(c->F_tot) * 4;
@@ -2303,6 +2306,7 @@ void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_
   f.E_tot = c->E_tot;
   f.vs = vs;
   f.x = x;
+  f.xi = xi;
   f.sing_ptr = c->sing.ptr.as<int64_t>();
   f.sing_pairs = c->sing.pairs.as<int32_t>();
   f.sing_blk = c->sing.blk.as<double>();
@@ -2480,8 +2484,10 @@ void incident_projection(pmchwt_ctx* c, const double* dirs, const pmchwt_complex
   }
 }
 
+// b = g/2 - A^i c_inc; g_keep / cinc_keep (optional, 2 vs nrhs doubles each)
+// receive g and c_inc for a later FP64 residual
 void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int nrhs, double* b,
-               bool fp64_interior = false) {
+               bool fp64_interior = false, DBuf* g_keep = nullptr, DBuf* cinc_keep = nullptr) {
   const int64_t E = c->E_tot, vs = vlen(c);
   DBuf g = dalloc_c<double>(c, size_t(2 * vs * nrhs)), cinc = dalloc_c<double>(c, size_t(2 * vs * nrhs)),
        t = dalloc_c<double>(c, size_t(2 * vs * nrhs));
@@ -2510,6 +2516,8 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   HIPCHK(hipMemcpyAsync(b, g.p, size_t(2 * vs * nrhs) * 8, hipMemcpyDeviceToDevice, c->stream));
   launch_axpby(b, t.as<double>(), vs, int(vs), nrhs, 0.5, -1.0, c->stream);
   HIPCHK(hipGetLastError());
+  if (g_keep) *g_keep = std::move(g);
+  if (cinc_keep) *cinc_keep = std::move(cinc);
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
@@ -3283,10 +3291,13 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     c->prof.lookahead_discarded = 0;
     c->prof.ms_free_apply = 0;
     c->prof.free_launches = 0;
-    // a MIXED operator with refinement solves the FP64 system: its right-hand
-    // side and refinement residuals use matrix-free FP64 products
+    // a MIXED operator with refinement solves the FP64 system: GMRES starts
+    // from the right-hand side of the stored (FP32) interior operators, and
+    // every refinement residual r = g/2 - A^i (c_inc + x) - A^e x is one
+    // matrix-free FP64 product, so the FP64 right-hand side enters through it
     const bool fp64_ir = c->precA == PMCHWT_MIXED && o->ir_max > 0;
-    build_rhs(c, dirs, pols, nrhs, b.as<double>(), fp64_ir);
+    DBuf g_inc, c_inc;
+    build_rhs(c, dirs, pols, nrhs, b.as<double>(), false, fp64_ir ? &g_inc : nullptr, fp64_ir ? &c_inc : nullptr);
     c->calls_A = 0;  // the right-hand side's own interior products are not solver matvecs
     c->calls_P = 0;
     // bt = Ptilde b
@@ -3306,11 +3317,16 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     // residual are those of this FP64 check
     int ir = 0;
     while (o->ir_max > 0) {
-      if (fp64_ir)
-        apply_A_free(c, x.as<double>(), r.as<double>(), nrhs, true);
-      else
+      if (fp64_ir) {
+        // u = c_inc + x (in d), r = g/2 - (A^i u + A^e x)
+        HIPCHK(hipMemcpyAsync(d.p, c_inc.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
+        launch_axpby(d.as<double>(), x.as<double>(), vs, int(vs), nrhs, 1.0, 1.0, c->stream);
+        apply_A_free(c, x.as<double>(), r.as<double>(), nrhs, true, d.as<double>());
+        launch_axpby(r.as<double>(), g_inc.as<double>(), vs, int(vs), nrhs, -1.0, 0.5, c->stream);
+      } else {
         apply_A(c, x.as<double>(), r.as<double>(), nrhs);
-      launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
+        launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
+      }
       apply_Ptilde(c, r.as<double>(), s1.as<double>(), s2.as<double>(), d.as<double>(), nrhs);
       std::vector<double> nr(nrhs), nb(nrhs);
       DBuf dn = dalloc_c<double>(c, 2 * nrhs);

@@ -81,7 +81,8 @@ struct FreeJob {
   int nrhs;
   int E_tot;
   int64_t vs;
-  const double* x;
+  const double* x;             // input of the exterior operators (and of the interior ones if xi is null)
+  const double* xi;            // input of the interior operators, or null
   const int64_t* sing_ptr;     // F+1: singular pairs of test triangle t at [sing_ptr[t], sing_ptr[t+1])
   const int32_t* sing_pairs;   // 2 per pair (t1, t2), sorted by t1
   const double* sing_blk;      // SingParams::blk of the same pairs

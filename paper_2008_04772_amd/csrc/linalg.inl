@@ -429,8 +429,10 @@ template void launch_combine3<double>(const double*, const double*, const double
 // exact difference X_rc - X_cr from a CSR correction, so the product equals
 // the one with the full matrices up to rounding.
 //
-// Tile t = (I, J) holds three T x T row-major complex blocks (C, S1, S2);
-// entries outside the n x n operator are zero.  Partial sums: slot (K, s) of
+// Tile t = (I, J) holds three T x T complex blocks (C, S1, S2) with their
+// rows interleaved (row r of C, of S1, of S2, then row r + 1), so that one
+// step of the product reads one contiguous span rather than three streams
+// a block apart; entries outside the n x n operator are zero.  Partial sums: slot (K, s) of
 // T rows x 4 doubles (yD re/im, yN re/im) is written by exactly one tile
 // (row sums of (K, s) for K <= s, column sums of (s, K) for K > s) and added
 // in slot order by k_sym_reduce.
@@ -446,13 +448,14 @@ __global__ void k_pack_sym3(const M* __restrict__ Se, const M* __restrict__ Ce, 
   const int R = tij[2 * t] * T + r, Cc = tij[2 * t + 1] * T + cc;
   M o[6] = {M(0), M(0), M(0), M(0), M(0), M(0)};
   if (R < n && Cc < n) combine_entry(Se, Ce, Si, Ci, int64_t(R) * ld + Cc, ke, kir, kii, o);
-  M* b = P + t * 3 * MAT + 2 * w;
+  // rows of the three blocks interleaved: tile t, row r, block b, column cc
+  M* b = P + t * 3 * MAT + int64_t(r) * 6 * T + 2 * cc;
   b[0] = o[0];
   b[1] = o[1];
-  b[MAT] = o[2];
-  b[MAT + 1] = o[3];
-  b[2 * MAT] = o[4];
-  b[2 * MAT + 1] = o[5];
+  b[2 * T] = o[2];
+  b[2 * T + 1] = o[3];
+  b[4 * T] = o[4];
+  b[4 * T + 1] = o[5];
 }
 
 // correction entry k at (R, Cc), tile(R) > tile(Cc): X_RCc - X_CcR for the
@@ -651,12 +654,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     V cv[RPS][NU], av[RPS][NU], bv[RPS][NU];
 #pragma unroll
     for (int j = 0; j < RPS; ++j) {
-      const V* rc = base + int64_t(r0 + G * j) * (T / 2) + cl;
+      const V* rc = base + int64_t(r0 + G * j) * (3 * T / 2) + cl;
 #pragma unroll
       for (int k = 0; k < NU; ++k) {
         cv[j][k] = __builtin_nontemporal_load(rc + LPR * k);
-        av[j][k] = __builtin_nontemporal_load(rc + MATV + LPR * k);
-        bv[j][k] = __builtin_nontemporal_load(rc + 2 * MATV + LPR * k);
+        av[j][k] = __builtin_nontemporal_load(rc + T / 2 + LPR * k);
+        bv[j][k] = __builtin_nontemporal_load(rc + T + LPR * k);
       }
     }
     double a[RPS][4];

@@ -1,7 +1,8 @@
 // Matrix-free FP64 products with the PMCHWT operator (Section 2) for the
-// iterative-refinement residual r = b - A x and the interior operator of the
-// right-hand side, (1/2 I - A^i) u^inc (Section 3.2), of a solve whose stored
-// operators are FP32.  Every entry is integrated again in FP64 with the same
+// iterative-refinement residual of a solve whose stored operators are FP32:
+// r = b - A x with b = g/2 - A^i c_inc (Section 3.2) is g/2 - (A^i u + A^e x)
+// with u = c_inc + x, one product whose exterior and interior operators read
+// different inputs (x and xi).  Every entry is integrated again in FP64 with the same
 // rules as the FP64 assembly (regular pairs: tensor symmetric rules by
 // relative distance; singular pairs: the Sauter-Schwab values the singular
 // kernel keeps in FP64), and contracted with x on the fly, so the product is
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(FREE_THREADS, 2) void k_free_apply(AsmParams<double
     const bool decay = kk == 1 && kii != 0.0;
     const double ik2 = 1.0 / (kr * kr + ki * ki);
     const cplx<double> g1 = kk == 0 ? fe1 : fi1, g2 = kk == 0 ? fe2 : fi2;
+    const double* xin = (kk == 1 && f.xi) ? f.xi : f.x;
     for (int t2 = threadIdx.x; t2 < F; t2 += FREE_THREADS) {
       if (kk == 1 && p.tscat[t2] != s1) continue;  // interior operators: one scatterer
       bool shared = false;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(FREE_THREADS, 2) void k_free_apply(AsmParams<double
         cplx<double> gxN[RC], gxD[RC], xD[RC], xN[RC];
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
-          const double* xr = f.x + 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
+          const double* xr = xin + 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
           xD[r] = {xr[2 * jb], xr[2 * jb + 1]};
           xN[r] = {xr[2 * (f.E_tot + jb)], xr[2 * (f.E_tot + jb) + 1]};
           gxN[r] = cmul(g1, xN[r]);
@@ -212,20 +214,25 @@ __global__ __launch_bounds__(FREE_THREADS, 2) void k_free_apply(AsmParams<double
 #pragma unroll
     for (int b = 0; b < 3; ++b) jb[b] = p.t2e[b * F + t2];
     const cplx<double>* blk = reinterpret_cast<const cplx<double>*>(f.sing_blk) + sp * 36;
+    const double* xin = f.xi ? f.xi : f.x;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      cplx<double> xD[RC], xN[RC];
+      cplx<double> xD[RC], xN[RC], uD[RC], uN[RC];
 #pragma unroll
       for (int r = 0; r < RC; ++r) {
-        const double* xr = f.x + 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
+        const int64_t ro = 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
+        const double* xr = f.x + ro;
+        const double* ur = xin + ro;
         xD[r] = {xr[2 * jb[b]], xr[2 * jb[b] + 1]};
         xN[r] = {xr[2 * (f.E_tot + jb[b])], xr[2 * (f.E_tot + jb[b]) + 1]};
+        uD[r] = {ur[2 * jb[b]], ur[2 * jb[b] + 1]};
+        uN[r] = {ur[2 * (f.E_tot + jb[b])], ur[2 * (f.E_tot + jb[b]) + 1]};
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const cplx<double>* e = blk + 4 * (3 * a + b);
         if (f.use_ext) apply_block<RC>(acc, a, e[0], e[1], fe1, fe2, xD, xN);
-        apply_block<RC>(acc, a, e[2], e[3], fi1, fi2, xD, xN);
+        apply_block<RC>(acc, a, e[2], e[3], fi1, fi2, uD, uN);
       }
     }
   }

@@ -99,13 +99,16 @@ struct ServeRun {
     d = DBuf();
     r = DBuf();
     sA = DBuf();
+    g_inc = DBuf();
+    c_inc = DBuf();
     hn.reset();
     if (c) pmchwt_destroy(c);
   }
 
-  // MIXED operators with refinement: FP64 right-hand side and residuals
-  // (matrix-free FP64 products), as in pmchwt_solve
+  // MIXED operators with refinement: FP64 residuals r = g/2 - A^i (c_inc +
+  // x) - A^e x (one matrix-free FP64 product each), as in pmchwt_solve
   bool fp64_ir = false;
+  DBuf g_inc, c_inc;
 
   void init() {
     const pmchwt_solver_opts& o = rec->so;
@@ -123,7 +126,8 @@ struct ServeRun {
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     t0 = now_ms();
     fp64_ir = c->precA == PMCHWT_MIXED && o.ir_max > 0;
-    build_rhs(c, rec->dirs.data(), rec->pols.data(), nrhs, b.as<double>(), fp64_ir);
+    build_rhs(c, rec->dirs.data(), rec->pols.data(), nrhs, b.as<double>(), false, fp64_ir ? &g_inc : nullptr,
+              fp64_ir ? &c_inc : nullptr);
     c->calls_A = 0;
     c->calls_P = 0;
     apply_Ptilde(c, b.as<double>(), bt.as<double>(), s1.as<double>(), s2.as<double>(), nrhs);
@@ -169,7 +173,10 @@ struct ServeRun {
   // the rest of the step's operator application, enqueued on the run's stream
   void post_A() {
     if (st == IR_CHECK) {  // r = b - A x, s1 = Ptilde r, |s1|, |bt|
-      launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
+      if (fp64_ir)  // r held A^i (c_inc + x) + A^e x
+        launch_axpby(r.as<double>(), g_inc.as<double>(), vs, int(vs), nrhs, -1.0, 0.5, c->stream);
+      else
+        launch_axpby(r.as<double>(), b.as<double>(), vs, int(vs), nrhs, -1.0, 1.0, c->stream);
       apply_Ptilde(c, r.as<double>(), s1.as<double>(), s2.as<double>(), d.as<double>(), nrhs);
       double* dn = g_norm_scratch();
       launch_norms(s1.as<double>(), vs, int(vs), nrhs, dn, c->stream);
@@ -450,7 +457,10 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
     R.grouped = !(c->precA == PMCHWT_MIXED && R.nrhs >= MFMA_MIN_RHS);
     if (R.st == ServeRun::IR_CHECK && R.fp64_ir) {  // FP64 refinement residual on the run's stream
       R.grouped = false;
-      apply_A_free(c, in, out, R.nrhs, true);
+      // interior input c_inc + x in d (free until the check's own scratch use)
+      HIPCHK(hipMemcpyAsync(R.d.p, R.c_inc.p, R.nd * 8, hipMemcpyDeviceToDevice, c->stream));
+      launch_axpby(R.d.as<double>(), in, vs, int(vs), R.nrhs, 1.0, 1.0, c->stream);
+      apply_A_free(c, in, out, R.nrhs, true, R.d.as<double>());
       continue;
     }
     if (!R.grouped) {
