@@ -220,6 +220,9 @@ typedef struct {
   double wall_dual;          /* host wall time of the barycentric refinement and the
                                 upload of its dual-cell tables (first assemble of a
                                 geometry)                                             */
+  double ms_fp64_copy;       /* device time of the FP64 copy of A that a MIXED solve
+                                with refinement and 4 or more right-hand sides
+                                assembles for its residuals (once per assemble)       */
 } pmchwt_profile;
 
 /* Version string of the library. */

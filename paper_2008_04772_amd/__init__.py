@@ -73,7 +73,7 @@ class pmchwt_profile(ctypes.Structure):
                 ("ms_matvec_reduce", ctypes.c_double), ("matvec_timed", ctypes.c_int64),
                 ("ms_free_apply", ctypes.c_double), ("free_launches", ctypes.c_int64),
                 ("wall_tables_A", ctypes.c_double), ("wall_tables_P", ctypes.c_double),
-                ("wall_dual", ctypes.c_double)]
+                ("wall_dual", ctypes.c_double), ("ms_fp64_copy", ctypes.c_double)]
 
 
 class pmchwt_server_opts(ctypes.Structure):

@@ -232,6 +232,16 @@ struct pmchwt_ctx {
   // preconditioner refines their products against these
   std::vector<SparseInv> MAcsr, MATcsr;
   std::vector<char> mass_sparse;
+  // FP64 copy of A (full rows) for the refinement residuals of MIXED solves
+  // with many right-hand sides, built on the first such solve after an
+  // assembly
+  struct {
+    bool valid = false;
+    DBuf Se, Ce;
+    std::vector<DBuf> Si, Ci;
+    std::vector<int64_t> ldI;
+    int64_t ldE = 0;
+  } a64;
   // structural patterns of M_A and M_A^T over the union edges (geometry only)
   struct {
     bool valid = false;
@@ -2323,6 +2333,125 @@ void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_
   if (use_ext) c->calls_A += 1;
 }
 
+// MIXED solves with refinement and at least this many right-hand sides take
+// their FP64 residuals from an FP64 copy of A instead of the matrix-free
+// product, which integrates every pair again for each right-hand side.
+constexpr int FREE_MAX_RHS = 4;
+
+// The FP64 copy of A: the FP64 assembly (full rows, no combined matrices)
+// run on the context's operator slots, with the FP32 state kept aside and
+// put back afterwards (also when the assembly fails).
+void ensure_a64(pmchwt_ctx* c) {
+  if (c->a64.valid) return;
+  struct Keep {
+    pmchwt_ctx* c;
+    DBuf Se, Ce, Si_ptr, Ci_ptr, ld_int, AC, AS1, AS2, pack, val, part;
+    std::vector<DBuf> Si, Ci;
+    std::vector<int64_t> ldI;
+    int64_t ldE;
+    bool comb, comb_ok, ready, stale[4];
+    pmchwt_profile prof;
+    double recompute;
+    int precA;
+    pmchwt_assembly_opts optA;
+    explicit Keep(pmchwt_ctx* cc) : c(cc) {
+      Se = std::move(c->Se);
+      Ce = std::move(c->Ce);
+      Si_ptr = std::move(c->Si_ptr);
+      Ci_ptr = std::move(c->Ci_ptr);
+      ld_int = std::move(c->ld_int);
+      AC = std::move(c->AC);
+      AS1 = std::move(c->AS1);
+      AS2 = std::move(c->AS2);
+      pack = std::move(c->sym.pack);
+      val = std::move(c->sym.val);
+      part = std::move(c->sym.part);
+      Si = std::move(c->Si);
+      Ci = std::move(c->Ci);
+      ldI = c->ldI;
+      ldE = c->ldE;
+      comb = c->comb;
+      comb_ok = c->comb_ok;
+      ready = c->sym.ready;
+      for (int k = 0; k < 4; ++k) stale[k] = c->sym.lower_stale[k];
+      prof = c->prof;
+      recompute = c->recompute;
+      precA = c->precA;
+      optA = c->optA;
+    }
+    ~Keep() {
+      c->Se = std::move(Se);
+      c->Ce = std::move(Ce);
+      c->Si_ptr = std::move(Si_ptr);
+      c->Ci_ptr = std::move(Ci_ptr);
+      c->ld_int = std::move(ld_int);
+      c->AC = std::move(AC);
+      c->AS1 = std::move(AS1);
+      c->AS2 = std::move(AS2);
+      c->sym.pack = std::move(pack);
+      c->sym.val = std::move(val);
+      c->sym.part = std::move(part);
+      c->Si = std::move(Si);
+      c->Ci = std::move(Ci);
+      c->ldI = ldI;
+      c->ldE = ldE;
+      c->comb = comb;
+      c->comb_ok = comb_ok;
+      c->sym.ready = ready;
+      for (int k = 0; k < 4; ++k) c->sym.lower_stale[k] = stale[k];
+      const double ms = c->prof.ms_assemble_A;
+      c->prof = prof;
+      c->prof.ms_fp64_copy = ms;
+      c->recompute = recompute;
+      c->precA = precA;
+      c->optA = optA;
+    }
+  } keep(c);
+  pmchwt_assembly_opts o = c->optA;
+  o.precision = PMCHWT_FP64;
+  o.operator_form = 1;
+  c->optA = o;
+  c->comb_ok = false;
+  c->precA = PMCHWT_FP64;
+  assemble_A_impl<double>(c, o);
+  c->a64.Se = std::move(c->Se);
+  c->a64.Ce = std::move(c->Ce);
+  c->a64.Si = std::move(c->Si);
+  c->a64.Ci = std::move(c->Ci);
+  c->a64.ldI = c->ldI;
+  c->a64.ldE = c->ldE;
+  c->a64.valid = true;
+}
+
+// y = A^i u + A^e x from the FP64 copy of A (u: input of the interior
+// operators), for the refinement residual g/2 - A^i (c_inc + x) - A^e x
+void apply_A64_split(pmchwt_ctx* c, const double* x, const double* u, double* y, int nrhs) {
+  const int64_t E = c->E_tot, vs = vlen(c);
+  launch_zero(y, 2 * vs * nrhs, c->stream);
+  launch_gemv_pmchwt<double>(c->a64.Se.as<double>(), c->a64.Ce.as<double>(), c->a64.ldE, int(E), int(E), c->k_ext,
+                             0.0, x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
+  for (size_t m = 0; m < c->sc.size(); ++m) {
+    const Scat& s = c->sc[m];
+    const int64_t o = s.edge_off;
+    launch_gemv_pmchwt<double>(c->a64.Si[m].as<double>(), c->a64.Ci[m].as<double>(), c->a64.ldI[m], s.topo.E,
+                               s.topo.E, s.k.real(), s.k.imag(), u + 2 * o, u + 2 * (E + o), y + 2 * o,
+                               y + 2 * (E + o), nrhs, vs, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  c->calls_A += 1;
+}
+
+// FP64 refinement residual product y = A^i u + A^e x: the FP64 copy of A for
+// many right-hand sides, else the matrix-free product
+void apply_A_resid(pmchwt_ctx* c, const double* x, const double* u, double* y, int nrhs) {
+  if (nrhs >= FREE_MAX_RHS) {
+    ensure_a64(c);
+    apply_A64_split(c, x, u, y, nrhs);
+  } else {
+    apply_A_free(c, x, y, nrhs, true, u);
+  }
+}
+
 // z = M_P^-1 P M_A^-1 y  (z overwritten; tmp: 2 vectors of scratch)
 void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double* t2, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -3051,6 +3180,11 @@ int pmchwt_assemble(pmchwt_ctx* c, const pmchwt_assembly_opts* A, const pmchwt_a
     c->have_A = false;
     flush_times(c);
     c->prof = pmchwt_profile{};
+    c->a64.valid = false;
+    c->a64.Se = DBuf();
+    c->a64.Ce = DBuf();
+    c->a64.Si.clear();
+    c->a64.Ci.clear();
     const double w0 = wall_ms();
     build_duals(c);
     c->prof.wall_dual = wall_ms() - w0;
@@ -3321,7 +3455,7 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
         // u = c_inc + x (in d), r = g/2 - (A^i u + A^e x)
         HIPCHK(hipMemcpyAsync(d.p, c_inc.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
         launch_axpby(d.as<double>(), x.as<double>(), vs, int(vs), nrhs, 1.0, 1.0, c->stream);
-        apply_A_free(c, x.as<double>(), r.as<double>(), nrhs, true, d.as<double>());
+        apply_A_resid(c, x.as<double>(), d.as<double>(), r.as<double>(), nrhs);
         launch_axpby(r.as<double>(), g_inc.as<double>(), vs, int(vs), nrhs, -1.0, 0.5, c->stream);
       } else {
         apply_A(c, x.as<double>(), r.as<double>(), nrhs);

@@ -281,7 +281,10 @@ __global__ void k_free_combine(FreeJob f, int F) {
 }
 
 void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t st) {
-  const int rc = f.nrhs >= 4 ? 4 : (f.nrhs >= 2 ? 2 : 1);
+  // one right-hand side per workgroup: the variants with 2 or 4 exceed the
+  // register file and spill (the integrals are the cost; callers with many
+  // right-hand sides use an assembled FP64 operator instead)
+  const int rc = 1;
   const dim3 grid{unsigned(p.F), unsigned((f.nrhs + rc - 1) / rc)};
   if (rc == 4)
     hipLaunchKernelGGL(k_free_apply<4>, grid, dim3(FREE_THREADS), 0, st, p, f);

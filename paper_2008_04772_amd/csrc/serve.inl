@@ -65,7 +65,18 @@ int64_t serve_estimate(const ServeRecord& r) {
   const double N = 2.0 * Etot, nr = r.nrhs, rho = r.so.restart;
   const double kry = (rho + 6.0) * nr * N * 16.0 * 2.0 + 10.0 * nr * N * 16.0 + 2.0 * 4.0 * nr * 2.0 * (Etot + 32) * 4.0;
   const double tables = 6.0 * Etot * 400.0;
-  return int64_t(1.15 * (A + slab + P + mass + kry + tables) + 64.0e6);
+  // FP64 copy of A for the refinement residuals of MIXED requests with many
+  // right-hand sides (full rows of every operator, FP64 slot-row slabs)
+  double a64 = 0.0;
+  if (r.oA.precision == PMCHWT_MIXED && r.so.ir_max > 0 && r.nrhs >= FREE_MAX_RHS) {
+    a64 = 2.0 * Etot * double(padld(int64_t(Etot))) * 16.0;
+    for (auto& t : r.tris) {
+      const double E = 1.5 * double(t.size() / 3);
+      a64 += 2.0 * E * double(padld(int64_t(E))) * 16.0;
+    }
+    a64 += slab;
+  }
+  return int64_t(1.15 * (A + slab + P + mass + kry + tables + a64) + 64.0e6);
 }
 
 // One admitted request: its context, solve buffers and the staged solve
@@ -460,7 +471,7 @@ void pmchwt_server::round(std::vector<std::unique_ptr<ServeRun>>& live) {
       // interior input c_inc + x in d (free until the check's own scratch use)
       HIPCHK(hipMemcpyAsync(R.d.p, R.c_inc.p, R.nd * 8, hipMemcpyDeviceToDevice, c->stream));
       launch_axpby(R.d.as<double>(), in, vs, int(vs), R.nrhs, 1.0, 1.0, c->stream);
-      apply_A_free(c, in, out, R.nrhs, true, R.d.as<double>());
+      apply_A_resid(c, in, R.d.as<double>(), out, R.nrhs);
       continue;
     }
     if (!R.grouped) {
