@@ -216,6 +216,9 @@ struct pmchwt_ctx {
   bool P_int = false, P_ext = false, P_C = false, P_cross = false;
   int64_t nnzP = 0;
   DBuf p_rowptr, p_col, PSi, PCi, PSe, PCe;
+  // FP32 copies of the values for the products of a MIXED preconditioner
+  // (the FP64 ones stay for copy-out)
+  DBuf PSi32, PCi32, PSe32, PCe32;
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_col;
   // mass / Gram
@@ -1364,6 +1367,10 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   c->PCi.release();
   c->PSe.release();
   c->PCe.release();
+  c->PSi32.release();
+  c->PCi32.release();
+  c->PSe32.release();
+  c->PCe32.release();
   c->precond = kind;
   c->P_int = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_INT || kind == PMCHWT_P_S_INT);
   c->P_ext = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_EXT || kind == PMCHWT_P_S_EXT);
@@ -1397,6 +1404,18 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
     if (c->P_C) vals(c->PCe);
   }
   run_nearfield_kernel(c, o, cells);
+  if (o.precision == PMCHWT_MIXED) {
+    auto f32 = [&](const DBuf& src, DBuf& dst) {
+      if (!src.p) return;
+      dst = dalloc_c<float>(c, 2 * size_t(std::max<int64_t>(c->nnzP, 1)));
+      launch_d2f(src.as<double>(), dst.as<float>(), 2 * c->nnzP, c->stream);
+    };
+    f32(c->PSi, c->PSi32);
+    f32(c->PCi, c->PCi32);
+    f32(c->PSe, c->PSe32);
+    f32(c->PCe, c->PCe32);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 // Near-field pattern of P (entries (i, j), i and j in one scatterer unless
@@ -2512,18 +2531,26 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   const int64_t* rp = c->p_rowptr.as<int64_t>();
   const int32_t* cl = c->p_col.as<int32_t>();
   if (!c->P_int && !c->P_ext) launch_zero(t2, 2 * vs * nrhs, c->stream);
+  // FP32 values when the preconditioner was assembled MIXED
+  auto spmv = [&](const int64_t* rpp, const DBuf& S64, const DBuf& C64, const DBuf& S32, const DBuf& C32, int rows,
+                  double kr, double ki, const double* xD, const double* xN, double* yD, double* yN, bool acc) {
+    if (S32.p)
+      launch_spmv_pmchwt<float>(rpp, cl, S32.as<float>(), c->P_C ? C32.as<float>() : nullptr, rows, kr, ki, xD, xN, yD,
+                                yN, nrhs, vs, c->stream, acc);
+    else
+      launch_spmv_pmchwt<double>(rpp, cl, S64.as<double>(), c->P_C ? C64.as<double>() : nullptr, rows, kr, ki, xD, xN,
+                                 yD, yN, nrhs, vs, c->stream, acc);
+  };
   if (c->P_int) {
     for (size_t m = 0; m < c->sc.size(); ++m) {
       const Scat& s = c->sc[m];
       const int64_t o = s.edge_off;
-      launch_spmv_pmchwt<double>(rp + o, cl, c->PSi.as<double>(), c->P_C ? c->PCi.as<double>() : nullptr, s.topo.E,
-                                 s.k.real(), s.k.imag(), t1, t1 + 2 * E, t2 + 2 * o, t2 + 2 * (E + o), nrhs, vs,
-                                 c->stream, false);
+      spmv(rp + o, c->PSi, c->PCi, c->PSi32, c->PCi32, s.topo.E, s.k.real(), s.k.imag(), t1, t1 + 2 * E, t2 + 2 * o,
+           t2 + 2 * (E + o), false);
     }
   }
   if (c->P_ext)
-    launch_spmv_pmchwt<double>(rp, cl, c->PSe.as<double>(), c->P_C ? c->PCe.as<double>() : nullptr, int(E), c->k_ext,
-                               0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, nrhs, vs, c->stream, c->P_int);
+    spmv(rp, c->PSe, c->PCe, c->PSe32, c->PCe32, int(E), c->k_ext, 0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, c->P_int);
   for (size_t m = 0; m < c->sc.size(); ++m) mass_inv(m, true, -1.0, t2, z);
   HIPCHK(hipGetLastError());
 }

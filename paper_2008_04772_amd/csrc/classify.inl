@@ -23,6 +23,17 @@ __global__ void k_cls_fill_i32(int32_t* p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
+// out[i] = float(in[i]) (rounded to nearest)
+__global__ void k_d2f(const double* in, float* out, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = float(in[i]);
+}
+
+void launch_d2f(const double* in, float* out, int64_t n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_d2f, dim3(unsigned(std::min<int64_t>(4096, (n + 255) / 256))), dim3(256), 0, st, in, out, n);
+}
+
 __global__ void k_cls_set_i64(int64_t* p, int64_t v) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }

@@ -520,6 +520,7 @@ struct SymRecJob {
   int32_t* item;
 };
 void launch_cls_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_d2f(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_cls_set_i64(int64_t* p, int64_t v, hipStream_t st);
 void launch_scan_i32(const int32_t* cnt, int n, int64_t* rowptr, hipStream_t st);
 void launch_nf_bin(const double* box, int E, const NfGrid& g, int32_t* gcell, int32_t* gcnt, hipStream_t st);
