@@ -127,12 +127,15 @@ struct HalfC {
 
 // R: precision of the pair moments and contractions (FP64, or FP32 for a
 // mixed-precision preconditioner); the kept entries are added in FP64.
-template <typename R>
+// NK: wavenumbers the LDS holds per child pair (1 or 2, the most any cell
+// pair of the launch needs); the slot sums stay in registers, slots lane,
+// lane + 64, ... of the N_v x N_w <= 256 of the pair
+constexpr int BC_SLOTS_PER_LANE = BC_MAX_RING * BC_MAX_RING / 4 / 64;
+template <typename R, int NK>
 __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
-  __shared__ R s_mom[BC_CHUNK_PAIRS * 2 * MOM_D];
+  __shared__ R s_mom[BC_CHUNK_PAIRS * NK * MOM_D];
   __shared__ double s_org[BC_MAX_RING][3];
-  __shared__ HalfC<R> s_half[BC_CHUNK_PAIRS / 2][2];
-  __shared__ R s_acc[BC_MAX_RING * BC_MAX_RING / 4][8];
+  __shared__ HalfC<R> s_half[BC_CHUNK_PAIRS / 2][NK];
   const int lane = threadIdx.x;
   const int64_t pr = blockIdx.x;
   const int v = j.cpairs[2 * pr], w = j.cpairs[2 * pr + 1];
@@ -147,8 +150,11 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
   const double kr0 = do_int ? j.k_int[2 * sc1] : j.k_ext, ki0 = do_int ? j.k_int[2 * sc1 + 1] : 0.0;
   const double kr1 = j.k_ext, ki1 = 0.0;
   const bool withC = j.want_C;
-  for (int s = lane; s < nslot; s += 64)
-    for (int q = 0; q < 8; ++q) s_acc[s][q] = R(0);
+  R acc[BC_SLOTS_PER_LANE][8];
+#pragma unroll
+  for (int t = 0; t < BC_SLOTS_PER_LANE; ++t)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[t][q] = R(0);
   const int rows_per_chunk = max(1, BC_CHUNK_PAIRS / n2);
   const double* cv = c.coef + 4 * c.coef_ptr[v];
   const double* cw = c.coef + 4 * c.coef_ptr[w];
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
                         j.q_far, R(k == 0 ? kr0 : kr1), R(k == 0 ? ki0 : ki1), withC, m);
         const R* f = reinterpret_cast<const R*>(&m);
 #pragma unroll
-        for (int q = 0; q < MOM_D; ++q) s_mom[(p * 2 + k) * MOM_D + q] = f[q];
+        for (int q = 0; q < MOM_D; ++q) s_mom[(p * NK + k) * MOM_D + q] = f[q];
       }
       if (u2 == 0)
         for (int d = 0; d < 3; ++d) s_org[u1 - r0][d] = ga.cen[d];
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
           const double* c2 = cw + 4 * (int64_t(sj) * n2 + u2);
           const R a2 = R(c2[0]);
           const R w2[3] = {R(c2[1] - c2[0] * o[0]), R(c2[2] - c2[0] * o[1]), R(c2[3] - c2[0] * o[2])};
-          const Moments<R>& m = *reinterpret_cast<const Moments<R>*>(&s_mom[((ur * n2 + u2) * 2 + k) * MOM_D]);
+          const Moments<R>& m = *reinterpret_cast<const Moments<R>*>(&s_mom[((ur * n2 + u2) * NK + k) * MOM_D]);
           // Ta
           T[0] += a2 * m.Mxy.re - (w2[0] * m.Mx[0].re + w2[1] * m.Mx[1].re + w2[2] * m.Mx[2].re);
           T[1] += a2 * m.Mxy.im - (w2[0] * m.Mx[0].im + w2[1] * m.Mx[1].im + w2[2] * m.Mx[2].im);
@@ -214,11 +220,11 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
     }
     __syncthreads();
     // ---- B2: test side, one (si, sj) per lane
-    for (int s = lane; s < nslot; s += 64) {
-      const int si = s / N2, sj = s % N2;
-      R acc[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = s_acc[s][q];
+    for (int t = 0; t < BC_SLOTS_PER_LANE; ++t) {
+      const int s = lane + 64 * t;
+      if (s >= nslot) continue;
+      const int si = s / N2, sj = s % N2;
       for (int k = 0; k < nk; ++k) {
         R sv_re = 0, sv_im = 0, sd_re = 0, sd_im = 0, cc_re = 0, cc_im = 0;
         for (int ur = 0; ur < nr; ++ur) {
@@ -244,33 +250,33 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
         const bool to_int = do_int && k == 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          acc[q] += to_int ? R(v[q]) : R(0);
-          acc[4 + q] += to_int ? R(0) : R(v[q]);
+          acc[t][q] += to_int ? R(v[q]) : R(0);
+          acc[t][4 + q] += to_int ? R(0) : R(v[q]);
         }
       }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s_acc[s][q] = acc[q];
     }
   }
-  __syncthreads();
   const int64_t* pos = j.slot_pos + j.slot_off[pr];
-  for (int s = lane; s < nslot; s += 64) {
+#pragma unroll
+  for (int t = 0; t < BC_SLOTS_PER_LANE; ++t) {
+    const int s = lane + 64 * t;
+    if (s >= nslot) continue;
     const int64_t ps = pos[s];
     if (ps < 0) continue;
     if (do_int) {
-      atomic_add(&j.out_Si[2 * ps], double(s_acc[s][0]));
-      atomic_add(&j.out_Si[2 * ps + 1], double(s_acc[s][1]));
+      atomic_add(&j.out_Si[2 * ps], double(acc[t][0]));
+      atomic_add(&j.out_Si[2 * ps + 1], double(acc[t][1]));
       if (withC) {
-        atomic_add(&j.out_Ci[2 * ps], double(s_acc[s][2]));
-        atomic_add(&j.out_Ci[2 * ps + 1], double(s_acc[s][3]));
+        atomic_add(&j.out_Ci[2 * ps], double(acc[t][2]));
+        atomic_add(&j.out_Ci[2 * ps + 1], double(acc[t][3]));
       }
     }
     if (do_ext) {
-      atomic_add(&j.out_Se[2 * ps], double(s_acc[s][4]));
-      atomic_add(&j.out_Se[2 * ps + 1], double(s_acc[s][5]));
+      atomic_add(&j.out_Se[2 * ps], double(acc[t][4]));
+      atomic_add(&j.out_Se[2 * ps + 1], double(acc[t][5]));
       if (withC) {
-        atomic_add(&j.out_Ce[2 * ps], double(s_acc[s][6]));
-        atomic_add(&j.out_Ce[2 * ps + 1], double(s_acc[s][7]));
+        atomic_add(&j.out_Ce[2 * ps], double(acc[t][6]));
+        atomic_add(&j.out_Ce[2 * ps + 1], double(acc[t][7]));
       }
     }
   }
@@ -283,10 +289,18 @@ void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, cons
     jj.npairs = std::min<int64_t>(j.npairs - p0, int64_t(1) << 30);
     jj.cpairs = j.cpairs + 2 * p0;
     jj.slot_off = j.slot_off + p0;
-    if (j.fp32)
-      hipLaunchKernelGGL(k_bc_nearfield<float>, dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
-    else
-      hipLaunchKernelGGL(k_bc_nearfield<double>, dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+    const bool two = j.want_int && j.want_ext;  // a cell pair may need both wavenumbers
+    if (j.fp32) {
+      if (two)
+        hipLaunchKernelGGL((k_bc_nearfield<float, 2>), dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+      else
+        hipLaunchKernelGGL((k_bc_nearfield<float, 1>), dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+    } else {
+      if (two)
+        hipLaunchKernelGGL((k_bc_nearfield<double, 2>), dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+      else
+        hipLaunchKernelGGL((k_bc_nearfield<double, 1>), dim3(unsigned(jj.npairs)), dim3(64), 0, st, c, jj);
+    }
   }
 }
 
