@@ -272,8 +272,8 @@ struct pmchwt_ctx {
     bool valid = false;
     double chi = 0;
     bool cross = false;
-    DBuf cpairs, slot_off, slot_pos;
-    int64_t npairs = 0, bary_pairs = 0, nnz = 0;
+    DBuf cpairs, slot_off, slot_pos, entry_slots;
+    int64_t npairs = 0, bary_pairs = 0, nnz = 0, nslots = 0;
     bool host_valid = false;  // h_rowptr / h_col hold the device pattern
   } nf;
   struct {
@@ -1391,9 +1391,8 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   }
   c->nnzP = c->nf.nnz;
   c->prof.bary_pairs = c->nf.bary_pairs;
-  auto vals = [&](DBuf& b) {
-    realloc_c<double>(c, b, 2 * size_t(c->nnzP));
-    launch_zero(b.as<double>(), 2 * c->nnzP, c->stream);
+  auto vals = [&](DBuf& b) {  // every entry is written by the gather of the near-field kernel
+    realloc_c<double>(c, b, 2 * size_t(std::max<int64_t>(c->nnzP, 1)));
   };
   if (c->P_int) {
     vals(c->PSi);
@@ -1545,6 +1544,9 @@ void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross, const CellDev
   c->nf.cpairs = dalloc_c<int32_t>(c, size_t(2 * std::max<int64_t>(npairs, 1)));
   c->nf.slot_off = dalloc_c<int64_t>(c, size_t(npairs) + 1);
   c->nf.slot_pos = dalloc_c<int64_t>(c, size_t(std::max<int64_t>(nslots, 1)));
+  c->nf.entry_slots = dalloc_c<int64_t>(c, 4 * size_t(std::max<int64_t>(nnz, 1)));
+  launch_cls_fill_i32(reinterpret_cast<int32_t*>(c->nf.entry_slots.p), 8 * std::max<int64_t>(nnz, 1), -1, st);
+  P.entry_slots = c->nf.entry_slots.as<int64_t>();
   P.pairoff = pairoff.as<int64_t>();
   P.slotbase = slotbase.as<int64_t>();
   P.cpairs = c->nf.cpairs.as<int32_t>();
@@ -1554,6 +1556,7 @@ void build_nearfield_tables(pmchwt_ctx* c, double chi, bool cross, const CellDev
   launch_cls_set_i64(c->nf.slot_off.as<int64_t>() + npairs, nslots, st);
   HIPCHK(hipGetLastError());
   c->nf.bary_pairs = 4 * nslots;  // 4 barycentric pairs per (slot of v) x (slot of w)
+  c->nf.nslots = nslots;
   c->nf.npairs = npairs;
   HIPCHK(hipStreamSynchronize(st));  // the host inputs above go out of scope
 }
@@ -1596,8 +1599,17 @@ void run_nearfield_kernel(pmchwt_ctx* c, const pmchwt_assembly_opts& o, CellDev&
   j.out_Ci = c->PCi.as<double>();
   j.out_Se = c->PSe.as<double>();
   j.out_Ce = c->PCe.as<double>();
+  j.nv = 2 * ((c->P_int ? 1 : 0) + (c->P_ext ? 1 : 0)) * (c->P_C ? 2 : 1);
+  DBuf sv = dalloc_c<double>(c, size_t(std::max<int64_t>(c->nf.nslots, 1)) * size_t(j.nv));
+  j.slot_val = sv.as<double>();
+  j.entry_slots = c->nf.entry_slots.as<int64_t>();
+  j.nnz = c->nf.nnz;
+  j.nslots = c->nf.nslots;
   EvTimer t(c->stream);
-  if (j.npairs > 0) launch_bc_nearfield(asm_params<double>(c), cells.params(), j, c->stream);
+  if (j.npairs > 0) {
+    launch_bc_nearfield(asm_params<double>(c), cells.params(), j, c->stream);
+    launch_bc_gather(j, c->stream);
+  }
   HIPCHK(hipGetLastError());
   c->prof.ms_assemble_P = t.stop();
   c->prof.nnz_P = c->nnzP;

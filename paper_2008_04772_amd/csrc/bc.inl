@@ -256,30 +256,73 @@ __global__ __launch_bounds__(64) void k_bc_nearfield(CellParams c, BCJob j) {
       }
     }
   }
-  const int64_t* pos = j.slot_pos + j.slot_off[pr];
+  // every slot of a kept entry written once (zero for an operator this pair
+  // does not reach); launch_bc_gather adds the four slots of each entry
+  const int64_t sbase = j.slot_off[pr];
+  const int64_t* pos = j.slot_pos + sbase;
+  const int oi = 0, oe = j.want_int ? (withC ? 4 : 2) : 0;
 #pragma unroll
   for (int t = 0; t < BC_SLOTS_PER_LANE; ++t) {
     const int s = lane + 64 * t;
     if (s >= nslot) continue;
-    const int64_t ps = pos[s];
-    if (ps < 0) continue;
-    if (do_int) {
-      atomic_add(&j.out_Si[2 * ps], double(acc[t][0]));
-      atomic_add(&j.out_Si[2 * ps + 1], double(acc[t][1]));
+    if (pos[s] < 0) continue;
+    double* o = j.slot_val + (sbase + s) * j.nv;
+    if (j.want_int) {
+      o[oi] = do_int ? double(acc[t][0]) : 0.0;
+      o[oi + 1] = do_int ? double(acc[t][1]) : 0.0;
       if (withC) {
-        atomic_add(&j.out_Ci[2 * ps], double(acc[t][2]));
-        atomic_add(&j.out_Ci[2 * ps + 1], double(acc[t][3]));
+        o[oi + 2] = do_int ? double(acc[t][2]) : 0.0;
+        o[oi + 3] = do_int ? double(acc[t][3]) : 0.0;
       }
     }
     if (do_ext) {
-      atomic_add(&j.out_Se[2 * ps], double(acc[t][4]));
-      atomic_add(&j.out_Se[2 * ps + 1], double(acc[t][5]));
+      o[oe] = double(acc[t][4]);
+      o[oe + 1] = double(acc[t][5]);
       if (withC) {
-        atomic_add(&j.out_Ce[2 * ps], double(acc[t][6]));
-        atomic_add(&j.out_Ce[2 * ps + 1], double(acc[t][7]));
+        o[oe + 2] = double(acc[t][6]);
+        o[oe + 3] = double(acc[t][7]);
       }
     }
   }
+}
+
+// one thread per kept entry: the sum of its four slots, in the order 2a + b
+__global__ void k_bc_gather(BCJob j) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= j.nnz) return;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    const int64_t sl = j.entry_slots[4 * p + q];
+    if (sl < 0 || sl >= j.nslots) continue;  // every kept entry has its four slots; guard only
+    const double* o = j.slot_val + sl * j.nv;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < j.nv) v[c] += o[c];
+  }
+  int c = 0;
+  if (j.want_int) {
+    j.out_Si[2 * p] = v[c];
+    j.out_Si[2 * p + 1] = v[c + 1];
+    c += 2;
+    if (j.want_C) {
+      j.out_Ci[2 * p] = v[c];
+      j.out_Ci[2 * p + 1] = v[c + 1];
+      c += 2;
+    }
+  }
+  if (j.want_ext) {
+    j.out_Se[2 * p] = v[c];
+    j.out_Se[2 * p + 1] = v[c + 1];
+    c += 2;
+    if (j.want_C) {
+      j.out_Ce[2 * p] = v[c];
+      j.out_Ce[2 * p + 1] = v[c + 1];
+    }
+  }
+}
+
+void launch_bc_gather(const BCJob& j, hipStream_t st) {
+  if (j.nnz > 0) hipLaunchKernelGGL(k_bc_gather, dim3(unsigned((j.nnz + 255) / 256)), dim3(256), 0, st, j);
 }
 
 void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, const BCJob& j, hipStream_t st) {

@@ -321,7 +321,12 @@ __global__ __launch_bounds__(256) void k_cell_pairs(CellPairJob J) {
       else
         b = m;
     }
-    J.slot_pos[sbase + s] = (a < J.rowptr[i + 1] && J.col[a] == j) ? a : -1;
+    const bool kept = a < J.rowptr[i + 1] && J.col[a] == j;
+    J.slot_pos[sbase + s] = kept ? a : -1;
+    if (kept) {  // which ends of i and j the cells v and w are
+      const int ai = J.ecell[2 * int64_t(i)] == cv ? 0 : 1, bj = J.ecell[2 * int64_t(j)] == cw ? 0 : 1;
+      J.entry_slots[4 * a + 2 * ai + bj] = sbase + s;
+    }
   }
 }
 

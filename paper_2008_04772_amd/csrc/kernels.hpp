@@ -154,6 +154,13 @@ struct BCJob {
   double* out_Ci;
   double* out_Se;
   double* out_Ce;
+  // per slot of every cell pair: the values of the kept entries (nv doubles:
+  // re, im of each operator the preconditioner needs, in the order Si, Ci,
+  // Se, Ce), which a gather adds per entry over its four slots in a fixed order
+  double* slot_val;
+  int nv;
+  const int64_t* entry_slots;
+  int64_t nnz, nslots;
 };
 
 // Mass / Gram / right-hand-side / far-field parameter blocks.
@@ -232,6 +239,8 @@ void launch_rows_combine(M* A, int64_t lda, const M* H, int64_t ldh, const int32
 template <typename M>
 void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st);
 
+// sum of the four slot values of every kept entry, in the order 2a + b
+void launch_bc_gather(const BCJob& j, hipStream_t st);
 void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, const BCJob& j, hipStream_t st);
 void launch_mass(const AsmParams<double>& geo, const CellParams& c, const MassJob& j, hipStream_t st);
 void launch_gram(const AsmParams<double>& geo, const MassJob& j, hipStream_t st);
@@ -490,6 +499,7 @@ struct CellPairJob {
   int32_t* cpairs;          // 2 per pair
   int64_t* slot_off;        // per pair
   int64_t* slot_pos;        // N_v x N_w CSR positions per pair, -1 = cut off
+  int64_t* entry_slots;     // 4 per kept entry (i, j): the slot of the cell pair (cell(i, a), cell(j, b)) at 2a + b
 };
 struct SingListJob {
   int F;
