@@ -287,6 +287,10 @@ struct pmchwt_ctx {
     // FP64 local blocks of the singular pairs (the matrix-free FP64 product
     // and the symmetric-tile correction read them)
     DBuf blk;
+    // every entry the singular pairs touch and its local-block entries, for
+    // the fixed-order scatter into the operators
+    DBuf e_row, e_col, e_iptr, e_item;
+    int64_t e_nnz = 0;
   } sing;
   DBuf free_slots;  // pass-1 output of the matrix-free FP64 product
   bool cells_valid = false;
@@ -779,23 +783,21 @@ int pow2_ceil(int64_t n) {
   return p;
 }
 
-// Index tables of the symmetric-tile form (one scatterer, geometry only):
-// the upper tiles in row-major order (host) and the correction pattern, i.e.
-// every entry (r, c) below the diagonal tiles that a pair of triangles
-// sharing a vertex (the Sauter-Schwab pairs) contributes to, with the
-// singular local-block entries that make it: + for those added to X_rc, -
-// for those added to X_cr (classification kernels, from the device pair list).
-void sym_tables(pmchwt_ctx* c) {
+// Records (row, column, singular local-block entry) grouped per entry:
+// crow / col of each entry in row-major order, iptr its first record (with
+// iptr[nnz] = the record count) and item the records in (column, item)
+// order.  all = 0: the correction entries below the diagonal tiles of the
+// symmetric-tile storage; all = 1: every entry a singular pair touches.
+struct RecTables {
+  DBuf rowptr, crow, col, iptr, item;
+  int64_t nnz = 0;
+};
+
+RecTables rec_tables(pmchwt_ctx* c, bool all) {
   const int n = int(c->E_tot);
-  if (c->sym.n == n) return;
   hipStream_t st = c->stream;
-  const int nt = (n + SYM_T - 1) / SYM_T;
-  std::vector<int32_t> tij;
-  for (int I = 0; I < nt; ++I)
-    for (int J = I; J < nt; ++J) {
-      tij.push_back(I);
-      tij.push_back(J);
-    }
+  if (9 * c->sing.npairs >= (int64_t(1) << 30))
+    throw Fail{PMCHWT_ERR_INVALID_MESH, "too many singular pairs for the 31-bit record items"};
   SymRecJob J{};
   J.npairs = c->sing.npairs;
   J.pairs = c->sing.pairs.as<int32_t>();
@@ -803,8 +805,11 @@ void sym_tables(pmchwt_ctx* c) {
   J.F = c->F_tot;
   J.tile = SYM_T;
   J.n = n;
+  J.all = all ? 1 : 0;
   DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), stats = dalloc_c<int32_t>(c, 4);
-  DBuf recptr = dalloc_c<int64_t>(c, size_t(n) + 1), rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  DBuf recptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  RecTables o;
+  o.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
   launch_cls_fill_i32(cnt.as<int32_t>(), n, 0, st);
   launch_cls_fill_i32(stats.as<int32_t>(), 4, 0, st);
   J.cnt = cnt.as<int32_t>();
@@ -815,7 +820,7 @@ void sym_tables(pmchwt_ctx* c) {
   int64_t nrec = 0;
   int32_t maxrec = 0;
   read_scalars(c, {{&nrec, {recptr.as<int64_t>() + n, 8}}, {&maxrec, {stats.as<int32_t>(), 4}}});
-  if (maxrec > 4096) throw Fail{PMCHWT_ERR_INVALID_MESH, "vertex valence too high for the symmetric-tile tables"};
+  if (maxrec > 4096) throw Fail{PMCHWT_ERR_INVALID_MESH, "vertex valence too high for the singular-entry tables"};
   DBuf rec = dalloc_c<int64_t>(c, size_t(std::max<int64_t>(nrec, 1)));
   launch_cls_fill_i32(cnt.as<int32_t>(), n, 0, st);
   J.recptr = recptr.as<int64_t>();
@@ -823,29 +828,53 @@ void sym_tables(pmchwt_ctx* c) {
   J.rec = rec.as<int64_t>();
   launch_sym_records(J, 1, st);
   launch_sym_sort(J, pow2_ceil(std::max(maxrec, 1)), st);
-  launch_scan_i32(cnt.as<int32_t>(), n, rowptr.as<int64_t>(), st);
+  launch_scan_i32(cnt.as<int32_t>(), n, o.rowptr.as<int64_t>(), st);
   HIPCHK(hipGetLastError());
-  int64_t nnz = 0;
-  read_scalars(c, {{&nnz, {rowptr.as<int64_t>() + n, 8}}});
-  c->sym.crow = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
-  c->sym.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
-  c->sym.iptr = dalloc_c<int64_t>(c, size_t(nnz) + 1);
-  c->sym.item = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nrec, 1)));
-  J.rowptr = rowptr.as<int64_t>();
-  J.crow = c->sym.crow.as<int32_t>();
-  J.col = c->sym.col.as<int32_t>();
-  J.iptr = c->sym.iptr.as<int64_t>();
-  J.item = c->sym.item.as<int32_t>();
+  read_scalars(c, {{&o.nnz, {o.rowptr.as<int64_t>() + n, 8}}});
+  o.crow = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+  o.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(o.nnz, 1)));
+  o.iptr = dalloc_c<int64_t>(c, size_t(o.nnz) + 1);
+  o.item = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nrec, 1)));
+  J.rowptr = o.rowptr.as<int64_t>();
+  J.crow = o.crow.as<int32_t>();
+  J.col = o.col.as<int32_t>();
+  J.iptr = o.iptr.as<int64_t>();
+  J.item = o.item.as<int32_t>();
   launch_sym_emit(J, st);
-  launch_cls_set_i64(c->sym.iptr.as<int64_t>() + nnz, nrec, st);
+  launch_cls_set_i64(o.iptr.as<int64_t>() + o.nnz, nrec, st);
   HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));  // the scratch tables above go out of scope
+  return o;
+}
+
+// Index tables of the symmetric-tile form (one scatterer, geometry only):
+// the upper tiles in row-major order (host) and the correction pattern, i.e.
+// every entry (r, c) below the diagonal tiles that a pair of triangles
+// sharing a vertex (the Sauter-Schwab pairs) contributes to, with the
+// singular local-block entries that make it: + for those added to X_rc, -
+// for those added to X_cr (classification kernels, from the device pair list).
+void sym_tables(pmchwt_ctx* c) {
+  const int n = int(c->E_tot);
+  if (c->sym.n == n) return;
+  const int nt = (n + SYM_T - 1) / SYM_T;
+  std::vector<int32_t> tij;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) {
+      tij.push_back(I);
+      tij.push_back(J);
+    }
+  RecTables r = rec_tables(c, false);
+  c->sym.crow = std::move(r.crow);
+  c->sym.col = std::move(r.col);
+  c->sym.iptr = std::move(r.iptr);
+  c->sym.item = std::move(r.item);
+  c->sym.rowptr = std::move(r.rowptr);
   c->sym.nt = nt;
   c->sym.ntiles = int64_t(tij.size() / 2);
-  c->sym.nnz = nnz;
+  c->sym.nnz = r.nnz;
   c->sym.tij = upload(c, tij);
-  c->sym.rowptr = std::move(rowptr);
   c->sym.n = n;
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipStreamSynchronize(c->stream));
 }
 
 // Singular pairs (ordered triangle pairs sharing at least one vertex; the
@@ -943,6 +972,14 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
     build_ss(c, o.n_singular, ss);
     const int npts_by_shared[4] = {0, ss.npts[1], ss.npts[2], ss.npts[3]};
     singular_list(c, npts_by_shared);
+    {
+      RecTables r = rec_tables(c, true);
+      c->sing.e_row = std::move(r.crow);
+      c->sing.e_col = std::move(r.col);
+      c->sing.e_iptr = std::move(r.iptr);
+      c->sing.e_item = std::move(r.item);
+      c->sing.e_nnz = r.nnz;
+    }
     std::vector<int32_t> eslot(2 * size_t(c->E_tot), 0);
     for (auto& sc : c->sc)
       for (int f = 0; f < sc.topo.F; ++f)
@@ -1172,6 +1209,11 @@ void assemble_A_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o) {
   // the FP64 singular blocks, kept for the matrix-free FP64 product
   realloc_c<double>(c, c->sing.blk, size_t(std::max<int64_t>(c->sing.npairs, 1)) * 72);
   sp_.blk = c->sing.blk.as<double>();
+  sp_.e_row = c->sing.e_row.as<int32_t>();
+  sp_.e_col = c->sing.e_col.as<int32_t>();
+  sp_.e_iptr = c->sing.e_iptr.as<int64_t>();
+  sp_.e_item = c->sing.e_item.as<int32_t>();
+  sp_.e_nnz = c->sing.e_nnz;
   {
     EvTimer t(c->stream);
     launch_singular<M>(p, sp_, c->stream);
@@ -2054,11 +2096,13 @@ void assemble_mass_impl(pmchwt_ctx* c, CellDev& cells) {
   const int64_t nnzM = c->mp.h_rowptr.back(), nnzT = c->mp.h_trowptr.back();
   DBuf mval = dalloc_c<double>(c, size_t(std::max<int64_t>(nnzM, 1))),
        tval = dalloc_c<double>(c, size_t(std::max<int64_t>(nnzT, 1)));
-  launch_zero(mval.as<double>(), std::max<int64_t>(nnzM, 1), c->stream);
-  launch_zero(tval.as<double>(), std::max<int64_t>(nnzT, 1), c->stream);
   launch_zero(c->g_val.as<double>(), int64_t(c->g_val.bytes / 8), c->stream);
-  MassJob mj{};
+  MassJob mj{};  // every entry of M_A and M_A^T is written once
   mj.nchild = cells.nchild;
+  mj.E = c->E_tot;
+  mj.nnz_m = nnzM;
+  mj.nnz_t = nnzT;
+  mj.edge_slots = c->sing.edge_slots.as<int32_t>();
   mj.child_cell = cells.child_cell.as<int32_t>();
   mj.child_pos = cells.child_pos.as<int32_t>();
   mj.child_parent = cells.child_parent.as<int32_t>();

@@ -6,7 +6,8 @@
 // Sauter-Schwab rules.  Each pair accumulates the kernel moments of
 // common.hpp once per wavenumber and contracts them against the three RWG
 // functions of each triangle; the 3x3 local blocks are scattered into the
-// dense matrices with hardware atomics.
+// dense matrices, each entry by one thread (regular pairs: the row
+// combine; singular pairs: a scatter over their entry tables).
 //
 // Layout in HBM: one dense row-major matrix per operator, complex
 // interleaved (re, im), element type double (FP64) or float (mixed).  The
@@ -44,13 +45,6 @@ __device__ __forceinline__ int classify_pair(double c1x, double c1y, double c1z,
   if (dist2 < 4.0 * m2) return 0;
   if (dist2 < 16.0 * m2) return 1;
   return 2;
-}
-
-template <typename M>
-__device__ __forceinline__ void add_entry(M* mat, int64_t ld, int i, int j, const cplx<double>& v) {
-  M* p = mat + 2 * (int64_t(i) * ld + j);
-  atomic_add(p, M(v.re));
-  atomic_add(p + 1, M(v.im));
 }
 
 // ---------------------------------------------------------------------------
@@ -375,28 +369,48 @@ __global__ __launch_bounds__(256) void k_singular(AsmParams<M> p, SingParams s) 
       w1[d] = al1 * pick3(u1, a);
       w2[d] = al2 * pick3(u2, b);
     }
-    const int i = p.t2e[a * F + t1], j = p.t2e[b * F + t2];
-    cplx<double> S, C;
-    contract<double, double>(me, al1, w1, al2, w2, ke_r, 0.0, true, S, C);
-    add_entry(p.Se, p.ld_ext, i, j, S);
-    add_entry(p.Ce, p.ld_ext, i, j, C);
-    contract<double, double>(mi, al1, w1, al2, w2, ki_r, ki_i, true, S, C);
-    const int o = p.edge_off[sc];
-    add_entry(p.Si[sc], p.ld_int[sc], i - o, j - o, S);
-    add_entry(p.Ci[sc], p.ld_int[sc], i - o, j - o, C);
-    if (s.blk) {
-      double* q = s.blk + 8 * (9 * pair + lane);
-      cplx<double> Se, Ce;
-      contract<double, double>(me, al1, w1, al2, w2, ke_r, 0.0, true, Se, Ce);
-      q[0] = Se.re;
-      q[1] = Se.im;
-      q[2] = Ce.re;
-      q[3] = Ce.im;
-      q[4] = S.re;
-      q[5] = S.im;
-      q[6] = C.re;
-      q[7] = C.im;
-    }
+    cplx<double> Se, Ce, Si, Ci;
+    contract<double, double>(me, al1, w1, al2, w2, ke_r, 0.0, true, Se, Ce);
+    contract<double, double>(mi, al1, w1, al2, w2, ki_r, ki_i, true, Si, Ci);
+    double* q = s.blk + 8 * (9 * pair + lane);
+    q[0] = Se.re;
+    q[1] = Se.im;
+    q[2] = Ce.re;
+    q[3] = Ce.im;
+    q[4] = Si.re;
+    q[5] = Si.im;
+    q[6] = Ci.re;
+    q[7] = Ci.im;
+  }
+}
+
+// One thread per matrix entry (r, c) that singular pairs touch: the sum of
+// its local-block entries in the order of the entry tables (pair, then 3a+b),
+// added to S^e, C^e (union indices) and S^i, C^i of the scatterer (local
+// indices).  Each entry has one writer, so the result does not depend on the
+// order in which the pairs were integrated.
+template <typename M>
+__global__ void k_sing_scatter(AsmParams<M> p, SingParams s) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= s.e_nnz) return;
+  const int r = s.e_row[k], c = s.e_col[k];
+  const int64_t b = s.e_iptr[k], e = s.e_iptr[k + 1];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t t = b; t < e; ++t) {
+    const double* q = s.blk + 8 * int64_t(uint32_t(s.e_item[t]) >> 1);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += q[u];
+  }
+  const int pr = int((uint32_t(s.e_item[b]) >> 1) / 9);
+  const int sc = p.tscat[s.pairs[2 * pr]];
+  const int o = p.edge_off[sc];
+  M* const mats[4] = {p.Se + 2 * (int64_t(r) * p.ld_ext + c), p.Ce + 2 * (int64_t(r) * p.ld_ext + c),
+                      p.Si[sc] + 2 * (int64_t(r - o) * p.ld_int[sc] + (c - o)),
+                      p.Ci[sc] + 2 * (int64_t(r - o) * p.ld_int[sc] + (c - o))};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    mats[m][0] = M(double(mats[m][0]) + v[2 * m]);
+    mats[m][1] = M(double(mats[m][1]) + v[2 * m + 1]);
   }
 }
 
@@ -439,6 +453,8 @@ void launch_singular(const AsmParams<M>& p, const SingParams& s, hipStream_t st)
   const int per_block = 256 / WAVE;
   const int64_t blocks = (s.npairs + per_block - 1) / per_block;
   hipLaunchKernelGGL((k_singular<M>), dim3(unsigned(blocks)), dim3(256), 0, st, p, s);
+  if (s.e_nnz > 0)
+    hipLaunchKernelGGL((k_sing_scatter<M>), dim3(unsigned((s.e_nnz + 255) / 256)), dim3(256), 0, st, p, s);
 }
 
 template void launch_regular_rows<double, double>(const AsmParams<double>&, const HalfJob<double>&, int, int, int,

@@ -349,80 +349,98 @@ void launch_bc_nearfield(const AsmParams<double>& geo, const CellParams& c, cons
 
 // ---------------------------------------------------------------------------
 // Mixed mass matrix (M_A)_ij = int bc_j . (n x rwg_i) (Section 3.2).  One
-// thread per (barycentric child, RWG local basis of its parent); the product
-// of two linear fields is integrated exactly by the degree-2 rule.
+// thread per entry of M_A's structural pattern: the sum over the barycentric
+// children of T+(i), then T-(i) (six each, in their order), of the children
+// lying in a dual cell at an end of edge j, where bc_j is linear and the
+// product of two linear fields is integrated exactly by the degree-2 rule.
+// One writer per entry and a fixed order: the values do not depend on the
+// schedule.  M_A^T takes the same values by a transposed gather.
 // ---------------------------------------------------------------------------
-__global__ void k_mass(AsmParams<double> g, CellParams c, MassJob j) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (tid >= int64_t(j.nchild) * 3) return;
-  const int ch = int(tid / 3), a = int(tid % 3);
-  const int T = j.child_parent[ch];
-  const int F = g.F;
-  double P[3][3];
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) P[k][d] = g.tv[(3 * k + d) * F + T];
-  double u[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
-  double v[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
-  double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
-  const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  for (int d = 0; d < 3; ++d) n[d] /= nn;
-  const double A = g.tarea[T];
-  const double ar = g.tsgn[a * F + T] / (2.0 * A);
-  double wr[3];
-  for (int d = 0; d < 3; ++d) wr[d] = ar * P[a][d];
-  const int i = g.t2e[a * F + T];
-  const int sc = g.tscat[T];
-  const int il = i - j.edge_off[sc];
-  const int cell = j.child_cell[ch], pos = j.child_pos[ch];
-  const int n2 = c.cell_ptr[cell + 1] - c.cell_ptr[cell];
-  const int N = n2 / 2;
-  double X[3][3];
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) X[k][d] = c.child_v[9 * int64_t(ch) + 3 * k + d];
-  const double Ac = c.child_area[ch];
-  // degree-2 rule: interior points (2/3, 1/6, 1/6), weights 1/3
-  double xq[3][3];
-  for (int q = 0; q < 3; ++q)
-    for (int d = 0; d < 3; ++d) {
-      double l0 = (q == 0) ? 2.0 / 3.0 : 1.0 / 6.0, l1 = (q == 1) ? 2.0 / 3.0 : 1.0 / 6.0,
-             l2 = (q == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
-      xq[q][d] = l0 * X[0][d] + l1 * X[1][d] + l2 * X[2][d];
-    }
-  const int64_t mb = j.m_rowptr[i], me = j.m_rowptr[i + 1];
-  for (int s = 0; s < N; ++s) {
-    const double* cf = c.coef + 4 * (c.coef_ptr[cell] + int64_t(s) * n2 + pos);
-    const int jg = j.inc_edges[j.inc_ptr[cell] + s];
-    const int jj = jg - j.edge_off[sc];
-    double acc = 0.0;
-    for (int q = 0; q < 3; ++q) {
-      double b[3], r[3];
-      for (int d = 0; d < 3; ++d) {
-        b[d] = cf[0] * xq[q][d] - cf[1 + d];
-        r[d] = ar * xq[q][d] - wr[d];
-      }
-      double nr[3] = {n[1] * r[2] - n[2] * r[1], n[2] * r[0] - n[0] * r[2], n[0] * r[1] - n[1] * r[0]};
-      acc += (b[0] * nr[0] + b[1] * nr[1] + b[2] * nr[2]) / 3.0;
-    }
-    // CSR positions of (i, jj) in M_A and (jg, il) in M_A^T (ascending rows)
-    int64_t a0 = mb, a1 = me;
-    while (a0 < a1) {
-      const int64_t m = (a0 + a1) >> 1;
-      if (j.m_col[m] < jj)
-        a0 = m + 1;
-      else
-        a1 = m;
-    }
-    int64_t b0 = j.t_rowptr[jg], b1 = j.t_rowptr[jg + 1];
-    while (b0 < b1) {
-      const int64_t m = (b0 + b1) >> 1;
-      if (j.t_col[m] < il)
-        b0 = m + 1;
-      else
-        b1 = m;
-    }
-    if (a0 < me && j.m_col[a0] == jj) atomic_add(&j.m_val[a0], acc * Ac);
-    if (b0 < j.t_rowptr[jg + 1] && j.t_col[b0] == il) atomic_add(&j.t_val[b0], acc * Ac);
+__device__ __forceinline__ int64_t row_of(const int64_t* rowptr, int n, int64_t p) {
+  int lo = 0, hi = n;  // the last row r with rowptr[r] <= p
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (rowptr[m] <= p)
+      lo = m;
+    else
+      hi = m;
   }
+  return lo;
+}
+
+__global__ void k_mass(AsmParams<double> g, CellParams c, MassJob j) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= j.nnz_m) return;
+  const int i = int(row_of(j.m_rowptr, j.E, p));
+  const int sc = j.edge_scat[i];
+  const int jg = j.m_col[p] + j.edge_off[sc];
+  const int F = g.F;
+  double sum = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int slot = j.edge_slots[2 * i + side];
+    const int T = slot / 3, a = slot - 3 * (slot / 3);
+    double P[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) P[k][d] = g.tv[(3 * k + d) * F + T];
+    double u[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    double v[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int d = 0; d < 3; ++d) n[d] /= nn;
+    const double A = g.tarea[T];
+    const double ar = g.tsgn[a * F + T] / (2.0 * A);
+    double wr[3];
+    for (int d = 0; d < 3; ++d) wr[d] = ar * P[a][d];
+    for (int k = 0; k < 6; ++k) {
+      const int ch = 6 * T + k;
+      const int cell = j.child_cell[ch];
+      const int i0 = j.inc_ptr[cell], N = j.inc_ptr[cell + 1] - i0;
+      int s = -1;
+      for (int t = 0; t < N; ++t)
+        if (j.inc_edges[i0 + t] == jg) s = t;
+      if (s < 0) continue;  // bc_j vanishes on this child
+      const int n2 = c.cell_ptr[cell + 1] - c.cell_ptr[cell];
+      const double* cf = c.coef + 4 * (c.coef_ptr[cell] + int64_t(s) * n2 + j.child_pos[ch]);
+      double X[3][3];
+      for (int q = 0; q < 3; ++q)
+        for (int d = 0; d < 3; ++d) X[q][d] = c.child_v[9 * int64_t(ch) + 3 * q + d];
+      double acc = 0.0;
+      for (int q = 0; q < 3; ++q) {  // interior points (2/3, 1/6, 1/6), weights 1/3
+        double b[3], r[3];
+        for (int d = 0; d < 3; ++d) {
+          const double l0 = (q == 0) ? 2.0 / 3.0 : 1.0 / 6.0, l1 = (q == 1) ? 2.0 / 3.0 : 1.0 / 6.0,
+                       l2 = (q == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
+          const double xq = l0 * X[0][d] + l1 * X[1][d] + l2 * X[2][d];
+          b[d] = cf[0] * xq - cf[1 + d];
+          r[d] = ar * xq - wr[d];
+        }
+        const double nr[3] = {n[1] * r[2] - n[2] * r[1], n[2] * r[0] - n[0] * r[2], n[0] * r[1] - n[1] * r[0]};
+        acc += (b[0] * nr[0] + b[1] * nr[1] + b[2] * nr[2]) / 3.0;
+      }
+      sum += acc * c.child_area[ch];
+    }
+  }
+  j.m_val[p] = sum;
+}
+
+// (M_A^T)_{j i} = (M_A)_{i j}: one thread per entry, the value read from row
+// i of M_A (ascending columns, binary search)
+__global__ void k_mass_trans(MassJob j) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= j.nnz_t) return;
+  const int jg = int(row_of(j.t_rowptr, j.E, p));
+  const int sc = j.edge_scat[jg], off = j.edge_off[sc];
+  const int i = j.t_col[p] + off, jl = jg - off;
+  int64_t a0 = j.m_rowptr[i], a1 = j.m_rowptr[i + 1];
+  const int64_t me = a1;
+  while (a0 < a1) {
+    const int64_t m = (a0 + a1) >> 1;
+    if (j.m_col[m] < jl)
+      a0 = m + 1;
+    else
+      a1 = m;
+  }
+  j.t_val[p] = (a0 < me && j.m_col[a0] == jl) ? j.m_val[a0] : 0.0;
 }
 
 constexpr int MASS_ROW_CAP = 128;  // candidate columns of one row of M_A or M_A^T
@@ -514,8 +532,8 @@ void launch_rebase_i64(const int64_t* in, int64_t n, int64_t* out, hipStream_t s
 }
 
 void launch_mass(const AsmParams<double>& geo, const CellParams& c, const MassJob& j, hipStream_t st) {
-  const int64_t n = int64_t(j.nchild) * 3;
-  hipLaunchKernelGGL(k_mass, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, geo, c, j);
+  if (j.nnz_m > 0) hipLaunchKernelGGL(k_mass, dim3(unsigned((j.nnz_m + 255) / 256)), dim3(256), 0, st, geo, c, j);
+  if (j.nnz_t > 0) hipLaunchKernelGGL(k_mass_trans, dim3(unsigned((j.nnz_t + 255) / 256)), dim3(256), 0, st, j);
 }
 
 // RWG Gram matrix int rwg_i . rwg_j: one thread per (triangle, a, b).

@@ -394,11 +394,13 @@ __global__ void k_sing_list(SingListJob J) {
 // ---------------------------------------------------------------------------
 
 // Every local block entry e = 9 q + 3 a + b of singular pair q = (f, g) adds
-// to (r, c) = (t2e(f, a), t2e(g, b)).  When r and c fall in different tile
-// rows it is a record of the correction entry below the diagonal tiles:
-// (r, c) with item e << 1 if tile(r) > tile(c), else (c, r) with item
-// (e << 1) | 1 (the entry is read transposed).  PASS 0 counts records per
-// row, PASS 1 places them (row-grouped, unordered within a row).
+// to (r, c) = (t2e(f, a), t2e(g, b)).  With J.all, every such e is a record
+// (r, c) with item e << 1: the entries the singular pairs touch, for their
+// fixed-order sum.  Otherwise, when r and c fall in different tile rows it
+// is a record of the correction entry below the diagonal tiles: (r, c) with
+// item e << 1 if tile(r) > tile(c), else (c, r) with item (e << 1) | 1 (the
+// entry is read transposed).  PASS 0 counts records per row, PASS 1 places
+// them (row-grouped, unordered within a row; k_sym_sort orders them).
 template <int PASS>
 __global__ void k_sym_records(SymRecJob J) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -408,9 +410,10 @@ __global__ void k_sym_records(SymRecJob J) {
   const int f = J.pairs[2 * q], g = J.pairs[2 * q + 1];
   const int r = J.t2e[a * J.F + f], c = J.t2e[b * J.F + g];
   const int tr = r / J.tile, tc = c / J.tile;
-  if (tr == tc) return;
-  const int R = tr > tc ? r : c, C = tr > tc ? c : r;
-  const int32_t item = (int32_t(idx) << 1) | (tr > tc ? 0 : 1);
+  if (!J.all && tr == tc) return;
+  const bool lower = J.all || tr > tc;
+  const int R = lower ? r : c, C = lower ? c : r;
+  const int32_t item = (int32_t(idx) << 1) | (lower ? 0 : 1);
   if (PASS == 0) {
     atomicMax(J.maxrec, atomicAdd(&J.cnt[R], 1) + 1);
   } else {

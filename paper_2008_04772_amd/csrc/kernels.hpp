@@ -69,7 +69,15 @@ struct SingParams {
   const int32_t* pairs;        // 2*npairs (t1, t2), ordered
   const double* tab[4];
   int npts[4];
-  double* blk;                 // optional FP64 local blocks: per pair, 9 (3a+b) x 4 (Se, Ce, Si, Ci) complex
+  double* blk;                 // FP64 local blocks: per pair, 9 (3a+b) x 4 (Se, Ce, Si, Ci) complex
+  // every matrix entry (e_row, e_col) the pairs touch (union indices) and its
+  // local-block entries e_item[e_iptr[k] .. e_iptr[k+1]) (9 pair + 3a + b,
+  // shifted left by one), in (pair, 3a+b) order
+  const int32_t* e_row;
+  const int32_t* e_col;
+  const int64_t* e_iptr;
+  const int32_t* e_item;
+  int64_t e_nnz;
 };
 
 // Matrix-free FP64 product y = A x (use_ext = 1) or y = A^i x (use_ext = 0)
@@ -166,6 +174,9 @@ struct BCJob {
 // Mass / Gram / right-hand-side / far-field parameter blocks.
 struct MassJob {
   int nchild;
+  int E;                       // union edges (rows of M_A and M_A^T)
+  int64_t nnz_m, nnz_t;
+  const int32_t* edge_slots;   // 2 per union edge: 3 T+ + a, 3 T- + a
   const int32_t* child_cell;   // cell of each child
   const int32_t* child_pos;    // ring position
   const int32_t* child_parent; // global primal triangle
@@ -518,6 +529,7 @@ struct SymRecJob {
   const int32_t* pairs;
   const int32_t* t2e;      // 3*F union edge of local basis a, SoA
   int F, tile, n;          // triangles, tile size, rows (edges)
+  int all;                 // every touched entry (no tile filter, no transpose)
   int32_t* cnt;            // records, then entries, per row
   int32_t* maxrec;         // longest record list of a row
   const int64_t* recptr;   // n+1

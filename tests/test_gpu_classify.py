@@ -113,24 +113,20 @@ def test_device_classification_counts(P, name, build, chi_h, precond):
 
 def test_reassembly_reuses_identical_tables(P):
     """A second assembly on the same context (tables cached) and a fresh
-    context (tables rebuilt) give the same operators.  The near-field P is
-    summed per entry in a fixed order, so its values are bitwise equal; the
-    RWG blocks of A equal up to the order of the singular kernel's atomic
-    additions (entries that cancel to about 1e-18 may come out as exact
-    zeros in one order and not in another)."""
+    context (tables rebuilt) give bitwise-equal operators: every entry of A
+    and of the near-field P is summed by one thread in a fixed order."""
     meshes = [synth.icosphere(2)]
     chi = 2.0 * synth.mean_edge_length(*meshes[0])
     a = make_ctx(P, meshes, EPS, 2.0, qP=(1, 1, 1), nP=1, chi=chi, precond="S_INT")
     b = make_ctx(P, meshes, EPS, 2.0, qP=(1, 1, 1), nP=1, chi=chi, precond="S_INT")
     b.assemble(P.assembly_opts((4, 3, 2), 4, -1.0, 0), P.assembly_opts((1, 1, 1), 1, chi, 0), "S_INT")
     assert a.profile()["nnz_P"] == b.profile()["nnz_P"]
-    x = a.get_block(P.OP_S, P.INT, P.BC, 0, 0)
-    y = b.get_block(P.OP_S, P.INT, P.BC, 0, 0)
-    assert np.array_equal(x, y)
-    for op, sp, med in ((P.OP_S, P.RWG, P.EXT), (P.OP_C, P.RWG, P.EXT), (P.OP_S, P.RWG, P.INT),
-                        (P.OP_C, P.RWG, P.INT)):
+    # S^i on BC: the one operator of this preconditioner; both RWG operators
+    for op, sp, med in ((P.OP_S, P.BC, P.INT), (P.OP_S, P.RWG, P.EXT), (P.OP_C, P.RWG, P.EXT),
+                        (P.OP_S, P.RWG, P.INT), (P.OP_C, P.RWG, P.INT)):
         x = a.get_block(op, med, sp, 0, 0)
         y = b.get_block(op, med, sp, 0, 0)
-        assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(y)), (op, med, sp)
+        assert np.array_equal(x, y), (op, med, sp)
+    assert np.array_equal(a.get_mass(0), b.get_mass(0))
     a.close()
     b.close()
