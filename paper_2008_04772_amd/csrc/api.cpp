@@ -2296,6 +2296,21 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
     return;
   }
   ensure_lower(c, 15);  // every product below reads whole rows
+  if (!f64 && nrhs >= MFMA_MIN_RHS && c->sc.size() == 1 && c->comb_ok) {
+    // the three combined operators on the matrix cores
+    if (!c->comb) build_comb<float>(c);
+    float* BD = mfma_ws(c, nrhs);
+    float* BN = BD + size_t(2) * nrhs * 2 * size_t(c->ldE);
+    LazyTimer tm(c), t(c, timed);
+    launch_mfma_comb(c->AC.as<float>(), c->AS1.as<float>(), c->AS2.as<float>(), c->ldE, int(E), int(E), x, x + 2 * E,
+                     y, y + 2 * E, nrhs, vs, BD, BN, c->stream);
+    HIPCHK(hipGetLastError());
+    tm.stop(&c->prof.ms_mfma_total);
+    t.stop(&c->prof.ms_matvec_total);
+    c->prof.mfma_launches += 2;
+    c->prof.mfma_flops += 32 * E * c->ldE * nrhs;
+    return;
+  }
   if (c->sym.ready && !c->comb && !(!f64 && nrhs >= MFMA_MIN_RHS)) {
     if (f64)
       build_comb<double>(c);

@@ -334,6 +334,13 @@ void launch_sym_reduce(const double* part, int nt, int n, const int64_t* rowptr,
 void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, int cols, double kr, double ki,
                         const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
                         float* B1, float* B2, hipStream_t st);
+// One scatterer's combined operators C = C^e + C^i, S1 = S^e/k_e + S^i/k_i,
+// S2 = -(k_e S^e + k_i S^i) (FP32, ld a multiple of 16) on the matrix cores:
+// yD = C xD + S1 xN, yN = C xN + S2 xD (overwritten); BD, BN are workspaces
+// of 2 nrhs x 2 ld floats each.
+void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
+                      const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
+                      float* BN, hipStream_t st);
 // y = alpha M x for a real FP32 matrix (ld a multiple of 32, zero padding
 // columns) on both trace components, on the matrix cores; B is a workspace
 // of 4 nrhs x ld floats.

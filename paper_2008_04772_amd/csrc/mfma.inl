@@ -60,7 +60,38 @@ __global__ void k_mfma_rhs(const double* __restrict__ xD, const double* __restri
   B2[r1 + 1] = float(b2r);
 }
 
+// Bhat^T of a plain complex block X (nrhs columns, vectors vstride apart):
+// real row 2c / 2c+1 for column c, real column 2k / 2k+1 for complex row k
+// (zero for k >= E), the 2 x 2 real block of every complex entry.
+template <typename T>
+__global__ void k_mfma_rhs_plain(const double* __restrict__ x, int64_t vstride, int E, int Kt, T* __restrict__ B) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // complex row
+  const int c = blockIdx.y;                             // complex column
+  if (2 * k >= Kt) return;
+  double br = 0, bi = 0;
+  if (k < E) {
+    br = x[2 * (int64_t(c) * vstride + k)];
+    bi = x[2 * (int64_t(c) * vstride + k) + 1];
+  }
+  const int64_t r0 = int64_t(2 * c) * Kt + 2 * k, r1 = r0 + Kt;
+  B[r0] = T(br);
+  B[r0 + 1] = T(-bi);
+  B[r1] = T(bi);
+  B[r1 + 1] = T(br);
+}
+
 // Output mappings of the real GEMM columns.
+// Complex block: real column n -> complex column n/2, part n%2 (overwrites y).
+template <typename R>
+struct CplxOut {
+  static constexpr bool kInit = false, kNegA = false;
+  __device__ __forceinline__ R init(int, int) const { return R(0); }
+  double* y;
+  int64_t vstride;
+  __device__ __forceinline__ void put(int r, int n, R v) const {
+    y[2 * (int64_t(n >> 1) * vstride + r) + (n & 1)] = double(v);
+  }
+};
 // PMCHWT product: real column n -> complex column c = n/2, part n%2;
 // c < nrhs -> yD of rhs c, else yN of rhs c - nrhs; added to y.
 struct PmchwtOut {
@@ -257,6 +288,25 @@ void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, in
   const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
   hipLaunchKernelGGL((k_mfma_gemm<PmchwtOut>), grid, dim3(256), 0, st, C, B1, Kt, 2 * ld, S, B2, Kt, 2 * ld, rows, Nr,
                      PmchwtOut{yD, yN, vstride, nrhs});
+}
+
+// One scatterer, the three combined operators C, S1, S2 (FP32, ld a multiple
+// of 16): yD = C xD + S1 xN and yN = C xN + S2 xD, two GEMM launches of two
+// K segments each (four complex products per right-hand side instead of the
+// eight of the per-medium form).  BD, BN: workspaces of 2 nrhs x 2 ld floats.
+void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
+                      const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
+                      float* BN, hipStream_t st) {
+  const int Kt = int(2 * ld);
+  const int Nr = 2 * nrhs;
+  const dim3 gb(unsigned((Kt / 2 + 255) / 256), unsigned(nrhs));
+  hipLaunchKernelGGL(k_mfma_rhs_plain<float>, gb, dim3(256), 0, st, xD, vstride, cols, Kt, BD);
+  hipLaunchKernelGGL(k_mfma_rhs_plain<float>, gb, dim3(256), 0, st, xN, vstride, cols, Kt, BN);
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
+  hipLaunchKernelGGL((k_mfma_gemm<CplxOut<float>>), grid, dim3(256), 0, st, C, BD, Kt, 2 * ld, S1, BN, Kt, 2 * ld,
+                     rows, Nr, CplxOut<float>{yD, vstride});
+  hipLaunchKernelGGL((k_mfma_gemm<CplxOut<float>>), grid, dim3(256), 0, st, C, BN, Kt, 2 * ld, S2, BD, Kt, 2 * ld,
+                     rows, Nr, CplxOut<float>{yN, vstride});
 }
 
 }  // namespace pmchwt
