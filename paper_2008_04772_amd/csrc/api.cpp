@@ -2259,6 +2259,18 @@ float* mfma_ws(pmchwt_ctx* c, int nrhs) {
   return c->mfma_ws.as<float>();
 }
 
+// FP64 workspace of the matrix-core products: 16 nrhs x ld doubles (the two
+// expanded right-hand blocks of a per-medium product)
+double* mfma_ws64(pmchwt_ctx* c, int nrhs) {
+  const size_t need = size_t(16) * nrhs * size_t(c->ldE) * sizeof(double);
+  if (c->mfma_ws_bytes < need) {
+    c->mfma_ws = DBuf();
+    c->mfma_ws = dalloc<float>(need / sizeof(float));
+    c->mfma_ws_bytes = need;
+  }
+  return reinterpret_cast<double*>(c->mfma_ws.p);
+}
+
 // y = A x (y overwritten)
 void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -2296,6 +2308,21 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
     return;
   }
   ensure_lower(c, 15);  // every product below reads whole rows
+  if (f64 && nrhs >= MFMA_MIN_RHS && c->sc.size() == 1 && c->comb_ok) {
+    // the three combined operators on the FP64 matrix cores
+    if (!c->comb) build_comb<double>(c);
+    double* BD = mfma_ws64(c, nrhs);
+    double* BN = BD + size_t(2) * nrhs * 2 * size_t(c->ldE);
+    LazyTimer tm(c), t(c, timed);
+    launch_mfma64_comb(c->AC.as<double>(), c->AS1.as<double>(), c->AS2.as<double>(), c->ldE, int(E), int(E), x,
+                       x + 2 * E, y, y + 2 * E, nrhs, vs, BD, BN, c->stream);
+    HIPCHK(hipGetLastError());
+    tm.stop(&c->prof.ms_mfma_total);
+    t.stop(&c->prof.ms_matvec_total);
+    c->prof.mfma_launches += 1;
+    c->prof.mfma_flops += 32 * E * c->ldE * nrhs;
+    return;
+  }
   if (!f64 && nrhs >= MFMA_MIN_RHS && c->sc.size() == 1 && c->comb_ok) {
     // the three combined operators on the matrix cores
     if (!c->comb) build_comb<float>(c);
@@ -2334,7 +2361,28 @@ void apply_A(pmchwt_ctx* c, const double* x, double* y, int nrhs) {
   }
   launch_zero(y, 2 * vs * nrhs, c->stream);
   LazyTimer t(c, timed);
-  if (c->precA == PMCHWT_FP64) {
+  if (f64 && nrhs >= MFMA_MIN_RHS) {
+    double* B1 = mfma_ws64(c, nrhs);
+    double* B2 = B1 + size_t(4) * nrhs * 2 * size_t(c->ldE);
+    LazyTimer tm(c);
+    launch_mfma64_pmchwt(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x, x + 2 * E,
+                         y, y + 2 * E, nrhs, vs, B1, B2, c->stream);
+    int64_t flops = 32 * E * c->ldE * nrhs;
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_mfma64_pmchwt(c->Si[m].as<double>(), c->Ci[m].as<double>(), c->ldI[m], s.topo.E, s.topo.E, s.k.real(),
+                           s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs, B1, B2,
+                           c->stream);
+      flops += 32 * int64_t(s.topo.E) * c->ldI[m] * nrhs;
+    }
+    HIPCHK(hipGetLastError());
+    tm.stop(&c->prof.ms_mfma_total);
+    c->prof.mfma_launches += 1 + int64_t(c->sc.size());
+    c->prof.mfma_flops += flops;
+    t.stop(&c->prof.ms_matvec_total);
+    return;
+  } else if (c->precA == PMCHWT_FP64) {
     launch_gemv_pmchwt<double>(c->Se.as<double>(), c->Ce.as<double>(), c->ldE, int(E), int(E), c->k_ext, 0.0, x,
                                x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
     for (size_t m = 0; m < c->sc.size(); ++m) {
@@ -2518,6 +2566,22 @@ void ensure_a64(pmchwt_ctx* c) {
 void apply_A64_split(pmchwt_ctx* c, const double* x, const double* u, double* y, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
   launch_zero(y, 2 * vs * nrhs, c->stream);
+  if (nrhs >= MFMA_MIN_RHS) {  // on the FP64 matrix cores
+    double* B1 = mfma_ws64(c, nrhs);
+    double* B2 = B1 + size_t(4) * nrhs * 2 * size_t(c->a64.ldE);
+    launch_mfma64_pmchwt(c->a64.Se.as<double>(), c->a64.Ce.as<double>(), c->a64.ldE, int(E), int(E), c->k_ext, 0.0,
+                         x, x + 2 * E, y, y + 2 * E, nrhs, vs, B1, B2, c->stream);
+    for (size_t m = 0; m < c->sc.size(); ++m) {
+      const Scat& s = c->sc[m];
+      const int64_t o = s.edge_off;
+      launch_mfma64_pmchwt(c->a64.Si[m].as<double>(), c->a64.Ci[m].as<double>(), c->a64.ldI[m], s.topo.E, s.topo.E,
+                           s.k.real(), s.k.imag(), u + 2 * o, u + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs,
+                           B1, B2, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    c->calls_A += 1;
+    return;
+  }
   launch_gemv_pmchwt<double>(c->a64.Se.as<double>(), c->a64.Ce.as<double>(), c->a64.ldE, int(E), int(E), c->k_ext,
                              0.0, x, x + 2 * E, y, y + 2 * E, nrhs, vs, c->stream);
   for (size_t m = 0; m < c->sc.size(); ++m) {
@@ -3610,6 +3674,27 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
   });
 }
 
+// Far field of nrhs current vectors (device, internal layout) at nobs
+// directions into F_out (6 doubles per direction and rhs): the FP64 matrix
+// cores for many right-hand sides, else the VALU sum.
+constexpr int FAR_MFMA_MIN_RHS = 8;
+void far_field_dev(pmchwt_ctx* c, const double* x, int nrhs, const double* obs, int nobs, double* F_out) {
+  const AsmParams<double> g = asm_params<double>(c);
+  if (nrhs >= FAR_MFMA_MIN_RHS) {
+    const FarMfmaPlan fp = far_mfma_plan(c->F_tot, nrhs, nobs);
+    DBuf wy = dalloc_c<double>(c, 4 * size_t(fp.npts)), wj = dalloc_c<double>(c, 12 * size_t(fp.npts) * nrhs),
+         wb = dalloc_c<double>(c, size_t(fp.n_B)), wp = dalloc_c<double>(c, size_t(fp.n_part));
+    launch_far_field_mfma(g, x, c->E_tot, nrhs, c->k_ext, obs, nobs, F_out, fp, wy.as<double>(), wj.as<double>(),
+                          wb.as<double>(), wp.as<double>(), c->stream);
+  } else {
+    const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs);
+    DBuf wy = dalloc_c<double>(c, fp.n_ypts), wj = dalloc_c<double>(c, fp.n_J), wp = dalloc_c<double>(c, fp.n_part);
+    launch_far_field(g, x, c->E_tot, nrhs, c->k_ext, obs, nobs, F_out, fp, wy.as<double>(), wj.as<double>(),
+                     wp.as<double>(), c->stream);
+  }
+  HIPCHK(hipGetLastError());
+}
+
 int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* obs, int32_t nobs,
                      pmchwt_complex* F) {
   return guarded(c, [&]() -> int {
@@ -3621,11 +3706,7 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     DBuf dx = upload(c, h);
     std::vector<double> ho(obs, obs + 3 * size_t(nobs));
     DBuf dobs = upload(c, ho), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs);
-    const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs);
-    DBuf wy = dalloc_c<double>(c, fp.n_ypts), wj = dalloc_c<double>(c, fp.n_J), wp = dalloc_c<double>(c, fp.n_part);
-    launch_far_field(asm_params<double>(c), dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs,
-                     dF.as<double>(), fp, wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
-    HIPCHK(hipGetLastError());
+    far_field_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nobs, dF.as<double>());
     std::vector<double> hf(6 * size_t(nobs) * nrhs);
     HIPCHK(hipMemcpyAsync(hf.data(), dF.p, hf.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -3747,17 +3828,11 @@ int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs
     to_internal(c, cur, nrhs, h);
     DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs),
          dsig = dalloc_c<double>(c, nrhs);
-    AsmParams<double> g = asm_params<double>(c);
-    const FarPlan fp = far_field_plan(c->F_tot, nrhs, nobs), fpd = far_field_plan(c->F_tot, nrhs, nrhs);
-    DBuf wy = dalloc_c<double>(c, fp.n_ypts), wj = dalloc_c<double>(c, fp.n_J),
-         wp = dalloc_c<double>(c, std::max(fp.n_part, fpd.n_part));
-    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dobs.as<double>(), nobs, dF.as<double>(), fp,
-                     wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
+    far_field_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nobs, dF.as<double>());
     launch_sigma_sca(dF.as<double>(), nobs, nrhs, dw.as<double>(), dsig.as<double>(), c->stream);
     std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
     DBuf dd = upload(c, hd), dFd = dalloc_c<double>(c, 6 * size_t(nrhs) * nrhs);
-    launch_far_field(g, dx.as<double>(), c->E_tot, nrhs, c->k_ext, dd.as<double>(), nrhs, dFd.as<double>(), fpd,
-                     wy.as<double>(), wj.as<double>(), wp.as<double>(), c->stream);
+    far_field_dev(c, dx.as<double>(), nrhs, dd.as<double>(), nrhs, dFd.as<double>());
     HIPCHK(hipGetLastError());
     std::vector<double> fd(6 * size_t(nrhs) * nrhs);
     HIPCHK(hipMemcpyAsync(ssca, dsig.p, 8 * size_t(nrhs), hipMemcpyDeviceToHost, c->stream));

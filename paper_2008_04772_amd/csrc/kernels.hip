@@ -5,6 +5,7 @@
 #include "bc.inl"
 #include "linalg.inl"
 #include "mfma.inl"
+#include "mfma64.inl"
 #include "refine.inl"
 #include "massinv.inl"
 #include "nearfield.inl"

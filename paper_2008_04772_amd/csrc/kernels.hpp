@@ -341,6 +341,15 @@ void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, in
 void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
                       const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
                       float* BN, hipStream_t st);
+// FP64 matrix-core forms of the two products above (ld a multiple of 8):
+// combined operators (BD, BN: 2 nrhs x 2 ld doubles each) and one medium
+// (B1, B2: 4 nrhs x 2 ld doubles each, result added to y).
+void launch_mfma64_comb(const double* C, const double* S1, const double* S2, int64_t ld, int rows, int cols,
+                        const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
+                        double* BD, double* BN, hipStream_t st);
+void launch_mfma64_pmchwt(const double* S, const double* C, int64_t ld, int rows, int cols, double kr, double ki,
+                          const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride,
+                          double* B1, double* B2, hipStream_t st);
 // y = alpha M x for a real FP32 matrix (ld a multiple of 32, zero padding
 // columns) on both trace components, on the matrix cores; B is a workspace
 // of 4 nrhs x ld floats.
@@ -467,6 +476,18 @@ struct FarPlan {
   int64_t n_ypts = 0, n_J = 0, n_part = 0;
 };
 FarPlan far_field_plan(int F, int nrhs, int nobs);
+// Far field on the FP64 matrix cores (many right-hand sides): rule points as
+// for the VALU sum, the expanded currents B (n_B doubles), K split nsplit
+// ways (partial sums part, n_part doubles).
+struct FarMfmaPlan {
+  int64_t npts = 0;
+  int Kt = 0, Nr = 0, nsplit = 1;
+  int64_t n_B = 0, n_part = 0;
+};
+FarMfmaPlan far_mfma_plan(int F, int nrhs, int nobs);
+void launch_far_field_mfma(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
+                           const double* obs, int nobs, double* F_out, const FarMfmaPlan& plan, double* ypts,
+                           double* J, double* B, double* part, hipStream_t st);
 FarPlan far_field_plan_capped(int F, int nrhs, int nobs, int64_t max_part);
 // Total electric field at points (region per point, rule-point data and the
 // sums; ypts: 4 doubles per rule point, J: near_j_doubles() per rhs and rule
