@@ -150,7 +150,9 @@ typedef struct {
  *              and ir_max > 0 the solve targets the FP64 system: the right-
  *              hand side's interior product and every residual use the
  *              matrix-free FP64 product of pmchwt_apply (which = 2, 3), and
- *              GMRES on the FP32 operators solves the correction equations. */
+ *              GMRES on the FP32 operators solves the correction equations,
+ *              each right-hand side only as far as brings its FP64
+ *              residual to half of tol (and at least by the factor tol). */
 typedef struct {
   double tol;
   int32_t restart;

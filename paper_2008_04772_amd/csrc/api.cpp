@@ -2854,6 +2854,17 @@ struct PinnedBuf {
   }
 };
 
+// Tolerance of a refinement correction solve for one right-hand side whose
+// preconditioned residual is nr against nb for the right-hand side itself:
+// the correction needs to bring the residual to tol nb only (half of it, for
+// the FP32 error of the correction), i.e. reduce nr by 0.5 tol nb / nr, and
+// at least by tol (the plain criterion); 1 when the residual already meets
+// tol (nothing to solve).
+double correction_tol(double tol, double nr, double nb) {
+  if (!(nr > tol * nb)) return 1.0;
+  return std::max(tol, 0.5 * tol * nb / nr);
+}
+
 // One restarted GMRES run as a resumable state machine.  Every step needs one
 // application of Op (input op_in(), output op_out(), done by the caller), then
 // stage1(), stage2(), stage3() in that order.  Between stages the run only
@@ -2877,6 +2888,7 @@ struct GmresRun {
   double* x;
   int nrhs, rho, max_iter;
   double tol;
+  std::vector<double> tolq;  // per right-hand side
   int64_t vs, vecd, vstep;
   int n;
   double *V, *w, *r, *s1, *s2, *s3, *dpar, *dn;
@@ -2919,8 +2931,11 @@ struct GmresRun {
   }
   cd& Hm(int q, int i, int jj) { return H[(size_t(q) * (rho + 1) + i) * rho + jj]; }
 
-  GmresRun(pmchwt_ctx* c_, const double* bt_, double* x_, int nrhs_, double tol_, int rho_, int max_iter_)
+  // tolq (optional): a tolerance per right-hand side (>= 1: nothing to do)
+  GmresRun(pmchwt_ctx* c_, const double* bt_, double* x_, int nrhs_, double tol_, int rho_, int max_iter_,
+           const double* tolq_ = nullptr)
       : c(c_), bt(bt_), x(x_), nrhs(nrhs_), rho(rho_), max_iter(max_iter_), tol(tol_),
+        tolq(tolq_ ? std::vector<double>(tolq_, tolq_ + nrhs_) : std::vector<double>(size_t(nrhs_), tol_)),
         hpin(pinned_bytes(nrhs_, rho_)), hres(2 * 8 * res_doubles(nrhs_, rho_), hipHostMallocCoherent) {
     vs = vlen(c);
     n = int(vs);
@@ -3012,6 +3027,9 @@ struct GmresRun {
       if (bnorm[q] == 0.0) {
         out.converged[q] = 1;
         out.relres[q] = 0.0;
+      } else if (tolq[q] >= 1.0) {
+        out.converged[q] = 1;
+        out.relres[q] = 1.0;
       }
     }
     begin_cycle();
@@ -3093,7 +3111,7 @@ struct GmresRun {
         if (out.converged[q] || jend[q] == 0) continue;
         out.restarts[q] += 1;
         out.relres[q] = beta[q] / bnorm[q];
-        if (beta[q] / bnorm[q] <= tol) out.converged[q] = 1;
+        if (beta[q] / bnorm[q] <= tolq[q]) out.converged[q] = 1;
       }
       begin_cycle();
     }
@@ -3150,7 +3168,7 @@ struct GmresRun {
       jend[q] = jj + 1;
       // converged inside the cycle (a convergence exactly at the cycle end
       // still goes through the cycle-end residual, as Table 1 counts it)
-      if (res <= tol && jj + 1 < rho) {
+      if (res <= tolq[q] && jj + 1 < rho) {
         done_cycle[q] = 1;
         active[q] = 0;
       } else {
@@ -3208,8 +3226,9 @@ struct GmresRun {
   }
 };
 
-GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol, int rho, int max_iter) {
-  GmresRun g(c, bt, x, nrhs, tol, rho, max_iter);
+GmresOut gmres(pmchwt_ctx* c, const double* bt, double* x, int nrhs, double tol, int rho, int max_iter,
+               const double* tolq = nullptr) {
+  GmresRun g(c, bt, x, nrhs, tol, rho, max_iter, tolq);
   g.start();
   while (g.phase != GmresRun::DONE) {
     op_apply(c, g.op_in(), g.op_out(), g.s1, g.s2, g.s3, nrhs);
@@ -3632,15 +3651,17 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
       HIPCHK(hipMemcpyAsync(nb.data(), dn.as<double>() + nrhs, 8 * nrhs, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       bool ok = true;
+      std::vector<double> tq(nrhs);
       for (int q = 0; q < nrhs; ++q) {
         const bool okq = nr[q] <= o->tol * nb[q];
         ok &= okq;
         g.relres[q] = nb[q] > 0 ? nr[q] / nb[q] : 0.0;
         g.converged[q] = okq ? 1 : 0;
+        tq[q] = correction_tol(o->tol, nr[q], nb[q]);
       }
       if (ok || ir == o->ir_max) break;
       HIPCHK(hipMemcpyAsync(r.p, s1.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
-      GmresOut g2 = gmres(c, r.as<double>(), d.as<double>(), nrhs, o->tol, o->restart, o->max_iter);
+      GmresOut g2 = gmres(c, r.as<double>(), d.as<double>(), nrhs, o->tol, o->restart, o->max_iter, tq.data());
       launch_axpby(x.as<double>(), d.as<double>(), vs, int(vs), nrhs, 1.0, 1.0, c->stream);
       int mi = 0;
       for (int q = 0; q < nrhs; ++q) mi = std::max(mi, g2.iters[q]);

@@ -212,18 +212,21 @@ struct ServeRun {
     HIPCHK(hipEventSynchronize(ev));
     const double* h = static_cast<const double*>(hn->p);
     bool ok = true;
+    std::vector<double> tq(nrhs);
     for (int q = 0; q < nrhs; ++q) {
       const bool okq = h[q] <= rec->so.tol * h[nrhs + q];
       ok &= okq;
       conv[q] = okq ? 1 : 0;
       relres[q] = h[nrhs + q] > 0 ? h[q] / h[nrhs + q] : 0.0;
+      tq[q] = correction_tol(rec->so.tol, h[q], h[nrhs + q]);
     }
     if (ok || ir == rec->so.ir_max) {
       st = FINISHED;
       return;
     }
     HIPCHK(hipMemcpyAsync(r.p, s1.p, nd * 8, hipMemcpyDeviceToDevice, c->stream));
-    g.reset(new GmresRun(c, r.as<double>(), d.as<double>(), nrhs, rec->so.tol, rec->so.restart, rec->so.max_iter));
+    g.reset(new GmresRun(c, r.as<double>(), d.as<double>(), nrhs, rec->so.tol, rec->so.restart, rec->so.max_iter,
+                         tq.data()));
     st = IR_SOLVE;
     g->start();
     advance_after_gmres();
