@@ -161,6 +161,13 @@ struct CellDev {
 
 }  // namespace
 
+// A BsrMat with the device buffers it points into.
+struct BsrHold {
+  DBuf bptr, bcol, t1, t2;
+  BsrMat m;
+  bool valid = false;
+};
+
 struct pmchwt_ctx {
   BufPool pool;  // first member: destroyed after every buffer that returns to it
   int device = 0;
@@ -219,6 +226,11 @@ struct pmchwt_ctx {
   // FP32 copies of the values for the products of a MIXED preconditioner
   // (the FP64 ones stay for copy-out)
   DBuf PSi32, PCi32, PSe32, PCe32;
+  // block-sparse copies of the FP32 P (interior per scatterer, exterior)
+  std::vector<BsrHold> bsrPi;
+  BsrHold bsrPe;
+  DBuf bsr_ws;  // expanded right-hand blocks of the block-sparse products
+  size_t bsr_ws_bytes = 0;
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_col;
   // mass / Gram
@@ -228,6 +240,7 @@ struct pmchwt_ctx {
   struct SparseInv {
     DBuf rowptr, col, val;  // val: float for an FP32 inverse, double for FP64
     int64_t nnz = 0;
+    BsrHold bsr;            // block-sparse copy of an FP32 inverse (many right-hand sides)
   };
   std::vector<SparseInv> MinvS, MinvTS;
   // FP64 M_A and M_A^T per scatterer (CSR, scatterer-local indices); when
@@ -1413,6 +1426,8 @@ void assemble_P_impl(pmchwt_ctx* c, const pmchwt_assembly_opts& o, int kind, Cel
   c->PCi32.release();
   c->PSe32.release();
   c->PCe32.release();
+  c->bsrPi.clear();
+  c->bsrPe = BsrHold();
   c->precond = kind;
   c->P_int = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_INT || kind == PMCHWT_P_S_INT);
   c->P_ext = (kind == PMCHWT_P_A || kind == PMCHWT_P_D || kind == PMCHWT_P_D_EXT || kind == PMCHWT_P_S_EXT);
@@ -2606,6 +2621,71 @@ void apply_A_resid(pmchwt_ctx* c, const double* x, const double* u, double* y, i
   }
 }
 
+// Block-sparse copy (BSR_T x BSR_T tiles) of an FP32 CSR matrix with rows
+// [0, rows) and columns [0, cols); v2: a second value set on the pattern.
+void build_bsr(pmchwt_ctx* c, const int64_t* rowptr, const int32_t* col, int rows, int cols, const float* v1,
+               const float* v2, bool cplx, BsrHold& h) {
+  hipStream_t st = c->stream;
+  const int nbr = (rows + BSR_T - 1) / BSR_T, nbc = (cols + BSR_T - 1) / BSR_T;
+  const size_t nb = size_t(nbr) * nbc;
+  DBuf flag = dalloc_c<int32_t>(c, nb);
+  launch_cls_fill_i32(flag.as<int32_t>(), int64_t(nb), 0, st);
+  launch_bsr_mark(rowptr, col, rows, nbc, flag.as<int32_t>(), st);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> hf(nb), bcol;
+  std::vector<int64_t> bptr(size_t(nbr) + 1, 0);
+  HIPCHK(hipMemcpyAsync(hf.data(), flag.p, nb * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int bi = 0; bi < nbr; ++bi) {
+    for (int bj = 0; bj < nbc; ++bj) {
+      int32_t& f = hf[size_t(bi) * nbc + bj];
+      if (f) {
+        f = int32_t(bcol.size());
+        bcol.push_back(bj);
+      } else {
+        f = -1;
+      }
+    }
+    bptr[size_t(bi) + 1] = int64_t(bcol.size());
+  }
+  const int64_t nt = int64_t(bcol.size());
+  const int kw = cplx ? 2 * BSR_T : BSR_T;
+  h.bptr = upload(c, bptr);
+  h.bcol = upload(c, bcol.empty() ? std::vector<int32_t>{0} : bcol);
+  DBuf tmap = upload(c, hf);
+  const size_t tv = size_t(std::max<int64_t>(nt, 1)) * BSR_T * kw;
+  h.t1 = dalloc_c<float>(c, tv);
+  launch_zero_f(h.t1.as<float>(), int64_t(tv), st);
+  launch_bsr_fill(rowptr, col, v1, rows, nbc, tmap.as<int32_t>(), cplx, h.t1.as<float>(), st);
+  if (v2) {
+    h.t2 = dalloc_c<float>(c, tv);
+    launch_zero_f(h.t2.as<float>(), int64_t(tv), st);
+    launch_bsr_fill(rowptr, col, v2, rows, nbc, tmap.as<int32_t>(), cplx, h.t2.as<float>(), st);
+  }
+  HIPCHK(hipGetLastError());
+  h.m.nbr = nbr;
+  h.m.nbc = nbc;
+  h.m.ntiles = nt;
+  h.m.bptr = h.bptr.as<int64_t>();
+  h.m.bcol = h.bcol.as<int32_t>();
+  h.m.tiles1 = h.t1.as<float>();
+  h.m.tiles2 = v2 ? h.t2.as<float>() : nullptr;
+  h.valid = true;
+  HIPCHK(hipStreamSynchronize(st));  // tmap and flag go out of scope
+}
+
+// workspace of the block-sparse products: two blocks of 4 nrhs x 2 nbc BSR_T floats
+float* bsr_ws(pmchwt_ctx* c, int nrhs) {
+  const int64_t kt = 2 * ((c->E_tot + BSR_T - 1) / BSR_T) * BSR_T;
+  const size_t need = size_t(2) * 4 * nrhs * size_t(kt) * sizeof(float);
+  if (c->bsr_ws_bytes < need) {
+    c->bsr_ws = DBuf();
+    c->bsr_ws = dalloc<float>(need / sizeof(float));
+    c->bsr_ws_bytes = need;
+  }
+  return c->bsr_ws.as<float>();
+}
+
 // z = M_P^-1 P M_A^-1 y  (z overwritten; tmp: 2 vectors of scratch)
 void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double* t2, int nrhs) {
   const int64_t E = c->E_tot, vs = vlen(c);
@@ -2614,18 +2694,25 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
     return;
   }
   c->calls_P += 1;
-  const bool mm = c->mass_f32 && nrhs >= MFMA_MIN_RHS;
-  float* Bw = mm ? mfma_ws(c, nrhs) : nullptr;
-  // out = alpha M_A^-1 in (transposed: M_A^-T) for scatterer m: the matrix-core
-  // product on the dense FP32 inverse for many right-hand sides (expanded
-  // from the sparse inverse when first needed), else the sparse inverse,
-  // else the dense FP64 one
+  const bool many = nrhs >= MFMA_MIN_RHS;
+  const bool mm = c->mass_f32 && many;
+  float* Bw = many ? bsr_ws(c, nrhs) : nullptr;
+  // out = alpha M_A^-1 in (transposed: M_A^-T) for scatterer m: for many
+  // right-hand sides the matrix-core product on the block-sparse copy of the
+  // sparse FP32 inverse (else on the dense FP32 inverse), else the sparse
+  // inverse, else the dense FP64 one
   auto mass_inv = [&](size_t m, bool tr, double alpha, const double* in, double* out) {
     const Scat& s = c->sc[m];
     const int64_t o = s.edge_off, ldm = ldmass(s.topo.E);
-    const pmchwt_ctx::SparseInv& S = tr ? c->MinvTS[m] : c->MinvS[m];
+    pmchwt_ctx::SparseInv& S = tr ? c->MinvTS[m] : c->MinvS[m];
     DBuf& Dn = tr ? c->MinvT[m] : c->Minv[m];
-    if (mm) {
+    const bool sp32 = S.rowptr.p && (c->mass_f32 || (m < c->mass_sparse.size() && c->mass_sparse[m]));
+    if (many && sp32 && !S.bsr.valid)
+      build_bsr(c, S.rowptr.as<int64_t>(), S.col.as<int32_t>(), s.topo.E, s.topo.E, S.val.as<float>(), nullptr, false,
+                S.bsr);
+    if (mm && S.bsr.valid) {
+      launch_bsr_real2(S.bsr.m, s.topo.E, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, Bw, c->stream);
+    } else if (mm) {
       if (!Dn.p) {
         Dn = dalloc_c<float>(c, size_t(ldm) * ldm);
         launch_zero_f(Dn.as<float>(), ldm * ldm, c->stream);
@@ -2646,11 +2733,21 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
       const int64_t* rp = S.rowptr.as<int64_t>();
       const int32_t* cl = S.col.as<int32_t>();
       const float* vl = S.val.as<float>();
-      launch_spmv_real2_csr(rp, cl, vl, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
+      // the products with X on the matrix cores for many right-hand sides: the
+      // FP32 rounding of their inputs is corrected like X's own error (the
+      // block-sparse copy stays from an earlier call; Bw exists only here)
+      const bool xb = many && S.bsr.valid;
+      if (xb)
+        launch_bsr_real2(S.bsr.m, s.topo.E, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, Bw, c->stream);
+      else
+        launch_spmv_real2_csr(rp, cl, vl, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
       launch_spmv_real2_csr(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), s.topo.E, -1.0,
                             out + 2 * o, tmp + 2 * o, nrhs, vs, E, c->stream);
       launch_axpby_rows(tmp + 2 * o, in + 2 * o, vs, s.topo.E, E, nrhs, 1.0, alpha, c->stream);
-      launch_spmv_real2_csr(rp, cl, vl, s.topo.E, 1.0, tmp + 2 * o, out + 2 * o, nrhs, vs, E, c->stream, 1.0);
+      if (xb)
+        launch_bsr_real2(S.bsr.m, s.topo.E, s.topo.E, 1.0, tmp + 2 * o, out + 2 * o, nrhs, vs, E, Bw, c->stream, true);
+      else
+        launch_spmv_real2_csr(rp, cl, vl, s.topo.E, 1.0, tmp + 2 * o, out + 2 * o, nrhs, vs, E, c->stream, 1.0);
     } else if (S.rowptr.p) {
       launch_spmv_real2_csr(S.rowptr.as<int64_t>(), S.col.as<int32_t>(), S.val.as<double>(), s.topo.E, alpha,
                             in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
@@ -2666,10 +2763,21 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   const int64_t* rp = c->p_rowptr.as<int64_t>();
   const int32_t* cl = c->p_col.as<int32_t>();
   if (!c->P_int && !c->P_ext) launch_zero(t2, 2 * vs * nrhs, c->stream);
-  // FP32 values when the preconditioner was assembled MIXED
+  // FP32 values when the preconditioner was assembled MIXED: for many
+  // right-hand sides the matrix-core product on their block-sparse copy
+  // (columns over the union, rows of the block)
+  const bool pbsr = many && (c->PSi32.p || c->PSe32.p);
+  if (pbsr) launch_zero(t2, 2 * vs * nrhs, c->stream);
   auto spmv = [&](const int64_t* rpp, const DBuf& S64, const DBuf& C64, const DBuf& S32, const DBuf& C32, int rows,
-                  double kr, double ki, const double* xD, const double* xN, double* yD, double* yN, bool acc) {
-    if (S32.p)
+                  double kr, double ki, const double* xD, const double* xN, double* yD, double* yN, bool acc,
+                  BsrHold* bh) {
+    if (pbsr && S32.p) {
+      if (!bh->valid)
+        build_bsr(c, rpp, cl, rows, int(E), S32.as<float>(), c->P_C ? C32.as<float>() : nullptr, true, *bh);
+      float* B1 = Bw;
+      float* B2 = Bw + size_t(4) * nrhs * 2 * size_t(bh->m.nbc) * BSR_T;
+      launch_bsr_pmchwt(bh->m, rows, int(E), kr, ki, xD, xN, yD, yN, nrhs, vs, B1, B2, c->stream);
+    } else if (S32.p)
       launch_spmv_pmchwt<float>(rpp, cl, S32.as<float>(), c->P_C ? C32.as<float>() : nullptr, rows, kr, ki, xD, xN, yD,
                                 yN, nrhs, vs, c->stream, acc);
     else
@@ -2677,15 +2785,17 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
                                  yD, yN, nrhs, vs, c->stream, acc);
   };
   if (c->P_int) {
+    if (c->bsrPi.size() != c->sc.size()) c->bsrPi.resize(c->sc.size());
     for (size_t m = 0; m < c->sc.size(); ++m) {
       const Scat& s = c->sc[m];
       const int64_t o = s.edge_off;
       spmv(rp + o, c->PSi, c->PCi, c->PSi32, c->PCi32, s.topo.E, s.k.real(), s.k.imag(), t1, t1 + 2 * E, t2 + 2 * o,
-           t2 + 2 * (E + o), false);
+           t2 + 2 * (E + o), false, &c->bsrPi[m]);
     }
   }
   if (c->P_ext)
-    spmv(rp, c->PSe, c->PCe, c->PSe32, c->PCe32, int(E), c->k_ext, 0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, c->P_int);
+    spmv(rp, c->PSe, c->PCe, c->PSe32, c->PCe32, int(E), c->k_ext, 0.0, t1, t1 + 2 * E, t2, t2 + 2 * E, c->P_int,
+         &c->bsrPe);
   for (size_t m = 0; m < c->sc.size(); ++m) mass_inv(m, true, -1.0, t2, z);
   HIPCHK(hipGetLastError());
 }

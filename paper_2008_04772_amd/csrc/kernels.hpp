@@ -341,6 +341,32 @@ void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, in
 void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
                       const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
                       float* BN, hipStream_t st);
+// Block-sparse rows of dense BSR_T x BSR_T FP32 tiles (the sparse operators
+// of the preconditioner, for products with many right-hand sides): row tile
+// bi holds tiles bptr[bi] .. bptr[bi+1] at column tiles bcol[t]; tiles of a
+// real matrix are BSR_T x BSR_T floats, of a complex one BSR_T x 2 BSR_T
+// ((re, im) pairs); tiles2 is a second value set on the same pattern (the C
+// operator of P) or null.
+constexpr int BSR_T = 128;
+struct BsrMat {
+  int nbr = 0, nbc = 0;
+  int64_t ntiles = 0;
+  const int64_t* bptr = nullptr;
+  const int32_t* bcol = nullptr;
+  const float* tiles1 = nullptr;
+  const float* tiles2 = nullptr;
+};
+void launch_bsr_mark(const int64_t* rowptr, const int32_t* col, int n, int nbc, int32_t* flag, hipStream_t st);
+void launch_bsr_fill(const int64_t* rowptr, const int32_t* col, const float* val, int n, int nbc, const int32_t* tmap,
+                     bool cplx, float* tiles, hipStream_t st);
+// y = alpha M x (+ beta y) for a real BSR matrix on both trace components
+// (B: 4 nrhs x nbc BSR_T floats)
+void launch_bsr_real2(const BsrMat& M, int rows, int cols, double alpha, const double* x, double* y, int nrhs,
+                      int64_t vstride, int64_t cstride, float* B, hipStream_t st, bool accumulate = false);
+// [yD | yN] += C [xD | xN] + S [xN / k | -k xD] for a complex BSR pair (S in
+// tiles1, C in tiles2 or absent); B1, B2: 4 nrhs x 2 nbc BSR_T floats each
+void launch_bsr_pmchwt(const BsrMat& M, int rows, int cols, double kr, double ki, const double* xD, const double* xN,
+                       double* yD, double* yN, int nrhs, int64_t vstride, float* B1, float* B2, hipStream_t st);
 // FP64 matrix-core forms of the two products above (ld a multiple of 8):
 // combined operators (BD, BN: 2 nrhs x 2 ld doubles each) and one medium
 // (B1, B2: 4 nrhs x 2 ld doubles each, result added to y).

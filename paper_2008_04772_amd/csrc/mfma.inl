@@ -121,6 +121,19 @@ struct Real2Out {
   }
 };
 
+// The same, added: y = alpha M x + y.
+struct Real2AccOut {
+  static constexpr bool kInit = false, kNegA = false;
+  __device__ __forceinline__ float init(int, int) const { return 0.0f; }
+  double* y;
+  int64_t vstride, cstride;
+  double alpha;
+  __device__ __forceinline__ void put(int r, int n, float v) const {
+    const int q = n >> 2, comp = (n >> 1) & 1, part = n & 1;
+    y[2 * (int64_t(q) * vstride + comp * cstride + r) + part] += alpha * double(v);
+  }
+};
+
 // Plain FP32 matrices: y[r * ld + n] = v, or y[r * ld + n] -= v.
 // (kInit: the accumulators start from init(r, n), and with kNegA the
 // product enters with a minus sign, so that y -= A B^T ends in plain stores)
@@ -288,6 +301,181 @@ void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, in
   const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
   hipLaunchKernelGGL((k_mfma_gemm<PmchwtOut>), grid, dim3(256), 0, st, C, B1, Kt, 2 * ld, S, B2, Kt, 2 * ld, rows, Nr,
                      PmchwtOut{yD, yN, vstride, nrhs});
+}
+
+// ---------------------------------------------------------------------------
+// Sparse operators (the near-field P, the sparse mass inverses) applied to
+// many right-hand sides on the matrix cores, as block-sparse rows of dense
+// 128 x 128 tiles: a product with a tile reuses each loaded right-hand-side
+// value for 128 rows, where a CSR product gathers it once per entry.
+// ---------------------------------------------------------------------------
+
+// flag[(i / BSR_T) nbc + col / BSR_T] = 1 for every entry of rows [0, n)
+__global__ void k_bsr_mark(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int n, int nbc,
+                           int32_t* __restrict__ flag) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  for (int64_t e = rowptr[i] + threadIdx.x; e < rowptr[i + 1]; e += blockDim.x)
+    flag[int64_t(i / BSR_T) * nbc + col[e] / BSR_T] = 1;
+}
+
+// tile values (zeroed beforehand): entry (i, j) of tile tmap[(i / T) nbc + j / T]
+// at row i % T, real column j % T (cplx: 2 (j % T) + {re, im})
+template <bool CPLX>
+__global__ void k_bsr_fill(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                           const float* __restrict__ val, int n, int nbc, const int32_t* __restrict__ tmap,
+                           float* __restrict__ tiles) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  constexpr int KW = CPLX ? 2 * BSR_T : BSR_T;
+  const int64_t rb = int64_t(i / BSR_T) * nbc;
+  for (int64_t e = rowptr[i] + threadIdx.x; e < rowptr[i + 1]; e += blockDim.x) {
+    const int j = col[e];
+    float* t = tiles + int64_t(tmap[rb + j / BSR_T]) * BSR_T * KW + int64_t(i % BSR_T) * KW;
+    if (CPLX) {
+      t[2 * (j % BSR_T)] = val[2 * e];
+      t[2 * (j % BSR_T) + 1] = val[2 * e + 1];
+    } else {
+      t[j % BSR_T] = val[e];
+    }
+  }
+}
+
+void launch_bsr_mark(const int64_t* rowptr, const int32_t* col, int n, int nbc, int32_t* flag, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_bsr_mark, dim3(unsigned(n)), dim3(64), 0, st, rowptr, col, n, nbc, flag);
+}
+void launch_bsr_fill(const int64_t* rowptr, const int32_t* col, const float* val, int n, int nbc, const int32_t* tmap,
+                     bool cplx, float* tiles, hipStream_t st) {
+  if (n <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(k_bsr_fill<true>, dim3(unsigned(n)), dim3(64), 0, st, rowptr, col, val, n, nbc, tmap, tiles);
+  else
+    hipLaunchKernelGGL(k_bsr_fill<false>, dim3(unsigned(n)), dim3(64), 0, st, rowptr, col, val, n, nbc, tmap, tiles);
+}
+
+// out = V1 B1 (+ V2 B2) over the tiles of the workgroup's row tile: tiles of
+// KW real columns (KW = 128 real, 256 complex as (re, im) pairs), the tile
+// in row-tile list position t at real K offset bcol[t] KW of the B rows
+// (length Kt).  Same MFMA tiling, LDS layout and prefetch as k_mfma_gemm.
+template <typename Out>
+__global__ __launch_bounds__(256, 2) void k_mfma_bsr(const float* __restrict__ V1, const float* __restrict__ V2,
+                                                     const int64_t* __restrict__ bptr,
+                                                     const int32_t* __restrict__ bcol, int KW,
+                                                     const float* __restrict__ B1, const float* __restrict__ B2,
+                                                     int Kt, int rows, int Nr, Out out) {
+  __shared__ float As[2][MF_BM * MF_LDK];
+  __shared__ float Bs[2][MF_BN * MF_LDK];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int bi = blockIdx.y;
+  const int m0 = bi * MF_BM, n0 = blockIdx.x * MF_BN;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int h = lane >> 5, l32 = lane & 31;
+  mf16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = mf16{};
+  const int64_t tb = bptr[bi];
+  const int ntl = int(bptr[bi + 1] - tb), kpt = KW / MF_BK;
+  const int nseg = V2 ? 2 : 1, nt = nseg * ntl * kpt;
+  const int lr = t >> 3, lc = (t & 7) * 4;
+  mf4 ra[4], rb[4];
+  auto gload = [&](int kt) {
+    const int seg = kt / (ntl * kpt), rem = kt - seg * ntl * kpt, tl = rem / kpt, kk = rem - tl * kpt;
+    const float* A = (seg == 0 ? V1 : V2) + (tb + tl) * int64_t(BSR_T) * KW + kk * MF_BK + lc;
+    const float* B = (seg == 0 ? B1 : B2) + int64_t(bcol[tb + tl]) * KW + kk * MF_BK + lc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = min(n0 + lr + 32 * q, Nr - 1);
+      ra[q] = __builtin_nontemporal_load(reinterpret_cast<const mf4*>(A + int64_t(lr + 32 * q) * KW));
+      rb[q] = *reinterpret_cast<const mf4*>(B + int64_t(c) * Kt);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<mf4*>(&As[buf][(lr + 32 * q) * MF_LDK + lc]) = ra[q];
+      *reinterpret_cast<mf4*>(&Bs[buf][(lr + 32 * q) * MF_LDK + lc]) = rb[q];
+    }
+  };
+  if (nt > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nt) gload(kt + 1);
+    float af[2][16], bf[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const mf4 a = *reinterpret_cast<const mf4*>(&As[buf][(wr + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        const mf4 b = *reinterpret_cast<const mf4*>(&Bs[buf][(wc + 32 * i + l32) * MF_LDK + 16 * h + 4 * q]);
+        af[i][4 * q] = a.x;
+        af[i][4 * q + 1] = a.y;
+        af[i][4 * q + 2] = a.z;
+        af[i][4 * q + 3] = a.w;
+        bf[i][4 * q] = b.x;
+        bf[i][4 * q + 1] = b.y;
+        bf[i][4 * q + 2] = b.z;
+        bf[i][4 * q + 3] = b.w;
+      }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][kk], bf[j][kk], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nt) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wc + 32 * j + l32;
+      if (n >= Nr) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = m0 + wr + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (r < rows) out.put(r, n, acc[i][j][e]);
+      }
+    }
+}
+
+void launch_bsr_real2(const BsrMat& M, int rows, int cols, double alpha, const double* x, double* y, int nrhs,
+                      int64_t vstride, int64_t cstride, float* B, hipStream_t st, bool accumulate) {
+  const int Kt = M.nbc * BSR_T;
+  const int Nr = 4 * nrhs;
+  hipLaunchKernelGGL(k_mfma_rhs_real, dim3(unsigned((Kt + 255) / 256), unsigned(Nr)), dim3(256), 0, st, x, vstride,
+                     cstride, cols, Kt, nrhs, B);
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned(M.nbr));
+  const float* none = nullptr;
+  if (accumulate)
+    hipLaunchKernelGGL((k_mfma_bsr<Real2AccOut>), grid, dim3(256), 0, st, M.tiles1, none, M.bptr, M.bcol, BSR_T, B, B,
+                       Kt, rows, Nr, Real2AccOut{y, vstride, cstride, alpha});
+  else
+    hipLaunchKernelGGL((k_mfma_bsr<Real2Out>), grid, dim3(256), 0, st, M.tiles1, none, M.bptr, M.bcol, BSR_T, B, B, Kt,
+                       rows, Nr, Real2Out{y, vstride, cstride, alpha});
+}
+
+void launch_bsr_pmchwt(const BsrMat& M, int rows, int cols, double kr, double ki, const double* xD, const double* xN,
+                       double* yD, double* yN, int nrhs, int64_t vstride, float* B1, float* B2, hipStream_t st) {
+  const int Kt = M.nbc * 2 * BSR_T;
+  const int Nr = 4 * nrhs;
+  hipLaunchKernelGGL(k_mfma_rhs, dim3(unsigned((Kt / 2 + 255) / 256), unsigned(2 * nrhs)), dim3(256), 0, st, xD, xN,
+                     vstride, cols, Kt, nrhs, kr, ki, B1, B2);
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned(M.nbr));
+  // C (tiles2, may be absent) against B1 = [X_D | X_N], S (tiles1) against B2
+  if (M.tiles2)
+    hipLaunchKernelGGL((k_mfma_bsr<PmchwtOut>), grid, dim3(256), 0, st, M.tiles2, M.tiles1, M.bptr, M.bcol,
+                       2 * BSR_T, B1, B2, Kt, rows, Nr, PmchwtOut{yD, yN, vstride, nrhs});
+  else
+    hipLaunchKernelGGL((k_mfma_bsr<PmchwtOut>), grid, dim3(256), 0, st, M.tiles1, static_cast<const float*>(nullptr),
+                       M.bptr, M.bcol, 2 * BSR_T, B2, B2, Kt, rows, Nr, PmchwtOut{yD, yN, vstride, nrhs});
 }
 
 // One scatterer, the three combined operators C, S1, S2 (FP32, ld a multiple

@@ -53,16 +53,25 @@ def test_mfma64_apply_against_oracle_and_gemv(P, case, nrhs):
     note(f"FP64 MFMA apply: {case}, nrhs={nrhs}")
     ctx = make_ctx(P, meshes, eps, k, qP=(1, 1, 1), nP=1, chi=0.5, precond="S_INT", precision=P.FP64,
                    precisionP=P.FP64)
-    pr = opm.Problem(meshes, eps, k)
+    pr = opm.Problem(meshes, eps, k, qP=(1, 1, 1), nP=1, chiP=0.5, precond="S_INT")
     pr.assemble_A()
     x = _x(nrhs, pr.N, 7)
     y = ctx.apply(0, x)                                                    # matrix cores (nrhs >= 16)
     y4 = np.concatenate([ctx.apply(0, x[i:i + 4]) for i in range(0, nrhs, 4)])  # GEMV path
     e_or, e_gv = rel_fro(y, x @ pr.A.T), rel_fro(y, y4)
     prof = ctx.profile()
-    note(f"  vs oracle {e_or:.2e}, vs GEMV path {e_gv:.2e}, mfma launches {prof['mfma_launches']}")
+    note(f"  A: vs oracle {e_or:.2e}, vs GEMV path {e_gv:.2e}, mfma launches {prof['mfma_launches']}")
     assert prof["mfma_launches"] >= 1
     assert e_or < 1e-12 and e_gv < 1e-13
+    # the FP64 preconditioner: the sparse FP32 mass inverse on the matrix cores
+    # (block-sparse tiles, inputs rounded to FP32) with its FP64 refinement
+    pr.assemble_P()
+    pr.assemble_mass()
+    yp = ctx.apply(1, x)
+    yp4 = np.concatenate([ctx.apply(1, x[i:i + 4]) for i in range(0, nrhs, 4)])
+    e_or, e_gv = rel_fro(yp, x @ (pr.precond_matrix() @ pr.A).T), rel_fro(yp, yp4)
+    note(f"  Ptilde A: vs oracle {e_or:.2e}, vs CSR path {e_gv:.2e}")
+    assert e_or < 1e-10 and e_gv < 1e-10
     ctx.close()
 
 
