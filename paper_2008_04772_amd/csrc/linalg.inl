@@ -882,7 +882,11 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
   double a[NR][8];
   for (int r = 0; r < NR; ++r)
     for (int q = 0; q < 8; ++q) a[r][q] = 0.0;
-  for (int64_t p = rowptr[row] + lane; p < rowptr[row + 1]; p += 64) {
+  const int64_t p1 = rowptr[row + 1];
+  // unrolled so that the index and value loads of later entries are in
+  // flight while earlier ones gather x (the sum per lane stays in order)
+#pragma unroll 4
+  for (int64_t p = rowptr[row] + lane; p < p1; p += 64) {
     const int j = col[p];
     double sr = 0, si = 0, cr = 0, ci = 0;
     if (S) {
@@ -2018,6 +2022,9 @@ __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restric
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
   const int64_t p1 = rowptr[row + 1];
+  // unrolled so that the index and value loads of later entries are in
+  // flight while earlier ones gather x (the sum per lane stays in order)
+#pragma unroll 4
   for (int64_t p = rowptr[row] + lane; p < p1; p += 64) {
     const int c = col[p];
     const double v = double(val[p]);
