@@ -867,33 +867,37 @@ template void launch_gemv_pmchwt<float>(const float*, const float*, int64_t, int
                                         hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Same block structure on a CSR pattern; S or C may be null.
+// Same block structure on a CSR pattern; S or C may be null (HS / HC: which
+// are present, so that only their sums are formed and reduced).  32 lanes per
+// row, two rows per wavefront: the near-field rows hold 100-300 entries.
 // ---------------------------------------------------------------------------
-template <typename M, int NR>
+template <typename M, int NR, bool HS, bool HC>
 __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__ rowptr,
                                                      const int32_t* __restrict__ col, const M* __restrict__ S,
                                                      const M* __restrict__ C, int rows, double kr, double ki,
                                                      const double* __restrict__ xD,
                                                      const double* __restrict__ xN, double* yD, double* yN,
                                                      int64_t vstride, int acc) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (row >= rows) return;
+  const int lane = threadIdx.x & 31;
+  const int row = blockIdx.x * (blockDim.x / 32) + threadIdx.x / 32;
+  const bool live = row < rows;  // both halves of a wavefront take part in the shuffles
   double a[NR][8];
+#pragma unroll
   for (int r = 0; r < NR; ++r)
+#pragma unroll
     for (int q = 0; q < 8; ++q) a[r][q] = 0.0;
-  const int64_t p1 = rowptr[row + 1];
+  const int64_t p0 = live ? rowptr[row] : 0, p1 = live ? rowptr[row + 1] : 0;
   // unrolled so that the index and value loads of later entries are in
   // flight while earlier ones gather x (the sum per lane stays in order)
 #pragma unroll 4
-  for (int64_t p = rowptr[row] + lane; p < p1; p += 64) {
+  for (int64_t p = p0 + lane; p < p1; p += 32) {
     const int j = col[p];
     double sr = 0, si = 0, cr = 0, ci = 0;
-    if (S) {
+    if (HS) {
       sr = double(S[2 * p]);
       si = double(S[2 * p + 1]);
     }
-    if (C) {
+    if (HC) {
       cr = double(C[2 * p]);
       ci = double(C[2 * p + 1]);
     }
@@ -902,19 +906,32 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
       const double* pd = xD + 2 * (int64_t(r) * vstride + j);
       const double* pn = xN + 2 * (int64_t(r) * vstride + j);
       const double dr = pd[0], di = pd[1], nr = pn[0], ni = pn[1];
-      a[r][0] += cr * dr - ci * di;
-      a[r][1] += cr * di + ci * dr;
-      a[r][2] += sr * nr - si * ni;
-      a[r][3] += sr * ni + si * nr;
-      a[r][4] += sr * dr - si * di;
-      a[r][5] += sr * di + si * dr;
-      a[r][6] += cr * nr - ci * ni;
-      a[r][7] += cr * ni + ci * nr;
+      if (HC) {
+        a[r][0] += cr * dr - ci * di;
+        a[r][1] += cr * di + ci * dr;
+        a[r][6] += cr * nr - ci * ni;
+        a[r][7] += cr * ni + ci * nr;
+      }
+      if (HS) {
+        a[r][2] += sr * nr - si * ni;
+        a[r][3] += sr * ni + si * nr;
+        a[r][4] += sr * dr - si * di;
+        a[r][5] += sr * di + si * dr;
+      }
     }
   }
+#pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int q = 0; q < 8; ++q) a[r][q] = wsum(a[r][q]);
-  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool used = (q >= 2 && q < 6) ? HS : HC;
+      if (!used) continue;
+      double v = a[r][q];
+#pragma unroll
+      for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+      a[r][q] = v;
+    }
+  if (live && lane == 0) {
     const double k2 = kr * kr + ki * ki;
     const double ikr = kr / k2, iki = -ki / k2;
     for (int r = 0; r < NR; ++r) {
@@ -931,11 +948,29 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
   }
 }
 
+template <typename M, int NR>
+static void spmv_pmchwt_launch(dim3 grid, const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows,
+                               double kr, double ki, const double* xd, const double* xn, double* yd, double* yn,
+                               int64_t vstride, bool acc, hipStream_t st) {
+  if (S && C)
+    hipLaunchKernelGGL((k_spmv_pmchwt<M, NR, true, true>), grid, dim3(256), 0, st, rowptr, col, S, C, rows, kr, ki,
+                       xd, xn, yd, yn, vstride, int(acc));
+  else if (S)
+    hipLaunchKernelGGL((k_spmv_pmchwt<M, NR, true, false>), grid, dim3(256), 0, st, rowptr, col, S, C, rows, kr, ki,
+                       xd, xn, yd, yn, vstride, int(acc));
+  else if (C)
+    hipLaunchKernelGGL((k_spmv_pmchwt<M, NR, false, true>), grid, dim3(256), 0, st, rowptr, col, S, C, rows, kr, ki,
+                       xd, xn, yd, yn, vstride, int(acc));
+  else
+    hipLaunchKernelGGL((k_spmv_pmchwt<M, NR, false, false>), grid, dim3(256), 0, st, rowptr, col, S, C, rows, kr, ki,
+                       xd, xn, yd, yn, vstride, int(acc));
+}
+
 template <typename M>
 void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows, double kr,
                         double ki, const double* xD, const double* xN, double* yD, double* yN, int nrhs,
                         int64_t vstride, hipStream_t st, bool acc) {
-  const dim3 grid((rows + 3) / 4), block(256);
+  const dim3 grid((rows + 7) / 8);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const double* xd = xD + 2 * int64_t(r0) * vstride;
@@ -943,12 +978,10 @@ void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, c
     double* yd = yD + 2 * int64_t(r0) * vstride;
     double* yn = yN + 2 * int64_t(r0) * vstride;
     if (left >= 4) {
-      hipLaunchKernelGGL((k_spmv_pmchwt<M, 4>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
-                         yn, vstride, int(acc));
+      spmv_pmchwt_launch<M, 4>(grid, rowptr, col, S, C, rows, kr, ki, xd, xn, yd, yn, vstride, acc, st);
       r0 += 4;
     } else {
-      hipLaunchKernelGGL((k_spmv_pmchwt<M, 1>), grid, block, 0, st, rowptr, col, S, C, rows, kr, ki, xd, xn, yd,
-                         yn, vstride, int(acc));
+      spmv_pmchwt_launch<M, 1>(grid, rowptr, col, S, C, rows, kr, ki, xd, xn, yd, yn, vstride, acc, st);
       r0 += 1;
     }
   }
