@@ -8,8 +8,11 @@ Checks at full size: sampled entries of the four dense operators against the
 oracle; the matrix-core product for all 128 right-hand sides against the
 GEMV path of the same context; the 128-RHS batched solve against FP64
 single-RHS solves on the GPU for two of the incident fields (cross sections
-within 1e-5, the bar for the mixed form).
+within 1e-5, the bar for the mixed form); both precisions on the first 4
+incident fields against the oracle's exact discrete cross sections (1e-8).
 """
+
+import os
 
 import numpy as np
 import pytest
@@ -105,3 +108,39 @@ def test_prism_batched_solve_vs_fp64(P, prism, mixed):
         note(f"  rhs {i}: ext {se[i]:.8f} / {e64[0]:.8f}, sca {ss[i]:.8f} / {s64[0]:.8f}")
         assert abs(se[i] - e64[0]) < 1e-5 * abs(e64[0])
         assert abs(ss[i] - s64[0]) < 1e-5 * abs(s64[0])
+
+
+def _golden_sigma():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "prism10368_sigma.txt")
+    ext, sca = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("rhs"):
+                w = line.split()
+                ext.append(float(w[3]))
+                sca.append(float(w[5]))
+    return np.array(ext), np.array(sca)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_prism_cross_sections_vs_oracle_golden(P, prism, mixed, precision):
+    """The first 4 incident fields of the workload (2 directions x 2
+    polarisations) solved to tol 1e-10 (MIXED: FP32 operators with the FP64
+    refinement residual from the FP64 copy of A; FP64: plain) against the
+    oracle's exact discrete cross sections (tests/golden/prism10368_sigma.txt,
+    written by tests/golden/make_prism10368.py), bar 1e-8."""
+    ext_r, sca_r = _golden_sigma()
+    dirs, pols = synth.plane_wave_set(64, seed=3)
+    dirs, pols = dirs[:len(ext_r)], pols[:len(ext_r)]
+    ctx = mixed if precision == "mixed" else _ctx(P, prism, P.FP64)
+    so = P.solver_opts(tol=1e-10, restart=200, max_iter=3000, ir_max=4 if precision == "mixed" else 0)
+    x, st = ctx.solve(dirs, pols, so)
+    se, ss = ctx.cross_sections(x, dirs, pols)
+    e_ext = np.max(np.abs(se - ext_r) / np.abs(ext_r))
+    e_sca = np.max(np.abs(ss - sca_r) / np.abs(sca_r))
+    note(f"  prism golden, {precision}: iterations {st.iterations}, ir {st.ir_steps}; sigma_ext rel {e_ext:.2e}, "
+         f"sigma_sca rel {e_sca:.2e}")
+    assert st.converged
+    assert e_ext < 1e-8 and e_sca < 1e-8
+    if precision == "fp64":
+        ctx.close()
