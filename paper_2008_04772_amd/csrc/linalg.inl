@@ -1156,16 +1156,19 @@ int dots_part_only(const double* V, int64_t vstep, int nvec, const double* w, in
 // of S partial values, h[r][i] = sum_s hp[(r hstride + i) S + s] (complex),
 // added in the order s = 0, 1, ... (S = 1: the coefficients themselves).  A
 // workgroup owns 64 consecutive elements; the coefficients of up to 1024
-// vectors at a time are summed into LDS, then its four wavefronts take every
-// fourth vector (coalesced 1 KB reads per vector, four loads in flight) and
-// the four partial results are added in a fixed order through LDS.
+// vectors at a time are summed into LDS, then its UPD_WAVES wavefronts take
+// every UPD_WAVES-th vector (coalesced 1 KB reads per vector, four loads in
+// flight each: with one workgroup per 64 elements there are only n / 64
+// workgroups, so the wavefronts of one are what fills the CU) and the partial
+// results are added in a fixed order through LDS.
 // With nrm2 given, the workgroup also stores the sum of |w|^2 over its 64
 // updated elements at nrm2[r gridDim.x + blockIdx.x] (0 for an inactive
 // right-hand side): the partial sums of the new vector's norm.
-__global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, int nvec, double* w,
-                                                int64_t wstride, int n, const int32_t* active, int64_t rstride_v,
-                                                const double* hp, int64_t hstride, int S, double sign,
-                                                double* nrm2) {
+constexpr int UPD_WAVES = 16;
+__global__ __launch_bounds__(64 * UPD_WAVES) void k_update(const double* V, int64_t vstep, int nvec, double* w,
+                                                           int64_t wstride, int n, const int32_t* active,
+                                                           int64_t rstride_v, const double* hp, int64_t hstride,
+                                                           int S, double sign, double* nrm2) {
   constexpr int CH = 1024;
   const int r = blockIdx.y;
   if (!active[r]) {
@@ -1179,13 +1182,15 @@ __global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, 
   const double2* base = reinterpret_cast<const double2*>(V) + int64_t(r) * rstride_v + kk;
   const double2* hr_ = reinterpret_cast<const double2*>(hp) + int64_t(r) * hstride * S;
   __shared__ double2 hs[CH];
-  __shared__ double2 part[3][64];
+  __shared__ double2 part[UPD_WAVES - 1][64];
   double re = 0, im = 0;
   for (int i0 = 0; i0 < nvec; i0 += CH) {
     const int nc = min(CH, nvec - i0);
     __syncthreads();
     for (int t = threadIdx.x; t < nc; t += blockDim.x) {
       double2 h = {0.0, 0.0};
+      // unrolled: the partial sums' loads in flight together (added in order)
+#pragma unroll 8
       for (int sidx = 0; sidx < S; ++sidx) {
         const double2 v = hr_[int64_t(i0 + t) * S + sidx];
         h.x += v.x;
@@ -1196,18 +1201,18 @@ __global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, 
     __syncthreads();
     const double2* bi = base + int64_t(i0) * vstep;
     int i = wv;
-    for (; i + 12 < nc; i += 16) {
+    for (; i + 3 * UPD_WAVES < nc; i += 4 * UPD_WAVES) {
       double2 v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = bi[int64_t(i + 4 * u) * vstep];
+      for (int u = 0; u < 4; ++u) v[u] = bi[int64_t(i + UPD_WAVES * u) * vstep];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double2 h = hs[i + 4 * u];
+        const double2 h = hs[i + UPD_WAVES * u];
         re += v[u].x * h.x - v[u].y * h.y;
         im += v[u].x * h.y + v[u].y * h.x;
       }
     }
-    for (; i < nc; i += 4) {
+    for (; i < nc; i += UPD_WAVES) {
       const double2 v = bi[int64_t(i) * vstep];
       const double2 h = hs[i];
       re += v.x * h.x - v.y * h.y;
@@ -1220,7 +1225,7 @@ __global__ __launch_bounds__(256) void k_update(const double* V, int64_t vstep, 
     double sq = 0.0;
     if (in) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < UPD_WAVES - 1; ++q) {
         re += part[q][lane].x;
         im += part[q][lane].y;
       }
@@ -1242,7 +1247,7 @@ int update_blocks(int n) { return (n + 63) / 64; }
 void launch_update(const double* V, int64_t vstep, int nvec, double* w, int64_t wstride, int n,
                    const int32_t* active, int nrhs, int64_t rstride_v, const double* h, int64_t hstride, double sign,
                    hipStream_t st, int S, double* nrm2) {
-  hipLaunchKernelGGL(k_update, dim3(update_blocks(n), nrhs), dim3(256), 0, st, V, vstep, nvec, w, wstride, n, active,
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(n), nrhs), dim3(64 * UPD_WAVES), 0, st, V, vstep, nvec, w, wstride, n, active,
                      rstride_v, h, hstride, S, sign, nrm2);
 }
 
@@ -1344,6 +1349,7 @@ __global__ void k_finish_step(const double* w, int64_t wstride, double* v, int64
     double2* f2 = reinterpret_cast<double2*>(fin) + int64_t(nrhs) * nvec + int64_t(r) * nvec;
     for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
       double2 a = {0.0, 0.0}, b = {0.0, 0.0};
+#pragma unroll 8
       for (int sidx = 0; sidx < S1; ++sidx) {
         const double2 u = p1[int64_t(i) * S1 + sidx], t = p2[int64_t(i) * S1 + sidx];
         a.x += u.x;
