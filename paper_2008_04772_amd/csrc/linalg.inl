@@ -1107,29 +1107,29 @@ __global__ void k_dots_part(const double* V, int64_t vstep, const double* w, int
     if (threadIdx.x == 0) o[0] = o[1] = 0.0;
     return;
   }
-  const double* v = V + 2 * (int64_t(i) * vstep + int64_t(r) * rstride_v);
-  const double* ww = w + 2 * int64_t(r) * wstride;
+  const double2* v = reinterpret_cast<const double2*>(V) + int64_t(i) * vstep + int64_t(r) * rstride_v;
+  const double2* ww = reinterpret_cast<const double2*>(w) + int64_t(r) * wstride;
   const int k0 = sidx * chunk, k1 = min(n, k0 + chunk);
   double re = 0, im = 0;
+#pragma unroll 4
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    const double vr = v[2 * k], vi = v[2 * k + 1], xr = ww[2 * k], xi = ww[2 * k + 1];
-    re += vr * xr + vi * xi;
-    im += vr * xi - vi * xr;
+    const double2 a = v[k], x = ww[k];
+    re += a.x * x.x + a.y * x.y;
+    im += a.x * x.y - a.y * x.x;
   }
-  __shared__ double sr[256], si[256];
-  sr[threadIdx.x] = re;
-  si[threadIdx.x] = im;
+  // wavefront sums, then the four wavefronts in order
+  re = wsum(re);
+  im = wsum(im);
+  __shared__ double sr[4], si[4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sr[wv] = re;
+    si[wv] = im;
+  }
   __syncthreads();
-  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
-    if (threadIdx.x < q) {
-      sr[threadIdx.x] += sr[threadIdx.x + q];
-      si[threadIdx.x] += si[threadIdx.x + q];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    o[0] = sr[0];
-    o[1] = si[0];
+    o[0] = ((sr[0] + sr[1]) + sr[2]) + sr[3];
+    o[1] = ((si[0] + si[1]) + si[2]) + si[3];
   }
 }
 
