@@ -161,10 +161,10 @@ struct SubOut {
 // permutation of k for both operands, so its 16 values per tile are
 // contiguous in LDS.
 template <typename Out>
-__global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ A1, const float* __restrict__ B1,
-                                                      int K1, int64_t lda1, const float* __restrict__ A2,
-                                                      const float* __restrict__ B2, int K2, int64_t lda2, int rows,
-                                                      int Nr, Out out) {
+__device__ __forceinline__ void mfma_gemm_tile(const float* __restrict__ A1, const float* __restrict__ B1, int K1,
+                                               int64_t lda1, const float* __restrict__ A2,
+                                               const float* __restrict__ B2, int K2, int64_t lda2, int rows, int Nr,
+                                               const Out& out) {
   __shared__ float As[2][MF_BM * MF_LDK];
   __shared__ float Bs[2][MF_BN * MF_LDK];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -256,6 +256,27 @@ __global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ 
         if (r < rows) out.put(r, n, acc[i][j][e]);
       }
     }
+}
+
+template <typename Out>
+__global__ __launch_bounds__(256, 2) void k_mfma_gemm(const float* __restrict__ A1, const float* __restrict__ B1,
+                                                      int K1, int64_t lda1, const float* __restrict__ A2,
+                                                      const float* __restrict__ B2, int K2, int64_t lda2, int rows,
+                                                      int Nr, Out out) {
+  mfma_gemm_tile<Out>(A1, B1, K1, lda1, A2, B2, K2, lda2, rows, Nr, out);
+}
+
+// Two products of the same shape in one launch, blockIdx.z picking (a) or
+// (b) (selected in scalar registers): twice the workgroups of one product
+// for outputs whose tiles alone do not fill the chip.
+template <typename Out>
+__global__ __launch_bounds__(256, 2) void k_mfma_gemm2(const float* A1a, const float* B1a, const float* A2a,
+                                                       const float* B2a, Out oa, const float* A1b, const float* B1b,
+                                                       const float* A2b, const float* B2b, Out ob, int K, int64_t lda,
+                                                       int rows, int Nr) {
+  const bool zb = blockIdx.z != 0;
+  const Out out = zb ? ob : oa;
+  mfma_gemm_tile<Out>(zb ? A1b : A1a, zb ? B1b : B1a, K, lda, zb ? A2b : A2a, zb ? B2b : B2a, K, lda, rows, Nr, out);
 }
 
 // Xhat^T for a real matrix: row n = (rhs n/4, component (n/2)%2, part n%2),
@@ -479,9 +500,9 @@ void launch_bsr_pmchwt(const BsrMat& M, int rows, int cols, double kr, double ki
 }
 
 // One scatterer, the three combined operators C, S1, S2 (FP32, ld a multiple
-// of 16): yD = C xD + S1 xN and yN = C xN + S2 xD, two GEMM launches of two
-// K segments each (four complex products per right-hand side instead of the
-// eight of the per-medium form).  BD, BN: workspaces of 2 nrhs x 2 ld floats.
+// of 16): yD = C xD + S1 xN and yN = C xN + S2 xD, two GEMMs of two K
+// segments each in one launch (four complex products per right-hand side
+// instead of the eight of the per-medium form).  BD, BN: workspaces of 2 nrhs x 2 ld floats.
 void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
                       const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
                       float* BN, hipStream_t st) {
@@ -490,11 +511,9 @@ void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t 
   const dim3 gb(unsigned((Kt / 2 + 255) / 256), unsigned(nrhs));
   hipLaunchKernelGGL(k_mfma_rhs_plain<float>, gb, dim3(256), 0, st, xD, vstride, cols, Kt, BD);
   hipLaunchKernelGGL(k_mfma_rhs_plain<float>, gb, dim3(256), 0, st, xN, vstride, cols, Kt, BN);
-  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM));
-  hipLaunchKernelGGL((k_mfma_gemm<CplxOut<float>>), grid, dim3(256), 0, st, C, BD, Kt, 2 * ld, S1, BN, Kt, 2 * ld,
-                     rows, Nr, CplxOut<float>{yD, vstride});
-  hipLaunchKernelGGL((k_mfma_gemm<CplxOut<float>>), grid, dim3(256), 0, st, C, BN, Kt, 2 * ld, S2, BD, Kt, 2 * ld,
-                     rows, Nr, CplxOut<float>{yN, vstride});
+  const dim3 grid(unsigned((Nr + MF_BN - 1) / MF_BN), unsigned((rows + MF_BM - 1) / MF_BM), 2);
+  hipLaunchKernelGGL((k_mfma_gemm2<CplxOut<float>>), grid, dim3(256), 0, st, C, BD, S1, BN, CplxOut<float>{yD, vstride},
+                     C, BN, S2, BD, CplxOut<float>{yN, vstride}, Kt, 2 * ld, rows, Nr);
 }
 
 }  // namespace pmchwt
