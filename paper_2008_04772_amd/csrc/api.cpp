@@ -2905,7 +2905,17 @@ void build_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
     const int64_t o = s.edge_off;
     const double* x = cinc.as<double>();
     double* y = t.as<double>();
-    if (c->precA == PMCHWT_FP64)
+    if (nrhs >= MFMA_MIN_RHS && c->precA == PMCHWT_FP64) {  // matrix cores for many right-hand sides
+      double* B1 = mfma_ws64(c, nrhs);
+      launch_mfma64_pmchwt(c->Si[m].as<double>(), c->Ci[m].as<double>(), c->ldI[m], s.topo.E, s.topo.E, s.k.real(),
+                           s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs, B1,
+                           B1 + size_t(4) * nrhs * 2 * size_t(c->ldE), c->stream);
+    } else if (nrhs >= MFMA_MIN_RHS) {
+      float* B1 = mfma_ws(c, nrhs);
+      launch_mfma_pmchwt(c->Si[m].as<float>(), c->Ci[m].as<float>(), c->ldI[m], s.topo.E, s.topo.E, s.k.real(),
+                         s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs, vs, B1,
+                         B1 + size_t(4) * nrhs * 2 * size_t(c->ldE), c->stream);
+    } else if (c->precA == PMCHWT_FP64)
       launch_gemv_pmchwt<double>(c->Si[m].as<double>(), c->Ci[m].as<double>(), c->ldI[m], s.topo.E, s.topo.E,
                                  s.k.real(), s.k.imag(), x + 2 * o, x + 2 * (E + o), y + 2 * o, y + 2 * (E + o), nrhs,
                                  vs, c->stream);
