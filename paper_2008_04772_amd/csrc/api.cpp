@@ -1928,57 +1928,78 @@ bool sparse_mass_inverse(pmchwt_ctx* c, const pmchwt_ctx::SparseInv& Mcsr, const
   const int steps = hops + 6;
   if (maxM > spinv_wmax() || maxT > spinv_wmax()) return false;
   const int cap = spinv_cap();
-  DBuf count = dalloc_c<int32_t>(c, 2 * size_t(n)), ball = dalloc_c<int32_t>(c, 2 * size_t(n) * cap);
-  // pass 1 for both inverses, then one wait for the ball sizes
-  auto job = [&](const pmchwt_ctx::SparseInv& g, const pmchwt_ctx::SparseInv& h, int which) {
-    SpInvJob J{};
-    J.n = n;
-    J.rp = g.rowptr.as<int64_t>();  // search graph: CSR of the matrix inverted
-    J.ci = g.col.as<int32_t>();
-    J.cp = h.rowptr.as<int64_t>();  // gather: its CSC = the CSR of its transpose
-    J.ri = h.col.as<int32_t>();
-    J.cv = h.val.as<double>();
-    J.hops = hops;
-    J.steps = steps;
-    J.a = 0.3;
-    J.b = 1.05;
-    J.count = count.as<int32_t>() + size_t(which) * n;
-    J.ball = ball.as<int32_t>() + size_t(which) * n * cap;
-    return J;
-  };
-  SpInvJob J0 = job(Mcsr, MTcsr, 0), J1 = job(MTcsr, Mcsr, 1);
-  launch_spinv_ball(J0, std::min(n, 4096), c->stream);
-  launch_spinv_ball(J1, std::min(n, 4096), c->stream);
+  hipStream_t st = c->stream;
+  DBuf count = dalloc_c<int32_t>(c, size_t(n)), ball = dalloc_c<int32_t>(c, size_t(n) * cap);
+  // the inverse of M_A: pass 1 (balls), one wait for their sizes, pass 2
+  SpInvJob J{};
+  J.n = n;
+  J.rp = Mcsr.rowptr.as<int64_t>();  // search graph: CSR of the matrix inverted
+  J.ci = Mcsr.col.as<int32_t>();
+  J.cp = MTcsr.rowptr.as<int64_t>();  // gather: its CSC = the CSR of its transpose
+  J.ri = MTcsr.col.as<int32_t>();
+  J.cv = MTcsr.val.as<double>();
+  J.hops = hops;
+  J.steps = steps;
+  J.a = 0.3;
+  J.b = 1.05;
+  J.count = count.as<int32_t>();
+  J.ball = ball.as<int32_t>();
+  launch_spinv_ball(J, std::min(n, 4096), st);
   HIPCHK(hipGetLastError());
-  std::vector<int32_t> hc(2 * size_t(n));
-  HIPCHK(hipMemcpyAsync(hc.data(), count.p, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  DBuf res = dalloc_c<double>(c, 2 * size_t(n));
-  for (int which = 0; which < 2; ++which) {
-    pmchwt_ctx::SparseInv& out = which == 0 ? inv : invT;
-    std::vector<int64_t> rowptr(size_t(n) + 1, 0);
-    for (int i = 0; i < n; ++i) {
-      const int b = hc[size_t(which) * n + i];
-      if (b < 0) return false;
-      rowptr[i + 1] = rowptr[i] + b;
-    }
-    out.nnz = rowptr[n];
-    out.rowptr = upload(c, rowptr);
-    out.col = dalloc_c<int32_t>(c, size_t(out.nnz));
-    out.val = dalloc_c<float>(c, size_t(out.nnz));
-    SpInvJob& J = which == 0 ? J0 : J1;
-    J.orp = out.rowptr.as<int64_t>();
-    J.ocol = out.col.as<int32_t>();
-    J.oval = out.val.p;
-    J.res = res.as<double>() + size_t(which) * n;
-    launch_spinv_vals<float>(J, std::min(n, 1024), c->stream);
-    HIPCHK(hipGetLastError());
+  std::vector<int32_t> hc(static_cast<size_t>(n));
+  HIPCHK(hipMemcpyAsync(hc.data(), count.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int64_t> rowptr(size_t(n) + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int b = hc[size_t(i)];
+    if (b < 0) return false;
+    rowptr[i + 1] = rowptr[i] + b;
   }
-  std::vector<double> hr(2 * size_t(n));
-  HIPCHK(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  inv.nnz = rowptr[n];
+  if (inv.nnz >= (int64_t(1) << 32)) return false;  // entry indices of the transpose's records are 32-bit
+  inv.rowptr = upload(c, rowptr);
+  inv.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(inv.nnz, 1)));
+  inv.val = dalloc_c<float>(c, size_t(std::max<int64_t>(inv.nnz, 1)));
+  DBuf res = dalloc_c<double>(c, size_t(n));
+  J.orp = inv.rowptr.as<int64_t>();
+  J.ocol = inv.col.as<int32_t>();
+  J.oval = inv.val.p;
+  J.res = res.as<double>();
+  launch_spinv_vals<float>(J, std::min(n, 1024), st);
+  HIPCHK(hipGetLastError());
+  // M_A^-T as the transpose of the computed inverse: its error is the
+  // transpose of the inverse's, and one ball search and Chebyshev pass less
+  const int64_t nnz = inv.nnz;
+  DBuf cnt = dalloc_c<int32_t>(c, size_t(n)), cur = dalloc_c<int32_t>(c, size_t(n)),
+       rec = dalloc_c<int64_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+  invT.nnz = nnz;
+  invT.rowptr = dalloc_c<int64_t>(c, size_t(n) + 1);
+  invT.col = dalloc_c<int32_t>(c, size_t(std::max<int64_t>(nnz, 1)));
+  invT.val = dalloc_c<float>(c, size_t(std::max<int64_t>(nnz, 1)));
+  launch_cls_fill_i32(cnt.as<int32_t>(), n, 0, st);
+  launch_cls_fill_i32(cur.as<int32_t>(), n, 0, st);
+  launch_csr_colcount(inv.col.as<int32_t>(), nnz, cnt.as<int32_t>(), st);
+  launch_scan_i32(cnt.as<int32_t>(), n, invT.rowptr.as<int64_t>(), st);
+  launch_csr_tplace(inv.rowptr.as<int64_t>(), inv.col.as<int32_t>(), n, invT.rowptr.as<int64_t>(), cur.as<int32_t>(),
+                    rec.as<int64_t>(), st);
+  std::vector<int32_t> hcnt(static_cast<size_t>(n));
+  HIPCHK(hipMemcpyAsync(hcnt.data(), cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  std::vector<double> hr(static_cast<size_t>(n));
+  HIPCHK(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int maxc = n > 0 ? *std::max_element(hcnt.begin(), hcnt.end()) : 0;
+  if (maxc > 4096) return false;  // LDS of the per-column sort
+  SymRecJob S{};
+  S.n = n;
+  S.recptr = invT.rowptr.as<int64_t>();
+  S.rec = rec.as<int64_t>();
+  S.cnt = cur.as<int32_t>();  // scratch: the sort writes a count per column
+  launch_sym_sort(S, pow2_ceil(std::max(maxc, 1)), st);
+  launch_csr_tgather(rec.as<int64_t>(), nnz, inv.val.as<float>(), invT.col.as<int32_t>(), invT.val.as<float>(), st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));  // the scratch tables above go out of scope
   c->prof.mass_iterations = steps;
-  c->prof.mass_residual = *std::max_element(hr.begin(), hr.end());
+  c->prof.mass_residual = n > 0 ? *std::max_element(hr.begin(), hr.end()) : 0.0;
   return true;
 }
 

@@ -123,6 +123,14 @@ struct SpInvJob {
   void* oval;
   double* res;
 };
+// transpose of an n x n CSR matrix (FP32 values): column counts (cnt zeroed),
+// records placed per column (cur zeroed; rec: nnz int64), then, after the
+// records are sorted per column (launch_sym_sort), columns and values
+void launch_csr_colcount(const int32_t* col, int64_t nnz, int32_t* cnt, hipStream_t st);
+void launch_csr_tplace(const int64_t* rowptr, const int32_t* col, int n, const int64_t* trowptr, int32_t* cur,
+                       int64_t* rec, hipStream_t st);
+void launch_csr_tgather(const int64_t* rec, int64_t nnz, const float* val, int32_t* tcol, float* tval,
+                        hipStream_t st);
 int spinv_cap();
 int spinv_wmax();
 void launch_spinv_ball(const SpInvJob& J, int grid, hipStream_t st);

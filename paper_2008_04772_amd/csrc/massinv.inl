@@ -220,6 +220,50 @@ void launch_csr_scatter_f32(const int64_t* rowptr, const int32_t* col, const flo
   hipLaunchKernelGGL(k_csr_scatter<float>, dim3(unsigned(n)), dim3(256), 0, st, rowptr, col, val, out, ld);
 }
 
+// ---------------------------------------------------------------------------
+// Transpose of an FP32 CSR matrix (the sparse M_A^-T from M_A^-1): column
+// counts, a scan, records (row << 32 | entry) placed per column, sorted per
+// column in LDS (k_sym_sort) so that the order is the row order whatever the
+// order of the atomic placements, then the gather of columns and values.
+// ---------------------------------------------------------------------------
+__global__ void k_csr_colcount(const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ cnt) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < nnz) atomicAdd(&cnt[col[p]], 1);
+}
+
+__global__ void k_csr_tplace(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int n,
+                             const int64_t* __restrict__ trowptr, int32_t* __restrict__ cur,
+                             int64_t* __restrict__ rec) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  for (int64_t p = rowptr[i] + threadIdx.x; p < rowptr[i + 1]; p += blockDim.x) {
+    const int j = col[p];
+    rec[trowptr[j] + atomicAdd(&cur[j], 1)] = (int64_t(i) << 32) | int64_t(uint32_t(p));
+  }
+}
+
+__global__ void k_csr_tgather(const int64_t* __restrict__ rec, int64_t nnz, const float* __restrict__ val,
+                              int32_t* __restrict__ tcol, float* __restrict__ tval) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const int64_t r = rec[q];
+  tcol[q] = int32_t(r >> 32);
+  tval[q] = val[uint32_t(r & 0xffffffffll)];
+}
+
+void launch_csr_colcount(const int32_t* col, int64_t nnz, int32_t* cnt, hipStream_t st) {
+  if (nnz > 0) hipLaunchKernelGGL(k_csr_colcount, dim3(unsigned((nnz + 255) / 256)), dim3(256), 0, st, col, nnz, cnt);
+}
+void launch_csr_tplace(const int64_t* rowptr, const int32_t* col, int n, const int64_t* trowptr, int32_t* cur,
+                       int64_t* rec, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_csr_tplace, dim3(unsigned(n)), dim3(64), 0, st, rowptr, col, n, trowptr, cur, rec);
+}
+void launch_csr_tgather(const int64_t* rec, int64_t nnz, const float* val, int32_t* tcol, float* tval,
+                        hipStream_t st) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_csr_tgather, dim3(unsigned((nnz + 255) / 256)), dim3(256), 0, st, rec, nnz, val, tcol, tval);
+}
+
 int spinv_cap() { return SPINV_CAP; }
 int spinv_wmax() { return SPINV_W; }
 
