@@ -288,6 +288,28 @@ int pmchwt_rhs(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols, 
 int pmchwt_apply(pmchwt_ctx *ctx, int32_t which, const pmchwt_complex *x, int32_t nrhs,
                  pmchwt_complex *y);
 
+/* Device-pointer forms (for callers whose vectors already live on the GPU,
+ * e.g. torch tensors).  x_dev, y_dev, currents_dev, obs_dev and F_dev are
+ * device pointers of the same sizes and layouts as the host arrays of the
+ * plain forms (complex interleaved, scatterer-major [D_m ; N_m] per right-hand
+ * side; obs_dev double[nobs*3]; F_dev nrhs*nobs*3), owned by the caller,
+ * allocated through the HIP runtime this library runs on (the process's
+ * libamdhip64) and not checked beyond null.  hip_stream is the caller's
+ * hipStream_t of that runtime (NULL:
+ * none): the context's work waits for what the caller enqueued on it before
+ * the call, and the caller's later work on it waits for the outputs.
+ * pmchwt_apply_device and pmchwt_far_field_device only enqueue (they return
+ * before the outputs are written); pmchwt_solve_device takes its plane waves
+ * from host memory, returns when the solve is done and writes the currents
+ * to currents_dev.  Errors as for the plain forms.                          */
+int pmchwt_apply_device(pmchwt_ctx *ctx, int32_t which, const pmchwt_complex *x_dev, int32_t nrhs,
+                        pmchwt_complex *y_dev, void *hip_stream);
+int pmchwt_solve_device(pmchwt_ctx *ctx, const double *dirs, const pmchwt_complex *pols, int32_t nrhs,
+                        const pmchwt_solver_opts *opts, pmchwt_complex *currents_dev,
+                        pmchwt_solve_stats *stats, void *hip_stream);
+int pmchwt_far_field_device(pmchwt_ctx *ctx, const pmchwt_complex *currents_dev, int32_t nrhs,
+                            const double *obs_dev, int32_t nobs, pmchwt_complex *F_dev, void *hip_stream);
+
 /* Solve for the scattered traces of nrhs incident plane waves (see
  * pmchwt_rhs) with GMRES on the preconditioned system.  currents_out[nrhs*N].
  * Returns PMCHWT_ERR_NOT_CONVERGED (outputs still written) if max_iter is

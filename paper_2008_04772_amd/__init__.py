@@ -131,6 +131,10 @@ _SIGS = {
                       ctypes.POINTER(pmchwt_solve_stats)], ctypes.c_int),
     "pmchwt_far_field": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
     "pmchwt_far_field_noalloc": ([_P, _pc, ctypes.c_int32, _pd, ctypes.c_int32, _pc], ctypes.c_int),
+    "pmchwt_apply_device": ([_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "pmchwt_solve_device": ([_P, _pd, _pc, ctypes.c_int32, ctypes.POINTER(pmchwt_solver_opts), _P,
+                             ctypes.POINTER(pmchwt_solve_stats), _P], ctypes.c_int),
+    "pmchwt_far_field_device": ([_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
     "pmchwt_near_field": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, ctypes.c_int32, _pc, _pi32], ctypes.c_int),
     "pmchwt_cross_sections": ([_P, _pc, ctypes.c_int32, _pd, _pc, _pd, _pd], ctypes.c_int),
     "pmchwt_bc_fields": ([_pd, ctypes.c_int32, _pi32, ctypes.c_int32, _pi64, _pi32, _pd], ctypes.c_int),
@@ -286,6 +290,29 @@ def pmchwt_apply(ctx, which, x):
     return y
 
 
+# Device-pointer forms: vectors are device addresses (ints) of memory from
+# the library's own HIP runtime (this process's libamdhip64), of the plain
+# forms' sizes and layouts; `stream` a hipStream_t as an int, or None.
+def pmchwt_apply_device(ctx, which, x_dev, nrhs, y_dev, stream=None):
+    _check(ctx, _lib.pmchwt_apply_device(ctx, int(which), _P(int(x_dev)), int(nrhs), _P(int(y_dev)),
+                                         _P(int(stream) if stream else None)))
+
+
+def pmchwt_solve_device(ctx, dirs, pols, opts, currents_dev, stream=None, allow_not_converged=False):
+    d, p = _waves(dirs, pols)
+    st = pmchwt_solve_stats()
+    allow = (ERR_NOT_CONVERGED,) if allow_not_converged else ()
+    _check(ctx, _lib.pmchwt_solve_device(ctx, _ptr(d, _pd), _ptr(p, _pc), len(d), ctypes.byref(opts),
+                                         _P(int(currents_dev)), ctypes.byref(st),
+                                         _P(int(stream) if stream else None)), allow)
+    return st
+
+
+def pmchwt_far_field_device(ctx, currents_dev, nrhs, obs_dev, nobs, F_dev, stream=None):
+    _check(ctx, _lib.pmchwt_far_field_device(ctx, _P(int(currents_dev)), int(nrhs), _P(int(obs_dev)), int(nobs),
+                                             _P(int(F_dev)), _P(int(stream) if stream else None)))
+
+
 def solver_opts(tol=1e-6, restart=200, max_iter=2000, ir_max=0):
     return pmchwt_solver_opts(float(tol), int(restart), int(max_iter), int(ir_max))
 
@@ -416,6 +443,15 @@ class Context:
 
     def solve(self, dirs, pols, opts, allow_not_converged=False):
         return pmchwt_solve(self.h, dirs, pols, opts, allow_not_converged)
+
+    def apply_device(self, which, x_dev, nrhs, y_dev, stream=None):
+        return pmchwt_apply_device(self.h, which, x_dev, nrhs, y_dev, stream)
+
+    def solve_device(self, dirs, pols, opts, currents_dev, stream=None, allow_not_converged=False):
+        return pmchwt_solve_device(self.h, dirs, pols, opts, currents_dev, stream, allow_not_converged)
+
+    def far_field_device(self, currents_dev, nrhs, obs_dev, nobs, F_dev, stream=None):
+        return pmchwt_far_field_device(self.h, currents_dev, nrhs, obs_dev, nobs, F_dev, stream)
 
     def far_field(self, currents, obs):
         return pmchwt_far_field(self.h, currents, obs)

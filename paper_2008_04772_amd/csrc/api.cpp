@@ -229,6 +229,9 @@ struct pmchwt_ctx {
   // block-sparse copies of the FP32 P (interior per scatterer, exterior)
   std::vector<BsrHold> bsrPi;
   BsrHold bsrPe;
+  DBuf soff;  // scatterers' first union edges (device, for the layout kernel)
+  int soff_n = -1;
+  int64_t soff_E = -1;
   DBuf bsr_ws;  // expanded right-hand blocks of the block-sparse products
   size_t bsr_ws_bytes = 0;
   std::vector<int64_t> h_rowptr;
@@ -2821,6 +2824,39 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
   HIPCHK(hipGetLastError());
 }
 
+// Device table of the scatterers' first union edges (and E_tot) for the
+// layout kernel, rebuilt when the scatterers change.
+const int32_t* scat_offsets(pmchwt_ctx* c) {
+  if (c->soff_n != int(c->sc.size()) || c->soff_E != c->E_tot) {
+    std::vector<int32_t> o;
+    for (auto& s : c->sc) o.push_back(s.edge_off);
+    o.push_back(int32_t(c->E_tot));
+    c->soff = upload(c, o);
+    c->soff_n = int(c->sc.size());
+    c->soff_E = c->E_tot;
+  }
+  return c->soff.as<int32_t>();
+}
+
+// Stream order between a caller's stream (device-pointer entry points; null:
+// none) and the context's: the context's work waits for what the caller has
+// enqueued so far, and the caller's later work waits for the context's.
+void stream_wait(hipStream_t waiter, hipStream_t on) {
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(e, on));
+  HIPCHK(hipStreamWaitEvent(waiter, e, 0));
+  HIPCHK(hipEventDestroy(e));
+}
+void order_before_ctx(pmchwt_ctx* c, void* user) {
+  hipStream_t u = static_cast<hipStream_t>(user);
+  if (u && u != c->stream) stream_wait(c->stream, u);
+}
+void order_after_ctx(pmchwt_ctx* c, void* user) {
+  hipStream_t u = static_cast<hipStream_t>(user);
+  if (u && u != c->stream) stream_wait(u, c->stream);
+}
+
 // API layout (scatterer-major [D_m ; N_m]) <-> internal layout ([D ; N] over the union)
 void to_internal(const pmchwt_ctx* c, const pmchwt_complex* in, int nrhs, std::vector<double>& out) {
   const int64_t E = c->E_tot, N = 2 * E;
@@ -3699,6 +3735,31 @@ int pmchwt_rhs(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, in
   });
 }
 
+int pmchwt_apply_device(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x_dev, int32_t nrhs,
+                        pmchwt_complex* y_dev, void* hip_stream) {
+  return guarded(c, [&]() -> int {
+    if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
+    if (nrhs <= 0 || !x_dev || !y_dev || which < 0 || which > 3) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    const size_t nd = size_t(2 * vlen(c) * nrhs);
+    const int32_t* soff = scat_offsets(c);
+    const int E = int(c->E_tot), nsc = int(c->sc.size());
+    DBuf dx = dalloc_c<double>(c, nd), dy = dalloc_c<double>(c, nd), s1 = dalloc_c<double>(c, nd),
+         s2 = dalloc_c<double>(c, nd), s3 = dalloc_c<double>(c, nd);
+    order_before_ctx(c, hip_stream);
+    launch_layout(reinterpret_cast<const double*>(x_dev), dx.as<double>(), nrhs, E, soff, nsc, true, c->stream);
+    if (which == 0)
+      apply_A(c, dx.as<double>(), dy.as<double>(), nrhs);
+    else if (which >= 2)
+      apply_A_free(c, dx.as<double>(), dy.as<double>(), nrhs, which == 2);
+    else
+      op_apply(c, dx.as<double>(), dy.as<double>(), s1.as<double>(), s2.as<double>(), s3.as<double>(), nrhs);
+    launch_layout(dy.as<double>(), reinterpret_cast<double*>(y_dev), nrhs, E, soff, nsc, false, c->stream);
+    HIPCHK(hipGetLastError());
+    order_after_ctx(c, hip_stream);  // the buffers above return to the pool in stream order
+    return PMCHWT_OK;
+  });
+}
+
 int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t nrhs, pmchwt_complex* y) {
   return guarded(c, [&]() -> int {
     if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
@@ -3722,11 +3783,15 @@ int pmchwt_apply(pmchwt_ctx* c, int32_t which, const pmchwt_complex* x, int32_t 
   });
 }
 
-int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs,
-                 const pmchwt_solver_opts* o, pmchwt_complex* cur, pmchwt_solve_stats* st) {
+// The solve of pmchwt_solve / pmchwt_solve_device: currents to host memory
+// (cur) or, in the API layout, to device memory (cur_dev, on the context's
+// stream, then ordered before the caller's stream `user`).
+static int solve_common(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs,
+                 const pmchwt_solver_opts* o, pmchwt_complex* cur, pmchwt_complex* cur_dev, void* user,
+                 pmchwt_solve_stats* st) {
   return guarded(c, [&]() -> int {
     if (!c->have_A) return fail(c, PMCHWT_ERR_STATE, "not assembled");
-    if (nrhs <= 0 || !dirs || !pols || !cur || !o) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    if (nrhs <= 0 || !dirs || !pols || !(cur || cur_dev) || !o) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
     if (!(o->tol > 0) || o->restart < 1 || o->restart > 1024 || o->max_iter < 1 || o->ir_max < 0)
       return fail(c, PMCHWT_ERR_INVALID_ARG, "bad solver options");
     const int64_t vs = vlen(c);
@@ -3812,10 +3877,18 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     const double ms = tm.stop();
     flush_times(c);
     mv_max = c->calls_A * A_matvecs(c) + c->calls_P * P_matvecs(c);
-    std::vector<double> h(nd);
-    HIPCHK(hipMemcpyAsync(h.data(), x.p, nd * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    to_api(c, h, nrhs, cur);
+    if (cur_dev) {
+      launch_layout(x.as<double>(), reinterpret_cast<double*>(cur_dev), nrhs, int(c->E_tot), scat_offsets(c),
+                    int(c->sc.size()), false, c->stream);
+      HIPCHK(hipGetLastError());
+      order_after_ctx(c, user);
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } else {
+      std::vector<double> h(nd);
+      HIPCHK(hipMemcpyAsync(h.data(), x.p, nd * 8, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      to_api(c, h, nrhs, cur);
+    }
     bool conv = true;
     double worst = 0;
     for (int q = 0; q < nrhs; ++q) {
@@ -3834,6 +3907,18 @@ int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, 
     if (!conv) return fail(c, PMCHWT_ERR_NOT_CONVERGED, "GMRES reached max_iter");
     return PMCHWT_OK;
   });
+}
+
+int pmchwt_solve(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs,
+                 const pmchwt_solver_opts* o, pmchwt_complex* cur, pmchwt_solve_stats* st) {
+  return solve_common(c, dirs, pols, nrhs, o, cur, nullptr, nullptr, st);
+}
+
+int pmchwt_solve_device(pmchwt_ctx* c, const double* dirs, const pmchwt_complex* pols, int32_t nrhs,
+                        const pmchwt_solver_opts* o, pmchwt_complex* currents_dev, pmchwt_solve_stats* st,
+                        void* hip_stream) {
+  if (!currents_dev) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+  return solve_common(c, dirs, pols, nrhs, o, nullptr, currents_dev, hip_stream, st);
 }
 
 // Far field of nrhs current vectors (device, internal layout) at nobs
@@ -3855,6 +3940,24 @@ void far_field_dev(pmchwt_ctx* c, const double* x, int nrhs, const double* obs, 
                      wp.as<double>(), c->stream);
   }
   HIPCHK(hipGetLastError());
+}
+
+int pmchwt_far_field_device(pmchwt_ctx* c, const pmchwt_complex* currents_dev, int32_t nrhs, const double* obs_dev,
+                            int32_t nobs, pmchwt_complex* F_dev, void* hip_stream) {
+  return guarded(c, [&]() -> int {
+    if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
+    if (nrhs <= 0 || nobs <= 0 || !currents_dev || !obs_dev || !F_dev)
+      return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
+    upload_geometry(c);
+    const int32_t* soff = scat_offsets(c);
+    DBuf dx = dalloc_c<double>(c, size_t(2 * vlen(c) * nrhs));
+    order_before_ctx(c, hip_stream);
+    launch_layout(reinterpret_cast<const double*>(currents_dev), dx.as<double>(), nrhs, int(c->E_tot), soff,
+                  int(c->sc.size()), true, c->stream);
+    far_field_dev(c, dx.as<double>(), nrhs, obs_dev, nobs, reinterpret_cast<double*>(F_dev));
+    order_after_ctx(c, hip_stream);
+    return PMCHWT_OK;
+  });
 }
 
 int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, const double* obs, int32_t nobs,

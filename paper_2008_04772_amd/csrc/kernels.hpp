@@ -349,6 +349,10 @@ void launch_mfma_pmchwt(const float* S, const float* C, int64_t ld, int rows, in
 void launch_mfma_comb(const float* C, const float* S1, const float* S2, int64_t ld, int rows, int cols,
                       const double* xD, const double* xN, double* yD, double* yN, int nrhs, int64_t vstride, float* BD,
                       float* BN, hipStream_t st);
+// API layout (scatterer-major [D_m ; N_m]) <-> internal layout ([D ; N] over
+// the union) of nrhs complex vectors on the device; soff: nsc + 1 edge offsets
+void launch_layout(const double* in, double* out, int nrhs, int E, const int32_t* soff, int nsc, bool to_internal,
+                   hipStream_t st);
 // Block-sparse rows of dense BSR_T x BSR_T FP32 tiles (the sparse operators
 // of the preconditioner, for products with many right-hand sides): row tile
 // bi holds tiles bptr[bi] .. bptr[bi+1] at column tiles bcol[t]; tiles of a

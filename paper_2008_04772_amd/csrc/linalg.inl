@@ -1379,6 +1379,40 @@ void launch_finish_step(const double* w, int64_t wstride, double* v, int64_t vst
                      S2, active, h1p, h2p, S1, nvec, nrhs, fin, flags, seq);
 }
 
+// API layout (scatterer-major [D_m ; N_m] per right-hand side, complex) <->
+// internal layout ([D ; N] over the union): one thread per (rhs, component,
+// union edge); soff: the scatterers' edge offsets (nsc + 1 entries, last E).
+__global__ void k_layout(const double* __restrict__ in, double* __restrict__ out, int nrhs, int E,
+                         const int32_t* __restrict__ soff, int nsc, int to_internal) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = 2 * int64_t(E);
+  if (t >= per * nrhs) return;
+  const int64_t r = t / per;
+  const int rem = int(t - r * per), comp = rem / E, e = rem - comp * E;
+  int lo = 0, hi = nsc;  // the last scatterer whose first edge is <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (soff[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int o = soff[lo], Em = soff[lo + 1] - o;
+  const int64_t ki = r * per + int64_t(comp) * E + e;
+  const int64_t ka = r * per + 2 * int64_t(o) + int64_t(comp) * Em + (e - o);
+  const int64_t src = to_internal ? ka : ki, dst = to_internal ? ki : ka;
+  out[2 * dst] = in[2 * src];
+  out[2 * dst + 1] = in[2 * src + 1];
+}
+
+void launch_layout(const double* in, double* out, int nrhs, int E, const int32_t* soff, int nsc, bool to_internal,
+                   hipStream_t st) {
+  const int64_t n = 2 * int64_t(E) * nrhs;
+  if (n > 0)
+    hipLaunchKernelGGL(k_layout, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, in, out, nrhs, E, soff, nsc,
+                       int(to_internal));
+}
+
 // y = a y + b x  (complex vectors, real scalars)
 __global__ void k_axpby(double* y, const double* x, int64_t stride, int n, double a, double b) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
