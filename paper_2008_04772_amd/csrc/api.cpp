@@ -308,7 +308,8 @@ struct pmchwt_ctx {
     DBuf e_row, e_col, e_iptr, e_item;
     int64_t e_nnz = 0;
   } sing;
-  DBuf free_slots;  // pass-1 output of the matrix-free FP64 product
+  DBuf free_slots;  // per-slot sums of the matrix-free FP64 product
+  DBuf free_part;   // its regular pairs' partial sums by tile
   bool cells_valid = false;
   CellDev cells;
   std::vector<std::pair<int, int>> slabs;
@@ -2483,6 +2484,8 @@ void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_
   const int64_t vs = vlen(c);
   const size_t need = size_t(nrhs) * 3 * size_t(c->F_tot) * 4;
   if (c->free_slots.bytes < need * 8) realloc_c<double>(c, c->free_slots, need);
+  const size_t need_part = size_t(free_part_doubles(c->F_tot, nrhs));
+  if (c->free_part.bytes < need_part * 8) realloc_c<double>(c, c->free_part, need_part);
   AsmParams<double> p = asm_params<double>(c);
   p.q_near = c->optA.q_near;
   p.q_medium = c->optA.q_medium;
@@ -2502,7 +2505,7 @@ void apply_A_free(pmchwt_ctx* c, const double* x, double* y, int nrhs, bool use_
   f.y = y;
   {
     LazyTimer t(c, true);
-    launch_free_apply(p, f, c->stream);
+    launch_free_apply(p, f, c->free_part.as<double>(), c->stream);
     HIPCHK(hipGetLastError());
     t.stop(&c->prof.ms_free_apply);
   }
@@ -3942,6 +3945,17 @@ void far_field_dev(pmchwt_ctx* c, const double* x, int nrhs, const double* obs, 
   HIPCHK(hipGetLastError());
 }
 
+// Far field of nrhs >= FAR_MFMA_MIN_RHS current vectors at nh directions and
+// their antipodes (F_out: 2 nh directions per rhs, the antipodes second).
+void far_field_pair_dev(pmchwt_ctx* c, const double* x, int nrhs, const double* obs, int nh, double* F_out) {
+  const FarMfmaPlan fp = far_pair_plan(c->F_tot, nrhs, nh);
+  DBuf wy = dalloc_c<double>(c, 4 * size_t(fp.npts)), wj = dalloc_c<double>(c, 12 * size_t(fp.npts) * nrhs),
+       wb = dalloc_c<double>(c, size_t(fp.n_B)), wp = dalloc_c<double>(c, size_t(fp.n_part));
+  launch_far_field_pair(asm_params<double>(c), x, c->E_tot, nrhs, c->k_ext, obs, nh, F_out, fp, wy.as<double>(),
+                        wj.as<double>(), wb.as<double>(), wp.as<double>(), c->stream);
+  HIPCHK(hipGetLastError());
+}
+
 int pmchwt_far_field_device(pmchwt_ctx* c, const pmchwt_complex* currents_dev, int32_t nrhs, const double* obs_dev,
                             int32_t nobs, pmchwt_complex* F_dev, void* hip_stream) {
   return guarded(c, [&]() -> int {
@@ -4075,25 +4089,36 @@ int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs
     if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
     if (nrhs <= 0 || !cur || !dirs || !pols || !sext || !ssca) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
     upload_geometry(c);
+    // sigma_sca: Gauss-Legendre in cos(theta) x uniform in phi.  The grid is
+    // closed under xh -> -xh (symmetric nodes and weights, an even number of
+    // phi nodes), so with the matrix cores the far field is formed for the
+    // upper half (the nodes of the second half of [0, 1]) and the antipodes.
     const int nth = 64, nph = 128, nobs = nth * nph;
+    const bool pairs = nrhs >= FAR_MFMA_MIN_RHS;
     std::vector<double> ct, wt;
     gauss_legendre01(nth, ct, wt);
     std::vector<double> obs(3 * size_t(nobs)), w(nobs);
-    for (int a = 0; a < nth; ++a)
+    const int a0 = pairs ? nth / 2 : 0, nh = (nth - a0) * nph;
+    for (int a = a0; a < nth; ++a)
       for (int b = 0; b < nph; ++b) {
         const double cz = 2.0 * ct[a] - 1.0, sz = std::sqrt(std::max(0.0, 1.0 - cz * cz));
         const double ph = 2.0 * M_PI * b / nph;
-        const int o = a * nph + b;
+        const int o = (a - a0) * nph + b;
         obs[3 * o] = sz * std::cos(ph);
         obs[3 * o + 1] = sz * std::sin(ph);
         obs[3 * o + 2] = cz;
         w[o] = 2.0 * wt[a] * (2.0 * M_PI / nph);
+        if (pairs) w[nh + o] = w[o];
       }
+    obs.resize(3 * size_t(nh));
     std::vector<double> h;
     to_internal(c, cur, nrhs, h);
     DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs),
          dsig = dalloc_c<double>(c, nrhs);
-    far_field_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nobs, dF.as<double>());
+    if (pairs)
+      far_field_pair_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nh, dF.as<double>());
+    else
+      far_field_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nobs, dF.as<double>());
     launch_sigma_sca(dF.as<double>(), nobs, nrhs, dw.as<double>(), dsig.as<double>(), c->stream);
     std::vector<double> hd(dirs, dirs + 3 * size_t(nrhs));
     DBuf dd = upload(c, hd), dFd = dalloc_c<double>(c, 6 * size_t(nrhs) * nrhs);

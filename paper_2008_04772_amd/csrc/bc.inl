@@ -769,6 +769,26 @@ __global__ __launch_bounds__(FAR_BLOCK) void k_far_sum(const double* ypts, const
   for (int c = 0; c < 12; ++c) out[int64_t(c) * nobs] = V[c];
 }
 
+// F(xh) = -(i / 4 pi) [k xh x V_D + V_N - xh (xh . V_N)] from the sums V (V_D
+// then V_N, (re, im) per component) into out (3 complex)
+__device__ __forceinline__ void far_from_sums(const double (&xh)[3], const double (&V)[12], double k,
+                                              double* __restrict__ out) {
+  const double* VD = V;
+  const double* VN = V + 6;
+  const double xv_re = xh[0] * VN[0] + xh[1] * VN[2] + xh[2] * VN[4];
+  const double xv_im = xh[0] * VN[1] + xh[1] * VN[3] + xh[2] * VN[5];
+  for (int d = 0; d < 3; ++d) {
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    const double cr = xh[d1] * VD[2 * d2] - xh[d2] * VD[2 * d1];
+    const double ci = xh[d1] * VD[2 * d2 + 1] - xh[d2] * VD[2 * d1 + 1];
+    const double b_re = k * cr + VN[2 * d] - xh[d] * xv_re;
+    const double b_im = k * ci + VN[2 * d + 1] - xh[d] * xv_im;
+    // -(i/4pi)(b_re + i b_im) = (b_im - i b_re)/(4pi)
+    out[2 * d] = b_im * INV_FOUR_PI;
+    out[2 * d + 1] = -b_re * INV_FOUR_PI;
+  }
+}
+
 __global__ void k_far_finish(const double* part, int nseg, double k, const double* obs, int nobs, int nrhs,
                              double* Fout) {
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -780,21 +800,39 @@ __global__ void k_far_finish(const double* part, int nseg, double k, const doubl
     const double* pp = part + (int64_t(r) * nseg + sg) * 12 * int64_t(nobs) + o;
     for (int c = 0; c < 12; ++c) V[c] += pp[int64_t(c) * nobs];
   }
-  const double* VD = V;
-  const double* VN = V + 6;
-  const double xv_re = xh[0] * VN[0] + xh[1] * VN[2] + xh[2] * VN[4];
-  const double xv_im = xh[0] * VN[1] + xh[1] * VN[3] + xh[2] * VN[5];
-  double* out = Fout + 6 * (int64_t(r) * nobs + o);
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-    const double cr = xh[d1] * VD[2 * d2] - xh[d2] * VD[2 * d1];
-    const double ci = xh[d1] * VD[2 * d2 + 1] - xh[d2] * VD[2 * d1 + 1];
-    const double b_re = k * cr + VN[2 * d] - xh[d] * xv_re;
-    const double b_im = k * ci + VN[2 * d + 1] - xh[d] * xv_im;
-    // -(i/4pi)(b_re + i b_im) = (b_im - i b_re)/(4pi)
-    out[2 * d] = b_im * INV_FOUR_PI;
-    out[2 * d + 1] = -b_re * INV_FOUR_PI;
+  far_from_sums(xh, V, k, Fout + 6 * (int64_t(r) * nobs + o));
+}
+
+// Antipodal pairs: part[((r nseg + s) 24 + 4 comp + 2 trig + part) nh + o]
+// holds the K split s of sum_p {cos, sin}(-k xh_o . y_p) {Re, Im} J_comp(y_p).
+// With phase cos + i sin at xh and cos - i sin at -xh:
+//   V(xh)  = (cc - ss) + i (cs + sc),   V(-xh) = (cc + ss) + i (cs - sc)
+// (cc = cos Re J, cs = cos Im J, sc = sin Re J, ss = sin Im J).  Writes F at
+// direction o and nh + o of the 2 nh per rhs.
+__global__ void k_far_finish_pair(const double* part, int nseg, double k, const double* obs, int nh, int nrhs,
+                                  double* Fout) {
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= int64_t(nh) * nrhs) return;
+  const int o = int(tid % nh), r = int(tid / nh);
+  double P[24];
+  for (int c = 0; c < 24; ++c) P[c] = 0.0;
+  for (int sg = 0; sg < nseg; ++sg) {
+    const double* pp = part + (int64_t(r) * nseg + sg) * 24 * int64_t(nh) + o;
+    for (int c = 0; c < 24; ++c) P[c] += pp[int64_t(c) * nh];
   }
+  double Vp[12], Vm[12];
+  for (int c = 0; c < 6; ++c) {
+    const double cc = P[4 * c], cs = P[4 * c + 1], sc = P[4 * c + 2], ss = P[4 * c + 3];
+    Vp[2 * c] = cc - ss;
+    Vp[2 * c + 1] = cs + sc;
+    Vm[2 * c] = cc + ss;
+    Vm[2 * c + 1] = cs - sc;
+  }
+  const double xp[3] = {obs[3 * o], obs[3 * o + 1], obs[3 * o + 2]};
+  const double xm[3] = {-xp[0], -xp[1], -xp[2]};
+  double* out = Fout + 6 * (int64_t(r) * 2 * nh + o);
+  far_from_sums(xp, Vp, k, out);
+  far_from_sums(xm, Vm, k, out + 6 * int64_t(nh));
 }
 
 FarPlan far_field_plan(int F, int nrhs, int nobs) {

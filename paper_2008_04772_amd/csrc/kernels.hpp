@@ -98,7 +98,9 @@ struct FreeJob {
   const int32_t* edge_slots;   // 2 per union edge: slot 3t+a of T+ and of T-
   double* y;
 };
-void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t st);
+// part: free_part_doubles(F, nrhs) doubles of partial sums (regular pairs by tile)
+int64_t free_part_doubles(int F, int nrhs);
+void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, double* part, hipStream_t st);
 
 // Sparse approximate inverse of a mass matrix M (one scatterer, n x n): row i
 // on the ball of columns within `hops` steps of M's sparsity graph, by a
@@ -519,13 +521,22 @@ FarPlan far_field_plan(int F, int nrhs, int nobs);
 // ways (partial sums part, n_part doubles).
 struct FarMfmaPlan {
   int64_t npts = 0;
-  int Kt = 0, Nr = 0, nsplit = 1;
+  int Kt = 0, Nr = 0, nsplit = 1, rows = 0;
   int64_t n_B = 0, n_part = 0;
 };
 FarMfmaPlan far_mfma_plan(int F, int nrhs, int nobs);
 void launch_far_field_mfma(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
                            const double* obs, int nobs, double* F_out, const FarMfmaPlan& plan, double* ypts,
                            double* J, double* B, double* part, hipStream_t st);
+// The same for nh directions and their antipodes (F_out: 2 nh directions per
+// rhs, direction nh + o = -obs[o]): the cosine and sine sums of the currents
+// are shared by a direction and its antipode, so the matrix product has half
+// the K extent (K = rule points, the currents' real and imaginary parts as
+// separate columns).
+FarMfmaPlan far_pair_plan(int F, int nrhs, int nh);
+void launch_far_field_pair(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
+                           const double* obs, int nh, double* F_out, const FarMfmaPlan& plan, double* ypts, double* J,
+                           double* B, double* part, hipStream_t st);
 FarPlan far_field_plan_capped(int F, int nrhs, int nobs, int64_t max_part);
 // Total electric field at points (region per point, rule-point data and the
 // sums; ypts: 4 doubles per rule point, J: near_j_doubles() per rhs and rule

@@ -36,6 +36,7 @@ struct Mem2Src {
   const double* B2;
   int K2;
   int64_t lda2;
+  static constexpr bool A_PAIRS = false;
   __device__ __forceinline__ int ntiles() const { return (K1 + K2) / M64_BK; }
   // thread t: row t / 2, eight doubles from column 8 (t % 2) of the tile
   __device__ __forceinline__ void load(int kt, int m0, int n0, int rows, int Nr, int t, double (&ra)[8],
@@ -74,6 +75,7 @@ struct FarSrc {
   int Kt, nobs;
   double k;
   int nkt, nsplit;
+  static constexpr bool A_PAIRS = false;
   __device__ __forceinline__ int kt0() const { return int(int64_t(blockIdx.z) * nkt / nsplit); }
   __device__ __forceinline__ int ntiles() const { return int(int64_t(blockIdx.z + 1) * nkt / nsplit) - kt0(); }
   __device__ __forceinline__ void load(int kt, int m0, int n0, int rows, int Nr, int t, double (&ra)[8],
@@ -91,6 +93,48 @@ struct FarSrc {
       ra[2 * q + 1] = sn;
     }
     const double2* pb = reinterpret_cast<const double2*>(B + int64_t(c) * Kt + k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 b = pb[q];
+      rb[2 * q] = b.x;
+      rb[2 * q + 1] = b.y;
+    }
+  }
+};
+
+// Antipodal pairs: a 128-row tile holds 64 directions, their cosine rows
+// (0..63) then their sine rows (64..127), of -k xh_o . y_p; K runs over the
+// rule points (K tile = 16 points) and B (Nr x Kt) holds the real and the
+// imaginary part of each complex current column as two real columns.  Thread
+// t computes the four points 4 (t % 4) + j of direction t / 4 once and
+// supplies both rows (A_PAIRS: ra[2 j] = cos, ra[2 j + 1] = sin).
+struct FarPairSrc {
+  const double* obs;   // 3 per direction
+  const double* ypts;  // 4 per rule point
+  const double* B;     // Nr x Kt
+  int64_t npts;
+  int Kt, nh;
+  double k;
+  int nkt, nsplit;
+  static constexpr bool A_PAIRS = true;
+  __device__ __forceinline__ int kt0() const { return int(int64_t(blockIdx.z) * nkt / nsplit); }
+  __device__ __forceinline__ int ntiles() const { return int(int64_t(blockIdx.z + 1) * nkt / nsplit) - kt0(); }
+  __device__ __forceinline__ void load(int kt, int m0, int n0, int, int Nr, int t, double (&ra)[8],
+                                       double (&rb)[8]) const {
+    const int kb = (kt0() + kt) * M64_BK;
+    const int o = min((m0 >> 1) + (t >> 2), nh - 1);
+    const double xh0 = -k * obs[3 * o], xh1 = -k * obs[3 * o + 1], xh2 = -k * obs[3 * o + 2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t p = min<int64_t>(kb + 4 * (t & 3) + j, npts - 1);  // padding points meet zero rows of B
+      const double* y = ypts + 4 * p;
+      double sn, cs;
+      sincos_taylor(xh0 * y[0] + xh1 * y[1] + xh2 * y[2], &sn, &cs);
+      ra[2 * j] = cs;
+      ra[2 * j + 1] = sn;
+    }
+    const int c = min(n0 + (t >> 1), Nr - 1);
+    const double2* pb = reinterpret_cast<const double2*>(B + int64_t(c) * Kt + kb + 8 * (t & 1));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double2 b = pb[q];
@@ -132,6 +176,20 @@ struct FarOut {
     part[((int64_t(r) * nseg + s) * 12 + 2 * comp + (n & 1)) * nobs + o] = v;
   }
 };
+// Antipodal-pair partial sums of K split s: tile row r -> direction
+// 64 (r / 128) + r % 64, trig = (r % 128) / 64 (cos, sin); real column n ->
+// rhs, component and part (Re, Im J) at
+// part[((rhs nseg + s) 24 + 4 comp + 2 trig + part) nh + o].
+struct FarPairOut {
+  double* part;
+  int nh, nseg;
+  __device__ __forceinline__ void put(int r, int n, int s, double v) const {
+    const int rl = r & 127, o = ((r >> 7) << 6) + (rl & 63);
+    if (o >= nh) return;
+    const int cc = n >> 1, rr = cc / 6, comp = cc - 6 * rr;
+    part[((int64_t(rr) * nseg + s) * 24 + 4 * comp + 2 * (rl >> 6) + (n & 1)) * nh + o] = v;
+  }
+};
 
 // out(rows x Nr) = sum over K of Ahat Bhat; blockIdx.z picks the pair
 // (s0, o0) for z = 0, else (s1, o1): two products in one launch, or (with
@@ -158,7 +216,10 @@ __global__ __launch_bounds__(256, 2) void k_mfma64(Src s0, Out o0, Src s1, Out o
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      As[buf][(sk + q) * M64_LD + srow] = ra[q];
+      if constexpr (Src::A_PAIRS)  // row t / 4 (cos) and 64 + t / 4 (sin), K column 4 (t % 4) + q / 2
+        As[buf][(4 * (t & 3) + (q >> 1)) * M64_LD + (q & 1) * 64 + (t >> 2)] = ra[q];
+      else
+        As[buf][(sk + q) * M64_LD + srow] = ra[q];
       Bs[buf][(sk + q) * M64_LD + srow] = rb[q];
     }
   };
@@ -295,6 +356,26 @@ __global__ void k_far_bhat(const double* __restrict__ J, int64_t npts, int Kt, i
   B[r1 + 1] = br;
 }
 
+// K splits of a far-field product: the first count (at least 32 K tiles per
+// split) whose workgroups fill the whole rounds of the chip's 512 slots (two
+// workgroups per CU) to at least 85 %, else the one that fills them best
+int far_nsplit(int64_t tiles, int nkt) {
+  constexpr int64_t slots = 512;
+  const int64_t cap = std::max<int64_t>(1, nkt / 32);
+  int64_t best = 1;
+  double best_eff = 0.0;
+  for (int64_t ns = 1; ns <= cap; ++ns) {
+    const int64_t w = tiles * ns, rounds = (w + slots - 1) / slots;
+    const double eff = double(w) / double(rounds * slots);
+    if (eff > best_eff) {
+      best_eff = eff;
+      best = ns;
+    }
+    if (eff >= 0.85) break;
+  }
+  return int(best);
+}
+
 FarMfmaPlan far_mfma_plan(int F, int nrhs, int nobs) {
   FarMfmaPlan p;
   p.npts = int64_t(F) * 6;
@@ -302,8 +383,8 @@ FarMfmaPlan far_mfma_plan(int F, int nrhs, int nobs) {
   p.Nr = 12 * nrhs;
   const int64_t tiles = int64_t((p.Nr + M64_BN - 1) / M64_BN) * ((nobs + M64_BM - 1) / M64_BM);
   const int nkt = p.Kt / M64_BK;
-  // about two workgroups per CU over the chip, at least 32 K tiles per split
-  p.nsplit = int(std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, nkt / 32)));
+  p.nsplit = far_nsplit(tiles, nkt);
+  p.rows = nobs;
   p.n_B = int64_t(p.Nr) * p.Kt;
   p.n_part = int64_t(nrhs) * p.nsplit * 12 * nobs;
   return p;
@@ -325,6 +406,61 @@ void launch_far_field_mfma(const AsmParams<double>& geo, const double* x, int64_
   const int64_t n = int64_t(nobs) * nrhs;
   hipLaunchKernelGGL(k_far_finish, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, part, plan.nsplit, k, obs, nobs,
                      nrhs, F_out);
+}
+
+// ---------------------------------------------------------------------------
+// Far field at nh directions and their antipodes: one FP64 GEMM of the
+// cosine and sine rows (2 per direction) against the real and imaginary
+// parts of the weighted currents, K = rule points, then k_far_finish_pair.
+// ---------------------------------------------------------------------------
+
+// B[12 r + c][p] = J[r][p][c] (c = 2 comp + {Re, Im}), zero for
+// npts <= p < Kt: per rhs a transpose of the npts x 12 current table, 64
+// points per workgroup through LDS (both sides coalesced)
+__global__ __launch_bounds__(256) void k_far_bsplit(const double* __restrict__ J, int64_t npts, int Kt,
+                                                    double* __restrict__ B) {
+  __shared__ double s[64 * 13];  // point q at 13 q (padded row)
+  const int64_t p0 = int64_t(blockIdx.x) * 64;
+  const int r = blockIdx.y;
+  const double* Jr = J + 12 * (int64_t(r) * npts + p0);
+  for (int i = threadIdx.x; i < 64 * 12; i += 256) s[13 * (i / 12) + i % 12] = p0 + i / 12 < npts ? Jr[i] : 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 12; i += 256) {
+    const int c = i >> 6, q = i & 63;
+    if (p0 + q < Kt) B[(12 * int64_t(r) + c) * Kt + p0 + q] = s[13 * q + c];
+  }
+}
+
+FarMfmaPlan far_pair_plan(int F, int nrhs, int nh) {
+  FarMfmaPlan p;
+  p.npts = int64_t(F) * 6;
+  p.Kt = int((p.npts + M64_BK - 1) / M64_BK * M64_BK);
+  p.Nr = 12 * nrhs;
+  p.rows = M64_BM * ((nh + M64_BM / 2 - 1) / (M64_BM / 2));
+  const int64_t tiles = int64_t((p.Nr + M64_BN - 1) / M64_BN) * (p.rows / M64_BM);
+  const int nkt = p.Kt / M64_BK;
+  p.nsplit = far_nsplit(tiles, nkt);
+  p.n_B = int64_t(p.Nr) * p.Kt;
+  p.n_part = int64_t(nrhs) * p.nsplit * 24 * nh;
+  return p;
+}
+
+void launch_far_field_pair(const AsmParams<double>& geo, const double* x, int64_t E_tot, int nrhs, double k,
+                           const double* obs, int nh, double* F_out, const FarMfmaPlan& plan, double* ypts, double* J,
+                           double* B, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_far_points, dim3(unsigned((plan.npts + 255) / 256)), dim3(256), 0, st, geo, x, E_tot, nrhs,
+                     plan.npts, ypts, J);
+  hipLaunchKernelGGL(k_far_bsplit, dim3(unsigned((plan.Kt + 63) / 64), unsigned(nrhs)), dim3(256), 0, st, J,
+                     plan.npts, plan.Kt, B);
+  const int nkt = plan.Kt / M64_BK;
+  const dim3 grid(unsigned((plan.Nr + M64_BN - 1) / M64_BN), unsigned(plan.rows / M64_BM), unsigned(plan.nsplit));
+  const FarPairSrc src{obs, ypts, B, plan.npts, plan.Kt, nh, k, nkt, plan.nsplit};
+  const FarPairOut out{part, nh, plan.nsplit};
+  hipLaunchKernelGGL((k_mfma64<FarPairSrc, FarPairOut>), grid, dim3(256), 0, st, src, out, src, out, plan.rows,
+                     plan.Nr);
+  const int64_t n = int64_t(nh) * nrhs;
+  hipLaunchKernelGGL(k_far_finish_pair, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, part, plan.nsplit, k, obs,
+                     nh, nrhs, F_out);
 }
 
 }  // namespace pmchwt

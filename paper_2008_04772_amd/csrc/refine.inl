@@ -8,260 +8,323 @@
 // kernel keeps in FP64), and contracted with x on the fly, so the product is
 // that of the FP64 Galerkin matrix without storing it.
 //
-// Pass 1: one workgroup per test triangle t1 (and chunk of RC right-hand
-// sides).  Its threads stride over the trial triangles; for each disjoint
-// pair and each wavenumber they accumulate the kernel moments, contract them
-// against the three RWG functions of either triangle and add
-//   yD[a] += C xD[b] + S/k xN[b],   yN[a] += C xN[b] - k S xD[b]
-// for every local test basis a of t1 (exterior k_e on every pair, interior
-// k_m on pairs of one scatterer).  Pairs that share a vertex read their
-// local blocks from the singular kernel's FP64 output.  The workgroup sums
-// its threads' values in a fixed order and writes one (yD, yN) per slot
-// (rhs, t1, a).  Pass 2 adds the two slots of every edge (T+ and T- carry the
-// RWG signs already).
+// The Galerkin blocks of S and C are symmetric (swapping the test and the
+// trial function swaps the two integration variables; for C both the
+// gradient and the triple product change sign), and the regular pairs' rule
+// is the same tensor rule in either order.  So every unordered regular pair
+// is integrated once and used both ways:
+//   pass 1 (k_free_tiles): upper tiles (I, J) of 64 x 64 triangles; wave w
+//   takes test triangles 16 w .. 16 w + 15 of tile I one at a time against
+//   the 64 trial triangles of tile J (one per lane; on diagonal tiles only
+//   the pairs above the diagonal).  For each pair and wavenumber the kernel
+//   moments give the 3 x 3 blocks S_ab, C_ab, which add
+//     yD[a] += C xD[b] + S/k xN[b],   yN[a] += C xN[b] - k S xD[b]
+//   to the test triangle's bases a (summed over the wave) and the same with
+//   a and b exchanged to the trial triangle's bases b (summed per lane over
+//   the wave's test triangles, then over the four wavefronts in order).
+//   The sums of tile I's triangles from tile J land at part[I][J], those of
+//   tile J's triangles at part[J][I] (diagonal tiles: row plus column sums).
+//   pass 2 (k_free_sing_sum): per triangle, its vertex-sharing pairs from
+//   the singular kernel's FP64 blocks, plus the partial sums part[K][0..nt)
+//   in order, into one (yD, yN) per slot (rhs, t, a).
+//   pass 3 (k_free_combine): the two slots of every edge (T+ and T- carry
+//   the RWG signs already).
+// Exterior operators (k_e) act on every pair, interior ones (k_m) on pairs
+// of one scatterer.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace pmchwt {
 
-constexpr int FREE_THREADS = 256;
+constexpr int FREE_TT = 64;                       // triangles per tile side
+constexpr int FREE_WAVES = 4;                     // wavefronts per workgroup
+constexpr int FREE_STEPS = FREE_TT / FREE_WAVES;  // test triangles per wavefront
 
+// sum over the 64 lanes (DPP within rows of 16, then across rows); every
+// lane gets it, in the same order on every lane
 __device__ __forceinline__ double wave_sum_free(double v) {
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, WAVE);
+  v += __shfl_xor(v, 32, WAVE);
   return v;
 }
 
-// acc[r][a][0] = yD, acc[r][a][1] = yN (complex) += C x + S factors
-template <int RC>
-__device__ __forceinline__ void apply_block(cplx<double> (&acc)[RC][3][2], int a, const cplx<double>& S,
-                                            const cplx<double>& C, const cplx<double>& f1, const cplx<double>& f2,
-                                            const cplx<double> (&xD)[RC], const cplx<double> (&xN)[RC]) {
-  const cplx<double> s1 = cmul(S, f1), s2 = cmul(S, f2);
-#pragma unroll
-  for (int r = 0; r < RC; ++r) {
-    const cplx<double> a1 = cmul(C, xD[r]), a2 = cmul(s1, xN[r]);
-    const cplx<double> b1 = cmul(C, xN[r]), b2 = cmul(s2, xD[r]);
-    acc[r][a][0].re += a1.re + a2.re;
-    acc[r][a][0].im += a1.im + a2.im;
-    acc[r][a][1].re += b1.re + b2.re;
-    acc[r][a][1].im += b1.im + b2.im;
-  }
+// row-major index t of the upper tiles (I <= J) of an nt x nt grid -> (I, J);
+// row I starts at I nt - I (I - 1) / 2
+__device__ __forceinline__ void upper_tile(int t, int nt, int& I, int& J) {
+  const double b = 2.0 * nt + 1.0;
+  int i = int((b - sqrt(b * b - 8.0 * double(t))) * 0.5);
+  i = max(0, min(i, nt - 1));
+  while (i > 0 && i * nt - i * (i - 1) / 2 > t) --i;
+  while (i + 1 < nt && (i + 1) * nt - (i + 1) * i / 2 <= t) ++i;
+  I = i;
+  J = i + (t - (i * nt - i * (i - 1) / 2));
 }
 
-template <int RC>
-__global__ __launch_bounds__(FREE_THREADS, 2) void k_free_apply(AsmParams<double> p, FreeJob f) {
-  __shared__ double red[FREE_THREADS / WAVE][RC * 12];
-  __shared__ double s_t1[3][4];  // per test basis a of t1: alpha, w (RT0 field alpha x - w)
-  __shared__ double s_x[14][4];  // points of every triangle rule on t1 (relative to its centroid), weight x A1
-  const int t1 = blockIdx.x;
-  const int r0 = blockIdx.y * RC;
-  const int F = p.F;
-  const int s1 = p.tscat[t1];
-  double c1[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) c1[d] = p.tcen[d * F + t1];
-  int va[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) va[k] = p.tvid[k * F + t1];
-  const double A1 = p.tarea[t1], d1 = p.tdiam2[t1];
-  if (threadIdx.x < 3) {
-    const int a = threadIdx.x;
-    const double al = p.tsgn[a * F + t1] / (2.0 * A1);
-    s_t1[a][0] = al;
-    for (int d = 0; d < 3; ++d) s_t1[a][1 + d] = al * (p.tv[(3 * a + d) * F + t1] - c1[d]);
-  } else if (threadIdx.x >= 32 && threadIdx.x < 46) {
-    const int i = threadIdx.x - 32;
+// (yD, yN) of one basis += C (xD, xN) + S (g1 xN, g2 xD) into o[0..3]
+__device__ __forceinline__ void free_add(double* o, const cplx<double>& S, const cplx<double>& C,
+                                         const cplx<double>& g1, const cplx<double>& g2, const cplx<double>& xD,
+                                         const cplx<double>& xN) {
+  const cplx<double> a1 = cmul(C, xD), a2 = cmul(S, cmul(g1, xN));
+  const cplx<double> b1 = cmul(C, xN), b2 = cmul(S, cmul(g2, xD));
+  o[0] += a1.re + a2.re;
+  o[1] += a1.im + a2.im;
+  o[2] += b1.re + b2.re;
+  o[3] += b1.im + b2.im;
+}
+
+// grid (upper tiles, nrhs); part: [rhs][K][L][64][12] (12 = 3 bases x yD, yN complex)
+__global__ __launch_bounds__(FREE_WAVES * WAVE, 2) void k_free_tiles(AsmParams<double> p, FreeJob f, int nt,
+                                                                     double* __restrict__ part) {
+  __shared__ double s_x[FREE_TT][14][4];              // test rule points (relative to the centroid), weight x area
+  __shared__ double s_a[FREE_TT][3][4];               // test bases: alpha, alpha (v_a - c1)
+  __shared__ double s_c[FREE_TT][4];                  // centroid, diameter^2
+  __shared__ int s_v[FREE_TT][4];                     // vertex ids, scatterer
+  __shared__ double s_row[FREE_TT][12];               // test triangles' sums
+  __shared__ double s_col[FREE_WAVES][FREE_TT][12];   // trial triangles' sums per wavefront
+  __shared__ double s_tv2[FREE_TT][3][4];             // trial triangles: vertices, alpha of each basis
+  __shared__ int s_e2[FREE_TT][3];                    // trial triangles' basis edges
+  int I, J;
+  upper_tile(blockIdx.x, nt, I, J);
+  const int r = blockIdx.y;
+  const int F = p.F, E = f.E_tot;
+  const double* xr = f.x + 2 * int64_t(r) * f.vs;
+  const double* ur = (f.xi ? f.xi : f.x) + 2 * int64_t(r) * f.vs;
+  // test tile data
+  for (int i = threadIdx.x; i < FREE_TT * 14; i += blockDim.x) {
+    const int lt = i / 14, q = i % 14, t1 = min(I * FREE_TT + lt, F - 1);
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = p.tcen[d * F + t1];
     for (int d = 0; d < 3; ++d) {
       double x = 0.0;
-      for (int k = 0; k < 3; ++k) x += c_rule_l[i][k] * (p.tv[(3 * k + d) * F + t1] - c1[d]);
-      s_x[i][d] = x;
+      for (int k = 0; k < 3; ++k) x += c_rule_l[q][k] * (p.tv[(3 * k + d) * F + t1] - c[d]);
+      s_x[lt][q][d] = x;
     }
-    s_x[i][3] = c_rule_w[i] * A1;
+    s_x[lt][q][3] = c_rule_w[q] * p.tarea[t1];
+  }
+  for (int i = threadIdx.x; i < FREE_TT * 3; i += blockDim.x) {
+    const int lt = i / 3, a = i % 3, t1 = min(I * FREE_TT + lt, F - 1);
+    const double al = p.tsgn[a * F + t1] / (2.0 * p.tarea[t1]);
+    s_a[lt][a][0] = al;
+    for (int d = 0; d < 3; ++d) s_a[lt][a][1 + d] = al * (p.tv[(3 * a + d) * F + t1] - p.tcen[d * F + t1]);
+  }
+  for (int i = threadIdx.x; i < FREE_WAVES * FREE_TT * 12; i += blockDim.x) (&s_col[0][0][0])[i] = 0.0;
+  for (int i = threadIdx.x; i < FREE_TT * 3; i += blockDim.x) {
+    const int lt = i / 3, b = i % 3, t2 = min(J * FREE_TT + lt, F - 1);
+    for (int d = 0; d < 3; ++d) s_tv2[lt][b][d] = p.tv[(3 * b + d) * F + t2];
+    s_tv2[lt][b][3] = p.tsgn[b * F + t2] / (2.0 * p.tarea[t2]);
+    s_e2[lt][b] = p.t2e[b * F + t2];
+  }
+  for (int lt = threadIdx.x; lt < FREE_TT; lt += blockDim.x) {
+    const int t1 = min(I * FREE_TT + lt, F - 1);
+    for (int d = 0; d < 3; ++d) s_c[lt][d] = p.tcen[d * F + t1];
+    s_c[lt][3] = p.tdiam2[t1];
+    for (int k = 0; k < 3; ++k) s_v[lt][k] = p.tvid[k * F + t1];
+    s_v[lt][3] = p.tscat[t1];
   }
   __syncthreads();
+
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int t2 = J * FREE_TT + lane;
+  const bool v2 = t2 < F;
+  const int t2c = v2 ? t2 : F - 1;
+  const double c2[3] = {p.tcen[t2c], p.tcen[F + t2c], p.tcen[2 * F + t2c]};
+  const double A2 = p.tarea[t2c], d2 = p.tdiam2[t2c];
+  const int vb0 = p.tvid[t2c], vb1 = p.tvid[F + t2c], vb2 = p.tvid[2 * F + t2c], s2 = p.tscat[t2c];
   const double ke = p.k_ext;
-  const double kir = p.k_int[2 * s1], kii = p.k_int[2 * s1 + 1];
-  // combination factors: 1/k and -k for the exterior and interior wavenumbers
-  const cplx<double> fe1 = {1.0 / ke, 0.0}, fe2 = {-ke, 0.0};
-  const double kim2 = kir * kir + kii * kii;
-  const cplx<double> fi1 = {kir / kim2, -kii / kim2}, fi2 = {-kir, -kii};
+  double* col = s_col[w][lane];  // this lane's trial triangle, summed over the wave's test triangles
 
-  cplx<double> acc[RC][3][2];
+  for (int st = 0; st < FREE_STEPS; ++st) {
+    const int lt1 = w * FREE_STEPS + st, t1 = I * FREE_TT + lt1;
+    double row[12];
 #pragma unroll
-  for (int r = 0; r < RC; ++r)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) acc[r][a][0] = acc[r][a][1] = {0.0, 0.0};
-  const int nr = min(RC, f.nrhs - r0);
-
-  // one wavenumber per sweep over the trial triangles: only one set of
-  // moments and the accumulators stay live
-  for (int kk = f.use_ext ? 0 : 1; kk < 2; ++kk) {
-    const double kr = kk == 0 ? ke : kir, ki = kk == 0 ? 0.0 : kii;
-    const bool decay = kk == 1 && kii != 0.0;
-    const double ik2 = 1.0 / (kr * kr + ki * ki);
-    const cplx<double> g1 = kk == 0 ? fe1 : fi1, g2 = kk == 0 ? fe2 : fi2;
-    const double* xin = (kk == 1 && f.xi) ? f.xi : f.x;
-    for (int t2 = threadIdx.x; t2 < F; t2 += FREE_THREADS) {
-      if (kk == 1 && p.tscat[t2] != s1) continue;  // interior operators: one scatterer
-      bool shared = false;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int vb = p.tvid[k * F + t2];
-        shared |= (vb == va[0]) | (vb == va[1]) | (vb == va[2]);
-      }
-      if (shared) continue;  // singular pair: read below from the FP64 blocks
-      const int cls = classify_pair(c1[0], c1[1], c1[2], p.tcen[t2], p.tcen[F + t2], p.tcen[2 * F + t2], d1,
-                                    p.tdiam2[t2]);
-      const int q = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
-      const int off = c_rule_off[q], n = c_rule_n[q];
+    for (int q = 0; q < 12; ++q) row[q] = 0.0;
+    bool live = v2 && t1 < F && (I != J || lane > lt1);
+    if (live) {
+      const int va0 = s_v[lt1][0], va1 = s_v[lt1][1], va2 = s_v[lt1][2];
+      const bool shared = vb0 == va0 || vb0 == va1 || vb0 == va2 || vb1 == va0 || vb1 == va1 || vb1 == va2 ||
+                          vb2 == va0 || vb2 == va1 || vb2 == va2;
+      live = !shared;  // vertex-sharing pairs: the singular kernel's FP64 blocks, in pass 2
+    }
+    if (live) {
+      const double c1[3] = {s_c[lt1][0], s_c[lt1][1], s_c[lt1][2]};
+      const int s1 = s_v[lt1][3];
+      const int cls = classify_pair(c1[0], c1[1], c1[2], c2[0], c2[1], c2[2], s_c[lt1][3], d2);
+      const int qr = cls == 0 ? p.q_near : (cls == 1 ? p.q_medium : p.q_far);
+      const int off = c_rule_off[qr], n = c_rule_n[qr];
       double P2[3][3];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) P2[k][d] = p.tv[(3 * k + d) * F + t2] - c1[d];
-      const double A2 = p.tarea[t2];
-      Moments<double> mm;
-      mm.zero();
+        for (int d = 0; d < 3; ++d) P2[k][d] = s_tv2[lane][k][d] - c1[d];
+      for (int kk = f.use_ext ? 0 : 1; kk < 2; ++kk) {
+        if (kk == 1 && s2 != s1) break;  // interior operators: one scatterer
+        const double kr = kk == 0 ? ke : p.k_int[2 * s1], ki = kk == 0 ? 0.0 : p.k_int[2 * s1 + 1];
+        const bool decay = kk == 1 && ki != 0.0;
+        const double ik2 = 1.0 / (kr * kr + ki * ki);
+        // combination factors 1/k and -k
+        const cplx<double> g1 = {kr * ik2, -ki * ik2}, g2 = {-kr, -ki};
+        const double* xin = kk == 0 ? xr : ur;
+        Moments<double> mm;
+        mm.zero();
 #pragma unroll 1
-      for (int a = 0; a < n; ++a) {
-        const double x[3] = {s_x[off + a][0], s_x[off + a][1], s_x[off + a][2]};
-        const double wa = s_x[off + a][3] * A2;
+        for (int a = 0; a < n; ++a) {
+          const double x[3] = {s_x[lt1][off + a][0], s_x[lt1][off + a][1], s_x[lt1][off + a][2]};
+          const double wa = s_x[lt1][off + a][3] * A2;
 #pragma unroll 1
-        for (int b = 0; b < n; ++b) {
-          double y[3];
-          const double lb0 = c_rule_l[off + b][0], lb1 = c_rule_l[off + b][1], lb2 = c_rule_l[off + b][2];
+          for (int b = 0; b < n; ++b) {
+            double y[3];
+            const double lb0 = c_rule_l[off + b][0], lb1 = c_rule_l[off + b][1], lb2 = c_rule_l[off + b][2];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
-          const double w = wa * c_rule_w[off + b];
-          const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          mm.add(helmholtz<double>(r2, kr, ki, decay, w), x, y, true);
+            for (int d = 0; d < 3; ++d) y[d] = lb0 * P2[0][d] + lb1 * P2[1][d] + lb2 * P2[2][d];
+            const double wgt = wa * c_rule_w[off + b];
+            const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+            mm.add(helmholtz<double>(dx * dx + dy * dy + dz * dz, kr, ki, decay, wgt), x, y, true);
+          }
         }
-      }
-      // contraction against the RT0 fields of both triangles, one trial basis
-      // b at a time (its b-only terms once, then the three test bases):
-      //   Sv = a1 a2 Mxy - a1 (w2.Mx) - a2 (w1.My) + (w1.w2) M0,  Sd = 4 a1 a2 M0,
-      //   S = -ik Sv - Sd/(ik),  C = -[a1 (w2.Nx) - a2 (w1.Nx) + w1.(Nd x w2)]
+        // contraction against the RT0 fields of both triangles, one trial basis
+        // b at a time:
+        //   Sv = a1 a2 Mxy - a1 (w2.Mx) - a2 (w1.My) + (w1.w2) M0,  Sd = 4 a1 a2 M0,
+        //   S = -ik Sv - Sd/(ik),  C = -[a1 (w2.Nx) - a2 (w1.Nx) + w1.(Nd x w2)]
 #pragma unroll 1
-      for (int b = 0; b < 3; ++b) {
-        const int jb = p.t2e[b * F + t2];
-        const double al2 = p.tsgn[b * F + t2] / (2.0 * A2);
-        double w2[3];
+        for (int b = 0; b < 3; ++b) {
+          const int jb = s_e2[lane][b];
+          const double al2 = s_tv2[lane][b][3];
+          double w2[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) w2[d] = al2 * (p.tv[(3 * b + d) * F + t2] - c1[d]);
-        cplx<double> Pb = {0, 0}, Qb = {0, 0}, Rb[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          Pb.re += w2[d] * mm.Mx[d].re;
-          Pb.im += w2[d] * mm.Mx[d].im;
-          Qb.re += w2[d] * mm.Nx[d].re;
-          Qb.im += w2[d] * mm.Nx[d].im;
-        }
-        Rb[0] = {mm.Nd[1].re * w2[2] - mm.Nd[2].re * w2[1], mm.Nd[1].im * w2[2] - mm.Nd[2].im * w2[1]};
-        Rb[1] = {mm.Nd[2].re * w2[0] - mm.Nd[0].re * w2[2], mm.Nd[2].im * w2[0] - mm.Nd[0].im * w2[2]};
-        Rb[2] = {mm.Nd[0].re * w2[1] - mm.Nd[1].re * w2[0], mm.Nd[0].im * w2[1] - mm.Nd[1].im * w2[0]};
-        cplx<double> gxN[RC], gxD[RC], xD[RC], xN[RC];
-#pragma unroll
-        for (int r = 0; r < RC; ++r) {
-          const double* xr = xin + 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
-          xD[r] = {xr[2 * jb], xr[2 * jb + 1]};
-          xN[r] = {xr[2 * (f.E_tot + jb)], xr[2 * (f.E_tot + jb) + 1]};
-          gxN[r] = cmul(g1, xN[r]);
-          gxD[r] = cmul(g2, xD[r]);
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const double al1 = s_t1[a][0];
-          const double w1[3] = {s_t1[a][1], s_t1[a][2], s_t1[a][3]};
-          cplx<double> Ua = {0, 0}, Va = {0, 0}, wR = {0, 0};
-          double ww = 0.0;
+          for (int d = 0; d < 3; ++d) w2[d] = al2 * (s_tv2[lane][b][d] - c1[d]);
+          cplx<double> Pb = {0, 0}, Qb = {0, 0}, Rb[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            Ua.re += w1[d] * mm.My[d].re;
-            Ua.im += w1[d] * mm.My[d].im;
-            Va.re += w1[d] * mm.Nx[d].re;
-            Va.im += w1[d] * mm.Nx[d].im;
-            wR.re += w1[d] * Rb[d].re;
-            wR.im += w1[d] * Rb[d].im;
-            ww += w1[d] * w2[d];
+            Pb.re += w2[d] * mm.Mx[d].re;
+            Pb.im += w2[d] * mm.Mx[d].im;
+            Qb.re += w2[d] * mm.Nx[d].re;
+            Qb.im += w2[d] * mm.Nx[d].im;
           }
-          const double aa = al1 * al2;
-          const double sv_re = aa * mm.Mxy.re - al1 * Pb.re - al2 * Ua.re + ww * mm.M0.re;
-          const double sv_im = aa * mm.Mxy.im - al1 * Pb.im - al2 * Ua.im + ww * mm.M0.im;
-          const double sd_re = 4.0 * aa * mm.M0.re, sd_im = 4.0 * aa * mm.M0.im;
-          const double t_re = (sd_re * kr + sd_im * ki) * ik2, t_im = (sd_im * kr - sd_re * ki) * ik2;
-          const cplx<double> S = {ki * sv_re + kr * sv_im - t_im, ki * sv_im - kr * sv_re + t_re};
-          const cplx<double> C = {-(al1 * Qb.re - al2 * Va.re + wR.re), -(al1 * Qb.im - al2 * Va.im + wR.im)};
+          Rb[0] = {mm.Nd[1].re * w2[2] - mm.Nd[2].re * w2[1], mm.Nd[1].im * w2[2] - mm.Nd[2].im * w2[1]};
+          Rb[1] = {mm.Nd[2].re * w2[0] - mm.Nd[0].re * w2[2], mm.Nd[2].im * w2[0] - mm.Nd[0].im * w2[2]};
+          Rb[2] = {mm.Nd[0].re * w2[1] - mm.Nd[1].re * w2[0], mm.Nd[0].im * w2[1] - mm.Nd[1].im * w2[0]};
+          const cplx<double> xbD = {xin[2 * jb], xin[2 * jb + 1]};
+          const cplx<double> xbN = {xin[2 * (E + jb)], xin[2 * (E + jb) + 1]};
+          double cb[4] = {0.0, 0.0, 0.0, 0.0};  // trial basis b's sum over the test bases
+#pragma unroll 1
+          for (int a = 0; a < 3; ++a) {
+            const double al1 = s_a[lt1][a][0];
+            const double w1[3] = {s_a[lt1][a][1], s_a[lt1][a][2], s_a[lt1][a][3]};
+            cplx<double> Ua = {0, 0}, Va = {0, 0}, wR = {0, 0};
+            double ww = 0.0;
 #pragma unroll
-          for (int r = 0; r < RC; ++r) {
-            const cplx<double> a1 = cmul(C, xD[r]), a2 = cmul(S, gxN[r]);
-            const cplx<double> b1 = cmul(C, xN[r]), b2 = cmul(S, gxD[r]);
-            acc[r][a][0].re += a1.re + a2.re;
-            acc[r][a][0].im += a1.im + a2.im;
-            acc[r][a][1].re += b1.re + b2.re;
-            acc[r][a][1].im += b1.im + b2.im;
+            for (int d = 0; d < 3; ++d) {
+              Ua.re += w1[d] * mm.My[d].re;
+              Ua.im += w1[d] * mm.My[d].im;
+              Va.re += w1[d] * mm.Nx[d].re;
+              Va.im += w1[d] * mm.Nx[d].im;
+              wR.re += w1[d] * Rb[d].re;
+              wR.im += w1[d] * Rb[d].im;
+              ww += w1[d] * w2[d];
+            }
+            const double aa = al1 * al2;
+            const double sv_re = aa * mm.Mxy.re - al1 * Pb.re - al2 * Ua.re + ww * mm.M0.re;
+            const double sv_im = aa * mm.Mxy.im - al1 * Pb.im - al2 * Ua.im + ww * mm.M0.im;
+            const double sd_re = 4.0 * aa * mm.M0.re, sd_im = 4.0 * aa * mm.M0.im;
+            const double t_re = (sd_re * kr + sd_im * ki) * ik2, t_im = (sd_im * kr - sd_re * ki) * ik2;
+            const cplx<double> S = {ki * sv_re + kr * sv_im - t_im, ki * sv_im - kr * sv_re + t_re};
+            const cplx<double> C = {-(al1 * Qb.re - al2 * Va.re + wR.re), -(al1 * Qb.im - al2 * Va.im + wR.im)};
+            double ra[4] = {0.0, 0.0, 0.0, 0.0};
+            free_add(ra, S, C, g1, g2, xbD, xbN);
+            // static register indices (a is a loop counter)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              row[q] += a == 0 ? ra[q] : 0.0;
+              row[4 + q] += a == 1 ? ra[q] : 0.0;
+              row[8 + q] += a == 2 ? ra[q] : 0.0;
+            }
+            const int ea = p.t2e[a * F + t1];  // the same for the whole wavefront
+            free_add(cb, S, C, g1, g2, cplx<double>{xin[2 * ea], xin[2 * ea + 1]},
+                     cplx<double>{xin[2 * (E + ea)], xin[2 * (E + ea) + 1]});
           }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) col[4 * b + q] += cb[q];
         }
       }
     }
-  }
-
-  // singular pairs of t1 (vertex-sharing, edge-sharing, identical)
-  const int64_t sp0 = f.sing_ptr[t1], sp1 = f.sing_ptr[t1 + 1];
-  for (int64_t sp = sp0 + threadIdx.x; sp < sp1; sp += FREE_THREADS) {
-    const int t2 = f.sing_pairs[2 * sp + 1];
-    int jb[3];
+    // the test triangle's sums over the wave's 64 trial triangles
 #pragma unroll
-    for (int b = 0; b < 3; ++b) jb[b] = p.t2e[b * F + t2];
+    for (int q = 0; q < 12; ++q) {
+      const double v = wave_sum_free(row[q]);
+      if (lane == 0) s_row[lt1][q] = v;
+    }
+  }
+  __syncthreads();
+  double* pr = part + int64_t(r) * nt * nt * FREE_TT * 12;
+  {
+    double* o = pr + (int64_t(J) * nt + I) * FREE_TT * 12;
+    for (int i = threadIdx.x; i < FREE_TT * 12; i += blockDim.x) {
+      const int l = i / 12, q = i % 12;
+      double v = s_col[0][l][q];
+#pragma unroll
+      for (int u = 1; u < FREE_WAVES; ++u) v += s_col[u][l][q];
+      if (I == J) v = s_row[l][q] + v;
+      o[i] = v;
+    }
+  }
+  if (I != J) {
+    double* o = pr + (int64_t(I) * nt + J) * FREE_TT * 12;
+    for (int i = threadIdx.x; i < FREE_TT * 12; i += blockDim.x) o[i] = s_row[i / 12][i % 12];
+  }
+}
+
+// grid (F, nrhs), one wavefront: the vertex-sharing pairs of test triangle
+// t1 (lanes over its pairs; the FP64 blocks of the singular kernel), summed
+// over the wave, then the regular pairs' partial sums of its tile row in
+// order; one (yD, yN) per slot (rhs, t1, a).
+__global__ __launch_bounds__(WAVE) void k_free_sing_sum(AsmParams<double> p, FreeJob f, int nt,
+                                                        const double* __restrict__ part) {
+  const int t1 = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int F = p.F, E = f.E_tot;
+  const int s1 = p.tscat[t1];
+  const double ke = p.k_ext;
+  const double kir = p.k_int[2 * s1], kii = p.k_int[2 * s1 + 1];
+  const double kim2 = kir * kir + kii * kii;
+  const cplx<double> fe1 = {1.0 / ke, 0.0}, fe2 = {-ke, 0.0};
+  const cplx<double> fi1 = {kir / kim2, -kii / kim2}, fi2 = {-kir, -kii};
+  const double* xr = f.x + 2 * int64_t(r) * f.vs;
+  const double* ur = (f.xi ? f.xi : f.x) + 2 * int64_t(r) * f.vs;
+  double acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+  const int64_t sp0 = f.sing_ptr[t1], sp1 = f.sing_ptr[t1 + 1];
+  for (int64_t sp = sp0 + lane; sp < sp1; sp += WAVE) {
+    const int t2 = f.sing_pairs[2 * sp + 1];
     const cplx<double>* blk = reinterpret_cast<const cplx<double>*>(f.sing_blk) + sp * 36;
-    const double* xin = f.xi ? f.xi : f.x;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      cplx<double> xD[RC], xN[RC], uD[RC], uN[RC];
-#pragma unroll
-      for (int r = 0; r < RC; ++r) {
-        const int64_t ro = 2 * (int64_t(r0 + (r < nr ? r : 0)) * f.vs);
-        const double* xr = f.x + ro;
-        const double* ur = xin + ro;
-        xD[r] = {xr[2 * jb[b]], xr[2 * jb[b] + 1]};
-        xN[r] = {xr[2 * (f.E_tot + jb[b])], xr[2 * (f.E_tot + jb[b]) + 1]};
-        uD[r] = {ur[2 * jb[b]], ur[2 * jb[b] + 1]};
-        uN[r] = {ur[2 * (f.E_tot + jb[b])], ur[2 * (f.E_tot + jb[b]) + 1]};
-      }
+      const int e = p.t2e[b * F + t2];
+      const cplx<double> xD = {xr[2 * e], xr[2 * e + 1]}, xN = {xr[2 * (E + e)], xr[2 * (E + e) + 1]};
+      const cplx<double> uD = {ur[2 * e], ur[2 * e + 1]}, uN = {ur[2 * (E + e)], ur[2 * (E + e) + 1]};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const cplx<double>* e = blk + 4 * (3 * a + b);
-        if (f.use_ext) apply_block<RC>(acc, a, e[0], e[1], fe1, fe2, xD, xN);
-        apply_block<RC>(acc, a, e[2], e[3], fi1, fi2, uD, uN);
+        const cplx<double>* en = blk + 4 * (3 * a + b);
+        if (f.use_ext) free_add(acc + 4 * a, en[0], en[1], fe1, fe2, xD, xN);
+        free_add(acc + 4 * a, en[2], en[3], fi1, fi2, uD, uN);
       }
     }
   }
-
-  // fixed-order reduction: lanes by butterfly, waves through LDS
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  double tot[12];
 #pragma unroll
-  for (int r = 0; r < RC; ++r)
+  for (int q = 0; q < 12; ++q) tot[q] = wave_sum_free(acc[q]);
+  if (lane < 12) {
+    double v = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const double vr = wave_sum_free(acc[r][a][c].re), vi = wave_sum_free(acc[r][a][c].im);
-        if (lane == 0) {
-          red[wv][((r * 3 + a) * 2 + c) * 2] = vr;
-          red[wv][((r * 3 + a) * 2 + c) * 2 + 1] = vi;
-        }
-      }
-  __syncthreads();
-  if (threadIdx.x < RC * 12) {
-    const int r = threadIdx.x / 12, rest = threadIdx.x % 12;
-    if (r < nr) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < FREE_THREADS / WAVE; ++w) s += red[w][threadIdx.x];
-      // slot layout: [rhs][3F slots][yD re, yD im, yN re, yN im]
-      const int a = rest / 4, c = rest % 4;
-      f.slots[(int64_t(r0 + r) * 3 * F + 3 * int64_t(t1) + a) * 4 + c] = s;
-    }
+    for (int q = 0; q < 12; ++q) v = q == lane ? tot[q] : v;
+    const int K = t1 / FREE_TT, tl = t1 - K * FREE_TT;
+    const double* pp = part + ((int64_t(r) * nt + K) * nt * FREE_TT + tl) * 12 + lane;
+    for (int L = 0; L < nt; ++L) v += pp[int64_t(L) * FREE_TT * 12];
+    // slot layout: [rhs][3F slots][yD re, yD im, yN re, yN im]
+    f.slots[(int64_t(r) * 3 * F + 3 * int64_t(t1)) * 4 + lane] = v;
   }
 }
 
@@ -280,18 +343,19 @@ __global__ void k_free_combine(FreeJob f, int F) {
   y[2 * (f.E_tot + i) + 1] = a[3] + b[3];
 }
 
-void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, hipStream_t st) {
-  // one right-hand side per workgroup: the variants with 2 or 4 exceed the
-  // register file and spill (the integrals are the cost; callers with many
-  // right-hand sides use an assembled FP64 operator instead)
-  const int rc = 1;
-  const dim3 grid{unsigned(p.F), unsigned((f.nrhs + rc - 1) / rc)};
-  if (rc == 4)
-    hipLaunchKernelGGL(k_free_apply<4>, grid, dim3(FREE_THREADS), 0, st, p, f);
-  else if (rc == 2)
-    hipLaunchKernelGGL(k_free_apply<2>, grid, dim3(FREE_THREADS), 0, st, p, f);
-  else
-    hipLaunchKernelGGL(k_free_apply<1>, grid, dim3(FREE_THREADS), 0, st, p, f);
+int free_tiles(int F) { return (F + FREE_TT - 1) / FREE_TT; }
+
+int64_t free_part_doubles(int F, int nrhs) {
+  const int64_t nt = free_tiles(F);
+  return int64_t(nrhs) * nt * nt * FREE_TT * 12;
+}
+
+void launch_free_apply(const AsmParams<double>& p, const FreeJob& f, double* part, hipStream_t st) {
+  const int nt = free_tiles(p.F);
+  const int64_t nup = int64_t(nt) * (nt + 1) / 2;
+  hipLaunchKernelGGL(k_free_tiles, dim3(unsigned(nup), unsigned(f.nrhs)), dim3(FREE_WAVES * WAVE), 0, st, p, f, nt,
+                     part);
+  hipLaunchKernelGGL(k_free_sing_sum, dim3(unsigned(p.F), unsigned(f.nrhs)), dim3(WAVE), 0, st, p, f, nt, part);
   const int64_t n = int64_t(f.E_tot) * f.nrhs;
   hipLaunchKernelGGL(k_free_combine, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, f, p.F);
 }

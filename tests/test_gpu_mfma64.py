@@ -1,6 +1,7 @@
 """Many-RHS FP64 products on the matrix cores: the PMCHWT operator (combined
 operators of one scatterer, per-medium form for several) and the far-field
-sum as a matrix product of plane-wave phases and surface currents.
+sum as a matrix product of plane-wave phases and surface currents (for the
+scattering cross section over direction pairs xh, -xh).
 
 Each is checked against the FP64 oracle and against the library's own VALU
 path on the same input (the operator in chunks of 4 right-hand sides, below
@@ -125,4 +126,47 @@ def test_fp64_batched_solve_cross_sections(P):
          f"sca {e_sca:.2e}")
     assert st.converged and prof["mfma_launches"] > 0
     assert err < 1e-9 and e_ext < 1e-9 and e_sca < 1e-9
+    ctx.close()
+
+
+def _sphere_grid(n_theta=64, n_phi=128):
+    """The cross sections' direction grid: Gauss-Legendre in cos(theta) x
+    uniform in phi, with weights."""
+    ct, wt = np.polynomial.legendre.leggauss(n_theta)
+    ph = 2 * np.pi * np.arange(n_phi) / n_phi
+    CT, PH = np.meshgrid(ct, ph, indexing="ij")
+    st = np.sqrt(1 - CT ** 2)
+    obs = np.stack([st * np.cos(PH), st * np.sin(PH), CT], axis=-1).reshape(-1, 3)
+    return obs, (wt[:, None] * np.full(n_phi, 2 * np.pi / n_phi)[None, :]).ravel()
+
+
+@pytest.mark.parametrize("mesh", ["bipyramid", "sphere2", "two prisms"])
+def test_sigma_sca_antipodal_pairs(P, mesh):
+    """sigma_sca with 8 or more right-hand sides forms the far field for the
+    upper half of the direction grid and takes the antipodes from the same
+    cosine and sine sums.  It must equal the grid sum of w |F|^2 over the
+    library's own far field at every grid direction (matrix cores, no
+    pairing), and sigma_sca of the VALU path (chunks of 4 right-hand sides):
+    the same directions and weights up to rounding, other summation orders.
+    The bipyramid's 60 rule points leave a ragged K tile."""
+    meshes = {"bipyramid": lambda: [bipyramid()], "sphere2": lambda: [synth.icosphere(2)],
+              "two prisms": lambda: synth.aggregate(2, 2, 3, seed=7)}[mesh]()
+    note(f"sigma_sca from antipodal pairs: {mesh}, 9 RHS")
+    ctx = make_ctx(P, meshes, EPS, 2.7, qP=(1, 1, 1), nP=1, chi=0.5, precond="S_INT")
+    _, N = ctx.sizes()
+    x = _x(9, N, 13)
+    d, p = synth.plane_wave_set(5, seed=3)
+    d, p = d[:9], p[:9]
+    se, ss = ctx.cross_sections(x, d, p)
+    obs, w = _sphere_grid()
+    Ff = ctx.far_field(x, obs)
+    ss_full = np.einsum("o,rod->r", w, np.abs(Ff) ** 2)
+    chunks = [ctx.cross_sections(x[i:i + 4], d[i:i + 4], p[i:i + 4]) for i in range(0, 9, 4)]
+    se4 = np.concatenate([c[0] for c in chunks])
+    ss4 = np.concatenate([c[1] for c in chunks])
+    e_full = np.max(np.abs(ss - ss_full) / np.abs(ss_full))
+    e_v = np.max(np.abs(ss - ss4) / np.abs(ss4))
+    e_ext = np.max(np.abs(se - se4) / np.abs(se4))
+    note(f"  sigma_sca vs full grid {e_full:.2e}, vs VALU path {e_v:.2e}; sigma_ext vs VALU path {e_ext:.2e}")
+    assert e_full < 1e-12 and e_v < 1e-12 and e_ext < 1e-12
     ctx.close()
