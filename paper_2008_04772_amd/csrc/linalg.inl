@@ -2166,17 +2166,21 @@ void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const doub
   spmv_real2_csr(rowptr, col, val, rows, alpha, x, y, nrhs, vstride, cstride, st, beta);
 }
 
-// sum of v over the 1024 threads of the workgroup, in a fixed tree order;
-// every thread gets it (red: 1024 doubles of LDS)
-__device__ __forceinline__ double block_sum1024(double v, double* red) {
-  red[threadIdx.x] = v;
+// sum of v over the 1024 threads of the workgroup, the same in every thread:
+// each wavefront's sum (DPP within rows of 16, then across rows), then the 16
+// wavefront sums in order.  The two slot sets red[0], red[1] alternate
+// between consecutive calls (set): a wavefront writes a set only after every
+// wavefront has passed the previous call's barrier, so after every read of
+// that set in the call before.  One barrier per call.
+__device__ __forceinline__ double block_sum1024(double v, double (*red)[16], int& set) {
+  v = row_sum<32>(v);
+  v += __shfl_xor(v, 32, WAVE);
+  if ((threadIdx.x & 63) == 0) red[set][threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double t = red[0];
-  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t += red[set][w];
+  set ^= 1;
   return t;
 }
 
@@ -2190,7 +2194,8 @@ __global__ __launch_bounds__(1024) void k_gram_cg(const int64_t* __restrict__ ro
                                                   const double* __restrict__ val, int n, const double* b,
                                                   int64_t bstride, double* x, int64_t xstride, double* work,
                                                   double tol2, int maxit) {
-  __shared__ double red[1024];
+  __shared__ double red[2][16];
+  int set = 0;
   const int v = blockIdx.x;
   const double* bv = b + 2 * int64_t(v) * bstride;
   double* xv = x + 2 * int64_t(v) * xstride;
@@ -2208,7 +2213,7 @@ __global__ __launch_bounds__(1024) void k_gram_cg(const int64_t* __restrict__ ro
     p[2 * i + 1] = bi;
     sum += br * br + bi * bi;
   }
-  double rr = block_sum1024(sum, red);  // its barriers also publish r and p to the workgroup
+  double rr = block_sum1024(sum, red, set);  // its barrier also publishes r and p to the workgroup
   const double rr0 = rr;
   for (int it = 0; it < maxit && rr > tol2 * rr0; ++it) {  // rr is the same in every thread
     sum = 0.0;
@@ -2224,7 +2229,7 @@ __global__ __launch_bounds__(1024) void k_gram_cg(const int64_t* __restrict__ ro
       q[2 * i + 1] = qi;
       sum += p[2 * i] * qr + p[2 * i + 1] * qi;
     }
-    const double pq = block_sum1024(sum, red);
+    const double pq = block_sum1024(sum, red, set);
     const double al = pq > 0 ? rr / pq : 0.0;
     sum = 0.0;
     for (int i = threadIdx.x; i < n; i += 1024) {
@@ -2235,7 +2240,7 @@ __global__ __launch_bounds__(1024) void k_gram_cg(const int64_t* __restrict__ ro
       r[2 * i + 1] = ri_;
       sum += rr_ * rr_ + ri_ * ri_;
     }
-    const double rn = block_sum1024(sum, red);
+    const double rn = block_sum1024(sum, red, set);
     const double be = rr > 0 ? rn / rr : 0.0;
     rr = rn;
     for (int i = threadIdx.x; i < n; i += 1024) {
