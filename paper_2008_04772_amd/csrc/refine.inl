@@ -87,6 +87,7 @@ __global__ __launch_bounds__(FREE_WAVES * WAVE, 2) void k_free_tiles(AsmParams<d
   __shared__ double s_col[FREE_WAVES][FREE_TT][12];   // trial triangles' sums per wavefront
   __shared__ double s_tv2[FREE_TT][3][4];             // trial triangles: vertices, alpha of each basis
   __shared__ int s_e2[FREE_TT][3];                    // trial triangles' basis edges
+  __shared__ double s_x1[FREE_WAVES][3][8];           // per wavefront, its test triangle's bases: xD, xN, uD, uN
   int I, J;
   upper_tile(blockIdx.x, nt, I, J);
   const int r = blockIdx.y;
@@ -142,6 +143,17 @@ __global__ __launch_bounds__(FREE_WAVES * WAVE, 2) void k_free_tiles(AsmParams<d
     double row[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) row[q] = 0.0;
+    // the exterior and interior inputs at the test triangle's three edges,
+    // once per step into this wavefront's slot (lane 8 a + c: basis a,
+    // c = xD re, im, xN re, im, uD re, im, uN re, im)
+    if (lane < 24) {
+      const int a = lane >> 3, c = lane & 7, e = p.t2e[a * F + min(t1, F - 1)];
+      const double* src = c < 4 ? xr : ur;
+      s_x1[w][a][c] = src[2 * ((c & 2) ? E + e : e) + (c & 1)];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     bool live = v2 && t1 < F && (I != J || lane > lt1);
     if (live) {
       const int va0 = s_v[lt1][0], va1 = s_v[lt1][1], va2 = s_v[lt1][2];
@@ -242,9 +254,8 @@ __global__ __launch_bounds__(FREE_WAVES * WAVE, 2) void k_free_tiles(AsmParams<d
               row[4 + q] += a == 1 ? ra[q] : 0.0;
               row[8 + q] += a == 2 ? ra[q] : 0.0;
             }
-            const int ea = p.t2e[a * F + t1];  // the same for the whole wavefront
-            free_add(cb, S, C, g1, g2, cplx<double>{xin[2 * ea], xin[2 * ea + 1]},
-                     cplx<double>{xin[2 * (E + ea)], xin[2 * (E + ea) + 1]});
+            const double* xa = s_x1[w][a] + 4 * kk;
+            free_add(cb, S, C, g1, g2, cplx<double>{xa[0], xa[1]}, cplx<double>{xa[2], xa[3]});
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) col[4 * b + q] += cb[q];
