@@ -878,6 +878,12 @@ __global__ __launch_bounds__(256) void k_spmv_pmchwt(const int64_t* __restrict__
                                                      const double* __restrict__ xD,
                                                      const double* __restrict__ xN, double* yD, double* yN,
                                                      int64_t vstride, int acc) {
+  // right-hand sides NR blockIdx.y .. NR blockIdx.y + NR - 1
+  const int64_t g0 = 2 * int64_t(blockIdx.y) * NR * vstride;
+  xD += g0;
+  xN += g0;
+  yD += g0;
+  yN += g0;
   const int lane = threadIdx.x & 31;
   const int row = blockIdx.x * (blockDim.x / 32) + threadIdx.x / 32;
   const bool live = row < rows;  // both halves of a wavefront take part in the shuffles
@@ -966,24 +972,21 @@ static void spmv_pmchwt_launch(dim3 grid, const int64_t* rowptr, const int32_t* 
                        xd, xn, yd, yn, vstride, int(acc));
 }
 
+// groups of 4 right-hand sides in one launch (grid.y over the groups), the
+// remainder one at a time in a second launch
 template <typename M>
 void launch_spmv_pmchwt(const int64_t* rowptr, const int32_t* col, const M* S, const M* C, int rows, double kr,
                         double ki, const double* xD, const double* xN, double* yD, double* yN, int nrhs,
                         int64_t vstride, hipStream_t st, bool acc) {
-  const dim3 grid((rows + 7) / 8);
-  for (int r0 = 0; r0 < nrhs;) {
-    const int left = nrhs - r0;
-    const double* xd = xD + 2 * int64_t(r0) * vstride;
-    const double* xn = xN + 2 * int64_t(r0) * vstride;
-    double* yd = yD + 2 * int64_t(r0) * vstride;
-    double* yn = yN + 2 * int64_t(r0) * vstride;
-    if (left >= 4) {
-      spmv_pmchwt_launch<M, 4>(grid, rowptr, col, S, C, rows, kr, ki, xd, xn, yd, yn, vstride, acc, st);
-      r0 += 4;
-    } else {
-      spmv_pmchwt_launch<M, 1>(grid, rowptr, col, S, C, rows, kr, ki, xd, xn, yd, yn, vstride, acc, st);
-      r0 += 1;
-    }
+  const unsigned gx = unsigned((rows + 7) / 8);
+  const int n4 = nrhs / 4, r0 = 4 * n4;
+  if (n4 > 0)
+    spmv_pmchwt_launch<M, 4>(dim3(gx, unsigned(n4)), rowptr, col, S, C, rows, kr, ki, xD, xN, yD, yN, vstride, acc,
+                             st);
+  if (nrhs > r0) {
+    const int64_t o = 2 * int64_t(r0) * vstride;
+    spmv_pmchwt_launch<M, 1>(dim3(gx, unsigned(nrhs - r0)), rowptr, col, S, C, rows, kr, ki, xD + o, xN + o, yD + o,
+                             yN + o, vstride, acc, st);
   }
 }
 template void launch_spmv_pmchwt<double>(const int64_t*, const int32_t*, const double*, const double*, int,
@@ -2088,6 +2091,9 @@ __global__ __launch_bounds__(256) void k_spmv_real2_csr(const int64_t* __restric
                                                         const VT* __restrict__ val, int rows, double alpha,
                                                         const double* __restrict__ x, double* y, int64_t vstride,
                                                         int64_t cstride, double beta) {
+  // right-hand sides NR blockIdx.y .. NR blockIdx.y + NR - 1
+  x += 2 * int64_t(blockIdx.y) * NR * vstride;
+  y += 2 * int64_t(blockIdx.y) * NR * vstride;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
@@ -2139,20 +2145,17 @@ template <typename VT>
 static void spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const VT* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
                            double beta) {
-  const dim3 grid(unsigned((rows + 3) / 4)), block(256);
-  for (int r0 = 0; r0 < nrhs;) {
-    const int left = nrhs - r0;
-    const double* xx = x + 2 * int64_t(r0) * vstride;
-    double* yy = y + 2 * int64_t(r0) * vstride;
-    if (left >= 4) {
-      hipLaunchKernelGGL((k_spmv_real2_csr<4, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
-                         vstride, cstride, beta);
-      r0 += 4;
-    } else {
-      hipLaunchKernelGGL((k_spmv_real2_csr<1, VT>), grid, block, 0, st, rowptr, col, val, rows, alpha, xx, yy,
-                         vstride, cstride, beta);
-      r0 += 1;
-    }
+  // groups of 4 right-hand sides in one launch (grid.y over the groups), the
+  // remainder one at a time in a second launch
+  const unsigned gx = unsigned((rows + 3) / 4);
+  const int n4 = nrhs / 4, r0 = 4 * n4;
+  if (n4 > 0)
+    hipLaunchKernelGGL((k_spmv_real2_csr<4, VT>), dim3(gx, unsigned(n4)), dim3(256), 0, st, rowptr, col, val, rows,
+                       alpha, x, y, vstride, cstride, beta);
+  if (nrhs > r0) {
+    const int64_t o = 2 * int64_t(r0) * vstride;
+    hipLaunchKernelGGL((k_spmv_real2_csr<1, VT>), dim3(gx, unsigned(nrhs - r0)), dim3(256), 0, st, rowptr, col, val,
+                       rows, alpha, x + o, y + o, vstride, cstride, beta);
   }
 }
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
