@@ -2768,8 +2768,14 @@ void apply_Ptilde(pmchwt_ctx* c, const double* y, double* z, double* t1, double*
         launch_bsr_real2(S.bsr.m, s.topo.E, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, Bw, c->stream);
       else
         launch_spmv_real2_csr(rp, cl, vl, s.topo.E, alpha, in + 2 * o, out + 2 * o, nrhs, vs, E, c->stream);
-      launch_spmv_real2_csr(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), s.topo.E, -1.0,
-                            out + 2 * o, tmp + 2 * o, nrhs, vs, E, c->stream);
+      if (many) {  // the residual's gathers from a copy with the right-hand sides adjacent per column
+        DBuf xt = dalloc_c<double>(c, 4 * size_t(s.topo.E) * nrhs);
+        launch_spmv_real2_csr_t(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), s.topo.E,
+                                s.topo.E, -1.0, out + 2 * o, tmp + 2 * o, nrhs, vs, E, xt.as<double>(), c->stream);
+      } else {
+        launch_spmv_real2_csr(Mm.rowptr.as<int64_t>(), Mm.col.as<int32_t>(), Mm.val.as<double>(), s.topo.E, -1.0,
+                              out + 2 * o, tmp + 2 * o, nrhs, vs, E, c->stream);
+      }
       launch_axpby_rows(tmp + 2 * o, in + 2 * o, vs, s.topo.E, E, nrhs, 1.0, alpha, c->stream);
       if (xb)
         launch_bsr_real2(S.bsr.m, s.topo.E, s.topo.E, 1.0, tmp + 2 * o, out + 2 * o, nrhs, vs, E, Bw, c->stream, true);

@@ -442,6 +442,14 @@ void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const floa
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const double* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
                            double beta = 0.0);
+// The same product for many right-hand sides from a gathered copy of x with
+// the right-hand sides adjacent per column (xt: 4 nrhs doubles per column of
+// x: xD re, im, xN re, im of each rhs), so that one entry's gathers for a
+// group of 4 right-hand sides read 128 contiguous bytes; same sums in the same
+// order as launch_spmv_real2_csr.  xt: 4 cols nrhs doubles of workspace.
+void launch_spmv_real2_csr_t(const int64_t* rowptr, const int32_t* col, const double* val, int rows, int cols,
+                             double alpha, const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride,
+                             double* xt, hipStream_t st);
 template <typename M>
 void launch_gemv_real2(const M* Mat, int64_t ld, int rows, int cols, double alpha, const double* x, double* y,
                        int nrhs, int64_t vstride, int64_t cstride, hipStream_t st);

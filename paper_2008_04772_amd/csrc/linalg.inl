@@ -2158,6 +2158,86 @@ static void spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const VT* 
                        rows, alpha, x + o, y + o, vstride, cstride, beta);
   }
 }
+// xt[(c nrhs + r) 4 + q] = (xD re, xD im, xN re, xN im)[q] of rhs r at column
+// c; thread per (rhs, column), consecutive threads along the columns
+__global__ void k_gather_cols(const double* __restrict__ x, int64_t vstride, int64_t cstride, int cols, int nrhs,
+                              double* __restrict__ xt) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(cols) * nrhs) return;
+  const int r = int(t / cols), c = int(t - int64_t(r) * cols);
+  const double* xr = x + 2 * int64_t(r) * vstride;
+  const double2 d = *reinterpret_cast<const double2*>(xr + 2 * int64_t(c));
+  const double2 n = *reinterpret_cast<const double2*>(xr + 2 * (cstride + c));
+  double* o = xt + (int64_t(c) * nrhs + r) * 4;
+  *reinterpret_cast<double2*>(o) = d;
+  *reinterpret_cast<double2*>(o + 2) = n;
+}
+
+// y = alpha M x (beta = 0) for every right-hand side, reading x from the
+// gathered copy xt.  16 lanes per row (four rows per wavefront: the rows of
+// M_A hold about 20 entries), each wavefront's rows taking every group of 4
+// right-hand sides in turn (the remainder as a last, partial group): one
+// wavefront per 4 rows for the whole batch instead of one per row and group.
+// Per group: lane sums over its entries in order, then over the 16 lanes.
+__global__ __launch_bounds__(256) void k_spmv_real2_csr_t(const int64_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val, int rows, double alpha,
+                                                          const double* __restrict__ xt, int nrhs, double* y,
+                                                          int64_t vstride, int64_t cstride) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const bool live = row < rows;  // every lane takes part in the row sums
+  const int64_t p0 = live ? rowptr[row] : 0, p1 = live ? rowptr[row + 1] : 0;
+  for (int rb = 0; rb < nrhs; rb += 4) {
+    const int nr = min(4, nrhs - rb);
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+    for (int64_t p = p0 + l16; p < p1; p += 16) {
+      const int c = col[p];
+      const double v = val[p];
+      const double2* src = reinterpret_cast<const double2*>(xt + (int64_t(c) * nrhs + rb) * 4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r < nr) {
+          const double2 x0 = src[2 * r], x1 = src[2 * r + 1];
+          acc[r][0] += v * x0.x;
+          acc[r][1] += v * x0.y;
+          acc[r][2] += v * x1.x;
+          acc[r][3] += v * x1.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] = row_sum<16>(acc[r][q]);
+    if (live && l16 == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r < nr) {
+          double* q0 = y + 2 * (int64_t(rb + r) * vstride + row);
+          double* q1 = q0 + 2 * cstride;
+          q0[0] = alpha * acc[r][0];
+          q0[1] = alpha * acc[r][1];
+          q1[0] = alpha * acc[r][2];
+          q1[1] = alpha * acc[r][3];
+        }
+      }
+    }
+  }
+}
+
+void launch_spmv_real2_csr_t(const int64_t* rowptr, const int32_t* col, const double* val, int rows, int cols,
+                             double alpha, const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride,
+                             double* xt, hipStream_t st) {
+  const int64_t n = int64_t(cols) * nrhs;
+  hipLaunchKernelGGL(k_gather_cols, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, x, vstride, cstride, cols, nrhs,
+                     xt);
+  hipLaunchKernelGGL(k_spmv_real2_csr_t, dim3(unsigned((rows + 15) / 16)), dim3(256), 0, st, rowptr, col, val, rows,
+                     alpha, xt, nrhs, y, vstride, cstride);
+}
+
 void launch_spmv_real2_csr(const int64_t* rowptr, const int32_t* col, const float* val, int rows, double alpha,
                            const double* x, double* y, int nrhs, int64_t vstride, int64_t cstride, hipStream_t st,
                            double beta) {
