@@ -3930,6 +3930,18 @@ int pmchwt_solve_device(pmchwt_ctx* c, const double* dirs, const pmchwt_complex*
   return solve_common(c, dirs, pols, nrhs, o, nullptr, currents_dev, hip_stream, st);
 }
 
+// Host currents (API layout: nrhs vectors of 2 E_tot complex, scatterer-major)
+// copied as they are and put into the internal layout on the device.
+DBuf upload_currents(pmchwt_ctx* c, const pmchwt_complex* cur, int nrhs) {
+  const size_t n_api = size_t(nrhs) * 2 * size_t(c->E_tot);
+  DBuf dapi = dalloc_c<double>(c, 2 * n_api);
+  HIPCHK(hipMemcpyAsync(dapi.p, cur, n_api * sizeof(pmchwt_complex), hipMemcpyHostToDevice, c->stream));
+  DBuf dx = dalloc_c<double>(c, size_t(2 * vlen(c) * nrhs));
+  launch_layout(dapi.as<double>(), dx.as<double>(), nrhs, int(c->E_tot), scat_offsets(c), int(c->sc.size()), true,
+                c->stream);
+  return dx;
+}
+
 // Far field of nrhs current vectors (device, internal layout) at nobs
 // directions into F_out (6 doubles per direction and rhs): the FP64 matrix
 // cores for many right-hand sides, else the VALU sum.
@@ -3986,9 +3998,7 @@ int pmchwt_far_field(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs, con
     if (c->sc.empty() || !(c->k_ext > 0)) return fail(c, PMCHWT_ERR_STATE, "no problem defined");
     if (nrhs <= 0 || nobs <= 0 || !cur || !obs || !F) return fail(c, PMCHWT_ERR_INVALID_ARG, "bad arguments");
     upload_geometry(c);
-    std::vector<double> h;
-    to_internal(c, cur, nrhs, h);
-    DBuf dx = upload(c, h);
+    DBuf dx = upload_currents(c, cur, nrhs);
     std::vector<double> ho(obs, obs + 3 * size_t(nobs));
     DBuf dobs = upload(c, ho), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs);
     far_field_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nobs, dF.as<double>());
@@ -4117,9 +4127,8 @@ int pmchwt_cross_sections(pmchwt_ctx* c, const pmchwt_complex* cur, int32_t nrhs
         if (pairs) w[nh + o] = w[o];
       }
     obs.resize(3 * size_t(nh));
-    std::vector<double> h;
-    to_internal(c, cur, nrhs, h);
-    DBuf dx = upload(c, h), dobs = upload(c, obs), dw = upload(c, w), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs),
+    DBuf dx = upload_currents(c, cur, nrhs);
+    DBuf dobs = upload(c, obs), dw = upload(c, w), dF = dalloc_c<double>(c, 6 * size_t(nobs) * nrhs),
          dsig = dalloc_c<double>(c, nrhs);
     if (pairs)
       far_field_pair_dev(c, dx.as<double>(), nrhs, dobs.as<double>(), nh, dF.as<double>());
